@@ -1,0 +1,153 @@
+"""Pins of the isothermal oracle: closed-form viscous decay, conservation, special cases and a
+brute-force streaming check."""
+import numpy as np
+import pytest
+
+from oracle import bgk
+from oracle.equilibrium import feq, moments
+from oracle.lattice import VARSIGMA2, opposite, velocities
+from paper_2609_28679_amd import inputs
+
+
+def _tgv_error(n, steps, u0, tau):
+    rho, u = inputs.taylor_green_2d(n, n, u0)
+    f = bgk.run(bgk.init_equilibrium(rho, u), bgk.omega_from_tau_lb(tau), steps)
+    _, un = moments(f)
+    nu = VARSIGMA2 * (tau - 0.5)
+    k = 2 * np.pi / n
+    amp = np.exp(-2 * nu * k * k * steps)
+    ua = u * amp
+    rel = np.sqrt(((un - ua) ** 2).sum() / (ua ** 2).sum())
+    # measured decay rate from the projection on the initial mode
+    a_meas = (un * u).sum() / (u * u).sum()
+    rate_err = abs(np.log(a_meas) / np.log(amp) - 1.0)
+    return rel, rate_err
+
+
+def test_omega_relation():
+    # beta = dt/(2 tau + dt), tau = tau_LB - 1/2 => 2 beta = 1/tau_LB
+    for t in (0.51, 0.6, 0.8, 1.0, 1.7):
+        assert bgk.omega_from_tau_lb(t) == pytest.approx(1.0 / t, rel=1e-15)
+
+
+def test_taylor_green_decay_64():
+    # config: 64^2 periodic, tau = 0.8 (nu = 0.1), u0 = 0.01, 1000 steps;
+    # analytic u(t) = u(0) exp(-2 nu k^2 t) with nu = varsigma^2 (tau - 1/2)
+    rel, rate_err = _tgv_error(64, 1000, 0.01, 0.8)
+    assert rel < 2.5e-3
+    assert rate_err < 1.5e-3
+
+
+def test_taylor_green_second_order_convergence():
+    # diffusive scaling: N doubles, t x4, u0 / 2; second order => error ratio ~ 4
+    r32, e32 = _tgv_error(32, 250, 0.02, 0.8)
+    r64, e64 = _tgv_error(64, 1000, 0.01, 0.8)
+    assert 3.5 < r32 / r64 < 4.5
+    assert 3.5 < e32 / e64 < 4.5
+
+
+def test_rest_state_is_invariant():
+    rho = np.full((6, 7), 1.3)
+    u = np.zeros((2, 6, 7))
+    f0 = bgk.init_equilibrium(rho, u)
+    f = bgk.run(f0, 1 / 0.7, 20, walls_y=True)
+    np.testing.assert_allclose(f, f0, rtol=1e-14)
+
+
+def test_tau_one_collision_returns_equilibrium():
+    rng = np.random.default_rng(0)
+    f = feq(np.ones((4, 5)), rng.uniform(-0.05, 0.05, (2, 4, 5)), VARSIGMA2)
+    f = f + rng.uniform(-1e-3, 1e-3, f.shape)
+    rho, u = moments(f)
+    np.testing.assert_allclose(bgk.collide(f, 1.0), feq(rho, u, VARSIGMA2), rtol=1e-14, atol=1e-16)
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_mass_and_momentum_conservation(walls):
+    rho, u = inputs.random_phase_turbulence_2d(32, seed=3)
+    f = bgk.init_equilibrium(rho, u)
+    m0 = f.sum()
+    c = velocities(2).astype(np.float64)
+    j0 = np.tensordot(c[:, 0], f, axes=(0, 0)).sum()
+    f = bgk.run(f, 1 / 0.55, 300, walls_y=walls)
+    assert abs(f.sum() - m0) / m0 < 1e-13
+    if not walls:
+        jx = np.tensordot(c[:, 0], f, axes=(0, 0)).sum()
+        jy = np.tensordot(c[:, 1], f, axes=(0, 0)).sum()
+        assert abs(jx - j0) < 1e-12
+        assert abs(jy) < 1e-12
+
+
+@pytest.mark.parametrize("D,walls", [(2, False), (2, True), (3, False), (3, True)])
+def test_stream_matches_brute_force_loop(D, walls):
+    shape = (3, 4, 5)[-D:]
+    Q = 3 ** D
+    rng = np.random.default_rng(1)
+    ft = rng.standard_normal((Q,) + shape)
+    out = bgk.stream(ft, walls)
+    c = velocities(D)
+    opp = opposite(D)
+    expect = np.full_like(ft, np.nan)
+    for i in range(Q):
+        for idx in np.ndindex(*shape):
+            # node index tuple is (.., y, x); component a sits at position D-1-a
+            dst = list(idx)
+            leaves = False
+            for a in range(D):
+                p = D - 1 - a
+                dst[p] = idx[p] + c[i, a]
+                if a == 1 and walls and not (0 <= dst[p] < shape[p]):
+                    leaves = True
+                dst[p] %= shape[p]
+            if leaves:
+                expect[(opp[i],) + idx] = ft[(i,) + idx]
+            else:
+                expect[(i,) + tuple(dst)] = ft[(i,) + idx]
+    assert not np.isnan(expect).any()
+    np.testing.assert_array_equal(out, expect)
+
+
+def test_channel_shear_wave_with_bounce_back_walls():
+    # u_x(y) = U sin(pi (y + 1/2)/ny) vanishes on both walls (y = -1/2, ny - 1/2) and decays
+    # as exp(-nu (pi/ny)^2 t) in the Navier-Stokes limit.
+    nx, ny, tau, steps, U = 4, 32, 0.8, 600, 1e-3
+    y = np.arange(ny) + 0.5
+    u = np.zeros((2, ny, nx))
+    u[0] = (U * np.sin(np.pi * y / ny))[:, None]
+    f = bgk.run(bgk.init_equilibrium(np.ones((ny, nx)), u), 1 / tau, steps, walls_y=True)
+    _, un = moments(f)
+    nu = VARSIGMA2 * (tau - 0.5)
+    expect = np.exp(-nu * (np.pi / ny) ** 2 * steps)
+    a_meas = (un[0] * u[0]).sum() / (u[0] ** 2).sum()
+    assert abs(np.log(a_meas) / np.log(expect) - 1.0) < 5e-3
+    assert np.abs(un[1]).max() < 1e-12
+
+
+def test_d3q27_z_invariant_run_reproduces_d2q9():
+    rho, u2 = inputs.taylor_green_2d(16, 16, 0.02)
+    f2 = bgk.run(bgk.init_equilibrium(rho, u2), 1 / 0.7, 30)
+    u3 = np.concatenate([u2, np.zeros((1, 16, 16))])[:, None]
+    f3 = bgk.run(bgk.init_equilibrium(rho[None], u3), 1 / 0.7, 30)
+    r3, v3 = moments(f3)
+    r2, v2 = moments(f2)
+    np.testing.assert_allclose(r3[0], r2, rtol=1e-13)
+    np.testing.assert_allclose(v3[:2, 0], v2, rtol=1e-10, atol=1e-15)
+
+
+def test_d3q27_taylor_green_early_energy_decay():
+    # early-time kinetic energy of the 3D Taylor-Green vortex decays at rate 6 nu k^2
+    n, tau, u0, steps = 24, 0.55, 0.01, 40
+    rho, u = inputs.taylor_green_3d(n, u0)
+    f = bgk.init_equilibrium(rho, u)
+    c = velocities(3).astype(np.float64)
+    omega = 1 / tau
+    energies = []
+    for _ in range(steps + 1):
+        r, v = moments(f)
+        energies.append(0.5 * (r * (v * v).sum(axis=0)).sum())
+        f = bgk.stream(bgk.collide(f, omega))
+    nu = VARSIGMA2 * (tau - 0.5)
+    k = 2 * np.pi / n
+    t = np.arange(steps + 1)
+    rate = -np.polyfit(t[10:], np.log(energies[10:]), 1)[0]
+    assert rate == pytest.approx(6 * nu * k * k, rel=3e-2)

@@ -1,0 +1,193 @@
+"""Pins of the double-distribution (ideal gas) oracle against the hydrodynamic limit of
+Sec. II D, conservation, and exact properties of the finite-difference correction."""
+import numpy as np
+import pytest
+
+from oracle import bgk, ddf
+from oracle.equilibrium import feq
+from paper_2609_28679_amd import inputs
+
+R, CV = 1.0 / 3.0, 5.0 / 6.0     # R / c_v = 0.4 (the nitrogen value of the paper's table)
+GAMMA = 1.0 + R / CV
+P0 = 1.0 / 3.0
+
+
+def _gas(tau_lb=0.6):
+    return ddf.Gas(R, CV, (tau_lb - 0.5) * P0)
+
+
+def _run_series(f, g, gas, steps, walls, phi_on, probe, stencil="central"):
+    out = []
+    for _ in range(steps):
+        out.append(probe(*ddf.moments(f, g)))
+        ft, gt = ddf.collide(f, g, gas, walls, phi_on, stencil)
+        f, g = bgk.stream(ft, walls), bgk.stream(gt, walls)
+    return np.array(out), f, g
+
+
+def _acoustic(T0, phi_on, n=32, steps=200, eps=1e-4, stencil="central"):
+    gas = _gas()
+    rho0 = P0 / (R * T0)
+    x = np.arange(n)
+    k = 2 * np.pi / n
+    shape = np.ones((4, 1))
+    rho = rho0 * (1 + eps * np.cos(k * x))[None, :] * shape          # isentropic pulse
+    T = T0 * (1 + (GAMMA - 1) * eps * np.cos(k * x))[None, :] * shape
+    f, g = ddf.init_equilibrium(rho, np.zeros((2, 4, n)), T, gas)
+    a, _, _ = _run_series(f, g, gas, steps, False, phi_on,
+                          lambda r, u, e: ((r[0] - rho0) * np.cos(k * x)).sum() * 2 / (n * rho0),
+                          stencil)
+    zc = [i + a[i] / (a[i] - a[i + 1]) for i in range(len(a) - 1) if a[i] * a[i + 1] < 0]
+    omega = np.pi / np.diff(zc).mean()
+    pk = [i for i in range(1, len(a) - 1) if abs(a[i]) >= abs(a[i - 1]) and abs(a[i]) >= abs(a[i + 1])]
+    damping = -np.polyfit(np.array(pk), np.log(np.abs(a[pk])), 1)[0]
+    nu = gas.mu / rho0
+    return omega / (np.sqrt(GAMMA * R * T0) * k), damping / (nu * k * k)
+
+
+def test_adiabatic_sound_speed():
+    # c_s^2 = gamma R T for the ideal gas (Sec. II A thermodynamic sound speed)
+    speed, _ = _acoustic(1.0, True)
+    assert speed == pytest.approx(1.0, abs=3e-3)
+
+
+@pytest.mark.parametrize("stencil", ["central", "upwind"])
+@pytest.mark.parametrize("T0", [1.0, 0.8])
+def test_acoustic_damping_with_galilean_correction(T0, stencil):
+    # Linearised Navier-Stokes-Fourier limit (Sec. II D) in 2D with eta = mu (2/D - R/c_v) and
+    # Prandtl number 1 (k = mu c_p): the amplitude damping rate of a sound wave is
+    # k^2/(2 rho) [mu (2 - 2/D) + eta + (gamma - 1) mu] = mu k^2 / rho.
+    _, damp = _acoustic(T0, True, stencil=stencil)
+    assert damp == pytest.approx(1.0, abs=1e-2)
+
+
+def test_galilean_correction_is_needed_off_reference_temperature():
+    # Without Phi the third-moment defect 3 rho u (theta - 1/3) corrupts the normal stress
+    # when theta != varsigma^2, so the damping misses the Navier-Stokes value.
+    _, damp_off = _acoustic(0.8, False)
+    assert abs(damp_off - 1.0) > 0.2
+
+
+def test_entropy_mode_thermal_diffusion():
+    # Isobaric temperature perturbation: decays at chi k^2 with chi = k_th/(rho c_p) = mu/rho
+    # at Prandtl number 1.
+    n, steps, eps, T0 = 32, 400, 1e-3, 1.0
+    gas = _gas()
+    k = 2 * np.pi / n
+    x = np.arange(n)
+    T = (T0 * (1 + eps * np.cos(k * x)))[None, :] * np.ones((4, 1))
+    rho = P0 / (R * T)
+    f, g = ddf.init_equilibrium(rho, np.zeros((2, 4, n)), T, gas)
+
+    def probe(r, u, rE):
+        Tn, _, _ = ddf.closure(r, u, rE, gas)
+        return ((Tn[0] - T0) * np.cos(k * x)).sum() * 2 / n
+
+    a, _, _ = _run_series(f, g, gas, steps, False, True, probe)
+    t = np.arange(steps)
+    rate = -np.polyfit(t[100:], np.log(a[100:]), 1)[0]
+    assert rate == pytest.approx(gas.mu / (P0 / (R * T0)) * k * k, rel=2e-2)
+
+
+def test_channel_shear_wave_viscosity_with_walls():
+    # mu = (1/(2 beta) - 1/2) P dt (Sec. II D): shear mode between no-slip walls decays at
+    # (mu/rho) (pi/ny)^2.
+    nx, ny, steps, U = 4, 24, 600, 1e-3
+    gas = _gas(0.8)
+    y = np.arange(ny) + 0.5
+    u = np.zeros((2, ny, nx))
+    u[0] = (U * np.sin(np.pi * y / ny))[:, None]
+    T = np.ones((ny, nx))
+    rho = P0 / (R * T)
+    f, g = ddf.init_equilibrium(rho, u, T, gas)
+    f, g = ddf.run(f, g, gas, steps, walls_y=True)
+    _, un, _ = ddf.moments(f, g)
+    expect = np.exp(-(gas.mu / 1.0) * (np.pi / ny) ** 2 * steps)
+    a = (un[0] * u[0]).sum() / (u[0] ** 2).sum()
+    assert abs(np.log(a) / np.log(expect) - 1.0) < 1e-2
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_conservation_mass_energy_momentum(walls):
+    gas = _gas(0.6)
+    if walls:
+        rho, u, T = inputs.thermal_shear_layer(64, seed=0, ny=32, T0=0.9)
+    else:
+        rho, u = inputs.random_phase_turbulence_2d(32, seed=4)
+        T = 1.0 + 0.05 * np.sin(2 * np.pi * np.arange(32) / 32)[None, :] * np.ones((32, 1))
+    f, g = ddf.init_equilibrium(rho, u, T, gas)
+    m0, e0 = f.sum(), g.sum()
+    from oracle.lattice import velocities
+    c = velocities(2).astype(np.float64)
+    j0 = [(c[:, a, None, None] * f).sum() for a in range(2)]
+    f, g = ddf.run(f, g, gas, 200, walls_y=walls)
+    assert np.isfinite(f).all() and np.isfinite(g).all()
+    assert abs(f.sum() - m0) / m0 < 1e-13
+    assert abs(g.sum() - e0) / e0 < 1e-13
+    if not walls:
+        for a in range(2):
+            assert abs((c[:, a, None, None] * f).sum() - j0[a]) < 1e-12
+
+
+def test_rest_state_and_uniform_flow_are_invariant():
+    gas = _gas()
+    rho = np.full((5, 6), 1.2)
+    T = np.full((5, 6), 0.9)
+    u = np.zeros((2, 5, 6))
+    f0, g0 = ddf.init_equilibrium(rho, u, T, gas)
+    f, g = ddf.run(f0, g0, gas, 10, walls_y=True)
+    np.testing.assert_allclose(f, f0, rtol=1e-13)
+    np.testing.assert_allclose(g, g0, rtol=1e-13)
+    u[0], u[1] = 0.07, -0.03
+    f0, g0 = ddf.init_equilibrium(rho, u, T, gas)
+    f, g = ddf.run(f0, g0, gas, 10, walls_y=False)
+    np.testing.assert_allclose(f, f0, rtol=1e-12)
+    np.testing.assert_allclose(g, g0, rtol=1e-12)
+
+
+def test_upwind_derivative_exact_for_quadratics_and_picks_the_upwind_side():
+    # Second-order one-sided and central differences are exact for quadratics; the side is
+    # chosen by the sign of u.
+    n = 12
+    x = np.arange(n, dtype=np.float64)
+    left = 1.0 + 2.0 * x + 0.5 * x * x          # exact derivative 2 + x
+    right = -3.0 + 0.25 * x * x                 # exact derivative 0.5 x
+    p = np.where(x < 6, left, right)
+    u = np.where(x < 6, 1.0, -1.0)
+    d = ddf.upwind_derivative(p, u, axis=0, wall=True)
+    # u > 0 at x = 2..5 uses only x-2..x (left branch); u < 0 at x = 6..9 only x..x+2
+    np.testing.assert_allclose(d[2:6], 2.0 + x[2:6], rtol=1e-14)
+    np.testing.assert_allclose(d[6:10], 0.5 * x[6:10], rtol=1e-14)
+    # central where u = 0
+    q = 1.0 + 2.0 * x + 0.5 * x * x
+    dc = ddf.upwind_derivative(q, np.zeros(n), axis=0, wall=True)
+    np.testing.assert_allclose(dc[1:-1], 2.0 + x[1:-1], rtol=1e-14)
+    # walls: zero-order extrapolated ghosts, so a constant stays flat to the edge
+    dz = ddf.upwind_derivative(np.full(n, 3.0), np.ones(n), axis=0, wall=True)
+    assert np.all(dz == 0.0)
+
+
+def test_upwind_derivative_converges_second_order_periodic():
+    errs = []
+    for n in (32, 64):
+        x = np.arange(n)
+        k = 2 * np.pi / n
+        p = np.sin(k * x)
+        d = ddf.upwind_derivative(p, np.ones(n), axis=0, wall=False)
+        errs.append(np.abs(d - k * np.cos(k * x)).max() / k)
+    assert 3.6 < errs[0] / errs[1] < 4.4
+
+
+def test_galilean_correction_vanishes_at_rest_and_is_cubic_at_reference_temperature():
+    rng = np.random.default_rng(0)
+    rho = rng.uniform(0.8, 1.2, (6, 7))
+    theta = rng.uniform(0.3, 0.36, (6, 7))
+    assert np.all(ddf.galilean_correction(rho, np.zeros((2, 6, 7)), theta, True) == 0.0)
+    # theta = 1/3: phi_a = rho u_a^3; a uniform u gives d_a(rho) u^3 only
+    u = np.full((2, 6, 7), 0.1)
+    rho_lin = np.ones((6, 7)) * (1.0 + 0.01 * np.arange(7))[None, :]
+    Phi = ddf.galilean_correction(rho_lin, u, np.full((6, 7), 1.0 / 3.0), False)
+    np.testing.assert_allclose(Phi[0][:, 1:-1], -(0.01 * 0.1 ** 3) / rho_lin[:, 1:-1], rtol=1e-9)
+    Phi_u = ddf.galilean_correction(rho_lin, u, np.full((6, 7), 1.0 / 3.0), False, "upwind")
+    np.testing.assert_allclose(Phi_u[0][:, 2:], -(0.01 * 0.1 ** 3) / rho_lin[:, 2:], rtol=1e-9)
+    np.testing.assert_allclose(Phi[1], 0.0, atol=1e-18)
