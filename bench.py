@@ -1,0 +1,186 @@
+"""Benchmark of the lattice Boltzmann collide-and-stream path on one MI355X.
+
+Headline workload: D2Q9 isothermal BGK, 2048 x 2048 periodic, float32, tau = 0.6, random-phase
+k^-5/3 decaying turbulence (seed 0, rms Mach 0.05), synthetic input. One step = one fused pull
+stream-collide launch over the whole lattice. Prints ONE JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-variants] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "counters_d2q9_bgk_fp32_2048.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2609_28679_amd", "csrc", "bgk.hip")
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def source_digest(path):
+    import hashlib
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def counter_traffic(nodes):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on
+    the current kernel source; None otherwise."""
+    if not os.path.exists(PROFILE_COUNTERS):
+        return None
+    kv = {}
+    for line in open(PROFILE_COUNTERS):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != source_digest(KERNEL_SOURCE):
+        return None
+    if int(kv.get("nodes", -1)) != nodes:
+        return None
+    return float(kv["hbm_bytes_per_launch"])
+
+
+def time_lattice(lat, steps, warmup):
+    """(wall seconds for exactly `steps` steps bracketed by synchronisation, event ms)."""
+    import torch
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms = lat.time_steps(steps)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, ms
+
+
+def variant(name, make, steps, warmup, bytes_per_node, extra=None):
+    import torch
+    lat = make()
+    wall, ms = time_lattice(lat, steps, warmup)
+    nodes = lat.nodes
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    per_launch_s = ms / 1e3 / steps
+    gbs = bytes_per_node * nodes / per_launch_s / 1e9
+    out = {"mlups": round(nodes * steps / wall / 1e6, 1),
+           "kernel_us": round(per_launch_s * 1e6, 2),
+           "algorithmic_GBs": round(gbs, 1),
+           "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+           "bytes_per_node": bytes_per_node}
+    if extra:
+        out.update(extra)
+    log("%s: %s" % (name, out))
+    return out
+
+
+def cpu_baseline():
+    """The FP64 NumPy oracle on a bounded sample of the headline workload."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import bgk
+    from paper_2609_28679_amd import inputs
+    n, steps = 2048, 4
+    rho, u = inputs.random_phase_turbulence_2d(n, seed=0)
+    f = bgk.init_equilibrium(rho, u)
+    omega = bgk.omega_from_tau_lb(0.6)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        bgk.run(f, omega, steps)
+        dt = time.perf_counter() - t0
+    return {"value": round(n * n * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": 1,
+            "kind": "oracle",
+            "sample": "D2Q9 FP64 NumPy oracle, 2048x2048 turbulence, tau 0.6, %d steps "
+                      "(%.1f s, one thread; host has %d CPUs)" % (steps, dt, os.cpu_count())}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the lattice is not sharded across GPUs in this "
+              "library (see DESIGN.md for how it would shard); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2609_28679_amd import binding, inputs
+
+    torch.cuda.set_device(0)
+    binding.load()
+    n, tau = 2048, 0.6
+    log("headline: D2Q9 FP32 %dx%d tau %g, warmup %d, steps %d" % (n, n, tau, args.warmup, args.steps))
+    rho, u = inputs.random_phase_turbulence_2d(n, seed=0)
+    lat = binding.Lattice(rho, u, tau=tau)
+    nodes = lat.nodes
+    wall, ms = time_lattice(lat, args.steps, args.warmup)
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    mlups = nodes * args.steps / wall / 1e6
+    per_launch_s = ms / 1e3 / args.steps
+    bytes_per_node = 72
+    achieved = bytes_per_node * nodes / per_launch_s / 1e9
+    traffic = counter_traffic(nodes)
+    log("headline: %.1f MLUPS, kernel %.2f us, %.1f GB/s" % (mlups, per_launch_s * 1e6, achieved))
+
+    variants = {}
+    if not args.no_variants:
+        vs = max(200, min(args.steps, 2000))
+        n4 = 4096
+        rho4, u4 = inputs.random_phase_turbulence_2d(n4, seed=0)
+        variants["d2q9_bgk_fp32_4096"] = variant(
+            "d2q9_bgk_fp32_4096", lambda: binding.Lattice(rho4, u4, tau=tau), vs, 20, 72)
+        del rho4, u4
+        r3, u3 = inputs.taylor_green_3d(256, 0.05)
+        variants["d3q27_bgk_fp32_256"] = variant(
+            "d3q27_bgk_fp32_256",
+            lambda: binding.Lattice(r3, u3, lattice="D3Q27", tau=0.55, diag_every=100),
+            max(100, vs // 10), 10, 216, {"diag_every": 100})
+        del r3, u3
+        variants["d2q9_bgk_fp64_2048"] = variant(
+            "d2q9_bgk_fp64_2048", lambda: binding.Lattice(rho, u, tau=tau, storage="fp64"),
+            max(200, vs // 4), 20, 144)
+
+    line = {
+        "metric": "MLUPS + % HBM roofline, plain FP32 vs reduced-storage vs surrogate at stated rel-L2",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "D2Q9 BGK 2048x2048 periodic FP32, tau 0.6, random-phase "
+                               "k^-5/3 turbulence (seed 0, rms Mach 0.05)",
+                   "lattice": "D2Q9", "nx": n, "ny": n, "tau": tau, "storage": "fp32",
+                   "parity": "velocity rel-L2 <= 1e-5 vs FP64 oracle (tests/test_gpu_bgk.py)"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic},
+        "variants": variants,
+    }
+    if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

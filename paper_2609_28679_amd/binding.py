@@ -1,0 +1,283 @@
+"""Thin ctypes binding of liblbm.so (names mirror include/lbm.h).
+
+Only argument marshalling happens here: every step of the lattice Boltzmann path runs in the
+HIP kernels of the library. PyTorch provides device memory (the context workspace) and the
+HIP stream. There is no CPU fallback: if the library is missing, loading fails loudly.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm.so")
+
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
+LATTICES = {"D2Q9": 0, "D3Q27": 1}
+MODELS = {"bgk": 0, "ddf": 1}
+STORAGES = {"fp32": 0, "bf16": 1, "fp16": 2, "fp64": 3}
+COLLISIONS = {"plain": 0, "mlp": 1}
+MLP_NPARAM = 5577
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("lbm error %d: %s" % (code, msg))
+        self.code = code
+
+
+class LbmParams(ctypes.Structure):
+    _fields_ = [
+        ("lattice", ctypes.c_int32), ("model", ctypes.c_int32), ("storage", ctypes.c_int32),
+        ("collision", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("nz", ctypes.c_int32), ("wall_y", ctypes.c_int32), ("tau", ctypes.c_double),
+        ("R", ctypes.c_double), ("cv", ctypes.c_double), ("phi", ctypes.c_int32),
+        ("fp16_scale_log2", ctypes.c_int32), ("diag_every", ctypes.c_int32),
+        ("mlp_tol", ctypes.c_double), ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+
+_P = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+_F = ctypes.POINTER(ctypes.c_float)
+_I64 = ctypes.c_int64
+
+# exported symbol -> (restype, argtypes)
+SIGNATURES = {
+    "lbm_default_params": (None, [ctypes.POINTER(LbmParams)]),
+    "lbm_workspace_size": (ctypes.c_int, [ctypes.POINTER(LbmParams), ctypes.POINTER(ctypes.c_size_t)]),
+    "lbm_create": (ctypes.c_int, [ctypes.POINTER(LbmParams), _D, _D, _D, ctypes.POINTER(_P)]),
+    "lbm_step": (ctypes.c_int, [_P, _I64]),
+    "lbm_time_steps": (ctypes.c_int, [_P, _I64, _F]),
+    "lbm_moments": (ctypes.c_int, [_P, _D, _D, _D, _D]),
+    "lbm_populations": (ctypes.c_int, [_P, _D, _D]),
+    "lbm_time": (ctypes.c_int, [_P, ctypes.POINTER(_I64)]),
+    "lbm_diag_history": (ctypes.c_int, [_P, _D, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "lbm_set_mlp": (ctypes.c_int, [_P, _F, ctypes.c_double]),
+    "lbm_mlp_stats": (ctypes.c_int, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
+    "lbm_harvest": (ctypes.c_int, [_P, _I64, _P, _P, _P]),
+    "lbm_mlp_create": (ctypes.c_int, [_F, _P, ctypes.POINTER(_P)]),
+    "lbm_mlp_destroy": (None, [_P]),
+    "lbm_mlp_get": (ctypes.c_int, [_P, _F]),
+    "lbm_mlp_forward": (ctypes.c_int, [_P, _P, _I64, _P]),
+    "lbm_mlp_grad": (ctypes.c_int, [_P, _P, _P, _I64, _P, _F]),
+    "lbm_mlp_train": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.c_int32, _I64, ctypes.c_float]),
+    "lbm_last_error": (ctypes.c_char_p, [_P]),
+    "lbm_destroy": (None, [_P]),
+}
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Load liblbm.so and declare its signatures. Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("liblbm.so not found at %s: build it with paper_2609_28679_amd.build"
+                          % path)
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_D) if a is not None else None
+
+
+def _check(rc, ctx=None):
+    if rc != LBM_OK:
+        msg = load().lbm_last_error(ctx)
+        raise LbmError(rc, msg.decode() if msg else "")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def current_stream_handle():
+    torch = _torch()
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Lattice:
+    """One lattice Boltzmann context on the current HIP device.
+
+    rho0: (ny, nx) or (nz, ny, nx) float64; u0: (D,) + that shape; T0 for the DDF model.
+    The context workspace is a torch uint8 tensor on the current device; launches go on
+    torch's current stream.
+    """
+
+    def __init__(self, rho0, u0, T0=None, *, lattice="D2Q9", model="bgk", storage="fp32",
+                 collision="plain", wall_y=False, tau=0.8, R=1.0 / 3.0, cv=5.0 / 6.0, phi=1,
+                 fp16_scale_log2=16, diag_every=0, mlp_tol=0.05, torch_workspace=True):
+        torch = _torch()
+        lib = load()
+        rho0 = np.ascontiguousarray(rho0, dtype=np.float64)
+        u0 = np.ascontiguousarray(u0, dtype=np.float64)
+        D = 2 if lattice == "D2Q9" else 3
+        if rho0.ndim == 2:
+            nz, (ny, nx) = 1, rho0.shape
+        else:
+            nz, ny, nx = rho0.shape
+        if u0.shape != (D,) + rho0.shape:
+            raise ValueError("u0 must have shape %s" % ((D,) + rho0.shape,))
+        self.D, self.Q = D, 3 ** D
+        self.shape = rho0.shape
+        self.nodes = rho0.size
+        self.model = model
+        p = LbmParams()
+        lib.lbm_default_params(ctypes.byref(p))
+        p.lattice = LATTICES[lattice]
+        p.model = MODELS[model]
+        p.storage = STORAGES[storage]
+        p.collision = COLLISIONS[collision]
+        p.nx, p.ny, p.nz = nx, ny, nz
+        p.wall_y = int(bool(wall_y))
+        p.tau, p.R, p.cv, p.phi = float(tau), float(R), float(cv), int(phi)
+        p.fp16_scale_log2 = int(fp16_scale_log2)
+        p.diag_every = int(diag_every)
+        p.mlp_tol = float(mlp_tol)
+        p.stream = current_stream_handle()
+        self._ws = None
+        if torch_workspace:
+            nbytes = ctypes.c_size_t(0)
+            _check(lib.lbm_workspace_size(ctypes.byref(p), ctypes.byref(nbytes)))
+            self._ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device="cuda")
+            p.workspace = self._ws.data_ptr()
+            p.workspace_bytes = nbytes.value
+        self.params = p
+        T = None if T0 is None else np.ascontiguousarray(T0, dtype=np.float64)
+        ctx = _P()
+        _check(lib.lbm_create(ctypes.byref(p), _dptr(rho0), _dptr(u0), _dptr(T), ctypes.byref(ctx)))
+        self.ctx = ctx
+
+    # -- hot path --------------------------------------------------------------------------
+    def step(self, n=1):
+        _check(load().lbm_step(self.ctx, int(n)), self.ctx)
+
+    def time_steps(self, n):
+        ms = ctypes.c_float(0.0)
+        _check(load().lbm_time_steps(self.ctx, int(n), ctypes.byref(ms)), self.ctx)
+        return float(ms.value)
+
+    # -- read-out --------------------------------------------------------------------------
+    def moments(self):
+        rho = np.empty(self.shape)
+        u = np.empty((self.D,) + self.shape)
+        T = np.empty(self.shape) if self.model == "ddf" else None
+        totals = np.empty(5)
+        _check(load().lbm_moments(self.ctx, _dptr(rho), _dptr(u), _dptr(T), _dptr(totals)), self.ctx)
+        return rho, u, T, totals
+
+    def populations(self):
+        f = np.empty((self.Q,) + self.shape)
+        g = np.empty((self.Q,) + self.shape) if self.model == "ddf" else None
+        _check(load().lbm_populations(self.ctx, _dptr(f), _dptr(g)), self.ctx)
+        return f, g
+
+    @property
+    def t(self):
+        t = _I64(0)
+        _check(load().lbm_time(self.ctx, ctypes.byref(t)), self.ctx)
+        return int(t.value)
+
+    def diag_history(self, max_entries=4096):
+        out = np.empty((max_entries, 6))
+        n = ctypes.c_int32(0)
+        _check(load().lbm_diag_history(self.ctx, _dptr(out), max_entries, ctypes.byref(n)), self.ctx)
+        return out[: n.value].copy()
+
+    # -- surrogate -------------------------------------------------------------------------
+    def set_mlp(self, weights, tol):
+        w = np.ascontiguousarray(weights, dtype=np.float32)
+        if w.size != MLP_NPARAM:
+            raise ValueError("expected %d parameters" % MLP_NPARAM)
+        _check(load().lbm_set_mlp(self.ctx, w.ctypes.data_as(_F), float(tol)), self.ctx)
+
+    def mlp_stats(self):
+        fb, up = _I64(0), _I64(0)
+        _check(load().lbm_mlp_stats(self.ctx, ctypes.byref(fb), ctypes.byref(up)), self.ctx)
+        return int(fb.value), int(up.value)
+
+    def harvest(self, nodes_dev, x_dev, y_dev):
+        """nodes_dev: int64 cuda tensor; x_dev (n, 12), y_dev (n, 9): float32 cuda tensors."""
+        n = nodes_dev.numel()
+        _check(load().lbm_harvest(self.ctx, n, nodes_dev.data_ptr(), x_dev.data_ptr(),
+                                  y_dev.data_ptr()), self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            load().lbm_destroy(self.ctx)
+            self.ctx = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Trainer:
+    """Surrogate trainer: float32 master weights and Adam state on the device."""
+
+    def __init__(self, weights):
+        w = np.ascontiguousarray(weights, dtype=np.float32)
+        if w.size != MLP_NPARAM:
+            raise ValueError("expected %d parameters" % MLP_NPARAM)
+        h = _P()
+        _check(load().lbm_mlp_create(w.ctypes.data_as(_F), current_stream_handle(), ctypes.byref(h)))
+        self.h = h
+
+    def weights(self):
+        w = np.empty(MLP_NPARAM, dtype=np.float32)
+        _check(load().lbm_mlp_get(self.h, w.ctypes.data_as(_F)))
+        return w
+
+    def forward(self, x_dev, y_dev):
+        _check(load().lbm_mlp_forward(self.h, x_dev.data_ptr(), x_dev.shape[0], y_dev.data_ptr()))
+
+    def grad(self, x_dev, t_dev, grad_dev, want_loss=True):
+        loss = ctypes.c_float(0.0)
+        _check(load().lbm_mlp_grad(self.h, x_dev.data_ptr(), t_dev.data_ptr(), x_dev.shape[0],
+                                   grad_dev.data_ptr(), ctypes.byref(loss) if want_loss else None))
+        return float(loss.value) if want_loss else None
+
+    def train(self, x_dev, t_dev, batch, steps, lr=1e-3):
+        _check(load().lbm_mlp_train(self.h, x_dev.data_ptr(), t_dev.data_ptr(), x_dev.shape[0],
+                                    int(batch), int(steps), float(lr)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().lbm_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pack_mlp(params):
+    """[W1, b1, W2, b2, W3, b3] -> float32 blob in the library's layout."""
+    return np.concatenate([np.asarray(p, dtype=np.float64).ravel() for p in params]).astype(np.float32)
+
+
+def unpack_mlp(blob):
+    b = np.asarray(blob, dtype=np.float64)
+    shapes = [(64, 12), (64,), (64, 64), (64,), (9, 64), (9,)]
+    out, k = [], 0
+    for s in shapes:
+        n = int(np.prod(s))
+        out.append(b[k:k + n].reshape(s))
+        k += n
+    return out

@@ -1,0 +1,390 @@
+// Isothermal fused pull stream-collide kernels (D2Q9 and D3Q27), float32 or float64 storage.
+//
+// One launch advances one time step of Eq. (LBM_f) of Sec. II C with f* = f^eq and
+// theta = varsigma^2 = 1/3 (no force, isothermal):
+//   buffer A holds the post-collision populations f~(t-1), stored shifted by the rest
+//   equilibrium, h_i = f_i - w_i with w_i = f_i^eq(rho = 1, u = 0): h is O(Mach), so float32
+//   storage keeps ~7 significant digits of the part that carries the flow instead of the
+//   part that is constant;
+//   pull:     f_i(x, t) = f~_i(x - c_i, t-1)  (periodic wrap, or half-way bounce-back
+//             f_i(x, t) = f~_ibar(x, t-1) where x - c_i lies beyond a y wall);
+//   moments:  rho = sum f_i, rho u = sum c_i f_i;
+//   equilibrium: f_i^eq = rho prod_a Psi_ia(u_a, theta + u_a^2) (Sec. II C);
+//   relax:    f~_i = f_i + omega (f_i^eq - f_i), omega = 2 beta (Sec. II B);
+//   store f~(t) into buffer B (non-temporal: it is not read again by this launch).
+// All arithmetic is float64 whatever the storage type: on this chip double-precision vector
+// FMA runs at the same rate as unpacked single precision, and float64 arithmetic removes the
+// coherent rounding drift that float32 arithmetic adds to every collision (the division
+// u = j / rho and the linear-in-u equilibrium terms round with a bias that accumulates in
+// the decay of a Taylor-Green mode at ~1.6e-8 per step).
+// Optional float64 conservation totals per workgroup (mass, momentum, kinetic energy of the
+// moments at time t) for the diagnostics.
+#include "device_common.h"
+
+namespace lbm {
+
+// Psi(c; u, theta + u^2) for c = -1, 0, +1 at theta = 1/3 (Sec. II C).
+__device__ __forceinline__ void psi3(double u, double (&p)[3]) {
+  const double u2 = u * u;
+  p[1] = (2.0 / 3.0) - u2;               // c = 0:  1 - theta - u^2
+  p[2] = (1.0 / 6.0) + 0.5 * (u2 + u);   // c = +1: (theta + u^2 + u) / 2
+  p[0] = (1.0 / 6.0) + 0.5 * (u2 - u);   // c = -1: (theta + u^2 - u) / 2
+}
+
+// Rest weights w_i = prod_a Psi(c_ia; 0, 1/3) as a function of the per-axis index k = c + 1.
+__device__ __forceinline__ double w1(int k) { return k == 1 ? 2.0 / 3.0 : 1.0 / 6.0; }
+
+// ---- D2Q9 ---------------------------------------------------------------------------------
+template <typename S, bool WALLS, bool DIAG>
+__global__ void __launch_bounds__(kBlock)
+k_bgk_d2q9(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int64_t pitch,
+           int64_t plane, double omega, int rows, double* __restrict__ partials) {
+  const int nbx = gridDim.x;
+  const int tile = xcd_tile(blockIdx.x + nbx * blockIdx.y, nbx * gridDim.y);
+  const int bx = tile % nbx;
+  const int by = tile / nbx;
+  const int x = bx * blockDim.x + threadIdx.x;
+  const int y0 = by * rows;
+  double acc[kDiagValues] = {0.0, 0.0, 0.0, 0.0, 0.0};
+
+  if (x < nx) {
+    const int xm = x == 0 ? nx - 1 : x - 1;
+    const int xp = x == nx - 1 ? 0 : x + 1;
+    const int yend = min(y0 + rows, ny);
+    for (int y = y0; y < yend; ++y) {
+      const int ym = y == 0 ? ny - 1 : y - 1;
+      const int yp = y == ny - 1 ? 0 : y + 1;
+      const int64_t r0 = (int64_t)y * pitch;
+      const int64_t rm = (int64_t)ym * pitch;
+      const int64_t rp = (int64_t)yp * pitch;
+      S hs[9];
+      // i = (cx+1) + 3(cy+1); source node x - c_i
+      hs[3] = A[3 * plane + r0 + xp];
+      hs[4] = A[4 * plane + r0 + x];
+      hs[5] = A[5 * plane + r0 + xm];
+      if (WALLS && y == ny - 1) {  // c_y = -1 would come from beyond the top wall
+        hs[0] = A[8 * plane + r0 + x];
+        hs[1] = A[7 * plane + r0 + x];
+        hs[2] = A[6 * plane + r0 + x];
+      } else {
+        hs[0] = A[0 * plane + rp + xp];
+        hs[1] = A[1 * plane + rp + x];
+        hs[2] = A[2 * plane + rp + xm];
+      }
+      if (WALLS && y == 0) {  // c_y = +1 would come from below the bottom wall
+        hs[6] = A[2 * plane + r0 + x];
+        hs[7] = A[1 * plane + r0 + x];
+        hs[8] = A[0 * plane + r0 + x];
+      } else {
+        hs[6] = A[6 * plane + rm + xp];
+        hs[7] = A[7 * plane + rm + x];
+        hs[8] = A[8 * plane + rm + xm];
+      }
+      double h[9];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) h[i] = (double)hs[i];
+      // sum w_i = 1 and sum c_i w_i = 0, so rho = 1 + sum h and rho u = sum c h
+      const double rho = 1.0 + (((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8]);
+      const double jx = (h[2] + h[5] + h[8]) - (h[0] + h[3] + h[6]);
+      const double jy = (h[6] + h[7] + h[8]) - (h[0] + h[1] + h[2]);
+      const double ux = jx / rho;
+      const double uy = jy / rho;
+      double px[3], py[3];
+      psi3(ux, px);
+      psi3(uy, py);
+      S* out = B + r0 + x;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        const double heq = rho * px[i % 3] * py[i / 3] - w1(i % 3) * w1(i / 3);
+        store_nt(out + i * plane, (S)(h[i] + omega * (heq - h[i])));
+      }
+      if (DIAG) {
+        acc[0] += rho;
+        acc[1] += jx;
+        acc[2] += jy;
+        acc[4] += 0.5 * rho * (ux * ux + uy * uy);
+      }
+    }
+  }
+  if (DIAG) block_sum_store<kDiagValues>(acc, partials + (int64_t)tile * kDiagValues);
+}
+
+// ---- D3Q27 --------------------------------------------------------------------------------
+template <typename S, bool WALLS, bool DIAG>
+__global__ void __launch_bounds__(kBlock)
+k_bgk_d3q27(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int nz, int64_t pitch,
+            int64_t plane, double omega, int rows, double* __restrict__ partials) {
+  const int nbx = gridDim.x;
+  const int tile = xcd_tile(blockIdx.x + nbx * blockIdx.y, nbx * gridDim.y);
+  const int bx = tile % nbx;
+  const int by = tile / nbx;
+  const int x = bx * blockDim.x + threadIdx.x;
+  const int r_begin = by * rows;
+  double acc[kDiagValues] = {0.0, 0.0, 0.0, 0.0, 0.0};
+
+  if (x < nx) {
+    int xs[3];
+    xs[0] = x == nx - 1 ? 0 : x + 1;  // c_x = -1: source x + 1
+    xs[1] = x;
+    xs[2] = x == 0 ? nx - 1 : x - 1;  // c_x = +1: source x - 1
+    const int r_end = min(r_begin + rows, ny * nz);
+    for (int r = r_begin; r < r_end; ++r) {
+      const int y = r % ny;
+      const int z = r / ny;
+      const int ysrc[3] = {y == ny - 1 ? 0 : y + 1, y, y == 0 ? ny - 1 : y - 1};
+      const int zsrc[3] = {z == nz - 1 ? 0 : z + 1, z, z == 0 ? nz - 1 : z - 1};
+      const int64_t self = ((int64_t)z * ny + y) * pitch + x;
+      double h[27];
+#pragma unroll
+      for (int i = 0; i < 27; ++i) {
+        const int cx = i % 3, cy = (i / 3) % 3, cz = i / 9;  // component + 1
+        const bool bounce = WALLS && ((cy == 2 && y == 0) || (cy == 0 && y == ny - 1));
+        if (bounce) {
+          h[i] = (double)A[(26 - i) * plane + self];
+        } else {
+          h[i] = (double)A[i * plane + ((int64_t)zsrc[cz] * ny + ysrc[cy]) * pitch + xs[cx]];
+        }
+      }
+      double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+      for (int i = 0; i < 27; ++i) {
+        const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
+        drho += h[i];
+        if (cx) jx += cx > 0 ? h[i] : -h[i];
+        if (cy) jy += cy > 0 ? h[i] : -h[i];
+        if (cz) jz += cz > 0 ? h[i] : -h[i];
+      }
+      const double rho = 1.0 + drho;
+      const double ux = jx / rho, uy = jy / rho, uz = jz / rho;
+      double px[3], py[3], pz[3];
+      psi3(ux, px);
+      psi3(uy, py);
+      psi3(uz, pz);
+      S* out = B + self;
+#pragma unroll
+      for (int i = 0; i < 27; ++i) {
+        const int a = i % 3, b = (i / 3) % 3, c = i / 9;
+        const double heq = rho * px[a] * py[b] * pz[c] - w1(a) * w1(b) * w1(c);
+        store_nt(out + i * plane, (S)(h[i] + omega * (heq - h[i])));
+      }
+      if (DIAG) {
+        acc[0] += rho;
+        acc[1] += jx;
+        acc[2] += jy;
+        acc[3] += jz;
+        acc[4] += 0.5 * rho * (ux * ux + uy * uy + uz * uz);
+      }
+    }
+  }
+  if (DIAG) block_sum_store<kDiagValues>(acc, partials + (int64_t)tile * kDiagValues);
+}
+
+// ---- initialisation and read-out -----------------------------------------------------------
+// f_i <- f_i^eq(rho, u) with theta = 1/3 (Fig. 1 initialisation), stored as h = f - w.
+template <typename S>
+__global__ void k_init_bgk(int D, const double* __restrict__ rho, const double* __restrict__ u,
+                           S* __restrict__ A, int nx, int ny, int nz, int64_t pitch,
+                           int64_t plane) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nodes = (int64_t)nx * ny * nz;
+  if (n >= nodes) return;
+  const int x = (int)(n % nx);
+  const int64_t row = n / nx;
+  const int64_t off = row * pitch + x;
+  double p[3][3];
+  for (int a = 0; a < D; ++a) psi3(u[a * nodes + n], p[a]);
+  const int Q = D == 2 ? 9 : 27;
+  for (int i = 0; i < Q; ++i) {
+    const int ka = i % 3, kb = (i / 3) % 3, kc = i / 9;
+    double v = rho[n] * p[0][ka] * p[1][kb];
+    double w = w1(ka) * w1(kb);
+    if (D == 3) {
+      v *= p[2][kc];
+      w *= w1(kc);
+    }
+    A[i * plane + off] = (S)(v - w);
+  }
+}
+
+// Moments of the stored post-collision state: the collision conserves rho and rho u, so these
+// equal the moments of the pre-collision populations at the same time.
+template <typename S>
+__global__ void k_moments_bgk(int D, const S* __restrict__ A, int nx, int ny, int nz,
+                              int64_t pitch, int64_t plane, double* __restrict__ rho,
+                              double* __restrict__ u) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nodes = (int64_t)nx * ny * nz;
+  if (n >= nodes) return;
+  const int x = (int)(n % nx);
+  const int64_t off = (n / nx) * pitch + x;
+  const int Q = D == 2 ? 9 : 27;
+  double s = 0.0, j[3] = {0.0, 0.0, 0.0};
+  for (int i = 0; i < Q; ++i) {
+    const double v = (double)A[i * plane + off];
+    s += v;
+    const int c[3] = {i % 3 - 1, (i / 3) % 3 - 1, i / 9 - 1};
+    for (int a = 0; a < D; ++a) j[a] += c[a] * v;
+  }
+  const double r = 1.0 + s;
+  rho[n] = r;
+  for (int a = 0; a < D; ++a) u[a * nodes + n] = j[a] / r;
+}
+
+// Population plane i decoded to float64 f_i = h_i + w_i.
+template <typename S>
+__global__ void k_decode_f(int D, int i, const S* __restrict__ Ai, int nx, int64_t nodes,
+                           int64_t pitch, double* __restrict__ f) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nodes) return;
+  const int64_t off = (n / nx) * pitch + (n % nx);
+  double w = w1(i % 3) * w1((i / 3) % 3);
+  if (D == 3) w *= w1(i / 9);
+  f[n] = (double)Ai[off] + w;
+}
+
+// ---- diagnostics ---------------------------------------------------------------------------
+__global__ void k_diag_finalize(const double* __restrict__ partials, int nblocks, double t,
+                                double* __restrict__ out) {
+  double v[kDiagValues] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+#pragma unroll
+    for (int k = 0; k < kDiagValues; ++k) v[k] += partials[(int64_t)b * kDiagValues + k];
+  __shared__ double tot[kDiagValues];
+  block_sum_store<kDiagValues>(v, tot);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out[0] = t;
+#pragma unroll
+    for (int k = 0; k < kDiagValues; ++k) out[1 + k] = tot[k];
+  }
+}
+
+__global__ void k_field_totals(int D, const double* __restrict__ rho, const double* __restrict__ u,
+                               const double* __restrict__ edens, int64_t nodes, int kinetic,
+                               double* __restrict__ partials) {
+  double v[kDiagValues] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nodes;
+       n += (int64_t)gridDim.x * blockDim.x) {
+    const double r = rho[n];
+    double u2 = 0.0;
+    v[0] += r;
+    for (int a = 0; a < D; ++a) {
+      const double ua = u[a * nodes + n];
+      v[1 + a] += r * ua;
+      u2 += ua * ua;
+    }
+    v[4] += kinetic ? 0.5 * r * u2 : edens[n];
+  }
+  block_sum_store<kDiagValues>(v, partials + (int64_t)blockIdx.x * kDiagValues);
+}
+
+// ---- launchers -----------------------------------------------------------------------------
+Grid make_grid(const Layout& L) {
+  Grid G;
+  G.bx = L.nx >= kBlock ? kBlock : ((L.nx + 63) / 64) * 64;
+  G.nbx = (L.nx + G.bx - 1) / G.bx;
+  const int64_t nrows = (int64_t)L.ny * L.nz;
+  // aim for >= 2048 workgroups (8 per compute unit) with at most 16 rows each
+  int64_t rows = (nrows * G.nbx + 2047) / 2048;
+  rows = rows < 1 ? 1 : (rows > 16 ? 16 : rows);
+  G.rows = (int)rows;
+  G.nby = (int)((nrows + rows - 1) / rows);
+  return G;
+}
+
+template <typename R>
+static hipError_t bgk2_(const void* A, void* B, const Layout& L, const Grid& G, double omega,
+                       bool walls, double* partials, hipStream_t s) {
+  dim3 grid(G.nbx, G.nby), block(G.bx);
+  auto a = static_cast<const R*>(A);
+  auto b = static_cast<R*>(B);
+  if (walls) {
+    if (partials)
+      k_bgk_d2q9<R, true, true><<<grid, block, 0, s>>>(a, b, L.nx, L.ny, L.pitch, L.plane, omega, G.rows, partials);
+    else
+      k_bgk_d2q9<R, true, false><<<grid, block, 0, s>>>(a, b, L.nx, L.ny, L.pitch, L.plane, omega, G.rows, nullptr);
+  } else {
+    if (partials)
+      k_bgk_d2q9<R, false, true><<<grid, block, 0, s>>>(a, b, L.nx, L.ny, L.pitch, L.plane, omega, G.rows, partials);
+    else
+      k_bgk_d2q9<R, false, false><<<grid, block, 0, s>>>(a, b, L.nx, L.ny, L.pitch, L.plane, omega, G.rows, nullptr);
+  }
+  return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t bgk3(const void* A, void* B, const Layout& L, const Grid& G, double omega,
+                       bool walls, double* partials, hipStream_t s) {
+  dim3 grid(G.nbx, G.nby), block(G.bx);
+  auto a = static_cast<const R*>(A);
+  auto b = static_cast<R*>(B);
+  if (walls) {
+    if (partials)
+      k_bgk_d3q27<R, true, true><<<grid, block, 0, s>>>(a, b, L.nx, L.ny, L.nz, L.pitch, L.plane, omega, G.rows, partials);
+    else
+      k_bgk_d3q27<R, true, false><<<grid, block, 0, s>>>(a, b, L.nx, L.ny, L.nz, L.pitch, L.plane, omega, G.rows, nullptr);
+  } else {
+    if (partials)
+      k_bgk_d3q27<R, false, true><<<grid, block, 0, s>>>(a, b, L.nx, L.ny, L.nz, L.pitch, L.plane, omega, G.rows, partials);
+    else
+      k_bgk_d3q27<R, false, false><<<grid, block, 0, s>>>(a, b, L.nx, L.ny, L.nz, L.pitch, L.plane, omega, G.rows, nullptr);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_bgk_d2q9(int kind, const void* A, void* B, const Layout& L, const Grid& G,
+                           double omega, bool walls, double* partials, hipStream_t s) {
+  return kind == 0 ? bgk2_<float>(A, B, L, G, omega, walls, partials, s)
+                   : bgk2_<double>(A, B, L, G, omega, walls, partials, s);
+}
+
+hipError_t launch_bgk_d3q27(int kind, const void* A, void* B, const Layout& L, const Grid& G,
+                            double omega, bool walls, double* partials, hipStream_t s) {
+  return kind == 0 ? bgk3<float>(A, B, L, G, omega, walls, partials, s)
+                   : bgk3<double>(A, B, L, G, omega, walls, partials, s);
+}
+
+static inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+hipError_t launch_init_bgk(int kind, int D, const double* rho, const double* u, void* A,
+                           const Layout& L, hipStream_t s) {
+  if (kind == 0)
+    k_init_bgk<float><<<nblk(L.nodes()), kBlock, 0, s>>>(D, rho, u, static_cast<float*>(A), L.nx, L.ny, L.nz, L.pitch, L.plane);
+  else
+    k_init_bgk<double><<<nblk(L.nodes()), kBlock, 0, s>>>(D, rho, u, static_cast<double*>(A), L.nx, L.ny, L.nz, L.pitch, L.plane);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments_bgk(int kind, int D, const void* A, const Layout& L, double* rho,
+                              double* u, hipStream_t s) {
+  if (kind == 0)
+    k_moments_bgk<float><<<nblk(L.nodes()), kBlock, 0, s>>>(D, static_cast<const float*>(A), L.nx, L.ny, L.nz, L.pitch, L.plane, rho, u);
+  else
+    k_moments_bgk<double><<<nblk(L.nodes()), kBlock, 0, s>>>(D, static_cast<const double*>(A), L.nx, L.ny, L.nz, L.pitch, L.plane, rho, u);
+  return hipGetLastError();
+}
+
+hipError_t launch_decode_f(int kind, int D, int i, const void* A, const Layout& L, double* f,
+                           hipStream_t s) {
+  if (kind == 0)
+    k_decode_f<float><<<nblk(L.nodes()), kBlock, 0, s>>>(D, i, static_cast<const float*>(A) + (int64_t)i * L.plane, L.nx, L.nodes(), L.pitch, f);
+  else
+    k_decode_f<double><<<nblk(L.nodes()), kBlock, 0, s>>>(D, i, static_cast<const double*>(A) + (int64_t)i * L.plane, L.nx, L.nodes(), L.pitch, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag_finalize(const double* partials, int nblocks, double t, double* out,
+                                hipStream_t s) {
+  k_diag_finalize<<<1, kBlock, 0, s>>>(partials, nblocks, t, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_field_totals(int D, const double* rho, const double* u, const double* edens,
+                               int64_t nodes, bool kinetic, double* partials, int nparts,
+                               double* out, hipStream_t s) {
+  k_field_totals<<<nparts, kBlock, 0, s>>>(D, rho, u, edens, nodes, kinetic ? 1 : 0, partials);
+  k_diag_finalize<<<1, kBlock, 0, s>>>(partials, nparts, 0.0, out);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

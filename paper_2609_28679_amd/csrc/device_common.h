@@ -1,0 +1,58 @@
+// Device-side helpers shared by the HIP kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "lbm_internal.h"
+
+namespace lbm {
+
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup b runs on XCD b % 8). Remap
+// the hardware order so that each XCD owns one contiguous range of tiles: neighbouring tiles
+// then share the XCD's L2 for their halo rows.
+__device__ __forceinline__ int xcd_tile(int b, int nblocks) {
+  const int per = nblocks / kNumXcd;
+  const int rem = nblocks % kNumXcd;
+  const int xcd = b % kNumXcd;
+  const int k = b / kNumXcd;
+  return xcd < rem ? xcd * (per + 1) + k : rem * (per + 1) + (xcd - rem) * per + k;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Deterministic workgroup sum of N doubles per thread; thread 0 writes out[0..N).
+template <int N>
+__device__ __forceinline__ void block_sum_store(double (&v)[N], double* out) {
+  __shared__ double red[kBlock / 64][N];
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) red[wid][k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s += red[w][k];
+      out[k] = s;
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void store_nt(T* p, T v) {
+  __builtin_nontemporal_store(v, p);
+}
+
+}  // namespace lbm

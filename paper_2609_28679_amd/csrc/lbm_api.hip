@@ -1,0 +1,404 @@
+// C-ABI host layer: parameter validation, device memory ownership, launch sequencing,
+// diagnostics bookkeeping and error reporting. All numerical work runs in the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_internal.h"
+
+using namespace lbm;
+
+namespace {
+thread_local std::string g_err;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+}  // namespace
+
+struct lbm_ctx {
+  lbm_params p{};
+  int D = 2, Q = 9;
+  int kind = 0;  // 0: float32 populations, 1: float64
+  Layout L{};
+  Grid G{};
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool own_ws = false;
+  void* A = nullptr;  // post-collision populations of the current time
+  void* B = nullptr;
+  double* partials = nullptr;  // per-workgroup diagnostics partial sums
+  int partial_slots = 0;
+  double* history = nullptr;   // ring of kHistoryCap rows {t, totals[5]}
+  double* readout = nullptr;   // nodes * (D + 2) doubles for moment read-out
+  int64_t hist_written = 0;
+  int64_t t = 0;
+  double omega = 0.0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::string err;
+};
+
+namespace {
+
+int fail(lbm_ctx* c, int code, const std::string& msg) {
+  if (c)
+    c->err = msg;
+  else
+    g_err = msg;
+  return code;
+}
+
+int hip_fail(lbm_ctx* c, hipError_t e, const char* where) {
+  return fail(c, LBM_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, expr)                                  \
+  do {                                                      \
+    hipError_t e_ = (expr);                                 \
+    if (e_ != hipSuccess) return hip_fail((ctx), e_, #expr); \
+  } while (0)
+
+struct Plan {
+  int D, Q, kind;
+  Layout L;
+  Grid G;
+  size_t elem;
+  size_t off_A, off_B, off_part, off_hist, off_read, total;
+  int partial_slots;
+};
+
+int validate(const lbm_params* p, std::string& why) {
+  if (!p) { why = "params is NULL"; return LBM_EINVAL; }
+  if (p->lattice != LBM_D2Q9 && p->lattice != LBM_D3Q27) { why = "lattice must be D2Q9 or D3Q27"; return LBM_EINVAL; }
+  if (p->model != LBM_MODEL_BGK && p->model != LBM_MODEL_DDF) { why = "unknown model"; return LBM_EINVAL; }
+  if (p->storage < LBM_STORE_FP32 || p->storage > LBM_STORE_FP64) { why = "unknown storage"; return LBM_EINVAL; }
+  if (p->collision != LBM_COLLIDE_PLAIN && p->collision != LBM_COLLIDE_MLP) { why = "unknown collision"; return LBM_EINVAL; }
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) { why = "lattice sizes must be >= 1"; return LBM_EINVAL; }
+  if (p->lattice == LBM_D2Q9 && p->nz != 1) { why = "D2Q9 requires nz = 1"; return LBM_EINVAL; }
+  if ((int64_t)p->nx * p->ny * p->nz > (int64_t)1 << 34) { why = "lattice too large"; return LBM_EINVAL; }
+  if (p->wall_y != 0 && p->wall_y != 1) { why = "wall_y must be 0 or 1"; return LBM_EINVAL; }
+  if (!(p->tau > 0.5) || !std::isfinite(p->tau)) { why = "tau must be a finite value > 1/2"; return LBM_EINVAL; }
+  if (p->diag_every < 0) { why = "diag_every must be >= 0"; return LBM_EINVAL; }
+  if (p->model != LBM_MODEL_BGK) { why = "model not supported by this build"; return LBM_EINVAL; }
+  if (p->storage != LBM_STORE_FP32 && p->storage != LBM_STORE_FP64) { why = "storage not supported for this model"; return LBM_EINVAL; }
+  if (p->collision != LBM_COLLIDE_PLAIN) { why = "collision not supported for this configuration"; return LBM_EINVAL; }
+  if (p->workspace && (reinterpret_cast<uintptr_t>(p->workspace) & 255u)) { why = "workspace must be 256-byte aligned"; return LBM_EINVAL; }
+  return LBM_OK;
+}
+
+void make_plan(const lbm_params* p, Plan& P) {
+  P.D = p->lattice == LBM_D2Q9 ? 2 : 3;
+  P.Q = P.D == 2 ? 9 : 27;
+  P.kind = p->storage == LBM_STORE_FP64 ? 1 : 0;
+  P.elem = P.kind ? 8 : 4;
+  P.L.nx = p->nx;
+  P.L.ny = p->ny;
+  P.L.nz = p->nz;
+  P.L.pitch = (int64_t)align_up((size_t)p->nx, 64);
+  // planes padded to a 4 KiB multiple plus 1 KiB so the Q read streams start on different
+  // HBM channels instead of all aliasing to the same one
+  const int64_t raw = P.L.pitch * p->ny * p->nz;
+  const int64_t epk = (int64_t)(4096 / P.elem);
+  P.L.plane = (raw + epk - 1) / epk * epk + epk / 4;
+  P.G = make_grid(P.L);
+  P.partial_slots = std::max(P.G.blocks(), 1024);
+  size_t off = 0;
+  const size_t pop = (size_t)P.Q * P.L.plane * P.elem;
+  P.off_A = off; off = align_up(off + pop, 256);
+  P.off_B = off; off = align_up(off + pop, 256);
+  P.off_part = off; off = align_up(off + (size_t)P.partial_slots * kDiagValues * 8, 256);
+  P.off_hist = off; off = align_up(off + (size_t)kHistoryCap * 6 * 8, 256);
+  P.off_read = off; off = align_up(off + (size_t)P.L.nodes() * (P.D + 2) * 8, 256);
+  P.total = off;
+}
+
+// Product-form factors must be positive: Psi_0 = 1 - theta - u^2 > 0 and
+// Psi_+- = (theta + u^2 +- u)/2 > 0 for every component.
+bool admissible(double theta, double u) {
+  const double z = theta + u * u;
+  return z < 1.0 && z > std::fabs(u);
+}
+
+}  // namespace
+
+extern "C" {
+
+void lbm_default_params(lbm_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->lattice = LBM_D2Q9;
+  p->model = LBM_MODEL_BGK;
+  p->storage = LBM_STORE_FP32;
+  p->collision = LBM_COLLIDE_PLAIN;
+  p->nx = 64;
+  p->ny = 64;
+  p->nz = 1;
+  p->wall_y = 0;
+  p->tau = 0.8;
+  p->R = 1.0 / 3.0;
+  p->cv = 5.0 / 6.0;
+  p->phi = 1;
+  p->fp16_scale_log2 = 16;
+  p->diag_every = 0;
+  p->mlp_tol = 0.05;
+  p->stream = nullptr;
+  p->workspace = nullptr;
+  p->workspace_bytes = 0;
+}
+
+int lbm_workspace_size(const lbm_params* p, size_t* bytes) {
+  std::string why;
+  int rc = validate(p, why);
+  if (rc) return fail(nullptr, rc, why);
+  if (!bytes) return fail(nullptr, LBM_EINVAL, "bytes is NULL");
+  Plan P;
+  make_plan(p, P);
+  *bytes = P.total;
+  return LBM_OK;
+}
+
+int lbm_create(const lbm_params* p, const double* rho0, const double* u0, const double* T0,
+               lbm_ctx** out) {
+  if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  std::string why;
+  int rc = validate(p, why);
+  if (rc) return fail(nullptr, rc, why);
+  if (!rho0 || !u0) return fail(nullptr, LBM_EINVAL, "rho0 and u0 are required");
+  (void)T0;
+  Plan P;
+  make_plan(p, P);
+  const int64_t nodes = P.L.nodes();
+  // host-side admissibility of the initial state
+  for (int64_t n = 0; n < nodes; ++n) {
+    if (!(rho0[n] > 0.0) || !std::isfinite(rho0[n]))
+      return fail(nullptr, LBM_EINVAL, "initial density must be finite and positive at node " + std::to_string(n));
+    for (int a = 0; a < P.D; ++a) {
+      const double ua = u0[a * nodes + n];
+      if (!std::isfinite(ua) || !admissible(1.0 / 3.0, ua))
+        return fail(nullptr, LBM_EINVAL, "initial velocity outside the positive product-form range at node " + std::to_string(n));
+    }
+  }
+  lbm_ctx* c = new lbm_ctx();
+  c->p = *p;
+  c->D = P.D;
+  c->Q = P.Q;
+  c->kind = P.kind;
+  c->L = P.L;
+  c->G = P.G;
+  c->stream = static_cast<hipStream_t>(p->stream);
+  c->omega = 1.0 / p->tau;  // omega = 2 beta = 1/tau_LB
+  c->partial_slots = P.partial_slots;
+  auto cleanup_fail = [&](int code) {
+    std::string m = c->err;
+    lbm_destroy(c);
+    return fail(nullptr, code, m);
+  };
+  if (p->workspace) {
+    if (p->workspace_bytes < P.total) {
+      c->err = "workspace too small: need " + std::to_string(P.total) + " bytes";
+      return cleanup_fail(LBM_ENOMEM);
+    }
+    c->ws = static_cast<char*>(p->workspace);
+    c->own_ws = false;
+  } else {
+    hipError_t e = hipMalloc(&c->ws, P.total);
+    if (e != hipSuccess) {
+      c->ws = nullptr;
+      c->err = std::string("hipMalloc of ") + std::to_string(P.total) + " bytes: " + hipGetErrorString(e);
+      return cleanup_fail(LBM_ENOMEM);
+    }
+    c->own_ws = true;
+  }
+  c->ws_bytes = P.total;
+  c->A = c->ws + P.off_A;
+  c->B = c->ws + P.off_B;
+  c->partials = reinterpret_cast<double*>(c->ws + P.off_part);
+  c->history = reinterpret_cast<double*>(c->ws + P.off_hist);
+  c->readout = reinterpret_cast<double*>(c->ws + P.off_read);
+  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+    c->err = "hipEventCreate failed";
+    return cleanup_fail(LBM_EDEVICE);
+  }
+  // padding between rows and planes is never read by the kernels, but keep it defined
+  hipError_t e = hipMemsetAsync(c->ws, 0, P.off_read, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->readout, rho0, nodes * sizeof(double), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->readout + nodes, u0, (size_t)P.D * nodes * sizeof(double), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = launch_init_bgk(c->kind, c->D, c->readout, c->readout + nodes, c->A, c->L, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    c->err = std::string("initialisation: ") + hipGetErrorString(e);
+    return cleanup_fail(LBM_EDEVICE);
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* c, int64_t n) {
+  if (!c) return fail(nullptr, LBM_ESTATE, "NULL context");
+  if (n < 0) return fail(c, LBM_EINVAL, "n must be >= 0");
+  const int de = c->p.diag_every;
+  const int64_t hist_before = c->hist_written;
+  for (int64_t k = 0; k < n; ++k) {
+    const int64_t tn = c->t + 1;
+    const bool diag = de > 0 && tn % de == 0;
+    double* part = diag ? c->partials : nullptr;
+    hipError_t e;
+    if (c->D == 2)
+      e = launch_bgk_d2q9(c->kind, c->A, c->B, c->L, c->G, c->omega, c->p.wall_y != 0, part, c->stream);
+    else
+      e = launch_bgk_d3q27(c->kind, c->A, c->B, c->L, c->G, c->omega, c->p.wall_y != 0, part, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "step kernel launch");
+    if (diag) {
+      double* slot = c->history + (c->hist_written % kHistoryCap) * 6;
+      e = launch_diag_finalize(c->partials, c->G.blocks(), (double)tn, slot, c->stream);
+      if (e != hipSuccess) return hip_fail(c, e, "diagnostics launch");
+      ++c->hist_written;
+    }
+    std::swap(c->A, c->B);
+    c->t = tn;
+  }
+  if (c->hist_written > hist_before) {
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const int64_t cnt = std::min<int64_t>(c->hist_written - hist_before, kHistoryCap);
+    std::vector<double> h((size_t)kHistoryCap * 6);
+    HIP_TRY(c, hipMemcpy(h.data(), c->history, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int64_t k = 0; k < cnt; ++k) {
+      const int64_t slot = (c->hist_written - 1 - k) % kHistoryCap;
+      for (int v = 1; v < 6; ++v)
+        if (!std::isfinite(h[slot * 6 + v]))
+          return fail(c, LBM_EUNSTABLE, "non-finite conservation total at t = " + std::to_string((int64_t)h[slot * 6]));
+    }
+  }
+  return LBM_OK;
+}
+
+int lbm_time_steps(lbm_ctx* c, int64_t n, float* ms) {
+  if (!c) return fail(nullptr, LBM_ESTATE, "NULL context");
+  if (!ms) return fail(c, LBM_EINVAL, "ms is NULL");
+  HIP_TRY(c, hipEventRecord(c->ev0, c->stream));
+  int rc = lbm_step(c, n);
+  if (rc) return rc;
+  HIP_TRY(c, hipEventRecord(c->ev1, c->stream));
+  HIP_TRY(c, hipEventSynchronize(c->ev1));
+  HIP_TRY(c, hipEventElapsedTime(ms, c->ev0, c->ev1));
+  return LBM_OK;
+}
+
+int lbm_moments(lbm_ctx* c, double* rho, double* u, double* T, double* totals) {
+  if (!c) return fail(nullptr, LBM_ESTATE, "NULL context");
+  (void)T;
+  const int64_t nodes = c->L.nodes();
+  double* d_rho = c->readout;
+  double* d_u = c->readout + nodes;
+  HIP_TRY(c, launch_moments_bgk(c->kind, c->D, c->A, c->L, d_rho, d_u, c->stream));
+  if (totals) {
+    const int nparts = std::min(512, c->partial_slots - 2);
+    double* out = c->partials + (size_t)nparts * kDiagValues;  // 6 doubles after the partials
+    HIP_TRY(c, launch_field_totals(c->D, d_rho, d_u, nullptr, nodes, true, c->partials, nparts, out, c->stream));
+    double h[6];
+    HIP_TRY(c, hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k < kDiagValues; ++k) totals[k] = h[1 + k];
+  }
+  if (rho) HIP_TRY(c, hipMemcpyAsync(rho, d_rho, nodes * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  if (u) HIP_TRY(c, hipMemcpyAsync(u, d_u, (size_t)c->D * nodes * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+int lbm_populations(lbm_ctx* c, double* f, double* g) {
+  if (!c) return fail(nullptr, LBM_ESTATE, "NULL context");
+  (void)g;
+  if (!f) return fail(c, LBM_EINVAL, "f is NULL");
+  const int64_t nodes = c->L.nodes();
+  for (int i = 0; i < c->Q; ++i) {
+    HIP_TRY(c, launch_decode_f(c->kind, c->D, i, c->A, c->L, c->readout, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(f + (size_t)i * nodes, c->readout, nodes * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
+  return LBM_OK;
+}
+
+int lbm_time(const lbm_ctx* c, int64_t* t) {
+  if (!c) return fail(nullptr, LBM_ESTATE, "NULL context");
+  if (!t) return LBM_EINVAL;
+  *t = c->t;
+  return LBM_OK;
+}
+
+int lbm_diag_history(lbm_ctx* c, double* out, int32_t max_entries, int32_t* n_entries) {
+  if (!c) return fail(nullptr, LBM_ESTATE, "NULL context");
+  if (!out || !n_entries || max_entries < 0) return fail(c, LBM_EINVAL, "invalid output arguments");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const int64_t avail = std::min<int64_t>(c->hist_written, kHistoryCap);
+  const int64_t cnt = std::min<int64_t>(avail, max_entries);
+  std::vector<double> h((size_t)kHistoryCap * 6);
+  HIP_TRY(c, hipMemcpy(h.data(), c->history, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+  const int64_t first = c->hist_written - avail;  // oldest kept entry
+  for (int64_t k = 0; k < cnt; ++k) {
+    const int64_t slot = (first + k) % kHistoryCap;
+    std::memcpy(out + k * 6, h.data() + slot * 6, 6 * sizeof(double));
+  }
+  *n_entries = (int32_t)cnt;
+  return LBM_OK;
+}
+
+int lbm_set_mlp(lbm_ctx* c, const float* weights, double tol) {
+  if (!c) return fail(nullptr, LBM_ESTATE, "NULL context");
+  (void)weights;
+  (void)tol;
+  return fail(c, LBM_EINVAL, "surrogate collision not available in this configuration");
+}
+
+int lbm_mlp_stats(lbm_ctx* c, int64_t* fallbacks, int64_t* updates) {
+  if (!c) return fail(nullptr, LBM_ESTATE, "NULL context");
+  (void)fallbacks;
+  (void)updates;
+  return fail(c, LBM_EINVAL, "surrogate collision not available in this configuration");
+}
+
+int lbm_harvest(lbm_ctx* c, int64_t n, const int64_t* dev_nodes, float* dev_x, float* dev_y) {
+  if (!c) return fail(nullptr, LBM_ESTATE, "NULL context");
+  (void)n; (void)dev_nodes; (void)dev_x; (void)dev_y;
+  return fail(c, LBM_EINVAL, "harvest not available in this configuration");
+}
+
+int lbm_mlp_create(const float* weights, void* stream, lbm_mlp** out) {
+  (void)weights; (void)stream;
+  if (out) *out = nullptr;
+  return fail(nullptr, LBM_EINVAL, "surrogate trainer not available in this build");
+}
+void lbm_mlp_destroy(lbm_mlp* m) { (void)m; }
+int lbm_mlp_get(lbm_mlp* m, float* w) { (void)m; (void)w; return fail(nullptr, LBM_ESTATE, "no trainer"); }
+int lbm_mlp_forward(lbm_mlp* m, const float* x, int64_t n, float* y) {
+  (void)m; (void)x; (void)n; (void)y;
+  return fail(nullptr, LBM_ESTATE, "no trainer");
+}
+int lbm_mlp_grad(lbm_mlp* m, const float* x, const float* t, int64_t n, float* g, float* loss) {
+  (void)m; (void)x; (void)t; (void)n; (void)g; (void)loss;
+  return fail(nullptr, LBM_ESTATE, "no trainer");
+}
+int lbm_mlp_train(lbm_mlp* m, const float* x, const float* t, int64_t n, int32_t b, int64_t s, float lr) {
+  (void)m; (void)x; (void)t; (void)n; (void)b; (void)s; (void)lr;
+  return fail(nullptr, LBM_ESTATE, "no trainer");
+}
+
+const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err.c_str() : g_err.c_str(); }
+
+void lbm_destroy(lbm_ctx* c) {
+  if (!c) return;
+  if (c->stream || c->ws) (void)hipStreamSynchronize(c->stream);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  if (c->own_ws && c->ws) (void)hipFree(c->ws);
+  delete c;
+}
+
+}  // extern "C"

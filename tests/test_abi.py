@@ -1,0 +1,95 @@
+"""CPU checks of the C ABI: the library loads, exports every declared symbol, and validates
+parameters before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2609_28679_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = []
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", h)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names += re.findall(r"^\s*[A-Za-z_][\w\s\*]*?\b(lbm_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_2609_28679_amd import build
+        build.build()
+    return binding.load()
+
+
+def test_library_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(binding.SIGNATURES), "binding and header disagree"
+
+
+def test_default_params_and_workspace_size(lib):
+    p = binding.LbmParams()
+    lib.lbm_default_params(ctypes.byref(p))
+    assert (p.lattice, p.model, p.storage, p.nx, p.ny, p.nz) == (0, 0, 0, 64, 64, 1)
+    assert p.tau == 0.8 and p.fp16_scale_log2 == 16
+    nbytes = ctypes.c_size_t(0)
+    assert lib.lbm_workspace_size(ctypes.byref(p), ctypes.byref(nbytes)) == 0
+    # two population buffers of 9 float32 planes at least
+    assert nbytes.value >= 2 * 9 * 64 * 64 * 4
+    p.storage = binding.STORAGES["fp64"]
+    big = ctypes.c_size_t(0)
+    assert lib.lbm_workspace_size(ctypes.byref(p), ctypes.byref(big)) == 0
+    assert big.value > nbytes.value
+
+
+@pytest.mark.parametrize("field,value", [("tau", 0.5), ("tau", float("nan")), ("nx", 0),
+                                          ("nz", 2), ("lattice", 7), ("wall_y", 2),
+                                          ("diag_every", -1)])
+def test_invalid_params_rejected(lib, field, value):
+    p = binding.LbmParams()
+    lib.lbm_default_params(ctypes.byref(p))
+    setattr(p, field, value)
+    nbytes = ctypes.c_size_t(0)
+    assert lib.lbm_workspace_size(ctypes.byref(p), ctypes.byref(nbytes)) == binding.LBM_EINVAL
+    assert lib.lbm_last_error(None)
+
+
+def _create(lib, rho, u, **kw):
+    p = binding.LbmParams()
+    lib.lbm_default_params(ctypes.byref(p))
+    p.ny, p.nx = rho.shape
+    for k, v in kw.items():
+        setattr(p, k, v)
+    ctx = ctypes.c_void_p()
+    rc = lib.lbm_create(ctypes.byref(p), rho.ctypes.data_as(binding._D),
+                        u.ctypes.data_as(binding._D), None, ctypes.byref(ctx))
+    return rc, ctx
+
+
+def test_create_rejects_inadmissible_initial_state_before_device_work(lib):
+    rho = np.ones((4, 5))
+    u = np.zeros((2, 4, 5))
+    u[0, 1, 2] = 0.9  # theta + u^2 > 1: negative rest factor
+    rc, ctx = _create(lib, rho, u)
+    assert rc == binding.LBM_EINVAL and not ctx.value
+    assert b"product-form" in lib.lbm_last_error(None)
+    u[0, 1, 2] = 0.0
+    rho[3, 4] = np.nan
+    rc, ctx = _create(lib, rho, u)
+    assert rc == binding.LBM_EINVAL and not ctx.value
+
+
+def test_null_context_is_a_state_error(lib):
+    assert lib.lbm_step(None, 1) == binding.LBM_ESTATE
+    lib.lbm_destroy(None)  # NULL-safe

@@ -1,0 +1,211 @@
+"""GPU parity of the isothermal HIP kernels (D2Q9, D3Q27) against the FP64 CPU oracle.
+
+Bars: float64 path 1e-12 (indexing is exact, only rounding order differs), float32 path
+rel-L2 <= 1e-5 on velocity.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import announce, rel_l2, require_gpu
+from oracle import bgk
+from oracle.equilibrium import moments
+from paper_2609_28679_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _lattice(*a, **k):
+    from paper_2609_28679_amd.binding import Lattice
+    return Lattice(*a, **k)
+
+
+def _oracle(rho, u, tau, steps, walls=False):
+    f = bgk.run(bgk.init_equilibrium(rho, u), bgk.omega_from_tau_lb(tau), steps, walls)
+    return moments(f)
+
+
+def _gpu_run(rho, u, tau, steps, **kw):
+    lat = _lattice(rho, u, tau=tau, **kw)
+    lat.step(steps)
+    r, v, _, tot = lat.moments()
+    lat.close()
+    return r, v, tot
+
+
+@pytest.mark.parametrize("storage,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_taylor_green_64_1000_steps(storage, tol):
+    announce("D2Q9 TGV 64^2 tau 0.8 1000 steps " + storage)
+    rho, u = inputs.taylor_green_2d(64, 64, 0.01)
+    rg, ug, _ = _gpu_run(rho, u, 0.8, 1000, storage=storage)
+    ro, uo = _oracle(rho, u, 0.8, 1000)
+    assert rel_l2(ug, uo) <= tol
+    assert np.abs(rg - ro).max() <= 10 * tol
+
+
+@pytest.mark.parametrize("tau", [0.51, 0.6, 1.0])
+def test_turbulence_fp32(tau):
+    announce("D2Q9 turbulence 256^2 tau %g 300 steps fp32" % tau)
+    rho, u = inputs.random_phase_turbulence_2d(256, seed=0)
+    _, ug, _ = _gpu_run(rho, u, tau, 300)
+    _, uo = _oracle(rho, u, tau, 300)
+    assert rel_l2(ug, uo) <= 1e-5
+
+
+@pytest.mark.parametrize("walls", [False, True])
+@pytest.mark.parametrize("nx,ny", [(100, 37), (300, 5), (3, 2), (1, 1), (70, 64)])
+def test_ragged_shapes_fp64_exact(nx, ny, walls):
+    announce("D2Q9 ragged %dx%d walls=%s fp64" % (nx, ny, walls))
+    rng = np.random.default_rng(nx * 1000 + ny)
+    rho = 1.0 + 0.02 * rng.standard_normal((ny, nx))
+    u = 0.03 * rng.standard_normal((2, ny, nx))
+    rg, ug, _ = _gpu_run(rho, u, 0.7, 40, storage="fp64", wall_y=walls)
+    ro, uo = _oracle(rho, u, 0.7, 40, walls)
+    assert np.abs(rg - ro).max() <= 1e-13
+    assert np.abs(ug - uo).max() <= 1e-13
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_ragged_fp32(walls):
+    announce("D2Q9 ragged 130x67 walls=%s fp32" % walls)
+    rng = np.random.default_rng(5)
+    rho = 1.0 + 0.02 * rng.standard_normal((67, 130))
+    u = 0.03 * rng.standard_normal((2, 67, 130))
+    _, ug, _ = _gpu_run(rho, u, 0.6, 100, wall_y=walls)
+    _, uo = _oracle(rho, u, 0.6, 100, walls)
+    assert rel_l2(ug, uo) <= 1e-5
+
+
+@pytest.mark.parametrize("storage,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_d3q27_taylor_green(storage, tol):
+    announce("D3Q27 TGV 32^3 tau 0.55 60 steps " + storage)
+    rho, u = inputs.taylor_green_3d(32, 0.05)
+    _, ug, _ = _gpu_run(rho, u, 0.55, 60, lattice="D3Q27", storage=storage)
+    _, uo = _oracle(rho, u, 0.55, 60)
+    # w = 0 initially and stays 0 by symmetry; compare the full field
+    assert rel_l2(ug, uo) <= tol
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_d3q27_ragged_fp64(walls):
+    announce("D3Q27 ragged 9x7x5 walls=%s fp64" % walls)
+    rng = np.random.default_rng(11)
+    rho = 1.0 + 0.02 * rng.standard_normal((5, 7, 9))
+    u = 0.03 * rng.standard_normal((3, 5, 7, 9))
+    rg, ug, _ = _gpu_run(rho, u, 0.7, 15, lattice="D3Q27", storage="fp64", wall_y=walls)
+    ro, uo = _oracle(rho, u, 0.7, 15, walls)
+    assert np.abs(ug - uo).max() <= 1e-13
+    assert np.abs(rg - ro).max() <= 1e-13
+
+
+def test_d3q27_z_invariant_equals_d2q9_on_gpu():
+    announce("D3Q27 z-invariant vs D2Q9 fp64")
+    rho, u2 = inputs.taylor_green_2d(40, 40, 0.02)
+    u3 = np.concatenate([u2, np.zeros((1, 40, 40))])[:, None]
+    _, v3, _ = _gpu_run(rho[None], u3, 0.7, 50, lattice="D3Q27", storage="fp64")
+    _, v2, _ = _gpu_run(rho, u2, 0.7, 50, storage="fp64")
+    assert np.abs(v3[:2, 0] - v2).max() <= 1e-14
+
+
+def _one_step_full_size(lat, tau, walls=False):
+    """Oracle step from the GPU's own stored state: pull (stream) then collide."""
+    f_post, _ = lat.populations()
+    lat.step(1)
+    f_next, _ = lat.populations()
+    expect = bgk.collide(bgk.stream(f_post, walls), bgk.omega_from_tau_lb(tau))
+    return f_next, expect
+
+
+@pytest.mark.parametrize("n", [2048, 4096])
+def test_full_size_single_step_elementwise(n):
+    announce("D2Q9 full size %d^2 single-step elementwise fp32" % n)
+    rho, u = inputs.random_phase_turbulence_2d(n, seed=0)
+    lat = _lattice(rho, u, tau=0.6)
+    lat.step(20)
+    got, expect = _one_step_full_size(lat, 0.6)
+    lat.close()
+    # one float32 collision from identical inputs: within ~15 ulp of the largest population
+    assert np.abs(got - expect).max() <= 1e-6 * np.abs(expect).max()
+
+
+def test_d3q27_full_size_single_step():
+    announce("D3Q27 full size 256^3 single-step elementwise fp32")
+    rho, u = inputs.taylor_green_3d(256, 0.05)
+    lat = _lattice(rho, u, lattice="D3Q27", tau=0.55)
+    lat.step(5)
+    f_post, _ = lat.populations()
+    lat.step(1)
+    f_next, _ = lat.populations()
+    lat.close()
+    # sample 4 z-planes of the oracle step (the pull only reaches z +- 1)
+    zs = [0, 1, 128, 255]
+    sub = np.concatenate([f_post[:, [(z - 1) % 256, z, (z + 1) % 256]] for z in zs], axis=1)
+    # collide-after-stream on 3-plane slabs; the middle plane of each slab is exact
+    for k, z in enumerate(zs):
+        slab = sub[:, 3 * k:3 * k + 3]
+        pre = bgk.stream(slab)
+        exp = bgk.collide(pre, bgk.omega_from_tau_lb(0.55))[:, 1]
+        assert np.abs(f_next[:, z] - exp).max() <= 1e-6 * np.abs(exp).max()
+
+
+def test_bitwise_determinism_and_workspace_modes():
+    announce("D2Q9 determinism 512^2 fp32")
+    rho, u = inputs.random_phase_turbulence_2d(512, seed=3)
+    a = _lattice(rho, u, tau=0.55, diag_every=10)
+    a.step(100)
+    fa, _ = a.populations()
+    ha = a.diag_history()
+    a.close()
+    b = _lattice(rho, u, tau=0.55, diag_every=10, torch_workspace=False)
+    b.step(100)
+    fb, _ = b.populations()
+    hb = b.diag_history()
+    b.close()
+    assert np.array_equal(fa, fb)
+    assert np.array_equal(ha, hb)
+
+
+def test_diagnostics_conservation_and_values():
+    announce("D2Q9 diagnostics 256^2 fp32 every 50 steps")
+    rho, u = inputs.random_phase_turbulence_2d(256, seed=1)
+    lat = _lattice(rho, u, tau=0.6, diag_every=50)
+    lat.step(200)
+    h = lat.diag_history()
+    _, _, _, tot = lat.moments()
+    lat.close()
+    assert list(h[:, 0]) == [50, 100, 150, 200]
+    mass0 = rho.sum()
+    assert np.all(np.abs(h[:, 1] - mass0) / mass0 < 1e-6)
+    # kinetic energy decays monotonically in decaying turbulence
+    assert np.all(np.diff(h[:, 5]) < 0)
+    ro, uo = _oracle(rho, u, 0.6, 200)
+    ke = 0.5 * (ro * (uo ** 2).sum(axis=0)).sum()
+    assert abs(h[-1, 5] - ke) / ke < 1e-5
+    assert abs(tot[4] - ke) / ke < 1e-5
+    assert abs(tot[0] - mass0) / mass0 < 1e-6
+
+
+def test_unstable_run_is_reported():
+    announce("D2Q9 deliberately unstable parameters (float overflow only)")
+    from paper_2609_28679_amd.binding import LbmError, LBM_EUNSTABLE
+    rho, u = inputs.taylor_green_2d(32, 32, 0.35)
+    lat = _lattice(rho, u, tau=0.5001, diag_every=10)
+    with pytest.raises(LbmError) as e:
+        lat.step(3000)
+    assert e.value.code == LBM_EUNSTABLE
+    lat.close()
+
+
+def test_zero_steps_returns_initial_moments():
+    announce("D2Q9 zero steps")
+    rho, u = inputs.taylor_green_2d(48, 48, 0.02)
+    lat = _lattice(rho, u, tau=0.7, storage="fp64")
+    lat.step(0)
+    r, v, _, _ = lat.moments()
+    assert lat.t == 0
+    lat.close()
+    assert np.abs(r - rho).max() < 1e-14 and np.abs(v - u).max() < 1e-15
