@@ -150,6 +150,12 @@ def main():
             lambda: binding.Lattice(r3, u3, lattice="D3Q27", tau=0.55, diag_every=100),
             max(100, vs // 10), 10, 216, {"diag_every": 100})
         del r3, u3
+        rs, us, ts = inputs.thermal_shear_layer(n4, seed=0)
+        variants["d2q9_ddf_fp32_4096"] = variant(
+            "d2q9_ddf_fp32_4096",
+            lambda: binding.Lattice(rs, us, ts, model="ddf", tau=0.6, wall_y=True, phi=1),
+            max(100, vs // 4), 10, 144, {"walls": "y", "phi": "central"})
+        del rs, us, ts
         variants["d2q9_bgk_fp64_2048"] = variant(
             "d2q9_bgk_fp64_2048", lambda: binding.Lattice(rho, u, tau=tau, storage="fp64"),
             max(200, vs // 4), 20, 144)

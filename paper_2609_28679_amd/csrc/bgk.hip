@@ -21,6 +21,8 @@
 // moments at time t) for the diagnostics.
 #include "device_common.h"
 
+#include <cstdlib>
+
 namespace lbm {
 
 // Psi(c; u, theta + u^2) for c = -1, 0, +1 at theta = 1/3 (Sec. II C).
@@ -110,8 +112,12 @@ k_bgk_d2q9(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int64_t p
 }
 
 // ---- D3Q27 --------------------------------------------------------------------------------
+// 3 waves per SIMD lets the compiler keep all 27 loads of a node in flight without spilling
+#ifndef LBM_D3Q27_WAVES
+#define LBM_D3Q27_WAVES 3
+#endif
 template <typename S, bool WALLS, bool DIAG>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LBM_D3Q27_WAVES)))
 k_bgk_d3q27(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int nz, int64_t pitch,
             int64_t plane, double omega, int rows, double* __restrict__ partials) {
   const int nbx = gridDim.x;
@@ -134,25 +140,28 @@ k_bgk_d3q27(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int nz, 
       const int ysrc[3] = {y == ny - 1 ? 0 : y + 1, y, y == 0 ? ny - 1 : y - 1};
       const int zsrc[3] = {z == nz - 1 ? 0 : z + 1, z, z == 0 ? nz - 1 : z - 1};
       const int64_t self = ((int64_t)z * ny + y) * pitch + x;
-      double h[27];
+      // populations stay in storage precision in registers (27 values); the arithmetic
+      // converts each one to float64 where it is used
+      S h[27];
 #pragma unroll
       for (int i = 0; i < 27; ++i) {
         const int cx = i % 3, cy = (i / 3) % 3, cz = i / 9;  // component + 1
         const bool bounce = WALLS && ((cy == 2 && y == 0) || (cy == 0 && y == ny - 1));
         if (bounce) {
-          h[i] = (double)A[(26 - i) * plane + self];
+          h[i] = A[(26 - i) * plane + self];
         } else {
-          h[i] = (double)A[i * plane + ((int64_t)zsrc[cz] * ny + ysrc[cy]) * pitch + xs[cx]];
+          h[i] = A[i * plane + ((int64_t)zsrc[cz] * ny + ysrc[cy]) * pitch + xs[cx]];
         }
       }
       double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
       for (int i = 0; i < 27; ++i) {
         const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
-        drho += h[i];
-        if (cx) jx += cx > 0 ? h[i] : -h[i];
-        if (cy) jy += cy > 0 ? h[i] : -h[i];
-        if (cz) jz += cz > 0 ? h[i] : -h[i];
+        const double v = (double)h[i];
+        drho += v;
+        if (cx) jx += cx > 0 ? v : -v;
+        if (cy) jy += cy > 0 ? v : -v;
+        if (cz) jz += cz > 0 ? v : -v;
       }
       const double rho = 1.0 + drho;
       const double ux = jx / rho, uy = jy / rho, uz = jz / rho;
@@ -165,7 +174,8 @@ k_bgk_d3q27(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int nz, 
       for (int i = 0; i < 27; ++i) {
         const int a = i % 3, b = (i / 3) % 3, c = i / 9;
         const double heq = rho * px[a] * py[b] * pz[c] - w1(a) * w1(b) * w1(c);
-        store_nt(out + i * plane, (S)(h[i] + omega * (heq - h[i])));
+        const double v = (double)h[i];
+        store_nt(out + i * plane, (S)(v + omega * (heq - v)));
       }
       if (DIAG) {
         acc[0] += rho;
@@ -280,13 +290,22 @@ __global__ void k_field_totals(int D, const double* __restrict__ rho, const doub
 
 // ---- launchers -----------------------------------------------------------------------------
 Grid make_grid(const Layout& L) {
+  // One row per workgroup measured best for the streaming kernels on MI355X (more
+  // workgroups in flight); the row count only grows for very large lattices.
+  int bx_max = kBlock, max_rows = 16;
+  int64_t target = 1 << 20;
+#ifdef LBM_TUNING_ENV
+  if (const char* v = getenv("LBM_BX")) bx_max = atoi(v);
+  if (const char* v = getenv("LBM_ROWS")) max_rows = atoi(v);
+  if (const char* v = getenv("LBM_TARGET")) target = atoll(v);
+#endif
   Grid G;
-  G.bx = L.nx >= kBlock ? kBlock : ((L.nx + 63) / 64) * 64;
+  G.bx = L.nx >= bx_max ? bx_max : ((L.nx + 63) / 64) * 64;
   G.nbx = (L.nx + G.bx - 1) / G.bx;
   const int64_t nrows = (int64_t)L.ny * L.nz;
-  // aim for >= 2048 workgroups (8 per compute unit) with at most 16 rows each
-  int64_t rows = (nrows * G.nbx + 2047) / 2048;
-  rows = rows < 1 ? 1 : (rows > 16 ? 16 : rows);
+  // aim for >= `target` workgroups (8 per compute unit) with at most max_rows rows each
+  int64_t rows = (nrows * G.nbx + target - 1) / target;
+  rows = rows < 1 ? 1 : (rows > max_rows ? max_rows : rows);
   G.rows = (int)rows;
   G.nby = (int)((nrows + rows - 1) / rows);
   return G;

@@ -1,0 +1,140 @@
+// Device helpers of the double-distribution (ideal gas) kernels, D2Q9.
+#pragma once
+
+#include "device_common.h"
+
+namespace lbm {
+
+// Per-axis factors of the product-form equilibria at velocity component v and reference
+// temperature theta (Sec. II C), indexed by k = c + 1:
+//   psi_c = Psi(c; v, theta + v^2):  1 - theta - v^2 (c = 0), (theta + v^2 +- v)/2 (c = +-1)
+//   chi_c = Psi(c; O, O^2) applied to v^2/2 with O = theta d/dv + v:
+//           a0 - a2 (c = 0), (a2 +- a1)/2 (c = +-1), where a0 = v^2/2, a1 = O a0 = theta v + v^3/2,
+//           a2 = O^2 a0 = theta^2 + 5/2 theta v^2 + v^4/2.
+// Then f_i^eq = rho psi_x psi_y and, the operators acting on E = e + u_x^2/2 + u_y^2/2,
+// g_i^eq = rho (e psi_x psi_y + chi_x psi_y + psi_x chi_y).
+struct Axis {
+  double psi[3];
+  double chi[3];
+};
+
+__device__ __forceinline__ void axis_eq(double v, double theta, Axis& a) {
+  const double v2 = v * v;
+  a.psi[1] = 1.0 - theta - v2;
+  a.psi[2] = 0.5 * (theta + v2 + v);
+  a.psi[0] = 0.5 * (theta + v2 - v);
+  const double a0 = 0.5 * v2;
+  const double a1 = theta * v + 0.5 * v2 * v;
+  const double a2 = theta * theta + 2.5 * theta * v2 + 0.5 * v2 * v2;
+  a.chi[1] = a0 - a2;
+  a.chi[2] = 0.5 * (a2 + a1);
+  a.chi[0] = 0.5 * (a2 - a1);
+}
+
+__device__ __forceinline__ void equilibria(double rho, double ux, double uy, double theta,
+                                           double e, double (&fe)[9], double (&ge)[9]) {
+  Axis X, Y;
+  axis_eq(ux, theta, X);
+  axis_eq(uy, theta, Y);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int a = i % 3, b = i / 3;
+    const double pp = X.psi[a] * Y.psi[b];
+    fe[i] = rho * pp;
+    ge[i] = rho * (e * pp + X.chi[a] * Y.psi[b] + X.psi[a] * Y.chi[b]);
+  }
+}
+
+struct Moments {
+  double rho, ux, uy, theta, e;
+};
+
+// rho = sum f, rho u = sum c f, rho E = sum g; T = (E - u^2/2)/c_v and theta = P/rho = R T.
+__device__ __forceinline__ void moments_closure(const double (&f)[9], const double (&g)[9],
+                                                const DdfParams& p, Moments& m) {
+  const double rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+  const double jx = (f[2] + f[5] + f[8]) - (f[0] + f[3] + f[6]);
+  const double jy = (f[6] + f[7] + f[8]) - (f[0] + f[1] + f[2]);
+  const double rE = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
+  const double inv = 1.0 / rho;
+  m.rho = rho;
+  m.ux = jx * inv;
+  m.uy = jy * inv;
+  m.e = rE * inv - 0.5 * (m.ux * m.ux + m.uy * m.uy);  // c_v T
+  m.theta = p.R * (m.e / p.cv);
+}
+
+// Pull of the nine populations of one distribution at node (x, row): f_i = A_i(x - c_i).
+// top/bot: the row touches the upper/lower half-way bounce-back wall.
+template <typename S>
+__device__ __forceinline__ void gather9(const S* __restrict__ A, int64_t plane, int64_t r0,
+                                        int64_t rm, int64_t rp, int x, int xm, int xp,
+                                        bool top, bool bot, S (&h)[9]) {
+  h[3] = A[3 * plane + r0 + xp];
+  h[4] = A[4 * plane + r0 + x];
+  h[5] = A[5 * plane + r0 + xm];
+  if (top) {
+    h[0] = A[8 * plane + r0 + x];
+    h[1] = A[7 * plane + r0 + x];
+    h[2] = A[6 * plane + r0 + x];
+  } else {
+    h[0] = A[0 * plane + rp + xp];
+    h[1] = A[1 * plane + rp + x];
+    h[2] = A[2 * plane + rp + xm];
+  }
+  if (bot) {
+    h[6] = A[2 * plane + r0 + x];
+    h[7] = A[1 * plane + r0 + x];
+    h[8] = A[0 * plane + r0 + x];
+  } else {
+    h[6] = A[6 * plane + rm + xp];
+    h[7] = A[7 * plane + rm + x];
+    h[8] = A[8 * plane + rm + xm];
+  }
+}
+
+// Second-order one-sided difference on the upwind side of u (central when u = 0).
+__device__ __forceinline__ double upwind_or_central(double pm2, double pm1, double p0, double pp1,
+                                                    double pp2, double u) {
+  if (u > 0.0) return 0.5 * (3.0 * p0 - 4.0 * pm1 + pm2);
+  if (u < 0.0) return -0.5 * (3.0 * p0 - 4.0 * pp1 + pp2);
+  return 0.5 * (pp1 - pm1);
+}
+
+// Collision of one node from its stored (shifted) populations and moments
+// m = {rho, u_x, u_y, theta, e, -}; Phi_xx, Phi_yy already include dt = 1.
+template <typename S>
+__device__ __forceinline__ void collide_ddf(const S (&hf)[9], const S (&hg)[9],
+                                            const double (&m)[6], double phxx, double phyy,
+                                            const DdfParams& p,
+                                            S (&of)[9], S (&og)[9]) {
+  const double rho = m[0], theta = m[3], e = m[4];
+  Axis X, Y;
+  axis_eq(m[1], theta, X);
+  axis_eq(m[2], theta, Y);
+  // shifted factors Psi(c; u, theta + u^2 + Phi): psi + Phi * (1/2, -1, 1/2)
+  double sx[3], sy[3];
+  sx[0] = X.psi[0] + 0.5 * phxx;
+  sx[1] = X.psi[1] - phxx;
+  sx[2] = X.psi[2] + 0.5 * phxx;
+  sy[0] = Y.psi[0] + 0.5 * phyy;
+  sy[1] = Y.psi[1] - phyy;
+  sy[2] = Y.psi[2] + 0.5 * phyy;
+  const double P = rho * theta;
+  const double omega = 2.0 * P / (2.0 * p.mu + P);  // 2 beta, beta = 1/(2 tau + 1), tau = mu/P
+  const double keep = 1.0 - 0.5 * omega;            // 1 - beta
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int a = i % 3, b = i / 3;
+    const double pp = X.psi[a] * Y.psi[b];
+    const double hfe = rho * pp - p.wf[i];  // f^eq - w
+    const double hge = rho * (e * pp + X.chi[a] * Y.psi[b] + X.psi[a] * Y.chi[b]) - p.wg[i];
+    const double dstar = rho * (sx[a] * sy[b] - pp);  // f* - f^eq
+    const double f = (double)hf[i];
+    const double g = (double)hg[i];
+    of[i] = (S)(f + omega * (hfe - f) + keep * dstar);
+    og[i] = (S)(g + omega * (hge - g));
+  }
+}
+
+}  // namespace lbm

@@ -13,6 +13,9 @@ namespace lbm {
 // the hardware order so that each XCD owns one contiguous range of tiles: neighbouring tiles
 // then share the XCD's L2 for their halo rows.
 __device__ __forceinline__ int xcd_tile(int b, int nblocks) {
+#if defined(LBM_NO_XCD_REMAP)
+  return b;
+#endif
   const int per = nblocks / kNumXcd;
   const int rem = nblocks % kNumXcd;
   const int xcd = b % kNumXcd;
@@ -52,7 +55,11 @@ __device__ __forceinline__ void block_sum_store(double (&v)[N], double* out) {
 
 template <typename T>
 __device__ __forceinline__ void store_nt(T* p, T v) {
+#if defined(LBM_PLAIN_STORES)
+  *p = v;
+#else
   __builtin_nontemporal_store(v, p);
+#endif
 }
 
 }  // namespace lbm

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -24,6 +25,9 @@ struct lbm_ctx {
   lbm_params p{};
   int D = 2, Q = 9;
   int kind = 0;  // 0: float32 populations, 1: float64
+  bool ddf = false;  // double-distribution ideal-gas model
+  int planes = 9;    // stored population planes per buffer
+  DdfParams dp{};
   Layout L{};
   Grid G{};
   hipStream_t stream = nullptr;
@@ -64,7 +68,8 @@ int hip_fail(lbm_ctx* c, hipError_t e, const char* where) {
   } while (0)
 
 struct Plan {
-  int D, Q, kind;
+  int D, Q, kind, planes;
+  bool ddf;
   Layout L;
   Grid G;
   size_t elem;
@@ -84,7 +89,11 @@ int validate(const lbm_params* p, std::string& why) {
   if (p->wall_y != 0 && p->wall_y != 1) { why = "wall_y must be 0 or 1"; return LBM_EINVAL; }
   if (!(p->tau > 0.5) || !std::isfinite(p->tau)) { why = "tau must be a finite value > 1/2"; return LBM_EINVAL; }
   if (p->diag_every < 0) { why = "diag_every must be >= 0"; return LBM_EINVAL; }
-  if (p->model != LBM_MODEL_BGK) { why = "model not supported by this build"; return LBM_EINVAL; }
+  if (p->model == LBM_MODEL_DDF) {
+    if (p->lattice != LBM_D2Q9) { why = "the double-distribution model is D2Q9 only"; return LBM_EINVAL; }
+    if (!(p->R > 0.0) || !(p->cv > 0.0) || !std::isfinite(p->R) || !std::isfinite(p->cv)) { why = "R and cv must be positive"; return LBM_EINVAL; }
+    if (p->phi < 0 || p->phi > 2) { why = "phi must be 0 (off), 1 (central) or 2 (upwind)"; return LBM_EINVAL; }
+  }
   if (p->storage != LBM_STORE_FP32 && p->storage != LBM_STORE_FP64) { why = "storage not supported for this model"; return LBM_EINVAL; }
   if (p->collision != LBM_COLLIDE_PLAIN) { why = "collision not supported for this configuration"; return LBM_EINVAL; }
   if (p->workspace && (reinterpret_cast<uintptr_t>(p->workspace) & 255u)) { why = "workspace must be 256-byte aligned"; return LBM_EINVAL; }
@@ -95,25 +104,35 @@ void make_plan(const lbm_params* p, Plan& P) {
   P.D = p->lattice == LBM_D2Q9 ? 2 : 3;
   P.Q = P.D == 2 ? 9 : 27;
   P.kind = p->storage == LBM_STORE_FP64 ? 1 : 0;
+  P.ddf = p->model == LBM_MODEL_DDF;
+  P.planes = P.ddf ? 2 * P.Q : P.Q;
   P.elem = P.kind ? 8 : 4;
   P.L.nx = p->nx;
   P.L.ny = p->ny;
   P.L.nz = p->nz;
-  P.L.pitch = (int64_t)align_up((size_t)p->nx, 64);
-  // planes padded to a 4 KiB multiple plus 1 KiB so the Q read streams start on different
-  // HBM channels instead of all aliasing to the same one
+  // Rows start on 256-byte boundaries. Population planes are padded to a 4 KiB multiple plus
+  // 17 KiB so that the Q concurrent read and write streams of a workgroup, which sit whole
+  // planes apart, start on different HBM channels; the padding was chosen by a sweep of row
+  // and plane padding on MI355X (D2Q9 at 2048^2 and 4096^2, D3Q27 at 256^3).
+  int64_t pitch = (int64_t)align_up((size_t)p->nx, (size_t)(256 / P.elem));
+  int64_t plane_pad = (int64_t)(17 * 1024 / P.elem);
+#ifdef LBM_TUNING_ENV
+  if (const char* v = getenv("LBM_PITCH_PAD")) pitch += atoll(v);
+  if (const char* v = getenv("LBM_PLANE_PAD")) plane_pad = atoll(v);
+#endif
+  P.L.pitch = pitch;
   const int64_t raw = P.L.pitch * p->ny * p->nz;
   const int64_t epk = (int64_t)(4096 / P.elem);
-  P.L.plane = (raw + epk - 1) / epk * epk + epk / 4;
-  P.G = make_grid(P.L);
+  P.L.plane = (raw + epk - 1) / epk * epk + plane_pad;
+  P.G = P.ddf ? make_grid_ddf(P.L, p->phi == 2 ? 2 : 1) : make_grid(P.L);
   P.partial_slots = std::max(P.G.blocks(), 1024);
   size_t off = 0;
-  const size_t pop = (size_t)P.Q * P.L.plane * P.elem;
+  const size_t pop = (size_t)P.planes * P.L.plane * P.elem;
   P.off_A = off; off = align_up(off + pop, 256);
   P.off_B = off; off = align_up(off + pop, 256);
   P.off_part = off; off = align_up(off + (size_t)P.partial_slots * kDiagValues * 8, 256);
   P.off_hist = off; off = align_up(off + (size_t)kHistoryCap * 6 * 8, 256);
-  P.off_read = off; off = align_up(off + (size_t)P.L.nodes() * (P.D + 2) * 8, 256);
+  P.off_read = off; off = align_up(off + (size_t)P.L.nodes() * (P.D + 3) * 8, 256);
   P.total = off;
 }
 
@@ -170,18 +189,24 @@ int lbm_create(const lbm_params* p, const double* rho0, const double* u0, const 
   int rc = validate(p, why);
   if (rc) return fail(nullptr, rc, why);
   if (!rho0 || !u0) return fail(nullptr, LBM_EINVAL, "rho0 and u0 are required");
-  (void)T0;
   Plan P;
   make_plan(p, P);
+  if (P.ddf && !T0) return fail(nullptr, LBM_EINVAL, "the double-distribution model needs T0");
   const int64_t nodes = P.L.nodes();
   // host-side admissibility of the initial state
   for (int64_t n = 0; n < nodes; ++n) {
     if (!(rho0[n] > 0.0) || !std::isfinite(rho0[n]))
       return fail(nullptr, LBM_EINVAL, "initial density must be finite and positive at node " + std::to_string(n));
+    double theta = 1.0 / 3.0;
+    if (P.ddf) {
+      if (!(T0[n] > 0.0) || !std::isfinite(T0[n]))
+        return fail(nullptr, LBM_EINVAL, "initial temperature must be finite and positive at node " + std::to_string(n));
+      theta = p->R * T0[n];
+    }
     for (int a = 0; a < P.D; ++a) {
       const double ua = u0[a * nodes + n];
-      if (!std::isfinite(ua) || !admissible(1.0 / 3.0, ua))
-        return fail(nullptr, LBM_EINVAL, "initial velocity outside the positive product-form range at node " + std::to_string(n));
+      if (!std::isfinite(ua) || !admissible(theta, ua))
+        return fail(nullptr, LBM_EINVAL, "initial state outside the positive product-form range at node " + std::to_string(n));
     }
   }
   lbm_ctx* c = new lbm_ctx();
@@ -189,6 +214,12 @@ int lbm_create(const lbm_params* p, const double* rho0, const double* u0, const 
   c->D = P.D;
   c->Q = P.Q;
   c->kind = P.kind;
+  c->ddf = P.ddf;
+  c->planes = P.planes;
+  c->dp.R = p->R;
+  c->dp.cv = p->cv;
+  c->dp.mu = (p->tau - 0.5) * (1.0 / 3.0);  // mu = (tau - 1/2) P0 at the reference P0 = 1/3
+  c->dp.phi = p->phi;
   c->L = P.L;
   c->G = P.G;
   c->stream = static_cast<hipStream_t>(p->stream);
@@ -230,7 +261,24 @@ int lbm_create(const lbm_params* p, const double* rho0, const double* u0, const 
   if (e == hipSuccess) e = hipMemcpyAsync(c->readout, rho0, nodes * sizeof(double), hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->readout + nodes, u0, (size_t)P.D * nodes * sizeof(double), hipMemcpyHostToDevice, c->stream);
-  if (e == hipSuccess) e = launch_init_bgk(c->kind, c->D, c->readout, c->readout + nodes, c->A, c->L, c->stream);
+  if (P.ddf) {
+    // Fig. 1: f <- f^eq, g <- g^eq into B, then one collide-only pass B -> A so that A holds
+    // the post-collision state of t = 0 (f* differs from f^eq when Phi is on)
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c->readout + 3 * nodes, T0, nodes * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_ddf_rest_state(c->dp, c->partials, c->stream);
+    double rest[18];
+    if (e == hipSuccess) e = hipMemcpyAsync(rest, c->partials, sizeof(rest), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    for (int i = 0; i < 9; ++i) {
+      c->dp.wf[i] = rest[i];
+      c->dp.wg[i] = rest[9 + i];
+    }
+    if (e == hipSuccess) e = launch_init_ddf(c->kind, c->readout, c->readout + nodes, c->readout + 3 * nodes, c->B, c->L, c->dp, c->stream);
+    if (e == hipSuccess) e = launch_ddf(c->kind, p->wall_y != 0, false, c->B, c->A, c->L, c->G, c->dp, nullptr, c->stream);
+  } else if (e == hipSuccess) {
+    e = launch_init_bgk(c->kind, c->D, c->readout, c->readout + nodes, c->A, c->L, c->stream);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     c->err = std::string("initialisation: ") + hipGetErrorString(e);
@@ -250,7 +298,9 @@ int lbm_step(lbm_ctx* c, int64_t n) {
     const bool diag = de > 0 && tn % de == 0;
     double* part = diag ? c->partials : nullptr;
     hipError_t e;
-    if (c->D == 2)
+    if (c->ddf)
+      e = launch_ddf(c->kind, c->p.wall_y != 0, true, c->A, c->B, c->L, c->G, c->dp, part, c->stream);
+    else if (c->D == 2)
       e = launch_bgk_d2q9(c->kind, c->A, c->B, c->L, c->G, c->omega, c->p.wall_y != 0, part, c->stream);
     else
       e = launch_bgk_d3q27(c->kind, c->A, c->B, c->L, c->G, c->omega, c->p.wall_y != 0, part, c->stream);
@@ -293,15 +343,19 @@ int lbm_time_steps(lbm_ctx* c, int64_t n, float* ms) {
 
 int lbm_moments(lbm_ctx* c, double* rho, double* u, double* T, double* totals) {
   if (!c) return fail(nullptr, LBM_ESTATE, "NULL context");
-  (void)T;
   const int64_t nodes = c->L.nodes();
   double* d_rho = c->readout;
   double* d_u = c->readout + nodes;
-  HIP_TRY(c, launch_moments_bgk(c->kind, c->D, c->A, c->L, d_rho, d_u, c->stream));
+  double* d_T = c->readout + (1 + c->D) * nodes;
+  double* d_e = d_T + nodes;
+  if (c->ddf)
+    HIP_TRY(c, launch_moments_ddf(c->kind, c->A, c->L, c->dp, d_rho, d_u, d_T, d_e, c->stream));
+  else
+    HIP_TRY(c, launch_moments_bgk(c->kind, c->D, c->A, c->L, d_rho, d_u, c->stream));
   if (totals) {
     const int nparts = std::min(512, c->partial_slots - 2);
     double* out = c->partials + (size_t)nparts * kDiagValues;  // 6 doubles after the partials
-    HIP_TRY(c, launch_field_totals(c->D, d_rho, d_u, nullptr, nodes, true, c->partials, nparts, out, c->stream));
+    HIP_TRY(c, launch_field_totals(c->D, d_rho, d_u, c->ddf ? d_e : nullptr, nodes, !c->ddf, c->partials, nparts, out, c->stream));
     double h[6];
     HIP_TRY(c, hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -309,18 +363,23 @@ int lbm_moments(lbm_ctx* c, double* rho, double* u, double* T, double* totals) {
   }
   if (rho) HIP_TRY(c, hipMemcpyAsync(rho, d_rho, nodes * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   if (u) HIP_TRY(c, hipMemcpyAsync(u, d_u, (size_t)c->D * nodes * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  if (T && c->ddf) HIP_TRY(c, hipMemcpyAsync(T, d_T, nodes * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return LBM_OK;
 }
 
 int lbm_populations(lbm_ctx* c, double* f, double* g) {
   if (!c) return fail(nullptr, LBM_ESTATE, "NULL context");
-  (void)g;
   if (!f) return fail(c, LBM_EINVAL, "f is NULL");
   const int64_t nodes = c->L.nodes();
-  for (int i = 0; i < c->Q; ++i) {
-    HIP_TRY(c, launch_decode_f(c->kind, c->D, i, c->A, c->L, c->readout, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(f + (size_t)i * nodes, c->readout, nodes * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  for (int i = 0; i < c->planes; ++i) {
+    double* dst = i < c->Q ? f + (size_t)i * nodes : (g ? g + (size_t)(i - c->Q) * nodes : nullptr);
+    if (!dst) continue;
+    if (c->ddf)
+      HIP_TRY(c, launch_decode_ddf(c->kind, i, c->A, c->L, c->dp, c->readout, c->stream));
+    else
+      HIP_TRY(c, launch_decode_f(c->kind, c->D, i, c->A, c->L, c->readout, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(dst, c->readout, nodes * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
   }
   return LBM_OK;

@@ -33,10 +33,16 @@ struct Grid {
 
 Grid make_grid(const Layout& L);
 
-// Reduced storage: float32 moment planes + 16-bit non-equilibrium planes.
-struct Reduced {
-  float* mom;       // [nm][nodes-with-pitch]: rho, u_x, u_y (+ T for the DDF model)
-  uint16_t* neq;    // [nn][nodes-with-pitch]
+// Ideal-gas double-distribution parameters (lattice units).
+struct DdfParams {
+  double R;    // gas constant
+  double cv;   // heat capacity at constant volume
+  double mu;   // dynamic shear viscosity; tau = mu / P per node
+  int phi;     // 0: no Galilean correction, 1: central derivative, 2: upwind derivative
+  // storage shift: f^eq and g^eq at rest at the reference state rho = 1, T = 1 (computed by
+  // launch_ddf_rest_state on the device at context creation)
+  double wf[9];
+  double wg[9];
 };
 
 // ---- launchers (return the first HIP error) -----------------------------------------------
@@ -52,6 +58,18 @@ hipError_t launch_moments_bgk(int kind, int D, const void* A, const Layout& L, d
 // Population plane i of the stored state decoded to float64 f_i (nodes values, no padding).
 hipError_t launch_decode_f(int kind, int D, int i, const void* A, const Layout& L, double* f,
                            hipStream_t s);
+// Double-distribution kernels (D2Q9): planes 0..8 hold f - w, planes 9..17 hold g - v.
+Grid make_grid_ddf(const Layout& L, int halo);
+// out[0..8] = f^eq, out[9..17] = g^eq at rho = 1, u = 0, T = 1 (18 doubles, device memory).
+hipError_t launch_ddf_rest_state(const DdfParams& prm, double* out, hipStream_t s);
+hipError_t launch_ddf(int kind, bool walls, bool pull, const void* A, void* B, const Layout& L,
+                      const Grid& G, const DdfParams& prm, double* partials, hipStream_t s);
+hipError_t launch_init_ddf(int kind, const double* rho, const double* u, const double* T,
+                           void* A, const Layout& L, const DdfParams& prm, hipStream_t s);
+hipError_t launch_moments_ddf(int kind, const void* A, const Layout& L, const DdfParams& prm,
+                              double* rho, double* u, double* T, double* edens, hipStream_t s);
+hipError_t launch_decode_ddf(int kind, int i, const void* A, const Layout& L,
+                             const DdfParams& prm, double* out, hipStream_t s);
 // Deterministic final pass over per-block partials: out[0] = t, out[1..5] = totals.
 hipError_t launch_diag_finalize(const double* partials, int nblocks, double t, double* out,
                                 hipStream_t s);

@@ -73,12 +73,13 @@ def random_phase_turbulence_2d(n, seed, kmax_frac=0.125, rms_mach=RMS_MACH_TURB)
     return rho, u
 
 
-def thermal_shear_layer(n, seed, ny=None, ushear=0.05, dT=0.1, T0=1.0, P0=1.0 / 3.0,
+def thermal_shear_layer(n, seed, ny=None, ushear=0.05, dT=0.1, T0=0.9, P0=1.0 / 3.0,
                         R=1.0 / 3.0, pert=5e-4, modes=8):
     """Thermal shear layer between walls at y = -1/2 and y = ny - 1/2.
 
     s = (y - y_c)/delta with y_c = (ny - 1)/2 and delta = n/128 (at least 1);
     u_x = ushear tanh(s);  T = T0 + dT tanh(s);  uniform pressure P0, rho = P0 / (R T);
+    the default T0 = 0.9 keeps T in [0.8, 1.0], i.e. theta = R T <= 1/3 with R = 1/3;
     u_y = pert * sum_{m=1..modes} a_m sin(2 pi m x / n + phi_m) exp(-s^2),
     with a_m and phi_m / (2 pi) uniform on [0, 1) from the seed.
     Returns rho, u (2, ny, n), T.

@@ -1,0 +1,130 @@
+"""GPU parity of the double-distribution (ideal gas) HIP kernel against the FP64 oracle.
+
+Bars: float64 storage 1e-12 (exact indexing, rounding order only); float32 storage rel-L2
+<= 1e-5 on velocity (and on temperature deviations)."""
+import numpy as np
+import pytest
+
+from gpu_util import announce, rel_l2, require_gpu
+from oracle import bgk, ddf
+from paper_2609_28679_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+R, CV, P0 = 1.0 / 3.0, 5.0 / 6.0, 1.0 / 3.0
+STENCIL = {1: "central", 2: "upwind"}
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _gas(tau):
+    return ddf.Gas(R, CV, (tau - 0.5) * P0)
+
+
+def _oracle(rho, u, T, tau, steps, walls, phi):
+    gas = _gas(tau)
+    f, g = ddf.init_equilibrium(rho, u, T, gas)
+    f, g = ddf.run(f, g, gas, steps, walls_y=walls, phi_on=phi > 0,
+                   stencil=STENCIL.get(phi, "central"))
+    return ddf.temperature(f, g, gas)
+
+
+def _gpu(rho, u, T, tau, steps, walls, phi, storage, **kw):
+    from paper_2609_28679_amd.binding import Lattice
+    lat = Lattice(rho, u, T, model="ddf", tau=tau, wall_y=walls, phi=phi, storage=storage,
+                  R=R, cv=CV, **kw)
+    lat.step(steps)
+    r, v, t, tot = lat.moments()
+    lat.close()
+    return r, v, t, tot
+
+
+@pytest.mark.parametrize("phi", [1, 2, 0])
+@pytest.mark.parametrize("walls", [True, False])
+def test_fp64_exact(phi, walls):
+    announce("DDF fp64 shear layer 128x64 phi=%d walls=%s 40 steps" % (phi, walls))
+    rho, u, T = inputs.thermal_shear_layer(128, seed=0, ny=64)
+    if not walls:  # periodic in y: use a smooth periodic temperature and velocity field
+        rho, u = inputs.random_phase_turbulence_2d(64, seed=2)
+        T = 0.9 + 0.05 * np.sin(2 * np.pi * np.arange(64) / 64)[None, :] * np.ones((64, 1))
+        rho = P0 / (R * T)
+    if phi == 2:
+        # The upwind stencil switches sides with the sign of u_a, so where u_a is zero to
+        # rounding (the shear layer's u_y underflows to exactly 0 away from its centre) the
+        # two float64 implementations may pick different sides. Break those exact zeros.
+        u = u + 1e-3 * np.random.default_rng(9).standard_normal(u.shape)
+    rg, ug, tg, _ = _gpu(rho, u, T, 0.6, 40, walls, phi, "fp64")
+    ro, uo, to = _oracle(rho, u, T, 0.6, 40, walls, phi)
+    assert np.abs(rg - ro).max() <= 1e-13
+    assert np.abs(ug - uo).max() <= 1e-13
+    assert np.abs(tg - to).max() <= 1e-13
+
+
+@pytest.mark.parametrize("nx,ny", [(300, 37), (5, 3), (254, 33), (509, 70)])
+def test_fp64_ragged_tiles(nx, ny):
+    announce("DDF fp64 ragged %dx%d walls" % (nx, ny))
+    rng = np.random.default_rng(nx + ny)
+    T = 0.9 + 0.05 * rng.standard_normal((ny, nx))
+    rho = P0 / (R * T) * (1 + 0.01 * rng.standard_normal((ny, nx)))
+    u = 0.02 * rng.standard_normal((2, ny, nx))
+    for phi in (1, 2):
+        rg, ug, tg, _ = _gpu(rho, u, T, 0.7, 12, True, phi, "fp64")
+        ro, uo, to = _oracle(rho, u, T, 0.7, 12, True, phi)
+        assert np.abs(ug - uo).max() <= 1e-13, phi
+        assert np.abs(tg - to).max() <= 1e-13, phi
+
+
+def test_fp32_shear_layer_parity():
+    announce("DDF fp32 shear layer 128x64 walls phi=1 300 steps")
+    rho, u, T = inputs.thermal_shear_layer(128, seed=0, ny=64)
+    _, ug, tg, _ = _gpu(rho, u, T, 0.6, 300, True, 1, "fp32")
+    _, uo, to = _oracle(rho, u, T, 0.6, 300, True, 1)
+    assert rel_l2(ug, uo) <= 1e-5
+    assert rel_l2(tg - 0.9, to - 0.9) <= 1e-5
+
+
+def test_conservation_fp32_walls():
+    announce("DDF fp32 conservation 512x256 walls 2000 steps")
+    rho, u, T = inputs.thermal_shear_layer(512, seed=0, ny=256)
+    from paper_2609_28679_amd.binding import Lattice
+    lat = Lattice(rho, u, T, model="ddf", tau=0.6, wall_y=True, phi=1, diag_every=100)
+    m0 = lat.moments()[3]
+    lat.step(2000)
+    h = lat.diag_history()
+    lat.close()
+    assert len(h) == 20
+    assert np.all(np.abs(h[:, 1] - m0[0]) / m0[0] < 1e-6)   # mass
+    assert np.all(np.abs(h[:, 5] - m0[4]) / m0[4] < 1e-6)   # total energy
+
+
+def test_full_size_rows_single_step():
+    announce("DDF fp32 full size 4096^2 walls: one step at sampled rows")
+    n = 4096
+    rho, u, T = inputs.thermal_shear_layer(n, seed=0)
+    from paper_2609_28679_amd.binding import Lattice
+    lat = Lattice(rho, u, T, model="ddf", tau=0.6, wall_y=True, phi=1)
+    lat.step(10)
+    f_post, g_post = lat.populations()
+    lat.step(1)
+    f_next, g_next = lat.populations()
+    lat.close()
+    gas = _gas(0.6)
+    for c in (0, 1, 2047, n - 2, n - 1):
+        lo, hi = max(c - 2, 0), min(c + 3, n)
+        # pre-collision populations of rows lo..hi-1: pull from the rows around them
+        src_lo, src_hi = max(lo - 1, 0), min(hi + 1, n)
+        fs = bgk.stream(f_post[:, src_lo:src_hi], walls_y=True)
+        gs = bgk.stream(g_post[:, src_lo:src_hi], walls_y=True)
+        # the slab's own first/last rows are only correct where they are real walls
+        keep = slice(lo - src_lo, hi - src_lo)
+        fpre, gpre = fs[:, keep], gs[:, keep]
+        # collide the slab (Phi from the slab's rows: exact for row c, which has both
+        # neighbours inside it or a wall next to it)
+        walls_slab = True
+        ft, gt = ddf.collide(fpre, gpre, gas, walls_slab, True, "central")
+        k = c - lo
+        assert np.abs(ft[:, k] - f_next[:, c]).max() <= 2e-6 * np.abs(f_next[:, c]).max(), c
+        assert np.abs(gt[:, k] - g_next[:, c]).max() <= 2e-6 * np.abs(g_next[:, c]).max(), c
