@@ -156,6 +156,10 @@ def main():
             lambda: binding.Lattice(rs, us, ts, model="ddf", tau=0.6, wall_y=True, phi=1),
             max(100, vs // 4), 10, 144, {"walls": "y", "phi": "central"})
         del rs, us, ts
+        for st in ("bf16", "fp16"):
+            variants["d2q9_bgk_%s_2048" % st] = variant(
+                "d2q9_bgk_%s_2048" % st, lambda: binding.Lattice(rho, u, tau=tau, storage=st),
+                vs, 20, 48, {"storage": "fp32 moments + %s f-f_eq (6 of 9 stored)" % st})
         variants["d2q9_bgk_fp64_2048"] = variant(
             "d2q9_bgk_fp64_2048", lambda: binding.Lattice(rho, u, tau=tau, storage="fp64"),
             max(200, vs // 4), 20, 144)

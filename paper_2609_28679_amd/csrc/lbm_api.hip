@@ -26,6 +26,8 @@ struct lbm_ctx {
   int D = 2, Q = 9;
   int kind = 0;  // 0: float32 populations, 1: float64
   bool ddf = false;  // double-distribution ideal-gas model
+  int codec = -1;    // reduced storage: 0 = bfloat16, 1 = float16 (scaled); -1 = none
+  float s_enc = 1.0f, s_dec = 1.0f;
   int planes = 9;    // stored population planes per buffer
   DdfParams dp{};
   Layout L{};
@@ -68,7 +70,7 @@ int hip_fail(lbm_ctx* c, hipError_t e, const char* where) {
   } while (0)
 
 struct Plan {
-  int D, Q, kind, planes;
+  int D, Q, kind, planes, codec;
   bool ddf;
   Layout L;
   Grid G;
@@ -94,7 +96,10 @@ int validate(const lbm_params* p, std::string& why) {
     if (!(p->R > 0.0) || !(p->cv > 0.0) || !std::isfinite(p->R) || !std::isfinite(p->cv)) { why = "R and cv must be positive"; return LBM_EINVAL; }
     if (p->phi < 0 || p->phi > 2) { why = "phi must be 0 (off), 1 (central) or 2 (upwind)"; return LBM_EINVAL; }
   }
-  if (p->storage != LBM_STORE_FP32 && p->storage != LBM_STORE_FP64) { why = "storage not supported for this model"; return LBM_EINVAL; }
+  const bool reduced = p->storage == LBM_STORE_BF16 || p->storage == LBM_STORE_FP16;
+  if (reduced && p->lattice != LBM_D2Q9) { why = "reduced storage is D2Q9 only"; return LBM_EINVAL; }
+  if (reduced && p->model != LBM_MODEL_BGK) { why = "reduced storage not supported for this model"; return LBM_EINVAL; }
+  if (p->storage == LBM_STORE_FP16 && (p->fp16_scale_log2 < 0 || p->fp16_scale_log2 > 24)) { why = "fp16_scale_log2 must be in [0, 24]"; return LBM_EINVAL; }
   if (p->collision != LBM_COLLIDE_PLAIN) { why = "collision not supported for this configuration"; return LBM_EINVAL; }
   if (p->workspace && (reinterpret_cast<uintptr_t>(p->workspace) & 255u)) { why = "workspace must be 256-byte aligned"; return LBM_EINVAL; }
   return LBM_OK;
@@ -104,6 +109,7 @@ void make_plan(const lbm_params* p, Plan& P) {
   P.D = p->lattice == LBM_D2Q9 ? 2 : 3;
   P.Q = P.D == 2 ? 9 : 27;
   P.kind = p->storage == LBM_STORE_FP64 ? 1 : 0;
+  P.codec = p->storage == LBM_STORE_BF16 ? 0 : (p->storage == LBM_STORE_FP16 ? 1 : -1);
   P.ddf = p->model == LBM_MODEL_DDF;
   P.planes = P.ddf ? 2 * P.Q : P.Q;
   P.elem = P.kind ? 8 : 4;
@@ -127,7 +133,9 @@ void make_plan(const lbm_params* p, Plan& P) {
   P.G = P.ddf ? make_grid_ddf(P.L, p->phi == 2 ? 2 : 1) : make_grid(P.L);
   P.partial_slots = std::max(P.G.blocks(), 1024);
   size_t off = 0;
-  const size_t pop = (size_t)P.planes * P.L.plane * P.elem;
+  // reduced storage: 3 float32 moment planes + 6 uint16 non-equilibrium planes
+  const size_t pop = P.codec >= 0 ? (size_t)P.L.plane * (3 * 4 + 6 * 2)
+                                   : (size_t)P.planes * P.L.plane * P.elem;
   P.off_A = off; off = align_up(off + pop, 256);
   P.off_B = off; off = align_up(off + pop, 256);
   P.off_part = off; off = align_up(off + (size_t)P.partial_slots * kDiagValues * 8, 256);
@@ -215,6 +223,11 @@ int lbm_create(const lbm_params* p, const double* rho0, const double* u0, const 
   c->Q = P.Q;
   c->kind = P.kind;
   c->ddf = P.ddf;
+  c->codec = P.codec;
+  if (P.codec == 1) {
+    c->s_enc = std::ldexp(1.0f, p->fp16_scale_log2);
+    c->s_dec = std::ldexp(1.0f, -p->fp16_scale_log2);
+  }
   c->planes = P.planes;
   c->dp.R = p->R;
   c->dp.cv = p->cv;
@@ -276,6 +289,8 @@ int lbm_create(const lbm_params* p, const double* rho0, const double* u0, const 
     }
     if (e == hipSuccess) e = launch_init_ddf(c->kind, c->readout, c->readout + nodes, c->readout + 3 * nodes, c->B, c->L, c->dp, c->stream);
     if (e == hipSuccess) e = launch_ddf(c->kind, p->wall_y != 0, false, c->B, c->A, c->L, c->G, c->dp, nullptr, c->stream);
+  } else if (e == hipSuccess && c->codec >= 0) {
+    e = launch_init_bgk_red(c->readout, c->readout + nodes, c->A, c->L, c->stream);
   } else if (e == hipSuccess) {
     e = launch_init_bgk(c->kind, c->D, c->readout, c->readout + nodes, c->A, c->L, c->stream);
   }
@@ -300,6 +315,8 @@ int lbm_step(lbm_ctx* c, int64_t n) {
     hipError_t e;
     if (c->ddf)
       e = launch_ddf(c->kind, c->p.wall_y != 0, true, c->A, c->B, c->L, c->G, c->dp, part, c->stream);
+    else if (c->codec >= 0)
+      e = launch_bgk_d2q9_red(c->codec, c->A, c->B, c->L, c->G, c->omega, c->p.wall_y != 0, c->s_enc, c->s_dec, part, c->stream);
     else if (c->D == 2)
       e = launch_bgk_d2q9(c->kind, c->A, c->B, c->L, c->G, c->omega, c->p.wall_y != 0, part, c->stream);
     else
@@ -350,6 +367,8 @@ int lbm_moments(lbm_ctx* c, double* rho, double* u, double* T, double* totals) {
   double* d_e = d_T + nodes;
   if (c->ddf)
     HIP_TRY(c, launch_moments_ddf(c->kind, c->A, c->L, c->dp, d_rho, d_u, d_T, d_e, c->stream));
+  else if (c->codec >= 0)
+    HIP_TRY(c, launch_moments_bgk_red(c->A, c->L, d_rho, d_u, c->stream));
   else
     HIP_TRY(c, launch_moments_bgk(c->kind, c->D, c->A, c->L, d_rho, d_u, c->stream));
   if (totals) {
@@ -377,6 +396,8 @@ int lbm_populations(lbm_ctx* c, double* f, double* g) {
     if (!dst) continue;
     if (c->ddf)
       HIP_TRY(c, launch_decode_ddf(c->kind, i, c->A, c->L, c->dp, c->readout, c->stream));
+    else if (c->codec >= 0)
+      HIP_TRY(c, launch_decode_bgk_red(c->codec, i, c->A, c->L, c->s_dec, c->readout, c->stream));
     else
       HIP_TRY(c, launch_decode_f(c->kind, c->D, i, c->A, c->L, c->readout, c->stream));
     HIP_TRY(c, hipMemcpyAsync(dst, c->readout, nodes * sizeof(double), hipMemcpyDeviceToHost, c->stream));

@@ -70,6 +70,17 @@ hipError_t launch_moments_ddf(int kind, const void* A, const Layout& L, const Dd
                               double* rho, double* u, double* T, double* edens, hipStream_t s);
 hipError_t launch_decode_ddf(int kind, int i, const void* A, const Layout& L,
                              const DdfParams& prm, double* out, hipStream_t s);
+// Reduced storage (D2Q9 isothermal): 3 float32 moment planes then 6 uint16 planes.
+// codec 0 = bfloat16, 1 = float16 with scale s_enc = 2^S, s_dec = 2^-S.
+hipError_t launch_bgk_d2q9_red(int codec, const void* A, void* B, const Layout& L, const Grid& G,
+                               double omega, bool walls, float s_enc, float s_dec,
+                               double* partials, hipStream_t s);
+hipError_t launch_init_bgk_red(const double* rho, const double* u, void* A, const Layout& L,
+                               hipStream_t s);
+hipError_t launch_moments_bgk_red(const void* A, const Layout& L, double* rho, double* u,
+                                  hipStream_t s);
+hipError_t launch_decode_bgk_red(int codec, int i, const void* A, const Layout& L, float s_dec,
+                                 double* out, hipStream_t s);
 // Deterministic final pass over per-block partials: out[0] = t, out[1..5] = totals.
 hipError_t launch_diag_finalize(const double* partials, int nblocks, double t, double* out,
                                 hipStream_t s);
