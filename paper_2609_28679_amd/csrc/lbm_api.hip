@@ -46,7 +46,23 @@ struct lbm_ctx {
   int64_t t = 0;
   double omega = 0.0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  float* mlp_w = nullptr;                  // surrogate weights (kMlpParams floats)
+  unsigned long long* mlp_cnt = nullptr;   // {fallbacks, updates}
+  bool mlp_set = false;
+  double mlp_tol = 0.0;
   std::string err;
+};
+
+struct lbm_mlp {
+  hipStream_t stream = nullptr;
+  float* w = nullptr;  // float32 master weights
+  float* m = nullptr;  // Adam first moment
+  float* v = nullptr;  // Adam second moment
+  float* partials = nullptr;
+  size_t partial_rows = 0;
+  float* scratch = nullptr;  // loss
+  int64_t t = 0;             // Adam steps taken
+  int64_t offset = 0;        // next training sample
 };
 
 namespace {
@@ -75,7 +91,7 @@ struct Plan {
   Layout L;
   Grid G;
   size_t elem;
-  size_t off_A, off_B, off_part, off_hist, off_read, total;
+  size_t off_A, off_B, off_part, off_hist, off_read, off_mlp, total;
   int partial_slots;
 };
 
@@ -100,7 +116,12 @@ int validate(const lbm_params* p, std::string& why) {
   if (reduced && p->lattice != LBM_D2Q9) { why = "reduced storage is D2Q9 only"; return LBM_EINVAL; }
   if (reduced && p->model != LBM_MODEL_BGK) { why = "reduced storage not supported for this model"; return LBM_EINVAL; }
   if (p->storage == LBM_STORE_FP16 && (p->fp16_scale_log2 < 0 || p->fp16_scale_log2 > 24)) { why = "fp16_scale_log2 must be in [0, 24]"; return LBM_EINVAL; }
-  if (p->collision != LBM_COLLIDE_PLAIN) { why = "collision not supported for this configuration"; return LBM_EINVAL; }
+  if (p->collision == LBM_COLLIDE_MLP &&
+      (p->lattice != LBM_D2Q9 || p->model != LBM_MODEL_BGK || p->storage != LBM_STORE_FP32)) {
+    why = "the surrogate collision needs D2Q9, the isothermal model and float32 storage";
+    return LBM_EINVAL;
+  }
+  if (!(p->mlp_tol >= 0.0)) { why = "mlp_tol must be >= 0"; return LBM_EINVAL; }
   if (p->workspace && (reinterpret_cast<uintptr_t>(p->workspace) & 255u)) { why = "workspace must be 256-byte aligned"; return LBM_EINVAL; }
   return LBM_OK;
 }
@@ -130,7 +151,8 @@ void make_plan(const lbm_params* p, Plan& P) {
   const int64_t raw = P.L.pitch * p->ny * p->nz;
   const int64_t epk = (int64_t)(4096 / P.elem);
   P.L.plane = (raw + epk - 1) / epk * epk + plane_pad;
-  P.G = P.ddf ? make_grid_ddf(P.L, p->phi == 2 ? 2 : 1) : make_grid(P.L);
+  P.G = P.ddf ? make_grid_ddf(P.L, p->phi == 2 ? 2 : 1)
+              : (p->collision == LBM_COLLIDE_MLP ? make_grid_mlp(P.L) : make_grid(P.L));
   P.partial_slots = std::max(P.G.blocks(), 1024);
   size_t off = 0;
   // reduced storage: 3 float32 moment planes + 6 uint16 non-equilibrium planes
@@ -141,6 +163,9 @@ void make_plan(const lbm_params* p, Plan& P) {
   P.off_part = off; off = align_up(off + (size_t)P.partial_slots * kDiagValues * 8, 256);
   P.off_hist = off; off = align_up(off + (size_t)kHistoryCap * 6 * 8, 256);
   P.off_read = off; off = align_up(off + (size_t)P.L.nodes() * (P.D + 3) * 8, 256);
+  // surrogate region: 16 bytes of 64-bit counters (8-byte aligned for the atomics), then the
+  // weights 256 bytes further
+  P.off_mlp = off; off = align_up(off + 256 + (size_t)kMlpParams * 4, 256);
   P.total = off;
 }
 
@@ -265,6 +290,9 @@ int lbm_create(const lbm_params* p, const double* rho0, const double* u0, const 
   c->partials = reinterpret_cast<double*>(c->ws + P.off_part);
   c->history = reinterpret_cast<double*>(c->ws + P.off_hist);
   c->readout = reinterpret_cast<double*>(c->ws + P.off_read);
+  c->mlp_cnt = reinterpret_cast<unsigned long long*>(c->ws + P.off_mlp);
+  c->mlp_w = reinterpret_cast<float*>(c->ws + P.off_mlp + 256);
+  c->mlp_tol = p->mlp_tol;
   if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
     c->err = "hipEventCreate failed";
     return cleanup_fail(LBM_EDEVICE);
@@ -313,7 +341,10 @@ int lbm_step(lbm_ctx* c, int64_t n) {
     const bool diag = de > 0 && tn % de == 0;
     double* part = diag ? c->partials : nullptr;
     hipError_t e;
-    if (c->ddf)
+    if (c->p.collision == LBM_COLLIDE_MLP) {
+      if (!c->mlp_set) return fail(c, LBM_ESTATE, "surrogate weights not installed (lbm_set_mlp)");
+      e = launch_bgk_d2q9_mlp(c->A, c->B, c->L, c->G, c->omega, c->p.wall_y != 0, c->mlp_w, c->mlp_tol, c->mlp_cnt, part, c->stream);
+    } else if (c->ddf)
       e = launch_ddf(c->kind, c->p.wall_y != 0, true, c->A, c->B, c->L, c->G, c->dp, part, c->stream);
     else if (c->codec >= 0)
       e = launch_bgk_d2q9_red(c->codec, c->A, c->B, c->L, c->G, c->omega, c->p.wall_y != 0, c->s_enc, c->s_dec, part, c->stream);
@@ -432,42 +463,136 @@ int lbm_diag_history(lbm_ctx* c, double* out, int32_t max_entries, int32_t* n_en
 
 int lbm_set_mlp(lbm_ctx* c, const float* weights, double tol) {
   if (!c) return fail(nullptr, LBM_ESTATE, "NULL context");
-  (void)weights;
-  (void)tol;
-  return fail(c, LBM_EINVAL, "surrogate collision not available in this configuration");
+  if (c->p.collision != LBM_COLLIDE_MLP) return fail(c, LBM_EINVAL, "context was not created with collision = LBM_COLLIDE_MLP");
+  if (!weights) return fail(c, LBM_EINVAL, "weights is NULL");
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(c, LBM_EINVAL, "tol must be finite and >= 0");
+  for (int k = 0; k < kMlpParams; ++k)
+    if (!std::isfinite(weights[k])) return fail(c, LBM_EINVAL, "non-finite weight at index " + std::to_string(k));
+  HIP_TRY(c, hipMemcpyAsync(c->mlp_w, weights, (size_t)kMlpParams * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->mlp_cnt, 0, 16, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->mlp_tol = tol;
+  c->mlp_set = true;
+  return LBM_OK;
 }
 
 int lbm_mlp_stats(lbm_ctx* c, int64_t* fallbacks, int64_t* updates) {
   if (!c) return fail(nullptr, LBM_ESTATE, "NULL context");
-  (void)fallbacks;
-  (void)updates;
-  return fail(c, LBM_EINVAL, "surrogate collision not available in this configuration");
+  if (c->p.collision != LBM_COLLIDE_MLP) return fail(c, LBM_EINVAL, "no surrogate collision in this context");
+  unsigned long long h[2] = {0, 0};
+  HIP_TRY(c, hipMemcpyAsync(h, c->mlp_cnt, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (fallbacks) *fallbacks = (int64_t)h[0];
+  if (updates) *updates = (int64_t)h[1];
+  return LBM_OK;
 }
 
 int lbm_harvest(lbm_ctx* c, int64_t n, const int64_t* dev_nodes, float* dev_x, float* dev_y) {
   if (!c) return fail(nullptr, LBM_ESTATE, "NULL context");
-  (void)n; (void)dev_nodes; (void)dev_x; (void)dev_y;
-  return fail(c, LBM_EINVAL, "harvest not available in this configuration");
+  if (c->D != 2 || c->ddf || c->kind != 0 || c->codec >= 0)
+    return fail(c, LBM_EINVAL, "harvest needs a D2Q9 isothermal context with float32 storage");
+  if (n < 0 || (n > 0 && (!dev_nodes || !dev_x || !dev_y))) return fail(c, LBM_EINVAL, "invalid harvest buffers");
+  if (n == 0) return LBM_OK;
+  HIP_TRY(c, launch_harvest(c->A, c->L, c->p.wall_y != 0, c->omega, dev_nodes, n, dev_x, dev_y, c->stream));
+  return LBM_OK;
 }
 
+namespace {
+int mlp_fail(int code, const std::string& msg) { return fail(nullptr, code, msg); }
+
+int mlp_ensure_partials(lbm_mlp* m, int B) {
+  const size_t rows = (size_t)mlp_partial_count(B);
+  if (rows <= m->partial_rows) return LBM_OK;
+  if (m->partials) (void)hipFree(m->partials);
+  m->partials = nullptr;
+  m->partial_rows = 0;
+  hipError_t e = hipMalloc(&m->partials, rows * (kMlpParams + 1) * sizeof(float));
+  if (e != hipSuccess) return mlp_fail(LBM_ENOMEM, std::string("trainer partials: ") + hipGetErrorString(e));
+  m->partial_rows = rows;
+  return LBM_OK;
+}
+}  // namespace
+
 int lbm_mlp_create(const float* weights, void* stream, lbm_mlp** out) {
-  (void)weights; (void)stream;
-  if (out) *out = nullptr;
-  return fail(nullptr, LBM_EINVAL, "surrogate trainer not available in this build");
+  if (!out) return mlp_fail(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!weights) return mlp_fail(LBM_EINVAL, "weights is NULL");
+  lbm_mlp* m = new lbm_mlp();
+  m->stream = static_cast<hipStream_t>(stream);
+  const size_t bytes = (size_t)kMlpParams * 4;
+  hipError_t e = hipMalloc(&m->w, bytes);
+  if (e == hipSuccess) e = hipMalloc(&m->m, bytes);
+  if (e == hipSuccess) e = hipMalloc(&m->v, bytes);
+  if (e == hipSuccess) e = hipMalloc(&m->scratch, 256);
+  if (e == hipSuccess) e = hipMemcpyAsync(m->w, weights, bytes, hipMemcpyHostToDevice, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(m->m, 0, bytes, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(m->v, 0, bytes, m->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+  if (e != hipSuccess) {
+    lbm_mlp_destroy(m);
+    return mlp_fail(LBM_ENOMEM, std::string("trainer allocation: ") + hipGetErrorString(e));
+  }
+  *out = m;
+  return LBM_OK;
 }
-void lbm_mlp_destroy(lbm_mlp* m) { (void)m; }
-int lbm_mlp_get(lbm_mlp* m, float* w) { (void)m; (void)w; return fail(nullptr, LBM_ESTATE, "no trainer"); }
+
+void lbm_mlp_destroy(lbm_mlp* m) {
+  if (!m) return;
+  (void)hipStreamSynchronize(m->stream);
+  if (m->w) (void)hipFree(m->w);
+  if (m->m) (void)hipFree(m->m);
+  if (m->v) (void)hipFree(m->v);
+  if (m->partials) (void)hipFree(m->partials);
+  if (m->scratch) (void)hipFree(m->scratch);
+  delete m;
+}
+
+int lbm_mlp_get(lbm_mlp* m, float* w) {
+  if (!m) return mlp_fail(LBM_ESTATE, "NULL trainer");
+  if (!w) return mlp_fail(LBM_EINVAL, "w is NULL");
+  hipError_t e = hipMemcpyAsync(w, m->w, (size_t)kMlpParams * 4, hipMemcpyDeviceToHost, m->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+  return e == hipSuccess ? LBM_OK : mlp_fail(LBM_EDEVICE, hipGetErrorString(e));
+}
+
 int lbm_mlp_forward(lbm_mlp* m, const float* x, int64_t n, float* y) {
-  (void)m; (void)x; (void)n; (void)y;
-  return fail(nullptr, LBM_ESTATE, "no trainer");
+  if (!m) return mlp_fail(LBM_ESTATE, "NULL trainer");
+  if (n < 0 || (n > 0 && (!x || !y))) return mlp_fail(LBM_EINVAL, "invalid buffers");
+  if (n == 0) return LBM_OK;
+  hipError_t e = launch_mlp_forward(x, n, m->w, y, m->stream);
+  return e == hipSuccess ? LBM_OK : mlp_fail(LBM_EDEVICE, hipGetErrorString(e));
 }
+
 int lbm_mlp_grad(lbm_mlp* m, const float* x, const float* t, int64_t n, float* g, float* loss) {
-  (void)m; (void)x; (void)t; (void)n; (void)g; (void)loss;
-  return fail(nullptr, LBM_ESTATE, "no trainer");
+  if (!m) return mlp_fail(LBM_ESTATE, "NULL trainer");
+  if (n <= 0 || n > (1 << 24) || !x || !t || !g) return mlp_fail(LBM_EINVAL, "invalid buffers or n outside [1, 2^24]");
+  int rc = mlp_ensure_partials(m, (int)n);
+  if (rc) return rc;
+  hipError_t e = launch_mlp_grad(x, t, n, 0, (int)n, m->w, m->partials, m->stream);
+  if (e == hipSuccess)
+    e = launch_mlp_reduce_adam(m->partials, mlp_partial_count((int)n), g, m->scratch, m->w, m->m, m->v, false, 0.0f, 1, m->stream);
+  if (e == hipSuccess && loss) {
+    e = hipMemcpyAsync(loss, m->scratch, sizeof(float), hipMemcpyDeviceToHost, m->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+  }
+  return e == hipSuccess ? LBM_OK : mlp_fail(LBM_EDEVICE, hipGetErrorString(e));
 }
-int lbm_mlp_train(lbm_mlp* m, const float* x, const float* t, int64_t n, int32_t b, int64_t s, float lr) {
-  (void)m; (void)x; (void)t; (void)n; (void)b; (void)s; (void)lr;
-  return fail(nullptr, LBM_ESTATE, "no trainer");
+
+int lbm_mlp_train(lbm_mlp* m, const float* x, const float* t, int64_t n, int32_t batch, int64_t steps, float lr) {
+  if (!m) return mlp_fail(LBM_ESTATE, "NULL trainer");
+  if (n <= 0 || batch <= 0 || batch > (1 << 20) || steps < 0 || !x || !t || !(lr > 0.0f))
+    return mlp_fail(LBM_EINVAL, "invalid training arguments");
+  int rc = mlp_ensure_partials(m, batch);
+  if (rc) return rc;
+  for (int64_t k = 0; k < steps; ++k) {
+    hipError_t e = launch_mlp_grad(x, t, n, m->offset, batch, m->w, m->partials, m->stream);
+    m->t += 1;
+    if (e == hipSuccess)
+      e = launch_mlp_reduce_adam(m->partials, mlp_partial_count(batch), nullptr, nullptr, m->w, m->m, m->v, true, lr, m->t, m->stream);
+    if (e != hipSuccess) return mlp_fail(LBM_EDEVICE, hipGetErrorString(e));
+    m->offset = (m->offset + batch) % n;
+  }
+  return LBM_OK;
 }
 
 const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err.c_str() : g_err.c_str(); }

@@ -81,6 +81,20 @@ hipError_t launch_moments_bgk_red(const void* A, const Layout& L, double* rho, d
                                   hipStream_t s);
 hipError_t launch_decode_bgk_red(int codec, int i, const void* A, const Layout& L, float s_dec,
                                  double* out, hipStream_t s);
+// Learned collision surrogate (D2Q9 isothermal, float32 storage).
+constexpr int kMlpParams = 5577;
+hipError_t launch_mlp_grad(const float* X, const float* T, int64_t n, int64_t start, int B,
+                           const float* w, float* partials, hipStream_t s);
+int mlp_partial_count(int B);  // partial gradient rows written by launch_mlp_grad (x 5578 floats)
+hipError_t launch_mlp_reduce_adam(const float* partials, int nw, float* grad, float* loss, float* w,
+                                  float* m, float* v, bool adam, float lr, int64_t t, hipStream_t s);
+hipError_t launch_mlp_forward(const float* X, int64_t n, const float* w, float* Y, hipStream_t s);
+hipError_t launch_harvest(const void* A, const Layout& L, bool walls, double omega,
+                          const int64_t* nodes, int64_t n, float* X, float* Y, hipStream_t s);
+Grid make_grid_mlp(const Layout& L);
+hipError_t launch_bgk_d2q9_mlp(const void* A, void* B, const Layout& L, const Grid& G, double omega,
+                               bool walls, const float* wblob, double tol,
+                               unsigned long long* counters, double* partials, hipStream_t s);
 // Deterministic final pass over per-block partials: out[0] = t, out[1..5] = totals.
 hipError_t launch_diag_finalize(const double* partials, int nblocks, double t, double* out,
                                 hipStream_t s);

@@ -1,0 +1,467 @@
+// Learned collision surrogate: training (forward, backward, Adam) and inference fused into the
+// D2Q9 stream-collide step, on bfloat16 matrix cores with float32 accumulation. See
+// mlp_common.h for the network, the transposed GEMM formulation and the register layouts.
+//
+// Training of one batch is two launches: k_mlp_grad (forward and backward, one wavefront per
+// 64 samples, per-wavefront partial gradients: the weight gradients are split along the
+// sample dimension, K) and k_mlp_reduce_adam (deterministic sum of the partials in a fixed
+// order, then the Adam update of the float32 master weights).
+#include "mlp_common.h"
+
+namespace lbm {
+
+constexpr int kPart = kNParam + 1;  // parameters + loss
+
+// ---- forward and backward of one batch -----------------------------------------------------
+// Samples (start + i) mod n for i in [0, B); wavefront w of the grid takes i in [64 w, 64 w + 64).
+__global__ void __launch_bounds__(kBlock)
+k_mlp_grad(const float* __restrict__ X, const float* __restrict__ T, int64_t n, int64_t start,
+           int B, const float* __restrict__ w, float* __restrict__ partials) {
+  __shared__ MlpLds s;
+  __shared__ short xs[4][64][16];
+  __shared__ float ys[4][64][16];
+  __shared__ short tA[4][64][64];
+  __shared__ short tB[4][64][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r = lane & 15, q = lane >> 4;
+  const int gw = blockIdx.x * 4 + wv;  // global wavefront
+  const int i_loc = gw * 64 + lane;
+  const bool valid = i_loc < B;
+  const int64_t idx = (start + (int64_t)(valid ? i_loc : 0)) % n;
+
+  mlp_load_lds(w, s);
+  // inputs (bfloat16, zero padded); invalid samples have zero input and zero gradient
+#pragma unroll
+  for (int k = 0; k < 16; ++k)
+    xs[wv][lane][k] = (valid && k < kIn) ? f2bf(X[idx * kIn + k]) : (short)0;
+  __syncthreads();
+
+  MlpAct a;
+  mlp_forward_wave(s, xs[wv], a, true);
+  // outputs to per-sample rows
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) ys[wv][16 * nt + r][4 * q + j] = a.y[nt][j];
+  // H2^T rows [hidden][sample] for dW3
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) tB[wv][16 * m + 4 * q + j][16 * nt + r] = a.h2[m][nt][j];
+  __syncthreads();
+
+  // ---- loss and output gradient (lane = sample) ----------------------------------------
+  float y[9], dy[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) y[i] = ys[wv][lane][i];
+  project9(y);
+  float loss = 0.0f;
+  const float scale = 2.0f / ((float)B * 9.0f);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const float d = valid ? y[i] - T[idx * kOut + i] : 0.0f;
+    loss += d * d;
+    dy[i] = scale * d;
+  }
+  project9(dy);  // the projection is symmetric: dL/dy = P dL/dyhat
+#pragma unroll
+  for (int o = 0; o < 16; ++o) tA[wv][o][lane] = o < 9 ? f2bf(dy[o]) : (short)0;
+  __syncthreads();
+
+  float* out = partials + (int64_t)gw * kPart;
+  // db3 and the loss: wavefront sums (fixed shuffle tree)
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const float v = (float)wave_sum((double)dy[i]);
+    if (lane == 0) out[oB3 + i] = v;
+  }
+  {
+    const float v = (float)wave_sum((double)loss);
+    if (lane == 0) out[kNParam] = v / ((float)B * 9.0f);
+  }
+  // dW3[o][h] = sum_s dy[s][o] h2[s][h]: A = dY^T (rows o), B = H2 (cols h), K = samples
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt)
+      acc = mfma16(ld4(&tA[wv][r][16 * kt + 4 * q]), ld4(&tB[wv][16 * nt + r][16 * kt + 4 * q]), acc);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (4 * q + j < kOut) out[oW3 + (4 * q + j) * kHid + 16 * nt + r] = acc[j];
+  }
+  // dH2^T = W3^T dY^T, then dZ2 = dH2 gelu'(Z2)
+  bf16x4 dz2[4][4];
+  float db2[4][4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    bf16x4 wa;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) wa[j] = s.w3[4 * q + j][16 * m + r];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) db2[m][j] = 0.0f;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      bf16x4 bb;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bb[j] = tA[wv][4 * q + j][16 * nt + r];
+      f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+      acc = mfma16(wa, bb, acc);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float g, dg;
+        gelu_and_grad(a.z2[m][nt][j], g, dg);
+        const float d = acc[j] * dg;
+        db2[m][j] += d;
+        dz2[m][nt][j] = f2bf(d);
+      }
+    }
+  }
+  __syncthreads();  // tA (dY^T) and tB (H2^T) are free again
+  // dZ2 rows [out][sample] into tA, H1^T rows [hidden][sample] into tB
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        tA[wv][16 * m + 4 * q + j][16 * nt + r] = dz2[m][nt][j];
+        tB[wv][16 * m + 4 * q + j][16 * nt + r] = a.h1[m][nt][j];
+      }
+  // db2: sum over the 16 lanes that share q (samples r)
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float v = db2[m][j];
+      v += __shfl_xor(v, 8, 64);
+      v += __shfl_xor(v, 4, 64);
+      v += __shfl_xor(v, 2, 64);
+      v += __shfl_xor(v, 1, 64);
+      if (r == 0) out[oB2 + 16 * m + 4 * q + j] = v;
+    }
+  __syncthreads();
+  // dW2 = dZ2^T H1
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int kt = 0; kt < 4; ++kt)
+        acc = mfma16(ld4(&tA[wv][16 * m + r][16 * kt + 4 * q]), ld4(&tB[wv][16 * nt + r][16 * kt + 4 * q]), acc);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) out[oW2 + (16 * m + 4 * q + j) * kHid + 16 * nt + r] = acc[j];
+    }
+  // dH1^T = W2^T dZ2^T, dZ1 = dH1 gelu'(Z1)
+  bf16x4 dz1[4][4];
+  float db1[4][4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    bf16x4 wa[4];
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) wa[kt][j] = s.w2[16 * kt + 4 * q + j][16 * m + r];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) db1[m][j] = 0.0f;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int kt = 0; kt < 4; ++kt) acc = mfma16(wa[kt], dz2[kt][nt], acc);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float g, dg;
+        gelu_and_grad(a.z1[m][nt][j], g, dg);
+        const float d = acc[j] * dg;
+        db1[m][j] += d;
+        dz1[m][nt][j] = f2bf(d);
+      }
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float v = db1[m][j];
+      v += __shfl_xor(v, 8, 64);
+      v += __shfl_xor(v, 4, 64);
+      v += __shfl_xor(v, 2, 64);
+      v += __shfl_xor(v, 1, 64);
+      if (r == 0) out[oB1 + 16 * m + 4 * q + j] = v;
+    }
+  __syncthreads();  // tA, tB free
+  // dZ1 rows [out][sample] into tA, X^T rows [feature][sample] into tB
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) tA[wv][16 * m + 4 * q + j][16 * nt + r] = dz1[m][nt][j];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) tB[wv][k][lane] = xs[wv][lane][k];
+  __syncthreads();
+  // dW1 = dZ1^T X (features 0..11 of 16)
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt)
+      acc = mfma16(ld4(&tA[wv][16 * m + r][16 * kt + 4 * q]), ld4(&tB[wv][r][16 * kt + 4 * q]), acc);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (r < kIn) out[oW1 + (16 * m + 4 * q + j) * kIn + r] = acc[j];
+  }
+}
+
+// Sum of the per-wavefront partials in wavefront order; optional gradient output and Adam step.
+__global__ void k_mlp_reduce_adam(const float* __restrict__ partials, int nw, float* __restrict__ grad,
+                                  float* __restrict__ loss, float* __restrict__ w, float* __restrict__ m,
+                                  float* __restrict__ v, int adam, float lr, float b1, float b2,
+                                  float eps, float c1, float c2) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p > kNParam) return;
+  float g = 0.0f;
+  for (int k = 0; k < nw; ++k) g += partials[(int64_t)k * kPart + p];
+  if (p == kNParam) {
+    if (loss) *loss = g;
+    return;
+  }
+  if (grad) grad[p] = g;
+  if (adam) {
+    const float mm = b1 * m[p] + (1.0f - b1) * g;
+    const float vv = b2 * v[p] + (1.0f - b2) * g * g;
+    m[p] = mm;
+    v[p] = vv;
+    // bias-corrected moments: c1 = 1 - b1^t, c2 = 1 - b2^t
+    w[p] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+  }
+}
+
+// Forward pass for n samples (projected outputs).
+__global__ void __launch_bounds__(kBlock)
+k_mlp_forward(const float* __restrict__ X, int64_t n, const float* __restrict__ w, float* __restrict__ Y) {
+  __shared__ MlpLds s;
+  __shared__ short xs[4][64][16];
+  __shared__ float ys[4][64][16];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t i = ((int64_t)blockIdx.x * 4 + wv) * 64 + lane;
+  const bool valid = i < n;
+  mlp_load_lds(w, s);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) xs[wv][lane][k] = (valid && k < kIn) ? f2bf(X[i * kIn + k]) : (short)0;
+  __syncthreads();
+  MlpAct a;
+  mlp_forward_wave(s, xs[wv], a, false);
+  const int r = lane & 15, q = lane >> 4;
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) ys[wv][16 * nt + r][4 * q + j] = a.y[nt][j];
+  __syncthreads();
+  float y[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) y[k] = ys[wv][lane][k];
+  project9(y);
+  if (valid)
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Y[i * kOut + k] = y[k];
+}
+
+// ---- lattice side: harvest and surrogate step ------------------------------------------------
+__device__ __forceinline__ double wrest(int i) {
+  return (i % 3 == 1 ? 2.0 / 3.0 : 1.0 / 6.0) * (i / 3 == 1 ? 2.0 / 3.0 : 1.0 / 6.0);
+}
+
+// Pre-collision populations at node (x, y) pulled from the shifted float32 state A.
+template <bool WALLS>
+__device__ __forceinline__ void pull9(const float* __restrict__ A, int nx, int ny, int64_t pitch,
+                                      int64_t plane, int x, int y, double (&f)[9]) {
+  const int xs[3] = {x == nx - 1 ? 0 : x + 1, x, x == 0 ? nx - 1 : x - 1};
+  const int ys[3] = {y == ny - 1 ? 0 : y + 1, y, y == 0 ? ny - 1 : y - 1};
+  const int64_t self = (int64_t)y * pitch + x;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int ka = i % 3, kb = i / 3;
+    const bool bounce = WALLS && ((kb == 2 && y == 0) || (kb == 0 && y == ny - 1));
+    const float h = bounce ? A[(8 - i) * plane + self] : A[i * plane + (int64_t)ys[kb] * pitch + xs[ka]];
+    f[i] = (double)h + wrest(i);
+  }
+}
+
+template <bool WALLS>
+__global__ void k_harvest(const float* __restrict__ A, int nx, int ny, int64_t pitch, int64_t plane,
+                          double omega, const int64_t* __restrict__ nodes, int64_t n,
+                          float* __restrict__ X, float* __restrict__ Y) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int64_t node = nodes[k];
+  const int x = (int)(node % nx), y = (int)(node / nx);
+  double f[9];
+  pull9<WALLS>(A, nx, ny, pitch, plane, x, y, f);
+  const double rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+  const double ux = ((f[2] + f[5] + f[8]) - (f[0] + f[3] + f[6])) / rho;
+  const double uy = ((f[6] + f[7] + f[8]) - (f[0] + f[1] + f[2])) / rho;
+  float xf[12];
+  mlp_features(f, rho, ux, uy, omega, xf);
+#pragma unroll
+  for (int i = 0; i < 12; ++i) X[k * kIn + i] = xf[i];
+  // plain-collision target S (f~ - f^eq)/rho = (1 - omega) S (f - f^eq)/rho
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Y[k * kOut + i] = (float)((1.0 - omega) * (double)xf[i]);
+}
+
+// One D2Q9 step with the surrogate collision and the per-node plain-collision judge.
+template <bool WALLS, bool DIAG>
+__global__ void __launch_bounds__(kBlock)
+k_bgk_d2q9_mlp(const float* __restrict__ A, float* __restrict__ B, int nx, int ny, int64_t pitch,
+               int64_t plane, double omega, int rows, const float* __restrict__ wblob, double tol,
+               unsigned long long* __restrict__ counters, double* __restrict__ partials) {
+  __shared__ MlpLds s;
+  __shared__ short xs[4][64][16];
+  __shared__ float ys[4][64][16];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r = lane & 15, q = lane >> 4;
+  const int nbx = gridDim.x;
+  const int tile = xcd_tile(blockIdx.x + nbx * blockIdx.y, nbx * gridDim.y);
+  const int bx = tile % nbx, by = tile / nbx;
+  const int x = bx * blockDim.x + threadIdx.x;
+  const bool valid = x < nx;
+  const int y0 = by * rows, yend = min(y0 + rows, ny);
+  double acc[kDiagValues] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  unsigned fallbacks = 0;
+  mlp_load_lds(wblob, s);
+  for (int y = y0; y < yend; ++y) {
+    double f[9];
+    double rho = 1.0, ux = 0.0, uy = 0.0;
+    float xf[12];
+    if (valid) {
+      pull9<WALLS>(A, nx, ny, pitch, plane, x, y, f);
+      rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+      ux = ((f[2] + f[5] + f[8]) - (f[0] + f[3] + f[6])) / rho;
+      uy = ((f[6] + f[7] + f[8]) - (f[0] + f[1] + f[2])) / rho;
+      mlp_features(f, rho, ux, uy, omega, xf);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 12; ++i) xf[i] = 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) xs[wv][lane][k] = k < kIn ? f2bf(xf[k]) : (short)0;
+    __syncthreads();
+    MlpAct a;
+    mlp_forward_wave(s, xs[wv], a, false);
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) ys[wv][16 * nt + r][4 * q + j] = a.y[nt][j];
+    __syncthreads();
+    if (valid) {
+      float yv[9];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) yv[i] = ys[wv][lane][i];
+      project9(yv);
+      const double u2x = ux * ux, u2y = uy * uy;
+      const double px[3] = {1.0 / 6.0 + 0.5 * (u2x - ux), 2.0 / 3.0 - u2x, 1.0 / 6.0 + 0.5 * (u2x + ux)};
+      const double py[3] = {1.0 / 6.0 + 0.5 * (u2y - uy), 2.0 / 3.0 - u2y, 1.0 / 6.0 + 0.5 * (u2y + uy)};
+      double fm[9], fp[9], err = 0.0, ref = 0.0;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        const double feq = rho * px[i % 3] * py[i / 3];
+        fm[i] = feq + rho * (double)yv[i] * (1.0 / kSNeq);  // surrogate
+        fp[i] = f[i] + omega * (feq - f[i]);                // paper's collision
+        err += (fm[i] - fp[i]) * (fm[i] - fp[i]);
+        ref += (fp[i] - feq) * (fp[i] - feq);
+      }
+      const bool fb = !(err <= tol * tol * ref);
+      fallbacks += fb ? 1u : 0u;
+      float* out = B + (int64_t)y * pitch + x;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) store_nt(out + i * plane, (float)((fb ? fp[i] : fm[i]) - wrest(i)));
+      if (DIAG) {
+        acc[0] += rho;
+        acc[1] += rho * ux;
+        acc[2] += rho * uy;
+        acc[4] += 0.5 * rho * (ux * ux + uy * uy);
+      }
+    }
+  }
+  // integer fallback counts: order-independent, so atomics stay deterministic
+  unsigned long long fb = (unsigned long long)fallbacks;
+  unsigned long long upd = (unsigned long long)(valid ? yend - y0 : 0);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    fb += __shfl_xor(fb, off, 64);
+    upd += __shfl_xor(upd, off, 64);
+  }
+  if (lane == 0) {
+    atomicAdd(counters, fb);
+    atomicAdd(counters + 1, upd);
+  }
+  if (DIAG) block_sum_store<kDiagValues>(acc, partials + (int64_t)tile * kDiagValues);
+}
+
+// ---- launchers ---------------------------------------------------------------------------------
+hipError_t launch_mlp_grad(const float* X, const float* T, int64_t n, int64_t start, int B,
+                           const float* w, float* partials, hipStream_t s) {
+  const int nw = (B + 63) / 64;
+  k_mlp_grad<<<(nw + 3) / 4, kBlock, 0, s>>>(X, T, n, start, B, w, partials);
+  return hipGetLastError();
+}
+
+int mlp_partial_count(int B) { return (((B + 63) / 64) + 3) / 4 * 4; }
+
+hipError_t launch_mlp_reduce_adam(const float* partials, int nw, float* grad, float* loss, float* w,
+                                  float* m, float* v, bool adam, float lr, int64_t t, hipStream_t s) {
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const float c1 = (float)(1.0 - std::pow(0.9, (double)t));
+  const float c2 = (float)(1.0 - std::pow(0.999, (double)t));
+  k_mlp_reduce_adam<<<(kNParam + 1 + kBlock - 1) / kBlock, kBlock, 0, s>>>(
+      partials, nw, grad, loss, w, m, v, adam ? 1 : 0, lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const float* X, int64_t n, const float* w, float* Y, hipStream_t s) {
+  const int64_t nw = (n + 63) / 64;
+  k_mlp_forward<<<(unsigned)((nw + 3) / 4), kBlock, 0, s>>>(X, n, w, Y);
+  return hipGetLastError();
+}
+
+hipError_t launch_harvest(const void* A, const Layout& L, bool walls, double omega,
+                          const int64_t* nodes, int64_t n, float* X, float* Y, hipStream_t s) {
+  const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
+  if (walls)
+    k_harvest<true><<<nb, kBlock, 0, s>>>(static_cast<const float*>(A), L.nx, L.ny, L.pitch, L.plane, omega, nodes, n, X, Y);
+  else
+    k_harvest<false><<<nb, kBlock, 0, s>>>(static_cast<const float*>(A), L.nx, L.ny, L.pitch, L.plane, omega, nodes, n, X, Y);
+  return hipGetLastError();
+}
+
+Grid make_grid_mlp(const Layout& L) {
+  Grid G;
+  G.bx = kBlock;
+  G.nbx = (L.nx + kBlock - 1) / kBlock;
+  G.rows = 8;  // amortises the per-workgroup weight load over 8 rows
+  G.nby = (L.ny + G.rows - 1) / G.rows;
+  return G;
+}
+
+hipError_t launch_bgk_d2q9_mlp(const void* A, void* B, const Layout& L, const Grid& G, double omega,
+                               bool walls, const float* wblob, double tol,
+                               unsigned long long* counters, double* partials, hipStream_t s) {
+  dim3 grid(G.nbx, G.nby), block(kBlock);
+  auto a = static_cast<const float*>(A);
+  auto b = static_cast<float*>(B);
+  if (walls) {
+    if (partials) k_bgk_d2q9_mlp<true, true><<<grid, block, 0, s>>>(a, b, L.nx, L.ny, L.pitch, L.plane, omega, G.rows, wblob, tol, counters, partials);
+    else k_bgk_d2q9_mlp<true, false><<<grid, block, 0, s>>>(a, b, L.nx, L.ny, L.pitch, L.plane, omega, G.rows, wblob, tol, counters, nullptr);
+  } else {
+    if (partials) k_bgk_d2q9_mlp<false, true><<<grid, block, 0, s>>>(a, b, L.nx, L.ny, L.pitch, L.plane, omega, G.rows, wblob, tol, counters, partials);
+    else k_bgk_d2q9_mlp<false, false><<<grid, block, 0, s>>>(a, b, L.nx, L.ny, L.pitch, L.plane, omega, G.rows, wblob, tol, counters, nullptr);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,190 @@
+// Learned collision surrogate: 12 -> 64 -> 64 -> 9 network on bfloat16 matrix cores.
+//
+// All three layers are evaluated in transposed form, Z^T = W H^T, one wavefront per 64 samples,
+// with v_mfma_f32_16x16x16_bf16 (D = A B + C, A 16x16 rows = output features, B 16x16 columns
+// = samples, float32 accumulation). Register layout of the 64 lanes l (j = 0..3):
+//   A (M x K):  A[l % 16][4 (l / 16) + j]
+//   B (K x N):  B[4 (l / 16) + j][l % 16]
+//   C/D (M x N): D[4 (l / 16) + j][l % 16]
+// so the output tile (m, n) of one layer is already the B operand tile (k = m, n) of the next:
+// activations never leave registers between layers. Weights (bfloat16) and biases (float32)
+// live in LDS; features, outputs and the transposed copies needed by the weight gradients go
+// through small per-wave LDS tiles.
+#pragma once
+
+#include "device_common.h"
+
+namespace lbm {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kIn = 12, kHid = 64, kOut = 9;
+constexpr int kNParam = 5577;
+// float32 parameter blob offsets: W1[64][12], b1[64], W2[64][64], b2[64], W3[9][64], b3[9]
+constexpr int oW1 = 0, oB1 = 768, oW2 = 832, oB2 = 4928, oW3 = 4992, oB3 = 5568;
+// input encoding scales (powers of two)
+constexpr float kSNeq = 1024.0f, kSU = 16.0f;
+
+__device__ __forceinline__ short f2bf(float f) {  // round to nearest even
+  uint32_t b = __float_as_uint(f);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return (short)(b >> 16);
+}
+__device__ __forceinline__ float bf2f(short h) {
+  return __uint_as_float(((uint32_t)(uint16_t)h) << 16);
+}
+
+__device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// GELU, tanh form (Hendrycks and Gimpel 2016), and its derivative, in float32;
+// tanh(t) = 1 - 2 / (1 + exp(2 t)).
+__device__ __forceinline__ void gelu_and_grad(float z, float& g, float& dg) {
+  const float k = 0.7978845608028654f, a = 0.044715f;
+  const float t = k * (z + a * z * z * z);
+  const float e = __expf(2.0f * t);
+  const float th = 1.0f - 2.0f / (1.0f + e);
+  g = 0.5f * z * (1.0f + th);
+  dg = 0.5f * (1.0f + th) + 0.5f * z * (1.0f - th * th) * k * (1.0f + 3.0f * a * z * z);
+}
+__device__ __forceinline__ float gelu(float z) {
+  const float k = 0.7978845608028654f, a = 0.044715f;
+  const float t = k * (z + a * z * z * z);
+  const float e = __expf(2.0f * t);
+  return 0.5f * z * (2.0f - 2.0f / (1.0f + e));
+}
+
+// Shared weights of one workgroup (bfloat16, zero padded) and biases (float32).
+struct MlpLds {
+  short w1[kHid][16];    // W1 padded to 16 inputs
+  short w2[kHid][kHid];
+  short w3[16][kHid];    // W3 padded to 16 outputs
+  float b1[kHid], b2[kHid], b3[16];
+};
+
+// Cooperative load of the float32 blob into LDS (rounded to bfloat16).
+__device__ __forceinline__ void mlp_load_lds(const float* __restrict__ w, MlpLds& s) {
+  for (int k = threadIdx.x; k < kHid * 16; k += blockDim.x) {
+    const int o = k / 16, i = k % 16;
+    s.w1[o][i] = i < kIn ? f2bf(w[oW1 + o * kIn + i]) : (short)0;
+  }
+  for (int k = threadIdx.x; k < kHid * kHid; k += blockDim.x)
+    s.w2[k / kHid][k % kHid] = f2bf(w[oW2 + k]);
+  for (int k = threadIdx.x; k < 16 * kHid; k += blockDim.x) {
+    const int o = k / kHid, i = k % kHid;
+    s.w3[o][i] = o < kOut ? f2bf(w[oW3 + o * kHid + i]) : (short)0;
+  }
+  for (int k = threadIdx.x; k < kHid; k += blockDim.x) {
+    s.b1[k] = w[oB1 + k];
+    s.b2[k] = w[oB2 + k];
+  }
+  for (int k = threadIdx.x; k < 16; k += blockDim.x) s.b3[k] = k < kOut ? w[oB3 + k] : 0.0f;
+}
+
+__device__ __forceinline__ bf16x4 ld4(const short* p) {
+  bf16x4 v;
+  v[0] = p[0];
+  v[1] = p[1];
+  v[2] = p[2];
+  v[3] = p[3];
+  return v;
+}
+
+__device__ __forceinline__ f32x4 bias4(const float* b, int lane) {
+  const int r = 4 * (lane >> 4);
+  f32x4 c;
+  c[0] = b[r];
+  c[1] = b[r + 1];
+  c[2] = b[r + 2];
+  c[3] = b[r + 3];
+  return c;
+}
+
+// Forward pass of one wavefront: 64 samples, sample s = 16 n + (l % 16) in tile column n.
+// xs: [64][16] bfloat16 inputs (row = sample). On return z1, z2 hold the pre-activations and
+// h1, h2 the bfloat16 activations in the C layout, y the outputs (C layout, rows 0..8 valid).
+struct MlpAct {
+  f32x4 z1[4][4], z2[4][4];  // [m][n]
+  bf16x4 h1[4][4], h2[4][4];
+  f32x4 y[4];                // [n]
+};
+
+__device__ __forceinline__ void mlp_forward_wave(const MlpLds& s, const short (*xs)[16],
+                                                 MlpAct& a, bool keep_z) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, q = lane >> 4;
+  // layer 1: K = 16 (12 inputs + zero padding)
+#pragma unroll
+  for (int n = 0; n < 4; ++n) {
+    const bf16x4 xb = ld4(&xs[16 * n + r][4 * q]);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      f32x4 acc = bias4(s.b1 + 16 * m, lane);
+      acc = mfma16(ld4(&s.w1[16 * m + r][4 * q]), xb, acc);
+      if (keep_z) a.z1[m][n] = acc;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) a.h1[m][n][j] = f2bf(gelu(acc[j]));
+    }
+  }
+  // layer 2: K = 64
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    bf16x4 wa[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) wa[k] = ld4(&s.w2[16 * m + r][16 * k + 4 * q]);
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      f32x4 acc = bias4(s.b2 + 16 * m, lane);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc = mfma16(wa[k], a.h1[k][n], acc);
+      if (keep_z) a.z2[m][n] = acc;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) a.h2[m][n][j] = f2bf(gelu(acc[j]));
+    }
+  }
+  // layer 3: 9 outputs padded to 16
+  bf16x4 w3a[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) w3a[k] = ld4(&s.w3[r][16 * k + 4 * q]);
+#pragma unroll
+  for (int n = 0; n < 4; ++n) {
+    f32x4 acc = bias4(s.b3, lane);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc = mfma16(w3a[k], a.h2[k][n], acc);
+    a.y[n] = acc;
+  }
+}
+
+// Orthogonal projection of 9 outputs onto zero mass and zero momentum (D2Q9 order
+// i = (c_x+1) + 3 (c_y+1)): y -= sum(y)/9 + c_x sum(c_x y)/6 + c_y sum(c_y y)/6.
+__device__ __forceinline__ void project9(float (&y)[9]) {
+  float s = 0.0f, sx = 0.0f, sy = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    s += y[i];
+    sx += (float)(i % 3 - 1) * y[i];
+    sy += (float)(i / 3 - 1) * y[i];
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i)
+    y[i] -= s * (1.0f / 9.0f) + (float)(i % 3 - 1) * sx * (1.0f / 6.0f) +
+            (float)(i / 3 - 1) * sy * (1.0f / 6.0f);
+}
+
+// Network inputs of one node from pre-collision f and its moments (theta = 1/3 equilibrium).
+__device__ __forceinline__ void mlp_features(const double (&f)[9], double rho, double ux,
+                                             double uy, double omega, float (&x)[12]) {
+  const double u2x = ux * ux, u2y = uy * uy;
+  const double px[3] = {1.0 / 6.0 + 0.5 * (u2x - ux), 2.0 / 3.0 - u2x, 1.0 / 6.0 + 0.5 * (u2x + ux)};
+  const double py[3] = {1.0 / 6.0 + 0.5 * (u2y - uy), 2.0 / 3.0 - u2y, 1.0 / 6.0 + 0.5 * (u2y + uy)};
+  const double inv = 1.0 / rho;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) x[i] = (float)(kSNeq * (f[i] - rho * px[i % 3] * py[i / 3]) * inv);
+  x[9] = (float)(kSU * ux);
+  x[10] = (float)(kSU * uy);
+  x[11] = (float)omega;
+}
+
+}  // namespace lbm

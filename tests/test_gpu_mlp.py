@@ -1,0 +1,149 @@
+"""GPU checks of the learned collision surrogate against the FP64 oracle of the network and of
+the lattice scheme: forward and gradients with the same bfloat16 roundings, harvest features,
+training, the tol = 0 fallback, and the trained surrogate's parity and gain."""
+import numpy as np
+import pytest
+
+from gpu_util import announce, rel_l2, require_gpu
+from oracle import bgk, mlp
+from oracle.equilibrium import moments
+from paper_2609_28679_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _binding():
+    from paper_2609_28679_amd import binding
+    return binding
+
+
+def _samples(n, seed):
+    """Network inputs of realistic magnitude: features of perturbed equilibria."""
+    from oracle.equilibrium import feq
+    from oracle.lattice import VARSIGMA2
+    rng = np.random.default_rng(seed)
+    rho = rng.uniform(0.97, 1.03, n)
+    u = rng.uniform(-0.06, 0.06, (2, n))
+    f = feq(rho, u, VARSIGMA2).T + rng.normal(0.0, 3e-4, (n, 9)) * rho[:, None]
+    omega = rng.choice([1 / 0.51, 1 / 0.6, 1.0], n)
+    x, _, _ = mlp.features(f, omega)
+    t = mlp.targets(f, omega)
+    return x.astype(np.float32), t.astype(np.float32)
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def test_forward_matches_oracle_with_bf16_roundings():
+    announce("MLP forward vs oracle (bf16 operands)")
+    import torch
+    b = _binding()
+    x, _ = _samples(1000, 1)
+    params = inputs.mlp_init(2)
+    blob = b.pack_mlp(params)
+    tr = b.Trainer(blob)
+    y = torch.empty((1000, 9), dtype=torch.float32, device="cuda")
+    tr.forward(_dev(x), y)
+    got = y.cpu().numpy().astype(np.float64)
+    exp, _ = mlp.forward(b.unpack_mlp(blob), x.astype(np.float64), bf16=True)
+    tr.close()
+    assert rel_l2(got, exp) <= 2e-3
+    np.testing.assert_allclose(got @ mlp.constraint_matrix().T, 0.0, atol=1e-5)
+
+
+def test_gradients_match_oracle_with_bf16_roundings():
+    announce("MLP gradients vs oracle (bf16 operands, fp32 accumulation)")
+    import torch
+    b = _binding()
+    x, t = _samples(2000, 3)
+    params = inputs.mlp_init(4)
+    blob = b.pack_mlp(params)
+    tr = b.Trainer(blob)
+    g = torch.empty(b.MLP_NPARAM, dtype=torch.float32, device="cuda")
+    loss = tr.grad(_dev(x), _dev(t), g)
+    tr.close()
+    got = b.unpack_mlp(g.cpu().numpy())
+    p64 = b.unpack_mlp(blob)
+    yhat, cache = mlp.forward(p64, x.astype(np.float64), bf16=True)
+    exp = mlp.backward(p64, cache, yhat, t.astype(np.float64), bf16=True)
+    assert loss == pytest.approx(mlp.loss(yhat, t.astype(np.float64)), rel=1e-3)
+    for k, name in enumerate(["W1", "b1", "W2", "b2", "W3", "b3"]):
+        assert rel_l2(got[k], exp[k]) <= 5e-3, name
+
+
+def test_harvest_features_and_targets():
+    announce("harvest 256^2 vs oracle features")
+    import torch
+    b = _binding()
+    rho, u = inputs.random_phase_turbulence_2d(256, seed=2)
+    lat = b.Lattice(rho, u, tau=0.6)
+    lat.step(30)
+    f_post, _ = lat.populations()
+    idx = np.sort(np.random.default_rng(0).choice(256 * 256, 500, replace=False)).astype(np.int64)
+    X = torch.empty((500, 12), dtype=torch.float32, device="cuda")
+    Y = torch.empty((500, 9), dtype=torch.float32, device="cuda")
+    lat.harvest(torch.from_numpy(idx).cuda(), X, Y)
+    lat.close()
+    pre = bgk.stream(f_post).reshape(9, -1)[:, idx].T
+    omega = np.full(500, 1 / 0.6)
+    xo, _, _ = mlp.features(pre, omega)
+    to = mlp.targets(pre, omega)
+    np.testing.assert_allclose(X.cpu().numpy(), xo, rtol=1e-5, atol=1e-5)
+    np.testing.assert_allclose(Y.cpu().numpy(), to, rtol=1e-5, atol=1e-5)
+
+
+def test_zero_tolerance_is_the_plain_collision():
+    announce("surrogate tol=0: every node falls back, result equals the plain scheme")
+    b = _binding()
+    rho, u = inputs.random_phase_turbulence_2d(128, seed=3)
+    lat = b.Lattice(rho, u, tau=0.6, collision="mlp")
+    lat.set_mlp(b.pack_mlp(inputs.mlp_init(1)), 0.0)
+    lat.step(100)
+    _, ug, _, _ = lat.moments()
+    fb, up = lat.mlp_stats()
+    lat.close()
+    assert fb == up == 100 * 128 * 128
+    _, uo = moments(bgk.run(bgk.init_equilibrium(rho, u), 1 / 0.6, 100))
+    assert rel_l2(ug, uo) <= 1e-5
+
+
+def test_training_and_surrogate_gain_and_parity():
+    announce("surrogate: harvest 256^2 x 3 tau, train, infer on held-out seed")
+    import torch
+    b = _binding()
+    from paper_2609_28679_amd import surrogate
+    fields = inputs.random_phase_turbulence_2d(256, seed=0)
+    X, Y = surrogate.harvest(fields, [0.51, 0.6, 1.0], 120000, (100, 1500), 12, seed=1)
+    X, Y = surrogate.shuffle(X, Y, 7)
+    init = inputs.mlp_init(11)
+    tr0 = b.Trainer(b.pack_mlp(init))
+    loss0 = surrogate.loss(tr0, X[:20000], Y[:20000])
+    tr0.close()
+    tr, w = surrogate.train(X, Y, init, batch=4096, steps=3000, lr=2e-3)
+    loss1 = surrogate.loss(tr, X[:20000], Y[:20000])
+    tr.close()
+    assert loss1 < 0.05 * loss0
+    # inference on a held-out field: per-step judge with fallback
+    rho, u = inputs.random_phase_turbulence_2d(256, seed=5)
+    steps, tol = 100, 0.05
+    _, uo = moments(bgk.run(bgk.init_equilibrium(rho, u), 1 / 0.6, steps))
+    res = {}
+    for name, weights in (("untrained", b.pack_mlp(init)), ("trained", w)):
+        lat = b.Lattice(rho, u, tau=0.6, collision="mlp")
+        lat.set_mlp(weights, tol)
+        lat.step(steps)
+        _, ug, _, _ = lat.moments()
+        fb, up = lat.mlp_stats()
+        lat.close()
+        res[name] = (fb / up, rel_l2(ug, uo))
+    print("surrogate gain:", res, flush=True)
+    assert res["trained"][0] < res["untrained"][0]
+    assert res["trained"][0] < 0.5
+    assert res["trained"][1] <= 1e-2
