@@ -81,6 +81,57 @@ def variant(name, make, steps, warmup, bytes_per_node, extra=None):
     return out
 
 
+def surrogate_variant(binding, inputs, steps):
+    """Config-5 recipe: 1M training pairs harvested from 2048^2 turbulence runs at three tau,
+    BF16 training, inference timed at 2048^2 (seed 5, tau 0.6) with the per-node plain judge;
+    velocity rel-L2 against the FP64 oracle measured on a 256^2 held-out run."""
+    import torch
+    from paper_2609_28679_amd import surrogate
+    from oracle import bgk
+    from oracle.equilibrium import moments
+    t0 = time.perf_counter()
+    fields = inputs.random_phase_turbulence_2d(2048, seed=0)
+    X, Y = surrogate.harvest(fields, [0.51, 0.6, 1.0], 1_000_000, (100, 10000), 20, seed=1)
+    X, Y = surrogate.shuffle(X, Y, 7)
+    t1 = time.perf_counter()
+    init = inputs.mlp_init(11)
+    torch.cuda.synchronize()
+    tt0 = time.perf_counter()
+    tr, w = surrogate.train(X, Y, init, batch=4096, steps=4000, lr=2e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - tt0
+    loss = surrogate.loss(tr, X[:65536], Y[:65536])
+    tr.close()
+    del X, Y
+    tol = 0.05
+    rho, u = inputs.random_phase_turbulence_2d(2048, seed=5)
+    lat = binding.Lattice(rho, u, tau=0.6, collision="mlp")
+    lat.set_mlp(w, tol)
+    wall, ms = time_lattice(lat, steps, 10)
+    fb, up = lat.mlp_stats()
+    nodes = lat.nodes
+    lat.close()
+    # parity on a held-out 256^2 field against the oracle
+    r2, u2 = inputs.random_phase_turbulence_2d(256, seed=5)
+    lat = binding.Lattice(r2, u2, tau=0.6, collision="mlp")
+    lat.set_mlp(w, tol)
+    lat.step(100)
+    _, ug, _, _ = lat.moments()
+    lat.close()
+    _, uo = moments(bgk.run(bgk.init_equilibrium(r2, u2), 1 / 0.6, 100))
+    rel = float(np.sqrt(((ug - uo) ** 2).sum() / (uo ** 2).sum()))
+    per = ms / 1e3 / steps
+    out = {"mlups": round(nodes * steps / wall / 1e6, 1), "kernel_us": round(per * 1e6, 2),
+           "algorithmic_GBs": round(72 * nodes / per / 1e9, 1),
+           "hbm_frac": round(72 * nodes / per / 1e9 / HBM_PEAK_GBS, 4),
+           "fallback_rate": round(fb / max(up, 1), 4), "tol": tol,
+           "velocity_rel_l2_vs_oracle_256_100steps": rel,
+           "train": {"samples": 1_000_000, "harvest_s": round(t1 - t0, 2), "steps": 4000,
+                     "batch": 4096, "train_s": round(t_train, 2), "final_loss": loss}}
+    log("surrogate: %s" % out)
+    return out
+
+
 def cpu_baseline():
     """The FP64 NumPy oracle on a bounded sample of the headline workload."""
     from threadpoolctl import threadpool_limits
@@ -155,11 +206,20 @@ def main():
             "d2q9_ddf_fp32_4096",
             lambda: binding.Lattice(rs, us, ts, model="ddf", tau=0.6, wall_y=True, phi=1),
             max(100, vs // 4), 10, 144, {"walls": "y", "phi": "central"})
+        for st in ("bf16", "fp16"):
+            variants["d2q9_ddf_%s_4096" % st] = variant(
+                "d2q9_ddf_%s_4096" % st,
+                lambda: binding.Lattice(rs, us, ts, model="ddf", tau=0.6, wall_y=True, phi=1,
+                                        storage=st),
+                max(100, vs // 4), 10, 88,
+                {"walls": "y", "phi": "central",
+                 "storage": "fp32 moments + %s non-equilibrium (6 f + 8 g of 18 stored)" % st})
         del rs, us, ts
         for st in ("bf16", "fp16"):
             variants["d2q9_bgk_%s_2048" % st] = variant(
                 "d2q9_bgk_%s_2048" % st, lambda: binding.Lattice(rho, u, tau=tau, storage=st),
                 vs, 20, 48, {"storage": "fp32 moments + %s f-f_eq (6 of 9 stored)" % st})
+        variants["d2q9_bgk_mlp_2048"] = surrogate_variant(binding, inputs, max(100, vs // 4))
         variants["d2q9_bgk_fp64_2048"] = variant(
             "d2q9_bgk_fp64_2048", lambda: binding.Lattice(rho, u, tau=tau, storage="fp64"),
             max(200, vs // 4), 20, 144)

@@ -24,17 +24,107 @@
 // columns are re-read by the neighbouring workgroup (L2 hits for the x halo of neighbouring
 // tiles on the same XCD).
 //
-// Storage: float32 or float64 planes holding f_i - w_i and g_i - v_i, where w, v are the
-// equilibria at rest at the reference state rho = 1, T = 1 (the part that carries the flow is
-// kept with full relative precision). Arithmetic is float64.
+// Storage policies (IO template parameter):
+//   IoFull<S>    float32 or float64 planes holding f_i - w_i and g_i - v_i, where w, v are the
+//                equilibria at rest at the reference state rho = 1, T = 1;
+//   IoRed<Codec> float32 moments (rho - 1, u_x, u_y, T - 1) + 16-bit non-equilibrium part, 6 of
+//                the 9 f values and 8 of the 9 g values (see reduced_common.h); the pull
+//                rebuilds each population from the source node's moments.
+// The register ring holds the pulled populations shifted by (w, v) in the policy's ring type.
+// Arithmetic is float64.
 #include "ddf_common.h"
+#include "reduced_common.h"
 
 namespace lbm {
 
-template <typename S, int HALO, bool WALLS, bool PULL, bool DIAG>
+template <typename S>
+struct IoFull {
+  using ring_t = S;
+  const S* A;
+  S* B;
+  int64_t plane;
+  __device__ __forceinline__ void gather(bool pull, int64_t r0, int64_t rm, int64_t rp, int x,
+                                         int xm, int xp, bool top, bool bot, const DdfParams&,
+                                         S (&hf)[9], S (&hg)[9]) const {
+    if (pull) {
+      gather9(A, plane, r0, rm, rp, x, xm, xp, top, bot, hf);
+      gather9(A + 9 * plane, plane, r0, rm, rp, x, xm, xp, top, bot, hg);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        hf[i] = A[i * plane + r0 + x];
+        hg[i] = A[(9 + i) * plane + r0 + x];
+      }
+    }
+  }
+  __device__ __forceinline__ void store(int64_t off, int i, double htf, double, double htg,
+                                        double) const {
+    store_nt(B + i * plane + off, (S)htf);
+    store_nt(B + (9 + i) * plane + off, (S)htg);
+  }
+  __device__ __forceinline__ void store_moments(int64_t, const double (&)[6], double) const {}
+};
+
+template <typename Codec>
+struct IoRed {
+  using ring_t = float;
+  const float* M;     // 4 moment planes
+  const uint16_t* N;  // kRedF f planes, then kRedG g planes
+  float* Mo;
+  uint16_t* No;
+  int64_t plane;
+  float s_enc, s_dec;
+  // post-collision population ii of node `src`, rebuilt and shifted by the rest state
+  __device__ __forceinline__ void pop(int64_t src, int ii, const DdfParams& p, double& hf,
+                                      double& hg) const {
+    const double rho = 1.0 + (double)M[src];
+    const double ux = (double)M[plane + src];
+    const double uy = (double)M[2 * plane + src];
+    const double T = 1.0 + (double)M[3 * plane + src];
+    const double theta = p.R * T, e = p.cv * T;
+    double pa, ca, pb, cb;
+    axis_eq1(ii % 3 - 1, ux, theta, pa, ca);
+    axis_eq1(ii / 3 - 1, uy, theta, pb, cb);
+    const double fe = rho * pa * pb;
+    const double ge = rho * (e * pa * pb + ca * pb + pa * cb);
+    hf = fe + neq_f<Codec>(N, plane, src, ii, s_dec) - p.wf[ii];
+    hg = ge + neq_g<Codec>(N + kRedF * plane, plane, src, ii, s_dec) - p.wg[ii];
+  }
+  __device__ __forceinline__ void gather(bool pull, int64_t r0, int64_t rm, int64_t rp, int x,
+                                         int xm, int xp, bool top, bool bot, const DdfParams& p,
+                                         float (&hf)[9], float (&hg)[9]) const {
+    const int xs[3] = {xp, x, xm};     // source column by c_x + 1
+    const int64_t ys[3] = {rp, r0, rm};  // source row offset by c_y + 1
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const int ka = i % 3, kb = i / 3;
+      const bool bounce = (kb == 2 && bot) || (kb == 0 && top);
+      const int ii = (pull && bounce) ? 8 - i : i;
+      const int64_t src = (!pull || bounce) ? r0 + x : ys[kb] + xs[ka];
+      double a, b;
+      pop(src, ii, p, a, b);
+      hf[i] = (float)a;
+      hg[i] = (float)b;
+    }
+  }
+  __device__ __forceinline__ void store(int64_t off, int i, double htf, double hfe, double htg,
+                                        double hge) const {
+    if (f_slot(i) >= 0) store_nt(No + f_slot(i) * plane + off, Codec::enc(htf - hfe, s_enc));
+    if (g_slot(i) >= 0) store_nt(No + (kRedF + g_slot(i)) * plane + off, Codec::enc(htg - hge, s_enc));
+  }
+  __device__ __forceinline__ void store_moments(int64_t off, const double (&m)[6], double R) const {
+    store_nt(Mo + off, (float)(m[0] - 1.0));
+    store_nt(Mo + plane + off, (float)m[1]);
+    store_nt(Mo + 2 * plane + off, (float)m[2]);
+    store_nt(Mo + 3 * plane + off, (float)(m[3] / R - 1.0));
+  }
+};
+
+template <class IO, int HALO, bool WALLS, bool PULL, bool DIAG>
 __global__ void __launch_bounds__(kBlock)
-k_ddf_d2q9(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int64_t pitch,
-           int64_t plane, DdfParams prm, int rows, double* __restrict__ partials) {
+k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
+           double* __restrict__ partials) {
+  using S = typename IO::ring_t;
   constexpr int H1 = HALO + 1;
   constexpr int P = 2 * HALO + 1;
   constexpr int TXI = kBlock - 2 * HALO;
@@ -59,9 +149,6 @@ k_ddf_d2q9(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int64_t p
   S ring_f[H1][9], ring_g[H1][9];
   double ring_m[H1][6];  // rho, u_x, u_y, theta, e, Phi_xx
   double acc[kDiagValues] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  const S* Ag = A + 9 * plane;
-  S* Bf = B;
-  S* Bg = B + 9 * plane;
 
   for (int k = 0; k < count; k += H1) {
 #pragma unroll
@@ -74,21 +161,11 @@ k_ddf_d2q9(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int64_t p
       double phx = 0.0, phy = 0.0;
       if (row_real) {
         // ---- gather (pull) ----------------------------------------------------------------
-        if (PULL) {
-          const int ym = rr == 0 ? ny - 1 : rr - 1;
-          const int yp = rr == ny - 1 ? 0 : rr + 1;
-          const int64_t r0 = (int64_t)rr * pitch, rm = (int64_t)ym * pitch, rp = (int64_t)yp * pitch;
-          const bool top = WALLS && rr == ny - 1, bot = WALLS && rr == 0;
-          gather9(A, plane, r0, rm, rp, x, xm, xp, top, bot, ring_f[j]);
-          gather9(Ag, plane, r0, rm, rp, x, xm, xp, top, bot, ring_g[j]);
-        } else {
-          const int64_t off = (int64_t)rr * pitch + x;
-#pragma unroll
-          for (int i = 0; i < 9; ++i) {
-            ring_f[j][i] = A[i * plane + off];
-            ring_g[j][i] = Ag[i * plane + off];
-          }
-        }
+        const int ym = rr == 0 ? ny - 1 : rr - 1;
+        const int yp = rr == ny - 1 ? 0 : rr + 1;
+        const int64_t r0 = (int64_t)rr * pitch, rm = (int64_t)ym * pitch, rp = (int64_t)yp * pitch;
+        const bool top = WALLS && rr == ny - 1, bot = WALLS && rr == 0;
+        io.gather(PULL, r0, rm, rp, x, xm, xp, top, bot, prm, ring_f[j], ring_g[j]);
         // ---- moments and closure ------------------------------------------------------------
         double f[9], g[9];
 #pragma unroll
@@ -143,14 +220,12 @@ k_ddf_d2q9(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int64_t p
           phyy = -d / ring_m[sc][0];
         }
         const double phxx = prm.phi ? ring_m[sc][5] : 0.0;
-        S of[9], og[9];
-        collide_ddf(ring_f[sc], ring_g[sc], ring_m[sc], phxx, phyy, prm, of, og);
         const int64_t off = (int64_t)cc * pitch + x;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-          store_nt(Bf + i * plane + off, of[i]);
-          store_nt(Bg + i * plane + off, og[i]);
-        }
+        collide_ddf(ring_f[sc], ring_g[sc], ring_m[sc], phxx, phyy, prm,
+                    [&](int i, double htf, double hfe, double htg, double hge) {
+                      io.store(off, i, htf, hfe, htg, hge);
+                    });
+        io.store_moments(off, ring_m[sc], prm.R);
         if (DIAG) {
           const double rho = ring_m[sc][0];
           acc[0] += rho;
@@ -237,41 +312,106 @@ Grid make_grid_ddf(const Layout& L, int halo) {
   return G;
 }
 
-template <typename S, int HALO, bool WALLS, bool PULL>
-static void ddf_launch(const void* A, void* B, const Layout& L, const Grid& G,
-                       const DdfParams& prm, double* partials, hipStream_t s) {
+template <class IO, int HALO, bool WALLS, bool PULL>
+static void ddf_launch(const IO& io, const Layout& L, const Grid& G, const DdfParams& prm,
+                       double* partials, hipStream_t s) {
   dim3 grid(G.nbx, G.nby), block(kBlock);
-  auto a = static_cast<const S*>(A);
-  auto b = static_cast<S*>(B);
   if (partials)
-    k_ddf_d2q9<S, HALO, WALLS, PULL, true><<<grid, block, 0, s>>>(a, b, L.nx, L.ny, L.pitch, L.plane, prm, G.rows, partials);
+    k_ddf_d2q9<IO, HALO, WALLS, PULL, true><<<grid, block, 0, s>>>(io, L.nx, L.ny, L.pitch, prm, G.rows, partials);
   else
-    k_ddf_d2q9<S, HALO, WALLS, PULL, false><<<grid, block, 0, s>>>(a, b, L.nx, L.ny, L.pitch, L.plane, prm, G.rows, nullptr);
+    k_ddf_d2q9<IO, HALO, WALLS, PULL, false><<<grid, block, 0, s>>>(io, L.nx, L.ny, L.pitch, prm, G.rows, nullptr);
 }
 
-template <typename S, int HALO>
-static void ddf_launch_w(bool walls, bool pull, const void* A, void* B, const Layout& L,
-                         const Grid& G, const DdfParams& prm, double* partials, hipStream_t s) {
+template <class IO, int HALO>
+static void ddf_launch_w(bool walls, bool pull, const IO& io, const Layout& L, const Grid& G,
+                         const DdfParams& prm, double* partials, hipStream_t s) {
   if (walls) {
-    if (pull) ddf_launch<S, HALO, true, true>(A, B, L, G, prm, partials, s);
-    else ddf_launch<S, HALO, true, false>(A, B, L, G, prm, partials, s);
+    if (pull) ddf_launch<IO, HALO, true, true>(io, L, G, prm, partials, s);
+    else ddf_launch<IO, HALO, true, false>(io, L, G, prm, partials, s);
   } else {
-    if (pull) ddf_launch<S, HALO, false, true>(A, B, L, G, prm, partials, s);
-    else ddf_launch<S, HALO, false, false>(A, B, L, G, prm, partials, s);
+    if (pull) ddf_launch<IO, HALO, false, true>(io, L, G, prm, partials, s);
+    else ddf_launch<IO, HALO, false, false>(io, L, G, prm, partials, s);
   }
 }
 
-hipError_t launch_ddf(int kind, bool walls, bool pull, const void* A, void* B, const Layout& L,
-                      const Grid& G, const DdfParams& prm, double* partials, hipStream_t s) {
-  const int halo = prm.phi == 2 ? 2 : 1;
-  if (kind == 0) {
-    if (halo == 1) ddf_launch_w<float, 1>(walls, pull, A, B, L, G, prm, partials, s);
-    else ddf_launch_w<float, 2>(walls, pull, A, B, L, G, prm, partials, s);
+template <class IO>
+static void ddf_launch_h(bool walls, bool pull, const IO& io, const Layout& L, const Grid& G,
+                         const DdfParams& prm, double* partials, hipStream_t s) {
+  if (prm.phi == 2) ddf_launch_w<IO, 2>(walls, pull, io, L, G, prm, partials, s);
+  else ddf_launch_w<IO, 1>(walls, pull, io, L, G, prm, partials, s);
+}
+
+// reduced buffer: 4 float32 moment planes, then kRedF + kRedG uint16 planes
+template <typename Codec>
+static IoRed<Codec> make_red(const void* A, void* B, const Layout& L, float se, float sd) {
+  IoRed<Codec> io;
+  io.M = static_cast<const float*>(A);
+  io.N = reinterpret_cast<const uint16_t*>(io.M + 4 * L.plane);
+  io.Mo = static_cast<float*>(B);
+  io.No = reinterpret_cast<uint16_t*>(io.Mo + 4 * L.plane);
+  io.plane = L.plane;
+  io.s_enc = se;
+  io.s_dec = sd;
+  return io;
+}
+
+hipError_t launch_ddf(int fmt, bool walls, bool pull, const void* A, void* B, const Layout& L,
+                      const Grid& G, const DdfParams& prm, float s_enc, float s_dec,
+                      double* partials, hipStream_t s) {
+  if (fmt == 0) {
+    IoFull<float> io{static_cast<const float*>(A), static_cast<float*>(B), L.plane};
+    ddf_launch_h(walls, pull, io, L, G, prm, partials, s);
+  } else if (fmt == 1) {
+    IoFull<double> io{static_cast<const double*>(A), static_cast<double*>(B), L.plane};
+    ddf_launch_h(walls, pull, io, L, G, prm, partials, s);
+  } else if (fmt == 2) {
+    ddf_launch_h(walls, pull, make_red<CodecBF16>(A, B, L, s_enc, s_dec), L, G, prm, partials, s);
   } else {
-    if (halo == 1) ddf_launch_w<double, 1>(walls, pull, A, B, L, G, prm, partials, s);
-    else ddf_launch_w<double, 2>(walls, pull, A, B, L, G, prm, partials, s);
+    ddf_launch_h(walls, pull, make_red<CodecFP16>(A, B, L, s_enc, s_dec), L, G, prm, partials, s);
   }
   return hipGetLastError();
+}
+
+// ---- reduced-storage initialisation and read-out ------------------------------------------------
+__global__ void k_init_ddf_red(const double* __restrict__ rho, const double* __restrict__ u,
+                               const double* __restrict__ T, float* __restrict__ M,
+                               uint16_t* __restrict__ N, int nx, int64_t nodes, int64_t pitch,
+                               int64_t plane) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nodes) return;
+  const int64_t off = (n / nx) * pitch + (n % nx);
+  M[off] = (float)(rho[n] - 1.0);
+  M[plane + off] = (float)u[n];
+  M[2 * plane + off] = (float)u[nodes + n];
+  M[3 * plane + off] = (float)(T[n] - 1.0);
+  for (int k = 0; k < kRedF + kRedG; ++k) N[k * plane + off] = 0;
+}
+
+__global__ void k_moments_ddf_red(const float* __restrict__ M, int nx, int64_t nodes, int64_t pitch,
+                                  int64_t plane, DdfParams prm, double* __restrict__ rho,
+                                  double* __restrict__ u, double* __restrict__ T,
+                                  double* __restrict__ edens) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nodes) return;
+  const int64_t off = (n / nx) * pitch + (n % nx);
+  const double r = 1.0 + (double)M[off], ux = (double)M[plane + off], uy = (double)M[2 * plane + off];
+  const double t = 1.0 + (double)M[3 * plane + off];
+  rho[n] = r;
+  u[n] = ux;
+  u[nodes + n] = uy;
+  T[n] = t;
+  edens[n] = r * (prm.cv * t + 0.5 * (ux * ux + uy * uy));
+}
+
+template <typename Codec>
+__global__ void k_decode_ddf_red(int i, IoRed<Codec> io, int nx, int64_t nodes, int64_t pitch,
+                                 DdfParams prm, double* __restrict__ out) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nodes) return;
+  const int64_t off = (n / nx) * pitch + (n % nx);
+  double hf, hg;
+  io.pop(off, i % 9, prm, hf, hg);
+  out[n] = i < 9 ? hf + prm.wf[i] : hg + prm.wg[i - 9];
 }
 
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
@@ -283,7 +423,10 @@ hipError_t launch_ddf_rest_state(const DdfParams& prm, double* out, hipStream_t 
 
 hipError_t launch_init_ddf(int kind, const double* rho, const double* u, const double* T,
                            void* A, const Layout& L, const DdfParams& prm, hipStream_t s) {
-  if (kind == 0)
+  if (kind >= 2) {
+    float* M = static_cast<float*>(A);
+    k_init_ddf_red<<<nblk(L.nodes()), kBlock, 0, s>>>(rho, u, T, M, reinterpret_cast<uint16_t*>(M + 4 * L.plane), L.nx, L.nodes(), L.pitch, L.plane);
+  } else if (kind == 0)
     k_init_ddf<float><<<nblk(L.nodes()), kBlock, 0, s>>>(rho, u, T, static_cast<float*>(A), L.nx, L.ny, L.pitch, L.plane, prm);
   else
     k_init_ddf<double><<<nblk(L.nodes()), kBlock, 0, s>>>(rho, u, T, static_cast<double*>(A), L.nx, L.ny, L.pitch, L.plane, prm);
@@ -292,7 +435,9 @@ hipError_t launch_init_ddf(int kind, const double* rho, const double* u, const d
 
 hipError_t launch_moments_ddf(int kind, const void* A, const Layout& L, const DdfParams& prm,
                               double* rho, double* u, double* T, double* edens, hipStream_t s) {
-  if (kind == 0)
+  if (kind >= 2)
+    k_moments_ddf_red<<<nblk(L.nodes()), kBlock, 0, s>>>(static_cast<const float*>(A), L.nx, L.nodes(), L.pitch, L.plane, prm, rho, u, T, edens);
+  else if (kind == 0)
     k_moments_ddf<float><<<nblk(L.nodes()), kBlock, 0, s>>>(static_cast<const float*>(A), L.nx, L.ny, L.pitch, L.plane, prm, rho, u, T, edens);
   else
     k_moments_ddf<double><<<nblk(L.nodes()), kBlock, 0, s>>>(static_cast<const double*>(A), L.nx, L.ny, L.pitch, L.plane, prm, rho, u, T, edens);
@@ -300,8 +445,12 @@ hipError_t launch_moments_ddf(int kind, const void* A, const Layout& L, const Dd
 }
 
 hipError_t launch_decode_ddf(int kind, int i, const void* A, const Layout& L,
-                             const DdfParams& prm, double* out, hipStream_t s) {
-  if (kind == 0)
+                             const DdfParams& prm, float s_dec, double* out, hipStream_t s) {
+  if (kind == 2)
+    k_decode_ddf_red<CodecBF16><<<nblk(L.nodes()), kBlock, 0, s>>>(i, make_red<CodecBF16>(A, nullptr, L, 1.0f, s_dec), L.nx, L.nodes(), L.pitch, prm, out);
+  else if (kind == 3)
+    k_decode_ddf_red<CodecFP16><<<nblk(L.nodes()), kBlock, 0, s>>>(i, make_red<CodecFP16>(A, nullptr, L, 1.0f, s_dec), L.nx, L.nodes(), L.pitch, prm, out);
+  else if (kind == 0)
     k_decode_ddf<float><<<nblk(L.nodes()), kBlock, 0, s>>>(i, static_cast<const float*>(A) + (int64_t)i * L.plane, L.nx, L.nodes(), L.pitch, prm, out);
   else
     k_decode_ddf<double><<<nblk(L.nodes()), kBlock, 0, s>>>(i, static_cast<const double*>(A) + (int64_t)i * L.plane, L.nx, L.nodes(), L.pitch, prm, out);

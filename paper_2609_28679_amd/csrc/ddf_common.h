@@ -101,13 +101,14 @@ __device__ __forceinline__ double upwind_or_central(double pm2, double pm1, doub
   return 0.5 * (pp1 - pm1);
 }
 
-// Collision of one node from its stored (shifted) populations and moments
-// m = {rho, u_x, u_y, theta, e, -}; Phi_xx, Phi_yy already include dt = 1.
-template <typename S>
-__device__ __forceinline__ void collide_ddf(const S (&hf)[9], const S (&hg)[9],
+// Collision of one node from its pre-collision populations held shifted by the rest state
+// (hf = f - w, hg = g - v) and its moments m = {rho, u_x, u_y, theta, e, -}; Phi_xx, Phi_yy
+// include dt = 1. For every i the sink receives the post-collision values and the
+// equilibria, all shifted: sink(i, f~ - w, f^eq - w, g~ - v, g^eq - v).
+template <typename R, typename Sink>
+__device__ __forceinline__ void collide_ddf(const R (&hf)[9], const R (&hg)[9],
                                             const double (&m)[6], double phxx, double phyy,
-                                            const DdfParams& p,
-                                            S (&of)[9], S (&og)[9]) {
+                                            const DdfParams& p, Sink&& sink) {
   const double rho = m[0], theta = m[3], e = m[4];
   Axis X, Y;
   axis_eq(m[1], theta, X);
@@ -132,8 +133,22 @@ __device__ __forceinline__ void collide_ddf(const S (&hf)[9], const S (&hg)[9],
     const double dstar = rho * (sx[a] * sy[b] - pp);  // f* - f^eq
     const double f = (double)hf[i];
     const double g = (double)hg[i];
-    of[i] = (S)(f + omega * (hfe - f) + keep * dstar);
-    og[i] = (S)(g + omega * (hge - g));
+    sink(i, f + omega * (hfe - f) + keep * dstar, hfe, g + omega * (hge - g), hge);
+  }
+}
+
+// Per-axis factors for one velocity component c only.
+__device__ __forceinline__ void axis_eq1(int c, double v, double theta, double& psi, double& chi) {
+  const double v2 = v * v;
+  const double a0 = 0.5 * v2;
+  const double a1 = theta * v + 0.5 * v2 * v;
+  const double a2 = theta * theta + 2.5 * theta * v2 + 0.5 * v2 * v2;
+  if (c == 0) {
+    psi = 1.0 - theta - v2;
+    chi = a0 - a2;
+  } else {
+    psi = 0.5 * (theta + v2 + c * v);
+    chi = 0.5 * (a2 + c * a1);
   }
 }
 

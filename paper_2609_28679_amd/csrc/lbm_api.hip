@@ -25,6 +25,7 @@ struct lbm_ctx {
   lbm_params p{};
   int D = 2, Q = 9;
   int kind = 0;  // 0: float32 populations, 1: float64
+  int fmt = 0;   // DDF storage format: 0 float32, 1 float64, 2 bfloat16, 3 float16 (reduced)
   bool ddf = false;  // double-distribution ideal-gas model
   int codec = -1;    // reduced storage: 0 = bfloat16, 1 = float16 (scaled); -1 = none
   float s_enc = 1.0f, s_dec = 1.0f;
@@ -114,7 +115,6 @@ int validate(const lbm_params* p, std::string& why) {
   }
   const bool reduced = p->storage == LBM_STORE_BF16 || p->storage == LBM_STORE_FP16;
   if (reduced && p->lattice != LBM_D2Q9) { why = "reduced storage is D2Q9 only"; return LBM_EINVAL; }
-  if (reduced && p->model != LBM_MODEL_BGK) { why = "reduced storage not supported for this model"; return LBM_EINVAL; }
   if (p->storage == LBM_STORE_FP16 && (p->fp16_scale_log2 < 0 || p->fp16_scale_log2 > 24)) { why = "fp16_scale_log2 must be in [0, 24]"; return LBM_EINVAL; }
   if (p->collision == LBM_COLLIDE_MLP &&
       (p->lattice != LBM_D2Q9 || p->model != LBM_MODEL_BGK || p->storage != LBM_STORE_FP32)) {
@@ -155,8 +155,10 @@ void make_plan(const lbm_params* p, Plan& P) {
               : (p->collision == LBM_COLLIDE_MLP ? make_grid_mlp(P.L) : make_grid(P.L));
   P.partial_slots = std::max(P.G.blocks(), 1024);
   size_t off = 0;
-  // reduced storage: 3 float32 moment planes + 6 uint16 non-equilibrium planes
-  const size_t pop = P.codec >= 0 ? (size_t)P.L.plane * (3 * 4 + 6 * 2)
+  // reduced storage: float32 moment planes + uint16 non-equilibrium planes
+  // (isothermal: 3 + 6, double distribution: 4 + 6 + 8)
+  const size_t pop = P.codec >= 0 ? (P.ddf ? (size_t)P.L.plane * (4 * 4 + 14 * 2)
+                                           : (size_t)P.L.plane * (3 * 4 + 6 * 2))
                                    : (size_t)P.planes * P.L.plane * P.elem;
   P.off_A = off; off = align_up(off + pop, 256);
   P.off_B = off; off = align_up(off + pop, 256);
@@ -249,6 +251,7 @@ int lbm_create(const lbm_params* p, const double* rho0, const double* u0, const 
   c->kind = P.kind;
   c->ddf = P.ddf;
   c->codec = P.codec;
+  c->fmt = P.codec >= 0 ? 2 + P.codec : P.kind;
   if (P.codec == 1) {
     c->s_enc = std::ldexp(1.0f, p->fp16_scale_log2);
     c->s_dec = std::ldexp(1.0f, -p->fp16_scale_log2);
@@ -315,8 +318,8 @@ int lbm_create(const lbm_params* p, const double* rho0, const double* u0, const 
       c->dp.wf[i] = rest[i];
       c->dp.wg[i] = rest[9 + i];
     }
-    if (e == hipSuccess) e = launch_init_ddf(c->kind, c->readout, c->readout + nodes, c->readout + 3 * nodes, c->B, c->L, c->dp, c->stream);
-    if (e == hipSuccess) e = launch_ddf(c->kind, p->wall_y != 0, false, c->B, c->A, c->L, c->G, c->dp, nullptr, c->stream);
+    if (e == hipSuccess) e = launch_init_ddf(c->fmt, c->readout, c->readout + nodes, c->readout + 3 * nodes, c->B, c->L, c->dp, c->stream);
+    if (e == hipSuccess) e = launch_ddf(c->fmt, p->wall_y != 0, false, c->B, c->A, c->L, c->G, c->dp, c->s_enc, c->s_dec, nullptr, c->stream);
   } else if (e == hipSuccess && c->codec >= 0) {
     e = launch_init_bgk_red(c->readout, c->readout + nodes, c->A, c->L, c->stream);
   } else if (e == hipSuccess) {
@@ -345,7 +348,7 @@ int lbm_step(lbm_ctx* c, int64_t n) {
       if (!c->mlp_set) return fail(c, LBM_ESTATE, "surrogate weights not installed (lbm_set_mlp)");
       e = launch_bgk_d2q9_mlp(c->A, c->B, c->L, c->G, c->omega, c->p.wall_y != 0, c->mlp_w, c->mlp_tol, c->mlp_cnt, part, c->stream);
     } else if (c->ddf)
-      e = launch_ddf(c->kind, c->p.wall_y != 0, true, c->A, c->B, c->L, c->G, c->dp, part, c->stream);
+      e = launch_ddf(c->fmt, c->p.wall_y != 0, true, c->A, c->B, c->L, c->G, c->dp, c->s_enc, c->s_dec, part, c->stream);
     else if (c->codec >= 0)
       e = launch_bgk_d2q9_red(c->codec, c->A, c->B, c->L, c->G, c->omega, c->p.wall_y != 0, c->s_enc, c->s_dec, part, c->stream);
     else if (c->D == 2)
@@ -397,7 +400,7 @@ int lbm_moments(lbm_ctx* c, double* rho, double* u, double* T, double* totals) {
   double* d_T = c->readout + (1 + c->D) * nodes;
   double* d_e = d_T + nodes;
   if (c->ddf)
-    HIP_TRY(c, launch_moments_ddf(c->kind, c->A, c->L, c->dp, d_rho, d_u, d_T, d_e, c->stream));
+    HIP_TRY(c, launch_moments_ddf(c->fmt, c->A, c->L, c->dp, d_rho, d_u, d_T, d_e, c->stream));
   else if (c->codec >= 0)
     HIP_TRY(c, launch_moments_bgk_red(c->A, c->L, d_rho, d_u, c->stream));
   else
@@ -426,7 +429,7 @@ int lbm_populations(lbm_ctx* c, double* f, double* g) {
     double* dst = i < c->Q ? f + (size_t)i * nodes : (g ? g + (size_t)(i - c->Q) * nodes : nullptr);
     if (!dst) continue;
     if (c->ddf)
-      HIP_TRY(c, launch_decode_ddf(c->kind, i, c->A, c->L, c->dp, c->readout, c->stream));
+      HIP_TRY(c, launch_decode_ddf(c->fmt, i, c->A, c->L, c->dp, c->s_dec, c->readout, c->stream));
     else if (c->codec >= 0)
       HIP_TRY(c, launch_decode_bgk_red(c->codec, i, c->A, c->L, c->s_dec, c->readout, c->stream));
     else

@@ -58,18 +58,21 @@ hipError_t launch_moments_bgk(int kind, int D, const void* A, const Layout& L, d
 // Population plane i of the stored state decoded to float64 f_i (nodes values, no padding).
 hipError_t launch_decode_f(int kind, int D, int i, const void* A, const Layout& L, double* f,
                            hipStream_t s);
-// Double-distribution kernels (D2Q9): planes 0..8 hold f - w, planes 9..17 hold g - v.
+// Double-distribution kernels (D2Q9). Storage format fmt / kind: 0 float32, 1 float64 (planes
+// 0..8 hold f - w, 9..17 hold g - v); 2 bfloat16, 3 float16 reduced storage (4 float32 moment
+// planes, then 6 f and 8 g uint16 planes).
 Grid make_grid_ddf(const Layout& L, int halo);
 // out[0..8] = f^eq, out[9..17] = g^eq at rho = 1, u = 0, T = 1 (18 doubles, device memory).
 hipError_t launch_ddf_rest_state(const DdfParams& prm, double* out, hipStream_t s);
-hipError_t launch_ddf(int kind, bool walls, bool pull, const void* A, void* B, const Layout& L,
-                      const Grid& G, const DdfParams& prm, double* partials, hipStream_t s);
+hipError_t launch_ddf(int fmt, bool walls, bool pull, const void* A, void* B, const Layout& L,
+                      const Grid& G, const DdfParams& prm, float s_enc, float s_dec,
+                      double* partials, hipStream_t s);
 hipError_t launch_init_ddf(int kind, const double* rho, const double* u, const double* T,
                            void* A, const Layout& L, const DdfParams& prm, hipStream_t s);
 hipError_t launch_moments_ddf(int kind, const void* A, const Layout& L, const DdfParams& prm,
                               double* rho, double* u, double* T, double* edens, hipStream_t s);
 hipError_t launch_decode_ddf(int kind, int i, const void* A, const Layout& L,
-                             const DdfParams& prm, double* out, hipStream_t s);
+                             const DdfParams& prm, float s_dec, double* out, hipStream_t s);
 // Reduced storage (D2Q9 isothermal): 3 float32 moment planes then 6 uint16 planes.
 // codec 0 = bfloat16, 1 = float16 with scale s_enc = 2^S, s_dec = 2^-S.
 hipError_t launch_bgk_d2q9_red(int codec, const void* A, void* B, const Layout& L, const Grid& G,

@@ -104,3 +104,84 @@ def test_full_size_single_step(storage):
     expect = bgk.collide(bgk.stream(f_post), bgk.omega_from_tau_lb(0.6))
     # the new state is re-encoded: 16-bit relative error on n ~ 1e-4 .. 1e-3 -> ~1e-6 absolute
     assert np.abs(f_next - expect).max() <= 1e-5
+
+
+# ---- double-distribution model ---------------------------------------------------------------
+from oracle import ddf  # noqa: E402
+
+R, CV, P0 = 1.0 / 3.0, 5.0 / 6.0, 1.0 / 3.0
+
+
+def _ddf_oracle(rho, u, T, tau, steps, walls, phi):
+    gas = ddf.Gas(R, CV, (tau - 0.5) * P0)
+    f, g = ddf.init_equilibrium(rho, u, T, gas)
+    f, g = ddf.run(f, g, gas, steps, walls_y=walls, phi_on=phi > 0,
+                   stencil={1: "central", 2: "upwind"}.get(phi, "central"))
+    return ddf.temperature(f, g, gas)
+
+
+@pytest.mark.parametrize("storage", CODECS)
+def test_ddf_shear_layer(storage):
+    announce("reduced %s DDF shear layer 128x64 walls 300 steps" % storage)
+    rho, u, T = inputs.thermal_shear_layer(128, seed=0, ny=64)
+    lat = _lattice(rho, u, T, model="ddf", tau=0.6, wall_y=True, phi=1, storage=storage)
+    lat.step(300)
+    _, ug, tg, _ = lat.moments()
+    lat.close()
+    _, uo, to = _ddf_oracle(rho, u, T, 0.6, 300, True, 1)
+    assert rel_l2(ug, uo) <= 1e-3
+    assert rel_l2(tg - 0.9, to - 0.9) <= 1e-3
+
+
+@pytest.mark.parametrize("storage", CODECS)
+def test_ddf_periodic_upwind(storage):
+    announce("reduced %s DDF periodic upwind 64x64 100 steps" % storage)
+    rho, u = inputs.random_phase_turbulence_2d(64, seed=2)
+    u = u + 0.02
+    T = 0.9 + 0.05 * np.sin(2 * np.pi * np.arange(64) / 64)[None, :] * np.ones((64, 1))
+    rho = P0 / (R * T)
+    lat = _lattice(rho, u, T, model="ddf", tau=0.6, wall_y=False, phi=2, storage=storage)
+    lat.step(100)
+    _, ug, tg, _ = lat.moments()
+    lat.close()
+    _, uo, to = _ddf_oracle(rho, u, T, 0.6, 100, False, 2)
+    assert rel_l2(ug, uo) <= 1e-3
+
+
+@pytest.mark.parametrize("storage", CODECS)
+def test_ddf_conservation(storage):
+    announce("reduced %s DDF conservation 512x256 walls 1000 steps" % storage)
+    rho, u, T = inputs.thermal_shear_layer(512, seed=0, ny=256)
+    lat = _lattice(rho, u, T, model="ddf", tau=0.6, wall_y=True, phi=1, storage=storage,
+                   diag_every=100)
+    t0 = lat.moments()[3]
+    lat.step(1000)
+    h = lat.diag_history()
+    lat.close()
+    assert np.all(np.abs(h[:, 1] - t0[0]) / t0[0] < 1e-6)
+    assert np.all(np.abs(h[:, 5] - t0[4]) / t0[4] < 1e-6)
+
+
+@pytest.mark.parametrize("storage", CODECS)
+def test_ddf_full_size_rows_single_step(storage):
+    announce("reduced %s DDF 4096^2 one step at sampled rows" % storage)
+    n = 4096
+    rho, u, T = inputs.thermal_shear_layer(n, seed=0)
+    lat = _lattice(rho, u, T, model="ddf", tau=0.6, wall_y=True, phi=1, storage=storage)
+    lat.step(10)
+    f_post, g_post = lat.populations()
+    lat.step(1)
+    f_next, g_next = lat.populations()
+    lat.close()
+    gas = ddf.Gas(R, CV, 0.1 * P0)
+    for c in (0, 2047, n - 1):
+        lo, hi = max(c - 2, 0), min(c + 3, n)
+        src_lo, src_hi = max(lo - 1, 0), min(hi + 1, n)
+        keep = slice(lo - src_lo, hi - src_lo)
+        fpre = bgk.stream(f_post[:, src_lo:src_hi], walls_y=True)[:, keep]
+        gpre = bgk.stream(g_post[:, src_lo:src_hi], walls_y=True)[:, keep]
+        ft, gt = ddf.collide(fpre, gpre, gas, True, True, "central")
+        k = c - lo
+        # re-encoding the new state: 16-bit relative error of the non-equilibrium part
+        assert np.abs(ft[:, k] - f_next[:, c]).max() <= 2e-5, c
+        assert np.abs(gt[:, k] - g_next[:, c]).max() <= 2e-5, c
