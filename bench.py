@@ -19,17 +19,21 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "counters_d2q9_bgk_fp32_2048.txt")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2609_28679_amd", "csrc", "bgk.hip")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2609_28679_amd", "csrc", f)
+                  for f in ("bgk.hip", "device_common.h")]
 
 
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def source_digest(path):
+def source_digest(paths):
     import hashlib
-    with open(path, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for p in paths:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def counter_traffic(nodes):
@@ -42,7 +46,7 @@ def counter_traffic(nodes):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha256_16") != source_digest(KERNEL_SOURCE):
+    if kv.get("kernel_source_sha256_16") != source_digest(KERNEL_SOURCES):
         return None
     if int(kv.get("nodes", -1)) != nodes:
         return None
@@ -138,7 +142,7 @@ def cpu_baseline():
 
     from oracle import bgk
     from paper_2609_28679_amd import inputs
-    n, steps = 2048, 4
+    n, steps = 2048, 40
     rho, u = inputs.random_phase_turbulence_2d(n, seed=0)
     f = bgk.init_equilibrium(rho, u)
     omega = bgk.omega_from_tau_lb(0.6)
@@ -159,6 +163,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a 1 GiB device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the lattice is not sharded across GPUs in this "
@@ -171,6 +177,14 @@ def main():
 
     torch.cuda.set_device(0)
     binding.load()
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: 3 x %d bytes read + written" % (src.numel() * 4))
+        del src, dst
     n, tau = 2048, 0.6
     log("headline: D2Q9 FP32 %dx%d tau %g, warmup %d, steps %d" % (n, n, tau, args.warmup, args.steps))
     rho, u = inputs.random_phase_turbulence_2d(n, seed=0)

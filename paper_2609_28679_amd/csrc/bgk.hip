@@ -289,6 +289,29 @@ __global__ void k_field_totals(int D, const double* __restrict__ rho, const doub
 }
 
 // ---- launchers -----------------------------------------------------------------------------
+Layout make_layout(int nx, int ny, int nz, int elem) {
+  // Rows start on 256-byte boundaries. Population planes are padded to a 4 KiB multiple plus
+  // 17 KiB so that the Q concurrent read and write streams of a workgroup, which sit whole
+  // planes apart, start on different HBM channels; the padding was chosen by a sweep of row
+  // and plane padding on MI355X (D2Q9 at 2048^2 and 4096^2, D3Q27 at 256^3).
+  Layout L;
+  L.nx = nx;
+  L.ny = ny;
+  L.nz = nz;
+  const int64_t row_align = 256 / elem;
+  int64_t pitch = ((int64_t)nx + row_align - 1) / row_align * row_align;
+  int64_t plane_pad = 17 * 1024 / elem;
+#ifdef LBM_TUNING_ENV
+  if (const char* v = getenv("LBM_PITCH_PAD")) pitch += atoll(v);
+  if (const char* v = getenv("LBM_PLANE_PAD")) plane_pad = atoll(v);
+#endif
+  L.pitch = pitch;
+  const int64_t raw = pitch * ny * nz;
+  const int64_t epk = 4096 / elem;
+  L.plane = (raw + epk - 1) / epk * epk + plane_pad;
+  return L;
+}
+
 Grid make_grid(const Layout& L) {
   // One row per workgroup measured best for the streaming kernels on MI355X (more
   // workgroups in flight); the row count only grows for very large lattices.

@@ -134,23 +134,7 @@ void make_plan(const lbm_params* p, Plan& P) {
   P.ddf = p->model == LBM_MODEL_DDF;
   P.planes = P.ddf ? 2 * P.Q : P.Q;
   P.elem = P.kind ? 8 : 4;
-  P.L.nx = p->nx;
-  P.L.ny = p->ny;
-  P.L.nz = p->nz;
-  // Rows start on 256-byte boundaries. Population planes are padded to a 4 KiB multiple plus
-  // 17 KiB so that the Q concurrent read and write streams of a workgroup, which sit whole
-  // planes apart, start on different HBM channels; the padding was chosen by a sweep of row
-  // and plane padding on MI355X (D2Q9 at 2048^2 and 4096^2, D3Q27 at 256^3).
-  int64_t pitch = (int64_t)align_up((size_t)p->nx, (size_t)(256 / P.elem));
-  int64_t plane_pad = (int64_t)(17 * 1024 / P.elem);
-#ifdef LBM_TUNING_ENV
-  if (const char* v = getenv("LBM_PITCH_PAD")) pitch += atoll(v);
-  if (const char* v = getenv("LBM_PLANE_PAD")) plane_pad = atoll(v);
-#endif
-  P.L.pitch = pitch;
-  const int64_t raw = P.L.pitch * p->ny * p->nz;
-  const int64_t epk = (int64_t)(4096 / P.elem);
-  P.L.plane = (raw + epk - 1) / epk * epk + plane_pad;
+  P.L = make_layout(p->nx, p->ny, p->nz, (int)P.elem);
   P.G = P.ddf ? make_grid_ddf(P.L, p->phi == 2 ? 2 : 1)
               : (p->collision == LBM_COLLIDE_MLP ? make_grid_mlp(P.L) : make_grid(P.L));
   P.partial_slots = std::max(P.G.blocks(), 1024);

@@ -31,6 +31,8 @@ struct Grid {
   int blocks() const { return nbx * nby; }
 };
 
+// Population layout for elements of `elem` bytes (row pitch and padded plane stride).
+Layout make_layout(int nx, int ny, int nz, int elem);
 Grid make_grid(const Layout& L);
 
 // Ideal-gas double-distribution parameters (lattice units).
