@@ -35,17 +35,22 @@
 #include "ddf_common.h"
 #include "reduced_common.h"
 
+#include <cstdlib>
+
 namespace lbm {
 
 template <typename S>
 struct IoFull {
   using ring_t = S;
+  static constexpr bool kStaged = false;
+  static constexpr int kStageFloats = 1;
   const S* A;
   S* B;
   int64_t plane;
+  __device__ __forceinline__ void stage(float*, int, int, int, int, int64_t, int, const DdfParams&) const {}
   __device__ __forceinline__ void gather(bool pull, int64_t r0, int64_t rm, int64_t rp, int x,
                                          int xm, int xp, bool top, bool bot, const DdfParams&,
-                                         S (&hf)[9], S (&hg)[9]) const {
+                                         int, int, const float*, S (&hf)[9], S (&hg)[9]) const {
     if (pull) {
       gather9(A, plane, r0, rm, rp, x, xm, xp, top, bot, hf);
       gather9(A + 9 * plane, plane, r0, rm, rp, x, xm, xp, top, bot, hg);
@@ -90,27 +95,71 @@ struct IoRed {
     hf = fe + neq_f<Codec>(N, plane, src, ii, s_dec) - p.wf[ii];
     hg = ge + neq_g<Codec>(N + kRedF * plane, plane, src, ii, s_dec) - p.wg[ii];
   }
-  __device__ __forceinline__ void gather(bool pull, int64_t r0, int64_t rm, int64_t rp, int x,
-                                         int xm, int xp, bool top, bool bot, const DdfParams& p,
-                                         float (&hf)[9], float (&hg)[9]) const {
-    const int xs[3] = {xp, x, xm};     // source column by c_x + 1
-    const int64_t ys[3] = {rp, r0, rm};  // source row offset by c_y + 1
+  // Staging: the rows of the 3-row pull window are decoded once per workgroup into LDS,
+  // stage[slot][c][k] with c the column x_first + c (258 columns: the workgroup's 256 plus one
+  // on each side) and k = 0..8 f - w, 9..17 g - v (19 floats per column: an odd stride keeps
+  // the lanes on distinct LDS banks).
+  static constexpr bool kStaged = true;
+  static constexpr int kCols = kBlock + 2, kStride = 19;
+  static constexpr int kStageFloats = 3 * kCols * kStride;
+  __device__ __forceinline__ void stage(float* st, int r, int ny, int nx, int x_first,
+                                        int64_t pitch, int walls, const DdfParams& p) const {
+    if (walls && (r < 0 || r >= ny)) return;  // beyond a wall: never pulled (bounce-back)
+    const int rr = ((r % ny) + ny) % ny;
+    float* dst = st + ((r % 3) + 3) % 3 * (kCols * kStride);
+    for (int c = threadIdx.x; c < kCols; c += kBlock) {
+      const int xg = (((x_first + c) % nx) + nx) % nx;
+      const int64_t off = (int64_t)rr * pitch + xg;
+      const double rho = 1.0 + (double)M[off];
+      const double ux = (double)M[plane + off];
+      const double uy = (double)M[2 * plane + off];
+      const double T = 1.0 + (double)M[3 * plane + off];
+      double nf[9], ng[9];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        if (f_slot(i) >= 0) nf[i] = (double)Codec::dec(N[f_slot(i) * plane + off], s_dec);
+        if (g_slot(i) >= 0) ng[i] = (double)Codec::dec(N[(kRedF + g_slot(i)) * plane + off], s_dec);
+      }
+      nf[5] = nf[0] - nf[2] + nf[3] + nf[6] - nf[8];
+      nf[7] = nf[0] + nf[1] + nf[2] - nf[6] - nf[8];
+      nf[4] = -(((nf[0] + nf[1]) + (nf[2] + nf[3])) + ((nf[5] + nf[6]) + (nf[7] + nf[8])));
+      ng[4] = -(((ng[0] + ng[1]) + (ng[2] + ng[3])) + ((ng[5] + ng[6]) + (ng[7] + ng[8])));
+      double fe[9], ge[9];
+      equilibria(rho, ux, uy, p.R * T, p.cv * T, fe, ge);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        dst[c * kStride + i] = (float)(fe[i] - p.wf[i] + nf[i]);
+        dst[c * kStride + 9 + i] = (float)(ge[i] - p.wg[i] + ng[i]);
+      }
+    }
+  }
+  // pull of node (column tid + 1 of the staged rows, row r) from LDS
+  __device__ __forceinline__ void gather(bool pull, int64_t, int64_t, int64_t, int, int, int,
+                                         bool top, bool bot, const DdfParams&, int r, int tid,
+                                         const float* st, float (&hf)[9], float (&hg)[9]) const {
+    auto at = [&](int row, int c, int k) {
+      return st[((row % 3) + 3) % 3 * (kCols * kStride) + c * kStride + k];
+    };
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       const int ka = i % 3, kb = i / 3;
       const bool bounce = (kb == 2 && bot) || (kb == 0 && top);
-      const int ii = (pull && bounce) ? 8 - i : i;
-      const int64_t src = (!pull || bounce) ? r0 + x : ys[kb] + xs[ka];
-      double a, b;
-      pop(src, ii, p, a, b);
-      hf[i] = (float)a;
-      hg[i] = (float)b;
+      if (!pull) {
+        hf[i] = at(r, tid + 1, i);
+        hg[i] = at(r, tid + 1, 9 + i);
+      } else if (bounce) {
+        hf[i] = at(r, tid + 1, 8 - i);
+        hg[i] = at(r, tid + 1, 17 - i);
+      } else {
+        hf[i] = at(r - (kb - 1), tid + 1 - (ka - 1), i);
+        hg[i] = at(r - (kb - 1), tid + 1 - (ka - 1), 9 + i);
+      }
     }
   }
   __device__ __forceinline__ void store(int64_t off, int i, double htf, double hfe, double htg,
                                         double hge) const {
-    if (f_slot(i) >= 0) store_nt(No + f_slot(i) * plane + off, Codec::enc(htf - hfe, s_enc));
-    if (g_slot(i) >= 0) store_nt(No + (kRedF + g_slot(i)) * plane + off, Codec::enc(htg - hge, s_enc));
+    if (f_slot(i) >= 0) store_nt(No + f_slot(i) * plane + off, Codec::enc((float)(htf - hfe), s_enc));
+    if (g_slot(i) >= 0) store_nt(No + (kRedF + g_slot(i)) * plane + off, Codec::enc((float)(htg - hge), s_enc));
   }
   __device__ __forceinline__ void store_moments(int64_t off, const double (&m)[6], double R) const {
     store_nt(Mo + off, (float)(m[0] - 1.0));
@@ -130,6 +179,7 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
   constexpr int TXI = kBlock - 2 * HALO;
   __shared__ double s_phix[2][kBlock];
   __shared__ double s_phiy[P][kBlock];
+  __shared__ float s_stage[IO::kStageFloats];
 
   const int nbx = gridDim.x;
   const int tile = xcd_tile(blockIdx.x + nbx * blockIdx.y, nbx * gridDim.y);
@@ -150,11 +200,20 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
   double ring_m[H1][6];  // rho, u_x, u_y, theta, e, Phi_xx
   double acc[kDiagValues] = {0.0, 0.0, 0.0, 0.0, 0.0};
 
+  const int x_first = x0 - HALO - 1;  // first staged column
+  if (IO::kStaged) {
+    io.stage(s_stage, y0 - HALO - 1, ny, nx, x_first, pitch, WALLS, prm);
+    io.stage(s_stage, y0 - HALO, ny, nx, x_first, pitch, WALLS, prm);
+  }
   for (int k = 0; k < count; k += H1) {
 #pragma unroll
     for (int j = 0; j < H1; ++j) {
       const int w = k + j;                 // window index (block-uniform)
       const int r = y0 - HALO + w;         // row being gathered
+      if (IO::kStaged) {
+        io.stage(s_stage, r + 1, ny, nx, x_first, pitch, WALLS, prm);
+        __syncthreads();
+      }
       const bool in_window = w < count;
       const bool row_real = in_window && (WALLS ? (r >= 0 && r < ny) : true);
       const int rr = WALLS ? r : ((r % ny) + ny) % ny;
@@ -165,7 +224,7 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
         const int yp = rr == ny - 1 ? 0 : rr + 1;
         const int64_t r0 = (int64_t)rr * pitch, rm = (int64_t)ym * pitch, rp = (int64_t)yp * pitch;
         const bool top = WALLS && rr == ny - 1, bot = WALLS && rr == 0;
-        io.gather(PULL, r0, rm, rp, x, xm, xp, top, bot, prm, ring_f[j], ring_g[j]);
+        io.gather(PULL, r0, rm, rp, x, xm, xp, top, bot, prm, r, tid, s_stage, ring_f[j], ring_g[j]);
         // ---- moments and closure ------------------------------------------------------------
         double f[9], g[9];
 #pragma unroll
@@ -308,6 +367,9 @@ Grid make_grid_ddf(const Layout& L, int halo) {
   const int txi = kBlock - 2 * halo;
   G.nbx = (L.nx + txi - 1) / txi;
   G.rows = 32;
+#ifdef LBM_TUNING_ENV
+  if (const char* v = getenv("LBM_DDF_ROWS")) G.rows = atoi(v);
+#endif
   G.nby = (L.ny + G.rows - 1) / G.rows;
   return G;
 }

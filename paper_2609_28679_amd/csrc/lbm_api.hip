@@ -135,8 +135,14 @@ void make_plan(const lbm_params* p, Plan& P) {
   P.planes = P.ddf ? 2 * P.Q : P.Q;
   P.elem = P.kind ? 8 : 4;
   P.L = make_layout(p->nx, p->ny, p->nz, (int)P.elem);
-  P.G = P.ddf ? make_grid_ddf(P.L, p->phi == 2 ? 2 : 1)
-              : (p->collision == LBM_COLLIDE_MLP ? make_grid_mlp(P.L) : make_grid(P.L));
+  if (P.ddf)
+    P.G = make_grid_ddf(P.L, p->phi == 2 ? 2 : 1);
+  else if (p->collision == LBM_COLLIDE_MLP)
+    P.G = make_grid_mlp(P.L);
+  else if (P.codec >= 0)
+    P.G = make_grid_red(P.L);
+  else
+    P.G = make_grid(P.L);
   P.partial_slots = std::max(P.G.blocks(), 1024);
   size_t off = 0;
   // reduced storage: float32 moment planes + uint16 non-equilibrium planes

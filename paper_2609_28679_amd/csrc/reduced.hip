@@ -9,6 +9,8 @@
 // m(x) = (rho - 1, u) and n(x) = f~(x) - f^eq(m(x)).
 #include "reduced_common.h"
 
+#include <cstdlib>
+
 namespace lbm {
 
 __device__ __forceinline__ double psi_c(int c, double u) {
@@ -16,65 +18,120 @@ __device__ __forceinline__ double psi_c(int c, double u) {
   return c == 0 ? (2.0 / 3.0) - u2 : (1.0 / 6.0) + 0.5 * (u2 + c * u);
 }
 
+// LDS-staged kernel. A workgroup owns 256 columns and `rows` rows and walks them bottom to
+// top. Each row that enters the 3-row window is decoded once, node by node, into its nine
+// post-collision populations (float32 in LDS, 258 columns with the periodic x halo); the pull
+// then reads the nine sources of a node from LDS. Every stored byte is read once per workgroup
+// with coalesced loads and every node's equilibrium is rebuilt once.
+//
+// Arithmetic is float32 in shifted form: h_i = f_i - w_i (w the rest weights), and with
+// psi_c = W_c + d_c (W = 2/3, 1/6, 1/6; d_0 = -u^2, d_+- = (u^2 +- u)/2) the equilibrium is
+//   f_i^eq - w_i = (rho - 1) psi_a psi_b + (W_a d_b + d_a W_b + d_a d_b),
+// a sum of O(Mach) terms, so every quantity keeps float32 relative precision of the part that
+// carries the flow. The stored non-equilibrium part has 8 (bfloat16) or 11 (float16) bits, so
+// float32 rounding (~1e-7 relative) stays far below it.
+constexpr int kRedCols = kBlock + 2;
+
+__device__ __forceinline__ void dpsi3(float u, float (&d)[3]) {
+  const float u2 = u * u;
+  d[0] = 0.5f * (u2 - u);
+  d[1] = -u2;
+  d[2] = 0.5f * (u2 + u);
+}
+__device__ __forceinline__ float wk(int k) { return k == 1 ? 2.0f / 3.0f : 1.0f / 6.0f; }
+
+// f_i^eq - w_i for the nine directions from drho = rho - 1 and the per-axis deviations
+__device__ __forceinline__ float heq_i(int i, float drho, const float (&dx)[3], const float (&dy)[3]) {
+  const int a = i % 3, b = i / 3;
+  const float pa = wk(a) + dx[a], pb = wk(b) + dy[b];
+  return drho * (pa * pb) + (wk(a) * dy[b] + dx[a] * wk(b) + dx[a] * dy[b]);
+}
+
 template <typename Codec, bool WALLS, bool DIAG>
 __global__ void __launch_bounds__(kBlock)
 k_bgk_d2q9_red(const float* __restrict__ M, const uint16_t* __restrict__ N, float* __restrict__ Mo,
                uint16_t* __restrict__ No, int nx, int ny, int64_t pitch, int64_t plane,
-               double omega, float s_enc, float s_dec, int rows, double* __restrict__ partials) {
+               double omega_d, float s_enc, float s_dec, int rows, double* __restrict__ partials) {
+  __shared__ float ring[3][kRedCols][9];
   const int nbx = gridDim.x;
   const int tile = xcd_tile(blockIdx.x + nbx * blockIdx.y, nbx * gridDim.y);
   const int bx = tile % nbx;
   const int by = tile / nbx;
-  const int x = bx * blockDim.x + threadIdx.x;
+  const int tid = threadIdx.x;
+  const int x0 = bx * kBlock;
+  const int x = x0 + tid;
   const int y0 = by * rows;
+  const int yend = min(y0 + rows, ny);
+  const float keep = (float)(1.0 - omega_d);  // f~ - f^eq = (1 - omega)(f - f^eq)
   double acc[kDiagValues] = {0.0, 0.0, 0.0, 0.0, 0.0};
 
-  if (x < nx) {
-    const int xs[3] = {x == nx - 1 ? 0 : x + 1, x, x == 0 ? nx - 1 : x - 1};  // by c_x + 1
-    const int yend = min(y0 + rows, ny);
-    for (int y = y0; y < yend; ++y) {
-      const int ys[3] = {y == ny - 1 ? 0 : y + 1, y, y == 0 ? ny - 1 : y - 1};
-      const int64_t self = (int64_t)y * pitch + x;
-      double f[9];
+  // decode row r (unwrapped index) into ring slot r mod 3
+  auto load_row = [&](int r) {
+    if (WALLS && (r < 0 || r >= ny)) return;  // beyond a wall: never pulled (bounce-back)
+    const int rr = ((r % ny) + ny) % ny;
+    float(*dst)[9] = ring[((r % 3) + 3) % 3];
+    for (int c = tid; c < kRedCols; c += kBlock) {
+      int xg = x0 - 1 + c;
+      xg = ((xg % nx) + nx) % nx;
+      const int64_t off = (int64_t)rr * pitch + xg;
+      const float drho = M[off];
+      const float ux = M[plane + off];
+      const float uy = M[2 * plane + off];
+      float n[9];
+#pragma unroll
+      for (int i = 0; i < 9; ++i)
+        if (f_slot(i) >= 0) n[i] = (float)Codec::dec(N[f_slot(i) * plane + off], s_dec);
+      n[5] = n[0] - n[2] + n[3] + n[6] - n[8];
+      n[7] = n[0] + n[1] + n[2] - n[6] - n[8];
+      n[4] = -(((n[0] + n[1]) + (n[2] + n[3])) + ((n[5] + n[6]) + (n[7] + n[8])));
+      float dx[3], dy[3];
+      dpsi3(ux, dx);
+      dpsi3(uy, dy);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) dst[c][i] = heq_i(i, drho, dx, dy) + n[i];
+    }
+  };
+
+  load_row(y0 - 1);
+  load_row(y0);
+  for (int y = y0; y < yend; ++y) {
+    load_row(y + 1);
+    __syncthreads();
+    if (x < nx) {
+      float h[9];
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         const int ka = i % 3, kb = i / 3;
         const bool bounce = WALLS && ((kb == 2 && y == 0) || (kb == 0 && y == ny - 1));
-        const int ii = bounce ? 8 - i : i;
-        const int64_t src = bounce ? self : (int64_t)ys[kb] * pitch + xs[ka];
-        const double rho = 1.0 + (double)M[src];
-        const double ux = (double)M[plane + src];
-        const double uy = (double)M[2 * plane + src];
-        const double feq = rho * psi_c(ii % 3 - 1, ux) * psi_c(ii / 3 - 1, uy);
-        f[i] = feq + neq_f<Codec>(N, plane, src, ii, s_dec);
+        h[i] = bounce ? ring[((y % 3) + 3) % 3][tid + 1][8 - i]
+                      : ring[(((y - kb + 1) % 3) + 3) % 3][tid + 1 - (ka - 1)][i];
       }
-      const double rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
-      const double jx = (f[2] + f[5] + f[8]) - (f[0] + f[3] + f[6]);
-      const double jy = (f[6] + f[7] + f[8]) - (f[0] + f[1] + f[2]);
-      const double ux = jx / rho, uy = jy / rho;
-      double px[3], py[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        px[k] = psi_c(k - 1, ux);
-        py[k] = psi_c(k - 1, uy);
-      }
-      // post-collision non-equilibrium part: f~ - f^eq = (1 - omega)(f - f^eq)
-      double n[9];
-#pragma unroll
-      for (int i = 0; i < 9; ++i) n[i] = (1.0 - omega) * (f[i] - rho * px[i % 3] * py[i / 3]);
-      store_nt(Mo + self, (float)(rho - 1.0));
-      store_nt(Mo + plane + self, (float)ux);
-      store_nt(Mo + 2 * plane + self, (float)uy);
+      // sum_i w_i = 1 and sum_i c_i w_i = 0
+      const float drho = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
+      const float jx = (h[2] + h[5] + h[8]) - (h[0] + h[3] + h[6]);
+      const float jy = (h[6] + h[7] + h[8]) - (h[0] + h[1] + h[2]);
+      const float rho = 1.0f + drho;
+      const float ux = jx / rho, uy = jy / rho;
+      float dx[3], dy[3];
+      dpsi3(ux, dx);
+      dpsi3(uy, dy);
+      const int64_t self = (int64_t)y * pitch + x;
+      store_nt(Mo + self, drho);
+      store_nt(Mo + plane + self, ux);
+      store_nt(Mo + 2 * plane + self, uy);
 #pragma unroll
       for (int i = 0; i < 9; ++i)
-        if (f_slot(i) >= 0) store_nt(No + f_slot(i) * plane + self, Codec::enc(n[i], s_enc));
+        if (f_slot(i) >= 0)
+          store_nt(No + f_slot(i) * plane + self,
+                   Codec::enc(keep * (h[i] - heq_i(i, drho, dx, dy)), s_enc));
       if (DIAG) {
-        acc[0] += rho;
-        acc[1] += jx;
-        acc[2] += jy;
-        acc[4] += 0.5 * rho * (ux * ux + uy * uy);
+        acc[0] += 1.0 + (double)drho;
+        acc[1] += (double)jx;
+        acc[2] += (double)jy;
+        acc[4] += 0.5 * (double)rho * ((double)ux * ux + (double)uy * uy);
       }
     }
+    __syncthreads();
   }
   if (DIAG) block_sum_store<kDiagValues>(acc, partials + (int64_t)tile * kDiagValues);
 }
@@ -116,11 +173,23 @@ __global__ void k_decode_bgk_red(int i, const float* __restrict__ M, const uint1
 }
 
 // ---- launchers -----------------------------------------------------------------------------
+Grid make_grid_red(const Layout& L) {
+  Grid G;
+  G.bx = kBlock;
+  G.nbx = (L.nx + kBlock - 1) / kBlock;
+  G.rows = 16;  // sweep on MI355X at 2048^2: 1 -> 88 us, 4 -> 62, 16 -> 56, 32 -> 77
+#ifdef LBM_TUNING_ENV
+  if (const char* v = getenv("LBM_RED_ROWS")) G.rows = atoi(v);
+#endif
+  G.nby = (L.ny + G.rows - 1) / G.rows;
+  return G;
+}
+
 template <typename Codec, bool WALLS>
 static void red_launch(const float* M, const uint16_t* N, float* Mo, uint16_t* No, const Layout& L,
                        const Grid& G, double omega, float se, float sd, double* partials,
                        hipStream_t s) {
-  dim3 grid(G.nbx, G.nby), block(G.bx);
+  dim3 grid(G.nbx, G.nby), block(kBlock);
   if (partials)
     k_bgk_d2q9_red<Codec, WALLS, true><<<grid, block, 0, s>>>(M, N, Mo, No, L.nx, L.ny, L.pitch, L.plane, omega, se, sd, G.rows, partials);
   else

@@ -11,8 +11,9 @@
 //                                               n_7 = n_0 + n_1 + n_2 - n_6 - n_8   (y momentum)
 //                                               n_4 = -sum_{i != 4} n_i            (mass)
 //   g: stored i != 4; rebuilt n_4 = -sum_{i != 4} n_i                               (energy)
-// Codecs: bfloat16 (float32 rounded to nearest even, upper 16 bits) or float16 of n * 2^S
-// (round to nearest even, subnormals kept; S lifts |n| ~ 1e-8 .. 1e-3 into the normal range).
+// Codecs (encode from float32): bfloat16 (round to nearest even, upper 16 bits) or float16 of
+// n * 2^S (round to nearest even, subnormals kept; S lifts |n| ~ 1e-8 .. 1e-3 into the normal
+// range). Values computed in float64 are rounded to float32 first.
 #pragma once
 
 #include "device_common.h"
@@ -20,25 +21,24 @@
 namespace lbm {
 
 struct CodecBF16 {
-  __device__ static __forceinline__ uint16_t enc(double v, float) {
-    const float f = (float)v;
+  __device__ static __forceinline__ uint16_t enc(float f, float) {
     uint32_t b = __float_as_uint(f);
     b += 0x7FFFu + ((b >> 16) & 1u);
     return (uint16_t)(b >> 16);
   }
-  __device__ static __forceinline__ double dec(uint16_t h, float) {
-    return (double)__uint_as_float((uint32_t)h << 16);
+  __device__ static __forceinline__ float dec(uint16_t h, float) {
+    return __uint_as_float((uint32_t)h << 16);
   }
 };
 
 struct CodecFP16 {
   // scale = 2^S on encode, 2^-S on decode (exact powers of two)
-  __device__ static __forceinline__ uint16_t enc(double v, float scale) {
-    const _Float16 h = (_Float16)((float)v * scale);
+  __device__ static __forceinline__ uint16_t enc(float v, float scale) {
+    const _Float16 h = (_Float16)(v * scale);
     return __builtin_bit_cast(uint16_t, h);
   }
-  __device__ static __forceinline__ double dec(uint16_t h, float inv_scale) {
-    return (double)((float)__builtin_bit_cast(_Float16, h) * inv_scale);
+  __device__ static __forceinline__ float dec(uint16_t h, float inv_scale) {
+    return (float)__builtin_bit_cast(_Float16, h) * inv_scale;
   }
 };
 
@@ -56,7 +56,7 @@ constexpr int kRedG = 8;  // stored g planes
 template <typename Codec>
 __device__ __forceinline__ double neq_f(const uint16_t* __restrict__ N, int64_t plane, int64_t off,
                                         int i, float s) {
-  auto d = [&](int slot) { return Codec::dec(N[slot * plane + off], s); };
+  auto d = [&](int slot) { return (double)Codec::dec(N[slot * plane + off], s); };
   switch (i) {
     case 5: return d(0) - d(2) + d(3) + d(4) - d(5);
     case 7: return d(0) + d(1) + d(2) - d(4) - d(5);
@@ -73,10 +73,10 @@ __device__ __forceinline__ double neq_f(const uint16_t* __restrict__ N, int64_t 
 template <typename Codec>
 __device__ __forceinline__ double neq_g(const uint16_t* __restrict__ N, int64_t plane, int64_t off,
                                         int i, float s) {
-  if (i != 4) return Codec::dec(N[g_slot(i) * plane + off], s);
+  if (i != 4) return (double)Codec::dec(N[g_slot(i) * plane + off], s);
   double t = 0.0;
 #pragma unroll
-  for (int k = 0; k < kRedG; ++k) t += Codec::dec(N[k * plane + off], s);
+  for (int k = 0; k < kRedG; ++k) t += (double)Codec::dec(N[k * plane + off], s);
   return -t;
 }
 
