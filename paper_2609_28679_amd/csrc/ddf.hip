@@ -361,12 +361,15 @@ __global__ void k_ddf_rest_state(DdfParams prm, double* __restrict__ out) {
 }
 
 // ---- launchers ------------------------------------------------------------------------------
-Grid make_grid_ddf(const Layout& L, int halo) {
+Grid make_grid_ddf(const Layout& L, int halo, bool reduced) {
   Grid G;
   G.bx = kBlock;
   const int txi = kBlock - 2 * halo;
   G.nbx = (L.nx + txi - 1) / txi;
-  G.rows = 32;
+  // rows per workgroup from a sweep on MI355X at 4096^2 (float32: 2 -> 588 us, 4 -> 553,
+  // 16 -> 599; reduced bf16: 4 -> 967, 16 -> 736, 32 -> 739): short windows give more
+  // workgroups in flight, the staged reduced kernel amortises its 2-row staging halo
+  G.rows = reduced ? 16 : 4;
 #ifdef LBM_TUNING_ENV
   if (const char* v = getenv("LBM_DDF_ROWS")) G.rows = atoi(v);
 #endif

@@ -136,7 +136,7 @@ void make_plan(const lbm_params* p, Plan& P) {
   P.elem = P.kind ? 8 : 4;
   P.L = make_layout(p->nx, p->ny, p->nz, (int)P.elem);
   if (P.ddf)
-    P.G = make_grid_ddf(P.L, p->phi == 2 ? 2 : 1);
+    P.G = make_grid_ddf(P.L, p->phi == 2 ? 2 : 1, P.codec >= 0);
   else if (p->collision == LBM_COLLIDE_MLP)
     P.G = make_grid_mlp(P.L);
   else if (P.codec >= 0)

@@ -63,7 +63,7 @@ hipError_t launch_decode_f(int kind, int D, int i, const void* A, const Layout& 
 // Double-distribution kernels (D2Q9). Storage format fmt / kind: 0 float32, 1 float64 (planes
 // 0..8 hold f - w, 9..17 hold g - v); 2 bfloat16, 3 float16 reduced storage (4 float32 moment
 // planes, then 6 f and 8 g uint16 planes).
-Grid make_grid_ddf(const Layout& L, int halo);
+Grid make_grid_ddf(const Layout& L, int halo, bool reduced);
 // out[0..8] = f^eq, out[9..17] = g^eq at rho = 1, u = 0, T = 1 (18 doubles, device memory).
 hipError_t launch_ddf_rest_state(const DdfParams& prm, double* out, hipStream_t s);
 hipError_t launch_ddf(int fmt, bool walls, bool pull, const void* A, void* B, const Layout& L,

@@ -18,10 +18,10 @@ __global__ void __launch_bounds__(kBlock)
 k_mlp_grad(const float* __restrict__ X, const float* __restrict__ T, int64_t n, int64_t start,
            int B, const float* __restrict__ w, float* __restrict__ partials) {
   __shared__ MlpLds s;
-  __shared__ short xs[4][64][16];
+  __shared__ __attribute__((aligned(16))) short xs[4][64][16];
   __shared__ float ys[4][64][16];
-  __shared__ short tA[4][64][64];
-  __shared__ short tB[4][64][64];
+  __shared__ __attribute__((aligned(16))) short tA[4][64][64];
+  __shared__ __attribute__((aligned(16))) short tB[4][64][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int r = lane & 15, q = lane >> 4;
   const int gw = blockIdx.x * 4 + wv;  // global wavefront
@@ -245,7 +245,7 @@ __global__ void k_mlp_reduce_adam(const float* __restrict__ partials, int nw, fl
 __global__ void __launch_bounds__(kBlock)
 k_mlp_forward(const float* __restrict__ X, int64_t n, const float* __restrict__ w, float* __restrict__ Y) {
   __shared__ MlpLds s;
-  __shared__ short xs[4][64][16];
+  __shared__ __attribute__((aligned(16))) short xs[4][64][16];
   __shared__ float ys[4][64][16];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t i = ((int64_t)blockIdx.x * 4 + wv) * 64 + lane;
@@ -254,13 +254,13 @@ k_mlp_forward(const float* __restrict__ X, int64_t n, const float* __restrict__ 
 #pragma unroll
   for (int k = 0; k < 16; ++k) xs[wv][lane][k] = (valid && k < kIn) ? f2bf(X[i * kIn + k]) : (short)0;
   __syncthreads();
-  MlpAct a;
-  mlp_forward_wave(s, xs[wv], a, false);
   const int r = lane & 15, q = lane >> 4;
 #pragma unroll
-  for (int nt = 0; nt < 4; ++nt)
+  for (int nt = 0; nt < 4; ++nt) {
+    const f32x4 yt = mlp_forward_tile(s, xs[wv], nt);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) ys[wv][16 * nt + r][4 * q + j] = a.y[nt][j];
+    for (int j = 0; j < 4; ++j) ys[wv][16 * nt + r][4 * q + j] = yt[j];
+  }
   __syncthreads();
   float y[9];
 #pragma unroll
@@ -276,10 +276,10 @@ __device__ __forceinline__ double wrest(int i) {
   return (i % 3 == 1 ? 2.0 / 3.0 : 1.0 / 6.0) * (i / 3 == 1 ? 2.0 / 3.0 : 1.0 / 6.0);
 }
 
-// Pre-collision populations at node (x, y) pulled from the shifted float32 state A.
+// Pre-collision shifted values h_i = f_i - w_i at node (x, y) pulled from the state A.
 template <bool WALLS>
-__device__ __forceinline__ void pull9(const float* __restrict__ A, int nx, int ny, int64_t pitch,
-                                      int64_t plane, int x, int y, double (&f)[9]) {
+__device__ __forceinline__ void pull9h(const float* __restrict__ A, int nx, int ny, int64_t pitch,
+                                       int64_t plane, int x, int y, float (&h)[9]) {
   const int xs[3] = {x == nx - 1 ? 0 : x + 1, x, x == 0 ? nx - 1 : x - 1};
   const int ys[3] = {y == ny - 1 ? 0 : y + 1, y, y == 0 ? ny - 1 : y - 1};
   const int64_t self = (int64_t)y * pitch + x;
@@ -287,9 +287,18 @@ __device__ __forceinline__ void pull9(const float* __restrict__ A, int nx, int n
   for (int i = 0; i < 9; ++i) {
     const int ka = i % 3, kb = i / 3;
     const bool bounce = WALLS && ((kb == 2 && y == 0) || (kb == 0 && y == ny - 1));
-    const float h = bounce ? A[(8 - i) * plane + self] : A[i * plane + (int64_t)ys[kb] * pitch + xs[ka]];
-    f[i] = (double)h + wrest(i);
+    h[i] = bounce ? A[(8 - i) * plane + self] : A[i * plane + (int64_t)ys[kb] * pitch + xs[ka]];
   }
+}
+
+// Pre-collision populations at node (x, y) pulled from the shifted float32 state A.
+template <bool WALLS>
+__device__ __forceinline__ void pull9(const float* __restrict__ A, int nx, int ny, int64_t pitch,
+                                      int64_t plane, int x, int y, double (&f)[9]) {
+  float h[9];
+  pull9h<WALLS>(A, nx, ny, pitch, plane, x, y, h);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) f[i] = (double)h[i] + wrest(i);
 }
 
 template <bool WALLS>
@@ -321,7 +330,7 @@ k_bgk_d2q9_mlp(const float* __restrict__ A, float* __restrict__ B, int nx, int n
                int64_t plane, double omega, int rows, const float* __restrict__ wblob, double tol,
                unsigned long long* __restrict__ counters, double* __restrict__ partials) {
   __shared__ MlpLds s;
-  __shared__ short xs[4][64][16];
+  __shared__ __attribute__((aligned(16))) short xs[4][64][16];
   __shared__ float ys[4][64][16];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int r = lane & 15, q = lane >> 4;
@@ -335,11 +344,15 @@ k_bgk_d2q9_mlp(const float* __restrict__ A, float* __restrict__ B, int nx, int n
   unsigned fallbacks = 0;
   mlp_load_lds(wblob, s);
   for (int y = y0; y < yend; ++y) {
-    double f[9];
+    // the shifted float32 values are kept across the network (9 registers instead of 18)
+    float h[9];
     double rho = 1.0, ux = 0.0, uy = 0.0;
     float xf[12];
     if (valid) {
-      pull9<WALLS>(A, nx, ny, pitch, plane, x, y, f);
+      pull9h<WALLS>(A, nx, ny, pitch, plane, x, y, h);
+      double f[9];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) f[i] = (double)h[i] + wrest(i);
       rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
       ux = ((f[2] + f[5] + f[8]) - (f[0] + f[3] + f[6])) / rho;
       uy = ((f[6] + f[7] + f[8]) - (f[0] + f[1] + f[2])) / rho;
@@ -351,12 +364,12 @@ k_bgk_d2q9_mlp(const float* __restrict__ A, float* __restrict__ B, int nx, int n
 #pragma unroll
     for (int k = 0; k < 16; ++k) xs[wv][lane][k] = k < kIn ? f2bf(xf[k]) : (short)0;
     __syncthreads();
-    MlpAct a;
-    mlp_forward_wave(s, xs[wv], a, false);
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt)
+    for (int nt = 0; nt < 4; ++nt) {
+      const f32x4 yt = mlp_forward_tile(s, xs[wv], nt);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) ys[wv][16 * nt + r][4 * q + j] = a.y[nt][j];
+      for (int j = 0; j < 4; ++j) ys[wv][16 * nt + r][4 * q + j] = yt[j];
+    }
     __syncthreads();
     if (valid) {
       float yv[9];
@@ -370,8 +383,9 @@ k_bgk_d2q9_mlp(const float* __restrict__ A, float* __restrict__ B, int nx, int n
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         const double feq = rho * px[i % 3] * py[i / 3];
+        const double fi = (double)h[i] + wrest(i);
         fm[i] = feq + rho * (double)yv[i] * (1.0 / kSNeq);  // surrogate
-        fp[i] = f[i] + omega * (feq - f[i]);                // paper's collision
+        fp[i] = fi + omega * (feq - fi);                    // paper's collision
         err += (fm[i] - fp[i]) * (fm[i] - fp[i]);
         ref += (fp[i] - feq) * (fp[i] - feq);
       }

@@ -26,11 +26,8 @@ constexpr int oW1 = 0, oB1 = 768, oW2 = 832, oB2 = 4928, oW3 = 4992, oB3 = 5568;
 // input encoding scales (powers of two)
 constexpr float kSNeq = 1024.0f, kSU = 16.0f;
 
-__device__ __forceinline__ short f2bf(float f) {  // round to nearest even
-  uint32_t b = __float_as_uint(f);
-  b += 0x7FFFu + ((b >> 16) & 1u);
-  return (short)(b >> 16);
-}
+// float32 -> bfloat16, round to nearest even (lowered to v_cvt_pk_bf16_f32 on gfx950)
+__device__ __forceinline__ short f2bf(float f) { return __builtin_bit_cast(short, (__bf16)f); }
 __device__ __forceinline__ float bf2f(short h) {
   return __uint_as_float(((uint32_t)(uint16_t)h) << 16);
 }
@@ -49,15 +46,16 @@ __device__ __forceinline__ void gelu_and_grad(float z, float& g, float& dg) {
   g = 0.5f * z * (1.0f + th);
   dg = 0.5f * (1.0f + th) + 0.5f * z * (1.0f - th * th) * k * (1.0f + 3.0f * a * z * z);
 }
+// Forward-only form: (1 + tanh t)/2 = 1/(1 + exp(-2t)), so gelu(z) = z / (1 + exp(-2t)),
+// one exponential and one hardware reciprocal.
 __device__ __forceinline__ float gelu(float z) {
-  const float k = 0.7978845608028654f, a = 0.044715f;
-  const float t = k * (z + a * z * z * z);
-  const float e = __expf(2.0f * t);
-  return 0.5f * z * (2.0f - 2.0f / (1.0f + e));
+  const float k2 = 2.0f * 0.7978845608028654f, a = 0.044715f;
+  const float t2 = k2 * (z + a * z * z * z);
+  return z * __builtin_amdgcn_rcpf(1.0f + __expf(-t2));
 }
 
 // Shared weights of one workgroup (bfloat16, zero padded) and biases (float32).
-struct MlpLds {
+struct __attribute__((aligned(16))) MlpLds {
   short w1[kHid][16];    // W1 padded to 16 inputs
   short w2[kHid][kHid];
   short w3[16][kHid];    // W3 padded to 16 outputs
@@ -83,13 +81,11 @@ __device__ __forceinline__ void mlp_load_lds(const float* __restrict__ w, MlpLds
   for (int k = threadIdx.x; k < 16; k += blockDim.x) s.b3[k] = k < kOut ? w[oB3 + k] : 0.0f;
 }
 
+// Four consecutive bfloat16 values from LDS; p is 8-byte aligned at every call site (rows of
+// 16 or 64 elements, column offsets multiples of 4, arrays 16-byte aligned), which lets the
+// compiler emit one ds_read_b64 with an immediate offset instead of a per-load address register.
 __device__ __forceinline__ bf16x4 ld4(const short* p) {
-  bf16x4 v;
-  v[0] = p[0];
-  v[1] = p[1];
-  v[2] = p[2];
-  v[3] = p[3];
-  return v;
+  return *reinterpret_cast<const bf16x4*>(__builtin_assume_aligned(p, 8));
 }
 
 __device__ __forceinline__ f32x4 bias4(const float* b, int lane) {
@@ -155,6 +151,35 @@ __device__ __forceinline__ void mlp_forward_wave(const MlpLds& s, const short (*
     for (int k = 0; k < 4; ++k) acc = mfma16(w3a[k], a.h2[k][n], acc);
     a.y[n] = acc;
   }
+}
+
+// Forward pass of node tile n (16 samples) only: the activations of one tile stay in
+// registers (8 VGPRs per layer), which keeps the inference kernel's register count low.
+// Returns the output tile (C layout, rows 0..8 valid).
+__device__ __forceinline__ f32x4 mlp_forward_tile(const MlpLds& s, const short (*xs)[16], int n) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, q = lane >> 4;
+  const bf16x4 xb = ld4(&xs[16 * n + r][4 * q]);
+  bf16x4 h1[4], h2[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    f32x4 acc = bias4(s.b1 + 16 * m, lane);
+    acc = mfma16(ld4(&s.w1[16 * m + r][4 * q]), xb, acc);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) h1[m][j] = f2bf(gelu(acc[j]));
+  }
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    f32x4 acc = bias4(s.b2 + 16 * m, lane);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc = mfma16(ld4(&s.w2[16 * m + r][16 * k + 4 * q]), h1[k], acc);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) h2[m][j] = f2bf(gelu(acc[j]));
+  }
+  f32x4 acc = bias4(s.b3, lane);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) acc = mfma16(ld4(&s.w3[r][16 * k + 4 * q]), h2[k], acc);
+  return acc;
 }
 
 // Orthogonal projection of 9 outputs onto zero mass and zero momentum (D2Q9 order
