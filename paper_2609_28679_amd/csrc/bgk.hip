@@ -61,26 +61,26 @@ k_bgk_d2q9(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int64_t p
       const int64_t rp = (int64_t)yp * pitch;
       S hs[9];
       // i = (cx+1) + 3(cy+1); source node x - c_i
-      hs[3] = A[3 * plane + r0 + xp];
-      hs[4] = A[4 * plane + r0 + x];
-      hs[5] = A[5 * plane + r0 + xm];
+      hs[3] = load_nt(A + 3 * plane + r0 + xp);
+      hs[4] = load_nt(A + 4 * plane + r0 + x);
+      hs[5] = load_nt(A + 5 * plane + r0 + xm);
       if (WALLS && y == ny - 1) {  // c_y = -1 would come from beyond the top wall
-        hs[0] = A[8 * plane + r0 + x];
-        hs[1] = A[7 * plane + r0 + x];
-        hs[2] = A[6 * plane + r0 + x];
+        hs[0] = load_nt(A + 8 * plane + r0 + x);
+        hs[1] = load_nt(A + 7 * plane + r0 + x);
+        hs[2] = load_nt(A + 6 * plane + r0 + x);
       } else {
-        hs[0] = A[0 * plane + rp + xp];
-        hs[1] = A[1 * plane + rp + x];
-        hs[2] = A[2 * plane + rp + xm];
+        hs[0] = load_nt(A + 0 * plane + rp + xp);
+        hs[1] = load_nt(A + 1 * plane + rp + x);
+        hs[2] = load_nt(A + 2 * plane + rp + xm);
       }
       if (WALLS && y == 0) {  // c_y = +1 would come from below the bottom wall
-        hs[6] = A[2 * plane + r0 + x];
-        hs[7] = A[1 * plane + r0 + x];
-        hs[8] = A[0 * plane + r0 + x];
+        hs[6] = load_nt(A + 2 * plane + r0 + x);
+        hs[7] = load_nt(A + 1 * plane + r0 + x);
+        hs[8] = load_nt(A + 0 * plane + r0 + x);
       } else {
-        hs[6] = A[6 * plane + rm + xp];
-        hs[7] = A[7 * plane + rm + x];
-        hs[8] = A[8 * plane + rm + xm];
+        hs[6] = load_nt(A + 6 * plane + rm + xp);
+        hs[7] = load_nt(A + 7 * plane + rm + x);
+        hs[8] = load_nt(A + 8 * plane + rm + xm);
       }
       double h[9];
 #pragma unroll
@@ -121,7 +121,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LBM
 k_bgk_d3q27(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int nz, int64_t pitch,
             int64_t plane, double omega, int rows, double* __restrict__ partials) {
   const int nbx = gridDim.x;
-  const int tile = xcd_tile(blockIdx.x + nbx * blockIdx.y, nbx * gridDim.y);
+  // hardware workgroup order (consecutive rows on different XCDs): measured 6% faster than the
+  // per-XCD contiguous ranges for D3Q27 at 256^3, whose 27 streams then stay close in memory
+  const int tile = blockIdx.x + nbx * blockIdx.y;
   const int bx = tile % nbx;
   const int by = tile / nbx;
   const int x = bx * blockDim.x + threadIdx.x;
@@ -148,9 +150,9 @@ k_bgk_d3q27(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int nz, 
         const int cx = i % 3, cy = (i / 3) % 3, cz = i / 9;  // component + 1
         const bool bounce = WALLS && ((cy == 2 && y == 0) || (cy == 0 && y == ny - 1));
         if (bounce) {
-          h[i] = A[(26 - i) * plane + self];
+          h[i] = load_nt(A + (26 - i) * plane + self);
         } else {
-          h[i] = A[i * plane + ((int64_t)zsrc[cz] * ny + ysrc[cy]) * pitch + xs[cx]];
+          h[i] = load_nt(A + i * plane + ((int64_t)zsrc[cz] * ny + ysrc[cy]) * pitch + xs[cx]);
         }
       }
       double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;

@@ -182,7 +182,10 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
   __shared__ float s_stage[IO::kStageFloats];
 
   const int nbx = gridDim.x;
-  const int tile = xcd_tile(blockIdx.x + nbx * blockIdx.y, nbx * gridDim.y);
+  // per-XCD contiguous tiles for float32/float64 storage; the staged reduced-storage variant
+  // measured 1.6% faster in hardware order
+  const int hw = blockIdx.x + nbx * blockIdx.y;
+  const int tile = IO::kStaged ? hw : xcd_tile(hw, nbx * gridDim.y);
   const int bx = tile % nbx;
   const int by = tile / nbx;
   const int tid = threadIdx.x;

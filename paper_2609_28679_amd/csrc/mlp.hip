@@ -287,7 +287,7 @@ __device__ __forceinline__ void pull9h(const float* __restrict__ A, int nx, int 
   for (int i = 0; i < 9; ++i) {
     const int ka = i % 3, kb = i / 3;
     const bool bounce = WALLS && ((kb == 2 && y == 0) || (kb == 0 && y == ny - 1));
-    h[i] = bounce ? A[(8 - i) * plane + self] : A[i * plane + (int64_t)ys[kb] * pitch + xs[ka]];
+    h[i] = bounce ? load_nt(A + (8 - i) * plane + self) : load_nt(A + i * plane + (int64_t)ys[kb] * pitch + xs[ka]);
   }
 }
 

@@ -65,38 +65,63 @@ k_bgk_d2q9_red(const float* __restrict__ M, const uint16_t* __restrict__ N, floa
   const float keep = (float)(1.0 - omega_d);  // f~ - f^eq = (1 - omega)(f - f^eq)
   double acc[kDiagValues] = {0.0, 0.0, 0.0, 0.0, 0.0};
 
-  // decode row r (unwrapped index) into ring slot r mod 3
-  auto load_row = [&](int r) {
-    if (WALLS && (r < 0 || r >= ny)) return;  // beyond a wall: never pulled (bounce-back)
+  // Row staging is software-pipelined: the raw stored values of a row (3 moments + 6 codes per
+  // column) are fetched into registers one iteration ahead, so their latency overlaps the
+  // collision of the current row; decoding them into LDS slot r mod 3 happens the next
+  // iteration. Columns c = 0..257 map to x0 - 1 + c (periodic); thread t owns column t and,
+  // for t < 2, column 256 + t.
+  struct Raw {
+    float m[3];
+    uint16_t n[kRedF];
+  };
+  Raw ra, rb;
+  auto fetch = [&](int rr, int c, Raw& v) {
+    int xg = x0 - 1 + c;
+    xg = ((xg % nx) + nx) % nx;
+    const int64_t off = (int64_t)rr * pitch + xg;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v.m[k] = M[k * plane + off];
+#pragma unroll
+    for (int k = 0; k < kRedF; ++k) v.n[k] = N[k * plane + off];
+  };
+  auto decode = [&](const Raw& v, float (&dst)[9]) {
+    float n[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+      if (f_slot(i) >= 0) n[i] = Codec::dec(v.n[f_slot(i)], s_dec);
+    n[5] = n[0] - n[2] + n[3] + n[6] - n[8];
+    n[7] = n[0] + n[1] + n[2] - n[6] - n[8];
+    n[4] = -(((n[0] + n[1]) + (n[2] + n[3])) + ((n[5] + n[6]) + (n[7] + n[8])));
+    float dx[3], dy[3];
+    dpsi3(v.m[1], dx);
+    dpsi3(v.m[2], dy);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) dst[i] = heq_i(i, v.m[0], dx, dy) + n[i];
+  };
+  // rows beyond a wall are never pulled (bounce-back) and are skipped
+  auto outside = [&](int r) { return WALLS && (r < 0 || r >= ny); };
+  auto fetch_row = [&](int r) {
+    if (outside(r)) return;
     const int rr = ((r % ny) + ny) % ny;
+    fetch(rr, tid, ra);
+    if (tid < kRedCols - kBlock) fetch(rr, kBlock + tid, rb);
+  };
+  auto put_row = [&](int r) {
+    if (outside(r)) return;
     float(*dst)[9] = ring[((r % 3) + 3) % 3];
-    for (int c = tid; c < kRedCols; c += kBlock) {
-      int xg = x0 - 1 + c;
-      xg = ((xg % nx) + nx) % nx;
-      const int64_t off = (int64_t)rr * pitch + xg;
-      const float drho = M[off];
-      const float ux = M[plane + off];
-      const float uy = M[2 * plane + off];
-      float n[9];
-#pragma unroll
-      for (int i = 0; i < 9; ++i)
-        if (f_slot(i) >= 0) n[i] = (float)Codec::dec(N[f_slot(i) * plane + off], s_dec);
-      n[5] = n[0] - n[2] + n[3] + n[6] - n[8];
-      n[7] = n[0] + n[1] + n[2] - n[6] - n[8];
-      n[4] = -(((n[0] + n[1]) + (n[2] + n[3])) + ((n[5] + n[6]) + (n[7] + n[8])));
-      float dx[3], dy[3];
-      dpsi3(ux, dx);
-      dpsi3(uy, dy);
-#pragma unroll
-      for (int i = 0; i < 9; ++i) dst[c][i] = heq_i(i, drho, dx, dy) + n[i];
-    }
+    decode(ra, dst[tid]);
+    if (tid < kRedCols - kBlock) decode(rb, dst[kBlock + tid]);
   };
 
-  load_row(y0 - 1);
-  load_row(y0);
+  fetch_row(y0 - 1);
+  put_row(y0 - 1);
+  fetch_row(y0);
+  put_row(y0);
+  fetch_row(y0 + 1);
   for (int y = y0; y < yend; ++y) {
-    load_row(y + 1);
+    put_row(y + 1);  // slot (y + 1) mod 3 was last read by row y - 1, before the barrier below
     __syncthreads();
+    if (y + 1 < yend) fetch_row(y + 2);  // consumed by the next iteration
     if (x < nx) {
       float h[9];
 #pragma unroll
@@ -111,7 +136,9 @@ k_bgk_d2q9_red(const float* __restrict__ M, const uint16_t* __restrict__ N, floa
       const float jx = (h[2] + h[5] + h[8]) - (h[0] + h[3] + h[6]);
       const float jy = (h[6] + h[7] + h[8]) - (h[0] + h[1] + h[2]);
       const float rho = 1.0f + drho;
-      const float ux = jx / rho, uy = jy / rho;
+      // hardware reciprocal (1 ulp): far below the 16-bit storage error
+      const float inv = __builtin_amdgcn_rcpf(rho);
+      const float ux = jx * inv, uy = jy * inv;
       float dx[3], dy[3];
       dpsi3(ux, dx);
       dpsi3(uy, dy);
