@@ -47,7 +47,9 @@ struct IoFull {
   const S* A;
   S* B;
   int64_t plane;
-  __device__ __forceinline__ void stage(float*, int, int, int, int, int64_t, int, const DdfParams&) const {}
+  struct RawRow {};
+  __device__ __forceinline__ void fetch_row(RawRow&, int, int, int, int, int64_t, int) const {}
+  __device__ __forceinline__ void put_row(float*, const RawRow&, int, int, int, const DdfParams&) const {}
   __device__ __forceinline__ void gather(bool pull, int64_t r0, int64_t rm, int64_t rp, int x,
                                          int xm, int xp, bool top, bool bot, const DdfParams&,
                                          int, int, const float*, S (&hf)[9], S (&hg)[9]) const {
@@ -102,36 +104,60 @@ struct IoRed {
   static constexpr bool kStaged = true;
   static constexpr int kCols = kBlock + 2, kStride = 19;
   static constexpr int kStageFloats = 3 * kCols * kStride;
-  __device__ __forceinline__ void stage(float* st, int r, int ny, int nx, int x_first,
-                                        int64_t pitch, int walls, const DdfParams& p) const {
-    if (walls && (r < 0 || r >= ny)) return;  // beyond a wall: never pulled (bounce-back)
-    const int rr = ((r % ny) + ny) % ny;
-    float* dst = st + ((r % 3) + 3) % 3 * (kCols * kStride);
-    for (int c = threadIdx.x; c < kCols; c += kBlock) {
-      const int xg = (((x_first + c) % nx) + nx) % nx;
-      const int64_t off = (int64_t)rr * pitch + xg;
-      const double rho = 1.0 + (double)M[off];
-      const double ux = (double)M[plane + off];
-      const double uy = (double)M[2 * plane + off];
-      const double T = 1.0 + (double)M[3 * plane + off];
-      double nf[9], ng[9];
+  // Raw stored values of one column (4 moments, 6 f codes, 8 g codes) and of the columns one
+  // thread stages: column t and, for t < 2, column 256 + t.
+  struct Raw {
+    float m[4];
+    uint16_t n[kRedF + kRedG];
+  };
+  struct RawRow {
+    Raw a, b;
+  };
+  __device__ __forceinline__ void fetch(Raw& v, int rr, int c, int nx, int64_t pitch) const {
+    const int xg = ((c % nx) + nx) % nx;
+    const int64_t off = (int64_t)rr * pitch + xg;
 #pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        if (f_slot(i) >= 0) nf[i] = (double)Codec::dec(N[f_slot(i) * plane + off], s_dec);
-        if (g_slot(i) >= 0) ng[i] = (double)Codec::dec(N[(kRedF + g_slot(i)) * plane + off], s_dec);
-      }
-      nf[5] = nf[0] - nf[2] + nf[3] + nf[6] - nf[8];
-      nf[7] = nf[0] + nf[1] + nf[2] - nf[6] - nf[8];
-      nf[4] = -(((nf[0] + nf[1]) + (nf[2] + nf[3])) + ((nf[5] + nf[6]) + (nf[7] + nf[8])));
-      ng[4] = -(((ng[0] + ng[1]) + (ng[2] + ng[3])) + ((ng[5] + ng[6]) + (ng[7] + ng[8])));
-      double fe[9], ge[9];
-      equilibria(rho, ux, uy, p.R * T, p.cv * T, fe, ge);
+    for (int k = 0; k < 4; ++k) v.m[k] = M[k * plane + off];
 #pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        dst[c * kStride + i] = (float)(fe[i] - p.wf[i] + nf[i]);
-        dst[c * kStride + 9 + i] = (float)(ge[i] - p.wg[i] + ng[i]);
-      }
+    for (int k = 0; k < kRedF + kRedG; ++k) v.n[k] = N[k * plane + off];
+  }
+  __device__ __forceinline__ void decode(const Raw& v, float* dst, const DdfParams& p) const {
+    const double rho = 1.0 + (double)v.m[0];
+    const double ux = (double)v.m[1];
+    const double uy = (double)v.m[2];
+    const double T = 1.0 + (double)v.m[3];
+    double nf[9], ng[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      if (f_slot(i) >= 0) nf[i] = (double)Codec::dec(v.n[f_slot(i)], s_dec);
+      if (g_slot(i) >= 0) ng[i] = (double)Codec::dec(v.n[kRedF + g_slot(i)], s_dec);
     }
+    nf[5] = nf[0] - nf[2] + nf[3] + nf[6] - nf[8];
+    nf[7] = nf[0] + nf[1] + nf[2] - nf[6] - nf[8];
+    nf[4] = -(((nf[0] + nf[1]) + (nf[2] + nf[3])) + ((nf[5] + nf[6]) + (nf[7] + nf[8])));
+    ng[4] = -(((ng[0] + ng[1]) + (ng[2] + ng[3])) + ((ng[5] + ng[6]) + (ng[7] + ng[8])));
+    double fe[9], ge[9];
+    equilibria(rho, ux, uy, p.R * T, p.cv * T, fe, ge);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      dst[i] = (float)(fe[i] - p.wf[i] + nf[i]);
+      dst[9 + i] = (float)(ge[i] - p.wg[i] + ng[i]);
+    }
+  }
+  // rows beyond a wall are never pulled (bounce-back) and are not staged
+  __device__ __forceinline__ void fetch_row(RawRow& rw, int r, int ny, int nx, int x_first,
+                                            int64_t pitch, int walls) const {
+    if (walls && (r < 0 || r >= ny)) return;
+    const int rr = ((r % ny) + ny) % ny;
+    fetch(rw.a, rr, x_first + (int)threadIdx.x, nx, pitch);
+    if (threadIdx.x < kCols - kBlock) fetch(rw.b, rr, x_first + kBlock + (int)threadIdx.x, nx, pitch);
+  }
+  __device__ __forceinline__ void put_row(float* st, const RawRow& rw, int r, int ny, int walls,
+                                          const DdfParams& p) const {
+    if (walls && (r < 0 || r >= ny)) return;
+    float* dst = st + ((r % 3) + 3) % 3 * (kCols * kStride);
+    decode(rw.a, dst + threadIdx.x * kStride, p);
+    if (threadIdx.x < kCols - kBlock) decode(rw.b, dst + (kBlock + threadIdx.x) * kStride, p);
   }
   // pull of node (column tid + 1 of the staged rows, row r) from LDS
   __device__ __forceinline__ void gather(bool pull, int64_t, int64_t, int64_t, int, int, int,
@@ -161,11 +187,11 @@ struct IoRed {
     if (f_slot(i) >= 0) store_nt(No + f_slot(i) * plane + off, Codec::enc((float)(htf - hfe), s_enc));
     if (g_slot(i) >= 0) store_nt(No + (kRedF + g_slot(i)) * plane + off, Codec::enc((float)(htg - hge), s_enc));
   }
-  __device__ __forceinline__ void store_moments(int64_t off, const double (&m)[6], double R) const {
+  __device__ __forceinline__ void store_moments(int64_t off, const double (&m)[6], double inv_R) const {
     store_nt(Mo + off, (float)(m[0] - 1.0));
     store_nt(Mo + plane + off, (float)m[1]);
     store_nt(Mo + 2 * plane + off, (float)m[2]);
-    store_nt(Mo + 3 * plane + off, (float)(m[3] / R - 1.0));
+    store_nt(Mo + 3 * plane + off, (float)(m[3] * inv_R - 1.0));
   }
 };
 
@@ -203,10 +229,16 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
   double ring_m[H1][6];  // rho, u_x, u_y, theta, e, Phi_xx
   double acc[kDiagValues] = {0.0, 0.0, 0.0, 0.0, 0.0};
 
+  // Staged rows are software-pipelined: the raw values of row r + 2 are fetched into registers
+  // while row r is processed and decoded into LDS at the start of the next iteration.
   const int x_first = x0 - HALO - 1;  // first staged column
+  typename IO::RawRow raw;
   if (IO::kStaged) {
-    io.stage(s_stage, y0 - HALO - 1, ny, nx, x_first, pitch, WALLS, prm);
-    io.stage(s_stage, y0 - HALO, ny, nx, x_first, pitch, WALLS, prm);
+    io.fetch_row(raw, y0 - HALO - 1, ny, nx, x_first, pitch, WALLS);
+    io.put_row(s_stage, raw, y0 - HALO - 1, ny, WALLS, prm);
+    io.fetch_row(raw, y0 - HALO, ny, nx, x_first, pitch, WALLS);
+    io.put_row(s_stage, raw, y0 - HALO, ny, WALLS, prm);
+    io.fetch_row(raw, y0 - HALO + 1, ny, nx, x_first, pitch, WALLS);
   }
   for (int k = 0; k < count; k += H1) {
 #pragma unroll
@@ -214,8 +246,11 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
       const int w = k + j;                 // window index (block-uniform)
       const int r = y0 - HALO + w;         // row being gathered
       if (IO::kStaged) {
-        io.stage(s_stage, r + 1, ny, nx, x_first, pitch, WALLS, prm);
+        // slot (r + 1) mod 3 holds row r - 2, last read by the gather of row r - 1, which is
+        // ordered before this write by the barrier that follows that gather
+        io.put_row(s_stage, raw, r + 1, ny, WALLS, prm);
         __syncthreads();
+        io.fetch_row(raw, r + 2, ny, nx, x_first, pitch, WALLS);
       }
       const bool in_window = w < count;
       const bool row_real = in_window && (WALLS ? (r >= 0 && r < ny) : true);
@@ -258,7 +293,7 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
           d = upwind_or_central(px[tid - 2], px[tid - 1], px[tid], px[tid + 1], px[tid + 2],
                                 ring_m[j][1]);
         }
-        ring_m[j][5] = -d / ring_m[j][0];
+        ring_m[j][5] = -d;  // -d(phi_x)/dx; divided by rho at the collision
       }
       // ---- collide the row gathered HALO rows earlier -----------------------------------------
       const int c = r - HALO;
@@ -279,15 +314,20 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
             d = 0.5 * (q[3] - q[1]);
           else
             d = upwind_or_central(q[0], q[1], q[2], q[3], q[4], ring_m[sc][2]);
-          phyy = -d / ring_m[sc][0];
+          phyy = -d;
         }
-        const double phxx = prm.phi ? ring_m[sc][5] : 0.0;
+        double phxx = 0.0;
+        if (prm.phi) {  // Phi_aa = -(1/rho) d(phi_a)/da: one reciprocal for both axes
+          const double inv_rho = 1.0 / ring_m[sc][0];
+          phxx = ring_m[sc][5] * inv_rho;
+          phyy *= inv_rho;
+        }
         const int64_t off = (int64_t)cc * pitch + x;
         collide_ddf(ring_f[sc], ring_g[sc], ring_m[sc], phxx, phyy, prm,
                     [&](int i, double htf, double hfe, double htg, double hge) {
                       io.store(off, i, htf, hfe, htg, hge);
                     });
-        io.store_moments(off, ring_m[sc], prm.R);
+        io.store_moments(off, ring_m[sc], prm.inv_R);
         if (DIAG) {
           const double rho = ring_m[sc][0];
           acc[0] += rho;

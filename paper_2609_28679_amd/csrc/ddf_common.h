@@ -61,7 +61,7 @@ __device__ __forceinline__ void moments_closure(const double (&f)[9], const doub
   m.ux = jx * inv;
   m.uy = jy * inv;
   m.e = rE * inv - 0.5 * (m.ux * m.ux + m.uy * m.uy);  // c_v T
-  m.theta = p.R * (m.e / p.cv);
+  m.theta = p.r_cv * m.e;
 }
 
 // Pull of the nine populations of one distribution at node (x, row): f_i = A_i(x - c_i).

@@ -249,6 +249,8 @@ int lbm_create(const lbm_params* p, const double* rho0, const double* u0, const 
   c->planes = P.planes;
   c->dp.R = p->R;
   c->dp.cv = p->cv;
+  c->dp.r_cv = p->R / p->cv;
+  c->dp.inv_R = 1.0 / p->R;
   c->dp.mu = (p->tau - 0.5) * (1.0 / 3.0);  // mu = (tau - 1/2) P0 at the reference P0 = 1/3
   c->dp.phi = p->phi;
   c->L = P.L;

@@ -39,6 +39,8 @@ Grid make_grid(const Layout& L);
 struct DdfParams {
   double R;    // gas constant
   double cv;   // heat capacity at constant volume
+  double r_cv; // R / cv (theta = R T = (R / cv) e)
+  double inv_R;  // 1 / R (T = theta / R)
   double mu;   // dynamic shear viscosity; tau = mu / P per node
   int phi;     // 0: no Galilean correction, 1: central derivative, 2: upwind derivative
   // storage shift: f^eq and g^eq at rest at the reference state rho = 1, T = 1 (computed by
