@@ -57,6 +57,12 @@ extern "C" {
 #define LBM_COLLIDE_PLAIN 0 /* the paper's collision */
 #define LBM_COLLIDE_MLP 1   /* learned surrogate with per-node fallback to the paper's collision */
 
+/* Streaming layout of the population state (isothermal D2Q9 with FP32/FP64 storage and the
+   paper's collision; every other configuration uses two buffers). */
+#define LBM_STREAM_AUTO 0        /* one buffer when its size is at most 256 MiB, else two */
+#define LBM_STREAM_TWO_BUFFERS 1 /* pull from buffer A, write buffer B, swap */
+#define LBM_STREAM_ONE_BUFFER 2  /* in place, alternating two access patterns (half the memory) */
+
 typedef struct lbm_ctx lbm_ctx; /* opaque; owned by the library */
 
 typedef struct {
@@ -75,6 +81,8 @@ typedef struct {
   int32_t fp16_scale_log2; /* LBM_STORE_FP16: S in [0, 24]; stored value = (f - f^eq) * 2^S */
   int32_t diag_every;  /* > 0: every diag_every steps record float64 totals (mass, momentum,
                           energy) computed inside the step kernel; 0 = off */
+  int32_t streaming;   /* LBM_STREAM_*; LBM_STREAM_ONE_BUFFER is rejected where unsupported.
+                          The choice changes memory use and speed, not the results. */
   double mlp_tol;      /* LBM_COLLIDE_MLP fallback threshold (see lbm_set_mlp) */
   void* stream;        /* hipStream_t for all work of this context; NULL = null stream */
   void* workspace;     /* optional caller-owned device memory (>= lbm_workspace_size bytes,
@@ -83,10 +91,11 @@ typedef struct {
 } lbm_params;
 
 /* Fill p with defaults: D2Q9 BGK FP32 plain, 64 x 64 x 1, periodic, tau 0.8, R = 1/3,
-   c_v = 5/6, phi 1, S = 16, no diagnostics, tol 0.05, null stream, no workspace. */
+   c_v = 5/6, phi 1, S = 16, no diagnostics, automatic streaming layout, tol 0.05, null
+   stream, no workspace. */
 void lbm_default_params(lbm_params* p);
 
-/* Device bytes the context needs for p (population buffers A and B, reduction scratch,
+/* Device bytes the context needs for p (population buffers: one or two, reduction scratch,
    diagnostics history). Returns LBM_EINVAL for invalid parameters. */
 int lbm_workspace_size(const lbm_params* p, size_t* bytes);
 

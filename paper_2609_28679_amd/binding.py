@@ -17,6 +17,7 @@ LATTICES = {"D2Q9": 0, "D3Q27": 1}
 MODELS = {"bgk": 0, "ddf": 1}
 STORAGES = {"fp32": 0, "bf16": 1, "fp16": 2, "fp64": 3}
 COLLISIONS = {"plain": 0, "mlp": 1}
+STREAMINGS = {"auto": 0, "two": 1, "one": 2}
 MLP_NPARAM = 5577
 
 
@@ -33,7 +34,7 @@ class LbmParams(ctypes.Structure):
         ("nz", ctypes.c_int32), ("wall_y", ctypes.c_int32), ("tau", ctypes.c_double),
         ("R", ctypes.c_double), ("cv", ctypes.c_double), ("phi", ctypes.c_int32),
         ("fp16_scale_log2", ctypes.c_int32), ("diag_every", ctypes.c_int32),
-        ("mlp_tol", ctypes.c_double), ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
+        ("streaming", ctypes.c_int32), ("mlp_tol", ctypes.c_double), ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t),
     ]
 
@@ -117,7 +118,8 @@ class Lattice:
 
     def __init__(self, rho0, u0, T0=None, *, lattice="D2Q9", model="bgk", storage="fp32",
                  collision="plain", wall_y=False, tau=0.8, R=1.0 / 3.0, cv=5.0 / 6.0, phi=1,
-                 fp16_scale_log2=16, diag_every=0, mlp_tol=0.05, torch_workspace=True):
+                 fp16_scale_log2=16, diag_every=0, mlp_tol=0.05, streaming="auto",
+                 torch_workspace=True):
         torch = _torch()
         lib = load()
         rho0 = np.ascontiguousarray(rho0, dtype=np.float64)
@@ -144,6 +146,7 @@ class Lattice:
         p.tau, p.R, p.cv, p.phi = float(tau), float(R), float(cv), int(phi)
         p.fp16_scale_log2 = int(fp16_scale_log2)
         p.diag_every = int(diag_every)
+        p.streaming = STREAMINGS[streaming]
         p.mlp_tol = float(mlp_tol)
         p.stream = current_stream_handle()
         self._ws = None

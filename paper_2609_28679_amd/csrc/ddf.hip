@@ -195,6 +195,9 @@ struct IoRed {
   }
 };
 
+#ifndef LBM_DDF_PREFETCH
+#define LBM_DDF_PREFETCH 0
+#endif
 template <class IO, int HALO, bool WALLS, bool PULL, bool DIAG>
 __global__ void __launch_bounds__(kBlock)
 k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
@@ -240,6 +243,25 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
     io.put_row(s_stage, raw, y0 - HALO, ny, WALLS, prm);
     io.fetch_row(raw, y0 - HALO + 1, ny, nx, x_first, pitch, WALLS);
   }
+  // Pull of window row r (periodic in y unless walls) into hf, hg.
+  auto gather_row = [&](int r, S(&hf)[9], S(&hg)[9]) {
+    const int rr = WALLS ? r : ((r % ny) + ny) % ny;
+    const int ym = rr == 0 ? ny - 1 : rr - 1;
+    const int yp = rr == ny - 1 ? 0 : rr + 1;
+    const int64_t r0 = (int64_t)rr * pitch, rm = (int64_t)ym * pitch, rp = (int64_t)yp * pitch;
+    const bool top = WALLS && rr == ny - 1, bot = WALLS && rr == 0;
+    io.gather(PULL, r0, rm, rp, x, xm, xp, top, bot, prm, r, tid, s_stage, hf, hg);
+  };
+  // window row w exists (inside the window and, with walls, inside the lattice)
+  auto real_row = [&](int w) {
+    const int r = y0 - HALO + w;
+    return w < count && (WALLS ? (r >= 0 && r < ny) : true);
+  };
+  // Unstaged storage prefetches: the pull of row r + 1 is issued before the moments of row r,
+  // so its loads are in flight during the row's arithmetic and barriers.
+  constexpr bool kPrefetch = !IO::kStaged && (LBM_DDF_PREFETCH != 0);
+  S pf_f[9], pf_g[9];
+  if (kPrefetch && real_row(0)) gather_row(y0 - HALO, pf_f, pf_g);
   for (int k = 0; k < count; k += H1) {
 #pragma unroll
     for (int j = 0; j < H1; ++j) {
@@ -253,16 +275,20 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
         io.fetch_row(raw, r + 2, ny, nx, x_first, pitch, WALLS);
       }
       const bool in_window = w < count;
-      const bool row_real = in_window && (WALLS ? (r >= 0 && r < ny) : true);
-      const int rr = WALLS ? r : ((r % ny) + ny) % ny;
+      const bool row_real = real_row(w);
       double phx = 0.0, phy = 0.0;
       if (row_real) {
         // ---- gather (pull) ----------------------------------------------------------------
-        const int ym = rr == 0 ? ny - 1 : rr - 1;
-        const int yp = rr == ny - 1 ? 0 : rr + 1;
-        const int64_t r0 = (int64_t)rr * pitch, rm = (int64_t)ym * pitch, rp = (int64_t)yp * pitch;
-        const bool top = WALLS && rr == ny - 1, bot = WALLS && rr == 0;
-        io.gather(PULL, r0, rm, rp, x, xm, xp, top, bot, prm, r, tid, s_stage, ring_f[j], ring_g[j]);
+        if (kPrefetch) {
+#pragma unroll
+          for (int i = 0; i < 9; ++i) {
+            ring_f[j][i] = pf_f[i];
+            ring_g[j][i] = pf_g[i];
+          }
+          if (real_row(w + 1)) gather_row(r + 1, pf_f, pf_g);
+        } else {
+          gather_row(r, ring_f[j], ring_g[j]);
+        }
         // ---- moments and closure ------------------------------------------------------------
         double f[9], g[9];
 #pragma unroll

@@ -30,6 +30,7 @@ struct lbm_ctx {
   int codec = -1;    // reduced storage: 0 = bfloat16, 1 = float16 (scaled); -1 = none
   float s_enc = 1.0f, s_dec = 1.0f;
   int planes = 9;    // stored population planes per buffer
+  bool aa = false;   // one buffer, in place (isothermal D2Q9): layout alternates with t parity
   DdfParams dp{};
   Layout L{};
   Grid G{};
@@ -38,7 +39,7 @@ struct lbm_ctx {
   size_t ws_bytes = 0;
   bool own_ws = false;
   void* A = nullptr;  // post-collision populations of the current time
-  void* B = nullptr;
+  void* B = nullptr;  // second buffer of the two-buffer layout (NULL with one buffer)
   double* partials = nullptr;  // per-workgroup diagnostics partial sums
   int partial_slots = 0;
   double* history = nullptr;   // ring of kHistoryCap rows {t, totals[5]}
@@ -88,7 +89,7 @@ int hip_fail(lbm_ctx* c, hipError_t e, const char* where) {
 
 struct Plan {
   int D, Q, kind, planes, codec;
-  bool ddf;
+  bool ddf, aa;
   Layout L;
   Grid G;
   size_t elem;
@@ -122,6 +123,13 @@ int validate(const lbm_params* p, std::string& why) {
     return LBM_EINVAL;
   }
   if (!(p->mlp_tol >= 0.0)) { why = "mlp_tol must be >= 0"; return LBM_EINVAL; }
+  if (p->streaming < LBM_STREAM_AUTO || p->streaming > LBM_STREAM_ONE_BUFFER) { why = "unknown streaming layout"; return LBM_EINVAL; }
+  if (p->streaming == LBM_STREAM_ONE_BUFFER &&
+      (p->lattice != LBM_D2Q9 || p->model != LBM_MODEL_BGK || p->collision != LBM_COLLIDE_PLAIN ||
+       (p->storage != LBM_STORE_FP32 && p->storage != LBM_STORE_FP64))) {
+    why = "one-buffer streaming needs D2Q9, the isothermal model, the paper's collision and FP32 or FP64 storage";
+    return LBM_EINVAL;
+  }
   if (p->workspace && (reinterpret_cast<uintptr_t>(p->workspace) & 255u)) { why = "workspace must be 256-byte aligned"; return LBM_EINVAL; }
   return LBM_OK;
 }
@@ -144,6 +152,12 @@ void make_plan(const lbm_params* p, Plan& P) {
   else
     P.G = make_grid(P.L);
   P.partial_slots = std::max(P.G.blocks(), 1024);
+  // One in-place buffer where supported and either requested or small enough to stay in the
+  // 256 MB last-level cache (measured faster there, slower for larger lattices).
+  const bool aa_ok = P.D == 2 && !P.ddf && P.codec < 0 && p->collision == LBM_COLLIDE_PLAIN;
+  const size_t one_buffer = (size_t)P.planes * P.L.plane * P.elem;
+  P.aa = aa_ok && (p->streaming == LBM_STREAM_ONE_BUFFER ||
+                   (p->streaming == LBM_STREAM_AUTO && one_buffer <= ((size_t)256 << 20)));
   size_t off = 0;
   // reduced storage: float32 moment planes + uint16 non-equilibrium planes
   // (isothermal: 3 + 6, double distribution: 4 + 6 + 8)
@@ -151,7 +165,7 @@ void make_plan(const lbm_params* p, Plan& P) {
                                            : (size_t)P.L.plane * (3 * 4 + 6 * 2))
                                    : (size_t)P.planes * P.L.plane * P.elem;
   P.off_A = off; off = align_up(off + pop, 256);
-  P.off_B = off; off = align_up(off + pop, 256);
+  P.off_B = off; if (!P.aa) off = align_up(off + pop, 256);
   P.off_part = off; off = align_up(off + (size_t)P.partial_slots * kDiagValues * 8, 256);
   P.off_hist = off; off = align_up(off + (size_t)kHistoryCap * 6 * 8, 256);
   P.off_read = off; off = align_up(off + (size_t)P.L.nodes() * (P.D + 3) * 8, 256);
@@ -160,6 +174,9 @@ void make_plan(const lbm_params* p, Plan& P) {
   P.off_mlp = off; off = align_up(off + 256 + (size_t)kMlpParams * 4, 256);
   P.total = off;
 }
+
+// Layout of the stored state for the read-out kernels: -1 two buffers, else the parity of t.
+int view_of(const lbm_ctx* c) { return c->aa ? (int)(c->t & 1) : -1; }
 
 // Product-form factors must be positive: Psi_0 = 1 - theta - u^2 > 0 and
 // Psi_+- = (theta + u^2 +- u)/2 > 0 for every component.
@@ -189,6 +206,7 @@ void lbm_default_params(lbm_params* p) {
   p->phi = 1;
   p->fp16_scale_log2 = 16;
   p->diag_every = 0;
+  p->streaming = LBM_STREAM_AUTO;
   p->mlp_tol = 0.05;
   p->stream = nullptr;
   p->workspace = nullptr;
@@ -247,6 +265,7 @@ int lbm_create(const lbm_params* p, const double* rho0, const double* u0, const 
     c->s_dec = std::ldexp(1.0f, -p->fp16_scale_log2);
   }
   c->planes = P.planes;
+  c->aa = P.aa;
   c->dp.R = p->R;
   c->dp.cv = p->cv;
   c->dp.r_cv = p->R / p->cv;
@@ -281,7 +300,7 @@ int lbm_create(const lbm_params* p, const double* rho0, const double* u0, const 
   }
   c->ws_bytes = P.total;
   c->A = c->ws + P.off_A;
-  c->B = c->ws + P.off_B;
+  c->B = P.aa ? nullptr : c->ws + P.off_B;
   c->partials = reinterpret_cast<double*>(c->ws + P.off_part);
   c->history = reinterpret_cast<double*>(c->ws + P.off_hist);
   c->readout = reinterpret_cast<double*>(c->ws + P.off_read);
@@ -315,7 +334,7 @@ int lbm_create(const lbm_params* p, const double* rho0, const double* u0, const 
   } else if (e == hipSuccess && c->codec >= 0) {
     e = launch_init_bgk_red(c->readout, c->readout + nodes, c->A, c->L, c->stream);
   } else if (e == hipSuccess) {
-    e = launch_init_bgk(c->kind, c->D, c->readout, c->readout + nodes, c->A, c->L, c->stream);
+    e = launch_init_bgk(c->kind, c->D, c->readout, c->readout + nodes, c->A, c->L, c->aa, c->stream);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
@@ -343,6 +362,8 @@ int lbm_step(lbm_ctx* c, int64_t n) {
       e = launch_ddf(c->fmt, c->p.wall_y != 0, true, c->A, c->B, c->L, c->G, c->dp, c->s_enc, c->s_dec, part, c->stream);
     else if (c->codec >= 0)
       e = launch_bgk_d2q9_red(c->codec, c->A, c->B, c->L, c->G, c->omega, c->p.wall_y != 0, c->s_enc, c->s_dec, part, c->stream);
+    else if (c->aa)
+      e = launch_bgk_d2q9_aa(c->kind, (c->t & 1) != 0, c->A, c->L, c->G, c->omega, c->p.wall_y != 0, part, c->stream);
     else if (c->D == 2)
       e = launch_bgk_d2q9(c->kind, c->A, c->B, c->L, c->G, c->omega, c->p.wall_y != 0, part, c->stream);
     else
@@ -354,7 +375,7 @@ int lbm_step(lbm_ctx* c, int64_t n) {
       if (e != hipSuccess) return hip_fail(c, e, "diagnostics launch");
       ++c->hist_written;
     }
-    std::swap(c->A, c->B);
+    if (!c->aa) std::swap(c->A, c->B);
     c->t = tn;
   }
   if (c->hist_written > hist_before) {
@@ -396,7 +417,7 @@ int lbm_moments(lbm_ctx* c, double* rho, double* u, double* T, double* totals) {
   else if (c->codec >= 0)
     HIP_TRY(c, launch_moments_bgk_red(c->A, c->L, d_rho, d_u, c->stream));
   else
-    HIP_TRY(c, launch_moments_bgk(c->kind, c->D, c->A, c->L, d_rho, d_u, c->stream));
+    HIP_TRY(c, launch_moments_bgk(c->kind, c->D, c->A, c->L, view_of(c), c->p.wall_y != 0, d_rho, d_u, c->stream));
   if (totals) {
     const int nparts = std::min(512, c->partial_slots - 2);
     double* out = c->partials + (size_t)nparts * kDiagValues;  // 6 doubles after the partials
@@ -425,7 +446,7 @@ int lbm_populations(lbm_ctx* c, double* f, double* g) {
     else if (c->codec >= 0)
       HIP_TRY(c, launch_decode_bgk_red(c->codec, i, c->A, c->L, c->s_dec, c->readout, c->stream));
     else
-      HIP_TRY(c, launch_decode_f(c->kind, c->D, i, c->A, c->L, c->readout, c->stream));
+      HIP_TRY(c, launch_decode_f(c->kind, c->D, i, c->A, c->L, view_of(c), c->p.wall_y != 0, c->readout, c->stream));
     HIP_TRY(c, hipMemcpyAsync(dst, c->readout, nodes * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
   }
@@ -488,7 +509,7 @@ int lbm_harvest(lbm_ctx* c, int64_t n, const int64_t* dev_nodes, float* dev_x, f
     return fail(c, LBM_EINVAL, "harvest needs a D2Q9 isothermal context with float32 storage");
   if (n < 0 || (n > 0 && (!dev_nodes || !dev_x || !dev_y))) return fail(c, LBM_EINVAL, "invalid harvest buffers");
   if (n == 0) return LBM_OK;
-  HIP_TRY(c, launch_harvest(c->A, c->L, c->p.wall_y != 0, c->omega, dev_nodes, n, dev_x, dev_y, c->stream));
+  HIP_TRY(c, launch_harvest(c->A, c->L, c->p.wall_y != 0, view_of(c), c->omega, dev_nodes, n, dev_x, dev_y, c->stream));
   return LBM_OK;
 }
 

@@ -55,13 +55,19 @@ hipError_t launch_bgk_d2q9(int kind, const void* A, void* B, const Layout& L, co
                            double omega, bool walls, double* partials, hipStream_t s);
 hipError_t launch_bgk_d3q27(int kind, const void* A, void* B, const Layout& L, const Grid& G,
                             double omega, bool walls, double* partials, hipStream_t s);
+// Single-buffer D2Q9 step (in place on A); odd = the step count so far is odd.
+hipError_t launch_bgk_d2q9_aa(int kind, bool odd, void* A, const Layout& L, const Grid& G,
+                              double omega, bool walls, double* partials, hipStream_t s);
+// swap: store population i in slot Q-1-i (single-buffer state at an even step count).
 hipError_t launch_init_bgk(int kind, int D, const double* rho, const double* u, void* A,
-                           const Layout& L, hipStream_t s);
-hipError_t launch_moments_bgk(int kind, int D, const void* A, const Layout& L, double* rho,
-                              double* u, hipStream_t s);
-// Population plane i of the stored state decoded to float64 f_i (nodes values, no padding).
-hipError_t launch_decode_f(int kind, int D, int i, const void* A, const Layout& L, double* f,
-                           hipStream_t s);
+                           const Layout& L, bool swap, hipStream_t s);
+// view: -1 two-buffer state; 0 / 1 single-buffer state after an even / odd step count.
+hipError_t launch_moments_bgk(int kind, int D, const void* A, const Layout& L, int view,
+                              bool walls, double* rho, double* u, hipStream_t s);
+// Post-collision population i of the stored state decoded to float64 f_i (nodes values, no
+// padding).
+hipError_t launch_decode_f(int kind, int D, int i, const void* A, const Layout& L, int view,
+                           bool walls, double* f, hipStream_t s);
 // Double-distribution kernels (D2Q9). Storage format fmt / kind: 0 float32, 1 float64 (planes
 // 0..8 hold f - w, 9..17 hold g - v); 2 bfloat16, 3 float16 reduced storage (4 float32 moment
 // planes, then 6 f and 8 g uint16 planes).
@@ -97,7 +103,7 @@ int mlp_partial_count(int B);  // partial gradient rows written by launch_mlp_gr
 hipError_t launch_mlp_reduce_adam(const float* partials, int nw, float* grad, float* loss, float* w,
                                   float* m, float* v, bool adam, float lr, int64_t t, hipStream_t s);
 hipError_t launch_mlp_forward(const float* X, int64_t n, const float* w, float* Y, hipStream_t s);
-hipError_t launch_harvest(const void* A, const Layout& L, bool walls, double omega,
+hipError_t launch_harvest(const void* A, const Layout& L, bool walls, int view, double omega,
                           const int64_t* nodes, int64_t n, float* X, float* Y, hipStream_t s);
 Grid make_grid_mlp(const Layout& L);
 hipError_t launch_bgk_d2q9_mlp(const void* A, void* B, const Layout& L, const Grid& G, double omega,

@@ -301,16 +301,44 @@ __device__ __forceinline__ void pull9(const float* __restrict__ A, int nx, int n
   for (int i = 0; i < 9; ++i) f[i] = (double)h[i] + wrest(i);
 }
 
+// Pre-collision populations of the next step at node (x, y) from a stored state of either
+// layout: view -1 two-buffer (pull of slot i from x - c_i), 0 single-buffer after an even step
+// count (slot 8-i of x - c_i; slot i of x where x - c_i lies beyond a wall), 1 single-buffer
+// after an odd step count (slot i of x, already streamed).
+template <bool WALLS>
+__device__ __forceinline__ void next_input9(const float* __restrict__ A, int nx, int ny,
+                                            int64_t pitch, int64_t plane, int view, int x, int y,
+                                            double (&f)[9]) {
+  if (view < 0) {
+    pull9<WALLS>(A, nx, ny, pitch, plane, x, y, f);
+    return;
+  }
+  const int xs[3] = {x == nx - 1 ? 0 : x + 1, x, x == 0 ? nx - 1 : x - 1};
+  const int ys[3] = {y == ny - 1 ? 0 : y + 1, y, y == 0 ? ny - 1 : y - 1};
+  const int64_t self = (int64_t)y * pitch + x;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int ka = i % 3, kb = i / 3;
+    const bool wall = WALLS && ((kb == 2 && y == 0) || (kb == 0 && y == ny - 1));
+    float h;
+    if (view == 1 || wall)
+      h = A[i * plane + self];
+    else
+      h = A[(8 - i) * plane + (int64_t)ys[kb] * pitch + xs[ka]];
+    f[i] = (double)h + wrest(i);
+  }
+}
+
 template <bool WALLS>
 __global__ void k_harvest(const float* __restrict__ A, int nx, int ny, int64_t pitch, int64_t plane,
-                          double omega, const int64_t* __restrict__ nodes, int64_t n,
+                          int view, double omega, const int64_t* __restrict__ nodes, int64_t n,
                           float* __restrict__ X, float* __restrict__ Y) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const int64_t node = nodes[k];
   const int x = (int)(node % nx), y = (int)(node / nx);
   double f[9];
-  pull9<WALLS>(A, nx, ny, pitch, plane, x, y, f);
+  next_input9<WALLS>(A, nx, ny, pitch, plane, view, x, y, f);
   const double rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
   const double ux = ((f[2] + f[5] + f[8]) - (f[0] + f[3] + f[6])) / rho;
   const double uy = ((f[6] + f[7] + f[8]) - (f[0] + f[1] + f[2])) / rho;
@@ -443,13 +471,13 @@ hipError_t launch_mlp_forward(const float* X, int64_t n, const float* w, float* 
   return hipGetLastError();
 }
 
-hipError_t launch_harvest(const void* A, const Layout& L, bool walls, double omega,
+hipError_t launch_harvest(const void* A, const Layout& L, bool walls, int view, double omega,
                           const int64_t* nodes, int64_t n, float* X, float* Y, hipStream_t s) {
   const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
   if (walls)
-    k_harvest<true><<<nb, kBlock, 0, s>>>(static_cast<const float*>(A), L.nx, L.ny, L.pitch, L.plane, omega, nodes, n, X, Y);
+    k_harvest<true><<<nb, kBlock, 0, s>>>(static_cast<const float*>(A), L.nx, L.ny, L.pitch, L.plane, view, omega, nodes, n, X, Y);
   else
-    k_harvest<false><<<nb, kBlock, 0, s>>>(static_cast<const float*>(A), L.nx, L.ny, L.pitch, L.plane, omega, nodes, n, X, Y);
+    k_harvest<false><<<nb, kBlock, 0, s>>>(static_cast<const float*>(A), L.nx, L.ny, L.pitch, L.plane, view, omega, nodes, n, X, Y);
   return hipGetLastError();
 }
 

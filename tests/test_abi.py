@@ -43,7 +43,9 @@ def test_default_params_and_workspace_size(lib):
     lib.lbm_default_params(ctypes.byref(p))
     assert (p.lattice, p.model, p.storage, p.nx, p.ny, p.nz) == (0, 0, 0, 64, 64, 1)
     assert p.tau == 0.8 and p.fp16_scale_log2 == 16
+    assert p.streaming == 0  # automatic layout
     nbytes = ctypes.c_size_t(0)
+    p.streaming = binding.STREAMINGS["two"]
     assert lib.lbm_workspace_size(ctypes.byref(p), ctypes.byref(nbytes)) == 0
     # two population buffers of 9 float32 planes at least
     assert nbytes.value >= 2 * 9 * 64 * 64 * 4
@@ -55,7 +57,8 @@ def test_default_params_and_workspace_size(lib):
 
 @pytest.mark.parametrize("field,value", [("tau", 0.5), ("tau", float("nan")), ("nx", 0),
                                           ("nz", 2), ("lattice", 7), ("wall_y", 2),
-                                          ("diag_every", -1)])
+                                          ("diag_every", -1), ("streaming", 3),
+                                          ("streaming", -1)])
 def test_invalid_params_rejected(lib, field, value):
     p = binding.LbmParams()
     lib.lbm_default_params(ctypes.byref(p))
@@ -93,3 +96,41 @@ def test_create_rejects_inadmissible_initial_state_before_device_work(lib):
 def test_null_context_is_a_state_error(lib):
     assert lib.lbm_step(None, 1) == binding.LBM_ESTATE
     lib.lbm_destroy(None)  # NULL-safe
+
+
+def _workspace(lib, **kw):
+    p = binding.LbmParams()
+    lib.lbm_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    n = ctypes.c_size_t(0)
+    rc = lib.lbm_workspace_size(ctypes.byref(p), ctypes.byref(n))
+    return rc, n.value
+
+
+def test_one_buffer_layout_halves_population_memory(lib):
+    one = binding.STREAMINGS["one"]
+    two = binding.STREAMINGS["two"]
+    auto = binding.STREAMINGS["auto"]
+    for storage, elem in (("fp32", 4), ("fp64", 8)):
+        st = binding.STORAGES[storage]
+        rc1, b1 = _workspace(lib, nx=1024, ny=1024, storage=st, streaming=one)
+        rc2, b2 = _workspace(lib, nx=1024, ny=1024, storage=st, streaming=two)
+        assert rc1 == rc2 == 0
+        assert b2 - b1 >= 9 * 1024 * 1024 * elem
+    # automatic choice: one buffer while it stays within 256 MiB, two beyond
+    _, small_auto = _workspace(lib, nx=2048, ny=2048, streaming=auto)
+    _, small_one = _workspace(lib, nx=2048, ny=2048, streaming=one)
+    _, big_auto = _workspace(lib, nx=4096, ny=4096, streaming=auto)
+    _, big_two = _workspace(lib, nx=4096, ny=4096, streaming=two)
+    assert small_auto == small_one and big_auto == big_two
+
+
+@pytest.mark.parametrize("kw", [dict(lattice=1, nz=4), dict(model=1),
+                                dict(storage=1), dict(storage=2), dict(collision=1)])
+def test_one_buffer_layout_rejected_where_unsupported(lib, kw):
+    rc, _ = _workspace(lib, streaming=binding.STREAMINGS["one"], **kw)
+    assert rc == binding.LBM_EINVAL
+    assert b"one-buffer" in lib.lbm_last_error(None)
+    rc, _ = _workspace(lib, streaming=binding.STREAMINGS["auto"], **kw)
+    assert rc == 0

@@ -56,15 +56,16 @@ def test_turbulence_fp32(tau):
     assert rel_l2(ug, uo) <= 1e-5
 
 
+@pytest.mark.parametrize("streaming,steps", [("two", 40), ("one", 40), ("one", 41)])
 @pytest.mark.parametrize("walls", [False, True])
 @pytest.mark.parametrize("nx,ny", [(100, 37), (300, 5), (3, 2), (1, 1), (70, 64)])
-def test_ragged_shapes_fp64_exact(nx, ny, walls):
-    announce("D2Q9 ragged %dx%d walls=%s fp64" % (nx, ny, walls))
+def test_ragged_shapes_fp64_exact(nx, ny, walls, streaming, steps):
+    announce("D2Q9 ragged %dx%d walls=%s fp64 %s buffer(s) %d steps" % (nx, ny, walls, streaming, steps))
     rng = np.random.default_rng(nx * 1000 + ny)
     rho = 1.0 + 0.02 * rng.standard_normal((ny, nx))
     u = 0.03 * rng.standard_normal((2, ny, nx))
-    rg, ug, _ = _gpu_run(rho, u, 0.7, 40, storage="fp64", wall_y=walls)
-    ro, uo = _oracle(rho, u, 0.7, 40, walls)
+    rg, ug, _ = _gpu_run(rho, u, 0.7, steps, storage="fp64", wall_y=walls, streaming=streaming)
+    ro, uo = _oracle(rho, u, 0.7, steps, walls)
     assert np.abs(rg - ro).max() <= 1e-13
     assert np.abs(ug - uo).max() <= 1e-13
 
@@ -120,11 +121,12 @@ def _one_step_full_size(lat, tau, walls=False):
     return f_next, expect
 
 
-@pytest.mark.parametrize("n", [2048, 4096])
-def test_full_size_single_step_elementwise(n):
-    announce("D2Q9 full size %d^2 single-step elementwise fp32" % n)
+@pytest.mark.parametrize("n,streaming", [(2048, "auto"), (2048, "two"), (4096, "auto"),
+                                         (4096, "one")])
+def test_full_size_single_step_elementwise(n, streaming):
+    announce("D2Q9 full size %d^2 single-step elementwise fp32 (%s layout)" % (n, streaming))
     rho, u = inputs.random_phase_turbulence_2d(n, seed=0)
-    lat = _lattice(rho, u, tau=0.6)
+    lat = _lattice(rho, u, tau=0.6, streaming=streaming)
     lat.step(20)
     got, expect = _one_step_full_size(lat, 0.6)
     lat.close()

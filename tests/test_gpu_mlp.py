@@ -147,3 +147,35 @@ def test_training_and_surrogate_gain_and_parity():
     assert res["trained"][0] < res["untrained"][0]
     assert res["trained"][0] < 0.5
     assert res["trained"][1] <= 1e-2
+
+
+def test_full_size_surrogate_step_sampled():
+    announce("surrogate 2048^2 one step (no fallback) vs oracle network at sampled nodes")
+    b = _binding()
+    from oracle.equilibrium import feq
+    from oracle.lattice import VARSIGMA2
+    n, tau = 2048, 0.6
+    rho, u = inputs.random_phase_turbulence_2d(n, seed=5)
+    blob = b.pack_mlp(inputs.mlp_init(11))
+    lat = b.Lattice(rho, u, tau=tau, collision="mlp")
+    lat.set_mlp(blob, 1e30)  # the judge never rejects: every node takes the network output
+    lat.step(3)
+    f_post, _ = lat.populations()
+    lat.step(1)
+    f_next, _ = lat.populations()
+    fb, up = lat.mlp_stats()
+    lat.close()
+    assert fb == 0 and up == 4 * n * n
+    idx = np.random.default_rng(4).choice(n * n, 20000, replace=False)
+    pre = bgk.stream(f_post).reshape(9, -1)[:, idx].T
+    got = f_next.reshape(9, -1)[:, idx].T
+    omega = np.full(idx.size, 1 / tau)
+    exp, fallback = mlp.surrogate_collide(b.unpack_mlp(blob), pre, omega, 1e30, bf16=True)
+    assert not fallback.any()
+    r, v = pre.sum(axis=1), np.stack([pre[:, [2, 5, 8]].sum(1) - pre[:, [0, 3, 6]].sum(1),
+                                      pre[:, [6, 7, 8]].sum(1) - pre[:, [0, 1, 2]].sum(1)])
+    fe = feq(r, v / r, VARSIGMA2).T
+    # network outputs agree to the bfloat16 activation roundings (forward test: 2e-3); mass
+    # and momentum of the output are those of the input on both sides
+    assert rel_l2(got - fe, exp - fe) <= 5e-3
+    np.testing.assert_allclose(got.sum(axis=1), r, rtol=0, atol=2e-6)
