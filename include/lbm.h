@@ -59,7 +59,7 @@ extern "C" {
 
 /* Streaming layout of the population state (isothermal D2Q9 with FP32/FP64 storage and the
    paper's collision; every other configuration uses two buffers). */
-#define LBM_STREAM_AUTO 0        /* one buffer when its size is at most 256 MiB, else two */
+#define LBM_STREAM_AUTO 0        /* one buffer when its size is at most 384 MiB, else two */
 #define LBM_STREAM_TWO_BUFFERS 1 /* pull from buffer A, write buffer B, swap */
 #define LBM_STREAM_ONE_BUFFER 2  /* in place, alternating two access patterns (half the memory) */
 

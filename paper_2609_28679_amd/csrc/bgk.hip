@@ -125,6 +125,25 @@ k_bgk_d2q9(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int64_t p
 // so the update is race-free without barriers. The state that fits the 256 MB last-level
 // cache at 2048^2 (151 MB in float32) stays resident there: measured 11% faster than the
 // two-buffer kernel at 2048^2, 12% slower at 4096^2, so the context picks it by size.
+// The state is read again by the next step, so loads and stores keep the default cache policy
+// (non-temporal hints measured slower here).
+template <typename T>
+__device__ __forceinline__ T aa_load(const T* p) {
+#if defined(LBM_AA_NT_LOADS)
+  return __builtin_nontemporal_load(p);
+#else
+  return *p;
+#endif
+}
+template <typename T>
+__device__ __forceinline__ void aa_store(T* p, T v) {
+#if defined(LBM_AA_NT_STORES)
+  __builtin_nontemporal_store(v, p);
+#else
+  *p = v;
+#endif
+}
+
 template <typename S, bool WALLS, bool DIAG, bool ODD>
 __global__ void __launch_bounds__(kBlock)
 k_bgk_d2q9_aa(S* __restrict__ A, int nx, int ny, int64_t pitch, int64_t plane, double omega,
@@ -164,9 +183,9 @@ k_bgk_d2q9_aa(S* __restrict__ A, int nx, int ny, int64_t pitch, int64_t plane, d
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         if (ODD)
-          hs[i] = A[i * plane + r0 + x];
+          hs[i] = aa_load(A + i * plane + r0 + x);
         else
-          hs[i] = wall_in[i] ? A[i * plane + r0 + x] : A[(8 - i) * plane + src[i]];
+          hs[i] = aa_load(wall_in[i] ? A + i * plane + r0 + x : A + (8 - i) * plane + src[i]);
       }
       double h[9];
 #pragma unroll
@@ -184,10 +203,10 @@ k_bgk_d2q9_aa(S* __restrict__ A, int nx, int ny, int64_t pitch, int64_t plane, d
         const double heq = rho * px[i % 3] * py[i / 3] - w1(i % 3) * w1(i / 3);
         const S v = (S)(h[i] + omega * (heq - h[i]));
         if (ODD) {
-          A[(8 - i) * plane + r0 + x] = v;
+          aa_store(A + (8 - i) * plane + r0 + x, v);
         } else {
           // destination x + c_i is the source of the opposite direction, x - c_(8-i)
-          A[wall_in[8 - i] ? (8 - i) * plane + r0 + x : i * plane + src[8 - i]] = v;
+          aa_store(A + (wall_in[8 - i] ? (8 - i) * plane + r0 + x : i * plane + src[8 - i]), v);
         }
       }
       if (DIAG) {

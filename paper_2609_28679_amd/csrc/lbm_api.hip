@@ -152,12 +152,14 @@ void make_plan(const lbm_params* p, Plan& P) {
   else
     P.G = make_grid(P.L);
   P.partial_slots = std::max(P.G.blocks(), 1024);
-  // One in-place buffer where supported and either requested or small enough to stay in the
-  // 256 MB last-level cache (measured faster there, slower for larger lattices).
+  // One in-place buffer where supported and either requested or small enough to profit from
+  // the 256 MB last-level cache. Measured float32 D2Q9 step times (one vs two buffers): 44 vs
+  // 51 us at 151 MB per buffer, 122 vs 131 us at 340 MB, equal at 399 MB, 235 vs 209 us at
+  // 604 MB; the crossover is taken as 384 MiB.
   const bool aa_ok = P.D == 2 && !P.ddf && P.codec < 0 && p->collision == LBM_COLLIDE_PLAIN;
   const size_t one_buffer = (size_t)P.planes * P.L.plane * P.elem;
   P.aa = aa_ok && (p->streaming == LBM_STREAM_ONE_BUFFER ||
-                   (p->streaming == LBM_STREAM_AUTO && one_buffer <= ((size_t)256 << 20)));
+                   (p->streaming == LBM_STREAM_AUTO && one_buffer <= ((size_t)384 << 20)));
   size_t off = 0;
   // reduced storage: float32 moment planes + uint16 non-equilibrium planes
   // (isothermal: 3 + 6, double distribution: 4 + 6 + 8)

@@ -118,7 +118,7 @@ def test_one_buffer_layout_halves_population_memory(lib):
         rc2, b2 = _workspace(lib, nx=1024, ny=1024, storage=st, streaming=two)
         assert rc1 == rc2 == 0
         assert b2 - b1 >= 9 * 1024 * 1024 * elem
-    # automatic choice: one buffer while it stays within 256 MiB, two beyond
+    # automatic choice: one buffer while it stays within 384 MiB, two beyond
     _, small_auto = _workspace(lib, nx=2048, ny=2048, streaming=auto)
     _, small_one = _workspace(lib, nx=2048, ny=2048, streaming=one)
     _, big_auto = _workspace(lib, nx=4096, ny=4096, streaming=auto)
