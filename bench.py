@@ -234,6 +234,11 @@ def main():
                 {"walls": "y", "phi": "central",
                  "storage": "fp32 moments + %s non-equilibrium (6 f + 8 g of 18 stored)" % st})
         del rs, us, ts
+        rho4, u4 = inputs.random_phase_turbulence_2d(n4, seed=0)
+        variants["d2q9_bgk_bf16_4096"] = variant(
+            "d2q9_bgk_bf16_4096", lambda: binding.Lattice(rho4, u4, tau=tau, storage="bf16"),
+            max(200, vs // 4), 20, 48, {"storage": "fp32 moments + bf16 f-f_eq (6 of 9 stored)"})
+        del rho4, u4
         for st in ("bf16", "fp16"):
             variants["d2q9_bgk_%s_2048" % st] = variant(
                 "d2q9_bgk_%s_2048" % st, lambda: binding.Lattice(rho, u, tau=tau, storage=st),
