@@ -57,8 +57,8 @@ extern "C" {
 #define LBM_COLLIDE_PLAIN 0 /* the paper's collision */
 #define LBM_COLLIDE_MLP 1   /* learned surrogate with per-node fallback to the paper's collision */
 
-/* Streaming layout of the population state (isothermal D2Q9 with FP32/FP64 storage and the
-   paper's collision; every other configuration uses two buffers). */
+/* Streaming layout of the population state (isothermal model, D2Q9 or D3Q27, with FP32/FP64
+   storage and the paper's collision; every other configuration uses two buffers). */
 #define LBM_STREAM_AUTO 0        /* one buffer when its size is at most 384 MiB, else two */
 #define LBM_STREAM_TWO_BUFFERS 1 /* pull from buffer A, write buffer B, swap */
 #define LBM_STREAM_ONE_BUFFER 2  /* in place, alternating two access patterns (half the memory) */

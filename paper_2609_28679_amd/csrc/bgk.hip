@@ -300,10 +300,91 @@ k_bgk_d3q27(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int nz, 
   if (DIAG) block_sum_store<kDiagValues>(acc, partials + (int64_t)tile * kDiagValues);
 }
 
+// ---- D3Q27, single buffer ----------------------------------------------------------------
+// The in-place two-step layout of k_bgk_d2q9_aa with 27 directions (slot Q-1-i = 26-i).
+template <typename S, bool WALLS, bool DIAG, bool ODD>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(ODD ? 3 : 2)))
+k_bgk_d3q27_aa(S* __restrict__ A, int nx, int ny, int nz, int64_t pitch, int64_t plane,
+               double omega, int rows, double* __restrict__ partials) {
+  const int nbx = gridDim.x;
+  const int tile = blockIdx.x + nbx * blockIdx.y;  // hardware order, as k_bgk_d3q27
+  const int bx = tile % nbx;
+  const int by = tile / nbx;
+  const int x = bx * blockDim.x + threadIdx.x;
+  const int r_begin = by * rows;
+  double acc[kDiagValues] = {0.0, 0.0, 0.0, 0.0, 0.0};
+
+  if (x < nx) {
+    int xs[3];
+    xs[0] = x == nx - 1 ? 0 : x + 1;  // c_x = -1: node x - c_x = x + 1
+    xs[1] = x;
+    xs[2] = x == 0 ? nx - 1 : x - 1;  // c_x = +1: node x - 1
+    const int r_end = min(r_begin + rows, ny * nz);
+    for (int r = r_begin; r < r_end; ++r) {
+      const int y = r % ny;
+      const int z = r / ny;
+      const int ysrc[3] = {y == ny - 1 ? 0 : y + 1, y, y == 0 ? ny - 1 : y - 1};
+      const int zsrc[3] = {z == nz - 1 ? 0 : z + 1, z, z == 0 ? nz - 1 : z - 1};
+      const int64_t self = ((int64_t)z * ny + y) * pitch + x;
+      // element offset of the node x - c_i, which is also the destination x + c_(26-i)
+      auto src = [&](int i) {
+        return ((int64_t)zsrc[i / 9] * ny + ysrc[(i / 3) % 3]) * pitch + xs[i % 3];
+      };
+      // x - c_i lies beyond a y wall
+      auto wall_in = [&](int i) {
+        const int cy = (i / 3) % 3;
+        return WALLS && ((cy == 2 && y == 0) || (cy == 0 && y == ny - 1));
+      };
+      S h[27];
+#pragma unroll
+      for (int i = 0; i < 27; ++i) {
+        if (ODD)
+          h[i] = aa_load(A + i * plane + self);
+        else
+          h[i] = aa_load(wall_in(i) ? A + i * plane + self : A + (26 - i) * plane + src(i));
+      }
+      double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+      for (int i = 0; i < 27; ++i) {
+        const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
+        const double v = (double)h[i];
+        drho += v;
+        if (cx) jx += cx > 0 ? v : -v;
+        if (cy) jy += cy > 0 ? v : -v;
+        if (cz) jz += cz > 0 ? v : -v;
+      }
+      const double rho = 1.0 + drho;
+      const double ux = jx / rho, uy = jy / rho, uz = jz / rho;
+      double px[3], py[3], pz[3];
+      psi3(ux, px);
+      psi3(uy, py);
+      psi3(uz, pz);
+#pragma unroll
+      for (int i = 0; i < 27; ++i) {
+        const int a = i % 3, b = (i / 3) % 3, c = i / 9;
+        const double heq = rho * px[a] * py[b] * pz[c] - w1(a) * w1(b) * w1(c);
+        const double v = (double)h[i];
+        const S o = (S)(v + omega * (heq - v));
+        if (ODD)
+          aa_store(A + (26 - i) * plane + self, o);
+        else
+          aa_store(wall_in(26 - i) ? A + (26 - i) * plane + self : A + i * plane + src(26 - i), o);
+      }
+      if (DIAG) {
+        acc[0] += rho;
+        acc[1] += jx;
+        acc[2] += jy;
+        acc[3] += jz;
+        acc[4] += 0.5 * rho * (ux * ux + uy * uy + uz * uz);
+      }
+    }
+  }
+  if (DIAG) block_sum_store<kDiagValues>(acc, partials + (int64_t)tile * kDiagValues);
+}
+
 // ---- initialisation and read-out -----------------------------------------------------------
-// f_i <- f_i^eq(rho, u) with theta = 1/3 (Fig. 1 initialisation), stored as h = f - w.
-// f <- f^eq of the initial fields, shifted; swap = 1 stores population i in slot Q-1-i (the
-// single-buffer state at an even step count).
+// f_i <- f_i^eq(rho, u) with theta = 1/3 (Fig. 1 initialisation), stored as h = f - w; swap = 1
+// stores population i in slot Q-1-i (the single-buffer state at an even step count).
 template <typename S>
 __global__ void k_init_bgk(int D, const double* __restrict__ rho, const double* __restrict__ u,
                            S* __restrict__ A, int nx, int ny, int nz, int64_t pitch,
@@ -468,7 +549,7 @@ Grid make_grid(const Layout& L) {
   int64_t rows = (nrows * G.nbx + target - 1) / target;
   rows = rows < 1 ? 1 : (rows > max_rows ? max_rows : rows);
   G.rows = (int)rows;
-  G.nby = (int)((nrows + rows - 1) / rows);
+  fit_rows(G, nrows);
   return G;
 }
 
@@ -548,6 +629,31 @@ hipError_t launch_bgk_d2q9_aa(int kind, bool odd, void* A, const Layout& L, cons
                               double omega, bool walls, double* partials, hipStream_t s) {
   return kind == 0 ? bgk2_aa<float>(A, L, G, omega, walls, odd, partials, s)
                    : bgk2_aa<double>(A, L, G, omega, walls, odd, partials, s);
+}
+
+template <typename R>
+static hipError_t bgk3_aa(void* A, const Layout& L, const Grid& G, double omega, bool walls,
+                          bool odd, double* partials, hipStream_t s) {
+  dim3 grid(G.nbx, G.nby), block(G.bx);
+  auto a = static_cast<R*>(A);
+#define LBM_AA_LAUNCH(W, D, O)                                                                \
+  k_bgk_d3q27_aa<R, W, D, O><<<grid, block, 0, s>>>(a, L.nx, L.ny, L.nz, L.pitch, L.plane, omega, \
+                                                    G.rows, partials)
+  if (walls) {
+    if (partials) { if (odd) LBM_AA_LAUNCH(true, true, true); else LBM_AA_LAUNCH(true, true, false); }
+    else { if (odd) LBM_AA_LAUNCH(true, false, true); else LBM_AA_LAUNCH(true, false, false); }
+  } else {
+    if (partials) { if (odd) LBM_AA_LAUNCH(false, true, true); else LBM_AA_LAUNCH(false, true, false); }
+    else { if (odd) LBM_AA_LAUNCH(false, false, true); else LBM_AA_LAUNCH(false, false, false); }
+  }
+#undef LBM_AA_LAUNCH
+  return hipGetLastError();
+}
+
+hipError_t launch_bgk_d3q27_aa(int kind, bool odd, void* A, const Layout& L, const Grid& G,
+                               double omega, bool walls, double* partials, hipStream_t s) {
+  return kind == 0 ? bgk3_aa<float>(A, L, G, omega, walls, odd, partials, s)
+                   : bgk3_aa<double>(A, L, G, omega, walls, odd, partials, s);
 }
 
 hipError_t launch_init_bgk(int kind, int D, const double* rho, const double* u, void* A,

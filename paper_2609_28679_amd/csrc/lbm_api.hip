@@ -30,7 +30,7 @@ struct lbm_ctx {
   int codec = -1;    // reduced storage: 0 = bfloat16, 1 = float16 (scaled); -1 = none
   float s_enc = 1.0f, s_dec = 1.0f;
   int planes = 9;    // stored population planes per buffer
-  bool aa = false;   // one buffer, in place (isothermal D2Q9): layout alternates with t parity
+  bool aa = false;   // one buffer, in place (isothermal model): layout alternates with t parity
   DdfParams dp{};
   Layout L{};
   Grid G{};
@@ -125,9 +125,9 @@ int validate(const lbm_params* p, std::string& why) {
   if (!(p->mlp_tol >= 0.0)) { why = "mlp_tol must be >= 0"; return LBM_EINVAL; }
   if (p->streaming < LBM_STREAM_AUTO || p->streaming > LBM_STREAM_ONE_BUFFER) { why = "unknown streaming layout"; return LBM_EINVAL; }
   if (p->streaming == LBM_STREAM_ONE_BUFFER &&
-      (p->lattice != LBM_D2Q9 || p->model != LBM_MODEL_BGK || p->collision != LBM_COLLIDE_PLAIN ||
+      (p->model != LBM_MODEL_BGK || p->collision != LBM_COLLIDE_PLAIN ||
        (p->storage != LBM_STORE_FP32 && p->storage != LBM_STORE_FP64))) {
-    why = "one-buffer streaming needs D2Q9, the isothermal model, the paper's collision and FP32 or FP64 storage";
+    why = "one-buffer streaming needs the isothermal model, the paper's collision and FP32 or FP64 storage";
     return LBM_EINVAL;
   }
   if (p->workspace && (reinterpret_cast<uintptr_t>(p->workspace) & 255u)) { why = "workspace must be 256-byte aligned"; return LBM_EINVAL; }
@@ -156,7 +156,7 @@ void make_plan(const lbm_params* p, Plan& P) {
   // the 256 MB last-level cache. Measured float32 D2Q9 step times (one vs two buffers): 44 vs
   // 51 us at 151 MB per buffer, 122 vs 131 us at 340 MB, equal at 399 MB, 235 vs 209 us at
   // 604 MB; the crossover is taken as 384 MiB.
-  const bool aa_ok = P.D == 2 && !P.ddf && P.codec < 0 && p->collision == LBM_COLLIDE_PLAIN;
+  const bool aa_ok = !P.ddf && P.codec < 0 && p->collision == LBM_COLLIDE_PLAIN;
   const size_t one_buffer = (size_t)P.planes * P.L.plane * P.elem;
   P.aa = aa_ok && (p->streaming == LBM_STREAM_ONE_BUFFER ||
                    (p->streaming == LBM_STREAM_AUTO && one_buffer <= ((size_t)384 << 20)));
@@ -364,8 +364,10 @@ int lbm_step(lbm_ctx* c, int64_t n) {
       e = launch_ddf(c->fmt, c->p.wall_y != 0, true, c->A, c->B, c->L, c->G, c->dp, c->s_enc, c->s_dec, part, c->stream);
     else if (c->codec >= 0)
       e = launch_bgk_d2q9_red(c->codec, c->A, c->B, c->L, c->G, c->omega, c->p.wall_y != 0, c->s_enc, c->s_dec, part, c->stream);
-    else if (c->aa)
+    else if (c->aa && c->D == 2)
       e = launch_bgk_d2q9_aa(c->kind, (c->t & 1) != 0, c->A, c->L, c->G, c->omega, c->p.wall_y != 0, part, c->stream);
+    else if (c->aa)
+      e = launch_bgk_d3q27_aa(c->kind, (c->t & 1) != 0, c->A, c->L, c->G, c->omega, c->p.wall_y != 0, part, c->stream);
     else if (c->D == 2)
       e = launch_bgk_d2q9(c->kind, c->A, c->B, c->L, c->G, c->omega, c->p.wall_y != 0, part, c->stream);
     else

@@ -31,6 +31,15 @@ struct Grid {
   int blocks() const { return nbx * nby; }
 };
 
+// Workgroups along the second grid dimension are kept within 65535 (the HIP launch limit on
+// this dimension): lattices with more rows give each workgroup more rows.
+constexpr int kMaxGridY = 65535;
+inline void fit_rows(Grid& G, int64_t nrows) {
+  if (G.rows < 1) G.rows = 1;
+  if ((nrows + G.rows - 1) / G.rows > kMaxGridY) G.rows = (int)((nrows + kMaxGridY - 1) / kMaxGridY);
+  G.nby = (int)((nrows + G.rows - 1) / G.rows);
+}
+
 // Population layout for elements of `elem` bytes (row pitch and padded plane stride).
 Layout make_layout(int nx, int ny, int nz, int elem);
 Grid make_grid(const Layout& L);
@@ -55,9 +64,11 @@ hipError_t launch_bgk_d2q9(int kind, const void* A, void* B, const Layout& L, co
                            double omega, bool walls, double* partials, hipStream_t s);
 hipError_t launch_bgk_d3q27(int kind, const void* A, void* B, const Layout& L, const Grid& G,
                             double omega, bool walls, double* partials, hipStream_t s);
-// Single-buffer D2Q9 step (in place on A); odd = the step count so far is odd.
+// Single-buffer steps (in place on A); odd = the step count so far is odd.
 hipError_t launch_bgk_d2q9_aa(int kind, bool odd, void* A, const Layout& L, const Grid& G,
                               double omega, bool walls, double* partials, hipStream_t s);
+hipError_t launch_bgk_d3q27_aa(int kind, bool odd, void* A, const Layout& L, const Grid& G,
+                               double omega, bool walls, double* partials, hipStream_t s);
 // swap: store population i in slot Q-1-i (single-buffer state at an even step count).
 hipError_t launch_init_bgk(int kind, int D, const double* rho, const double* u, void* A,
                            const Layout& L, bool swap, hipStream_t s);

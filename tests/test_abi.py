@@ -118,6 +118,10 @@ def test_one_buffer_layout_halves_population_memory(lib):
         rc2, b2 = _workspace(lib, nx=1024, ny=1024, storage=st, streaming=two)
         assert rc1 == rc2 == 0
         assert b2 - b1 >= 9 * 1024 * 1024 * elem
+    # D3Q27 too
+    rc3, b3 = _workspace(lib, lattice=1, nx=64, ny=64, nz=64, streaming=one)
+    rc4, b4 = _workspace(lib, lattice=1, nx=64, ny=64, nz=64, streaming=two)
+    assert rc3 == rc4 == 0 and b4 - b3 >= 27 * 64 ** 3 * 4
     # automatic choice: one buffer while it stays within 384 MiB, two beyond
     _, small_auto = _workspace(lib, nx=2048, ny=2048, streaming=auto)
     _, small_one = _workspace(lib, nx=2048, ny=2048, streaming=one)
@@ -126,8 +130,8 @@ def test_one_buffer_layout_halves_population_memory(lib):
     assert small_auto == small_one and big_auto == big_two
 
 
-@pytest.mark.parametrize("kw", [dict(lattice=1, nz=4), dict(model=1),
-                                dict(storage=1), dict(storage=2), dict(collision=1)])
+@pytest.mark.parametrize("kw", [dict(model=1), dict(storage=1), dict(storage=2),
+                                dict(collision=1)])
 def test_one_buffer_layout_rejected_where_unsupported(lib, kw):
     rc, _ = _workspace(lib, streaming=binding.STREAMINGS["one"], **kw)
     assert rc == binding.LBM_EINVAL

@@ -91,13 +91,15 @@ def test_d3q27_taylor_green(storage, tol):
     assert rel_l2(ug, uo) <= tol
 
 
+@pytest.mark.parametrize("streaming", ["two", "one"])
 @pytest.mark.parametrize("walls", [False, True])
-def test_d3q27_ragged_fp64(walls):
-    announce("D3Q27 ragged 9x7x5 walls=%s fp64" % walls)
+def test_d3q27_ragged_fp64(walls, streaming):
+    announce("D3Q27 ragged 9x7x5 walls=%s fp64 %s buffer(s)" % (walls, streaming))
     rng = np.random.default_rng(11)
     rho = 1.0 + 0.02 * rng.standard_normal((5, 7, 9))
     u = 0.03 * rng.standard_normal((3, 5, 7, 9))
-    rg, ug, _ = _gpu_run(rho, u, 0.7, 15, lattice="D3Q27", storage="fp64", wall_y=walls)
+    rg, ug, _ = _gpu_run(rho, u, 0.7, 15, lattice="D3Q27", storage="fp64", wall_y=walls,
+                         streaming=streaming)
     ro, uo = _oracle(rho, u, 0.7, 15, walls)
     assert np.abs(ug - uo).max() <= 1e-13
     assert np.abs(rg - ro).max() <= 1e-13
@@ -211,3 +213,31 @@ def test_zero_steps_returns_initial_moments():
     assert lat.t == 0
     lat.close()
     assert np.abs(r - rho).max() < 1e-14 and np.abs(v - u).max() < 1e-15
+
+
+@pytest.mark.parametrize("streaming", ["two", "one"])
+@pytest.mark.parametrize("walls", [False, True])
+def test_tall_lattice_more_rows_than_grid_limit(walls, streaming):
+    """70000 rows exceed the 65535 workgroups the launch allows along y: each workgroup then
+    takes several rows."""
+    announce("D2Q9 tall 3x70000 walls=%s fp64 %s buffer(s)" % (walls, streaming))
+    rng = np.random.default_rng(21)
+    ny, nx = 70000, 3
+    rho = 1.0 + 0.02 * rng.standard_normal((ny, nx))
+    u = 0.03 * rng.standard_normal((2, ny, nx))
+    rg, ug, _ = _gpu_run(rho, u, 0.7, 5, storage="fp64", wall_y=walls, streaming=streaming)
+    ro, uo = _oracle(rho, u, 0.7, 5, walls)
+    assert np.abs(rg - ro).max() <= 1e-13
+    assert np.abs(ug - uo).max() <= 1e-13
+
+
+def test_d3q27_tall_lattice_more_rows_than_grid_limit():
+    announce("D3Q27 tall 3x5x14000 (70000 rows) fp64")
+    rng = np.random.default_rng(22)
+    shape = (14000, 5, 3)
+    rho = 1.0 + 0.02 * rng.standard_normal(shape)
+    u = 0.03 * rng.standard_normal((3,) + shape)
+    rg, ug, _ = _gpu_run(rho, u, 0.7, 3, lattice="D3Q27", storage="fp64")
+    ro, uo = _oracle(rho, u, 0.7, 3)
+    assert np.abs(rg - ro).max() <= 1e-13
+    assert np.abs(ug - uo).max() <= 1e-13

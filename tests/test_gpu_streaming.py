@@ -1,7 +1,7 @@
-"""The one-buffer (in-place) and two-buffer streaming layouts of the isothermal D2Q9 path hold
+"""The one-buffer (in-place) and two-buffer streaming layouts of the isothermal path hold
 the same state in different places: every read-out (populations, moments, conservation
-history, surrogate training features) must agree bit for bit after even and odd step
-counts, with periodic and wall boundaries."""
+history, surrogate training features) must agree after even and odd step counts, with
+periodic and wall boundaries: bit for bit for D2Q9, to the last bits of float64 for D3Q27."""
 import numpy as np
 import pytest
 
@@ -19,24 +19,34 @@ def _pair(storage, walls, diag_every=0, shape=(45, 70), seed=3):
     from paper_2609_28679_amd.binding import Lattice
     rng = np.random.default_rng(seed)
     rho = 1.0 + 0.02 * rng.standard_normal(shape)
-    u = 0.03 * rng.standard_normal((2,) + shape)
-    kw = dict(tau=0.62, storage=storage, wall_y=walls, diag_every=diag_every)
+    u = 0.03 * rng.standard_normal((len(shape),) + shape)
+    kw = dict(tau=0.62, storage=storage, wall_y=walls, diag_every=diag_every,
+              lattice="D2Q9" if len(shape) == 2 else "D3Q27")
     return (Lattice(rho, u, streaming="two", **kw), Lattice(rho, u, streaming="one", **kw))
 
 
 @pytest.mark.parametrize("walls", [False, True])
 @pytest.mark.parametrize("storage", ["fp32", "fp64"])
-def test_layouts_bitwise_identical(storage, walls):
-    announce("D2Q9 one vs two buffers %s walls=%s, t = 0..7" % (storage, walls))
-    two, one = _pair(storage, walls)
+@pytest.mark.parametrize("shape", [(45, 70), (9, 7, 11)])
+def test_layouts_bitwise_identical(shape, storage, walls):
+    announce("%s one vs two buffers %s walls=%s, t = 0..7" % (shape, storage, walls))
+    two, one = _pair(storage, walls, shape=shape)
+
+    def same(a, b):
+        if len(shape) == 2:  # the D2Q9 kernels round identically: bit for bit
+            return np.array_equal(a, b)
+        # the two D3Q27 kernels may contract a different set of multiply-adds into FMAs, so
+        # float64 results can differ in the last bits; an indexing error would be O(1e-3)
+        return np.abs(a - b).max() <= 1e-14 * max(np.abs(b).max(), 1.0)
+
     for t in range(8):
         f2, _ = two.populations()
         f1, _ = one.populations()
-        assert np.array_equal(f1, f2), "populations differ at t = %d" % t
+        assert same(f1, f2), "populations differ at t = %d" % t
         r2, u2, _, tot2 = two.moments()
         r1, u1, _, tot1 = one.moments()
-        assert np.array_equal(r1, r2) and np.array_equal(u1, u2), "moments differ at t = %d" % t
-        assert np.array_equal(tot1, tot2)
+        assert same(r1, r2) and same(u1, u2), "moments differ at t = %d" % t
+        assert same(tot1, tot2)
         two.step(1)
         one.step(1)
     two.close()
