@@ -43,6 +43,7 @@ template <typename S>
 struct IoFull {
   using ring_t = S;
   static constexpr bool kStaged = false;
+  static constexpr int kEdge = 0;
   static constexpr int kStageFloats = 1;
   const S* A;
   S* B;
@@ -98,21 +99,20 @@ struct IoRed {
     hg = ge + neq_g<Codec>(N + kRedF * plane, plane, src, ii, s_dec) - p.wg[ii];
   }
   // Staging: the rows of the 3-row pull window are decoded once per workgroup into LDS,
-  // stage[slot][c][k] with c the column x_first + c (258 columns: the workgroup's 256 plus one
-  // on each side) and k = 0..8 f - w, 9..17 g - v (19 floats per column: an odd stride keeps
-  // the lanes on distinct LDS banks).
+  // stage[slot][c][k] with c = thread index, column x_first + c (one column per thread, so no
+  // wavefront decodes twice; the outermost thread on each side only stages) and k = 0..8
+  // f - w, 9..17 g - v (19 floats per column: an odd stride keeps the lanes on distinct LDS
+  // banks).
   static constexpr bool kStaged = true;
-  static constexpr int kCols = kBlock + 2, kStride = 19;
+  static constexpr int kEdge = 1;  // threads per side that stage but do not pull
+  static constexpr int kCols = kBlock, kStride = 19;
   static constexpr int kStageFloats = 3 * kCols * kStride;
-  // Raw stored values of one column (4 moments, 6 f codes, 8 g codes) and of the columns one
-  // thread stages: column t and, for t < 2, column 256 + t.
+  // Raw stored values of one column: 4 moments, 6 f codes, 8 g codes.
   struct Raw {
     float m[4];
     uint16_t n[kRedF + kRedG];
   };
-  struct RawRow {
-    Raw a, b;
-  };
+  using RawRow = Raw;
   __device__ __forceinline__ void fetch(Raw& v, int rr, int c, int nx, int64_t pitch) const {
     const int xg = ((c % nx) + nx) % nx;
     const int64_t off = (int64_t)rr * pitch + xg;
@@ -149,17 +149,15 @@ struct IoRed {
                                             int64_t pitch, int walls) const {
     if (walls && (r < 0 || r >= ny)) return;
     const int rr = ((r % ny) + ny) % ny;
-    fetch(rw.a, rr, x_first + (int)threadIdx.x, nx, pitch);
-    if (threadIdx.x < kCols - kBlock) fetch(rw.b, rr, x_first + kBlock + (int)threadIdx.x, nx, pitch);
+    fetch(rw, rr, x_first + (int)threadIdx.x, nx, pitch);
   }
   __device__ __forceinline__ void put_row(float* st, const RawRow& rw, int r, int ny, int walls,
                                           const DdfParams& p) const {
     if (walls && (r < 0 || r >= ny)) return;
     float* dst = st + ((r % 3) + 3) % 3 * (kCols * kStride);
-    decode(rw.a, dst + threadIdx.x * kStride, p);
-    if (threadIdx.x < kCols - kBlock) decode(rw.b, dst + (kBlock + threadIdx.x) * kStride, p);
+    decode(rw, dst + threadIdx.x * kStride, p);
   }
-  // pull of node (column tid + 1 of the staged rows, row r) from LDS
+  // pull of node (staged column tid, row r) from LDS; 1 <= tid <= kBlock - 2
   __device__ __forceinline__ void gather(bool pull, int64_t, int64_t, int64_t, int, int, int,
                                          bool top, bool bot, const DdfParams&, int r, int tid,
                                          const float* st, float (&hf)[9], float (&hg)[9]) const {
@@ -171,14 +169,14 @@ struct IoRed {
       const int ka = i % 3, kb = i / 3;
       const bool bounce = (kb == 2 && bot) || (kb == 0 && top);
       if (!pull) {
-        hf[i] = at(r, tid + 1, i);
-        hg[i] = at(r, tid + 1, 9 + i);
+        hf[i] = at(r, tid, i);
+        hg[i] = at(r, tid, 9 + i);
       } else if (bounce) {
-        hf[i] = at(r, tid + 1, 8 - i);
-        hg[i] = at(r, tid + 1, 17 - i);
+        hf[i] = at(r, tid, 8 - i);
+        hg[i] = at(r, tid, 17 - i);
       } else {
-        hf[i] = at(r - (kb - 1), tid + 1 - (ka - 1), i);
-        hg[i] = at(r - (kb - 1), tid + 1 - (ka - 1), 9 + i);
+        hf[i] = at(r - (kb - 1), tid - (ka - 1), i);
+        hg[i] = at(r - (kb - 1), tid - (ka - 1), 9 + i);
       }
     }
   }
@@ -205,7 +203,8 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
   using S = typename IO::ring_t;
   constexpr int H1 = HALO + 1;
   constexpr int P = 2 * HALO + 1;
-  constexpr int TXI = kBlock - 2 * HALO;
+  constexpr int EDGE = IO::kEdge;  // staging-only threads per side
+  constexpr int TXI = kBlock - 2 * HALO - 2 * EDGE;
   __shared__ double s_phix[2][kBlock];
   __shared__ double s_phiy[P][kBlock];
   __shared__ float s_stage[IO::kStageFloats];
@@ -219,9 +218,10 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
   const int by = tile / nbx;
   const int tid = threadIdx.x;
   const int x0 = bx * TXI;
-  const int xu = x0 - HALO + tid;                 // unwrapped column
+  const int xu = x0 - HALO - EDGE + tid;          // unwrapped column
   const int x = ((xu % nx) + nx) % nx;            // periodic in x
-  const bool own = tid >= HALO && tid < kBlock - HALO && xu < nx;
+  const bool own = tid >= HALO + EDGE && tid < kBlock - HALO - EDGE && xu < nx;
+  const bool puller = tid >= EDGE && tid < kBlock - EDGE;  // has all its pull sources
   const int xm = x == 0 ? nx - 1 : x - 1;
   const int xp = x == nx - 1 ? 0 : x + 1;
   const int y0 = by * rows;
@@ -234,7 +234,7 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
 
   // Staged rows are software-pipelined: the raw values of row r + 2 are fetched into registers
   // while row r is processed and decoded into LDS at the start of the next iteration.
-  const int x_first = x0 - HALO - 1;  // first staged column
+  const int x_first = x0 - HALO - EDGE;  // first staged column (thread 0's)
   typename IO::RawRow raw;
   if (IO::kStaged) {
     io.fetch_row(raw, y0 - HALO - 1, ny, nx, x_first, pitch, WALLS);
@@ -277,7 +277,7 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
       const bool in_window = w < count;
       const bool row_real = real_row(w);
       double phx = 0.0, phy = 0.0;
-      if (row_real) {
+      if (row_real && puller) {
         // ---- gather (pull) ----------------------------------------------------------------
         if (kPrefetch) {
 #pragma unroll
@@ -433,7 +433,9 @@ __global__ void k_ddf_rest_state(DdfParams prm, double* __restrict__ out) {
 Grid make_grid_ddf(const Layout& L, int halo, bool reduced) {
   Grid G;
   G.bx = kBlock;
-  const int txi = kBlock - 2 * halo;
+  // own columns per workgroup: kBlock - 2 halo, less one staging-only thread per side when
+  // the rows are staged (the kernel's TXI)
+  const int txi = kBlock - 2 * halo - (reduced ? 2 : 0);
   G.nbx = (L.nx + txi - 1) / txi;
   // rows per workgroup from a sweep on MI355X at 4096^2 (float32: 2 -> 588 us, 4 -> 553,
   // 16 -> 599; reduced bf16: 4 -> 967, 16 -> 736, 32 -> 739): short windows give more
@@ -442,7 +444,7 @@ Grid make_grid_ddf(const Layout& L, int halo, bool reduced) {
 #ifdef LBM_TUNING_ENV
   if (const char* v = getenv("LBM_DDF_ROWS")) G.rows = atoi(v);
 #endif
-  G.nby = (L.ny + G.rows - 1) / G.rows;
+  fit_rows(G, L.ny);
   return G;
 }
 
