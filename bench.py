@@ -163,6 +163,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--only", default="",
+                    help="comma-separated variant names to run (default: all)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -205,48 +207,67 @@ def main():
     if not args.no_variants:
         vs = max(200, min(args.steps, 2000))
         n4 = 4096
-        rho4, u4 = inputs.random_phase_turbulence_2d(n4, seed=0)
-        variants["d2q9_bgk_fp32_2048_two_buffers"] = variant(
-            "d2q9_bgk_fp32_2048_two_buffers",
-            lambda: binding.Lattice(rho, u, tau=tau, streaming="two"), vs, 20, 72,
-            {"streaming": "two buffers (pull A -> B)"})
-        variants["d2q9_bgk_fp32_4096"] = variant(
-            "d2q9_bgk_fp32_4096", lambda: binding.Lattice(rho4, u4, tau=tau), vs, 20, 72,
-            {"streaming": "two buffers (automatic choice above 256 MiB)"})
-        del rho4, u4
-        r3, u3 = inputs.taylor_green_3d(256, 0.05)
-        variants["d3q27_bgk_fp32_256"] = variant(
-            "d3q27_bgk_fp32_256",
-            lambda: binding.Lattice(r3, u3, lattice="D3Q27", tau=0.55, diag_every=100),
-            max(100, vs // 10), 10, 216, {"diag_every": 100})
-        del r3, u3
-        rs, us, ts = inputs.thermal_shear_layer(n4, seed=0)
-        variants["d2q9_ddf_fp32_4096"] = variant(
-            "d2q9_ddf_fp32_4096",
-            lambda: binding.Lattice(rs, us, ts, model="ddf", tau=0.6, wall_y=True, phi=1),
-            max(100, vs // 4), 10, 144, {"walls": "y", "phi": "central"})
-        for st in ("bf16", "fp16"):
-            variants["d2q9_ddf_%s_4096" % st] = variant(
-                "d2q9_ddf_%s_4096" % st,
-                lambda: binding.Lattice(rs, us, ts, model="ddf", tau=0.6, wall_y=True, phi=1,
-                                        storage=st),
-                max(100, vs // 4), 10, 88,
-                {"walls": "y", "phi": "central",
-                 "storage": "fp32 moments + %s non-equilibrium (6 f + 8 g of 18 stored)" % st})
-        del rs, us, ts
-        rho4, u4 = inputs.random_phase_turbulence_2d(n4, seed=0)
-        variants["d2q9_bgk_bf16_4096"] = variant(
-            "d2q9_bgk_bf16_4096", lambda: binding.Lattice(rho4, u4, tau=tau, storage="bf16"),
-            max(200, vs // 4), 20, 48, {"storage": "fp32 moments + bf16 f-f_eq (6 of 9 stored)"})
-        del rho4, u4
-        for st in ("bf16", "fp16"):
-            variants["d2q9_bgk_%s_2048" % st] = variant(
-                "d2q9_bgk_%s_2048" % st, lambda: binding.Lattice(rho, u, tau=tau, storage=st),
-                vs, 20, 48, {"storage": "fp32 moments + %s f-f_eq (6 of 9 stored)" % st})
-        variants["d2q9_bgk_mlp_2048"] = surrogate_variant(binding, inputs, max(100, vs // 4))
-        variants["d2q9_bgk_fp64_2048"] = variant(
-            "d2q9_bgk_fp64_2048", lambda: binding.Lattice(rho, u, tau=tau, storage="fp64"),
-            max(200, vs // 4), 20, 144)
+        fields = {}
+
+        def get(key, make):
+            """Inputs shared by several variants, generated once on first use."""
+            if key not in fields:
+                fields[key] = make()
+            return fields[key]
+
+        turb4 = lambda: get("turb4096", lambda: inputs.random_phase_turbulence_2d(n4, seed=0))
+        tgv3 = lambda: get("tgv256", lambda: inputs.taylor_green_3d(256, 0.05))
+        shear4 = lambda: get("shear4096", lambda: inputs.thermal_shear_layer(n4, seed=0))
+
+        def ddf_lattice(storage):
+            rs, us, ts = shear4()
+            return binding.Lattice(rs, us, ts, model="ddf", tau=0.6, wall_y=True, phi=1,
+                                   storage=storage)
+
+        red = "fp32 moments + %s f-f_eq (6 of 9 stored)"
+        red_ddf = "fp32 moments + %s non-equilibrium (6 f + 8 g of 18 stored)"
+        plan = [
+            ("d2q9_bgk_fp32_2048_two_buffers", lambda n: variant(
+                n, lambda: binding.Lattice(rho, u, tau=tau, streaming="two"), vs, 20, 72,
+                {"streaming": "two buffers (pull A -> B)"})),
+            ("d2q9_bgk_fp32_4096", lambda n: variant(
+                n, lambda: binding.Lattice(*turb4(), tau=tau), vs, 20, 72,
+                {"streaming": "two buffers (automatic choice above 384 MiB)"})),
+            ("d3q27_bgk_fp32_256", lambda n: variant(
+                n, lambda: binding.Lattice(*tgv3(), lattice="D3Q27", tau=0.55, diag_every=100),
+                max(100, vs // 10), 10, 216, {"diag_every": 100})),
+            ("d2q9_ddf_fp32_4096", lambda n: variant(
+                n, lambda: ddf_lattice("fp32"), max(100, vs // 4), 10, 144,
+                {"walls": "y", "phi": "central"})),
+            ("d2q9_ddf_bf16_4096", lambda n: variant(
+                n, lambda: ddf_lattice("bf16"), max(100, vs // 4), 10, 88,
+                {"walls": "y", "phi": "central", "storage": red_ddf % "bf16"})),
+            ("d2q9_ddf_fp16_4096", lambda n: variant(
+                n, lambda: ddf_lattice("fp16"), max(100, vs // 4), 10, 88,
+                {"walls": "y", "phi": "central", "storage": red_ddf % "fp16"})),
+            ("d2q9_bgk_bf16_4096", lambda n: variant(
+                n, lambda: binding.Lattice(*turb4(), tau=tau, storage="bf16"),
+                max(200, vs // 4), 20, 48, {"storage": red % "bf16"})),
+            ("d2q9_bgk_bf16_2048", lambda n: variant(
+                n, lambda: binding.Lattice(rho, u, tau=tau, storage="bf16"), vs, 20, 48,
+                {"storage": red % "bf16"})),
+            ("d2q9_bgk_fp16_2048", lambda n: variant(
+                n, lambda: binding.Lattice(rho, u, tau=tau, storage="fp16"), vs, 20, 48,
+                {"storage": red % "fp16"})),
+            ("d2q9_bgk_mlp_2048", lambda n: surrogate_variant(binding, inputs,
+                                                              max(100, vs // 4))),
+            ("d2q9_bgk_fp64_2048", lambda n: variant(
+                n, lambda: binding.Lattice(rho, u, tau=tau, storage="fp64"),
+                max(200, vs // 4), 20, 144)),
+        ]
+        only = set(args.only.split(",")) if args.only else None
+        if only and not only <= {name for name, _ in plan}:
+            log("unknown variant(s) in --only: %s" % sorted(only - {name for name, _ in plan}))
+            sys.exit(2)
+        for name, run in plan:
+            if only is None or name in only:
+                variants[name] = run(name)
+        fields.clear()
 
     line = {
         "metric": "MLUPS + % HBM roofline, plain FP32 vs reduced-storage vs surrogate at stated rel-L2",
