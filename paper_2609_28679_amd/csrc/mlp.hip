@@ -392,9 +392,13 @@ k_bgk_d2q9_mlp(const float* __restrict__ A, float* __restrict__ B, int nx, int n
 #pragma unroll
     for (int k = 0; k < 16; ++k) xs[wv][lane][k] = k < kIn ? f2bf(xf[k]) : (short)0;
     __syncthreads();
-#pragma unroll
+    // The weights are re-read from LDS for every tile instead of living in registers across
+    // the row loop: fewer registers, more wavefronts in flight.
+    const MlpLds* sw = &s;
+    asm volatile("" : "+v"(sw));
+#pragma unroll 1
     for (int nt = 0; nt < 4; ++nt) {
-      const f32x4 yt = mlp_forward_tile(s, xs[wv], nt);
+      const f32x4 yt = mlp_forward_tile(*sw, xs[wv], nt);
 #pragma unroll
       for (int j = 0; j < 4; ++j) ys[wv][16 * nt + r][4 * q + j] = yt[j];
     }
@@ -486,7 +490,7 @@ Grid make_grid_mlp(const Layout& L) {
   G.bx = kBlock;
   G.nbx = (L.nx + kBlock - 1) / kBlock;
   G.rows = 8;  // amortises the per-workgroup weight load over 8 rows
-  G.nby = (L.ny + G.rows - 1) / G.rows;
+  fit_rows(G, L.ny);
   return G;
 }
 
