@@ -24,27 +24,34 @@ __device__ __forceinline__ double psi_c(int c, double u) {
 // then reads the nine sources of a node from LDS. Every stored byte is read once per workgroup
 // with coalesced loads and every node's equilibrium is rebuilt once.
 //
-// Arithmetic is float32 in shifted form: h_i = f_i - w_i (w the rest weights), and with
+// Arithmetic is in shifted form: h_i = f_i - w_i (w the rest weights), and with
 // psi_c = W_c + d_c (W = 2/3, 1/6, 1/6; d_0 = -u^2, d_+- = (u^2 +- u)/2) the equilibrium is
-//   f_i^eq - w_i = (rho - 1) psi_a psi_b + (W_a d_b + d_a W_b + d_a d_b),
-// a sum of O(Mach) terms, so every quantity keeps float32 relative precision of the part that
-// carries the flow. The stored non-equilibrium part has 8 (bfloat16) or 11 (float16) bits, so
-// float32 rounding (~1e-7 relative) stays far below it.
+//   f_i^eq - w_i = (rho - 1) psi_a psi_b + (W_a d_b + d_a W_b + d_a d_b).
+// The rebuild of the stored rows runs in float64 (held in LDS as float32 h), the collision in
+// float32. A float32 rebuild drifts coherently: the float32 values of W repeat the same
+// rounding at every node and step, and the velocity rel-L2 against the float64 scheme grew
+// linearly to 5e-4 (tau 0.6) and 1.1e-3 (tau 0.51) after 10^4 steps at 256^2, the same for
+// bfloat16 and float16 codes. With the float64 rebuild it stays at the storage level:
+// bfloat16 1.7e-5 / 8e-5, float16 1.8e-6 / 1.4e-5 after 10^4 steps (tau 0.6 / 0.51), at 52 us
+// per 2048^2 step (all float32: 47 us; all float64: 58 us).
 constexpr int kRedCols = kBlock + 2;
 
-__device__ __forceinline__ void dpsi3(float u, float (&d)[3]) {
-  const float u2 = u * u;
-  d[0] = 0.5f * (u2 - u);
+template <typename T>
+__device__ __forceinline__ void dpsi3(T u, T (&d)[3]) {
+  const T u2 = u * u;
+  d[0] = T(0.5) * (u2 - u);
   d[1] = -u2;
-  d[2] = 0.5f * (u2 + u);
+  d[2] = T(0.5) * (u2 + u);
 }
-__device__ __forceinline__ float wk(int k) { return k == 1 ? 2.0f / 3.0f : 1.0f / 6.0f; }
+template <typename T>
+__device__ __forceinline__ T wk(int k) { return k == 1 ? T(2) / T(3) : T(1) / T(6); }
 
 // f_i^eq - w_i for the nine directions from drho = rho - 1 and the per-axis deviations
-__device__ __forceinline__ float heq_i(int i, float drho, const float (&dx)[3], const float (&dy)[3]) {
+template <typename T>
+__device__ __forceinline__ T heq_i(int i, T drho, const T (&dx)[3], const T (&dy)[3]) {
   const int a = i % 3, b = i / 3;
-  const float pa = wk(a) + dx[a], pb = wk(b) + dy[b];
-  return drho * (pa * pb) + (wk(a) * dy[b] + dx[a] * wk(b) + dx[a] * dy[b]);
+  const T pa = wk<T>(a) + dx[a], pb = wk<T>(b) + dy[b];
+  return drho * (pa * pb) + (wk<T>(a) * dy[b] + dx[a] * wk<T>(b) + dx[a] * dy[b]);
 }
 
 template <typename Codec, bool WALLS, bool DIAG>
@@ -85,18 +92,18 @@ k_bgk_d2q9_red(const float* __restrict__ M, const uint16_t* __restrict__ N, floa
     for (int k = 0; k < kRedF; ++k) v.n[k] = N[k * plane + off];
   };
   auto decode = [&](const Raw& v, float (&dst)[9]) {
-    float n[9];
+    double n[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i)
-      if (f_slot(i) >= 0) n[i] = Codec::dec(v.n[f_slot(i)], s_dec);
+      if (f_slot(i) >= 0) n[i] = (double)Codec::dec(v.n[f_slot(i)], s_dec);
     n[5] = n[0] - n[2] + n[3] + n[6] - n[8];
     n[7] = n[0] + n[1] + n[2] - n[6] - n[8];
     n[4] = -(((n[0] + n[1]) + (n[2] + n[3])) + ((n[5] + n[6]) + (n[7] + n[8])));
-    float dx[3], dy[3];
-    dpsi3(v.m[1], dx);
-    dpsi3(v.m[2], dy);
+    double dx[3], dy[3];
+    dpsi3((double)v.m[1], dx);
+    dpsi3((double)v.m[2], dy);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) dst[i] = heq_i(i, v.m[0], dx, dy) + n[i];
+    for (int i = 0; i < 9; ++i) dst[i] = (float)(heq_i(i, (double)v.m[0], dx, dy) + n[i]);
   };
   // rows beyond a wall are never pulled (bounce-back) and are skipped
   auto outside = [&](int r) { return WALLS && (r < 0 || r >= ny); };
@@ -136,9 +143,7 @@ k_bgk_d2q9_red(const float* __restrict__ M, const uint16_t* __restrict__ N, floa
       const float jx = (h[2] + h[5] + h[8]) - (h[0] + h[3] + h[6]);
       const float jy = (h[6] + h[7] + h[8]) - (h[0] + h[1] + h[2]);
       const float rho = 1.0f + drho;
-      // hardware reciprocal (1 ulp): far below the 16-bit storage error
-      const float inv = __builtin_amdgcn_rcpf(rho);
-      const float ux = jx * inv, uy = jy * inv;
+      const float ux = jx / rho, uy = jy / rho;
       float dx[3], dy[3];
       dpsi3(ux, dx);
       dpsi3(uy, dy);
