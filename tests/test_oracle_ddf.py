@@ -45,10 +45,34 @@ def _acoustic(T0, phi_on, n=32, steps=200, eps=1e-4, stencil="central"):
     return omega / (np.sqrt(GAMMA * R * T0) * k), damping / (nu * k * k)
 
 
+def _golden(name):
+    import os
+    vals = {}
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
+    for line in open(path):
+        line = line.split("#")[0].strip()
+        if line:
+            k, v = line.split("=")
+            vals[k.strip()] = float(v)
+    return vals
+
+
+def test_gas_constants_follow_the_papers_nitrogen_value():
+    # tests/golden/nitrogen_ideal_gas.txt: R / c_v = 0.4 from the paper's nitrogen table
+    gold = _golden("nitrogen_ideal_gas.txt")
+    assert R / CV == pytest.approx(gold["R_over_cv"], rel=1e-15)
+    assert (R, CV) == (pytest.approx(gold["R"]), pytest.approx(gold["cv"]))
+    assert GAMMA == pytest.approx(gold["gamma"], rel=1e-15)
+
+
 def test_adiabatic_sound_speed():
-    # c_s^2 = gamma R T for the ideal gas (Sec. II A thermodynamic sound speed)
+    # c_s^2 = gamma R T for the ideal gas (Sec. II A thermodynamic sound speed); the measured
+    # frequency of an isentropic pulse in the oracle gives c_s^2 / (R T) = 1.4 for the paper's
+    # R / c_v = 0.4 (tests/golden/nitrogen_ideal_gas.txt)
+    gold = _golden("nitrogen_ideal_gas.txt")
     speed, _ = _acoustic(1.0, True)
     assert speed == pytest.approx(1.0, abs=3e-3)
+    assert speed ** 2 * GAMMA == pytest.approx(gold["cs2_over_RT"], rel=6e-3)
 
 
 @pytest.mark.parametrize("stencil", ["central", "upwind"])
