@@ -219,9 +219,9 @@ def main():
         tgv3 = lambda: get("tgv256", lambda: inputs.taylor_green_3d(256, 0.05))
         shear4 = lambda: get("shear4096", lambda: inputs.thermal_shear_layer(n4, seed=0))
 
-        def ddf_lattice(storage):
+        def ddf_lattice(storage, phi=1):
             rs, us, ts = shear4()
-            return binding.Lattice(rs, us, ts, model="ddf", tau=0.6, wall_y=True, phi=1,
+            return binding.Lattice(rs, us, ts, model="ddf", tau=0.6, wall_y=True, phi=phi,
                                    storage=storage)
 
         red = "fp32 moments + %s f-f_eq (6 of 9 stored)"
@@ -239,6 +239,9 @@ def main():
             ("d2q9_ddf_fp32_4096", lambda n: variant(
                 n, lambda: ddf_lattice("fp32"), max(100, vs // 4), 10, 144,
                 {"walls": "y", "phi": "central"})),
+            ("d2q9_ddf_fp32_4096_upwind", lambda n: variant(
+                n, lambda: ddf_lattice("fp32", phi=2), max(100, vs // 4), 10, 144,
+                {"walls": "y", "phi": "upwind"})),
             ("d2q9_ddf_bf16_4096", lambda n: variant(
                 n, lambda: ddf_lattice("bf16"), max(100, vs // 4), 10, 88,
                 {"walls": "y", "phi": "central", "storage": red_ddf % "bf16"})),

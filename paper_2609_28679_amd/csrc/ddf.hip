@@ -193,9 +193,6 @@ struct IoRed {
   }
 };
 
-#ifndef LBM_DDF_PREFETCH
-#define LBM_DDF_PREFETCH 0
-#endif
 template <class IO, int HALO, bool WALLS, bool PULL, bool DIAG>
 __global__ void __launch_bounds__(kBlock)
 k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
@@ -228,6 +225,7 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
   const int yend = min(y0 + rows, ny);
   const int count = (yend - y0) + 2 * HALO;       // window rows
 
+
   S ring_f[H1][9], ring_g[H1][9];
   double ring_m[H1][6];  // rho, u_x, u_y, theta, e, Phi_xx
   double acc[kDiagValues] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -253,20 +251,16 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
     io.gather(PULL, r0, rm, rp, x, xm, xp, top, bot, prm, r, tid, s_stage, hf, hg);
   };
   // window row w exists (inside the window and, with walls, inside the lattice)
+  auto row_of = [&](int w) { return y0 - HALO + w; };
   auto real_row = [&](int w) {
-    const int r = y0 - HALO + w;
+    const int r = row_of(w);
     return w < count && (WALLS ? (r >= 0 && r < ny) : true);
   };
-  // Unstaged storage prefetches: the pull of row r + 1 is issued before the moments of row r,
-  // so its loads are in flight during the row's arithmetic and barriers.
-  constexpr bool kPrefetch = !IO::kStaged && (LBM_DDF_PREFETCH != 0);
-  S pf_f[9], pf_g[9];
-  if (kPrefetch && real_row(0)) gather_row(y0 - HALO, pf_f, pf_g);
   for (int k = 0; k < count; k += H1) {
 #pragma unroll
     for (int j = 0; j < H1; ++j) {
       const int w = k + j;                 // window index (block-uniform)
-      const int r = y0 - HALO + w;         // row being gathered
+      const int r = row_of(w);             // row being gathered
       if (IO::kStaged) {
         // slot (r + 1) mod 3 holds row r - 2, last read by the gather of row r - 1, which is
         // ordered before this write by the barrier that follows that gather
@@ -279,16 +273,7 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
       double phx = 0.0, phy = 0.0;
       if (row_real && puller) {
         // ---- gather (pull) ----------------------------------------------------------------
-        if (kPrefetch) {
-#pragma unroll
-          for (int i = 0; i < 9; ++i) {
-            ring_f[j][i] = pf_f[i];
-            ring_g[j][i] = pf_g[i];
-          }
-          if (real_row(w + 1)) gather_row(r + 1, pf_f, pf_g);
-        } else {
-          gather_row(r, ring_f[j], ring_g[j]);
-        }
+        gather_row(r, ring_f[j], ring_g[j]);
         // ---- moments and closure ------------------------------------------------------------
         double f[9], g[9];
 #pragma unroll
@@ -437,10 +422,12 @@ Grid make_grid_ddf(const Layout& L, int halo, bool reduced) {
   // the rows are staged (the kernel's TXI)
   const int txi = kBlock - 2 * halo - (reduced ? 2 : 0);
   G.nbx = (L.nx + txi - 1) / txi;
-  // rows per workgroup from a sweep on MI355X at 4096^2 (float32: 2 -> 588 us, 4 -> 553,
-  // 16 -> 599; reduced bf16: 4 -> 967, 16 -> 736, 32 -> 739): short windows give more
-  // workgroups in flight, the staged reduced kernel amortises its 2-row staging halo
-  G.rows = reduced ? 16 : 4;
+  // rows per workgroup from sweeps on MI355X at 4096^2 with walls (float32, central Phi:
+  // 2 -> 588 us, 4 -> 553, 8 -> 580, 16 -> 599; float32, upwind Phi: 4 -> 646, 8 -> 596,
+  // 16 -> 586; reduced bf16: 8 -> 676, 16 -> 602, 32 -> 604): short windows give more
+  // workgroups in flight, taller ones amortise the halo rows (two per side for the upwind
+  // stencil) and the staged kernel's 2-row staging halo
+  G.rows = reduced ? 16 : (halo == 2 ? 16 : 4);
 #ifdef LBM_TUNING_ENV
   if (const char* v = getenv("LBM_DDF_ROWS")) G.rows = atoi(v);
 #endif
