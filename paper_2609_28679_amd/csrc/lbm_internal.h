@@ -31,9 +31,9 @@ struct Grid {
   int blocks() const { return nbx * nby; }
 };
 
-// Workgroups along the second grid dimension are kept within 65535 (the HIP launch limit on
-// this dimension): lattices with more rows give each workgroup more rows.
-constexpr int kMaxGridY = 65535;
+// Workgroups along the second grid dimension are kept within 65536 (the launch limit of this
+// dimension on the device): lattices with more rows give each workgroup more rows.
+constexpr int kMaxGridY = 65536;
 inline void fit_rows(Grid& G, int64_t nrows) {
   if (G.rows < 1) G.rows = 1;
   if ((nrows + G.rows - 1) / G.rows > kMaxGridY) G.rows = (int)((nrows + kMaxGridY - 1) / kMaxGridY);
