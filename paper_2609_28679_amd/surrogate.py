@@ -44,10 +44,12 @@ def shuffle(X, Y, seed):
     return X[p].contiguous(), Y[p].contiguous()
 
 
-def train(X, Y, init_params, batch=4096, steps=4000, lr=1e-3):
-    """Adam on the MSE loss; returns (trainer, float32 weight blob)."""
+def train(X, Y, init_params, batch=4096, steps=4000, lr=1e-3, schedule=None):
+    """Adam on the MSE loss; returns (trainer, float32 weight blob). `schedule`, a list of
+    (steps, lr) stages run in order with the Adam state carried over, replaces steps and lr."""
     tr = binding.Trainer(binding.pack_mlp(init_params))
-    tr.train(X, Y, batch, steps, lr)
+    for n, rate in (schedule or [(steps, lr)]):
+        tr.train(X, Y, batch, n, rate)
     return tr, tr.weights()
 
 
