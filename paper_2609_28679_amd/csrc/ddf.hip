@@ -13,9 +13,10 @@
 //   beta = 1/(2 tau + 1), tau = mu/P, omega = 2 beta;
 //   f~ = f + omega (f^eq - f) + (1 - beta)(f* - f^eq),  g~ = g + omega (g^eq - g).
 //
-// Tiling. A workgroup of 256 threads owns 256 - 2 HALO columns and `rows` rows; each thread
-// holds one column (the HALO columns at either side only supply neighbour moments) and walks
-// the rows y0 - HALO .. y0 + rows + HALO - 1 bottom to top. For each row it gathers the
+// Tiling. A workgroup of 256 threads owns 256 - 2 HALO columns (256 - 2 HALO - 2 with staged
+// rows, whose outermost thread on each side only stages) and `rows` rows; each thread holds
+// one column (the HALO columns at either side only supply neighbour moments) and walks the
+// rows y0 - HALO .. y0 + rows + HALO - 1 bottom to top. For each row it gathers the
 // populations, computes the moments and the correction fluxes phi_a, exchanges phi_x across the
 // row through LDS (x derivative) and keeps phi_y of the last 2 HALO + 1 rows of its own column
 // in LDS (y derivative). A row is collided HALO rows after it was gathered, when the y
@@ -28,8 +29,10 @@
 //   IoFull<S>    float32 or float64 planes holding f_i - w_i and g_i - v_i, where w, v are the
 //                equilibria at rest at the reference state rho = 1, T = 1;
 //   IoRed<Codec> float32 moments (rho - 1, u_x, u_y, T - 1) + 16-bit non-equilibrium part, 6 of
-//                the 9 f values and 8 of the 9 g values (see reduced_common.h); the pull
-//                rebuilds each population from the source node's moments.
+//                the 9 f values and 8 of the 9 g values (see reduced_common.h); every row of
+//                the window is rebuilt once per workgroup into LDS (software-pipelined: the raw
+//                values of the row after next are loaded while the current row collides) and
+//                the pull reads the rebuilt populations from there.
 // The register ring holds the pulled populations shifted by (w, v) in the policy's ring type.
 // Arithmetic is float64.
 #include "ddf_common.h"
