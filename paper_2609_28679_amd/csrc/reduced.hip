@@ -5,7 +5,7 @@
 // node s = x - c_i, rebuilt from that node's stored moments and non-equilibrium part,
 //   f_i(x, t) = f_i^eq(m(s)) + n_i(s)       (f_ibar(x) at a half-way bounce-back wall),
 // with the product-form equilibrium of Sec. II C at theta = 1/3. The collision is the plain
-// BGK relaxation of Eq. (LBM_f) with f* = f^eq in float64; the new state is written back as
+// BGK relaxation of Eq. (LBM_f) with f* = f^eq; the new state is written back as
 // m(x) = (rho - 1, u) and n(x) = f~(x) - f^eq(m(x)).
 #include "reduced_common.h"
 
