@@ -1,10 +1,13 @@
-"""Isothermal scheme: Eq. (LBM_f) of Sec. II C with no body force (F = 0), no shift
-(f* = f^eq, so the (1 - beta) term vanishes), reference temperature theta = varsigma^2 = 1/3
-and g not evolved (the isothermal mode used for the Poiseuille runs of Sec. III A).
+"""Isothermal scheme: Eq. (LBM_f) of Sec. II C at reference temperature theta = varsigma^2 =
+1/3 (so Phi = 0), g not evolved (the isothermal mode used for the Poiseuille runs of
+Sec. III A), with an optional uniform body force F per unit volume.
 
 One time step is collide-then-stream, literally:
-    f~_i(x, t)       = f_i + 2 beta (f_i^eq - f_i)                 (collide)
+    rho = sum f, rho u = sum c f + F/2                              (moments, Sec. II C)
+    f~_i(x, t)       = f_i + 2 beta (f_i^eq - f_i) + (1 - beta)(f_i^* - f_i^eq)   (collide)
     f_i(x + c_i, t+1) = f~_i(x, t)                                   (stream, np.roll)
+where f^* is the shifted equilibrium at u* = u + F/rho and theta* = theta (Sec. II C; no heat
+source, and alpha = 0 has no effect at constant theta); without a force f^* = f^eq.
 with beta = dt / (2 tau + dt) (Sec. II B). In lattice units dt = 1; the relaxation rate is
 omega = 2 beta = 1 / tau_LB with tau_LB = tau + 1/2, so that the shear viscosity of
 Sec. II D, mu = (1/(2 beta) - 1/2) P dt, gives nu = mu / rho = varsigma^2 (tau_LB - 1/2).
@@ -15,7 +18,7 @@ returns to its node with the opposite velocity.
 """
 import numpy as np
 
-from .equilibrium import feq, moments
+from .equilibrium import feq, fstar, moments
 from .lattice import VARSIGMA2, opposite, velocities
 
 
@@ -30,11 +33,17 @@ def init_equilibrium(rho, u):
     return feq(rho, u, VARSIGMA2)
 
 
-def collide(f, omega):
-    """Post-collision populations f + omega (f^eq - f) with theta = 1/3."""
-    rho, u = moments(f)
+def collide(f, omega, F=None):
+    """Post-collision populations f + omega (f^eq - f) + (1 - omega/2)(f^* - f^eq), theta = 1/3."""
+    rho, u = moments(f, F=F)
     fe = feq(rho, u, VARSIGMA2)
-    return f + omega * (fe - f)
+    out = f + omega * (fe - f)
+    if F is not None:
+        D = u.shape[0]
+        ustar = u + np.asarray(F, dtype=np.float64).reshape((D,) + (1,) * (u.ndim - 1)) / rho
+        fs = fstar(rho, ustar, VARSIGMA2, np.zeros_like(ustar))
+        out = out + (1.0 - 0.5 * omega) * (fs - fe)
+    return out
 
 
 def stream(ft, walls_y=False):
@@ -65,8 +74,8 @@ def stream(ft, walls_y=False):
     return out
 
 
-def run(f, omega, nsteps, walls_y=False):
+def run(f, omega, nsteps, walls_y=False, F=None):
     """nsteps repetitions of collide then stream; returns the pre-collision state."""
     for _ in range(nsteps):
-        f = stream(collide(f, omega), walls_y)
+        f = stream(collide(f, omega, F), walls_y)
     return f

@@ -127,16 +127,20 @@ def geq(rho, u, theta, e):
     return out
 
 
-def moments(f, g=None):
-    """Conserved fields with F = Q = 0 (Sec. II C, definitions of rho, rho u, rho E).
+def moments(f, g=None, F=None):
+    """Conserved fields (Sec. II C, definitions of rho, rho u, rho E): rho = sum f and
+    rho u = sum c f + dt F / 2 (dt = 1; F = 0 when not given; a uniform F has shape (D,)).
 
-    Returns rho, u (shape (D,) + S) and, if g is given, rho E.
+    Returns rho, u (shape (D,) + S) and, if g is given, rho E = sum g (no heat source, and
+    the u . F / 2 term is left to the caller that evolves g with a force).
     """
     Q = f.shape[0]
     D = {9: 2, 27: 3}[Q]
     c = velocities(D)
     rho = f.sum(axis=0)
     j = np.stack([np.tensordot(c[:, a].astype(np.float64), f, axes=(0, 0)) for a in range(D)])
+    if F is not None:
+        j = j + 0.5 * np.asarray(F, dtype=np.float64).reshape((D,) + (1,) * (j.ndim - 1))
     u = j / rho
     if g is None:
         return rho, u

@@ -151,3 +151,79 @@ def test_d3q27_taylor_green_early_energy_decay():
     t = np.arange(steps + 1)
     rate = -np.polyfit(t[10:], np.log(energies[10:]), 1)[0]
     assert rate == pytest.approx(6 * nu * k * k, rel=3e-2)
+
+
+# ---- body force (Sec. II C: rho u = sum c f + F/2, shifted equilibrium at u* = u + F/rho) ----
+
+def test_uniform_force_accelerates_a_uniform_state_exactly():
+    # no gradients: every node gains F/rho of velocity per step, starting from the half-step
+    # value u0 + F/(2 rho) of the equilibrium initialisation
+    rho0, u0, F = 1.1, np.array([0.01, -0.02]), np.array([1e-4, 3e-5])
+    rho = np.full((6, 7), rho0)
+    u = u0[:, None, None] * np.ones((2, 6, 7))
+    f = bgk.init_equilibrium(rho, u)
+    om = bgk.omega_from_tau_lb(0.7)
+    for t in range(6):
+        r, v = moments(f, F=F)
+        expect = u0 + F / (2 * rho0) + t * F / rho0
+        np.testing.assert_allclose(v.reshape(2, -1), expect[:, None] * np.ones((1, 42)), rtol=0, atol=1e-16)
+        np.testing.assert_allclose(r, rho0, rtol=1e-15)
+        f = bgk.stream(bgk.collide(f, om, F))
+
+
+def test_total_momentum_grows_by_the_force_each_step():
+    rng = np.random.default_rng(3)
+    rho = 1.0 + 0.02 * rng.standard_normal((9, 11))
+    u = 0.03 * rng.standard_normal((2, 9, 11))
+    F = np.array([2e-4, -1e-4])
+    f = bgk.init_equilibrium(rho, u)
+    om = bgk.omega_from_tau_lb(0.6)
+    prev = None
+    for _ in range(5):
+        r, v = moments(f, F=F)
+        total = (r * v).reshape(2, -1).sum(axis=1)
+        if prev is not None:
+            np.testing.assert_allclose(total - prev, 99 * F, rtol=1e-9)
+        prev = total
+        f = bgk.stream(bgk.collide(f, om, F))
+
+
+def test_force_of_zero_is_the_unforced_scheme():
+    rng = np.random.default_rng(4)
+    rho = 1.0 + 0.02 * rng.standard_normal((5, 6))
+    u = 0.03 * rng.standard_normal((2, 5, 6))
+    f = bgk.init_equilibrium(rho, u)
+    a = bgk.run(f, 1.3, 7)
+    b = bgk.run(f, 1.3, 7, F=np.zeros(2))
+    np.testing.assert_allclose(a, b, rtol=0, atol=1e-16)
+
+
+def _poiseuille_error(ny, tau=1.0, F=1e-6):
+    """Steady force-driven channel flow between half-way bounce-back walls at y = -1/2 and
+    y = ny - 1/2 against u(y) = F/(2 rho nu) (y + 1/2)(ny - 1/2 - y)."""
+    nu = (tau - 0.5) / 3.0
+    y = np.arange(ny)
+    exact = F / (2 * nu) * (y + 0.5) * (ny - 0.5 - y)
+    rho = np.ones((ny, 3))
+    u = np.zeros((2, ny, 3))
+    u[0] = exact[:, None]
+    f = bgk.init_equilibrium(rho, u)
+    om = bgk.omega_from_tau_lb(tau)
+    Fv = np.array([F, 0.0])
+    prev = None
+    for k in range(200000):
+        f = bgk.stream(bgk.collide(f, om, Fv), walls_y=True)
+        if k % 200 == 0:
+            ux = moments(f, F=Fv)[1][0, :, 0]
+            if prev is not None and np.abs(ux - prev).max() < 1e-11 * exact.max():
+                break
+            prev = ux
+    ux = moments(f, F=Fv)[1][0, :, 0]
+    return np.sqrt(((ux - exact) ** 2).sum() / (exact ** 2).sum())
+
+
+def test_force_driven_poiseuille_converges_second_order():
+    # Sec. III A: isothermal force-driven Poiseuille flow, parabolic profile, second order
+    e6, e12, e24 = (_poiseuille_error(n) for n in (6, 12, 24))
+    assert e6 < 5e-2
+    assert e6 / e12 > 3.5 and e12 / e24 > 3.5
