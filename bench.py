@@ -233,12 +233,20 @@ def main():
             ("d2q9_bgk_fp32_2048_two_buffers", lambda n: variant(
                 n, lambda: binding.Lattice(rho, u, tau=tau, streaming="two"), vs, 20, 72,
                 {"streaming": "two buffers (pull A -> B)"})),
+            ("d2q9_bgk_fp32_2048_forced", lambda n: variant(
+                n, lambda: binding.Lattice(rho, u, tau=tau, force=(1e-6, 0.0)), vs, 20, 72,
+                {"force": "uniform (1e-6, 0), shifted equilibrium",
+                 "streaming": "one buffer, in place"})),
             ("d2q9_bgk_fp32_4096", lambda n: variant(
                 n, lambda: binding.Lattice(*turb4(), tau=tau), vs, 20, 72,
                 {"streaming": "two buffers (automatic choice above 384 MiB)"})),
             ("d3q27_bgk_fp32_256", lambda n: variant(
                 n, lambda: binding.Lattice(*tgv3(), lattice="D3Q27", tau=0.55, diag_every=100),
                 max(100, vs // 10), 10, 216, {"diag_every": 100})),
+            ("d3q27_bgk_fp32_256_forced", lambda n: variant(
+                n, lambda: binding.Lattice(*tgv3(), lattice="D3Q27", tau=0.55,
+                                           force=(1e-6, 0.0, 0.0)),
+                max(100, vs // 10), 10, 216, {"force": "uniform (1e-6, 0, 0)"})),
             ("d2q9_ddf_fp32_4096", lambda n: variant(
                 n, lambda: ddf_lattice("fp32"), max(100, vs // 4), 10, 144,
                 {"walls": "y", "phi": "central"})),

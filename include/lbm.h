@@ -77,6 +77,10 @@ typedef struct {
                   viscosity mu = (tau - 1/2) P0; per node tau_kin = mu / P (Sec. II A). */
   double R, cv;        /* DDF ideal gas constant and heat capacity (Sec. III A); Pr = 1 and the
                           bulk viscosity eta = mu (2/D - R/c_v) (Sec. II E) so alpha = 0 */
+  double force[3];     /* uniform body force per unit volume F (lattice units), applied through
+                          the shifted equilibrium f^* at u + F/rho (Sec. II C) with
+                          rho u = sum c f + F/2. Isothermal model with the paper's collision and
+                          FP32/FP64 storage only; force[2] = 0 for D2Q9; all zero = no force. */
   int32_t phi;         /* DDF: 1 = Galilean correction Phi on (the paper), 0 = off */
   int32_t fp16_scale_log2; /* LBM_STORE_FP16: S in [0, 24]; stored value = (f - f^eq) * 2^S */
   int32_t diag_every;  /* > 0: every diag_every steps record float64 totals (mass, momentum,
@@ -91,7 +95,7 @@ typedef struct {
 } lbm_params;
 
 /* Fill p with defaults: D2Q9 BGK FP32 plain, 64 x 64 x 1, periodic, tau 0.8, R = 1/3,
-   c_v = 5/6, phi 1, S = 16, no diagnostics, automatic streaming layout, tol 0.05, null
+   c_v = 5/6, no force, phi 1, S = 16, no diagnostics, automatic streaming layout, tol 0.05, null
    stream, no workspace. */
 void lbm_default_params(lbm_params* p);
 
@@ -119,7 +123,7 @@ int lbm_step(lbm_ctx* ctx, int64_t n);
 int lbm_time_steps(lbm_ctx* ctx, int64_t n, float* ms);
 
 /* Moments of the pre-collision populations at the current time t (Sec. II C: rho = sum f,
-   rho u = sum c f, rho E = sum g). rho: [nodes], u: [D][nodes], T: [nodes] (DDF only, may be
+   rho u = sum c f (+ F/2 with a body force), rho E = sum g). rho: [nodes], u: [D][nodes], T: [nodes] (DDF only, may be
    NULL), totals: {mass, rho u_x, rho u_y, rho u_z, energy} as float64 sums (energy = kinetic
    energy sum rho |u|^2 / 2 for BGK, total energy sum rho E for DDF); any output may be NULL.
    Caller-owned host buffers. Synchronises. */
@@ -160,7 +164,7 @@ int lbm_mlp_stats(lbm_ctx* ctx, int64_t* fallbacks, int64_t* updates);
 /* Training-pair harvest at the current time: for n node indices (device int64 array, values
    in [0, nodes)), write the network inputs of the populations the next step would collide
    (dev_x: [n][12] float32) and the plain-collision targets 1024 (f~_i - f_i^eq)/rho
-   (dev_y: [n][9] float32). D2Q9 BGK only. */
+   (dev_y: [n][9] float32). D2Q9 BGK with float32 storage and no body force only. */
 int lbm_harvest(lbm_ctx* ctx, int64_t n, const int64_t* dev_nodes, float* dev_x, float* dev_y);
 
 typedef struct lbm_mlp lbm_mlp; /* trainer: float32 master weights + Adam state on device */

@@ -32,7 +32,8 @@ class LbmParams(ctypes.Structure):
         ("lattice", ctypes.c_int32), ("model", ctypes.c_int32), ("storage", ctypes.c_int32),
         ("collision", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
         ("nz", ctypes.c_int32), ("wall_y", ctypes.c_int32), ("tau", ctypes.c_double),
-        ("R", ctypes.c_double), ("cv", ctypes.c_double), ("phi", ctypes.c_int32),
+        ("R", ctypes.c_double), ("cv", ctypes.c_double), ("force", ctypes.c_double * 3),
+        ("phi", ctypes.c_int32),
         ("fp16_scale_log2", ctypes.c_int32), ("diag_every", ctypes.c_int32),
         ("streaming", ctypes.c_int32), ("mlp_tol", ctypes.c_double), ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t),
@@ -111,7 +112,8 @@ def current_stream_handle():
 class Lattice:
     """One lattice Boltzmann context on the current HIP device.
 
-    rho0: (ny, nx) or (nz, ny, nx) float64; u0: (D,) + that shape; T0 for the DDF model.
+    rho0: (ny, nx) or (nz, ny, nx) float64; u0: (D,) + that shape; T0 for the DDF model;
+    force: uniform body force (D components) for the isothermal model, or None.
     The context workspace is a torch uint8 tensor on the current device; launches go on
     torch's current stream.
     """
@@ -119,7 +121,7 @@ class Lattice:
     def __init__(self, rho0, u0, T0=None, *, lattice="D2Q9", model="bgk", storage="fp32",
                  collision="plain", wall_y=False, tau=0.8, R=1.0 / 3.0, cv=5.0 / 6.0, phi=1,
                  fp16_scale_log2=16, diag_every=0, mlp_tol=0.05, streaming="auto",
-                 torch_workspace=True):
+                 force=None, torch_workspace=True):
         torch = _torch()
         lib = load()
         rho0 = np.ascontiguousarray(rho0, dtype=np.float64)
@@ -144,6 +146,12 @@ class Lattice:
         p.nx, p.ny, p.nz = nx, ny, nz
         p.wall_y = int(bool(wall_y))
         p.tau, p.R, p.cv, p.phi = float(tau), float(R), float(cv), int(phi)
+        if force is not None:
+            fv = [float(v) for v in force]
+            if len(fv) != D:
+                raise ValueError("force must have %d components" % D)
+            for a, v in enumerate(fv):
+                p.force[a] = v
         p.fp16_scale_log2 = int(fp16_scale_log2)
         p.diag_every = int(diag_every)
         p.streaming = STREAMINGS[streaming]

@@ -1,16 +1,17 @@
 // Isothermal fused pull stream-collide kernels (D2Q9 and D3Q27), float32 or float64 storage.
 //
-// One launch advances one time step of Eq. (LBM_f) of Sec. II C with f* = f^eq and
-// theta = varsigma^2 = 1/3 (no force, isothermal):
+// One launch advances one time step of Eq. (LBM_f) of Sec. II C at
+// theta = varsigma^2 = 1/3 (isothermal), with an optional uniform body force F:
 //   buffer A holds the post-collision populations f~(t-1), stored shifted by the rest
 //   equilibrium, h_i = f_i - w_i with w_i = f_i^eq(rho = 1, u = 0): h is O(Mach), so float32
 //   storage keeps ~7 significant digits of the part that carries the flow instead of the
 //   part that is constant;
 //   pull:     f_i(x, t) = f~_i(x - c_i, t-1)  (periodic wrap, or half-way bounce-back
 //             f_i(x, t) = f~_ibar(x, t-1) where x - c_i lies beyond a y wall);
-//   moments:  rho = sum f_i, rho u = sum c_i f_i;
+//   moments:  rho = sum f_i, rho u = sum c_i f_i + F/2;
 //   equilibrium: f_i^eq = rho prod_a Psi_ia(u_a, theta + u_a^2) (Sec. II C);
-//   relax:    f~_i = f_i + omega (f_i^eq - f_i), omega = 2 beta (Sec. II B);
+//   relax:    f~_i = f_i + omega (f_i^eq - f_i) + (1 - omega/2)(f_i^* - f_i^eq), omega = 2 beta
+//             (Sec. II B), f^* the equilibrium at u + F/rho (f^* = f^eq without a force);
 //   store f~(t) into buffer B (non-temporal: it is not read again by this launch).
 // All arithmetic is float64 whatever the storage type: on this chip double-precision vector
 // FMA runs at the same rate as unpacked single precision, and float64 arithmetic removes the
@@ -22,6 +23,7 @@
 #include "device_common.h"
 
 #include <cstdlib>
+#include <type_traits>
 
 namespace lbm {
 
@@ -36,11 +38,101 @@ __device__ __forceinline__ void psi3(double u, double (&p)[3]) {
 // Rest weights w_i = prod_a Psi(c_ia; 0, 1/3) as a function of the per-axis index k = c + 1.
 __device__ __forceinline__ double w1(int k) { return k == 1 ? 2.0 / 3.0 : 1.0 / 6.0; }
 
+// Moments of one node for the diagnostics: rho, rho u (with the half-step force term) and u.
+struct NodeMoments {
+  double rho, j[3], u[3];
+};
+
+// Collision of one node held shifted (h = f - w), Eq. (LBM_f) at theta = 1/3 (Phi = 0):
+//   rho = sum f, rho u = sum c f + F/2,
+//   f~ = f + omega (f^eq - f) + (1 - omega/2)(f^* - f^eq),
+// where f^* is the equilibrium at u* = u + F/rho (Sec. II C; no heat source, theta* = theta).
+// Without a force (FORCE = false) f^* = f^eq. `sink(i, h~_i)` receives the post-collision
+// values in storage precision. D2Q9 and D3Q27 (D = 2, 3; i = (cx+1) + 3(cy+1) + 9(cz+1)).
+template <int D, bool FORCE, typename S, typename Sink>
+__device__ __forceinline__ void collide_bgk(const S (&hs)[D == 2 ? 9 : 27], double omega,
+                                            const Force& F, NodeMoments& m, Sink&& sink) {
+  constexpr int Q = D == 2 ? 9 : 27;
+  double rho, j[3] = {0.0, 0.0, 0.0};
+  if (D == 2) {
+    double h[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) h[i] = (double)hs[i];
+    // sum w_i = 1 and sum c_i w_i = 0, so rho = 1 + sum h and rho u = sum c h
+    rho = 1.0 + (((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8]);
+    j[0] = (h[2] + h[5] + h[8]) - (h[0] + h[3] + h[6]);
+    j[1] = (h[6] + h[7] + h[8]) - (h[0] + h[1] + h[2]);
+  } else {
+    double drho = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
+      const double v = (double)hs[i];
+      drho += v;
+      if (cx) j[0] += cx > 0 ? v : -v;
+      if (cy) j[1] += cy > 0 ? v : -v;
+      if (cz) j[2] += cz > 0 ? v : -v;
+    }
+    rho = 1.0 + drho;
+  }
+  if (FORCE) {
+    j[0] += 0.5 * F.x;
+    j[1] += 0.5 * F.y;
+    if (D == 3) j[2] += 0.5 * F.z;
+  }
+  double p[3][3], ps[3][3];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    m.u[a] = j[a] / rho;
+    psi3(m.u[a], p[a]);
+  }
+  if (FORCE) {
+    const double fa[3] = {F.x, F.y, F.z};
+#pragma unroll
+    for (int a = 0; a < D; ++a) psi3(m.u[a] + fa[a] / rho, ps[a]);
+  }
+  const double keep = 1.0 - 0.5 * omega;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int a = i % 3, b = (i / 3) % 3, c = i / 9;
+    // rho p_a p_b (p_c), multiplied left to right so that rho p_a is shared between directions
+    double feq = rho * p[0][a] * p[1][b];
+    double ww = w1(a) * w1(b);
+    if (D == 3) {
+      feq *= p[2][c];
+      ww *= w1(c);
+    }
+    const double heq = feq - ww;
+    const double v = (double)hs[i];
+    double out = v + omega * (heq - v);
+    if (FORCE) {
+      double fs = rho * ps[0][a] * ps[1][b];
+      if (D == 3) fs *= ps[2][c];
+      out += keep * (fs - feq);
+    }
+    sink(i, (S)out);
+  }
+  m.rho = rho;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) m.j[a] = a < D ? j[a] : 0.0;
+}
+
+template <int D>
+__device__ __forceinline__ void add_diag(double (&acc)[kDiagValues], const NodeMoments& m) {
+  acc[0] += m.rho;
+  acc[1] += m.j[0];
+  acc[2] += m.j[1];
+  if (D == 3) acc[3] += m.j[2];
+  double u2 = m.u[0] * m.u[0] + m.u[1] * m.u[1];
+  if (D == 3) u2 += m.u[2] * m.u[2];
+  acc[4] += 0.5 * m.rho * u2;
+}
+
 // ---- D2Q9 ---------------------------------------------------------------------------------
-template <typename S, bool WALLS, bool DIAG>
+template <typename S, bool WALLS, bool DIAG, bool FORCE>
 __global__ void __launch_bounds__(kBlock)
 k_bgk_d2q9(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int64_t pitch,
-           int64_t plane, double omega, int rows, double* __restrict__ partials) {
+           int64_t plane, double omega, Force F, int rows, double* __restrict__ partials) {
   const int nbx = gridDim.x;
   const int tile = xcd_tile(blockIdx.x + nbx * blockIdx.y, nbx * gridDim.y);
   const int bx = tile % nbx;
@@ -82,30 +174,10 @@ k_bgk_d2q9(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int64_t p
         hs[7] = load_nt(A + 7 * plane + rm + x);
         hs[8] = load_nt(A + 8 * plane + rm + xm);
       }
-      double h[9];
-#pragma unroll
-      for (int i = 0; i < 9; ++i) h[i] = (double)hs[i];
-      // sum w_i = 1 and sum c_i w_i = 0, so rho = 1 + sum h and rho u = sum c h
-      const double rho = 1.0 + (((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8]);
-      const double jx = (h[2] + h[5] + h[8]) - (h[0] + h[3] + h[6]);
-      const double jy = (h[6] + h[7] + h[8]) - (h[0] + h[1] + h[2]);
-      const double ux = jx / rho;
-      const double uy = jy / rho;
-      double px[3], py[3];
-      psi3(ux, px);
-      psi3(uy, py);
       S* out = B + r0 + x;
-#pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        const double heq = rho * px[i % 3] * py[i / 3] - w1(i % 3) * w1(i / 3);
-        store_nt(out + i * plane, (S)(h[i] + omega * (heq - h[i])));
-      }
-      if (DIAG) {
-        acc[0] += rho;
-        acc[1] += jx;
-        acc[2] += jy;
-        acc[4] += 0.5 * rho * (ux * ux + uy * uy);
-      }
+      NodeMoments m;
+      collide_bgk<2, FORCE>(hs, omega, F, m, [&](int i, S v) { store_nt(out + i * plane, v); });
+      if (DIAG) add_diag<2>(acc, m);
     }
   }
   if (DIAG) block_sum_store<kDiagValues>(acc, partials + (int64_t)tile * kDiagValues);
@@ -144,10 +216,10 @@ __device__ __forceinline__ void aa_store(T* p, T v) {
 #endif
 }
 
-template <typename S, bool WALLS, bool DIAG, bool ODD>
+template <typename S, bool WALLS, bool DIAG, bool ODD, bool FORCE>
 __global__ void __launch_bounds__(kBlock)
 k_bgk_d2q9_aa(S* __restrict__ A, int nx, int ny, int64_t pitch, int64_t plane, double omega,
-              int rows, double* __restrict__ partials) {
+              Force F, int rows, double* __restrict__ partials) {
   const int nbx = gridDim.x;
   const int tile = xcd_tile(blockIdx.x + nbx * blockIdx.y, nbx * gridDim.y);
   const int bx = tile % nbx;
@@ -187,34 +259,16 @@ k_bgk_d2q9_aa(S* __restrict__ A, int nx, int ny, int64_t pitch, int64_t plane, d
         else
           hs[i] = aa_load(wall_in[i] ? A + i * plane + r0 + x : A + (8 - i) * plane + src[i]);
       }
-      double h[9];
-#pragma unroll
-      for (int i = 0; i < 9; ++i) h[i] = (double)hs[i];
-      const double rho = 1.0 + (((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8]);
-      const double jx = (h[2] + h[5] + h[8]) - (h[0] + h[3] + h[6]);
-      const double jy = (h[6] + h[7] + h[8]) - (h[0] + h[1] + h[2]);
-      const double ux = jx / rho;
-      const double uy = jy / rho;
-      double px[3], py[3];
-      psi3(ux, px);
-      psi3(uy, py);
-#pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        const double heq = rho * px[i % 3] * py[i / 3] - w1(i % 3) * w1(i / 3);
-        const S v = (S)(h[i] + omega * (heq - h[i]));
+      NodeMoments m;
+      collide_bgk<2, FORCE>(hs, omega, F, m, [&](int i, S v) {
         if (ODD) {
           aa_store(A + (8 - i) * plane + r0 + x, v);
         } else {
           // destination x + c_i is the source of the opposite direction, x - c_(8-i)
           aa_store(A + (wall_in[8 - i] ? (8 - i) * plane + r0 + x : i * plane + src[8 - i]), v);
         }
-      }
-      if (DIAG) {
-        acc[0] += rho;
-        acc[1] += jx;
-        acc[2] += jy;
-        acc[4] += 0.5 * rho * (ux * ux + uy * uy);
-      }
+      });
+      if (DIAG) add_diag<2>(acc, m);
     }
   }
   if (DIAG) block_sum_store<kDiagValues>(acc, partials + (int64_t)tile * kDiagValues);
@@ -225,10 +279,10 @@ k_bgk_d2q9_aa(S* __restrict__ A, int nx, int ny, int64_t pitch, int64_t plane, d
 #ifndef LBM_D3Q27_WAVES
 #define LBM_D3Q27_WAVES 3
 #endif
-template <typename S, bool WALLS, bool DIAG>
+template <typename S, bool WALLS, bool DIAG, bool FORCE>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LBM_D3Q27_WAVES)))
 k_bgk_d3q27(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int nz, int64_t pitch,
-            int64_t plane, double omega, int rows, double* __restrict__ partials) {
+            int64_t plane, double omega, Force F, int rows, double* __restrict__ partials) {
   const int nbx = gridDim.x;
   // hardware workgroup order (consecutive rows on different XCDs): measured 6% faster than the
   // per-XCD contiguous ranges for D3Q27 at 256^3, whose 27 streams then stay close in memory
@@ -264,37 +318,10 @@ k_bgk_d3q27(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int nz, 
           h[i] = load_nt(A + i * plane + ((int64_t)zsrc[cz] * ny + ysrc[cy]) * pitch + xs[cx]);
         }
       }
-      double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
-#pragma unroll
-      for (int i = 0; i < 27; ++i) {
-        const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
-        const double v = (double)h[i];
-        drho += v;
-        if (cx) jx += cx > 0 ? v : -v;
-        if (cy) jy += cy > 0 ? v : -v;
-        if (cz) jz += cz > 0 ? v : -v;
-      }
-      const double rho = 1.0 + drho;
-      const double ux = jx / rho, uy = jy / rho, uz = jz / rho;
-      double px[3], py[3], pz[3];
-      psi3(ux, px);
-      psi3(uy, py);
-      psi3(uz, pz);
       S* out = B + self;
-#pragma unroll
-      for (int i = 0; i < 27; ++i) {
-        const int a = i % 3, b = (i / 3) % 3, c = i / 9;
-        const double heq = rho * px[a] * py[b] * pz[c] - w1(a) * w1(b) * w1(c);
-        const double v = (double)h[i];
-        store_nt(out + i * plane, (S)(v + omega * (heq - v)));
-      }
-      if (DIAG) {
-        acc[0] += rho;
-        acc[1] += jx;
-        acc[2] += jy;
-        acc[3] += jz;
-        acc[4] += 0.5 * rho * (ux * ux + uy * uy + uz * uz);
-      }
+      NodeMoments m;
+      collide_bgk<3, FORCE>(h, omega, F, m, [&](int i, S v) { store_nt(out + i * plane, v); });
+      if (DIAG) add_diag<3>(acc, m);
     }
   }
   if (DIAG) block_sum_store<kDiagValues>(acc, partials + (int64_t)tile * kDiagValues);
@@ -302,10 +329,10 @@ k_bgk_d3q27(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int nz, 
 
 // ---- D3Q27, single buffer ----------------------------------------------------------------
 // The in-place two-step layout of k_bgk_d2q9_aa with 27 directions (slot Q-1-i = 26-i).
-template <typename S, bool WALLS, bool DIAG, bool ODD>
+template <typename S, bool WALLS, bool DIAG, bool ODD, bool FORCE>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(ODD ? 3 : 2)))
 k_bgk_d3q27_aa(S* __restrict__ A, int nx, int ny, int nz, int64_t pitch, int64_t plane,
-               double omega, int rows, double* __restrict__ partials) {
+               double omega, Force F, int rows, double* __restrict__ partials) {
   const int nbx = gridDim.x;
   const int tile = blockIdx.x + nbx * blockIdx.y;  // hardware order, as k_bgk_d3q27
   const int bx = tile % nbx;
@@ -343,40 +370,14 @@ k_bgk_d3q27_aa(S* __restrict__ A, int nx, int ny, int nz, int64_t pitch, int64_t
         else
           h[i] = aa_load(wall_in(i) ? A + i * plane + self : A + (26 - i) * plane + src(i));
       }
-      double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
-#pragma unroll
-      for (int i = 0; i < 27; ++i) {
-        const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
-        const double v = (double)h[i];
-        drho += v;
-        if (cx) jx += cx > 0 ? v : -v;
-        if (cy) jy += cy > 0 ? v : -v;
-        if (cz) jz += cz > 0 ? v : -v;
-      }
-      const double rho = 1.0 + drho;
-      const double ux = jx / rho, uy = jy / rho, uz = jz / rho;
-      double px[3], py[3], pz[3];
-      psi3(ux, px);
-      psi3(uy, py);
-      psi3(uz, pz);
-#pragma unroll
-      for (int i = 0; i < 27; ++i) {
-        const int a = i % 3, b = (i / 3) % 3, c = i / 9;
-        const double heq = rho * px[a] * py[b] * pz[c] - w1(a) * w1(b) * w1(c);
-        const double v = (double)h[i];
-        const S o = (S)(v + omega * (heq - v));
+      NodeMoments m;
+      collide_bgk<3, FORCE>(h, omega, F, m, [&](int i, S o) {
         if (ODD)
           aa_store(A + (26 - i) * plane + self, o);
         else
           aa_store(wall_in(26 - i) ? A + (26 - i) * plane + self : A + i * plane + src(26 - i), o);
-      }
-      if (DIAG) {
-        acc[0] += rho;
-        acc[1] += jx;
-        acc[2] += jy;
-        acc[3] += jz;
-        acc[4] += 0.5 * rho * (ux * ux + uy * uy + uz * uz);
-      }
+      });
+      if (DIAG) add_diag<3>(acc, m);
     }
   }
   if (DIAG) block_sum_store<kDiagValues>(acc, partials + (int64_t)tile * kDiagValues);
@@ -384,11 +385,13 @@ k_bgk_d3q27_aa(S* __restrict__ A, int nx, int ny, int nz, int64_t pitch, int64_t
 
 // ---- initialisation and read-out -----------------------------------------------------------
 // f_i <- f_i^eq(rho, u) with theta = 1/3 (Fig. 1 initialisation), stored as h = f - w; swap = 1
-// stores population i in slot Q-1-i (the single-buffer state at an even step count).
-template <typename S>
+// stores population i in slot Q-1-i (the single-buffer state at an even step count). The
+// stored state is post-collision: without a force the collision leaves an equilibrium as it
+// is; with a force (FORCE) the equilibrium is collided once, in float64, before it is stored.
+template <typename S, bool FORCE>
 __global__ void k_init_bgk(int D, const double* __restrict__ rho, const double* __restrict__ u,
                            S* __restrict__ A, int nx, int ny, int nz, int64_t pitch,
-                           int64_t plane, int swap) {
+                           int64_t plane, int swap, double omega, Force F) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nodes = (int64_t)nx * ny * nz;
   if (n >= nodes) return;
@@ -398,6 +401,7 @@ __global__ void k_init_bgk(int D, const double* __restrict__ rho, const double* 
   double p[3][3];
   for (int a = 0; a < D; ++a) psi3(u[a * nodes + n], p[a]);
   const int Q = D == 2 ? 9 : 27;
+  double h[27];
   for (int i = 0; i < Q; ++i) {
     const int ka = i % 3, kb = (i / 3) % 3, kc = i / 9;
     double v = rho[n] * p[0][ka] * p[1][kb];
@@ -406,7 +410,20 @@ __global__ void k_init_bgk(int D, const double* __restrict__ rho, const double* 
       v *= p[2][kc];
       w *= w1(kc);
     }
-    A[(swap ? Q - 1 - i : i) * plane + off] = (S)(v - w);
+    h[i] = v - w;
+  }
+  auto put = [&](int i, double v) { A[(swap ? Q - 1 - i : i) * plane + off] = (S)v; };
+  if (!FORCE) {
+    for (int i = 0; i < Q; ++i) put(i, h[i]);
+    return;
+  }
+  NodeMoments m;
+  if (D == 2) {
+    double h9[9];
+    for (int i = 0; i < 9; ++i) h9[i] = h[i];
+    collide_bgk<2, true>(h9, omega, F, m, put);
+  } else {
+    collide_bgk<3, true>(h, omega, F, m, put);
   }
 }
 
@@ -430,11 +447,13 @@ __device__ __forceinline__ int64_t post_index(int view, int walls, int D, int nx
   return i * plane + ((int64_t)zd * ny + yw) * pitch + xd;
 }
 
-// Moments of the stored post-collision state: the collision conserves rho and rho u, so these
-// equal the moments of the pre-collision populations at the same time.
+// Moments of the stored post-collision state: the collision conserves rho and, without a force,
+// rho u, so these equal the moments of the pre-collision populations at the same time. With a
+// force the collision adds F to sum c f, and rho u = sum c f + F/2 before it, so
+// rho u = sum c f~ - F/2.
 template <typename S>
 __global__ void k_moments_bgk(int D, const S* __restrict__ A, int nx, int ny, int nz,
-                              int64_t pitch, int64_t plane, int view, int walls,
+                              int64_t pitch, int64_t plane, int view, int walls, Force F,
                               double* __restrict__ rho, double* __restrict__ u) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nodes = (int64_t)nx * ny * nz;
@@ -450,6 +469,9 @@ __global__ void k_moments_bgk(int D, const S* __restrict__ A, int nx, int ny, in
     const int c[3] = {i % 3 - 1, (i / 3) % 3 - 1, i / 9 - 1};
     for (int a = 0; a < D; ++a) j[a] += c[a] * v;
   }
+  j[0] -= 0.5 * F.x;
+  j[1] -= 0.5 * F.y;
+  j[2] -= 0.5 * F.z;
   const double r = 1.0 + s;
   rho[n] = r;
   for (int a = 0; a < D; ++a) u[a * nodes + n] = j[a] / r;
@@ -553,124 +575,140 @@ Grid make_grid(const Layout& L) {
   return G;
 }
 
+// Calls fn(std::integral_constant<bool, b>{}): turns a run-time flag into a template argument.
+template <typename Fn>
+static void with_flag(bool b, Fn&& fn) {
+  if (b)
+    fn(std::true_type{});
+  else
+    fn(std::false_type{});
+}
+
 template <typename R>
 static hipError_t bgk2_(const void* A, void* B, const Layout& L, const Grid& G, double omega,
-                       bool walls, double* partials, hipStream_t s) {
+                        const Force& F, bool walls, double* partials, hipStream_t s) {
   dim3 grid(G.nbx, G.nby), block(G.bx);
   auto a = static_cast<const R*>(A);
   auto b = static_cast<R*>(B);
-  if (walls) {
-    if (partials)
-      k_bgk_d2q9<R, true, true><<<grid, block, 0, s>>>(a, b, L.nx, L.ny, L.pitch, L.plane, omega, G.rows, partials);
-    else
-      k_bgk_d2q9<R, true, false><<<grid, block, 0, s>>>(a, b, L.nx, L.ny, L.pitch, L.plane, omega, G.rows, nullptr);
-  } else {
-    if (partials)
-      k_bgk_d2q9<R, false, true><<<grid, block, 0, s>>>(a, b, L.nx, L.ny, L.pitch, L.plane, omega, G.rows, partials);
-    else
-      k_bgk_d2q9<R, false, false><<<grid, block, 0, s>>>(a, b, L.nx, L.ny, L.pitch, L.plane, omega, G.rows, nullptr);
-  }
+  with_flag(walls, [&](auto W) {
+    with_flag(partials != nullptr, [&](auto Dg) {
+      with_flag(F.on(), [&](auto Fo) {
+        k_bgk_d2q9<R, decltype(W)::value, decltype(Dg)::value, decltype(Fo)::value>
+            <<<grid, block, 0, s>>>(a, b, L.nx, L.ny, L.pitch, L.plane, omega, F, G.rows, partials);
+      });
+    });
+  });
   return hipGetLastError();
 }
 
 template <typename R>
 static hipError_t bgk3(const void* A, void* B, const Layout& L, const Grid& G, double omega,
-                       bool walls, double* partials, hipStream_t s) {
+                       const Force& F, bool walls, double* partials, hipStream_t s) {
   dim3 grid(G.nbx, G.nby), block(G.bx);
   auto a = static_cast<const R*>(A);
   auto b = static_cast<R*>(B);
-  if (walls) {
-    if (partials)
-      k_bgk_d3q27<R, true, true><<<grid, block, 0, s>>>(a, b, L.nx, L.ny, L.nz, L.pitch, L.plane, omega, G.rows, partials);
-    else
-      k_bgk_d3q27<R, true, false><<<grid, block, 0, s>>>(a, b, L.nx, L.ny, L.nz, L.pitch, L.plane, omega, G.rows, nullptr);
-  } else {
-    if (partials)
-      k_bgk_d3q27<R, false, true><<<grid, block, 0, s>>>(a, b, L.nx, L.ny, L.nz, L.pitch, L.plane, omega, G.rows, partials);
-    else
-      k_bgk_d3q27<R, false, false><<<grid, block, 0, s>>>(a, b, L.nx, L.ny, L.nz, L.pitch, L.plane, omega, G.rows, nullptr);
-  }
+  with_flag(walls, [&](auto W) {
+    with_flag(partials != nullptr, [&](auto Dg) {
+      with_flag(F.on(), [&](auto Fo) {
+        k_bgk_d3q27<R, decltype(W)::value, decltype(Dg)::value, decltype(Fo)::value>
+            <<<grid, block, 0, s>>>(a, b, L.nx, L.ny, L.nz, L.pitch, L.plane, omega, F, G.rows,
+                                    partials);
+      });
+    });
+  });
   return hipGetLastError();
 }
 
 hipError_t launch_bgk_d2q9(int kind, const void* A, void* B, const Layout& L, const Grid& G,
-                           double omega, bool walls, double* partials, hipStream_t s) {
-  return kind == 0 ? bgk2_<float>(A, B, L, G, omega, walls, partials, s)
-                   : bgk2_<double>(A, B, L, G, omega, walls, partials, s);
+                           double omega, const Force& F, bool walls, double* partials,
+                           hipStream_t s) {
+  return kind == 0 ? bgk2_<float>(A, B, L, G, omega, F, walls, partials, s)
+                   : bgk2_<double>(A, B, L, G, omega, F, walls, partials, s);
 }
 
 hipError_t launch_bgk_d3q27(int kind, const void* A, void* B, const Layout& L, const Grid& G,
-                            double omega, bool walls, double* partials, hipStream_t s) {
-  return kind == 0 ? bgk3<float>(A, B, L, G, omega, walls, partials, s)
-                   : bgk3<double>(A, B, L, G, omega, walls, partials, s);
+                            double omega, const Force& F, bool walls, double* partials,
+                            hipStream_t s) {
+  return kind == 0 ? bgk3<float>(A, B, L, G, omega, F, walls, partials, s)
+                   : bgk3<double>(A, B, L, G, omega, F, walls, partials, s);
 }
 
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 template <typename R>
-static hipError_t bgk2_aa(void* A, const Layout& L, const Grid& G, double omega, bool walls,
-                          bool odd, double* partials, hipStream_t s) {
+static hipError_t bgk2_aa(void* A, const Layout& L, const Grid& G, double omega, const Force& F,
+                          bool walls, bool odd, double* partials, hipStream_t s) {
   dim3 grid(G.nbx, G.nby), block(G.bx);
   auto a = static_cast<R*>(A);
-#define LBM_AA_LAUNCH(W, D, O) \
-  k_bgk_d2q9_aa<R, W, D, O><<<grid, block, 0, s>>>(a, L.nx, L.ny, L.pitch, L.plane, omega, G.rows, partials)
-  if (walls) {
-    if (partials) { if (odd) LBM_AA_LAUNCH(true, true, true); else LBM_AA_LAUNCH(true, true, false); }
-    else { if (odd) LBM_AA_LAUNCH(true, false, true); else LBM_AA_LAUNCH(true, false, false); }
-  } else {
-    if (partials) { if (odd) LBM_AA_LAUNCH(false, true, true); else LBM_AA_LAUNCH(false, true, false); }
-    else { if (odd) LBM_AA_LAUNCH(false, false, true); else LBM_AA_LAUNCH(false, false, false); }
-  }
-#undef LBM_AA_LAUNCH
+  with_flag(walls, [&](auto W) {
+    with_flag(partials != nullptr, [&](auto Dg) {
+      with_flag(odd, [&](auto O) {
+        with_flag(F.on(), [&](auto Fo) {
+          k_bgk_d2q9_aa<R, decltype(W)::value, decltype(Dg)::value, decltype(O)::value,
+                        decltype(Fo)::value>
+              <<<grid, block, 0, s>>>(a, L.nx, L.ny, L.pitch, L.plane, omega, F, G.rows, partials);
+        });
+      });
+    });
+  });
   return hipGetLastError();
 }
 
 hipError_t launch_bgk_d2q9_aa(int kind, bool odd, void* A, const Layout& L, const Grid& G,
-                              double omega, bool walls, double* partials, hipStream_t s) {
-  return kind == 0 ? bgk2_aa<float>(A, L, G, omega, walls, odd, partials, s)
-                   : bgk2_aa<double>(A, L, G, omega, walls, odd, partials, s);
+                              double omega, const Force& F, bool walls, double* partials,
+                              hipStream_t s) {
+  return kind == 0 ? bgk2_aa<float>(A, L, G, omega, F, walls, odd, partials, s)
+                   : bgk2_aa<double>(A, L, G, omega, F, walls, odd, partials, s);
 }
 
 template <typename R>
-static hipError_t bgk3_aa(void* A, const Layout& L, const Grid& G, double omega, bool walls,
-                          bool odd, double* partials, hipStream_t s) {
+static hipError_t bgk3_aa(void* A, const Layout& L, const Grid& G, double omega, const Force& F,
+                          bool walls, bool odd, double* partials, hipStream_t s) {
   dim3 grid(G.nbx, G.nby), block(G.bx);
   auto a = static_cast<R*>(A);
-#define LBM_AA_LAUNCH(W, D, O)                                                                \
-  k_bgk_d3q27_aa<R, W, D, O><<<grid, block, 0, s>>>(a, L.nx, L.ny, L.nz, L.pitch, L.plane, omega, \
-                                                    G.rows, partials)
-  if (walls) {
-    if (partials) { if (odd) LBM_AA_LAUNCH(true, true, true); else LBM_AA_LAUNCH(true, true, false); }
-    else { if (odd) LBM_AA_LAUNCH(true, false, true); else LBM_AA_LAUNCH(true, false, false); }
-  } else {
-    if (partials) { if (odd) LBM_AA_LAUNCH(false, true, true); else LBM_AA_LAUNCH(false, true, false); }
-    else { if (odd) LBM_AA_LAUNCH(false, false, true); else LBM_AA_LAUNCH(false, false, false); }
-  }
-#undef LBM_AA_LAUNCH
+  with_flag(walls, [&](auto W) {
+    with_flag(partials != nullptr, [&](auto Dg) {
+      with_flag(odd, [&](auto O) {
+        with_flag(F.on(), [&](auto Fo) {
+          k_bgk_d3q27_aa<R, decltype(W)::value, decltype(Dg)::value, decltype(O)::value,
+                         decltype(Fo)::value><<<grid, block, 0, s>>>(
+              a, L.nx, L.ny, L.nz, L.pitch, L.plane, omega, F, G.rows, partials);
+        });
+      });
+    });
+  });
   return hipGetLastError();
 }
 
 hipError_t launch_bgk_d3q27_aa(int kind, bool odd, void* A, const Layout& L, const Grid& G,
-                               double omega, bool walls, double* partials, hipStream_t s) {
-  return kind == 0 ? bgk3_aa<float>(A, L, G, omega, walls, odd, partials, s)
-                   : bgk3_aa<double>(A, L, G, omega, walls, odd, partials, s);
+                               double omega, const Force& F, bool walls, double* partials,
+                               hipStream_t s) {
+  return kind == 0 ? bgk3_aa<float>(A, L, G, omega, F, walls, odd, partials, s)
+                   : bgk3_aa<double>(A, L, G, omega, F, walls, odd, partials, s);
 }
 
 hipError_t launch_init_bgk(int kind, int D, const double* rho, const double* u, void* A,
-                           const Layout& L, bool swap, hipStream_t s) {
-  if (kind == 0)
-    k_init_bgk<float><<<nblk(L.nodes()), kBlock, 0, s>>>(D, rho, u, static_cast<float*>(A), L.nx, L.ny, L.nz, L.pitch, L.plane, swap ? 1 : 0);
-  else
-    k_init_bgk<double><<<nblk(L.nodes()), kBlock, 0, s>>>(D, rho, u, static_cast<double*>(A), L.nx, L.ny, L.nz, L.pitch, L.plane, swap ? 1 : 0);
+                           const Layout& L, bool swap, double omega, const Force& F,
+                           hipStream_t s) {
+  const int sw = swap ? 1 : 0;
+  with_flag(F.on(), [&](auto Fo) {
+    constexpr bool FO = decltype(Fo)::value;
+    if (kind == 0)
+      k_init_bgk<float, FO><<<nblk(L.nodes()), kBlock, 0, s>>>(
+          D, rho, u, static_cast<float*>(A), L.nx, L.ny, L.nz, L.pitch, L.plane, sw, omega, F);
+    else
+      k_init_bgk<double, FO><<<nblk(L.nodes()), kBlock, 0, s>>>(
+          D, rho, u, static_cast<double*>(A), L.nx, L.ny, L.nz, L.pitch, L.plane, sw, omega, F);
+  });
   return hipGetLastError();
 }
 
 hipError_t launch_moments_bgk(int kind, int D, const void* A, const Layout& L, int view,
-                              bool walls, double* rho, double* u, hipStream_t s) {
+                              bool walls, const Force& F, double* rho, double* u, hipStream_t s) {
   if (kind == 0)
-    k_moments_bgk<float><<<nblk(L.nodes()), kBlock, 0, s>>>(D, static_cast<const float*>(A), L.nx, L.ny, L.nz, L.pitch, L.plane, view, walls ? 1 : 0, rho, u);
+    k_moments_bgk<float><<<nblk(L.nodes()), kBlock, 0, s>>>(D, static_cast<const float*>(A), L.nx, L.ny, L.nz, L.pitch, L.plane, view, walls ? 1 : 0, F, rho, u);
   else
-    k_moments_bgk<double><<<nblk(L.nodes()), kBlock, 0, s>>>(D, static_cast<const double*>(A), L.nx, L.ny, L.nz, L.pitch, L.plane, view, walls ? 1 : 0, rho, u);
+    k_moments_bgk<double><<<nblk(L.nodes()), kBlock, 0, s>>>(D, static_cast<const double*>(A), L.nx, L.ny, L.nz, L.pitch, L.plane, view, walls ? 1 : 0, F, rho, u);
   return hipGetLastError();
 }
 

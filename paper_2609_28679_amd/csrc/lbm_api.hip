@@ -47,6 +47,7 @@ struct lbm_ctx {
   int64_t hist_written = 0;
   int64_t t = 0;
   double omega = 0.0;
+  Force F;  // uniform body force (zero: none)
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   float* mlp_w = nullptr;                  // surrogate weights (kMlpParams floats)
   unsigned long long* mlp_cnt = nullptr;   // {fallbacks, updates}
@@ -123,6 +124,15 @@ int validate(const lbm_params* p, std::string& why) {
     return LBM_EINVAL;
   }
   if (!(p->mlp_tol >= 0.0)) { why = "mlp_tol must be >= 0"; return LBM_EINVAL; }
+  const bool forced = p->force[0] != 0.0 || p->force[1] != 0.0 || p->force[2] != 0.0;
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(p->force[a])) { why = "force must be finite"; return LBM_EINVAL; }
+  if (forced && (p->model != LBM_MODEL_BGK || p->collision != LBM_COLLIDE_PLAIN ||
+                 (p->storage != LBM_STORE_FP32 && p->storage != LBM_STORE_FP64))) {
+    why = "a body force needs the isothermal model, the paper's collision and FP32 or FP64 storage";
+    return LBM_EINVAL;
+  }
+  if (forced && p->lattice == LBM_D2Q9 && p->force[2] != 0.0) { why = "D2Q9 requires force[2] = 0"; return LBM_EINVAL; }
   if (p->streaming < LBM_STREAM_AUTO || p->streaming > LBM_STREAM_ONE_BUFFER) { why = "unknown streaming layout"; return LBM_EINVAL; }
   if (p->streaming == LBM_STREAM_ONE_BUFFER &&
       (p->model != LBM_MODEL_BGK || p->collision != LBM_COLLIDE_PLAIN ||
@@ -278,6 +288,9 @@ int lbm_create(const lbm_params* p, const double* rho0, const double* u0, const 
   c->G = P.G;
   c->stream = static_cast<hipStream_t>(p->stream);
   c->omega = 1.0 / p->tau;  // omega = 2 beta = 1/tau_LB
+  c->F.x = p->force[0];
+  c->F.y = p->force[1];
+  c->F.z = c->D == 3 ? p->force[2] : 0.0;
   c->partial_slots = P.partial_slots;
   auto cleanup_fail = [&](int code) {
     std::string m = c->err;
@@ -336,7 +349,7 @@ int lbm_create(const lbm_params* p, const double* rho0, const double* u0, const 
   } else if (e == hipSuccess && c->codec >= 0) {
     e = launch_init_bgk_red(c->readout, c->readout + nodes, c->A, c->L, c->stream);
   } else if (e == hipSuccess) {
-    e = launch_init_bgk(c->kind, c->D, c->readout, c->readout + nodes, c->A, c->L, c->aa, c->stream);
+    e = launch_init_bgk(c->kind, c->D, c->readout, c->readout + nodes, c->A, c->L, c->aa, c->omega, c->F, c->stream);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
@@ -365,13 +378,13 @@ int lbm_step(lbm_ctx* c, int64_t n) {
     else if (c->codec >= 0)
       e = launch_bgk_d2q9_red(c->codec, c->A, c->B, c->L, c->G, c->omega, c->p.wall_y != 0, c->s_enc, c->s_dec, part, c->stream);
     else if (c->aa && c->D == 2)
-      e = launch_bgk_d2q9_aa(c->kind, (c->t & 1) != 0, c->A, c->L, c->G, c->omega, c->p.wall_y != 0, part, c->stream);
+      e = launch_bgk_d2q9_aa(c->kind, (c->t & 1) != 0, c->A, c->L, c->G, c->omega, c->F, c->p.wall_y != 0, part, c->stream);
     else if (c->aa)
-      e = launch_bgk_d3q27_aa(c->kind, (c->t & 1) != 0, c->A, c->L, c->G, c->omega, c->p.wall_y != 0, part, c->stream);
+      e = launch_bgk_d3q27_aa(c->kind, (c->t & 1) != 0, c->A, c->L, c->G, c->omega, c->F, c->p.wall_y != 0, part, c->stream);
     else if (c->D == 2)
-      e = launch_bgk_d2q9(c->kind, c->A, c->B, c->L, c->G, c->omega, c->p.wall_y != 0, part, c->stream);
+      e = launch_bgk_d2q9(c->kind, c->A, c->B, c->L, c->G, c->omega, c->F, c->p.wall_y != 0, part, c->stream);
     else
-      e = launch_bgk_d3q27(c->kind, c->A, c->B, c->L, c->G, c->omega, c->p.wall_y != 0, part, c->stream);
+      e = launch_bgk_d3q27(c->kind, c->A, c->B, c->L, c->G, c->omega, c->F, c->p.wall_y != 0, part, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "step kernel launch");
     if (diag) {
       double* slot = c->history + (c->hist_written % kHistoryCap) * 6;
@@ -421,7 +434,7 @@ int lbm_moments(lbm_ctx* c, double* rho, double* u, double* T, double* totals) {
   else if (c->codec >= 0)
     HIP_TRY(c, launch_moments_bgk_red(c->A, c->L, d_rho, d_u, c->stream));
   else
-    HIP_TRY(c, launch_moments_bgk(c->kind, c->D, c->A, c->L, view_of(c), c->p.wall_y != 0, d_rho, d_u, c->stream));
+    HIP_TRY(c, launch_moments_bgk(c->kind, c->D, c->A, c->L, view_of(c), c->p.wall_y != 0, c->F, d_rho, d_u, c->stream));
   if (totals) {
     const int nparts = std::min(512, c->partial_slots - 2);
     double* out = c->partials + (size_t)nparts * kDiagValues;  // 6 doubles after the partials
@@ -509,8 +522,8 @@ int lbm_mlp_stats(lbm_ctx* c, int64_t* fallbacks, int64_t* updates) {
 
 int lbm_harvest(lbm_ctx* c, int64_t n, const int64_t* dev_nodes, float* dev_x, float* dev_y) {
   if (!c) return fail(nullptr, LBM_ESTATE, "NULL context");
-  if (c->D != 2 || c->ddf || c->kind != 0 || c->codec >= 0)
-    return fail(c, LBM_EINVAL, "harvest needs a D2Q9 isothermal context with float32 storage");
+  if (c->D != 2 || c->ddf || c->kind != 0 || c->codec >= 0 || c->F.on())
+    return fail(c, LBM_EINVAL, "harvest needs a D2Q9 isothermal context with float32 storage and no force");
   if (n < 0 || (n > 0 && (!dev_nodes || !dev_x || !dev_y))) return fail(c, LBM_EINVAL, "invalid harvest buffers");
   if (n == 0) return LBM_OK;
   HIP_TRY(c, launch_harvest(c->A, c->L, c->p.wall_y != 0, view_of(c), c->omega, dev_nodes, n, dev_x, dev_y, c->stream));

@@ -31,6 +31,12 @@ struct Grid {
   int blocks() const { return nbx * nby; }
 };
 
+// Uniform body force per unit volume (lattice units); zero when the context has none.
+struct Force {
+  double x = 0.0, y = 0.0, z = 0.0;
+  bool on() const { return x != 0.0 || y != 0.0 || z != 0.0; }
+};
+
 // Workgroups along the second grid dimension are kept within 65536 (the launch limit of this
 // dimension on the device): lattices with more rows give each workgroup more rows.
 constexpr int kMaxGridY = 65536;
@@ -61,20 +67,26 @@ struct DdfParams {
 // ---- launchers (return the first HIP error) -----------------------------------------------
 // Real = float (kind 0) or double (kind 1).
 hipError_t launch_bgk_d2q9(int kind, const void* A, void* B, const Layout& L, const Grid& G,
-                           double omega, bool walls, double* partials, hipStream_t s);
+                           double omega, const Force& F, bool walls, double* partials,
+                           hipStream_t s);
 hipError_t launch_bgk_d3q27(int kind, const void* A, void* B, const Layout& L, const Grid& G,
-                            double omega, bool walls, double* partials, hipStream_t s);
+                            double omega, const Force& F, bool walls, double* partials,
+                            hipStream_t s);
 // Single-buffer steps (in place on A); odd = the step count so far is odd.
 hipError_t launch_bgk_d2q9_aa(int kind, bool odd, void* A, const Layout& L, const Grid& G,
-                              double omega, bool walls, double* partials, hipStream_t s);
+                              double omega, const Force& F, bool walls, double* partials,
+                              hipStream_t s);
 hipError_t launch_bgk_d3q27_aa(int kind, bool odd, void* A, const Layout& L, const Grid& G,
-                               double omega, bool walls, double* partials, hipStream_t s);
-// swap: store population i in slot Q-1-i (single-buffer state at an even step count).
+                               double omega, const Force& F, bool walls, double* partials,
+                               hipStream_t s);
+// swap: store population i in slot Q-1-i (single-buffer state at an even step count). With a
+// force the equilibrium is collided once (the stored state is post-collision at t = 0).
 hipError_t launch_init_bgk(int kind, int D, const double* rho, const double* u, void* A,
-                           const Layout& L, bool swap, hipStream_t s);
+                           const Layout& L, bool swap, double omega, const Force& F,
+                           hipStream_t s);
 // view: -1 two-buffer state; 0 / 1 single-buffer state after an even / odd step count.
 hipError_t launch_moments_bgk(int kind, int D, const void* A, const Layout& L, int view,
-                              bool walls, double* rho, double* u, hipStream_t s);
+                              bool walls, const Force& F, double* rho, double* u, hipStream_t s);
 // Post-collision population i of the stored state decoded to float64 f_i (nodes values, no
 // padding).
 hipError_t launch_decode_f(int kind, int D, int i, const void* A, const Layout& L, int view,

@@ -138,3 +138,36 @@ def test_one_buffer_layout_rejected_where_unsupported(lib, kw):
     assert b"one-buffer" in lib.lbm_last_error(None)
     rc, _ = _workspace(lib, streaming=binding.STREAMINGS["auto"], **kw)
     assert rc == 0
+
+
+@pytest.mark.parametrize("kw", [dict(model=1), dict(storage=1), dict(storage=2),
+                                dict(collision=1), dict(force_z=1e-6),
+                                dict(force_x=float("nan")), dict(force_y=float("inf"))])
+def test_body_force_rejected_where_unsupported(lib, kw):
+    kw = dict(kw)
+    force = [kw.pop("force_x", 1e-6), kw.pop("force_y", 0.0), kw.pop("force_z", 0.0)]
+    p = binding.LbmParams()
+    lib.lbm_default_params(ctypes.byref(p))
+    assert list(p.force) == [0.0, 0.0, 0.0]  # default: no force
+    for k, v in kw.items():
+        setattr(p, k, v)
+    for a in range(3):
+        p.force[a] = force[a]
+    n = ctypes.c_size_t(0)
+    assert lib.lbm_workspace_size(ctypes.byref(p), ctypes.byref(n)) == binding.LBM_EINVAL
+    assert b"force" in lib.lbm_last_error(None)
+
+
+@pytest.mark.parametrize("lattice, nz, force", [(0, 1, (1e-6, -2e-6, 0.0)),
+                                                (1, 8, (0.0, 1e-6, 3e-6))])
+def test_body_force_accepted_for_the_isothermal_model(lib, lattice, nz, force):
+    for storage in (0, 3):  # float32, float64
+        for streaming in (1, 2):
+            p = binding.LbmParams()
+            lib.lbm_default_params(ctypes.byref(p))
+            p.lattice, p.nx, p.ny, p.nz = lattice, 8, 8, nz
+            p.storage, p.streaming = storage, streaming
+            for a in range(3):
+                p.force[a] = force[a]
+            n = ctypes.c_size_t(0)
+            assert lib.lbm_workspace_size(ctypes.byref(p), ctypes.byref(n)) == 0
