@@ -118,6 +118,12 @@ int lbm_create(const lbm_params* p, const double* rho0, const double* u0, const 
    end and returns LBM_EUNSTABLE if any totals recorded during the call are non-finite. */
 int lbm_step(lbm_ctx* ctx, int64_t n);
 
+/* Replace the uniform body force (force[3], as lbm_params.force) for the collisions of the
+   following steps, e.g. a force that varies in time. The stored state keeps the force of the
+   collision that produced it, which lbm_moments uses (rho u = sum c f~ - F/2 after a forced
+   collision). LBM_EINVAL where lbm_params.force would be rejected; no device work. */
+int lbm_set_force(lbm_ctx* ctx, const double* force);
+
 /* Time n steps with HIP events recorded on the context stream around the launches; *ms is
    the elapsed time in milliseconds. Synchronises. */
 int lbm_time_steps(lbm_ctx* ctx, int64_t n, float* ms);

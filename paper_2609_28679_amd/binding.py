@@ -51,6 +51,7 @@ SIGNATURES = {
     "lbm_workspace_size": (ctypes.c_int, [ctypes.POINTER(LbmParams), ctypes.POINTER(ctypes.c_size_t)]),
     "lbm_create": (ctypes.c_int, [ctypes.POINTER(LbmParams), _D, _D, _D, ctypes.POINTER(_P)]),
     "lbm_step": (ctypes.c_int, [_P, _I64]),
+    "lbm_set_force": (ctypes.c_int, [_P, _D]),
     "lbm_time_steps": (ctypes.c_int, [_P, _I64, _F]),
     "lbm_moments": (ctypes.c_int, [_P, _D, _D, _D, _D]),
     "lbm_populations": (ctypes.c_int, [_P, _D, _D]),
@@ -173,6 +174,14 @@ class Lattice:
     # -- hot path --------------------------------------------------------------------------
     def step(self, n=1):
         _check(load().lbm_step(self.ctx, int(n)), self.ctx)
+
+    def set_force(self, force):
+        """Uniform body force (D components) for the collisions of the following steps."""
+        fv = [float(v) for v in force]
+        if len(fv) != self.D:
+            raise ValueError("force must have %d components" % self.D)
+        arr = (ctypes.c_double * 3)(*(fv + [0.0] * (3 - self.D)))
+        _check(load().lbm_set_force(self.ctx, arr), self.ctx)
 
     def time_steps(self, n):
         ms = ctypes.c_float(0.0)

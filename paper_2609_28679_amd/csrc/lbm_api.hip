@@ -47,7 +47,8 @@ struct lbm_ctx {
   int64_t hist_written = 0;
   int64_t t = 0;
   double omega = 0.0;
-  Force F;  // uniform body force (zero: none)
+  Force F;        // uniform body force of the next collision (zero: none)
+  Force F_state;  // force of the collision that produced the stored state (read-outs)
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   float* mlp_w = nullptr;                  // surrogate weights (kMlpParams floats)
   unsigned long long* mlp_cnt = nullptr;   // {fallbacks, updates}
@@ -98,6 +99,21 @@ struct Plan {
   int partial_slots;
 };
 
+// A body force is supported by the isothermal model with the paper's collision and FP32 or FP64
+// storage; it must be finite, and its z component zero on D2Q9.
+int validate_force(const lbm_params* p, const double* force, std::string& why) {
+  const bool forced = force[0] != 0.0 || force[1] != 0.0 || force[2] != 0.0;
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(force[a])) { why = "force must be finite"; return LBM_EINVAL; }
+  if (forced && (p->model != LBM_MODEL_BGK || p->collision != LBM_COLLIDE_PLAIN ||
+                 (p->storage != LBM_STORE_FP32 && p->storage != LBM_STORE_FP64))) {
+    why = "a body force needs the isothermal model, the paper's collision and FP32 or FP64 storage";
+    return LBM_EINVAL;
+  }
+  if (forced && p->lattice == LBM_D2Q9 && force[2] != 0.0) { why = "D2Q9 requires force[2] = 0"; return LBM_EINVAL; }
+  return LBM_OK;
+}
+
 int validate(const lbm_params* p, std::string& why) {
   if (!p) { why = "params is NULL"; return LBM_EINVAL; }
   if (p->lattice != LBM_D2Q9 && p->lattice != LBM_D3Q27) { why = "lattice must be D2Q9 or D3Q27"; return LBM_EINVAL; }
@@ -124,15 +140,7 @@ int validate(const lbm_params* p, std::string& why) {
     return LBM_EINVAL;
   }
   if (!(p->mlp_tol >= 0.0)) { why = "mlp_tol must be >= 0"; return LBM_EINVAL; }
-  const bool forced = p->force[0] != 0.0 || p->force[1] != 0.0 || p->force[2] != 0.0;
-  for (int a = 0; a < 3; ++a)
-    if (!std::isfinite(p->force[a])) { why = "force must be finite"; return LBM_EINVAL; }
-  if (forced && (p->model != LBM_MODEL_BGK || p->collision != LBM_COLLIDE_PLAIN ||
-                 (p->storage != LBM_STORE_FP32 && p->storage != LBM_STORE_FP64))) {
-    why = "a body force needs the isothermal model, the paper's collision and FP32 or FP64 storage";
-    return LBM_EINVAL;
-  }
-  if (forced && p->lattice == LBM_D2Q9 && p->force[2] != 0.0) { why = "D2Q9 requires force[2] = 0"; return LBM_EINVAL; }
+  if (int rc = validate_force(p, p->force, why)) return rc;
   if (p->streaming < LBM_STREAM_AUTO || p->streaming > LBM_STREAM_ONE_BUFFER) { why = "unknown streaming layout"; return LBM_EINVAL; }
   if (p->streaming == LBM_STREAM_ONE_BUFFER &&
       (p->model != LBM_MODEL_BGK || p->collision != LBM_COLLIDE_PLAIN ||
@@ -291,6 +299,7 @@ int lbm_create(const lbm_params* p, const double* rho0, const double* u0, const 
   c->F.x = p->force[0];
   c->F.y = p->force[1];
   c->F.z = c->D == 3 ? p->force[2] : 0.0;
+  c->F_state = c->F;
   c->partial_slots = P.partial_slots;
   auto cleanup_fail = [&](int code) {
     std::string m = c->err;
@@ -394,6 +403,7 @@ int lbm_step(lbm_ctx* c, int64_t n) {
     }
     if (!c->aa) std::swap(c->A, c->B);
     c->t = tn;
+    c->F_state = c->F;
   }
   if (c->hist_written > hist_before) {
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -407,6 +417,17 @@ int lbm_step(lbm_ctx* c, int64_t n) {
           return fail(c, LBM_EUNSTABLE, "non-finite conservation total at t = " + std::to_string((int64_t)h[slot * 6]));
     }
   }
+  return LBM_OK;
+}
+
+int lbm_set_force(lbm_ctx* c, const double* force) {
+  if (!c) return fail(nullptr, LBM_ESTATE, "NULL context");
+  if (!force) return fail(c, LBM_EINVAL, "force is NULL");
+  std::string why;
+  if (int rc = validate_force(&c->p, force, why)) return fail(c, rc, why);
+  c->F.x = force[0];
+  c->F.y = force[1];
+  c->F.z = c->D == 3 ? force[2] : 0.0;
   return LBM_OK;
 }
 
@@ -434,7 +455,7 @@ int lbm_moments(lbm_ctx* c, double* rho, double* u, double* T, double* totals) {
   else if (c->codec >= 0)
     HIP_TRY(c, launch_moments_bgk_red(c->A, c->L, d_rho, d_u, c->stream));
   else
-    HIP_TRY(c, launch_moments_bgk(c->kind, c->D, c->A, c->L, view_of(c), c->p.wall_y != 0, c->F, d_rho, d_u, c->stream));
+    HIP_TRY(c, launch_moments_bgk(c->kind, c->D, c->A, c->L, view_of(c), c->p.wall_y != 0, c->F_state, d_rho, d_u, c->stream));
   if (totals) {
     const int nparts = std::min(512, c->partial_slots - 2);
     double* out = c->partials + (size_t)nparts * kDiagValues;  // 6 doubles after the partials
@@ -522,7 +543,7 @@ int lbm_mlp_stats(lbm_ctx* c, int64_t* fallbacks, int64_t* updates) {
 
 int lbm_harvest(lbm_ctx* c, int64_t n, const int64_t* dev_nodes, float* dev_x, float* dev_y) {
   if (!c) return fail(nullptr, LBM_ESTATE, "NULL context");
-  if (c->D != 2 || c->ddf || c->kind != 0 || c->codec >= 0 || c->F.on())
+  if (c->D != 2 || c->ddf || c->kind != 0 || c->codec >= 0 || c->F.on() || c->F_state.on())
     return fail(c, LBM_EINVAL, "harvest needs a D2Q9 isothermal context with float32 storage and no force");
   if (n < 0 || (n > 0 && (!dev_nodes || !dev_x || !dev_y))) return fail(c, LBM_EINVAL, "invalid harvest buffers");
   if (n == 0) return LBM_OK;

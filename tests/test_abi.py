@@ -95,6 +95,7 @@ def test_create_rejects_inadmissible_initial_state_before_device_work(lib):
 
 def test_null_context_is_a_state_error(lib):
     assert lib.lbm_step(None, 1) == binding.LBM_ESTATE
+    assert lib.lbm_set_force(None, (ctypes.c_double * 3)(0.0, 0.0, 0.0)) == binding.LBM_ESTATE
     lib.lbm_destroy(None)  # NULL-safe
 
 

@@ -163,3 +163,37 @@ def test_poiseuille_profile(storage, tol):
     assert rel_l2(ug[0], np.broadcast_to(uo[:, None], (ny, nx))) <= tol
     assert np.abs(ug[1]).max() <= 1e-6 * exact.max()
     assert rel_l2(uo, exact) <= 3e-3
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_womersley_time_varying_force(storage):
+    # Sec. III A: pulsatile channel flow at Wo = 4 with the force changed before every step;
+    # the GPU samples of the last period match the oracle's, and both the analytic solution
+    from womersley import Case, oracle_samples
+    case = Case(32)
+    nx = 64
+    announce("D2Q9 Womersley ny=%d %s %d steps" % (case.ny, storage, case.nsteps))
+    rho = np.ones((case.ny, nx))
+    u = np.zeros((2, case.ny, nx))
+    u[0] = case.initial_ux()[:, None]
+    lat = _lattice(rho, u, storage=storage, wall_y=True, tau=case.tau,
+                   force=(case.force(0), 0.0))
+    want = set(case.samples)
+    gpu = {}
+    for t in range(case.nsteps + 1):
+        if t in want:
+            _, ug, _, _ = lat.moments()
+            assert np.abs(ug[0] - ug[0][:, :1]).max() <= 1e-6 * np.abs(ug[0]).max()
+            gpu[t] = ug[0][:, 0].copy()
+        lat.set_force((case.force(t + 1), 0.0))
+        lat.step(1)
+    lat.close()
+    ref = oracle_samples(case)
+    if storage == "fp64":  # rounding order only: the float64 bar on velocity
+        assert max(np.abs(gpu[t] - ref[t]).max() for t in case.samples) <= 1e-13
+    else:
+        num = sum(((gpu[t] - ref[t]) ** 2).sum() for t in case.samples)
+        den = sum((ref[t] ** 2).sum() for t in case.samples)
+        assert np.sqrt(num / den) <= 1e-5
+    assert case.rel_l2(gpu) <= 1.5e-3
+
