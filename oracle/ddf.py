@@ -1,20 +1,26 @@
 """Double-distribution scheme for an ideal gas, Sec. II C with Fig. 1 and Sec. III A.
 
-Per node and step, in the order of Fig. 1 (no body force and no heat source, F = Q = 0):
-  rho = sum f,  rho u = sum c f,  rho E = sum g                    (Sec. II C moments)
+Per node and step, in the order of Fig. 1, with an optional uniform body force F (per unit
+volume) and heat source Q (energy per unit volume and time); dt = 1:
+  rho = sum f,  rho u = sum c f + F/2,  rho E = sum g + (u.F + Q)/2   (Sec. II C moments)
   T = (E - u^2/2) / c_v,  P = rho R T                               (Sec. III A, ideal gas)
   theta = P / rho                                                   (Sec. II A closure)
-  u* = u;  theta* = theta                                            (shifts with F = Q = 0
-        and alpha = 0, which the bulk viscosity eta = mu (2/D - R/c_v) of Sec. II E gives)
-  Phi_aa = -(1/rho) d_a (rho u_a^3 + 3 rho u_a (theta - varsigma^2))  (Galilean correction)
-  f^eq, f* = rho prod Psi(u*, theta* + u*^2 + Phi), g^eq                (Sec. II C)
-  g* = g^eq(rho, u*, T*, theta*) + q^c term; with F = Q = 0, T* = T, and for the ideal gas at
-       Prandtl number 1 (k = mu c_p) the flux q^c = dt P (grad h - (k/mu) grad T) vanishes
-       identically because h = c_p T, so g* = g^eq
+  u* = u + F/rho                                                    (shifted velocity)
+  theta* = theta + alpha theta div u + (gamma - 1) Q/rho with alpha = 0, which the bulk
+        viscosity eta = mu (2/D - R/c_v) of Sec. II E gives, and gamma - 1 = R/c_v for the
+        ideal gas (Sec. II A, gamma = 1 + (dP/dT)_rho / (rho c_v))
+  T* = T + Q/(rho c_v) - F.F/(2 rho^2 c_v)                          (shifted temperature)
+  Phi_aa = -(1/rho) d_a (rho u_a^3 + 3 rho u_a (theta - varsigma^2))  (Galilean correction,
+        from the unshifted fields)
+  f^eq = rho prod Psi(u, theta + u^2),  f* = rho prod Psi(u*, theta* + u*^2 + Phi)   (Sec. II C)
+  g^eq = g^eq(rho, u, T, theta),  g* = g^eq(rho, u*, T*, theta*) + q^c term; for the ideal
+       gas at Prandtl number 1 (k = mu c_p) the flux q^c = dt P (grad h - (k/mu) grad T)
+       vanishes identically because h = c_p T
   tau = mu / P,  beta = dt / (2 tau + dt)                            (Sec. II A, II B)
   f~ = f + 2 beta (f^eq - f) + (1 - beta)(f* - f^eq)                   (Eq. LBM_f)
   g~ = g + 2 beta (g^eq - g) + (1 - beta)(g* - g^eq)                   (Eq. LBM_g)
   stream both (periodic in x, half-way bounce-back at the y walls when enabled).
+Without sources (F = 0, Q = 0) u* = u, theta* = theta, T* = T and g* = g^eq.
 
 Derivative inside the Galilean correction. The paper computes all derivatives with standard
 second-order central differences, except the first derivative of the correction, for which it
@@ -44,6 +50,21 @@ class Gas:
         self.R = float(R)
         self.cv = float(cv)
         self.mu = float(mu)
+
+    @property
+    def gamma(self):
+        """gamma = 1 + (dP/dT)_rho / (rho c_v) with P = rho R T: 1 + R/c_v = c_p/c_v."""
+        return 1.0 + self.R / self.cv
+
+
+def _field(F, D, shape):
+    """The force as a (D,) + node-shape array (zero when F is None)."""
+    if F is None:
+        return np.zeros((D,) + shape)
+    F = np.asarray(F, dtype=np.float64)
+    if F.ndim == 1:  # one vector for every node
+        F = F.reshape((D,) + (1,) * len(shape))
+    return np.broadcast_to(F, (D,) + shape)
 
 
 def closure(rho, u, rhoE, gas):
@@ -103,28 +124,34 @@ def galilean_correction(rho, u, theta, walls_y, stencil="central"):
     return out
 
 
-def equilibria(rho, u, rhoE, gas, walls_y, phi_on=True, stencil="central"):
-    """f^eq, f*, g^eq (= g*), beta at every node (Fig. 1 order)."""
+def equilibria(rho, u, rhoE, gas, walls_y, phi_on=True, stencil="central", F=None, Q=0.0):
+    """f^eq, f*, g^eq, g*, beta at every node (Fig. 1 order) from the moments (rho, u, rho E
+    already carry the half-step source terms)."""
+    D = u.shape[0]
     T, P, theta = closure(rho, u, rhoE, gas)
     e = gas.cv * T
+    Fv = _field(F, D, rho.shape)
+    ustar = u + Fv / rho
+    thetastar = theta + (gas.gamma - 1.0) * Q / rho
+    Tstar = T + Q / (rho * gas.cv) - (Fv * Fv).sum(axis=0) / (2.0 * rho * rho * gas.cv)
     fe = feq(rho, u, theta)
-    if phi_on:
-        Phi = galilean_correction(rho, u, theta, walls_y, stencil)
-        fs = fstar(rho, u, theta, Phi)
-    else:
-        fs = fe
+    Phi = galilean_correction(rho, u, theta, walls_y, stencil) if phi_on else np.zeros_like(u)
+    fs = fstar(rho, ustar, thetastar, Phi)
     ge = geq(rho, u, theta, e)
+    gs = geq(rho, ustar, thetastar, gas.cv * Tstar)
     tau = gas.mu / P
     beta = 1.0 / (2.0 * tau + 1.0)
-    return fe, fs, ge, beta
+    return fe, fs, ge, gs, beta
 
 
-def moments(f, g):
+def moments(f, g, F=None, Q=0.0):
+    """rho = sum f, rho u = sum c f + F/2, rho E = sum g + (u.F + Q)/2 (Sec. II C)."""
     D = {9: 2, 27: 3}[f.shape[0]]
     c = velocities(D).astype(np.float64)
     rho = f.sum(axis=0)
-    u = np.stack([np.tensordot(c[:, a], f, axes=(0, 0)) for a in range(D)]) / rho
-    return rho, u, g.sum(axis=0)
+    Fv = _field(F, D, rho.shape)
+    u = (np.stack([np.tensordot(c[:, a], f, axes=(0, 0)) for a in range(D)]) + 0.5 * Fv) / rho
+    return rho, u, g.sum(axis=0) + 0.5 * ((u * Fv).sum(axis=0) + Q)
 
 
 def init_equilibrium(rho, u, T, gas):
@@ -133,23 +160,23 @@ def init_equilibrium(rho, u, T, gas):
     return feq(rho, u, theta), geq(rho, u, theta, gas.cv * T)
 
 
-def collide(f, g, gas, walls_y, phi_on=True, stencil="central"):
-    rho, u, rhoE = moments(f, g)
-    fe, fs, ge, beta = equilibria(rho, u, rhoE, gas, walls_y, phi_on, stencil)
+def collide(f, g, gas, walls_y, phi_on=True, stencil="central", F=None, Q=0.0):
+    rho, u, rhoE = moments(f, g, F, Q)
+    fe, fs, ge, gs, beta = equilibria(rho, u, rhoE, gas, walls_y, phi_on, stencil, F, Q)
     ft = f + 2.0 * beta * (fe - f) + (1.0 - beta) * (fs - fe)
-    gt = g + 2.0 * beta * (ge - g)
+    gt = g + 2.0 * beta * (ge - g) + (1.0 - beta) * (gs - ge)
     return ft, gt
 
 
-def run(f, g, gas, nsteps, walls_y=True, phi_on=True, stencil="central"):
+def run(f, g, gas, nsteps, walls_y=True, phi_on=True, stencil="central", F=None, Q=0.0):
     for _ in range(nsteps):
-        ft, gt = collide(f, g, gas, walls_y, phi_on, stencil)
+        ft, gt = collide(f, g, gas, walls_y, phi_on, stencil, F, Q)
         f = bgk.stream(ft, walls_y)
         g = bgk.stream(gt, walls_y)
     return f, g
 
 
-def temperature(f, g, gas):
-    rho, u, rhoE = moments(f, g)
+def temperature(f, g, gas, F=None, Q=0.0):
+    rho, u, rhoE = moments(f, g, F, Q)
     T, _, _ = closure(rho, u, rhoE, gas)
     return rho, u, T

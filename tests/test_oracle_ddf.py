@@ -215,3 +215,105 @@ def test_galilean_correction_vanishes_at_rest_and_is_cubic_at_reference_temperat
     Phi_u = ddf.galilean_correction(rho_lin, u, np.full((6, 7), 1.0 / 3.0), False, "upwind")
     np.testing.assert_allclose(Phi_u[0][:, 2:], -(0.01 * 0.1 ** 3) / rho_lin[:, 2:], rtol=1e-9)
     np.testing.assert_allclose(Phi[1], 0.0, atol=1e-18)
+
+
+# ---- body force and heat source (Sec. II C: rho u = sum c f + F/2, rho E = sum g + (u.F + Q)/2,
+# shifted u*, theta*, T*; ideal gas, alpha = 0, Pr = 1) ----------------------------------------
+
+def _velocity_moment2(f, a):
+    """sum_i c_ia^2 f_i (D2Q9)."""
+    from oracle.lattice import velocities
+    c = velocities(2).astype(np.float64)
+    return np.tensordot(c[:, a] ** 2, f, axes=(0, 0))
+
+
+def test_isochoric_heating_raises_temperature_by_q_over_rho_cv_per_step():
+    # Sec. III B (isochoric heating): a uniform heat source on a periodic box at rest raises
+    # T by exactly Q / (rho c_v) and P = rho R T by exactly R Q / c_v per step; the read-out at
+    # t = 0 already holds half a step of heating
+    gas = _gas()
+    rho0, T0, Q = 1.2, 0.9, 1e-4
+    rho = np.full((4, 5), rho0)
+    f, g = ddf.init_equilibrium(rho, np.zeros((2, 4, 5)), np.full((4, 5), T0), gas)
+    for t in range(8):
+        r, u, T = ddf.temperature(f, g, gas, Q=Q)
+        expect = T0 + Q / (2 * rho0 * CV) + t * Q / (rho0 * CV)
+        assert np.abs(T - expect).max() <= 1e-14
+        assert np.abs(u).max() <= 1e-16
+        np.testing.assert_allclose(r, rho0, rtol=1e-15)
+        ft, gt = ddf.collide(f, g, gas, False, True, "central", Q=Q)
+        f, g = bgk.stream(ft), bgk.stream(gt)
+
+
+def test_heated_pressure_tensor_tracks_the_thermodynamic_pressure():
+    # the shift theta* = theta + (gamma - 1) Q/rho makes the second moment of f, averaged over
+    # the collision, equal P = rho R T at every step of uniform heating; without it the
+    # populations lag the heating by a viscosity-dependent amount (~1e-5 relative here)
+    gas = _gas(0.8)
+    rho0, T0, Q = 1.1, 0.8, 2e-4
+    f, g = ddf.init_equilibrium(np.full((3, 4), rho0), np.zeros((2, 3, 4)), np.full((3, 4), T0), gas)
+    for _ in range(10):
+        r, _, T = ddf.temperature(f, g, gas, Q=Q)
+        ft, gt = ddf.collide(f, g, gas, False, True, "central", Q=Q)
+        for a in range(2):
+            mid = 0.5 * (_velocity_moment2(f, a) + _velocity_moment2(ft, a))
+            assert np.abs(mid - r * R * T).max() <= 1e-14
+        f, g = bgk.stream(ft), bgk.stream(gt)
+
+
+def test_uniform_force_accelerates_without_heating():
+    # no gradients: u gains F/rho per step, and the F.F term of T* keeps the temperature exactly
+    # constant (the force's work goes into kinetic energy only)
+    gas = _gas()
+    rho0, T0 = 1.2, 0.9
+    u0, F = np.array([0.02, 0.01]), np.array([1e-4, -2e-4])
+    f, g = ddf.init_equilibrium(np.full((4, 4), rho0), u0[:, None, None] * np.ones((2, 4, 4)),
+                                np.full((4, 4), T0), gas)
+    T_first = None
+    for t in range(8):
+        _, u, T = ddf.temperature(f, g, gas, F=F)
+        expect = u0 + F / (2 * rho0) + t * F / rho0
+        assert np.abs(u - expect[:, None, None]).max() <= 1e-15
+        T_first = T if T_first is None else T_first
+        assert np.abs(T - T_first).max() <= 1e-15
+        ft, gt = ddf.collide(f, g, gas, False, True, "central", F=F)
+        f, g = bgk.stream(ft), bgk.stream(gt)
+
+
+@pytest.mark.parametrize("stencil", ["central", "upwind"])
+def test_source_budget_on_a_periodic_field(stencil):
+    # streaming conserves the sums on a periodic lattice, so per step the total sum of g grows
+    # by exactly sum(u.F) + nodes Q (u the half-step velocity) and sum c f by nodes F
+    gas = _gas()
+    rng = np.random.default_rng(1)
+    rho = 1.0 + 0.05 * rng.standard_normal((8, 10))
+    u = 0.05 * rng.standard_normal((2, 8, 10))
+    T = 0.9 + 0.05 * rng.standard_normal((8, 10))
+    F, Q = np.array([1e-4, -2e-4]), 2e-4
+    from oracle.lattice import velocities
+    c = velocities(2).astype(np.float64)
+    f, g = ddf.init_equilibrium(rho, u, T, gas)
+    for _ in range(5):
+        r, v, _ = ddf.moments(f, g, F, Q)
+        ft, gt = ddf.collide(f, g, gas, False, True, stencil, F, Q)
+        f2, g2 = bgk.stream(ft), bgk.stream(gt)
+        expect = (v * F[:, None, None]).sum() + Q * r.size
+        assert abs((g2.sum() - g.sum()) / expect - 1.0) <= 1e-11
+        for a in range(2):
+            dj = np.tensordot(c[:, a], f2 - f, axes=(0, 0)).sum()
+            assert abs(dj / (F[a] * r.size) - 1.0) <= 1e-11
+        np.testing.assert_allclose(f2.sum(), f.sum(), rtol=1e-15)
+        f, g = f2, g2
+
+
+def test_zero_sources_are_the_unforced_scheme():
+    gas = _gas()
+    rng = np.random.default_rng(2)
+    rho = 1.0 + 0.05 * rng.standard_normal((6, 7))
+    u = 0.05 * rng.standard_normal((2, 6, 7))
+    T = 0.9 + 0.05 * rng.standard_normal((6, 7))
+    f0, g0 = ddf.init_equilibrium(rho, u, T, gas)
+    a = ddf.run(f0, g0, gas, 6, walls_y=True)
+    b = ddf.run(f0, g0, gas, 6, walls_y=True, F=np.zeros(2), Q=0.0)
+    for x, y in zip(a, b):
+        assert np.abs(x - y).max() == 0.0
