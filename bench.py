@@ -222,10 +222,10 @@ def main():
         tgv3 = lambda: get("tgv256", lambda: inputs.taylor_green_3d(256, 0.05))
         shear4 = lambda: get("shear4096", lambda: inputs.thermal_shear_layer(n4, seed=0))
 
-        def ddf_lattice(storage, phi=1):
+        def ddf_lattice(storage, phi=1, **kw):
             rs, us, ts = shear4()
             return binding.Lattice(rs, us, ts, model="ddf", tau=0.6, wall_y=True, phi=phi,
-                                   storage=storage)
+                                   storage=storage, **kw)
 
         red = "fp32 moments + %s f-f_eq (6 of 9 stored)"
         red_ddf = "fp32 moments + %s non-equilibrium (6 f + 8 g of 18 stored)"
@@ -250,6 +250,11 @@ def main():
             ("d2q9_ddf_fp32_4096", lambda n: variant(
                 n, lambda: ddf_lattice("fp32"), max(100, vs // 4), 10, 144,
                 {"walls": "y", "phi": "central"})),
+            ("d2q9_ddf_fp32_4096_sources", lambda n: variant(
+                n, lambda: ddf_lattice("fp32", force=(1e-7, 0.0), heat_source=1e-8),
+                max(100, vs // 4), 10, 144,
+                {"walls": "y", "phi": "central",
+                 "sources": "uniform force (1e-7, 0) and heat source 1e-8"})),
             ("d2q9_ddf_fp32_4096_upwind", lambda n: variant(
                 n, lambda: ddf_lattice("fp32", phi=2), max(100, vs // 4), 10, 144,
                 {"walls": "y", "phi": "upwind"})),

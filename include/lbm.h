@@ -78,9 +78,13 @@ typedef struct {
   double R, cv;        /* DDF ideal gas constant and heat capacity (Sec. III A); Pr = 1 and the
                           bulk viscosity eta = mu (2/D - R/c_v) (Sec. II E) so alpha = 0 */
   double force[3];     /* uniform body force per unit volume F (lattice units), applied through
-                          the shifted equilibrium f^* at u + F/rho (Sec. II C) with
-                          rho u = sum c f + F/2. Isothermal model with the paper's collision and
-                          FP32/FP64 storage only; force[2] = 0 for D2Q9; all zero = no force. */
+                          the shifted equilibria at u* = u + F/rho (Sec. II C) with
+                          rho u = sum c f + F/2 (DDF: also T* and rho E = sum g + u.F/2).
+                          The paper's collision with FP32/FP64 storage only; force[2] = 0 for
+                          D2Q9; all zero = no force. */
+  double heat_source;  /* DDF only: uniform heat source Q per unit volume and time step, applied
+                          through theta* = theta + (gamma - 1) Q/rho and T* = T + Q/(rho c_v)
+                          with rho E = sum g + Q/2 (Sec. II C); FP32/FP64 storage; 0 = none. */
   int32_t phi;         /* DDF: 1 = Galilean correction Phi on (the paper), 0 = off */
   int32_t fp16_scale_log2; /* LBM_STORE_FP16: S in [0, 24]; stored value = (f - f^eq) * 2^S */
   int32_t diag_every;  /* > 0: every diag_every steps record float64 totals (mass, momentum,
@@ -95,7 +99,7 @@ typedef struct {
 } lbm_params;
 
 /* Fill p with defaults: D2Q9 BGK FP32 plain, 64 x 64 x 1, periodic, tau 0.8, R = 1/3,
-   c_v = 5/6, no force, phi 1, S = 16, no diagnostics, automatic streaming layout, tol 0.05, null
+   c_v = 5/6, no force or heat source, phi 1, S = 16, no diagnostics, automatic streaming layout, tol 0.05, null
    stream, no workspace. */
 void lbm_default_params(lbm_params* p);
 
@@ -124,12 +128,15 @@ int lbm_step(lbm_ctx* ctx, int64_t n);
    collision). LBM_EINVAL where lbm_params.force would be rejected; no device work. */
 int lbm_set_force(lbm_ctx* ctx, const double* force);
 
+/* The same for the heat source Q (lbm_params.heat_source; DDF only). */
+int lbm_set_heat_source(lbm_ctx* ctx, double heat_source);
+
 /* Time n steps with HIP events recorded on the context stream around the launches; *ms is
    the elapsed time in milliseconds. Synchronises. */
 int lbm_time_steps(lbm_ctx* ctx, int64_t n, float* ms);
 
 /* Moments of the pre-collision populations at the current time t (Sec. II C: rho = sum f,
-   rho u = sum c f (+ F/2 with a body force), rho E = sum g). rho: [nodes], u: [D][nodes], T: [nodes] (DDF only, may be
+   rho u = sum c f (+ F/2 with a body force), rho E = sum g (+ (u.F + Q)/2 with sources)). rho: [nodes], u: [D][nodes], T: [nodes] (DDF only, may be
    NULL), totals: {mass, rho u_x, rho u_y, rho u_z, energy} as float64 sums (energy = kinetic
    energy sum rho |u|^2 / 2 for BGK, total energy sum rho E for DDF); any output may be NULL.
    Caller-owned host buffers. Synchronises. */

@@ -33,7 +33,7 @@ class LbmParams(ctypes.Structure):
         ("collision", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
         ("nz", ctypes.c_int32), ("wall_y", ctypes.c_int32), ("tau", ctypes.c_double),
         ("R", ctypes.c_double), ("cv", ctypes.c_double), ("force", ctypes.c_double * 3),
-        ("phi", ctypes.c_int32),
+        ("heat_source", ctypes.c_double), ("phi", ctypes.c_int32),
         ("fp16_scale_log2", ctypes.c_int32), ("diag_every", ctypes.c_int32),
         ("streaming", ctypes.c_int32), ("mlp_tol", ctypes.c_double), ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t),
@@ -52,6 +52,7 @@ SIGNATURES = {
     "lbm_create": (ctypes.c_int, [ctypes.POINTER(LbmParams), _D, _D, _D, ctypes.POINTER(_P)]),
     "lbm_step": (ctypes.c_int, [_P, _I64]),
     "lbm_set_force": (ctypes.c_int, [_P, _D]),
+    "lbm_set_heat_source": (ctypes.c_int, [_P, ctypes.c_double]),
     "lbm_time_steps": (ctypes.c_int, [_P, _I64, _F]),
     "lbm_moments": (ctypes.c_int, [_P, _D, _D, _D, _D]),
     "lbm_populations": (ctypes.c_int, [_P, _D, _D]),
@@ -114,7 +115,8 @@ class Lattice:
     """One lattice Boltzmann context on the current HIP device.
 
     rho0: (ny, nx) or (nz, ny, nx) float64; u0: (D,) + that shape; T0 for the DDF model;
-    force: uniform body force (D components) for the isothermal model, or None.
+    force: uniform body force (D components) or None; heat_source: uniform heat source Q
+    (double-distribution model).
     The context workspace is a torch uint8 tensor on the current device; launches go on
     torch's current stream.
     """
@@ -122,7 +124,7 @@ class Lattice:
     def __init__(self, rho0, u0, T0=None, *, lattice="D2Q9", model="bgk", storage="fp32",
                  collision="plain", wall_y=False, tau=0.8, R=1.0 / 3.0, cv=5.0 / 6.0, phi=1,
                  fp16_scale_log2=16, diag_every=0, mlp_tol=0.05, streaming="auto",
-                 force=None, torch_workspace=True):
+                 force=None, heat_source=0.0, torch_workspace=True):
         torch = _torch()
         lib = load()
         rho0 = np.ascontiguousarray(rho0, dtype=np.float64)
@@ -153,6 +155,7 @@ class Lattice:
                 raise ValueError("force must have %d components" % D)
             for a, v in enumerate(fv):
                 p.force[a] = v
+        p.heat_source = float(heat_source)
         p.fp16_scale_log2 = int(fp16_scale_log2)
         p.diag_every = int(diag_every)
         p.streaming = STREAMINGS[streaming]
@@ -182,6 +185,10 @@ class Lattice:
             raise ValueError("force must have %d components" % self.D)
         arr = (ctypes.c_double * 3)(*(fv + [0.0] * (3 - self.D)))
         _check(load().lbm_set_force(self.ctx, arr), self.ctx)
+
+    def set_heat_source(self, heat_source):
+        """Uniform heat source Q for the collisions of the following steps (DDF)."""
+        _check(load().lbm_set_heat_source(self.ctx, float(heat_source)), self.ctx)
 
     def time_steps(self, n):
         ms = ctypes.c_float(0.0)

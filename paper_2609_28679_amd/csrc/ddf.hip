@@ -1,17 +1,21 @@
 // Double-distribution (f, g) fused pull stream-collide kernel, D2Q9, ideal gas.
 //
 // One launch advances one time step of Eq. (LBM_f) and Eq. (LBM_g) of Sec. II C in the order
-// of Fig. 1 (no body force, no heat source):
+// of Fig. 1, with an optional uniform body force F and heat source Q (float32/float64 storage):
 //   pull f_i, g_i from x - c_i (periodic in x; periodic or half-way bounce-back walls in y);
-//   rho = sum f, rho u = sum c f, rho E = sum g;  T = (E - u^2/2)/c_v, P = rho R T,
-//   theta = P/rho (ideal gas, Sec. III A);
+//   rho = sum f, rho u = sum c f + F/2, rho E = sum g + (u.F + Q)/2;  T = (E - u^2/2)/c_v,
+//   P = rho R T, theta = P/rho (ideal gas, Sec. III A);
 //   Galilean correction Phi_aa = -(1/rho) d_a(rho u_a^3 + 3 rho u_a (theta - 1/3)) with a
 //   finite-difference derivative of the moments of the neighbouring nodes at the same time
 //   level (central, or one-sided on the upwind side of u_a);
-//   f^eq, f* = rho prod_a Psi(u_a, theta + u_a^2 + Phi_aa), g^eq = g* (closed form of the
-//   operator-generated energy equilibrium; q^c = 0 at Prandtl number 1);
+//   shifted state u* = u + F/rho, theta* = theta + (gamma - 1) Q/rho,
+//   T* = T + Q/(rho c_v) - F.F/(2 rho^2 c_v) (u*, theta*, T* = u, theta, T without sources);
+//   f^eq, f* = rho prod_a Psi(u*_a, theta* + u*_a^2 + Phi_aa), g^eq, g* = g^eq(rho, u*, T*,
+//   theta*) (closed form of the operator-generated energy equilibrium; q^c = 0 at Prandtl
+//   number 1);
 //   beta = 1/(2 tau + 1), tau = mu/P, omega = 2 beta;
-//   f~ = f + omega (f^eq - f) + (1 - beta)(f* - f^eq),  g~ = g + omega (g^eq - g).
+//   f~ = f + omega (f^eq - f) + (1 - beta)(f* - f^eq),
+//   g~ = g + omega (g^eq - g) + (1 - beta)(g* - g^eq).
 //
 // Tiling. A workgroup of 256 threads owns 256 - 2 HALO columns (256 - 2 HALO - 2 with staged
 // rows, whose outermost thread on each side only stages) and `rows` rows; each thread holds
@@ -196,7 +200,7 @@ struct IoRed {
   }
 };
 
-template <class IO, int HALO, bool WALLS, bool PULL, bool DIAG>
+template <class IO, int HALO, bool WALLS, bool PULL, bool DIAG, bool SRC>
 __global__ void __launch_bounds__(kBlock)
 k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
            double* __restrict__ partials) {
@@ -285,7 +289,7 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
           g[i] = (double)ring_g[j][i] + prm.wg[i];
         }
         Moments m;
-        moments_closure(f, g, prm, m);
+        moments_closure<SRC>(f, g, prm, m, prm.Fx, prm.Fy, prm.Q);
         ring_m[j][0] = m.rho;
         ring_m[j][1] = m.ux;
         ring_m[j][2] = m.uy;
@@ -337,7 +341,7 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
           phyy *= inv_rho;
         }
         const int64_t off = (int64_t)cc * pitch + x;
-        collide_ddf(ring_f[sc], ring_g[sc], ring_m[sc], phxx, phyy, prm,
+        collide_ddf<SRC>(ring_f[sc], ring_g[sc], ring_m[sc], phxx, phyy, prm,
                     [&](int i, double htf, double hfe, double htg, double hge) {
                       io.store(off, i, htf, hfe, htg, hge);
                     });
@@ -375,7 +379,10 @@ __global__ void k_init_ddf(const double* __restrict__ rho, const double* __restr
   }
 }
 
-// rho, u, T of the stored state (the collision conserves rho, rho u and rho E).
+// rho, u, T of the stored state. The collision conserves rho, rho u and rho E without sources;
+// with sources the stored (post-collision) sums carry a whole step of F and Q, so the moments
+// at the same time are those of the closure with the sources of that collision negated
+// (prm.Fx, prm.Fy, prm.Q hold them).
 template <typename S>
 __global__ void k_moments_ddf(const S* __restrict__ A, int nx, int ny, int64_t pitch,
                               int64_t plane, DdfParams prm, double* __restrict__ rho,
@@ -391,7 +398,7 @@ __global__ void k_moments_ddf(const S* __restrict__ A, int nx, int ny, int64_t p
     g[i] = (double)A[(9 + i) * plane + off] + prm.wg[i];
   }
   Moments m;
-  moments_closure(f, g, prm, m);
+  moments_closure<true>(f, g, prm, m, -prm.Fx, -prm.Fy, -prm.Q);
   rho[n] = m.rho;
   u[n] = m.ux;
   u[nodes + n] = m.uy;
@@ -438,14 +445,28 @@ Grid make_grid_ddf(const Layout& L, int halo, bool reduced) {
   return G;
 }
 
+template <class IO, int HALO, bool WALLS, bool PULL, bool SRC>
+static void ddf_launch_s(const IO& io, const Layout& L, const Grid& G, const DdfParams& prm,
+                         double* partials, hipStream_t s) {
+  dim3 grid(G.nbx, G.nby), block(kBlock);
+  if (partials)
+    k_ddf_d2q9<IO, HALO, WALLS, PULL, true, SRC><<<grid, block, 0, s>>>(io, L.nx, L.ny, L.pitch, prm, G.rows, partials);
+  else
+    k_ddf_d2q9<IO, HALO, WALLS, PULL, false, SRC><<<grid, block, 0, s>>>(io, L.nx, L.ny, L.pitch, prm, G.rows, nullptr);
+}
+
+// Source terms exist for float32/float64 storage only (the context rejects them with reduced
+// storage, whose codec assumes a non-equilibrium part without mass and momentum).
 template <class IO, int HALO, bool WALLS, bool PULL>
 static void ddf_launch(const IO& io, const Layout& L, const Grid& G, const DdfParams& prm,
                        double* partials, hipStream_t s) {
-  dim3 grid(G.nbx, G.nby), block(kBlock);
-  if (partials)
-    k_ddf_d2q9<IO, HALO, WALLS, PULL, true><<<grid, block, 0, s>>>(io, L.nx, L.ny, L.pitch, prm, G.rows, partials);
-  else
-    k_ddf_d2q9<IO, HALO, WALLS, PULL, false><<<grid, block, 0, s>>>(io, L.nx, L.ny, L.pitch, prm, G.rows, nullptr);
+  if constexpr (!IO::kStaged) {
+    if (prm.src) {
+      ddf_launch_s<IO, HALO, WALLS, PULL, true>(io, L, G, prm, partials, s);
+      return;
+    }
+  }
+  ddf_launch_s<IO, HALO, WALLS, PULL, false>(io, L, G, prm, partials, s);
 }
 
 template <class IO, int HALO>
@@ -484,6 +505,7 @@ static IoRed<Codec> make_red(const void* A, void* B, const Layout& L, float se, 
 hipError_t launch_ddf(int fmt, bool walls, bool pull, const void* A, void* B, const Layout& L,
                       const Grid& G, const DdfParams& prm, float s_enc, float s_dec,
                       double* partials, hipStream_t s) {
+  if (prm.src && fmt >= 2) return hipErrorInvalidValue;  // no source terms with reduced storage
   if (fmt == 0) {
     IoFull<float> io{static_cast<const float*>(A), static_cast<float*>(B), L.plane};
     ddf_launch_h(walls, pull, io, L, G, prm, partials, s);

@@ -50,16 +50,27 @@ struct Moments {
 };
 
 // rho = sum f, rho u = sum c f, rho E = sum g; T = (E - u^2/2)/c_v and theta = P/rho = R T.
+// With sources (SRC) the half-step terms of Sec. II C enter: rho u = sum c f + sF/2 and
+// rho E = sum g + (u.sF + sQ)/2, (sF, sQ) = (F, Q) of the collision that follows. The
+// post-collision state (whose sums carry a whole step of the sources) gives the same moments
+// with (sF, sQ) = -(F, Q) of the collision that produced it.
+template <bool SRC = false>
 __device__ __forceinline__ void moments_closure(const double (&f)[9], const double (&g)[9],
-                                                const DdfParams& p, Moments& m) {
+                                                const DdfParams& p, Moments& m, double sFx = 0.0,
+                                                double sFy = 0.0, double sQ = 0.0) {
   const double rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
-  const double jx = (f[2] + f[5] + f[8]) - (f[0] + f[3] + f[6]);
-  const double jy = (f[6] + f[7] + f[8]) - (f[0] + f[1] + f[2]);
-  const double rE = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
+  double jx = (f[2] + f[5] + f[8]) - (f[0] + f[3] + f[6]);
+  double jy = (f[6] + f[7] + f[8]) - (f[0] + f[1] + f[2]);
+  double rE = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
+  if (SRC) {
+    jx += 0.5 * sFx;
+    jy += 0.5 * sFy;
+  }
   const double inv = 1.0 / rho;
   m.rho = rho;
   m.ux = jx * inv;
   m.uy = jy * inv;
+  if (SRC) rE += 0.5 * ((m.ux * sFx + m.uy * sFy) + sQ);
   m.e = rE * inv - 0.5 * (m.ux * m.ux + m.uy * m.uy);  // c_v T
   m.theta = p.r_cv * m.e;
 }
@@ -105,7 +116,11 @@ __device__ __forceinline__ double upwind_or_central(double pm2, double pm1, doub
 // (hf = f - w, hg = g - v) and its moments m = {rho, u_x, u_y, theta, e, -}; Phi_xx, Phi_yy
 // include dt = 1. For every i the sink receives the post-collision values and the
 // equilibria, all shifted: sink(i, f~ - w, f^eq - w, g~ - v, g^eq - v).
-template <typename R, typename Sink>
+// Without sources f* = rho prod Psi(u, theta + u^2 + Phi) and g* = g^eq. With sources (SRC,
+// Sec. II C) f* and g* are taken at the shifted state u* = u + F/rho,
+// theta* = theta + (gamma - 1) Q/rho with gamma - 1 = R/c_v (ideal gas; alpha = 0), and
+// c_v T* = e + Q/rho - F.F/(2 rho^2); q^c = 0 at Prandtl number 1.
+template <bool SRC = false, typename R, typename Sink>
 __device__ __forceinline__ void collide_ddf(const R (&hf)[9], const R (&hg)[9],
                                             const double (&m)[6], double phxx, double phyy,
                                             const DdfParams& p, Sink&& sink) {
@@ -113,14 +128,24 @@ __device__ __forceinline__ void collide_ddf(const R (&hf)[9], const R (&hg)[9],
   Axis X, Y;
   axis_eq(m[1], theta, X);
   axis_eq(m[2], theta, Y);
-  // shifted factors Psi(c; u, theta + u^2 + Phi): psi + Phi * (1/2, -1, 1/2)
+  // shifted state: the factors of f*, g* (the unshifted ones without sources)
+  Axis XS = X, YS = Y;
+  double es = e;
+  if (SRC) {
+    const double inv = 1.0 / rho;
+    const double thetas = theta + p.r_cv * p.Q * inv;
+    axis_eq(m[1] + p.Fx * inv, thetas, XS);
+    axis_eq(m[2] + p.Fy * inv, thetas, YS);
+    es = e + p.Q * inv - 0.5 * (p.Fx * p.Fx + p.Fy * p.Fy) * inv * inv;
+  }
+  // Psi(c; u*, theta* + u*^2 + Phi): psi* + Phi * (1/2, -1, 1/2)
   double sx[3], sy[3];
-  sx[0] = X.psi[0] + 0.5 * phxx;
-  sx[1] = X.psi[1] - phxx;
-  sx[2] = X.psi[2] + 0.5 * phxx;
-  sy[0] = Y.psi[0] + 0.5 * phyy;
-  sy[1] = Y.psi[1] - phyy;
-  sy[2] = Y.psi[2] + 0.5 * phyy;
+  sx[0] = XS.psi[0] + 0.5 * phxx;
+  sx[1] = XS.psi[1] - phxx;
+  sx[2] = XS.psi[2] + 0.5 * phxx;
+  sy[0] = YS.psi[0] + 0.5 * phyy;
+  sy[1] = YS.psi[1] - phyy;
+  sy[2] = YS.psi[2] + 0.5 * phyy;
   const double P = rho * theta;
   const double omega = 2.0 * P / (2.0 * p.mu + P);  // 2 beta, beta = 1/(2 tau + 1), tau = mu/P
   const double keep = 1.0 - 0.5 * omega;            // 1 - beta
@@ -129,11 +154,21 @@ __device__ __forceinline__ void collide_ddf(const R (&hf)[9], const R (&hg)[9],
     const int a = i % 3, b = i / 3;
     const double pp = X.psi[a] * Y.psi[b];
     const double hfe = rho * pp - p.wf[i];  // f^eq - w
-    const double hge = rho * (e * pp + X.chi[a] * Y.psi[b] + X.psi[a] * Y.chi[b]) - p.wg[i];
-    const double dstar = rho * (sx[a] * sy[b] - pp);  // f* - f^eq
     const double f = (double)hf[i];
     const double g = (double)hg[i];
-    sink(i, f + omega * (hfe - f) + keep * dstar, hfe, g + omega * (hge - g), hge);
+    if (SRC) {
+      const double fe = rho * pp;
+      const double ge = rho * (e * pp + X.chi[a] * Y.psi[b] + X.psi[a] * Y.chi[b]);
+      const double gs = rho * (es * (XS.psi[a] * YS.psi[b]) + XS.chi[a] * YS.psi[b] +
+                               XS.psi[a] * YS.chi[b]);
+      const double hge = ge - p.wg[i];
+      sink(i, f + omega * (hfe - f) + keep * (rho * (sx[a] * sy[b]) - fe), hfe,
+           g + omega * (hge - g) + keep * (gs - ge), hge);
+    } else {
+      const double hge = rho * (e * pp + X.chi[a] * Y.psi[b] + X.psi[a] * Y.chi[b]) - p.wg[i];
+      const double dstar = rho * (sx[a] * sy[b] - pp);  // f* - f^eq
+      sink(i, f + omega * (hfe - f) + keep * dstar, hfe, g + omega * (hge - g), hge);
+    }
   }
 }
 

@@ -49,6 +49,7 @@ struct lbm_ctx {
   double omega = 0.0;
   Force F;        // uniform body force of the next collision (zero: none)
   Force F_state;  // force of the collision that produced the stored state (read-outs)
+  double heat = 0.0, heat_state = 0.0;  // heat source Q (DDF): next collision / stored state
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   float* mlp_w = nullptr;                  // surrogate weights (kMlpParams floats)
   unsigned long long* mlp_cnt = nullptr;   // {fallbacks, updates}
@@ -89,6 +90,14 @@ int hip_fail(lbm_ctx* c, hipError_t e, const char* where) {
     if (e_ != hipSuccess) return hip_fail((ctx), e_, #expr); \
   } while (0)
 
+// The double-distribution kernels take the sources of the next collision from DdfParams.
+void sync_sources(lbm_ctx* c) {
+  c->dp.Fx = c->F.x;
+  c->dp.Fy = c->F.y;
+  c->dp.Q = c->heat;
+  c->dp.src = c->F.on() || c->heat != 0.0;
+}
+
 struct Plan {
   int D, Q, kind, planes, codec;
   bool ddf, aa;
@@ -99,15 +108,22 @@ struct Plan {
   int partial_slots;
 };
 
-// A body force is supported by the isothermal model with the paper's collision and FP32 or FP64
-// storage; it must be finite, and its z component zero on D2Q9.
-int validate_force(const lbm_params* p, const double* force, std::string& why) {
+// Sources: a body force needs the paper's collision and FP32 or FP64 storage (isothermal or
+// double-distribution model), a heat source in addition the double-distribution model. Both
+// must be finite; the force's z component must be zero on D2Q9.
+int validate_sources(const lbm_params* p, const double* force, double heat, std::string& why) {
   const bool forced = force[0] != 0.0 || force[1] != 0.0 || force[2] != 0.0;
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(force[a])) { why = "force must be finite"; return LBM_EINVAL; }
-  if (forced && (p->model != LBM_MODEL_BGK || p->collision != LBM_COLLIDE_PLAIN ||
-                 (p->storage != LBM_STORE_FP32 && p->storage != LBM_STORE_FP64))) {
-    why = "a body force needs the isothermal model, the paper's collision and FP32 or FP64 storage";
+  if (!std::isfinite(heat)) { why = "heat_source must be finite"; return LBM_EINVAL; }
+  const bool plain = p->collision == LBM_COLLIDE_PLAIN &&
+                     (p->storage == LBM_STORE_FP32 || p->storage == LBM_STORE_FP64);
+  if (forced && !plain) {
+    why = "a body force needs the paper's collision and FP32 or FP64 storage";
+    return LBM_EINVAL;
+  }
+  if (heat != 0.0 && (p->model != LBM_MODEL_DDF || !plain)) {
+    why = "a heat_source needs the double-distribution model with FP32 or FP64 storage";
     return LBM_EINVAL;
   }
   if (forced && p->lattice == LBM_D2Q9 && force[2] != 0.0) { why = "D2Q9 requires force[2] = 0"; return LBM_EINVAL; }
@@ -140,7 +156,7 @@ int validate(const lbm_params* p, std::string& why) {
     return LBM_EINVAL;
   }
   if (!(p->mlp_tol >= 0.0)) { why = "mlp_tol must be >= 0"; return LBM_EINVAL; }
-  if (int rc = validate_force(p, p->force, why)) return rc;
+  if (int rc = validate_sources(p, p->force, p->heat_source, why)) return rc;
   if (p->streaming < LBM_STREAM_AUTO || p->streaming > LBM_STREAM_ONE_BUFFER) { why = "unknown streaming layout"; return LBM_EINVAL; }
   if (p->streaming == LBM_STREAM_ONE_BUFFER &&
       (p->model != LBM_MODEL_BGK || p->collision != LBM_COLLIDE_PLAIN ||
@@ -300,6 +316,8 @@ int lbm_create(const lbm_params* p, const double* rho0, const double* u0, const 
   c->F.y = p->force[1];
   c->F.z = c->D == 3 ? p->force[2] : 0.0;
   c->F_state = c->F;
+  c->heat = c->heat_state = p->heat_source;
+  sync_sources(c);
   c->partial_slots = P.partial_slots;
   auto cleanup_fail = [&](int code) {
     std::string m = c->err;
@@ -404,6 +422,7 @@ int lbm_step(lbm_ctx* c, int64_t n) {
     if (!c->aa) std::swap(c->A, c->B);
     c->t = tn;
     c->F_state = c->F;
+    c->heat_state = c->heat;
   }
   if (c->hist_written > hist_before) {
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -424,10 +443,21 @@ int lbm_set_force(lbm_ctx* c, const double* force) {
   if (!c) return fail(nullptr, LBM_ESTATE, "NULL context");
   if (!force) return fail(c, LBM_EINVAL, "force is NULL");
   std::string why;
-  if (int rc = validate_force(&c->p, force, why)) return fail(c, rc, why);
+  if (int rc = validate_sources(&c->p, force, c->heat, why)) return fail(c, rc, why);
   c->F.x = force[0];
   c->F.y = force[1];
   c->F.z = c->D == 3 ? force[2] : 0.0;
+  sync_sources(c);
+  return LBM_OK;
+}
+
+int lbm_set_heat_source(lbm_ctx* c, double heat_source) {
+  if (!c) return fail(nullptr, LBM_ESTATE, "NULL context");
+  const double f[3] = {c->F.x, c->F.y, c->F.z};
+  std::string why;
+  if (int rc = validate_sources(&c->p, f, heat_source, why)) return fail(c, rc, why);
+  c->heat = heat_source;
+  sync_sources(c);
   return LBM_OK;
 }
 
@@ -450,9 +480,14 @@ int lbm_moments(lbm_ctx* c, double* rho, double* u, double* T, double* totals) {
   double* d_u = c->readout + nodes;
   double* d_T = c->readout + (1 + c->D) * nodes;
   double* d_e = d_T + nodes;
-  if (c->ddf)
-    HIP_TRY(c, launch_moments_ddf(c->fmt, c->A, c->L, c->dp, d_rho, d_u, d_T, d_e, c->stream));
-  else if (c->codec >= 0)
+  if (c->ddf) {
+    // the read-out removes the sources of the collision that produced the stored state
+    DdfParams rd = c->dp;
+    rd.Fx = c->F_state.x;
+    rd.Fy = c->F_state.y;
+    rd.Q = c->heat_state;
+    HIP_TRY(c, launch_moments_ddf(c->fmt, c->A, c->L, rd, d_rho, d_u, d_T, d_e, c->stream));
+  } else if (c->codec >= 0)
     HIP_TRY(c, launch_moments_bgk_red(c->A, c->L, d_rho, d_u, c->stream));
   else
     HIP_TRY(c, launch_moments_bgk(c->kind, c->D, c->A, c->L, view_of(c), c->p.wall_y != 0, c->F_state, d_rho, d_u, c->stream));

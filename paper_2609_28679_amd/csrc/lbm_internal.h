@@ -58,6 +58,10 @@ struct DdfParams {
   double inv_R;  // 1 / R (T = theta / R)
   double mu;   // dynamic shear viscosity; tau = mu / P per node
   int phi;     // 0: no Galilean correction, 1: central derivative, 2: upwind derivative
+  // uniform body force (Fx, Fy) and heat source Q of the collision (lattice units); src = any
+  // of them non-zero (the kernels then take the source-term path)
+  double Fx = 0.0, Fy = 0.0, Q = 0.0;
+  bool src = false;
   // storage shift: f^eq and g^eq at rest at the reference state rho = 1, T = 1 (computed by
   // launch_ddf_rest_state on the device at context creation)
   double wf[9];

@@ -96,6 +96,7 @@ def test_create_rejects_inadmissible_initial_state_before_device_work(lib):
 def test_null_context_is_a_state_error(lib):
     assert lib.lbm_step(None, 1) == binding.LBM_ESTATE
     assert lib.lbm_set_force(None, (ctypes.c_double * 3)(0.0, 0.0, 0.0)) == binding.LBM_ESTATE
+    assert lib.lbm_set_heat_source(None, 0.0) == binding.LBM_ESTATE
     lib.lbm_destroy(None)  # NULL-safe
 
 
@@ -141,12 +142,15 @@ def test_one_buffer_layout_rejected_where_unsupported(lib, kw):
     assert rc == 0
 
 
-@pytest.mark.parametrize("kw", [dict(model=1), dict(storage=1), dict(storage=2),
+@pytest.mark.parametrize("kw", [dict(storage=1), dict(storage=2), dict(model=1, storage=1),
                                 dict(collision=1), dict(force_z=1e-6),
-                                dict(force_x=float("nan")), dict(force_y=float("inf"))])
-def test_body_force_rejected_where_unsupported(lib, kw):
+                                dict(force_x=float("nan")), dict(force_y=float("inf")),
+                                dict(heat=1e-6), dict(model=1, storage=2, heat=1e-6, force_x=0.0),
+                                dict(model=1, heat=float("nan"), force_x=0.0)])
+def test_sources_rejected_where_unsupported(lib, kw):
     kw = dict(kw)
     force = [kw.pop("force_x", 1e-6), kw.pop("force_y", 0.0), kw.pop("force_z", 0.0)]
+    heat = kw.pop("heat", 0.0)
     p = binding.LbmParams()
     lib.lbm_default_params(ctypes.byref(p))
     assert list(p.force) == [0.0, 0.0, 0.0]  # default: no force
@@ -154,21 +158,26 @@ def test_body_force_rejected_where_unsupported(lib, kw):
         setattr(p, k, v)
     for a in range(3):
         p.force[a] = force[a]
+    p.heat_source = heat
     n = ctypes.c_size_t(0)
     assert lib.lbm_workspace_size(ctypes.byref(p), ctypes.byref(n)) == binding.LBM_EINVAL
-    assert b"force" in lib.lbm_last_error(None)
+    assert b"force" in lib.lbm_last_error(None) or b"heat_source" in lib.lbm_last_error(None)
 
 
-@pytest.mark.parametrize("lattice, nz, force", [(0, 1, (1e-6, -2e-6, 0.0)),
-                                                (1, 8, (0.0, 1e-6, 3e-6))])
-def test_body_force_accepted_for_the_isothermal_model(lib, lattice, nz, force):
+@pytest.mark.parametrize("lattice, model, nz, force, heat", [
+    (0, 0, 1, (1e-6, -2e-6, 0.0), 0.0), (1, 0, 8, (0.0, 1e-6, 3e-6), 0.0),
+    (0, 1, 1, (1e-6, -2e-6, 0.0), 0.0), (0, 1, 1, (0.0, 0.0, 0.0), 1e-5),
+    (0, 1, 1, (1e-6, 0.0, 0.0), -1e-5)])
+def test_sources_accepted(lib, lattice, model, nz, force, heat):
     for storage in (0, 3):  # float32, float64
-        for streaming in (1, 2):
+        for streaming in ((1, 2) if model == 0 else (0,)):
             p = binding.LbmParams()
             lib.lbm_default_params(ctypes.byref(p))
-            p.lattice, p.nx, p.ny, p.nz = lattice, 8, 8, nz
+            assert p.heat_source == 0.0
+            p.lattice, p.model, p.nx, p.ny, p.nz = lattice, model, 8, 8, nz
             p.storage, p.streaming = storage, streaming
             for a in range(3):
                 p.force[a] = force[a]
+            p.heat_source = heat
             n = ctypes.c_size_t(0)
             assert lib.lbm_workspace_size(ctypes.byref(p), ctypes.byref(n)) == 0
