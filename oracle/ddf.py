@@ -6,21 +6,24 @@ volume) and heat source Q (energy per unit volume and time); dt = 1:
   T = (E - u^2/2) / c_v,  P = rho R T                               (Sec. III A, ideal gas)
   theta = P / rho                                                   (Sec. II A closure)
   u* = u + F/rho                                                    (shifted velocity)
-  theta* = theta + alpha theta div u + (gamma - 1) Q/rho with alpha = 0, which the bulk
-        viscosity eta = mu (2/D - R/c_v) of Sec. II E gives, and gamma - 1 = R/c_v for the
-        ideal gas (Sec. II A, gamma = 1 + (dP/dT)_rho / (rho c_v))
+  theta* = theta + alpha theta div u + (gamma - 1) Q/rho with
+        alpha = (D+2)/D - gamma - eta/mu (Sec. II A; 0 for the Navier-Stokes bulk viscosity
+        eta = mu (2/D - R/c_v) of Sec. II E, the default) and gamma - 1 = R/c_v for the
+        ideal gas (gamma = 1 + (dP/dT)_rho / (rho c_v)); div u by central differences
   T* = T + Q/(rho c_v) - F.F/(2 rho^2 c_v)                          (shifted temperature)
   Phi_aa = -(1/rho) d_a (rho u_a^3 + 3 rho u_a (theta - varsigma^2))  (Galilean correction,
         from the unshifted fields)
   f^eq = rho prod Psi(u, theta + u^2),  f* = rho prod Psi(u*, theta* + u*^2 + Phi)   (Sec. II C)
-  g^eq = g^eq(rho, u, T, theta),  g* = g^eq(rho, u*, T*, theta*) + q^c term; for the ideal
-       gas at Prandtl number 1 (k = mu c_p) the flux q^c = dt P (grad h - (k/mu) grad T)
-       vanishes identically because h = c_p T
+  g^eq = g^eq(rho, u, T, theta),  g* = g^eq(rho, u*, T*, theta*) + c_i.q^c/2 on |c_i|^2 = 1,
+       q^c = dt P (grad h - (k/mu) grad T) = P (c_p - k/mu) grad T for the ideal gas
+       (h = c_p T), k = mu c_p / Pr; it vanishes at Prandtl number 1 (the default); grad T by
+       central differences
   tau = mu / P,  beta = dt / (2 tau + dt)                            (Sec. II A, II B)
   f~ = f + 2 beta (f^eq - f) + (1 - beta)(f* - f^eq)                   (Eq. LBM_f)
   g~ = g + 2 beta (g^eq - g) + (1 - beta)(g* - g^eq)                   (Eq. LBM_g)
   stream both (periodic in x, half-way bounce-back at the y walls when enabled).
-Without sources (F = 0, Q = 0) u* = u, theta* = theta, T* = T and g* = g^eq.
+Without sources (F = 0, Q = 0) at Pr = 1 and the Navier-Stokes bulk viscosity u* = u,
+theta* = theta, T* = T and g* = g^eq.
 
 Derivative inside the Galilean correction. The paper computes all derivatives with standard
 second-order central differences, except the first derivative of the correction, for which it
@@ -44,17 +47,38 @@ from .lattice import VARSIGMA2, velocities
 
 
 class Gas:
-    """Ideal-gas parameters: gas constant R, heat capacity c_v, dynamic viscosity mu."""
+    """Ideal-gas parameters: gas constant R, heat capacity c_v, dynamic viscosity mu, Prandtl
+    number Pr = mu c_p / k (thermal conductivity k) and bulk viscosity ratio eta/mu (None: the
+    Navier-Stokes value 2/D - R/c_v of Sec. II E, for which alpha = 0)."""
 
-    def __init__(self, R, cv, mu):
+    def __init__(self, R, cv, mu, prandtl=1.0, eta_over_mu=None):
         self.R = float(R)
         self.cv = float(cv)
         self.mu = float(mu)
+        self.prandtl = float(prandtl)
+        self.eta_over_mu = None if eta_over_mu is None else float(eta_over_mu)
 
     @property
     def gamma(self):
         """gamma = 1 + (dP/dT)_rho / (rho c_v) with P = rho R T: 1 + R/c_v = c_p/c_v."""
         return 1.0 + self.R / self.cv
+
+    @property
+    def cp(self):
+        return self.cv + self.R
+
+    def alpha(self, D):
+        """alpha = (D+2)/D - rho c_s^2/P - eta/mu (Sec. II A) with rho c_s^2 / P = gamma for the
+        ideal gas; exactly 0 for the Navier-Stokes bulk viscosity."""
+        if self.eta_over_mu is None:
+            return 0.0
+        return (D + 2.0) / D - self.gamma - self.eta_over_mu
+
+    def qc_coefficient(self):
+        """q^c = dt P (grad h - (k/mu) grad T) (Eq. qc_1) with h = e + P/rho = c_p T for the
+        ideal gas, so grad h = c_p grad T for any linear difference operator and
+        q^c = P (c_p - k/mu) grad T, k/mu = c_p / Pr; exactly 0 at Pr = 1."""
+        return self.cp - self.cp / self.prandtl
 
 
 def _field(F, D, shape):
@@ -106,6 +130,12 @@ def upwind_derivative(p, u_a, axis, wall):
     return np.where(u_a > 0, back, np.where(u_a < 0, fwd, cen))
 
 
+def divergence(u, walls_y):
+    """div u by second-order central differences (Sec. II E), wall ghosts as for Phi."""
+    D = u.shape[0]
+    return sum(central_derivative(u[a], u.ndim - 2 - a, walls_y and a == 1) for a in range(D))
+
+
 def galilean_correction(rho, u, theta, walls_y, stencil="central"):
     """dt Phi_aa = -(1/rho) d_a (rho u_a^3 + 3 rho u_a (theta - varsigma^2)), per axis."""
     D = u.shape[0]
@@ -133,12 +163,23 @@ def equilibria(rho, u, rhoE, gas, walls_y, phi_on=True, stencil="central", F=Non
     Fv = _field(F, D, rho.shape)
     ustar = u + Fv / rho
     thetastar = theta + (gas.gamma - 1.0) * Q / rho
+    alpha = gas.alpha(D)
+    if alpha != 0.0:  # theta* = theta + dt alpha theta div u + ... (Eq. sh_temp_1)
+        thetastar = thetastar + alpha * theta * divergence(u, walls_y)
     Tstar = T + Q / (rho * gas.cv) - (Fv * Fv).sum(axis=0) / (2.0 * rho * rho * gas.cv)
     fe = feq(rho, u, theta)
     Phi = galilean_correction(rho, u, theta, walls_y, stencil) if phi_on else np.zeros_like(u)
     fs = fstar(rho, ustar, thetastar, Phi)
     ge = geq(rho, u, theta, e)
     gs = geq(rho, ustar, thetastar, gas.cv * Tstar)
+    kq = gas.qc_coefficient()
+    if kq != 0.0:  # g* += c_i . q^c / 2 on the velocities with |c_i|^2 = 1 (Eq. LBMgstar)
+        c = velocities(D)
+        qc = [P * kq * central_derivative(T, rho.ndim - 1 - a, walls_y and a == 1)
+              for a in range(D)]
+        for i, ci in enumerate(c):
+            if (ci * ci).sum() == 1:
+                gs[i] = gs[i] + 0.5 * sum(ci[a] * qc[a] for a in range(D))
     tau = gas.mu / P
     beta = 1.0 / (2.0 * tau + 1.0)
     return fe, fs, ge, gs, beta

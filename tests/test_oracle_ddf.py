@@ -317,3 +317,68 @@ def test_zero_sources_are_the_unforced_scheme():
     b = ddf.run(f0, g0, gas, 6, walls_y=True, F=np.zeros(2), Q=0.0)
     for x, y in zip(a, b):
         assert np.abs(x - y).max() == 0.0
+
+
+# ---- Prandtl number and bulk viscosity (Sec. II A: alpha = (D+2)/D - rho c_s^2/P - eta/mu in
+# theta*; Eq. qc_1: q^c = dt P (grad h - (k/mu) grad T) in g*) ----------------------------------
+
+def _gas_t(prandtl=1.0, eta_over_mu=None, tau_lb=0.6):
+    return ddf.Gas(R, CV, (tau_lb - 0.5) * P0, prandtl=prandtl, eta_over_mu=eta_over_mu)
+
+
+@pytest.mark.parametrize("prandtl", [0.5, 2.0])
+def test_entropy_mode_diffuses_at_the_prandtl_conductivity(prandtl):
+    # an isobaric temperature mode decays at k_th/(rho c_p) k^2 = mu/(Pr rho) k^2
+    n, steps, eps, T0 = 32, 400, 1e-3, 1.0
+    gas = _gas_t(prandtl)
+    k = 2 * np.pi / n
+    x = np.arange(n)
+    T = (T0 * (1 + eps * np.cos(k * x)))[None, :] * np.ones((4, 1))
+    f, g = ddf.init_equilibrium(P0 / (R * T), np.zeros((2, 4, n)), T, gas)
+
+    def probe(r, u, rE):
+        Tn, _, _ = ddf.closure(r, u, rE, gas)
+        return ((Tn[0] - T0) * np.cos(k * x)).sum() * 2 / n
+
+    a, _, _ = _run_series(f, g, gas, steps, False, True, probe)
+    rate = -np.polyfit(np.arange(steps)[100:], np.log(a[100:]), 1)[0]
+    assert rate == pytest.approx(gas.mu / (P0 / (R * T0)) * k * k / prandtl, rel=2.5e-2)
+
+
+def _acoustic_damping(gas, n=32, steps=200, eps=1e-4, T0=1.0):
+    rho0 = P0 / (R * T0)
+    x = np.arange(n)
+    k = 2 * np.pi / n
+    sh = np.ones((4, 1))
+    rho = rho0 * (1 + eps * np.cos(k * x))[None, :] * sh
+    T = T0 * (1 + (GAMMA - 1) * eps * np.cos(k * x))[None, :] * sh
+    f, g = ddf.init_equilibrium(rho, np.zeros((2, 4, n)), T, gas)
+    a, _, _ = _run_series(f, g, gas, steps, False, True,
+                          lambda r, u, e: ((r[0] - rho0) * np.cos(k * x)).sum() * 2 / (n * rho0))
+    pk = [i for i in range(1, len(a) - 1) if abs(a[i]) >= abs(a[i - 1]) and abs(a[i]) >= abs(a[i + 1])]
+    damping = -np.polyfit(np.array(pk), np.log(np.abs(a[pk])), 1)[0]
+    return damping, k, rho0
+
+
+@pytest.mark.parametrize("prandtl,eta_over_mu", [(2.0, None), (0.5, None), (1.0, 2.0),
+                                                 (1.0, 0.0), (2.0, 3.0)])
+def test_acoustic_damping_follows_bulk_viscosity_and_conductivity(prandtl, eta_over_mu):
+    # linearised Navier-Stokes-Fourier limit in 2D: a sound wave's amplitude decays at
+    # k^2/(2 rho) [mu (2 - 2/D) + eta + (gamma - 1) k_th / c_p], k_th = mu c_p / Pr; eta/mu = None
+    # is the Navier-Stokes value 2/D - R/c_v
+    gas = _gas_t(prandtl, eta_over_mu)
+    damping, k, rho0 = _acoustic_damping(gas)
+    eta = (1.0 - R / CV) if eta_over_mu is None else eta_over_mu
+    expect = k * k / (2 * rho0) * gas.mu * (1.0 + eta + (GAMMA - 1) / prandtl)
+    assert damping == pytest.approx(expect, rel=1.5e-2)
+
+
+def test_transport_terms_vanish_on_a_uniform_flow():
+    # grad T = div u = 0 on a uniform state: Pr and eta change nothing there
+    rho = np.full((4, 6), 1.1)
+    u = np.array([0.03, -0.01])[:, None, None] * np.ones((2, 4, 6))
+    T = np.full((4, 6), 0.9)
+    a = ddf.run(*ddf.init_equilibrium(rho, u, T, _gas_t()), _gas_t(), 4, walls_y=False)
+    b = ddf.run(*ddf.init_equilibrium(rho, u, T, _gas_t()), _gas_t(2.0, 3.0), 4, walls_y=False)
+    for x, y in zip(a, b):
+        assert np.abs(x - y).max() <= 1e-16
