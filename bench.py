@@ -255,6 +255,11 @@ def main():
                 max(100, vs // 4), 10, 144,
                 {"walls": "y", "phi": "central",
                  "sources": "uniform force (1e-7, 0) and heat source 1e-8"})),
+            ("d2q9_ddf_fp32_4096_prandtl", lambda n: variant(
+                n, lambda: ddf_lattice("fp32", prandtl=0.71, eta_over_mu=1.0),
+                max(100, vs // 4), 10, 144,
+                {"walls": "y", "phi": "central",
+                 "transport": "Pr 0.71 (heat flux q^c), eta/mu 1 (alpha theta div u)"})),
             ("d2q9_ddf_fp32_4096_upwind", lambda n: variant(
                 n, lambda: ddf_lattice("fp32", phi=2), max(100, vs // 4), 10, 144,
                 {"walls": "y", "phi": "upwind"})),

@@ -85,6 +85,13 @@ typedef struct {
   double heat_source;  /* DDF only: uniform heat source Q per unit volume and time step, applied
                           through theta* = theta + (gamma - 1) Q/rho and T* = T + Q/(rho c_v)
                           with rho E = sum g + Q/2 (Sec. II C); FP32/FP64 storage; 0 = none. */
+  double prandtl;      /* DDF: Prandtl number Pr = mu c_p / k > 0 (default 1); Pr != 1 adds the
+                          heat-flux term c_i.q^c/2, q^c = P (grad h - (k/mu) grad T), to g*
+                          (Sec. II C, Eq. qc_1; central differences). FP32/FP64 storage. */
+  double eta_over_mu;  /* DDF: bulk viscosity ratio eta/mu >= 0, or < 0 (default -1) for the
+                          Navier-Stokes value 2/D - R/c_v; sets alpha = (D+2)/D - gamma - eta/mu
+                          in theta* = theta + alpha theta div u (Sec. II A). Values >= 0 need
+                          FP32/FP64 storage. */
   int32_t phi;         /* DDF: 1 = Galilean correction Phi on (the paper), 0 = off */
   int32_t fp16_scale_log2; /* LBM_STORE_FP16: S in [0, 24]; stored value = (f - f^eq) * 2^S */
   int32_t diag_every;  /* > 0: every diag_every steps record float64 totals (mass, momentum,
@@ -99,7 +106,7 @@ typedef struct {
 } lbm_params;
 
 /* Fill p with defaults: D2Q9 BGK FP32 plain, 64 x 64 x 1, periodic, tau 0.8, R = 1/3,
-   c_v = 5/6, no force or heat source, phi 1, S = 16, no diagnostics, automatic streaming layout, tol 0.05, null
+   c_v = 5/6, no force or heat source, Pr 1, Navier-Stokes bulk viscosity, phi 1, S = 16, no diagnostics, automatic streaming layout, tol 0.05, null
    stream, no workspace. */
 void lbm_default_params(lbm_params* p);
 

@@ -33,7 +33,8 @@ class LbmParams(ctypes.Structure):
         ("collision", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
         ("nz", ctypes.c_int32), ("wall_y", ctypes.c_int32), ("tau", ctypes.c_double),
         ("R", ctypes.c_double), ("cv", ctypes.c_double), ("force", ctypes.c_double * 3),
-        ("heat_source", ctypes.c_double), ("phi", ctypes.c_int32),
+        ("heat_source", ctypes.c_double), ("prandtl", ctypes.c_double),
+        ("eta_over_mu", ctypes.c_double), ("phi", ctypes.c_int32),
         ("fp16_scale_log2", ctypes.c_int32), ("diag_every", ctypes.c_int32),
         ("streaming", ctypes.c_int32), ("mlp_tol", ctypes.c_double), ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t),
@@ -115,7 +116,8 @@ class Lattice:
     """One lattice Boltzmann context on the current HIP device.
 
     rho0: (ny, nx) or (nz, ny, nx) float64; u0: (D,) + that shape; T0 for the DDF model;
-    force: uniform body force (D components) or None; heat_source: uniform heat source Q
+    force: uniform body force (D components) or None; heat_source: uniform heat source Q,
+    prandtl: Prandtl number, eta_over_mu: bulk viscosity ratio (< 0: Navier-Stokes value)
     (double-distribution model).
     The context workspace is a torch uint8 tensor on the current device; launches go on
     torch's current stream.
@@ -124,7 +126,8 @@ class Lattice:
     def __init__(self, rho0, u0, T0=None, *, lattice="D2Q9", model="bgk", storage="fp32",
                  collision="plain", wall_y=False, tau=0.8, R=1.0 / 3.0, cv=5.0 / 6.0, phi=1,
                  fp16_scale_log2=16, diag_every=0, mlp_tol=0.05, streaming="auto",
-                 force=None, heat_source=0.0, torch_workspace=True):
+                 force=None, heat_source=0.0, prandtl=1.0, eta_over_mu=-1.0,
+                 torch_workspace=True):
         torch = _torch()
         lib = load()
         rho0 = np.ascontiguousarray(rho0, dtype=np.float64)
@@ -156,6 +159,8 @@ class Lattice:
             for a, v in enumerate(fv):
                 p.force[a] = v
         p.heat_source = float(heat_source)
+        p.prandtl = float(prandtl)
+        p.eta_over_mu = float(eta_over_mu)
         p.fp16_scale_log2 = int(fp16_scale_log2)
         p.diag_every = int(diag_every)
         p.streaming = STREAMINGS[streaming]

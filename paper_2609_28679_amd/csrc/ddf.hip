@@ -77,7 +77,7 @@ struct IoFull {
     store_nt(B + i * plane + off, (S)htf);
     store_nt(B + (9 + i) * plane + off, (S)htg);
   }
-  __device__ __forceinline__ void store_moments(int64_t, const double (&)[6], double) const {}
+  __device__ __forceinline__ void store_moments(int64_t, const double*, double) const {}
 };
 
 template <typename Codec>
@@ -192,7 +192,7 @@ struct IoRed {
     if (f_slot(i) >= 0) store_nt(No + f_slot(i) * plane + off, Codec::enc((float)(htf - hfe), s_enc));
     if (g_slot(i) >= 0) store_nt(No + (kRedF + g_slot(i)) * plane + off, Codec::enc((float)(htg - hge), s_enc));
   }
-  __device__ __forceinline__ void store_moments(int64_t off, const double (&m)[6], double inv_R) const {
+  __device__ __forceinline__ void store_moments(int64_t off, const double* m, double inv_R) const {
     store_nt(Mo + off, (float)(m[0] - 1.0));
     store_nt(Mo + plane + off, (float)m[1]);
     store_nt(Mo + 2 * plane + off, (float)m[2]);
@@ -200,7 +200,7 @@ struct IoRed {
   }
 };
 
-template <class IO, int HALO, bool WALLS, bool PULL, bool DIAG, bool SRC>
+template <class IO, int HALO, bool WALLS, bool PULL, bool DIAG, bool EXT>
 __global__ void __launch_bounds__(kBlock)
 k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
            double* __restrict__ partials) {
@@ -212,6 +212,12 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
   __shared__ double s_phix[2][kBlock];
   __shared__ double s_phiy[P][kBlock];
   __shared__ float s_stage[IO::kStageFloats];
+  // extended path with transport control: T and u_x of the gathered row (x derivatives) and T,
+  // u_y of the last P rows per column (y derivatives)
+  constexpr int NE = EXT ? kBlock : 1;
+  __shared__ double s_tx[2][NE], s_ux[2][NE];
+  __shared__ double s_ty[P][NE], s_uy[P][NE];
+  constexpr int NM = EXT ? 8 : 6;
 
   const int nbx = gridDim.x;
   // per-XCD contiguous tiles for float32/float64 storage; the staged reduced-storage variant
@@ -234,7 +240,7 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
 
 
   S ring_f[H1][9], ring_g[H1][9];
-  double ring_m[H1][6];  // rho, u_x, u_y, theta, e, Phi_xx
+  double ring_m[H1][NM];  // rho, u_x, u_y, theta, e, Phi_xx [, dT/dx, du_x/dx]
   double acc[kDiagValues] = {0.0, 0.0, 0.0, 0.0, 0.0};
 
   // Staged rows are software-pipelined: the raw values of row r + 2 are fetched into registers
@@ -289,7 +295,7 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
           g[i] = (double)ring_g[j][i] + prm.wg[i];
         }
         Moments m;
-        moments_closure<SRC>(f, g, prm, m, prm.Fx, prm.Fy, prm.Q);
+        moments_closure<EXT>(f, g, prm, m, prm.Fx, prm.Fy, prm.Q);
         ring_m[j][0] = m.rho;
         ring_m[j][1] = m.ux;
         ring_m[j][2] = m.uy;
@@ -297,10 +303,22 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
         ring_m[j][4] = m.e;
         phx = m.rho * m.ux * (m.ux * m.ux + 3.0 * (m.theta - 1.0 / 3.0));
         phy = m.rho * m.uy * (m.uy * m.uy + 3.0 * (m.theta - 1.0 / 3.0));
+        if (EXT && prm.full) {
+          const double T = m.theta * prm.inv_R;
+          s_tx[w & 1][tid] = T;
+          s_ux[w & 1][tid] = m.ux;
+          s_ty[((r % P) + P) % P][tid] = T;
+          s_uy[((r % P) + P) % P][tid] = m.uy;
+        }
       }
       s_phix[w & 1][tid] = phx;
       s_phiy[((r % P) + P) % P][tid] = phy;
       __syncthreads();
+      // ---- x derivatives of T and u_x (transport control) --------------------------------------
+      if (EXT && prm.full && row_real && own) {
+        ring_m[j][6] = 0.5 * (s_tx[w & 1][tid + 1] - s_tx[w & 1][tid - 1]);
+        ring_m[j][7] = 0.5 * (s_ux[w & 1][tid + 1] - s_ux[w & 1][tid - 1]);
+      }
       // ---- x derivative of phi_x on the gathered row -----------------------------------------
       if (row_real && own && prm.phi) {
         const double* px = s_phix[w & 1];
@@ -340,8 +358,20 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
           phxx = ring_m[sc][5] * inv_rho;
           phyy *= inv_rho;
         }
+        // y derivatives of T and u_y (transport control), central with zero-order wall ghosts
+        double dTdy = 0.0, duydy = 0.0;
+        if (EXT && prm.full) {
+          int rm1 = c - 1, rp1 = c + 1;
+          if (WALLS) {
+            rm1 = rm1 < 0 ? 0 : rm1;
+            rp1 = rp1 > ny - 1 ? ny - 1 : rp1;
+          }
+          const int sm = ((rm1 % P) + P) % P, sp = ((rp1 % P) + P) % P;
+          dTdy = 0.5 * (s_ty[sp][tid] - s_ty[sm][tid]);
+          duydy = 0.5 * (s_uy[sp][tid] - s_uy[sm][tid]);
+        }
         const int64_t off = (int64_t)cc * pitch + x;
-        collide_ddf<SRC>(ring_f[sc], ring_g[sc], ring_m[sc], phxx, phyy, prm,
+        collide_ddf<EXT>(ring_f[sc], ring_g[sc], ring_m[sc], phxx, phyy, dTdy, duydy, prm,
                     [&](int i, double htf, double hfe, double htg, double hge) {
                       io.store(off, i, htf, hfe, htg, hge);
                     });
@@ -445,23 +475,24 @@ Grid make_grid_ddf(const Layout& L, int halo, bool reduced) {
   return G;
 }
 
-template <class IO, int HALO, bool WALLS, bool PULL, bool SRC>
+template <class IO, int HALO, bool WALLS, bool PULL, bool EXT>
 static void ddf_launch_s(const IO& io, const Layout& L, const Grid& G, const DdfParams& prm,
                          double* partials, hipStream_t s) {
   dim3 grid(G.nbx, G.nby), block(kBlock);
   if (partials)
-    k_ddf_d2q9<IO, HALO, WALLS, PULL, true, SRC><<<grid, block, 0, s>>>(io, L.nx, L.ny, L.pitch, prm, G.rows, partials);
+    k_ddf_d2q9<IO, HALO, WALLS, PULL, true, EXT><<<grid, block, 0, s>>>(io, L.nx, L.ny, L.pitch, prm, G.rows, partials);
   else
-    k_ddf_d2q9<IO, HALO, WALLS, PULL, false, SRC><<<grid, block, 0, s>>>(io, L.nx, L.ny, L.pitch, prm, G.rows, nullptr);
+    k_ddf_d2q9<IO, HALO, WALLS, PULL, false, EXT><<<grid, block, 0, s>>>(io, L.nx, L.ny, L.pitch, prm, G.rows, nullptr);
 }
 
-// Source terms exist for float32/float64 storage only (the context rejects them with reduced
-// storage, whose codec assumes a non-equilibrium part without mass and momentum).
+// The extended path (sources, transport control) exists for float32/float64 storage only (the
+// context rejects it with reduced storage, whose codec assumes a non-equilibrium part without
+// mass and momentum).
 template <class IO, int HALO, bool WALLS, bool PULL>
 static void ddf_launch(const IO& io, const Layout& L, const Grid& G, const DdfParams& prm,
                        double* partials, hipStream_t s) {
   if constexpr (!IO::kStaged) {
-    if (prm.src) {
+    if (prm.ext()) {
       ddf_launch_s<IO, HALO, WALLS, PULL, true>(io, L, G, prm, partials, s);
       return;
     }
@@ -505,7 +536,7 @@ static IoRed<Codec> make_red(const void* A, void* B, const Layout& L, float se, 
 hipError_t launch_ddf(int fmt, bool walls, bool pull, const void* A, void* B, const Layout& L,
                       const Grid& G, const DdfParams& prm, float s_enc, float s_dec,
                       double* partials, hipStream_t s) {
-  if (prm.src && fmt >= 2) return hipErrorInvalidValue;  // no source terms with reduced storage
+  if (prm.ext() && fmt >= 2) return hipErrorInvalidValue;  // no extended path with reduced storage
   if (fmt == 0) {
     IoFull<float> io{static_cast<const float*>(A), static_cast<float*>(B), L.plane};
     ddf_launch_h(walls, pull, io, L, G, prm, partials, s);

@@ -113,27 +113,36 @@ __device__ __forceinline__ double upwind_or_central(double pm2, double pm1, doub
 }
 
 // Collision of one node from its pre-collision populations held shifted by the rest state
-// (hf = f - w, hg = g - v) and its moments m = {rho, u_x, u_y, theta, e, -}; Phi_xx, Phi_yy
-// include dt = 1. For every i the sink receives the post-collision values and the
-// equilibria, all shifted: sink(i, f~ - w, f^eq - w, g~ - v, g^eq - v).
-// Without sources f* = rho prod Psi(u, theta + u^2 + Phi) and g* = g^eq. With sources (SRC,
-// Sec. II C) f* and g* are taken at the shifted state u* = u + F/rho,
-// theta* = theta + (gamma - 1) Q/rho with gamma - 1 = R/c_v (ideal gas; alpha = 0), and
-// c_v T* = e + Q/rho - F.F/(2 rho^2); q^c = 0 at Prandtl number 1.
-template <bool SRC = false, typename R, typename Sink>
+// (hf = f - w, hg = g - v) and its moments m = {rho, u_x, u_y, theta, e, -, dT/dx, du_x/dx};
+// Phi_xx, Phi_yy include dt = 1. For every i the sink receives the post-collision values and
+// the equilibria, all shifted: sink(i, f~ - w, f^eq - w, g~ - v, g^eq - v).
+// Without the extended path (EXT = false) f* = rho prod Psi(u, theta + u^2 + Phi) and
+// g* = g^eq. With it (Sec. II C) f* and g* are taken at the shifted state u* = u + F/rho,
+// theta* = theta + alpha theta div u + (gamma - 1) Q/rho with gamma - 1 = R/c_v (ideal gas),
+// c_v T* = e + Q/rho - F.F/(2 rho^2), and g* gains c_i.q^c/2 on the four velocities with
+// |c_i| = 1, q^c = P (c_p - k/mu) grad T (the ideal-gas form of P (grad h - (k/mu) grad T));
+// m[6], m[7], dTdy, duydy are used only when p.full.
+template <bool EXT = false, typename R, typename Sink>
 __device__ __forceinline__ void collide_ddf(const R (&hf)[9], const R (&hg)[9],
-                                            const double (&m)[6], double phxx, double phyy,
-                                            const DdfParams& p, Sink&& sink) {
+                                            const double* m, double phxx, double phyy,
+                                            double dTdy, double duydy, const DdfParams& p,
+                                            Sink&& sink) {
   const double rho = m[0], theta = m[3], e = m[4];
+  const double P = rho * theta;
   Axis X, Y;
   axis_eq(m[1], theta, X);
   axis_eq(m[2], theta, Y);
-  // shifted state: the factors of f*, g* (the unshifted ones without sources)
+  // shifted state: the factors of f*, g* (the unshifted ones without the extended path)
   Axis XS = X, YS = Y;
-  double es = e;
-  if (SRC) {
+  double es = e, qx = 0.0, qy = 0.0;
+  if (EXT) {
     const double inv = 1.0 / rho;
-    const double thetas = theta + p.r_cv * p.Q * inv;
+    double thetas = theta + p.r_cv * p.Q * inv;
+    if (p.full) {
+      thetas += p.alpha * theta * (m[7] + duydy);
+      qx = P * p.qc * m[6];
+      qy = P * p.qc * dTdy;
+    }
     axis_eq(m[1] + p.Fx * inv, thetas, XS);
     axis_eq(m[2] + p.Fy * inv, thetas, YS);
     es = e + p.Q * inv - 0.5 * (p.Fx * p.Fx + p.Fy * p.Fy) * inv * inv;
@@ -146,7 +155,6 @@ __device__ __forceinline__ void collide_ddf(const R (&hf)[9], const R (&hg)[9],
   sy[0] = YS.psi[0] + 0.5 * phyy;
   sy[1] = YS.psi[1] - phyy;
   sy[2] = YS.psi[2] + 0.5 * phyy;
-  const double P = rho * theta;
   const double omega = 2.0 * P / (2.0 * p.mu + P);  // 2 beta, beta = 1/(2 tau + 1), tau = mu/P
   const double keep = 1.0 - 0.5 * omega;            // 1 - beta
 #pragma unroll
@@ -156,11 +164,15 @@ __device__ __forceinline__ void collide_ddf(const R (&hf)[9], const R (&hg)[9],
     const double hfe = rho * pp - p.wf[i];  // f^eq - w
     const double f = (double)hf[i];
     const double g = (double)hg[i];
-    if (SRC) {
+    if (EXT) {
       const double fe = rho * pp;
       const double ge = rho * (e * pp + X.chi[a] * Y.psi[b] + X.psi[a] * Y.chi[b]);
-      const double gs = rho * (es * (XS.psi[a] * YS.psi[b]) + XS.chi[a] * YS.psi[b] +
-                               XS.psi[a] * YS.chi[b]);
+      double gs = rho * (es * (XS.psi[a] * YS.psi[b]) + XS.chi[a] * YS.psi[b] +
+                         XS.psi[a] * YS.chi[b]);
+      if (i == 1) gs -= 0.5 * qy;  // c = (0, -1)
+      if (i == 3) gs -= 0.5 * qx;  // c = (-1, 0)
+      if (i == 5) gs += 0.5 * qx;  // c = (+1, 0)
+      if (i == 7) gs += 0.5 * qy;  // c = (0, +1)
       const double hge = ge - p.wg[i];
       sink(i, f + omega * (hfe - f) + keep * (rho * (sx[a] * sy[b]) - fe), hfe,
            g + omega * (hge - g) + keep * (gs - ge), hge);

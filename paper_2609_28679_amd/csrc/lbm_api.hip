@@ -147,6 +147,13 @@ int validate(const lbm_params* p, std::string& why) {
     if (!(p->R > 0.0) || !(p->cv > 0.0) || !std::isfinite(p->R) || !std::isfinite(p->cv)) { why = "R and cv must be positive"; return LBM_EINVAL; }
     if (p->phi < 0 || p->phi > 2) { why = "phi must be 0 (off), 1 (central) or 2 (upwind)"; return LBM_EINVAL; }
   }
+  if (!(p->prandtl > 0.0) || !std::isfinite(p->prandtl)) { why = "prandtl must be a finite value > 0"; return LBM_EINVAL; }
+  if (!std::isfinite(p->eta_over_mu)) { why = "eta_over_mu must be finite"; return LBM_EINVAL; }
+  if ((p->prandtl != 1.0 || p->eta_over_mu >= 0.0) &&
+      (p->model != LBM_MODEL_DDF || (p->storage != LBM_STORE_FP32 && p->storage != LBM_STORE_FP64))) {
+    why = "prandtl != 1 and eta_over_mu >= 0 need the double-distribution model with FP32 or FP64 storage";
+    return LBM_EINVAL;
+  }
   const bool reduced = p->storage == LBM_STORE_BF16 || p->storage == LBM_STORE_FP16;
   if (reduced && p->lattice != LBM_D2Q9) { why = "reduced storage is D2Q9 only"; return LBM_EINVAL; }
   if (p->storage == LBM_STORE_FP16 && (p->fp16_scale_log2 < 0 || p->fp16_scale_log2 > 24)) { why = "fp16_scale_log2 must be in [0, 24]"; return LBM_EINVAL; }
@@ -239,6 +246,8 @@ void lbm_default_params(lbm_params* p) {
   p->tau = 0.8;
   p->R = 1.0 / 3.0;
   p->cv = 5.0 / 6.0;
+  p->prandtl = 1.0;
+  p->eta_over_mu = -1.0;
   p->phi = 1;
   p->fp16_scale_log2 = 16;
   p->diag_every = 0;
@@ -308,6 +317,14 @@ int lbm_create(const lbm_params* p, const double* rho0, const double* u0, const 
   c->dp.inv_R = 1.0 / p->R;
   c->dp.mu = (p->tau - 0.5) * (1.0 / 3.0);  // mu = (tau - 1/2) P0 at the reference P0 = 1/3
   c->dp.phi = p->phi;
+  {
+    // alpha = (D+2)/D - rho c_s^2/P - eta/mu with rho c_s^2/P = gamma = 1 + R/c_v (ideal gas);
+    // exactly 0 for the Navier-Stokes bulk viscosity. qc = c_p - k/mu, k/mu = c_p / Pr.
+    const double D = 2.0, gamma = 1.0 + p->R / p->cv, cp = p->cv + p->R;
+    c->dp.alpha = p->eta_over_mu >= 0.0 ? (D + 2.0) / D - gamma - p->eta_over_mu : 0.0;
+    c->dp.qc = p->prandtl != 1.0 ? cp - cp / p->prandtl : 0.0;
+    c->dp.full = c->dp.alpha != 0.0 || c->dp.qc != 0.0;
+  }
   c->L = P.L;
   c->G = P.G;
   c->stream = static_cast<hipStream_t>(p->stream);

@@ -59,9 +59,15 @@ struct DdfParams {
   double mu;   // dynamic shear viscosity; tau = mu / P per node
   int phi;     // 0: no Galilean correction, 1: central derivative, 2: upwind derivative
   // uniform body force (Fx, Fy) and heat source Q of the collision (lattice units); src = any
-  // of them non-zero (the kernels then take the source-term path)
+  // of them non-zero
   double Fx = 0.0, Fy = 0.0, Q = 0.0;
   bool src = false;
+  // transport control: alpha = (D+2)/D - gamma - eta/mu in theta* (bulk viscosity eta) and
+  // qc = c_p - k/mu in q^c = P qc grad T (Prandtl number); full = either non-zero
+  double alpha = 0.0, qc = 0.0;
+  bool full = false;
+  // the kernels take the extended path (shifted state with sources and/or transport terms)
+  bool ext() const { return src || full; }
   // storage shift: f^eq and g^eq at rest at the reference state rho = 1, T = 1 (computed by
   // launch_ddf_rest_state on the device at context creation)
   double wf[9];

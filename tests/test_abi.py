@@ -181,3 +181,22 @@ def test_sources_accepted(lib, lattice, model, nz, force, heat):
             p.heat_source = heat
             n = ctypes.c_size_t(0)
             assert lib.lbm_workspace_size(ctypes.byref(p), ctypes.byref(n)) == 0
+
+
+@pytest.mark.parametrize("kw", [dict(prandtl=0.0), dict(prandtl=float("nan")),
+                                dict(eta_over_mu=float("inf")), dict(prandtl=2.0),
+                                dict(eta_over_mu=1.0), dict(model=1, storage=1, prandtl=2.0),
+                                dict(model=1, storage=2, eta_over_mu=0.0)])
+def test_transport_parameters_validated(lib, kw):
+    rc, _ = _workspace(lib, **kw)
+    assert rc == binding.LBM_EINVAL
+    assert b"prandtl" in lib.lbm_last_error(None) or b"eta_over_mu" in lib.lbm_last_error(None)
+
+
+def test_transport_parameters_accepted_for_the_thermal_model(lib):
+    p = binding.LbmParams()
+    lib.lbm_default_params(ctypes.byref(p))
+    assert p.prandtl == 1.0 and p.eta_over_mu < 0
+    for storage in (0, 3):
+        rc, _ = _workspace(lib, model=1, storage=storage, prandtl=0.71, eta_over_mu=0.0)
+        assert rc == 0

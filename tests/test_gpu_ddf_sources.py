@@ -154,3 +154,52 @@ def test_sources_changed_between_steps():
         assert np.abs(ug - uo).max() <= 1e-13, k
         assert np.abs(tg - to).max() <= 1e-13, k
     lat.close()
+
+
+# ---- transport control: Prandtl number (q^c in g*) and bulk viscosity (alpha in theta*) ------
+
+@pytest.mark.parametrize("phi", [1, 2])
+@pytest.mark.parametrize("walls", [True, False])
+@pytest.mark.parametrize("prandtl,eta,F,Q", [(0.5, -1.0, (0.0, 0.0), 0.0),
+                                             (2.0, 2.0, (0.0, 0.0), 0.0),
+                                             (1.0, 0.0, (1e-4, -2e-4), 1e-4),
+                                             (0.71, 1.5, (-1e-4, 1e-4), -2e-4)])
+def test_transport_control_fp64_matches_oracle(prandtl, eta, F, Q, walls, phi):
+    announce("DDF fp64 Pr=%g eta/mu=%g F=%s Q=%g walls=%s phi=%d 300x37 9 steps"
+             % (prandtl, eta, F, Q, walls, phi))
+    rho, u, T = _random_fields(37, 300, seed=21)
+    tau, steps = 0.7, 9
+    lat = _lattice(rho, u, T, tau=tau, wall_y=walls, phi=phi, storage="fp64", force=F,
+                   heat_source=Q, prandtl=prandtl, eta_over_mu=eta)
+    lat.step(steps)
+    rg, ug, tg, _ = lat.moments()
+    fg, gg = lat.populations()
+    lat.close()
+    gas = ddf.Gas(R, CV, (tau - 0.5) * P0, prandtl=prandtl,
+                  eta_over_mu=None if eta < 0 else eta)
+    Fv = np.asarray(F)
+    f, g = ddf.init_equilibrium(rho, u, T, gas)
+    f, g = ddf.run(f, g, gas, steps, walls_y=walls, stencil=STENCIL[phi], F=Fv, Q=Q)
+    ro, uo, to = ddf.temperature(f, g, gas, F=Fv, Q=Q)
+    assert np.abs(rg - ro).max() <= 1e-13
+    assert np.abs(ug - uo).max() <= 1e-13
+    assert np.abs(tg - to).max() <= 1e-13
+    ft, gt = ddf.collide(f, g, gas, walls, True, STENCIL[phi], F=Fv, Q=Q)
+    assert np.abs(fg - ft).max() <= 1e-13
+    assert np.abs(gg - gt).max() <= 1e-13
+
+
+def test_transport_control_fp32_shear_layer():
+    announce("DDF fp32 shear layer 128x64 walls Pr 0.71 eta/mu 1 300 steps")
+    rho, u, T = inputs.thermal_shear_layer(128, seed=0, ny=64)
+    lat = _lattice(rho, u, T, tau=0.6, wall_y=True, phi=1, storage="fp32", prandtl=0.71,
+                   eta_over_mu=1.0)
+    lat.step(300)
+    _, ug, tg, _ = lat.moments()
+    lat.close()
+    gas = ddf.Gas(R, CV, 0.1 * P0, prandtl=0.71, eta_over_mu=1.0)
+    f, g = ddf.init_equilibrium(rho, u, T, gas)
+    f, g = ddf.run(f, g, gas, 300, walls_y=True)
+    _, uo, to = ddf.temperature(f, g, gas)
+    assert rel_l2(ug, uo) <= 1e-5
+    assert rel_l2(tg - 0.9, to - 0.9) <= 1e-5
