@@ -151,6 +151,29 @@ def test_geq_closed_form_derivation_matches_operator_application():
         np.testing.assert_allclose(g[i], expect, rtol=1e-12, atol=1e-15)
 
 
+def test_geq_closed_form_d3q27_matches_operator_application():
+    # the same derivation in 3D: the operators act on E = e + sum_a u_a^2/2 one axis at a time,
+    # g_i = e f_i + rho [chi_x psi_y psi_z + psi_x chi_y psi_z + psi_x psi_y chi_z]
+    rho, u, theta = _random_state(3, (5,), seed=18)
+    e = np.random.default_rng(19).uniform(0.5, 2.0, size=rho.shape)
+    g = eq.geq(rho, u, theta, e)
+
+    def psi1(c, v):
+        return {0: 1 - theta - v * v, 1: 0.5 * (theta + v * v + v), -1: 0.5 * (theta + v * v - v)}[c]
+
+    def chi(c, v):
+        a0 = 0.5 * v * v
+        a1 = theta * v + 0.5 * v ** 3
+        a2 = theta ** 2 + 2.5 * theta * v * v + 0.5 * v ** 4
+        return {0: a0 - a2, 1: 0.5 * (a2 + a1), -1: 0.5 * (a2 - a1)}[c]
+
+    for i, (cx, cy, cz) in enumerate(velocities(3)):
+        px, py, pz = psi1(cx, u[0]), psi1(cy, u[1]), psi1(cz, u[2])
+        expect = e * rho * px * py * pz + rho * (chi(cx, u[0]) * py * pz + px * chi(cy, u[1]) * pz
+                                                 + px * py * chi(cz, u[2]))
+        np.testing.assert_allclose(g[i], expect, rtol=1e-12, atol=1e-15)
+
+
 def test_moments_inverts_equilibrium():
     rho, u, theta = _random_state(3, (3, 2, 2), seed=10)
     r, v = eq.moments(eq.feq(rho, u, theta))
