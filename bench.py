@@ -260,6 +260,11 @@ def main():
                 max(100, vs // 4), 10, 144,
                 {"walls": "y", "phi": "central",
                  "transport": "Pr 0.71 (heat flux q^c), eta/mu 1 (alpha theta div u)"})),
+            ("d3q27_ddf_fp32_256", lambda n: variant(
+                n, lambda: binding.Lattice(*inputs.thermal_taylor_green_3d(256, 0.05),
+                                           lattice="D3Q27", model="ddf", tau=0.6, phi=1),
+                max(50, vs // 20), 5, 432,
+                {"phi": "central", "launches": "2 per step (fluxes, collision)"})),
             ("d2q9_ddf_fp32_4096_upwind", lambda n: variant(
                 n, lambda: ddf_lattice("fp32", phi=2), max(100, vs // 4), 10, 144,
                 {"walls": "y", "phi": "upwind"})),

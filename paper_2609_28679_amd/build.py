@@ -8,7 +8,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
 
-SOURCES = ["lbm_api.hip", "bgk.hip", "ddf.hip", "reduced.hip", "mlp.hip"]
+SOURCES = ["lbm_api.hip", "bgk.hip", "ddf.hip", "ddf3.hip", "reduced.hip", "mlp.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

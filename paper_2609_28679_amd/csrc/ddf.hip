@@ -436,13 +436,15 @@ __global__ void k_moments_ddf(const S* __restrict__ A, int nx, int ny, int64_t p
   edens[n] = m.rho * (m.e + 0.5 * (m.ux * m.ux + m.uy * m.uy));
 }
 
+// Population plane i (f_i for i < Q, g_(i-Q) after) decoded to float64; D2Q9 and D3Q27 (the
+// rows of all planes are consecutive at `pitch`).
 template <typename S>
-__global__ void k_decode_ddf(int i, const S* __restrict__ Ai, int nx, int64_t nodes,
+__global__ void k_decode_ddf(int Q, int i, const S* __restrict__ Ai, int nx, int64_t nodes,
                              int64_t pitch, DdfParams prm, double* __restrict__ out) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= nodes) return;
   const int64_t off = (n / nx) * pitch + (n % nx);
-  out[n] = (double)Ai[off] + (i < 9 ? prm.wf[i] : prm.wg[i - 9]);
+  out[n] = (double)Ai[off] + (i < Q ? prm.wf[i] : prm.wg[i - Q]);
 }
 
 __global__ void k_ddf_rest_state(DdfParams prm, double* __restrict__ out) {
@@ -623,16 +625,16 @@ hipError_t launch_moments_ddf(int kind, const void* A, const Layout& L, const Dd
   return hipGetLastError();
 }
 
-hipError_t launch_decode_ddf(int kind, int i, const void* A, const Layout& L,
+hipError_t launch_decode_ddf(int kind, int Q, int i, const void* A, const Layout& L,
                              const DdfParams& prm, float s_dec, double* out, hipStream_t s) {
   if (kind == 2)
     k_decode_ddf_red<CodecBF16><<<nblk(L.nodes()), kBlock, 0, s>>>(i, make_red<CodecBF16>(A, nullptr, L, 1.0f, s_dec), L.nx, L.nodes(), L.pitch, prm, out);
   else if (kind == 3)
     k_decode_ddf_red<CodecFP16><<<nblk(L.nodes()), kBlock, 0, s>>>(i, make_red<CodecFP16>(A, nullptr, L, 1.0f, s_dec), L.nx, L.nodes(), L.pitch, prm, out);
   else if (kind == 0)
-    k_decode_ddf<float><<<nblk(L.nodes()), kBlock, 0, s>>>(i, static_cast<const float*>(A) + (int64_t)i * L.plane, L.nx, L.nodes(), L.pitch, prm, out);
+    k_decode_ddf<float><<<nblk(L.nodes()), kBlock, 0, s>>>(Q, i, static_cast<const float*>(A) + (int64_t)i * L.plane, L.nx, L.nodes(), L.pitch, prm, out);
   else
-    k_decode_ddf<double><<<nblk(L.nodes()), kBlock, 0, s>>>(i, static_cast<const double*>(A) + (int64_t)i * L.plane, L.nx, L.nodes(), L.pitch, prm, out);
+    k_decode_ddf<double><<<nblk(L.nodes()), kBlock, 0, s>>>(Q, i, static_cast<const double*>(A) + (int64_t)i * L.plane, L.nx, L.nodes(), L.pitch, prm, out);
   return hipGetLastError();
 }
 

@@ -1,0 +1,387 @@
+// Double-distribution (f, g) stream-collide step for D3Q27, ideal gas, float32 or float64
+// storage: Eq. (LBM_f) and Eq. (LBM_g) of Sec. II C in the order of Fig. 1, with the optional
+// body force, heat source and transport control of the D2Q9 kernel (ddf.hip).
+//
+// Two launches per step:
+//   k_ddf3_flux     pulls the 27 + 27 populations of every node, computes its moments and
+//                   writes the Galilean-correction fluxes phi_a = rho u_a (u_a^2 + 3 (theta - 1/3))
+//                   (and, with transport control, T and u) to a float64 field;
+//   k_ddf3_collide  pulls the same populations again, recomputes the same moments, takes the
+//                   finite-difference derivatives of the neighbours' fields (central, or the
+//                   upwind-biased stencil for phi), collides and stores.
+// The second pull re-reads what the first one read: 432 B of populations per node in float32
+// are read twice, so the pair moves about 1.5x the algorithmic traffic of one fused sweep.
+// The D2Q9 kernel avoids the re-read by exchanging the moments of a workgroup's row through
+// LDS; in 3D a node's derivative stencil spans three planes, which a one-row tile cannot hold.
+//
+// Storage: 54 planes, f_i - w_i (i < 27) then g_i - v_i, with w, v the equilibria at rest at
+// rho = 1, T = 1; i = (cx+1) + 3(cy+1) + 9(cz+1), opposite 26 - i. Walls: half-way bounce-back
+// at the y ends; x and z periodic. Arithmetic is float64.
+#include "ddf_common.h"
+
+#include <type_traits>
+
+namespace lbm {
+
+struct Moments3 {
+  double rho, u[3], theta, e;
+};
+
+// Pull of the 27 + 27 populations of node (x, y, z): h_i = A_i(x - c_i), or the node's own
+// opposite population where x - c_i lies beyond a y wall; PULL = false reads the node's own
+// slots (the collide-only pass at creation).
+template <typename S, bool WALLS, bool PULL>
+__device__ __forceinline__ void gather27(const S* __restrict__ A, int64_t plane, int nx, int ny,
+                                         int nz, int64_t pitch, int x, int y, int z,
+                                         S (&hf)[27], S (&hg)[27]) {
+  const int64_t self = ((int64_t)z * ny + y) * pitch + x;
+  if (!PULL) {
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+      hf[i] = A[i * plane + self];
+      hg[i] = A[(27 + i) * plane + self];
+    }
+    return;
+  }
+  const int xs[3] = {x == nx - 1 ? 0 : x + 1, x, x == 0 ? nx - 1 : x - 1};  // x - c_x
+  const int ys[3] = {y == ny - 1 ? 0 : y + 1, y, y == 0 ? ny - 1 : y - 1};
+  const int zs[3] = {z == nz - 1 ? 0 : z + 1, z, z == 0 ? nz - 1 : z - 1};
+#pragma unroll
+  for (int i = 0; i < 27; ++i) {
+    const int a = i % 3, b = (i / 3) % 3, c = i / 9;
+    const bool bounce = WALLS && ((b == 2 && y == 0) || (b == 0 && y == ny - 1));
+    if (bounce) {
+      hf[i] = A[(26 - i) * plane + self];
+      hg[i] = A[(53 - i) * plane + self];
+    } else {
+      const int64_t src = ((int64_t)zs[c] * ny + ys[b]) * pitch + xs[a];
+      hf[i] = A[i * plane + src];
+      hg[i] = A[(27 + i) * plane + src];
+    }
+  }
+}
+
+// rho = sum f, rho u = sum c f + sF/2, rho E = sum g + (u.sF + sQ)/2 (Sec. II C), then
+// T = (E - u^2/2)/c_v and theta = R T. (sF, sQ) as in moments_closure (ddf_common.h).
+template <bool EXT, typename S>
+__device__ __forceinline__ void moments3(const S (&hf)[27], const S (&hg)[27], const DdfParams& p,
+                                         Moments3& m, double sFx, double sFy, double sFz,
+                                         double sQ) {
+  double rho = 0.0, j[3] = {0.0, 0.0, 0.0}, rE = 0.0;
+#pragma unroll
+  for (int i = 0; i < 27; ++i) {
+    const double f = (double)hf[i] + p.wf[i];
+    rho += f;
+    const int c[3] = {i % 3 - 1, (i / 3) % 3 - 1, i / 9 - 1};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      if (c[a]) j[a] += c[a] > 0 ? f : -f;
+    rE += (double)hg[i] + p.wg[i];
+  }
+  if (EXT) {
+    j[0] += 0.5 * sFx;
+    j[1] += 0.5 * sFy;
+    j[2] += 0.5 * sFz;
+  }
+  const double inv = 1.0 / rho;
+  m.rho = rho;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) m.u[a] = j[a] * inv;
+  if (EXT) rE += 0.5 * ((m.u[0] * sFx + m.u[1] * sFy + m.u[2] * sFz) + sQ);
+  m.e = rE * inv - 0.5 * (m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2]);
+  m.theta = p.r_cv * m.e;
+}
+
+// f^eq and g^eq in product form (Sec. II C; the operator-generated g^eq in closed form,
+// g_i = rho [e psi_x psi_y psi_z + chi_x psi_y psi_z + psi_x chi_y psi_z + psi_x psi_y chi_z]).
+__device__ __forceinline__ void equilibria3(double rho, double e, int i, const Axis (&ax)[3],
+                                            double& fe, double& ge) {
+  const int a = i % 3, b = (i / 3) % 3, c = i / 9;
+  const double px = ax[0].psi[a], py = ax[1].psi[b], pz = ax[2].psi[c];
+  const double pp = px * py * pz;
+  fe = rho * pp;
+  ge = rho * (e * pp + ax[0].chi[a] * py * pz + px * ax[1].chi[b] * pz + px * py * ax[2].chi[c]);
+}
+
+// Collision of one node (see collide_ddf in ddf_common.h for the D2Q9 form): ph[a] = Phi_aa,
+// gT[a] = dT/da and divu = div u (used only when p.full); sink(i, f~ - w, g~ - v).
+template <bool EXT, typename S, typename Sink>
+__device__ __forceinline__ void collide3(const S (&hf)[27], const S (&hg)[27], const Moments3& m,
+                                         const double (&ph)[3], const double (&gT)[3],
+                                         double divu, const DdfParams& p, Sink&& sink) {
+  const double rho = m.rho, theta = m.theta, e = m.e;
+  const double P = rho * theta;
+  Axis X[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) axis_eq(m.u[a], theta, X[a]);
+  Axis XS[3] = {X[0], X[1], X[2]};
+  double es = e, q[3] = {0.0, 0.0, 0.0};
+  if (EXT) {
+    const double inv = 1.0 / rho;
+    const double Fa[3] = {p.Fx, p.Fy, p.Fz};
+    double thetas = theta + p.r_cv * p.Q * inv;
+    if (p.full) {
+      thetas += p.alpha * theta * divu;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) q[a] = P * p.qc * gT[a];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) axis_eq(m.u[a] + Fa[a] * inv, thetas, XS[a]);
+    es = e + p.Q * inv - 0.5 * (p.Fx * p.Fx + p.Fy * p.Fy + p.Fz * p.Fz) * inv * inv;
+  }
+  // Psi(c; u*, theta* + u*^2 + Phi) = psi* + Phi * (1/2, -1, 1/2)
+  double s[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    s[a][0] = XS[a].psi[0] + 0.5 * ph[a];
+    s[a][1] = XS[a].psi[1] - ph[a];
+    s[a][2] = XS[a].psi[2] + 0.5 * ph[a];
+  }
+  const double omega = 2.0 * P / (2.0 * p.mu + P);  // 2 beta, beta = 1/(2 tau + 1), tau = mu/P
+  const double keep = 1.0 - 0.5 * omega;            // 1 - beta
+#pragma unroll
+  for (int i = 0; i < 27; ++i) {
+    const int a = i % 3, b = (i / 3) % 3, c = i / 9;
+    double fe, ge;
+    equilibria3(rho, e, i, X, fe, ge);
+    const double hfe = fe - p.wf[i], hge = ge - p.wg[i];
+    const double f = (double)hf[i], g = (double)hg[i];
+    const double fs = rho * (s[0][a] * s[1][b] * s[2][c]);
+    double gstar_minus_ge = 0.0;
+    if (EXT) {
+      double gs, fsx;
+      equilibria3(rho, es, i, XS, fsx, gs);
+      // c_i . q^c / 2 on the six velocities with |c_i| = 1
+      const int ca = a - 1, cb = b - 1, cc = c - 1;
+      if (ca * ca + cb * cb + cc * cc == 1) gs += 0.5 * (ca * q[0] + cb * q[1] + cc * q[2]);
+      gstar_minus_ge = gs - ge;
+    }
+    sink(i, f + omega * (hfe - f) + keep * (fs - fe), g + omega * (hge - g) + keep * gstar_minus_ge);
+  }
+}
+
+// ---- kernels --------------------------------------------------------------------------------
+// Fields written by k_ddf3_flux (float64, each `plane` elements at the population offsets):
+//   0..2 phi_x, phi_y, phi_z;  with transport control 3: T, 4..6: u_x, u_y, u_z.
+template <typename S, bool WALLS, bool PULL, bool EXT>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
+k_ddf3_flux(const S* __restrict__ A, int nx, int ny, int nz, int64_t pitch, int64_t plane,
+            DdfParams prm, int rows, double* __restrict__ fld) {
+  const int nbx = gridDim.x;
+  const int tile = blockIdx.x + nbx * blockIdx.y;
+  const int bx = tile % nbx, by = tile / nbx;
+  const int x = bx * blockDim.x + threadIdx.x;
+  if (x >= nx) return;
+  const int r_end = min(by * rows + rows, ny * nz);
+  for (int r = by * rows; r < r_end; ++r) {
+    const int y = r % ny, z = r / ny;
+    S hf[27], hg[27];
+    gather27<S, WALLS, PULL>(A, plane, nx, ny, nz, pitch, x, y, z, hf, hg);
+    Moments3 m;
+    moments3<EXT>(hf, hg, prm, m, prm.Fx, prm.Fy, prm.Fz, prm.Q);
+    const int64_t off = ((int64_t)z * ny + y) * pitch + x;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      fld[a * plane + off] = m.rho * m.u[a] * (m.u[a] * m.u[a] + 3.0 * (m.theta - 1.0 / 3.0));
+    if (EXT && prm.full) {
+      fld[3 * plane + off] = m.theta * prm.inv_R;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) fld[(4 + a) * plane + off] = m.u[a];
+    }
+  }
+}
+
+template <typename S, int HALO, bool WALLS, bool PULL, bool DIAG, bool EXT>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
+k_ddf3_collide(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int nz,
+               int64_t pitch, int64_t plane, DdfParams prm, const double* __restrict__ fld,
+               int rows, double* __restrict__ partials) {
+  const int nbx = gridDim.x;
+  const int tile = blockIdx.x + nbx * blockIdx.y;
+  const int bx = tile % nbx, by = tile / nbx;
+  const int x = bx * blockDim.x + threadIdx.x;
+  double acc[kDiagValues] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (x < nx) {
+    const int r_end = min(by * rows + rows, ny * nz);
+    for (int r = by * rows; r < r_end; ++r) {
+      const int y = r % ny, z = r / ny;
+      S hf[27], hg[27];
+      gather27<S, WALLS, PULL>(A, plane, nx, ny, nz, pitch, x, y, z, hf, hg);
+      Moments3 m;
+      moments3<EXT>(hf, hg, prm, m, prm.Fx, prm.Fy, prm.Fz, prm.Q);
+      const int64_t off = ((int64_t)z * ny + y) * pitch + x;
+      // offset of the node k steps along axis a: periodic in x and z; in y periodic, or the
+      // nearest fluid row beyond a wall (zero-order ghosts, Sec. III A)
+      auto at = [&](int a, int k) -> int64_t {
+        int xx = x, yy = y, zz = z;
+        if (a == 0) xx = ((x + k) % nx + nx) % nx;
+        if (a == 1) {
+          yy = y + k;
+          if (WALLS)
+            yy = yy < 0 ? 0 : (yy > ny - 1 ? ny - 1 : yy);
+          else
+            yy = (yy % ny + ny) % ny;
+        }
+        if (a == 2) zz = ((z + k) % nz + nz) % nz;
+        return ((int64_t)zz * ny + yy) * pitch + xx;
+      };
+      double ph[3] = {0.0, 0.0, 0.0};
+      if (prm.phi) {
+        const double inv_rho = 1.0 / m.rho;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const double* F = fld + a * plane;
+          double d;
+          if (HALO == 1)
+            d = 0.5 * (F[at(a, 1)] - F[at(a, -1)]);
+          else
+            d = upwind_or_central(F[at(a, -2)], F[at(a, -1)], F[off], F[at(a, 1)], F[at(a, 2)],
+                                  m.u[a]);
+          ph[a] = -d * inv_rho;
+        }
+      }
+      double gT[3] = {0.0, 0.0, 0.0}, divu = 0.0;
+      if (EXT && prm.full) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          gT[a] = 0.5 * (fld[3 * plane + at(a, 1)] - fld[3 * plane + at(a, -1)]);
+          divu += 0.5 * (fld[(4 + a) * plane + at(a, 1)] - fld[(4 + a) * plane + at(a, -1)]);
+        }
+      }
+      S* out = B + off;
+      collide3<EXT>(hf, hg, m, ph, gT, divu, prm, [&](int i, double tf, double tg) {
+        store_nt(out + i * plane, (S)tf);
+        store_nt(out + (27 + i) * plane, (S)tg);
+      });
+      if (DIAG) {
+        acc[0] += m.rho;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) acc[1 + a] += m.rho * m.u[a];
+        const double u2 = m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2];
+        acc[4] += m.rho * (m.e + 0.5 * u2);
+      }
+    }
+  }
+  if (DIAG) block_sum_store<kDiagValues>(acc, partials + (int64_t)tile * kDiagValues);
+}
+
+// f <- f^eq, g <- g^eq of the initial fields (Fig. 1), shifted by the rest state.
+template <typename S>
+__global__ void k_init_ddf3(const double* __restrict__ rho, const double* __restrict__ u,
+                            const double* __restrict__ T, S* __restrict__ A, int nx, int64_t nodes,
+                            int64_t pitch, int64_t plane, DdfParams prm) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nodes) return;
+  const int64_t off = (n / nx) * pitch + (n % nx);
+  const double theta = prm.R * T[n];
+  const double uu[3] = {u[n], u[nodes + n], u[2 * nodes + n]};
+  Axis X[3];
+  for (int a = 0; a < 3; ++a) axis_eq(uu[a], theta, X[a]);
+  for (int i = 0; i < 27; ++i) {
+    double fe, ge;
+    equilibria3(rho[n], prm.cv * T[n], i, X, fe, ge);
+    A[i * plane + off] = (S)(fe - prm.wf[i]);
+    A[(27 + i) * plane + off] = (S)(ge - prm.wg[i]);
+  }
+}
+
+// rho, u, T and rho E of the stored post-collision state: the closure with the sources of the
+// collision that produced it negated (prm.Fx, prm.Fy, prm.Fz, prm.Q hold them).
+template <typename S>
+__global__ void k_moments_ddf3(const S* __restrict__ A, int nx, int64_t nodes, int64_t pitch,
+                               int64_t plane, DdfParams prm, double* __restrict__ rho,
+                               double* __restrict__ u, double* __restrict__ T,
+                               double* __restrict__ edens) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nodes) return;
+  const int64_t off = (n / nx) * pitch + (n % nx);
+  S hf[27], hg[27];
+  for (int i = 0; i < 27; ++i) {
+    hf[i] = A[i * plane + off];
+    hg[i] = A[(27 + i) * plane + off];
+  }
+  Moments3 m;
+  moments3<true>(hf, hg, prm, m, -prm.Fx, -prm.Fy, -prm.Fz, -prm.Q);
+  rho[n] = m.rho;
+  for (int a = 0; a < 3; ++a) u[a * nodes + n] = m.u[a];
+  T[n] = m.theta / prm.R;
+  edens[n] = m.rho * (m.e + 0.5 * (m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2]));
+}
+
+__global__ void k_ddf3_rest_state(DdfParams prm, double* __restrict__ out) {
+  Axis X[3];
+  for (int a = 0; a < 3; ++a) axis_eq(0.0, prm.R, X[a]);
+  for (int i = 0; i < 27; ++i) equilibria3(1.0, prm.cv, i, X, out[i], out[27 + i]);
+}
+
+// ---- launchers ------------------------------------------------------------------------------
+static inline unsigned nblk3(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+hipError_t launch_ddf3_rest_state(const DdfParams& prm, double* out, hipStream_t s) {
+  k_ddf3_rest_state<<<1, 1, 0, s>>>(prm, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_ddf3(int kind, const double* rho, const double* u, const double* T,
+                            void* A, const Layout& L, const DdfParams& prm, hipStream_t s) {
+  if (kind == 0)
+    k_init_ddf3<float><<<nblk3(L.nodes()), kBlock, 0, s>>>(rho, u, T, static_cast<float*>(A), L.nx, L.nodes(), L.pitch, L.plane, prm);
+  else
+    k_init_ddf3<double><<<nblk3(L.nodes()), kBlock, 0, s>>>(rho, u, T, static_cast<double*>(A), L.nx, L.nodes(), L.pitch, L.plane, prm);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments_ddf3(int kind, const void* A, const Layout& L, const DdfParams& prm,
+                               double* rho, double* u, double* T, double* edens, hipStream_t s) {
+  if (kind == 0)
+    k_moments_ddf3<float><<<nblk3(L.nodes()), kBlock, 0, s>>>(static_cast<const float*>(A), L.nx, L.nodes(), L.pitch, L.plane, prm, rho, u, T, edens);
+  else
+    k_moments_ddf3<double><<<nblk3(L.nodes()), kBlock, 0, s>>>(static_cast<const double*>(A), L.nx, L.nodes(), L.pitch, L.plane, prm, rho, u, T, edens);
+  return hipGetLastError();
+}
+
+template <typename Fn>
+static void flag(bool b, Fn&& fn) {
+  if (b)
+    fn(std::true_type{});
+  else
+    fn(std::false_type{});
+}
+
+template <typename S>
+static void ddf3_step(bool walls, bool pull, const S* A, S* B, const Layout& L, const Grid& G,
+                      const DdfParams& prm, double* fld, double* partials, hipStream_t s) {
+  dim3 grid(G.nbx, G.nby), block(G.bx);
+  flag(walls, [&](auto W) {
+    flag(pull, [&](auto Pl) {
+      flag(prm.ext(), [&](auto E) {
+        constexpr bool w = decltype(W)::value, pl = decltype(Pl)::value, e = decltype(E)::value;
+        k_ddf3_flux<S, w, pl, e><<<grid, block, 0, s>>>(A, L.nx, L.ny, L.nz, L.pitch, L.plane,
+                                                        prm, G.rows, fld);
+        flag(partials != nullptr, [&](auto Dg) {
+          constexpr bool dg = decltype(Dg)::value;
+          if (prm.phi == 2)
+            k_ddf3_collide<S, 2, w, pl, dg, e><<<grid, block, 0, s>>>(
+                A, B, L.nx, L.ny, L.nz, L.pitch, L.plane, prm, fld, G.rows, partials);
+          else
+            k_ddf3_collide<S, 1, w, pl, dg, e><<<grid, block, 0, s>>>(
+                A, B, L.nx, L.ny, L.nz, L.pitch, L.plane, prm, fld, G.rows, partials);
+        });
+      });
+    });
+  });
+}
+
+hipError_t launch_ddf3(int kind, bool walls, bool pull, const void* A, void* B, const Layout& L,
+                       const Grid& G, const DdfParams& prm, double* fld, double* partials,
+                       hipStream_t s) {
+  if (kind == 0)
+    ddf3_step<float>(walls, pull, static_cast<const float*>(A), static_cast<float*>(B), L, G,
+                     prm, fld, partials, s);
+  else
+    ddf3_step<double>(walls, pull, static_cast<const double*>(A), static_cast<double*>(B), L, G,
+                      prm, fld, partials, s);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

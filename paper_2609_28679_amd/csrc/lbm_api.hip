@@ -32,6 +32,7 @@ struct lbm_ctx {
   int planes = 9;    // stored population planes per buffer
   bool aa = false;   // one buffer, in place (isothermal model): layout alternates with t parity
   DdfParams dp{};
+  double* fld = nullptr;  // D3Q27 double distribution: derivative fields
   Layout L{};
   Grid G{};
   hipStream_t stream = nullptr;
@@ -94,12 +95,14 @@ int hip_fail(lbm_ctx* c, hipError_t e, const char* where) {
 void sync_sources(lbm_ctx* c) {
   c->dp.Fx = c->F.x;
   c->dp.Fy = c->F.y;
+  c->dp.Fz = c->F.z;
   c->dp.Q = c->heat;
   c->dp.src = c->F.on() || c->heat != 0.0;
 }
 
 struct Plan {
   int D, Q, kind, planes, codec;
+  size_t off_fld;  // D3Q27 double distribution: derivative fields (7 float64 planes)
   bool ddf, aa;
   Layout L;
   Grid G;
@@ -143,7 +146,6 @@ int validate(const lbm_params* p, std::string& why) {
   if (!(p->tau > 0.5) || !std::isfinite(p->tau)) { why = "tau must be a finite value > 1/2"; return LBM_EINVAL; }
   if (p->diag_every < 0) { why = "diag_every must be >= 0"; return LBM_EINVAL; }
   if (p->model == LBM_MODEL_DDF) {
-    if (p->lattice != LBM_D2Q9) { why = "the double-distribution model is D2Q9 only"; return LBM_EINVAL; }
     if (!(p->R > 0.0) || !(p->cv > 0.0) || !std::isfinite(p->R) || !std::isfinite(p->cv)) { why = "R and cv must be positive"; return LBM_EINVAL; }
     if (p->phi < 0 || p->phi > 2) { why = "phi must be 0 (off), 1 (central) or 2 (upwind)"; return LBM_EINVAL; }
   }
@@ -184,7 +186,7 @@ void make_plan(const lbm_params* p, Plan& P) {
   P.planes = P.ddf ? 2 * P.Q : P.Q;
   P.elem = P.kind ? 8 : 4;
   P.L = make_layout(p->nx, p->ny, p->nz, (int)P.elem);
-  if (P.ddf)
+  if (P.ddf && P.D == 2)
     P.G = make_grid_ddf(P.L, p->phi == 2 ? 2 : 1, P.codec >= 0);
   else if (p->collision == LBM_COLLIDE_MLP)
     P.G = make_grid_mlp(P.L);
@@ -215,6 +217,8 @@ void make_plan(const lbm_params* p, Plan& P) {
   // surrogate region: 16 bytes of 64-bit counters (8-byte aligned for the atomics), then the
   // weights 256 bytes further
   P.off_mlp = off; off = align_up(off + 256 + (size_t)kMlpParams * 4, 256);
+  P.off_fld = off;
+  if (P.ddf && P.D == 3) off = align_up(off + (size_t)7 * P.L.plane * 8, 256);
   P.total = off;
 }
 
@@ -320,7 +324,7 @@ int lbm_create(const lbm_params* p, const double* rho0, const double* u0, const 
   {
     // alpha = (D+2)/D - rho c_s^2/P - eta/mu with rho c_s^2/P = gamma = 1 + R/c_v (ideal gas);
     // exactly 0 for the Navier-Stokes bulk viscosity. qc = c_p - k/mu, k/mu = c_p / Pr.
-    const double D = 2.0, gamma = 1.0 + p->R / p->cv, cp = p->cv + p->R;
+    const double D = (double)P.D, gamma = 1.0 + p->R / p->cv, cp = p->cv + p->R;
     c->dp.alpha = p->eta_over_mu >= 0.0 ? (D + 2.0) / D - gamma - p->eta_over_mu : 0.0;
     c->dp.qc = p->prandtl != 1.0 ? cp - cp / p->prandtl : 0.0;
     c->dp.full = c->dp.alpha != 0.0 || c->dp.qc != 0.0;
@@ -363,6 +367,7 @@ int lbm_create(const lbm_params* p, const double* rho0, const double* u0, const 
   c->partials = reinterpret_cast<double*>(c->ws + P.off_part);
   c->history = reinterpret_cast<double*>(c->ws + P.off_hist);
   c->readout = reinterpret_cast<double*>(c->ws + P.off_read);
+  if (P.ddf && P.D == 3) c->fld = reinterpret_cast<double*>(c->ws + P.off_fld);
   c->mlp_cnt = reinterpret_cast<unsigned long long*>(c->ws + P.off_mlp);
   c->mlp_w = reinterpret_cast<float*>(c->ws + P.off_mlp + 256);
   c->mlp_tol = p->mlp_tol;
@@ -378,18 +383,26 @@ int lbm_create(const lbm_params* p, const double* rho0, const double* u0, const 
   if (P.ddf) {
     // Fig. 1: f <- f^eq, g <- g^eq into B, then one collide-only pass B -> A so that A holds
     // the post-collision state of t = 0 (f* differs from f^eq when Phi is on)
+    double* d_T0 = c->readout + (size_t)(1 + P.D) * nodes;
     if (e == hipSuccess)
-      e = hipMemcpyAsync(c->readout + 3 * nodes, T0, nodes * sizeof(double), hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = launch_ddf_rest_state(c->dp, c->partials, c->stream);
-    double rest[18];
+      e = hipMemcpyAsync(d_T0, T0, nodes * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+      e = P.D == 2 ? launch_ddf_rest_state(c->dp, c->partials, c->stream)
+                   : launch_ddf3_rest_state(c->dp, c->partials, c->stream);
+    double rest[54];
     if (e == hipSuccess) e = hipMemcpyAsync(rest, c->partials, sizeof(rest), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    for (int i = 0; i < 9; ++i) {
+    for (int i = 0; i < P.Q; ++i) {
       c->dp.wf[i] = rest[i];
-      c->dp.wg[i] = rest[9 + i];
+      c->dp.wg[i] = rest[P.Q + i];
     }
-    if (e == hipSuccess) e = launch_init_ddf(c->fmt, c->readout, c->readout + nodes, c->readout + 3 * nodes, c->B, c->L, c->dp, c->stream);
-    if (e == hipSuccess) e = launch_ddf(c->fmt, p->wall_y != 0, false, c->B, c->A, c->L, c->G, c->dp, c->s_enc, c->s_dec, nullptr, c->stream);
+    if (P.D == 2) {
+      if (e == hipSuccess) e = launch_init_ddf(c->fmt, c->readout, c->readout + nodes, d_T0, c->B, c->L, c->dp, c->stream);
+      if (e == hipSuccess) e = launch_ddf(c->fmt, p->wall_y != 0, false, c->B, c->A, c->L, c->G, c->dp, c->s_enc, c->s_dec, nullptr, c->stream);
+    } else {
+      if (e == hipSuccess) e = launch_init_ddf3(c->kind, c->readout, c->readout + nodes, d_T0, c->B, c->L, c->dp, c->stream);
+      if (e == hipSuccess) e = launch_ddf3(c->kind, p->wall_y != 0, false, c->B, c->A, c->L, c->G, c->dp, c->fld, nullptr, c->stream);
+    }
   } else if (e == hipSuccess && c->codec >= 0) {
     e = launch_init_bgk_red(c->readout, c->readout + nodes, c->A, c->L, c->stream);
   } else if (e == hipSuccess) {
@@ -417,7 +430,9 @@ int lbm_step(lbm_ctx* c, int64_t n) {
     if (c->p.collision == LBM_COLLIDE_MLP) {
       if (!c->mlp_set) return fail(c, LBM_ESTATE, "surrogate weights not installed (lbm_set_mlp)");
       e = launch_bgk_d2q9_mlp(c->A, c->B, c->L, c->G, c->omega, c->p.wall_y != 0, c->mlp_w, c->mlp_tol, c->mlp_cnt, part, c->stream);
-    } else if (c->ddf)
+    } else if (c->ddf && c->D == 3)
+      e = launch_ddf3(c->kind, c->p.wall_y != 0, true, c->A, c->B, c->L, c->G, c->dp, c->fld, part, c->stream);
+    else if (c->ddf)
       e = launch_ddf(c->fmt, c->p.wall_y != 0, true, c->A, c->B, c->L, c->G, c->dp, c->s_enc, c->s_dec, part, c->stream);
     else if (c->codec >= 0)
       e = launch_bgk_d2q9_red(c->codec, c->A, c->B, c->L, c->G, c->omega, c->p.wall_y != 0, c->s_enc, c->s_dec, part, c->stream);
@@ -502,8 +517,12 @@ int lbm_moments(lbm_ctx* c, double* rho, double* u, double* T, double* totals) {
     DdfParams rd = c->dp;
     rd.Fx = c->F_state.x;
     rd.Fy = c->F_state.y;
+    rd.Fz = c->F_state.z;
     rd.Q = c->heat_state;
-    HIP_TRY(c, launch_moments_ddf(c->fmt, c->A, c->L, rd, d_rho, d_u, d_T, d_e, c->stream));
+    if (c->D == 3)
+      HIP_TRY(c, launch_moments_ddf3(c->kind, c->A, c->L, rd, d_rho, d_u, d_T, d_e, c->stream));
+    else
+      HIP_TRY(c, launch_moments_ddf(c->fmt, c->A, c->L, rd, d_rho, d_u, d_T, d_e, c->stream));
   } else if (c->codec >= 0)
     HIP_TRY(c, launch_moments_bgk_red(c->A, c->L, d_rho, d_u, c->stream));
   else
@@ -532,7 +551,7 @@ int lbm_populations(lbm_ctx* c, double* f, double* g) {
     double* dst = i < c->Q ? f + (size_t)i * nodes : (g ? g + (size_t)(i - c->Q) * nodes : nullptr);
     if (!dst) continue;
     if (c->ddf)
-      HIP_TRY(c, launch_decode_ddf(c->fmt, i, c->A, c->L, c->dp, c->s_dec, c->readout, c->stream));
+      HIP_TRY(c, launch_decode_ddf(c->fmt, c->Q, i, c->A, c->L, c->dp, c->s_dec, c->readout, c->stream));
     else if (c->codec >= 0)
       HIP_TRY(c, launch_decode_bgk_red(c->codec, i, c->A, c->L, c->s_dec, c->readout, c->stream));
     else

@@ -60,7 +60,7 @@ struct DdfParams {
   int phi;     // 0: no Galilean correction, 1: central derivative, 2: upwind derivative
   // uniform body force (Fx, Fy) and heat source Q of the collision (lattice units); src = any
   // of them non-zero
-  double Fx = 0.0, Fy = 0.0, Q = 0.0;
+  double Fx = 0.0, Fy = 0.0, Fz = 0.0, Q = 0.0;
   bool src = false;
   // transport control: alpha = (D+2)/D - gamma - eta/mu in theta* (bulk viscosity eta) and
   // qc = c_p - k/mu in q^c = P qc grad T (Prandtl number); full = either non-zero
@@ -69,9 +69,10 @@ struct DdfParams {
   // the kernels take the extended path (shifted state with sources and/or transport terms)
   bool ext() const { return src || full; }
   // storage shift: f^eq and g^eq at rest at the reference state rho = 1, T = 1 (computed by
-  // launch_ddf_rest_state on the device at context creation)
-  double wf[9];
-  double wg[9];
+  // launch_ddf_rest_state / launch_ddf3_rest_state on the device at context creation; the
+  // first 9 entries for D2Q9, 27 for D3Q27)
+  double wf[27];
+  double wg[27];
 };
 
 // ---- launchers (return the first HIP error) -----------------------------------------------
@@ -114,8 +115,19 @@ hipError_t launch_init_ddf(int kind, const double* rho, const double* u, const d
                            void* A, const Layout& L, const DdfParams& prm, hipStream_t s);
 hipError_t launch_moments_ddf(int kind, const void* A, const Layout& L, const DdfParams& prm,
                               double* rho, double* u, double* T, double* edens, hipStream_t s);
-hipError_t launch_decode_ddf(int kind, int i, const void* A, const Layout& L,
+hipError_t launch_decode_ddf(int kind, int Q, int i, const void* A, const Layout& L,
                              const DdfParams& prm, float s_dec, double* out, hipStream_t s);
+// D3Q27 double distribution (float32 kind 0 / float64 kind 1 storage, 54 planes). One step is
+// two launches: fluxes (and, with transport control, T and u) into `fld` (7 float64 fields of
+// L.plane elements), then the collision; pull = false collides in place of streaming.
+hipError_t launch_ddf3_rest_state(const DdfParams& prm, double* out, hipStream_t s);
+hipError_t launch_init_ddf3(int kind, const double* rho, const double* u, const double* T,
+                            void* A, const Layout& L, const DdfParams& prm, hipStream_t s);
+hipError_t launch_ddf3(int kind, bool walls, bool pull, const void* A, void* B, const Layout& L,
+                       const Grid& G, const DdfParams& prm, double* fld, double* partials,
+                       hipStream_t s);
+hipError_t launch_moments_ddf3(int kind, const void* A, const Layout& L, const DdfParams& prm,
+                               double* rho, double* u, double* T, double* edens, hipStream_t s);
 // Reduced storage (D2Q9 isothermal): 3 float32 moment planes then 6 uint16 planes.
 // codec 0 = bfloat16, 1 = float16 with scale s_enc = 2^S, s_dec = 2^-S.
 Grid make_grid_red(const Layout& L);

@@ -45,6 +45,15 @@ def taylor_green_3d(n, u0, rho0=1.0):
     return rho, u
 
 
+def thermal_taylor_green_3d(n, u0, T0=0.9, P0=1.0 / 3.0, R=1.0 / 3.0):
+    """The 3D Taylor-Green velocity of taylor_green_3d at uniform temperature T0 and pressure
+    P0 (ideal gas, rho = P0 / (R T0)): the double-distribution workload in 3D."""
+    _, u = taylor_green_3d(n, u0)
+    T = np.full((n, n, n), float(T0))
+    rho = np.full((n, n, n), P0 / (R * T0))
+    return rho, u, T
+
+
 def random_phase_turbulence_2d(n, seed, kmax_frac=0.125, rms_mach=RMS_MACH_TURB):
     """Divergence-free random-phase velocity field with energy spectrum E(k) ~ k^(-5/3).
 

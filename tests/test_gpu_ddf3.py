@@ -1,0 +1,116 @@
+"""GPU parity of the D3Q27 double-distribution kernels (two launches per step: fluxes, then the
+collision) against the FP64 oracle.
+
+Bars: float64 storage 1e-13 absolute on rho, u and T and on the stored post-collision
+populations (exact indexing, rounding order only); float32 storage rel-L2 <= 1e-5 on velocity
+and on temperature deviations. The oracle's D3Q27 double distribution applies the operator
+definition of g^eq literally and is slow, so the lattices here are small but span several
+workgroups in x and ragged tile edges.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import announce, rel_l2, require_gpu
+from oracle import ddf
+
+pytestmark = pytest.mark.gpu
+
+R, CV, P0 = 1.0 / 3.0, 5.0 / 6.0, 1.0 / 3.0
+STENCIL = {0: "central", 1: "central", 2: "upwind"}
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _fields(shape, seed):
+    rng = np.random.default_rng(seed)
+    T = 0.9 + 0.05 * rng.standard_normal(shape)
+    rho = P0 / (R * T) * (1 + 0.01 * rng.standard_normal(shape))
+    u = 0.03 * rng.standard_normal((3,) + shape)  # no exact zeros (upwind side choice)
+    return rho, u, T
+
+
+def _run(rho, u, T, steps, storage, tau=0.7, **kw):
+    from paper_2609_28679_amd.binding import Lattice
+    lat = Lattice(rho, u, T, lattice="D3Q27", model="ddf", R=R, cv=CV, tau=tau,
+                  storage=storage, **kw)
+    lat.step(steps)
+    r, v, t, tot = lat.moments()
+    f, g = lat.populations()
+    lat.close()
+    return r, v, t, tot, f, g
+
+
+EXTRA = [dict(), dict(force=(1e-4, -2e-4, 1e-4), heat_source=1e-4, prandtl=0.71,
+                      eta_over_mu=1.5)]
+
+
+@pytest.mark.parametrize("extra", [0, 1])
+@pytest.mark.parametrize("phi", [1, 2, 0])
+@pytest.mark.parametrize("walls", [True, False])
+def test_fp64_matches_oracle(walls, phi, extra):
+    kw = EXTRA[extra]
+    shape = (5, 7, 9)
+    announce("D3Q27 DDF fp64 %s walls=%s phi=%d extra=%s 5 steps" % (shape, walls, phi, kw))
+    rho, u, T = _fields(shape, seed=31 + extra)
+    steps, tau = 5, 0.7
+    rg, ug, tg, tot, fg, gg = _run(rho, u, T, steps, "fp64", tau=tau, wall_y=walls, phi=phi,
+                                   **kw)
+    eta = kw.get("eta_over_mu")
+    gas = ddf.Gas(R, CV, (tau - 0.5) * P0, prandtl=kw.get("prandtl", 1.0), eta_over_mu=eta)
+    F = np.asarray(kw["force"]) if "force" in kw else None
+    Q = kw.get("heat_source", 0.0)
+    f, g = ddf.init_equilibrium(rho, u, T, gas)
+    f, g = ddf.run(f, g, gas, steps, walls_y=walls, phi_on=phi > 0, stencil=STENCIL[phi],
+                   F=F, Q=Q)
+    ro, uo, to = ddf.temperature(f, g, gas, F=F, Q=Q)
+    assert np.abs(rg - ro).max() <= 1e-13
+    assert np.abs(ug - uo).max() <= 1e-13
+    assert np.abs(tg - to).max() <= 1e-13
+    ft, gt = ddf.collide(f, g, gas, walls, phi > 0, STENCIL[phi], F=F, Q=Q)
+    assert np.abs(fg - ft).max() <= 1e-13
+    assert np.abs(gg - gt).max() <= 1e-13
+    assert abs(tot[0] - ro.sum()) <= 1e-10
+
+
+def test_fp64_several_workgroups_in_x():
+    shape = (3, 4, 300)
+    announce("D3Q27 DDF fp64 %s walls phi=1 3 steps" % (shape,))
+    rho, u, T = _fields(shape, seed=40)
+    rg, ug, tg, _, _, _ = _run(rho, u, T, 3, "fp64", wall_y=True, phi=1)
+    gas = ddf.Gas(R, CV, 0.2 * P0)
+    f, g = ddf.run(*ddf.init_equilibrium(rho, u, T, gas), gas, 3, walls_y=True)
+    ro, uo, to = ddf.temperature(f, g, gas)
+    assert np.abs(ug - uo).max() <= 1e-13
+    assert np.abs(tg - to).max() <= 1e-13
+
+
+def test_fp32_matches_oracle():
+    shape = (10, 8, 40)
+    announce("D3Q27 DDF fp32 %s walls phi=1 20 steps" % (shape,))
+    rho, u, T = _fields(shape, seed=41)
+    _, ug, tg, _, _, _ = _run(rho, u, T, 20, "fp32", tau=0.6, wall_y=True, phi=1)
+    gas = ddf.Gas(R, CV, 0.1 * P0)
+    f, g = ddf.run(*ddf.init_equilibrium(rho, u, T, gas), gas, 20, walls_y=True)
+    _, uo, to = ddf.temperature(f, g, gas)
+    assert rel_l2(ug, uo) <= 1e-5
+    assert rel_l2(tg - 0.9, to - 0.9) <= 1e-5
+
+
+def test_conservation_with_diagnostics():
+    shape = (16, 16, 64)
+    announce("D3Q27 DDF fp64 %s periodic conservation 50 steps" % (shape,))
+    rho, u, T = _fields(shape, seed=42)
+    from paper_2609_28679_amd.binding import Lattice
+    lat = Lattice(rho, u, T, lattice="D3Q27", model="ddf", R=R, cv=CV, tau=0.6,
+                  storage="fp64", wall_y=False, phi=1, diag_every=10)
+    m0 = lat.moments()[3]
+    lat.step(50)
+    h = lat.diag_history()
+    lat.close()
+    assert len(h) == 5
+    assert np.all(np.abs(h[:, 1] - m0[0]) <= 1e-12 * m0[0])              # mass
+    assert np.all(np.abs(h[:, 2:5] - m0[1:4]) <= 1e-12 * m0[0])           # momentum
+    assert np.all(np.abs(h[:, 5] - m0[4]) <= 1e-12 * m0[4])               # total energy
