@@ -67,7 +67,7 @@ typedef struct lbm_ctx lbm_ctx; /* opaque; owned by the library */
 
 typedef struct {
   int32_t lattice;   /* LBM_D2Q9 or LBM_D3Q27 */
-  int32_t model;     /* LBM_MODEL_BGK or LBM_MODEL_DDF (DDF: D2Q9 only) */
+  int32_t model;     /* LBM_MODEL_BGK or LBM_MODEL_DDF (DDF on D3Q27: FP32/FP64 storage) */
   int32_t storage;   /* LBM_STORE_*; reduced storage (BF16, FP16): D2Q9 only */
   int32_t collision; /* LBM_COLLIDE_*; MLP: D2Q9 BGK with FP32 storage only */
   int32_t nx, ny, nz; /* lattice size in nodes; nz = 1 for D2Q9; each >= 1 (nx, ny >= 3) */
