@@ -209,7 +209,57 @@ def collide(f, g, gas, walls_y, phi_on=True, stencil="central", F=None, Q=0.0):
     return ft, gt
 
 
-def run(f, g, gas, nsteps, walls_y=True, phi_on=True, stencil="central", F=None, Q=0.0):
+class NeqWalls:
+    """Non-equilibrium extrapolation walls (App. B, thermal Couette): the first and last rows
+    (y = 0 and y = ny - 1) are boundary nodes B on the walls, with wall velocities u_lo, u_hi
+    (D components) and temperatures T_lo, T_hi; N is the neighbouring row (1 or ny - 2).
+    density="pressure" (the default reading) takes rho_B = rho_N T_N / T_W, the density that
+    continues the pressure P_N = rho_N R T_N to the wall; density="literal" takes rho_B = rho_N,
+    the paper's extrapolation written out (the two agree where T_N = T_W)."""
+
+    def __init__(self, u_lo, T_lo, u_hi, T_hi, density="pressure"):
+        self.u = (np.asarray(u_lo, dtype=np.float64), np.asarray(u_hi, dtype=np.float64))
+        self.T = (float(T_lo), float(T_hi))
+        if density not in ("pressure", "literal"):
+            raise ValueError(density)
+        self.density = density
+
+
+def apply_neq_walls(f, g, gas, walls):
+    """Boundary rows of the pre-collision populations:
+    f_B = f^eq(rho_B, u_W, T_W) + (f_N - f^eq(rho_N, u_N, T_N)), and the same for g (App. B),
+    with rho_B from NeqWalls.density. No sources (the context rejects them with these walls)."""
+    rho, u, rhoE = moments(f, g)
+    T, _, theta = closure(rho, u, rhoE, gas)
+    fe = feq(rho, u, theta)
+    ge = geq(rho, u, theta, gas.cv * T)
+    ny = f.shape[-2]
+    f, g = f.copy(), g.copy()
+    D = u.shape[0]
+    for side, (B, N) in enumerate(((0, 1), (ny - 1, ny - 2))):
+        TW = walls.T[side]
+        rN, TN = rho[..., N, :], T[..., N, :]
+        rB = rN * TN / TW if walls.density == "pressure" else rN
+        uW = walls.u[side].reshape((D,) + (1,) * rB.ndim) * np.ones((D,) + rB.shape)
+        TWf = np.full(rB.shape, TW)
+        f[..., B, :] = feq(rB, uW, gas.R * TWf) + (f[..., N, :] - fe[..., N, :])
+        g[..., B, :] = geq(rB, uW, gas.R * TWf, gas.cv * TWf) + (g[..., N, :] - ge[..., N, :])
+    return f, g
+
+
+def run(f, g, gas, nsteps, walls_y=True, phi_on=True, stencil="central", F=None, Q=0.0,
+        neq=None):
+    """nsteps of collide-then-stream from the pre-collision state (f, g). With neq (NeqWalls)
+    the boundary rows are rebuilt before every collision and once more at the end, so the
+    returned state is the pre-collision state of the last time; streaming then wraps
+    periodically (the wrapped boundary rows are rebuilt) and derivative ghosts at the walls
+    are zero-order as for the bounce-back walls."""
+    if neq is not None:
+        for _ in range(nsteps):
+            f, g = apply_neq_walls(f, g, gas, neq)
+            ft, gt = collide(f, g, gas, True, phi_on, stencil, F, Q)
+            f, g = bgk.stream(ft), bgk.stream(gt)
+        return apply_neq_walls(f, g, gas, neq)
     for _ in range(nsteps):
         ft, gt = collide(f, g, gas, walls_y, phi_on, stencil, F, Q)
         f = bgk.stream(ft, walls_y)
