@@ -71,7 +71,10 @@ typedef struct {
   int32_t storage;   /* LBM_STORE_*; reduced storage (BF16, FP16): D2Q9 only */
   int32_t collision; /* LBM_COLLIDE_*; MLP: D2Q9 BGK with FP32 storage only */
   int32_t nx, ny, nz; /* lattice size in nodes; nz = 1 for D2Q9; each >= 1 (nx, ny >= 3) */
-  int32_t wall_y;     /* 0: periodic in y; 1: half-way bounce-back walls at y = -1/2 and ny-1/2 */
+  int32_t wall_y;     /* 0: periodic in y; 1: half-way bounce-back walls at y = -1/2 and ny-1/2;
+                         2 (DDF, D2Q9, FP32/FP64, ny >= 3, no sources): non-equilibrium
+                         extrapolation walls on the rows y = 0 and y = ny-1 with the velocities
+                         wall_u and temperatures wall_T (App. B, thermal Couette) */
   double tau;  /* BGK: tau_LB = 1/(2 beta) > 1/2, so nu = (tau - 1/2)/3.
                   DDF: the same value at the reference pressure P0 = 1/3 defines the dynamic
                   viscosity mu = (tau - 1/2) P0; per node tau_kin = mu / P (Sec. II A). */
@@ -92,6 +95,12 @@ typedef struct {
                           Navier-Stokes value 2/D - R/c_v; sets alpha = (D+2)/D - gamma - eta/mu
                           in theta* = theta + alpha theta div u (Sec. II A). Values >= 0 need
                           FP32/FP64 storage. */
+  double wall_u[2][3]; /* wall_y = 2: wall velocity [bottom (y = 0), top (y = ny-1)][x, y, z];
+                          the normal component must be 0 */
+  double wall_T[2];    /* wall_y = 2: wall temperatures [bottom, top], > 0 */
+  int32_t wall_density; /* wall_y = 2: boundary density rho_B; 0 (default) = rho_N T_N / T_W
+                          (the neighbour's pressure continued to the wall), 1 = rho_N (the
+                          extrapolation as written in App. B; it leaks mass where T_N != T_W) */
   int32_t phi;         /* DDF: 1 = Galilean correction Phi on (the paper), 0 = off */
   int32_t fp16_scale_log2; /* LBM_STORE_FP16: S in [0, 24]; stored value = (f - f^eq) * 2^S */
   int32_t diag_every;  /* > 0: every diag_every steps record float64 totals (mass, momentum,

@@ -34,7 +34,9 @@ class LbmParams(ctypes.Structure):
         ("nz", ctypes.c_int32), ("wall_y", ctypes.c_int32), ("tau", ctypes.c_double),
         ("R", ctypes.c_double), ("cv", ctypes.c_double), ("force", ctypes.c_double * 3),
         ("heat_source", ctypes.c_double), ("prandtl", ctypes.c_double),
-        ("eta_over_mu", ctypes.c_double), ("phi", ctypes.c_int32),
+        ("eta_over_mu", ctypes.c_double), ("wall_u", (ctypes.c_double * 3) * 2),
+        ("wall_T", ctypes.c_double * 2), ("wall_density", ctypes.c_int32),
+        ("phi", ctypes.c_int32),
         ("fp16_scale_log2", ctypes.c_int32), ("diag_every", ctypes.c_int32),
         ("streaming", ctypes.c_int32), ("mlp_tol", ctypes.c_double), ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t),
@@ -117,7 +119,9 @@ class Lattice:
 
     rho0: (ny, nx) or (nz, ny, nx) float64; u0: (D,) + that shape; T0 for the DDF model;
     force: uniform body force (D components) or None; heat_source: uniform heat source Q,
-    prandtl: Prandtl number, eta_over_mu: bulk viscosity ratio (< 0: Navier-Stokes value)
+    prandtl: Prandtl number, eta_over_mu: bulk viscosity ratio (< 0: Navier-Stokes value),
+    neq_walls: non-equilibrium extrapolation walls on the first and last rows,
+    dict(u=((ux, uy), (ux, uy)), T=(T_bottom, T_top), density="pressure"|"literal")
     (double-distribution model).
     The context workspace is a torch uint8 tensor on the current device; launches go on
     torch's current stream.
@@ -127,7 +131,7 @@ class Lattice:
                  collision="plain", wall_y=False, tau=0.8, R=1.0 / 3.0, cv=5.0 / 6.0, phi=1,
                  fp16_scale_log2=16, diag_every=0, mlp_tol=0.05, streaming="auto",
                  force=None, heat_source=0.0, prandtl=1.0, eta_over_mu=-1.0,
-                 torch_workspace=True):
+                 neq_walls=None, torch_workspace=True):
         torch = _torch()
         lib = load()
         rho0 = np.ascontiguousarray(rho0, dtype=np.float64)
@@ -161,6 +165,14 @@ class Lattice:
         p.heat_source = float(heat_source)
         p.prandtl = float(prandtl)
         p.eta_over_mu = float(eta_over_mu)
+        if neq_walls is not None:
+            # dict(u=((ux, uy), (ux, uy)), T=(T_bottom, T_top), density="pressure"|"literal")
+            p.wall_y = 2
+            for side in range(2):
+                for a, v in enumerate(neq_walls["u"][side]):
+                    p.wall_u[side][a] = float(v)
+                p.wall_T[side] = float(neq_walls["T"][side])
+            p.wall_density = {"pressure": 0, "literal": 1}[neq_walls.get("density", "pressure")]
         p.fp16_scale_log2 = int(fp16_scale_log2)
         p.diag_every = int(diag_every)
         p.streaming = STREAMINGS[streaming]

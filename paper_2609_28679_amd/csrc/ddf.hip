@@ -55,6 +55,7 @@ struct IoFull {
   const S* A;
   S* B;
   int64_t plane;
+  const S* nb;  // boundary rows of the non-equilibrium extrapolation walls (k_ddf_neq_rows)
   struct RawRow {};
   __device__ __forceinline__ void fetch_row(RawRow&, int, int, int, int, int64_t, int) const {}
   __device__ __forceinline__ void put_row(float*, const RawRow&, int, int, int, const DdfParams&) const {}
@@ -70,6 +71,15 @@ struct IoFull {
         hf[i] = A[i * plane + r0 + x];
         hg[i] = A[(9 + i) * plane + r0 + x];
       }
+    }
+  }
+  // pre-collision populations of boundary row `side` (0: y = 0, 1: y = ny - 1), column x
+  __device__ __forceinline__ void gather_wall(int side, int x, int64_t pitch, S (&hf)[9],
+                                             S (&hg)[9]) const {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      hf[i] = nb[(side * 18 + i) * pitch + x];
+      hg[i] = nb[(side * 18 + 9 + i) * pitch + x];
     }
   }
   __device__ __forceinline__ void store(int64_t off, int i, double htf, double, double htg,
@@ -261,6 +271,12 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
     const int yp = rr == ny - 1 ? 0 : rr + 1;
     const int64_t r0 = (int64_t)rr * pitch, rm = (int64_t)ym * pitch, rp = (int64_t)yp * pitch;
     const bool top = WALLS && rr == ny - 1, bot = WALLS && rr == 0;
+    if constexpr (!IO::kStaged) {
+      if (WALLS && prm.neq && (top || bot)) {  // rebuilt boundary rows (k_ddf_neq_rows)
+        io.gather_wall(top ? 1 : 0, x, pitch, hf, hg);
+        return;
+      }
+    }
     io.gather(PULL, r0, rm, rp, x, xm, xp, top, bot, prm, r, tid, s_stage, hf, hg);
   };
   // window row w exists (inside the window and, with walls, inside the lattice)
@@ -535,15 +551,74 @@ static IoRed<Codec> make_red(const void* A, void* B, const Layout& L, float se, 
   return io;
 }
 
+// Non-equilibrium extrapolation walls (App. B): the pre-collision populations of the boundary
+// rows B (y = 0, ny - 1, on the walls) are f^eq(rho_B, u_W, T_W) + f_N - f^eq(rho_N, u_N, T_N)
+// with N the neighbouring row (1, ny - 2), pulled like any fluid row (PULL = false: its own
+// slots), and rho_B = rho_N T_N / T_W (pressure continued to the wall) or rho_N (literal).
+// One thread per column, gridDim.y = 2 walls; the rows go to nb[(side*18 + k)*pitch + x],
+// k < 9 f - w, k >= 9 g - v.
+template <typename S, bool PULL>
+__global__ void __launch_bounds__(kBlock)
+k_ddf_neq_rows(const S* __restrict__ A, int nx, int ny, int64_t pitch, int64_t plane,
+               DdfParams prm, S* __restrict__ nb) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= nx) return;
+  const int side = blockIdx.y;
+  const int N = side ? ny - 2 : 1;
+  const int xm = x == 0 ? nx - 1 : x - 1;
+  const int xp = x == nx - 1 ? 0 : x + 1;
+  S hf[9], hg[9];
+  const int64_t r0 = (int64_t)N * pitch;
+  if (PULL) {
+    gather9(A, plane, r0, r0 - pitch, r0 + pitch, x, xm, xp, false, false, hf);
+    gather9(A + 9 * plane, plane, r0, r0 - pitch, r0 + pitch, x, xm, xp, false, false, hg);
+  } else {
+    for (int i = 0; i < 9; ++i) {
+      hf[i] = A[i * plane + r0 + x];
+      hg[i] = A[(9 + i) * plane + r0 + x];
+    }
+  }
+  double f[9], g[9];
+  for (int i = 0; i < 9; ++i) {
+    f[i] = (double)hf[i] + prm.wf[i];
+    g[i] = (double)hg[i] + prm.wg[i];
+  }
+  Moments m;
+  moments_closure(f, g, prm, m);
+  double feN[9], geN[9], feB[9], geB[9];
+  equilibria(m.rho, m.ux, m.uy, m.theta, m.e, feN, geN);
+  const double TW = prm.Tw[side];
+  const double TN = m.theta * prm.inv_R;
+  const double rhoB = prm.neq_literal ? m.rho : m.rho * TN / TW;
+  equilibria(rhoB, prm.uw[side][0], prm.uw[side][1], prm.R * TW, prm.cv * TW, feB, geB);
+  for (int i = 0; i < 9; ++i) {
+    nb[(side * 18 + i) * pitch + x] = (S)(feB[i] + (f[i] - feN[i]) - prm.wf[i]);
+    nb[(side * 18 + 9 + i) * pitch + x] = (S)(geB[i] + (g[i] - geN[i]) - prm.wg[i]);
+  }
+}
+
 hipError_t launch_ddf(int fmt, bool walls, bool pull, const void* A, void* B, const Layout& L,
                       const Grid& G, const DdfParams& prm, float s_enc, float s_dec,
-                      double* partials, hipStream_t s) {
+                      double* partials, void* nb, hipStream_t s) {
   if (prm.ext() && fmt >= 2) return hipErrorInvalidValue;  // no extended path with reduced storage
+  if (prm.neq) {
+    if (fmt >= 2 || !walls || !nb || L.ny < 3) return hipErrorInvalidValue;
+    dim3 grid((L.nx + kBlock - 1) / kBlock, 2);
+    if (fmt == 0) {
+      if (pull) k_ddf_neq_rows<float, true><<<grid, kBlock, 0, s>>>(static_cast<const float*>(A), L.nx, L.ny, L.pitch, L.plane, prm, static_cast<float*>(nb));
+      else k_ddf_neq_rows<float, false><<<grid, kBlock, 0, s>>>(static_cast<const float*>(A), L.nx, L.ny, L.pitch, L.plane, prm, static_cast<float*>(nb));
+    } else {
+      if (pull) k_ddf_neq_rows<double, true><<<grid, kBlock, 0, s>>>(static_cast<const double*>(A), L.nx, L.ny, L.pitch, L.plane, prm, static_cast<double*>(nb));
+      else k_ddf_neq_rows<double, false><<<grid, kBlock, 0, s>>>(static_cast<const double*>(A), L.nx, L.ny, L.pitch, L.plane, prm, static_cast<double*>(nb));
+    }
+  }
   if (fmt == 0) {
-    IoFull<float> io{static_cast<const float*>(A), static_cast<float*>(B), L.plane};
+    IoFull<float> io{static_cast<const float*>(A), static_cast<float*>(B), L.plane,
+                     static_cast<const float*>(nb)};
     ddf_launch_h(walls, pull, io, L, G, prm, partials, s);
   } else if (fmt == 1) {
-    IoFull<double> io{static_cast<const double*>(A), static_cast<double*>(B), L.plane};
+    IoFull<double> io{static_cast<const double*>(A), static_cast<double*>(B), L.plane,
+                      static_cast<const double*>(nb)};
     ddf_launch_h(walls, pull, io, L, G, prm, partials, s);
   } else if (fmt == 2) {
     ddf_launch_h(walls, pull, make_red<CodecBF16>(A, B, L, s_enc, s_dec), L, G, prm, partials, s);

@@ -33,6 +33,7 @@ struct lbm_ctx {
   bool aa = false;   // one buffer, in place (isothermal model): layout alternates with t parity
   DdfParams dp{};
   double* fld = nullptr;  // D3Q27 double distribution: derivative fields
+  void* nb = nullptr;     // non-equilibrium extrapolation walls: boundary rows
   Layout L{};
   Grid G{};
   hipStream_t stream = nullptr;
@@ -103,6 +104,7 @@ void sync_sources(lbm_ctx* c) {
 struct Plan {
   int D, Q, kind, planes, codec;
   size_t off_fld;  // D3Q27 double distribution: derivative fields (7 float64 planes)
+  size_t off_nb;   // non-equilibrium extrapolation walls: 2 x 18 boundary rows
   bool ddf, aa;
   Layout L;
   Grid G;
@@ -110,6 +112,13 @@ struct Plan {
   size_t off_A, off_B, off_part, off_hist, off_read, off_mlp, total;
   int partial_slots;
 };
+
+// Product-form factors must be positive: Psi_0 = 1 - theta - u^2 > 0 and
+// Psi_+- = (theta + u^2 +- u)/2 > 0 for every component.
+bool admissible(double theta, double u) {
+  const double z = theta + u * u;
+  return z < 1.0 && z > std::fabs(u);
+}
 
 // Sources: a body force needs the paper's collision and FP32 or FP64 storage (isothermal or
 // double-distribution model), a heat source in addition the double-distribution model. Both
@@ -130,6 +139,7 @@ int validate_sources(const lbm_params* p, const double* force, double heat, std:
     return LBM_EINVAL;
   }
   if (forced && p->lattice == LBM_D2Q9 && force[2] != 0.0) { why = "D2Q9 requires force[2] = 0"; return LBM_EINVAL; }
+  if ((forced || heat != 0.0) && p->wall_y == 2) { why = "force and heat_source are not supported with wall_y = 2"; return LBM_EINVAL; }
   return LBM_OK;
 }
 
@@ -142,7 +152,23 @@ int validate(const lbm_params* p, std::string& why) {
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) { why = "lattice sizes must be >= 1"; return LBM_EINVAL; }
   if (p->lattice == LBM_D2Q9 && p->nz != 1) { why = "D2Q9 requires nz = 1"; return LBM_EINVAL; }
   if ((int64_t)p->nx * p->ny * p->nz > (int64_t)1 << 34) { why = "lattice too large"; return LBM_EINVAL; }
-  if (p->wall_y != 0 && p->wall_y != 1) { why = "wall_y must be 0 or 1"; return LBM_EINVAL; }
+  if (p->wall_y < 0 || p->wall_y > 2) { why = "wall_y must be 0, 1 or 2"; return LBM_EINVAL; }
+  if (p->wall_y == 2) {
+    if (p->model != LBM_MODEL_DDF || p->lattice != LBM_D2Q9 ||
+        (p->storage != LBM_STORE_FP32 && p->storage != LBM_STORE_FP64) || p->ny < 3) {
+      why = "non-equilibrium extrapolation walls (wall_y = 2) need the D2Q9 double-distribution model, FP32 or FP64 storage and ny >= 3";
+      return LBM_EINVAL;
+    }
+    for (int side = 0; side < 2; ++side) {
+      const double T = p->wall_T[side], ux = p->wall_u[side][0];
+      if (!(T > 0.0) || !std::isfinite(T) || !std::isfinite(ux) || p->wall_u[side][1] != 0.0 ||
+          p->wall_u[side][2] != 0.0 || !admissible(p->R * T, ux) || !admissible(p->R * T, 0.0)) {
+        why = "wall_T must be positive and wall_u tangential (x only) and admissible";
+        return LBM_EINVAL;
+      }
+    }
+    if (p->wall_density != 0 && p->wall_density != 1) { why = "wall_density must be 0 or 1"; return LBM_EINVAL; }
+  }
   if (!(p->tau > 0.5) || !std::isfinite(p->tau)) { why = "tau must be a finite value > 1/2"; return LBM_EINVAL; }
   if (p->diag_every < 0) { why = "diag_every must be >= 0"; return LBM_EINVAL; }
   if (p->model == LBM_MODEL_DDF) {
@@ -219,18 +245,14 @@ void make_plan(const lbm_params* p, Plan& P) {
   P.off_mlp = off; off = align_up(off + 256 + (size_t)kMlpParams * 4, 256);
   P.off_fld = off;
   if (P.ddf && P.D == 3) off = align_up(off + (size_t)7 * P.L.plane * 8, 256);
+  P.off_nb = off;
+  if (p->wall_y == 2) off = align_up(off + (size_t)36 * P.L.pitch * P.elem, 256);
   P.total = off;
 }
 
 // Layout of the stored state for the read-out kernels: -1 two buffers, else the parity of t.
 int view_of(const lbm_ctx* c) { return c->aa ? (int)(c->t & 1) : -1; }
 
-// Product-form factors must be positive: Psi_0 = 1 - theta - u^2 > 0 and
-// Psi_+- = (theta + u^2 +- u)/2 > 0 for every component.
-bool admissible(double theta, double u) {
-  const double z = theta + u * u;
-  return z < 1.0 && z > std::fabs(u);
-}
 
 }  // namespace
 
@@ -321,6 +343,15 @@ int lbm_create(const lbm_params* p, const double* rho0, const double* u0, const 
   c->dp.inv_R = 1.0 / p->R;
   c->dp.mu = (p->tau - 0.5) * (1.0 / 3.0);  // mu = (tau - 1/2) P0 at the reference P0 = 1/3
   c->dp.phi = p->phi;
+  if (p->wall_y == 2) {
+    c->dp.neq = 1;
+    c->dp.neq_literal = p->wall_density;
+    for (int side = 0; side < 2; ++side) {
+      c->dp.uw[side][0] = p->wall_u[side][0];
+      c->dp.uw[side][1] = p->wall_u[side][1];
+      c->dp.Tw[side] = p->wall_T[side];
+    }
+  }
   {
     // alpha = (D+2)/D - rho c_s^2/P - eta/mu with rho c_s^2/P = gamma = 1 + R/c_v (ideal gas);
     // exactly 0 for the Navier-Stokes bulk viscosity. qc = c_p - k/mu, k/mu = c_p / Pr.
@@ -368,6 +399,7 @@ int lbm_create(const lbm_params* p, const double* rho0, const double* u0, const 
   c->history = reinterpret_cast<double*>(c->ws + P.off_hist);
   c->readout = reinterpret_cast<double*>(c->ws + P.off_read);
   if (P.ddf && P.D == 3) c->fld = reinterpret_cast<double*>(c->ws + P.off_fld);
+  if (p->wall_y == 2) c->nb = c->ws + P.off_nb;
   c->mlp_cnt = reinterpret_cast<unsigned long long*>(c->ws + P.off_mlp);
   c->mlp_w = reinterpret_cast<float*>(c->ws + P.off_mlp + 256);
   c->mlp_tol = p->mlp_tol;
@@ -398,7 +430,7 @@ int lbm_create(const lbm_params* p, const double* rho0, const double* u0, const 
     }
     if (P.D == 2) {
       if (e == hipSuccess) e = launch_init_ddf(c->fmt, c->readout, c->readout + nodes, d_T0, c->B, c->L, c->dp, c->stream);
-      if (e == hipSuccess) e = launch_ddf(c->fmt, p->wall_y != 0, false, c->B, c->A, c->L, c->G, c->dp, c->s_enc, c->s_dec, nullptr, c->stream);
+      if (e == hipSuccess) e = launch_ddf(c->fmt, p->wall_y != 0, false, c->B, c->A, c->L, c->G, c->dp, c->s_enc, c->s_dec, nullptr, c->nb, c->stream);
     } else {
       if (e == hipSuccess) e = launch_init_ddf3(c->kind, c->readout, c->readout + nodes, d_T0, c->B, c->L, c->dp, c->stream);
       if (e == hipSuccess) e = launch_ddf3(c->kind, p->wall_y != 0, false, c->B, c->A, c->L, c->G, c->dp, c->fld, nullptr, c->stream);
@@ -433,7 +465,7 @@ int lbm_step(lbm_ctx* c, int64_t n) {
     } else if (c->ddf && c->D == 3)
       e = launch_ddf3(c->kind, c->p.wall_y != 0, true, c->A, c->B, c->L, c->G, c->dp, c->fld, part, c->stream);
     else if (c->ddf)
-      e = launch_ddf(c->fmt, c->p.wall_y != 0, true, c->A, c->B, c->L, c->G, c->dp, c->s_enc, c->s_dec, part, c->stream);
+      e = launch_ddf(c->fmt, c->p.wall_y != 0, true, c->A, c->B, c->L, c->G, c->dp, c->s_enc, c->s_dec, part, c->nb, c->stream);
     else if (c->codec >= 0)
       e = launch_bgk_d2q9_red(c->codec, c->A, c->B, c->L, c->G, c->omega, c->p.wall_y != 0, c->s_enc, c->s_dec, part, c->stream);
     else if (c->aa && c->D == 2)

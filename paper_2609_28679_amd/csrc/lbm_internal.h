@@ -68,6 +68,12 @@ struct DdfParams {
   bool full = false;
   // the kernels take the extended path (shifted state with sources and/or transport terms)
   bool ext() const { return src || full; }
+  // non-equilibrium extrapolation walls (D2Q9, rows 0 and ny-1 on the walls): wall velocity
+  // uw[side][axis] and temperature Tw[side] (side 0: y = 0, 1: y = ny - 1); neq_literal selects
+  // rho_B = rho_N instead of rho_N T_N / T_W
+  int neq = 0, neq_literal = 0;
+  double uw[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+  double Tw[2] = {1.0, 1.0};
   // storage shift: f^eq and g^eq at rest at the reference state rho = 1, T = 1 (computed by
   // launch_ddf_rest_state / launch_ddf3_rest_state on the device at context creation; the
   // first 9 entries for D2Q9, 27 for D3Q27)
@@ -108,9 +114,11 @@ hipError_t launch_decode_f(int kind, int D, int i, const void* A, const Layout& 
 Grid make_grid_ddf(const Layout& L, int halo, bool reduced);
 // out[0..8] = f^eq, out[9..17] = g^eq at rho = 1, u = 0, T = 1 (18 doubles, device memory).
 hipError_t launch_ddf_rest_state(const DdfParams& prm, double* out, hipStream_t s);
+// nb: boundary-row buffer of the non-equilibrium extrapolation walls (2 x 18 rows of `pitch`
+// storage elements; used when prm.neq, NULL otherwise).
 hipError_t launch_ddf(int fmt, bool walls, bool pull, const void* A, void* B, const Layout& L,
                       const Grid& G, const DdfParams& prm, float s_enc, float s_dec,
-                      double* partials, hipStream_t s);
+                      double* partials, void* nb, hipStream_t s);
 hipError_t launch_init_ddf(int kind, const double* rho, const double* u, const double* T,
                            void* A, const Layout& L, const DdfParams& prm, hipStream_t s);
 hipError_t launch_moments_ddf(int kind, const void* A, const Layout& L, const DdfParams& prm,

@@ -200,3 +200,35 @@ def test_transport_parameters_accepted_for_the_thermal_model(lib):
     for storage in (0, 3):
         rc, _ = _workspace(lib, model=1, storage=storage, prandtl=0.71, eta_over_mu=0.0)
         assert rc == 0
+
+
+def _neq_params(lib, **kw):
+    p = binding.LbmParams()
+    lib.lbm_default_params(ctypes.byref(p))
+    p.model, p.wall_y, p.ny = 1, 2, 16
+    p.wall_T[0], p.wall_T[1] = 1.0, 1.1
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+@pytest.mark.parametrize("kw", [dict(model=0), dict(storage=1), dict(lattice=1, nz=4),
+                                dict(ny=2), dict(wall_density=2), dict(heat_source=1e-5)])
+def test_neq_walls_rejected_where_unsupported(lib, kw):
+    p = _neq_params(lib, **kw)
+    n = ctypes.c_size_t(0)
+    assert lib.lbm_workspace_size(ctypes.byref(p), ctypes.byref(n)) == binding.LBM_EINVAL
+
+
+def test_neq_walls_validate_wall_state(lib):
+    n = ctypes.c_size_t(0)
+    p = _neq_params(lib)
+    assert lib.lbm_workspace_size(ctypes.byref(p), ctypes.byref(n)) == 0
+    p.wall_T[1] = 0.0
+    assert lib.lbm_workspace_size(ctypes.byref(p), ctypes.byref(n)) == binding.LBM_EINVAL
+    p = _neq_params(lib)
+    p.wall_u[1][1] = 0.01  # normal wall velocity
+    assert lib.lbm_workspace_size(ctypes.byref(p), ctypes.byref(n)) == binding.LBM_EINVAL
+    p = _neq_params(lib)
+    p.wall_u[1][0] = 0.9  # inadmissible product-form factors at the wall
+    assert lib.lbm_workspace_size(ctypes.byref(p), ctypes.byref(n)) == binding.LBM_EINVAL
