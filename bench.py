@@ -260,6 +260,12 @@ def main():
                 max(100, vs // 4), 10, 144,
                 {"walls": "y", "phi": "central",
                  "transport": "Pr 0.71 (heat flux q^c), eta/mu 1 (alpha theta div u)"})),
+            ("d2q9_ddf_fp32_4096_neq_walls", lambda n: variant(
+                n, lambda: ddf_lattice("fp32", neq_walls=dict(u=((-0.05, 0.0), (0.05, 0.0)),
+                                                              T=(0.8, 1.0))),
+                max(100, vs // 4), 10, 144,
+                {"walls": "y, non-equilibrium extrapolation (u_W = -+0.05, T_W = 0.8 / 1.0)",
+                 "phi": "central"})),
             ("d3q27_ddf_fp32_256", lambda n: variant(
                 n, lambda: binding.Lattice(*inputs.thermal_taylor_green_3d(256, 0.05),
                                            lattice="D3Q27", model="ddf", tau=0.6, phi=1),
