@@ -1,0 +1,140 @@
+"""Full-size checks in the launch configurations that bench.py times, for the workloads with a
+body force, heat source, transport control, non-equilibrium extrapolation walls and the D3Q27
+double distribution: one GPU step from the GPU's own stored state against the oracle's step,
+element by element on whole lattices, row slabs or node neighbourhoods that the oracle can
+compute (a node's step reads its neighbours up to two spacings away: the pull, then the
+derivative stencils of the moments).
+
+Bar: float32 storage, one step from identical inputs: within 2e-6 of the largest population
+of the compared set (a few float32 ulp of arithmetic done in float64).
+"""
+import numpy as np
+import pytest
+
+from gpu_util import announce, require_gpu
+from oracle import bgk, ddf
+from paper_2609_28679_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+R, CV, P0 = 1.0 / 3.0, 5.0 / 6.0, 1.0 / 3.0
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _lattice(*a, **k):
+    from paper_2609_28679_amd.binding import Lattice
+    return Lattice(*a, **k)
+
+
+def _close(got, want, tol=2e-6):
+    return np.abs(got - want).max() <= tol * np.abs(want).max()
+
+
+def _two_snapshots(lat, warm):
+    lat.step(warm)
+    post = lat.populations()
+    lat.step(1)
+    nxt = lat.populations()
+    lat.close()
+    return post, nxt
+
+
+def test_forced_d2q9_2048_one_buffer():
+    announce("D2Q9 2048^2 fp32 one buffer, uniform force (bench configuration): one step")
+    rho, u = inputs.random_phase_turbulence_2d(2048, seed=0)
+    F = np.array([1e-6, 0.0])
+    lat = _lattice(rho, u, tau=0.6, force=tuple(F))
+    (f_post, _), (f_next, _) = _two_snapshots(lat, 20)
+    want = bgk.collide(bgk.stream(f_post), bgk.omega_from_tau_lb(0.6), F)
+    assert _close(f_next, want)
+
+
+def test_forced_d3q27_256():
+    announce("D3Q27 256^3 fp32, uniform force (bench configuration): one step on 4 slabs")
+    rho, u = inputs.taylor_green_3d(256, 0.05)
+    F = np.array([1e-6, 0.0, 0.0])
+    lat = _lattice(rho, u, lattice="D3Q27", tau=0.55, force=tuple(F))
+    (f_post, _), (f_next, _) = _two_snapshots(lat, 5)
+    om = bgk.omega_from_tau_lb(0.55)
+    for z in (0, 1, 128, 255):
+        slab = f_post[:, [(z - 1) % 256, z, (z + 1) % 256]]
+        want = bgk.collide(bgk.stream(slab), om, F)[:, 1]
+        assert _close(f_next[:, z], want), z
+
+
+def _ddf_rows(f_post, g_post, f_next, g_next, gas, rows, F=None, Q=0.0):
+    """Row slabs of the D2Q9 double distribution with bounce-back walls at the lattice ends."""
+    n = f_post.shape[1]
+    for c in rows:
+        lo, hi = max(c - 2, 0), min(c + 3, n)
+        src_lo, src_hi = max(lo - 1, 0), min(hi + 1, n)
+        fs = bgk.stream(f_post[:, src_lo:src_hi], walls_y=True)
+        gs = bgk.stream(g_post[:, src_lo:src_hi], walls_y=True)
+        keep = slice(lo - src_lo, hi - src_lo)
+        ft, gt = ddf.collide(fs[:, keep], gs[:, keep], gas, True, True, "central", F=F, Q=Q)
+        k = c - lo
+        assert _close(f_next[:, c], ft[:, k]), c
+        assert _close(g_next[:, c], gt[:, k]), c
+
+
+@pytest.mark.parametrize("case", ["sources", "transport"])
+def test_ddf_4096_extended(case):
+    n = 4096
+    announce("DDF 4096^2 fp32 walls, %s (bench configuration): one step at sampled rows" % case)
+    rho, u, T = inputs.thermal_shear_layer(n, seed=0)
+    if case == "sources":
+        kw, F, Q = dict(force=(1e-7, 0.0), heat_source=1e-8), np.array([1e-7, 0.0]), 1e-8
+        gas = ddf.Gas(R, CV, 0.1 * P0)
+    else:
+        kw, F, Q = dict(prandtl=0.71, eta_over_mu=1.0), None, 0.0
+        gas = ddf.Gas(R, CV, 0.1 * P0, prandtl=0.71, eta_over_mu=1.0)
+    lat = _lattice(rho, u, T, model="ddf", tau=0.6, wall_y=True, phi=1, **kw)
+    (f_post, g_post), (f_next, g_next) = _two_snapshots(lat, 10)
+    _ddf_rows(f_post, g_post, f_next, g_next, gas, (0, 1, 2047, n - 2, n - 1), F, Q)
+
+
+def test_ddf_4096_neq_walls():
+    n = 4096
+    announce("DDF 4096^2 fp32 non-equilibrium extrapolation walls (bench configuration): one step")
+    rho, u, T = inputs.thermal_shear_layer(n, seed=0)
+    lat = _lattice(rho, u, T, model="ddf", tau=0.6, phi=1,
+                   neq_walls=dict(u=((-0.05, 0.0), (0.05, 0.0)), T=(0.8, 1.0)))
+    (f_post, g_post), (f_next, g_next) = _two_snapshots(lat, 10)
+    gas = ddf.Gas(R, CV, 0.1 * P0)
+    walls = ddf.NeqWalls((-0.05, 0.0), 0.8, (0.05, 0.0), 1.0)
+    # rows 0..4 and n-5..n-1 stacked: the boundary rows are rebuilt from rows 1 and n-2, and
+    # rows 0, 1, n-2, n-1 only reach rows inside their own block (the junction is never read)
+    block = np.r_[0:5, n - 5:n]
+    fs = np.concatenate([bgk.stream(f_post[:, 0:5]), bgk.stream(f_post[:, n - 5:n])], axis=1)
+    gs = np.concatenate([bgk.stream(g_post[:, 0:5]), bgk.stream(g_post[:, n - 5:n])], axis=1)
+    fs, gs = ddf.apply_neq_walls(fs, gs, gas, walls)
+    ft, gt = ddf.collide(fs, gs, gas, True, True, "central")
+    for k in (0, 1, 8, 9):
+        c = block[k]
+        assert _close(f_next[:, c], ft[:, k]), c
+        assert _close(g_next[:, c], gt[:, k]), c
+    # an interior row is an ordinary row
+    _ddf_rows(f_post, g_post, f_next, g_next, gas, (2047,))
+
+
+def test_ddf3_256():
+    n = 256
+    announce("D3Q27 DDF 256^3 fp32 periodic (bench configuration): one step at sampled nodes")
+    rho, u, T = inputs.thermal_taylor_green_3d(n, 0.05)
+    lat = _lattice(rho, u, T, lattice="D3Q27", model="ddf", tau=0.6, phi=1)
+    (f_post, g_post), (f_next, g_next) = _two_snapshots(lat, 5)
+    gas = ddf.Gas(R, CV, 0.1 * P0)
+    rng = np.random.default_rng(3)
+    nodes = [(0, 0, 0), (255, 128, 1), (17, 255, 254)] + [tuple(v) for v in rng.integers(0, n, (3, 3))]
+    for z, y, x in nodes:
+        # the 5^3 neighbourhood, streamed and collided as a periodic box: its centre is exact
+        idx = np.ix_(*[[(c + d) % n for d in range(-2, 3)] for c in (z, y, x)])
+        fb = np.stack([f_post[i][idx] for i in range(27)])
+        gb = np.stack([g_post[i][idx] for i in range(27)])
+        ft, gt = ddf.collide(bgk.stream(fb), bgk.stream(gb), gas, False, True, "central")
+        assert _close(f_next[:, z, y, x], ft[:, 2, 2, 2]), (z, y, x)
+        assert _close(g_next[:, z, y, x], gt[:, 2, 2, 2]), (z, y, x)
