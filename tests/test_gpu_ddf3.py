@@ -114,3 +114,22 @@ def test_conservation_with_diagnostics():
     assert np.all(np.abs(h[:, 1] - m0[0]) <= 1e-12 * m0[0])              # mass
     assert np.all(np.abs(h[:, 2:5] - m0[1:4]) <= 1e-12 * m0[0])           # momentum
     assert np.all(np.abs(h[:, 5] - m0[4]) <= 1e-12 * m0[4])               # total energy
+
+
+@pytest.mark.parametrize("phi", [1, 0])
+@pytest.mark.parametrize("walls", [True, False])
+def test_fp32_ragged_lattice(walls, phi):
+    # float32 storage on a 37 x 33 x 20 lattice (ragged workgroups in x, rows over several
+    # workgroups), 4 steps: stored populations and velocity against the oracle
+    shape = (20, 33, 37)
+    announce("D3Q27 DDF fp32 %s walls=%s phi=%d 4 steps" % (shape, walls, phi))
+    rho, u, T = _fields(shape, seed=43 + phi)
+    tau = 0.7
+    _, ug, tg, _, fg, gg = _run(rho, u, T, 4, "fp32", tau=tau, wall_y=walls, phi=phi)
+    gas = ddf.Gas(R, CV, (tau - 0.5) * P0)
+    f, g = ddf.run(*ddf.init_equilibrium(rho, u, T, gas), gas, 4, walls_y=walls, phi_on=phi > 0)
+    ft, gt = ddf.collide(f, g, gas, walls, phi > 0, "central")
+    assert np.abs(fg - ft).max() <= 2e-6 * np.abs(ft).max()
+    assert np.abs(gg - gt).max() <= 2e-6 * np.abs(gt).max()
+    _, uo, to = ddf.temperature(f, g, gas)
+    assert rel_l2(ug, uo) <= 1e-5
