@@ -47,16 +47,62 @@ from .lattice import VARSIGMA2, velocities
 
 
 class Gas:
-    """Ideal-gas parameters: gas constant R, heat capacity c_v, dynamic viscosity mu, Prandtl
-    number Pr = mu c_p / k (thermal conductivity k) and bulk viscosity ratio eta/mu (None: the
-    Navier-Stokes value 2/D - R/c_v of Sec. II E, for which alpha = 0)."""
+    """Fluid parameters: gas constant R, heat capacity c_v, dynamic viscosity mu, Prandtl
+    number Pr = mu c_p0 / k (thermal conductivity k, c_p0 = c_v + R) and bulk viscosity ratio
+    eta/mu (None: the Navier-Stokes value 2/D - R/c_v named in Sec. II E, for which alpha = 0 in
+    the ideal gas). a, b: van der Waals constants (Sec. III C, Eq. vdw_eos),
+    P = rho R T / (1 - b rho) - a rho^2 with e = c_v T - a rho (Eq. lbm_temp); a = b = 0 is
+    the ideal gas of Sec. III A."""
 
-    def __init__(self, R, cv, mu, prandtl=1.0, eta_over_mu=None):
+    def __init__(self, R, cv, mu, prandtl=1.0, eta_over_mu=None, a=0.0, b=0.0):
         self.R = float(R)
         self.cv = float(cv)
         self.mu = float(mu)
         self.prandtl = float(prandtl)
         self.eta_over_mu = None if eta_over_mu is None else float(eta_over_mu)
+        self.a = float(a)
+        self.b = float(b)
+
+    @property
+    def ideal(self):
+        return self.a == 0.0 and self.b == 0.0
+
+    # ---- equation of state (van der Waals; ideal gas at a = b = 0) ----------------------
+    def pressure(self, rho, T):
+        if self.ideal:
+            return rho * self.R * T
+        return rho * self.R * T / (1.0 - self.b * rho) - self.a * rho * rho
+
+    def temperature_of(self, rho, e):
+        """T from the specific internal energy (Eq. lbm_temp: T = (e + a rho) / c_v)."""
+        if self.ideal:
+            return e / self.cv
+        return (e + self.a * rho) / self.cv
+
+    def internal_energy(self, rho, T):
+        if self.ideal:
+            return self.cv * T
+        return self.cv * T - self.a * rho
+
+    def gamma_minus_1(self, rho):
+        """(dP/dT)_rho / (rho c_v) (Sec. II A, Eq. corr_heat_source); R / c_v for the ideal gas."""
+        if self.ideal:
+            return self.gamma - 1.0
+        return self.R / ((1.0 - self.b * rho) * self.cv)
+
+    def sound_speed2(self, rho, T):
+        """c_s^2 = (dP/drho)_T + T / (rho^2 c_v) (dP/dT)_rho^2 (Sec. II A)."""
+        dPdrho = self.R * T / (1.0 - self.b * rho) ** 2 - 2.0 * self.a * rho
+        dPdT = rho * self.R / (1.0 - self.b * rho)
+        return dPdrho + T / (rho * rho * self.cv) * dPdT * dPdT
+
+    def alpha_field(self, D, rho, T, P):
+        """alpha = (D+2)/D - rho c_s^2 / P - eta/mu (Eq. corr_bulk) per node; for the ideal gas
+        the constant of alpha()."""
+        if self.ideal:
+            return self.alpha(D)
+        eta = (2.0 / D - self.R / self.cv) if self.eta_over_mu is None else self.eta_over_mu
+        return (D + 2.0) / D - rho * self.sound_speed2(rho, T) / P - eta
 
     @property
     def gamma(self):
@@ -92,11 +138,12 @@ def _field(F, D, shape):
 
 
 def closure(rho, u, rhoE, gas):
-    """T, P, theta from the conserved fields (ideal gas, Sec. III A)."""
+    """T, P, theta from the conserved fields: T from the caloric relation (Sec. III A ideal gas,
+    Eq. lbm_temp for van der Waals), P from the equation of state, theta = P / rho."""
     E = rhoE / rho
     usq = (u * u).sum(axis=0)
-    T = (E - 0.5 * usq) / gas.cv
-    P = rho * gas.R * T
+    T = gas.temperature_of(rho, E - 0.5 * usq)
+    P = gas.pressure(rho, T)
     theta = P / rho
     return T, P, theta
 
@@ -159,24 +206,33 @@ def equilibria(rho, u, rhoE, gas, walls_y, phi_on=True, stencil="central", F=Non
     already carry the half-step source terms)."""
     D = u.shape[0]
     T, P, theta = closure(rho, u, rhoE, gas)
-    e = gas.cv * T
+    e = gas.internal_energy(rho, T)
     Fv = _field(F, D, rho.shape)
     ustar = u + Fv / rho
-    thetastar = theta + (gas.gamma - 1.0) * Q / rho
-    alpha = gas.alpha(D)
-    if alpha != 0.0:  # theta* = theta + dt alpha theta div u + ... (Eq. sh_temp_1)
+    thetastar = theta + gas.gamma_minus_1(rho) * Q / rho
+    alpha = gas.alpha_field(D, rho, T, P)
+    if np.any(alpha != 0.0):  # theta* = theta + dt alpha theta div u + ... (Eq. sh_temp_1)
         thetastar = thetastar + alpha * theta * divergence(u, walls_y)
     Tstar = T + Q / (rho * gas.cv) - (Fv * Fv).sum(axis=0) / (2.0 * rho * rho * gas.cv)
     fe = feq(rho, u, theta)
     Phi = galilean_correction(rho, u, theta, walls_y, stencil) if phi_on else np.zeros_like(u)
     fs = fstar(rho, ustar, thetastar, Phi)
     ge = geq(rho, u, theta, e)
-    gs = geq(rho, ustar, thetastar, gas.cv * Tstar)
-    kq = gas.qc_coefficient()
-    if kq != 0.0:  # g* += c_i . q^c / 2 on the velocities with |c_i|^2 = 1 (Eq. LBMgstar)
-        c = velocities(D)
-        qc = [P * kq * central_derivative(T, rho.ndim - 1 - a, walls_y and a == 1)
+    gs = geq(rho, ustar, thetastar, gas.internal_energy(rho, Tstar))
+    c = velocities(D)
+    qc = None
+    if gas.ideal:
+        kq = gas.qc_coefficient()
+        if kq != 0.0:
+            qc = [P * kq * central_derivative(T, rho.ndim - 1 - a, walls_y and a == 1)
+                  for a in range(D)]
+    else:  # q^c = dt P (grad h - (k/mu) grad T), h = e + P/rho (Eqs. qc_1, enthalpy)
+        h = e + P / rho
+        kmu = gas.cp / gas.prandtl
+        qc = [P * (central_derivative(h, rho.ndim - 1 - a, walls_y and a == 1)
+                   - kmu * central_derivative(T, rho.ndim - 1 - a, walls_y and a == 1))
               for a in range(D)]
+    if qc is not None:  # g* += c_i . q^c / 2 on the velocities with |c_i|^2 = 1 (Eq. LBMgstar)
         for i, ci in enumerate(c):
             if (ci * ci).sum() == 1:
                 gs[i] = gs[i] + 0.5 * sum(ci[a] * qc[a] for a in range(D))
@@ -197,8 +253,8 @@ def moments(f, g, F=None, Q=0.0):
 
 def init_equilibrium(rho, u, T, gas):
     """Fig. 1: f <- f^eq, g <- g^eq of the initial fields."""
-    theta = gas.R * T
-    return feq(rho, u, theta), geq(rho, u, theta, gas.cv * T)
+    theta = gas.pressure(rho, T) / rho
+    return feq(rho, u, theta), geq(rho, u, theta, gas.internal_energy(rho, T))
 
 
 def collide(f, g, gas, walls_y, phi_on=True, stencil="central", F=None, Q=0.0):
@@ -229,6 +285,8 @@ def apply_neq_walls(f, g, gas, walls):
     """Boundary rows of the pre-collision populations:
     f_B = f^eq(rho_B, u_W, T_W) + (f_N - f^eq(rho_N, u_N, T_N)), and the same for g (App. B),
     with rho_B from NeqWalls.density. No sources (the context rejects them with these walls)."""
+    if not gas.ideal:
+        raise ValueError("non-equilibrium extrapolation walls are written for the ideal gas")
     rho, u, rhoE = moments(f, g)
     T, _, theta = closure(rho, u, rhoE, gas)
     fe = feq(rho, u, theta)
