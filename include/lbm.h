@@ -95,6 +95,11 @@ typedef struct {
                           Navier-Stokes value 2/D - R/c_v; sets alpha = (D+2)/D - gamma - eta/mu
                           in theta* = theta + alpha theta div u (Sec. II A). Values >= 0 need
                           FP32/FP64 storage. */
+  int32_t eos;         /* DDF equation of state: 0 = ideal gas (Sec. III A), 1 = van der Waals
+                          P = rho R T / (1 - b rho) - a rho^2 with e = c_v T - a rho (Sec. III C);
+                          van der Waals: D2Q9, FP32/FP64 storage, wall_y 0 or 1. Its alpha and
+                          q^c are per node (k/mu = (c_v + R) / prandtl). */
+  double vdw_a, vdw_b; /* van der Waals a >= 0, b >= 0 (lattice units); 1 - b rho > 0 */
   double wall_u[2][3]; /* wall_y = 2: wall velocity [bottom (y = 0), top (y = ny-1)][x, y, z];
                           the normal component must be 0 */
   double wall_T[2];    /* wall_y = 2: wall temperatures [bottom, top], > 0 */
@@ -115,7 +120,7 @@ typedef struct {
 } lbm_params;
 
 /* Fill p with defaults: D2Q9 BGK FP32 plain, 64 x 64 x 1, periodic, tau 0.8, R = 1/3,
-   c_v = 5/6, no force or heat source, Pr 1, Navier-Stokes bulk viscosity, phi 1, S = 16, no diagnostics, automatic streaming layout, tol 0.05, null
+   c_v = 5/6, ideal gas, no force or heat source, Pr 1, Navier-Stokes bulk viscosity, phi 1, S = 16, no diagnostics, automatic streaming layout, tol 0.05, null
    stream, no workspace. */
 void lbm_default_params(lbm_params* p);
 

@@ -34,7 +34,8 @@ class LbmParams(ctypes.Structure):
         ("nz", ctypes.c_int32), ("wall_y", ctypes.c_int32), ("tau", ctypes.c_double),
         ("R", ctypes.c_double), ("cv", ctypes.c_double), ("force", ctypes.c_double * 3),
         ("heat_source", ctypes.c_double), ("prandtl", ctypes.c_double),
-        ("eta_over_mu", ctypes.c_double), ("wall_u", (ctypes.c_double * 3) * 2),
+        ("eta_over_mu", ctypes.c_double), ("eos", ctypes.c_int32), ("vdw_a", ctypes.c_double),
+        ("vdw_b", ctypes.c_double), ("wall_u", (ctypes.c_double * 3) * 2),
         ("wall_T", ctypes.c_double * 2), ("wall_density", ctypes.c_int32),
         ("phi", ctypes.c_int32),
         ("fp16_scale_log2", ctypes.c_int32), ("diag_every", ctypes.c_int32),
@@ -121,8 +122,8 @@ class Lattice:
     force: uniform body force (D components) or None; heat_source: uniform heat source Q,
     prandtl: Prandtl number, eta_over_mu: bulk viscosity ratio (< 0: Navier-Stokes value),
     neq_walls: non-equilibrium extrapolation walls on the first and last rows,
-    dict(u=((ux, uy), (ux, uy)), T=(T_bottom, T_top), density="pressure"|"literal")
-    (double-distribution model).
+    dict(u=((ux, uy), (ux, uy)), T=(T_bottom, T_top), density="pressure"|"literal"),
+    vdw: (a, b) for a van der Waals fluid (double-distribution model).
     The context workspace is a torch uint8 tensor on the current device; launches go on
     torch's current stream.
     """
@@ -131,7 +132,7 @@ class Lattice:
                  collision="plain", wall_y=False, tau=0.8, R=1.0 / 3.0, cv=5.0 / 6.0, phi=1,
                  fp16_scale_log2=16, diag_every=0, mlp_tol=0.05, streaming="auto",
                  force=None, heat_source=0.0, prandtl=1.0, eta_over_mu=-1.0,
-                 neq_walls=None, torch_workspace=True):
+                 neq_walls=None, vdw=None, torch_workspace=True):
         torch = _torch()
         lib = load()
         rho0 = np.ascontiguousarray(rho0, dtype=np.float64)
@@ -165,6 +166,9 @@ class Lattice:
         p.heat_source = float(heat_source)
         p.prandtl = float(prandtl)
         p.eta_over_mu = float(eta_over_mu)
+        if vdw is not None:  # van der Waals fluid: (a, b)
+            p.eos = 1
+            p.vdw_a, p.vdw_b = float(vdw[0]), float(vdw[1])
         if neq_walls is not None:
             # dict(u=((ux, uy), (ux, uy)), T=(T_bottom, T_top), density="pressure"|"literal")
             p.wall_y = 2

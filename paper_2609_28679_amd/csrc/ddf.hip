@@ -225,9 +225,9 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
   // extended path with transport control: T and u_x of the gathered row (x derivatives) and T,
   // u_y of the last P rows per column (y derivatives)
   constexpr int NE = EXT ? kBlock : 1;
-  __shared__ double s_tx[2][NE], s_ux[2][NE];
-  __shared__ double s_ty[P][NE], s_uy[P][NE];
-  constexpr int NM = EXT ? 8 : 6;
+  __shared__ double s_tx[2][NE], s_ux[2][NE], s_hx[2][NE];
+  __shared__ double s_ty[P][NE], s_uy[P][NE], s_hy[P][NE];
+  constexpr int NM = EXT ? 9 : 6;
 
   const int nbx = gridDim.x;
   // per-XCD contiguous tiles for float32/float64 storage; the staged reduced-storage variant
@@ -250,7 +250,7 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
 
 
   S ring_f[H1][9], ring_g[H1][9];
-  double ring_m[H1][NM];  // rho, u_x, u_y, theta, e, Phi_xx [, dT/dx, du_x/dx]
+  double ring_m[H1][NM];  // rho, u_x, u_y, theta, e, Phi_xx [, dT/dx, du_x/dx, dh/dx]
   double acc[kDiagValues] = {0.0, 0.0, 0.0, 0.0, 0.0};
 
   // Staged rows are software-pipelined: the raw values of row r + 2 are fetched into registers
@@ -320,11 +320,15 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
         phx = m.rho * m.ux * (m.ux * m.ux + 3.0 * (m.theta - 1.0 / 3.0));
         phy = m.rho * m.uy * (m.uy * m.uy + 3.0 * (m.theta - 1.0 / 3.0));
         if (EXT && prm.full) {
-          const double T = m.theta * prm.inv_R;
+          const double T = node_temperature(prm, m.rho, m.e, m.theta);
           s_tx[w & 1][tid] = T;
           s_ux[w & 1][tid] = m.ux;
           s_ty[((r % P) + P) % P][tid] = T;
           s_uy[((r % P) + P) % P][tid] = m.uy;
+          if (prm.eos) {  // specific enthalpy h = e + P / rho
+            s_hx[w & 1][tid] = m.e + m.theta;
+            s_hy[((r % P) + P) % P][tid] = m.e + m.theta;
+          }
         }
       }
       s_phix[w & 1][tid] = phx;
@@ -334,6 +338,7 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
       if (EXT && prm.full && row_real && own) {
         ring_m[j][6] = 0.5 * (s_tx[w & 1][tid + 1] - s_tx[w & 1][tid - 1]);
         ring_m[j][7] = 0.5 * (s_ux[w & 1][tid + 1] - s_ux[w & 1][tid - 1]);
+        if (prm.eos) ring_m[j][8] = 0.5 * (s_hx[w & 1][tid + 1] - s_hx[w & 1][tid - 1]);
       }
       // ---- x derivative of phi_x on the gathered row -----------------------------------------
       if (row_real && own && prm.phi) {
@@ -375,7 +380,7 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
           phyy *= inv_rho;
         }
         // y derivatives of T and u_y (transport control), central with zero-order wall ghosts
-        double dTdy = 0.0, duydy = 0.0;
+        double dTdy = 0.0, duydy = 0.0, dhdy = 0.0;
         if (EXT && prm.full) {
           int rm1 = c - 1, rp1 = c + 1;
           if (WALLS) {
@@ -385,9 +390,10 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
           const int sm = ((rm1 % P) + P) % P, sp = ((rp1 % P) + P) % P;
           dTdy = 0.5 * (s_ty[sp][tid] - s_ty[sm][tid]);
           duydy = 0.5 * (s_uy[sp][tid] - s_uy[sm][tid]);
+          if (prm.eos) dhdy = 0.5 * (s_hy[sp][tid] - s_hy[sm][tid]);
         }
         const int64_t off = (int64_t)cc * pitch + x;
-        collide_ddf<EXT>(ring_f[sc], ring_g[sc], ring_m[sc], phxx, phyy, dTdy, duydy, prm,
+        collide_ddf<EXT>(ring_f[sc], ring_g[sc], ring_m[sc], phxx, phyy, dTdy, duydy, dhdy, prm,
                     [&](int i, double htf, double hfe, double htg, double hge) {
                       io.store(off, i, htf, hfe, htg, hge);
                     });
@@ -415,9 +421,13 @@ __global__ void k_init_ddf(const double* __restrict__ rho, const double* __restr
   const int64_t nodes = (int64_t)nx * ny;
   if (n >= nodes) return;
   const int64_t off = (n / nx) * pitch + (n % nx);
-  const double theta = prm.R * T[n];
+  double theta = prm.R * T[n], e = prm.cv * T[n];
+  if (prm.eos) {  // van der Waals: theta = P / rho, e = c_v T - a rho
+    theta = prm.R * T[n] / (1.0 - prm.vb * rho[n]) - prm.va * rho[n];
+    e -= prm.va * rho[n];
+  }
   double fe[9], ge[9];
-  equilibria(rho[n], u[n], u[nodes + n], theta, prm.cv * T[n], fe, ge);
+  equilibria(rho[n], u[n], u[nodes + n], theta, e, fe, ge);
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     A[i * plane + off] = (S)(fe[i] - prm.wf[i]);
@@ -448,7 +458,7 @@ __global__ void k_moments_ddf(const S* __restrict__ A, int nx, int ny, int64_t p
   rho[n] = m.rho;
   u[n] = m.ux;
   u[nodes + n] = m.uy;
-  T[n] = m.theta / prm.R;
+  T[n] = prm.eos ? (m.e + prm.va * m.rho) / prm.cv : m.theta / prm.R;
   edens[n] = m.rho * (m.e + 0.5 * (m.ux * m.ux + m.uy * m.uy));
 }
 

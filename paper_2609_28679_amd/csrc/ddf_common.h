@@ -71,8 +71,19 @@ __device__ __forceinline__ void moments_closure(const double (&f)[9], const doub
   m.ux = jx * inv;
   m.uy = jy * inv;
   if (SRC) rE += 0.5 * ((m.ux * sFx + m.uy * sFy) + sQ);
-  m.e = rE * inv - 0.5 * (m.ux * m.ux + m.uy * m.uy);  // c_v T
-  m.theta = p.r_cv * m.e;
+  m.e = rE * inv - 0.5 * (m.ux * m.ux + m.uy * m.uy);  // specific internal energy
+  if (p.eos) {  // van der Waals: T = (e + a rho) / c_v (Eq. lbm_temp), theta = P / rho
+    const double T = (m.e + p.va * rho) / p.cv;
+    m.theta = p.R * T / (1.0 - p.vb * rho) - p.va * rho;
+  } else {
+    m.theta = p.r_cv * m.e;  // ideal gas: theta = R T = (R / c_v) e
+  }
+}
+
+// Temperature of a node from its moments (ideal gas: theta / R; van der Waals: Eq. lbm_temp).
+__device__ __forceinline__ double node_temperature(const DdfParams& p, double rho, double e,
+                                                   double theta) {
+  return p.eos ? (e + p.va * rho) / p.cv : theta * p.inv_R;
 }
 
 // Pull of the nine populations of one distribution at node (x, row): f_i = A_i(x - c_i).
@@ -113,7 +124,8 @@ __device__ __forceinline__ double upwind_or_central(double pm2, double pm1, doub
 }
 
 // Collision of one node from its pre-collision populations held shifted by the rest state
-// (hf = f - w, hg = g - v) and its moments m = {rho, u_x, u_y, theta, e, -, dT/dx, du_x/dx};
+// (hf = f - w, hg = g - v) and its moments m = {rho, u_x, u_y, theta, e, -, dT/dx, du_x/dx,
+// dh/dx} (the derivatives on the extended path only);
 // Phi_xx, Phi_yy include dt = 1. For every i the sink receives the post-collision values and
 // the equilibria, all shifted: sink(i, f~ - w, f^eq - w, g~ - v, g^eq - v).
 // Without the extended path (EXT = false) f* = rho prod Psi(u, theta + u^2 + Phi) and
@@ -121,12 +133,14 @@ __device__ __forceinline__ double upwind_or_central(double pm2, double pm1, doub
 // theta* = theta + alpha theta div u + (gamma - 1) Q/rho with gamma - 1 = R/c_v (ideal gas),
 // c_v T* = e + Q/rho - F.F/(2 rho^2), and g* gains c_i.q^c/2 on the four velocities with
 // |c_i| = 1, q^c = P (c_p - k/mu) grad T (the ideal-gas form of P (grad h - (k/mu) grad T));
-// m[6], m[7], dTdy, duydy are used only when p.full.
+// m[6], m[7], dTdy, duydy are used only when p.full; for the van der Waals fluid (p.eos)
+// gamma - 1 and alpha are per node and q^c = P (grad h - (k/mu) grad T) with h = e + P/rho
+// (m[8], dhdy).
 template <bool EXT = false, typename R, typename Sink>
 __device__ __forceinline__ void collide_ddf(const R (&hf)[9], const R (&hg)[9],
                                             const double* m, double phxx, double phyy,
-                                            double dTdy, double duydy, const DdfParams& p,
-                                            Sink&& sink) {
+                                            double dTdy, double duydy, double dhdy,
+                                            const DdfParams& p, Sink&& sink) {
   const double rho = m[0], theta = m[3], e = m[4];
   const double P = rho * theta;
   Axis X, Y;
@@ -137,11 +151,23 @@ __device__ __forceinline__ void collide_ddf(const R (&hf)[9], const R (&hg)[9],
   double es = e, qx = 0.0, qy = 0.0;
   if (EXT) {
     const double inv = 1.0 / rho;
-    double thetas = theta + p.r_cv * p.Q * inv;
-    if (p.full) {
-      thetas += p.alpha * theta * (m[7] + duydy);
-      qx = P * p.qc * m[6];
-      qy = P * p.qc * dTdy;
+    double thetas;
+    if (p.eos) {  // van der Waals: gamma - 1 = R / ((1 - b rho) c_v), alpha and q^c per node
+      const double omb = 1.0 - p.vb * rho;
+      const double T = (e + p.va * rho) / p.cv;
+      const double cs2 = p.R * T / (omb * omb) - 2.0 * p.va * rho +
+                         T * p.R * p.R / (p.cv * omb * omb);
+      const double alpha = 2.0 - rho * cs2 / P - p.eta;  // (D+2)/D - rho c_s^2 / P - eta/mu
+      thetas = theta + p.R / (omb * p.cv) * p.Q * inv + alpha * theta * (m[7] + duydy);
+      qx = P * (m[8] - p.kmu * m[6]);
+      qy = P * (dhdy - p.kmu * dTdy);
+    } else {
+      thetas = theta + p.r_cv * p.Q * inv;
+      if (p.full) {
+        thetas += p.alpha * theta * (m[7] + duydy);
+        qx = P * p.qc * m[6];
+        qy = P * p.qc * dTdy;
+      }
     }
     axis_eq(m[1] + p.Fx * inv, thetas, XS);
     axis_eq(m[2] + p.Fy * inv, thetas, YS);

@@ -175,6 +175,18 @@ int validate(const lbm_params* p, std::string& why) {
     if (!(p->R > 0.0) || !(p->cv > 0.0) || !std::isfinite(p->R) || !std::isfinite(p->cv)) { why = "R and cv must be positive"; return LBM_EINVAL; }
     if (p->phi < 0 || p->phi > 2) { why = "phi must be 0 (off), 1 (central) or 2 (upwind)"; return LBM_EINVAL; }
   }
+  if (p->eos != 0 && p->eos != 1) { why = "eos must be 0 (ideal gas) or 1 (van der Waals)"; return LBM_EINVAL; }
+  if (p->eos == 1) {
+    if (p->model != LBM_MODEL_DDF || p->lattice != LBM_D2Q9 ||
+        (p->storage != LBM_STORE_FP32 && p->storage != LBM_STORE_FP64) || p->wall_y == 2) {
+      why = "the van der Waals eos needs the D2Q9 double-distribution model, FP32 or FP64 storage and wall_y 0 or 1";
+      return LBM_EINVAL;
+    }
+    if (!(p->vdw_a >= 0.0) || !(p->vdw_b >= 0.0) || !std::isfinite(p->vdw_a) || !std::isfinite(p->vdw_b)) {
+      why = "vdw_a and vdw_b must be finite and >= 0";
+      return LBM_EINVAL;
+    }
+  }
   if (!(p->prandtl > 0.0) || !std::isfinite(p->prandtl)) { why = "prandtl must be a finite value > 0"; return LBM_EINVAL; }
   if (!std::isfinite(p->eta_over_mu)) { why = "eta_over_mu must be finite"; return LBM_EINVAL; }
   if ((p->prandtl != 1.0 || p->eta_over_mu >= 0.0) &&
@@ -316,6 +328,12 @@ int lbm_create(const lbm_params* p, const double* rho0, const double* u0, const 
       if (!(T0[n] > 0.0) || !std::isfinite(T0[n]))
         return fail(nullptr, LBM_EINVAL, "initial temperature must be finite and positive at node " + std::to_string(n));
       theta = p->R * T0[n];
+      if (p->eos == 1) {  // van der Waals: theta = P / rho, with 1 - b rho > 0 and P > 0
+        const double omb = 1.0 - p->vdw_b * rho0[n];
+        theta = p->R * T0[n] / omb - p->vdw_a * rho0[n];
+        if (!(omb > 0.0) || !(theta > 0.0))
+          return fail(nullptr, LBM_EINVAL, "initial state outside the van der Waals range (1 - b rho > 0, P > 0) at node " + std::to_string(n));
+      }
     }
     for (int a = 0; a < P.D; ++a) {
       const double ua = u0[a * nodes + n];
@@ -359,6 +377,14 @@ int lbm_create(const lbm_params* p, const double* rho0, const double* u0, const 
     c->dp.alpha = p->eta_over_mu >= 0.0 ? (D + 2.0) / D - gamma - p->eta_over_mu : 0.0;
     c->dp.qc = p->prandtl != 1.0 ? cp - cp / p->prandtl : 0.0;
     c->dp.full = c->dp.alpha != 0.0 || c->dp.qc != 0.0;
+    if (p->eos == 1) {  // van der Waals: alpha and q^c per node, always the extended path
+      c->dp.eos = 1;
+      c->dp.va = p->vdw_a;
+      c->dp.vb = p->vdw_b;
+      c->dp.eta = p->eta_over_mu >= 0.0 ? p->eta_over_mu : 2.0 / D - p->R / p->cv;
+      c->dp.kmu = cp / p->prandtl;
+      c->dp.full = true;
+    }
   }
   c->L = P.L;
   c->G = P.G;

@@ -66,6 +66,12 @@ struct DdfParams {
   // qc = c_p - k/mu in q^c = P qc grad T (Prandtl number); full = either non-zero
   double alpha = 0.0, qc = 0.0;
   bool full = false;
+  // van der Waals fluid (eos = 1; D2Q9): P = rho R T / (1 - vb rho) - va rho^2, e = c_v T - va rho.
+  // Its alpha is computed per node with the bulk viscosity ratio eta, and its heat flux
+  // q^c = P (grad h - kmu grad T) uses kmu = k / mu = (c_v + R) / Pr; it always takes the
+  // extended path (full).
+  int eos = 0;
+  double va = 0.0, vb = 0.0, eta = 0.0, kmu = 0.0;
   // the kernels take the extended path (shifted state with sources and/or transport terms)
   bool ext() const { return src || full; }
   // non-equilibrium extrapolation walls (D2Q9, rows 0 and ny-1 on the walls): wall velocity

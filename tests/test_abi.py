@@ -232,3 +232,18 @@ def test_neq_walls_validate_wall_state(lib):
     p = _neq_params(lib)
     p.wall_u[1][0] = 0.9  # inadmissible product-form factors at the wall
     assert lib.lbm_workspace_size(ctypes.byref(p), ctypes.byref(n)) == binding.LBM_EINVAL
+
+
+@pytest.mark.parametrize("kw", [dict(eos=2), dict(eos=1), dict(eos=1, model=1, lattice=1, nz=4),
+                                dict(eos=1, model=1, storage=1),
+                                dict(eos=1, model=1, vdw_a=-1.0),
+                                dict(eos=1, model=1, vdw_b=float("nan"))])
+def test_van_der_waals_rejected_where_unsupported(lib, kw):
+    rc, _ = _workspace(lib, **kw)
+    assert rc == binding.LBM_EINVAL
+
+
+def test_van_der_waals_accepted_for_the_d2q9_thermal_model(lib):
+    for storage in (0, 3):
+        rc, _ = _workspace(lib, eos=1, model=1, storage=storage, vdw_a=0.27, vdw_b=0.2)
+        assert rc == 0
