@@ -210,7 +210,9 @@ struct IoRed {
   }
 };
 
-template <class IO, int HALO, bool WALLS, bool PULL, bool DIAG, bool EXT>
+// EXT: 0 = paper's collision without sources, 1 = extended path (sources and/or transport
+// control, ideal gas), 2 = extended path for the van der Waals fluid.
+template <class IO, int HALO, bool WALLS, bool PULL, bool DIAG, int EXT>
 __global__ void __launch_bounds__(kBlock)
 k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
            double* __restrict__ partials) {
@@ -224,10 +226,13 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
   __shared__ float s_stage[IO::kStageFloats];
   // extended path with transport control: T and u_x of the gathered row (x derivatives) and T,
   // u_y of the last P rows per column (y derivatives)
-  constexpr int NE = EXT ? kBlock : 1;
-  __shared__ double s_tx[2][NE], s_ux[2][NE], s_hx[2][NE];
-  __shared__ double s_ty[P][NE], s_uy[P][NE], s_hy[P][NE];
-  constexpr int NM = EXT ? 9 : 6;
+  constexpr bool X = EXT > 0;
+  constexpr bool VDW = EXT == 2;
+  constexpr int NE = X ? kBlock : 1;
+  constexpr int NH = VDW ? kBlock : 1;
+  __shared__ double s_tx[2][NE], s_ux[2][NE], s_hx[2][NH];
+  __shared__ double s_ty[P][NE], s_uy[P][NE], s_hy[P][NH];
+  constexpr int NM = X ? (VDW ? 9 : 8) : 6;
 
   const int nbx = gridDim.x;
   // per-XCD contiguous tiles for float32/float64 storage; the staged reduced-storage variant
@@ -311,7 +316,7 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
           g[i] = (double)ring_g[j][i] + prm.wg[i];
         }
         Moments m;
-        moments_closure<EXT>(f, g, prm, m, prm.Fx, prm.Fy, prm.Q);
+        moments_closure<X, VDW>(f, g, prm, m, prm.Fx, prm.Fy, prm.Q);
         ring_m[j][0] = m.rho;
         ring_m[j][1] = m.ux;
         ring_m[j][2] = m.uy;
@@ -319,13 +324,13 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
         ring_m[j][4] = m.e;
         phx = m.rho * m.ux * (m.ux * m.ux + 3.0 * (m.theta - 1.0 / 3.0));
         phy = m.rho * m.uy * (m.uy * m.uy + 3.0 * (m.theta - 1.0 / 3.0));
-        if (EXT && prm.full) {
-          const double T = node_temperature(prm, m.rho, m.e, m.theta);
+        if (X && prm.full) {
+          const double T = node_temperature<VDW>(prm, m.rho, m.e, m.theta);
           s_tx[w & 1][tid] = T;
           s_ux[w & 1][tid] = m.ux;
           s_ty[((r % P) + P) % P][tid] = T;
           s_uy[((r % P) + P) % P][tid] = m.uy;
-          if (prm.eos) {  // specific enthalpy h = e + P / rho
+          if constexpr (VDW) {  // specific enthalpy h = e + P / rho
             s_hx[w & 1][tid] = m.e + m.theta;
             s_hy[((r % P) + P) % P][tid] = m.e + m.theta;
           }
@@ -335,10 +340,10 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
       s_phiy[((r % P) + P) % P][tid] = phy;
       __syncthreads();
       // ---- x derivatives of T and u_x (transport control) --------------------------------------
-      if (EXT && prm.full && row_real && own) {
+      if (X && prm.full && row_real && own) {
         ring_m[j][6] = 0.5 * (s_tx[w & 1][tid + 1] - s_tx[w & 1][tid - 1]);
         ring_m[j][7] = 0.5 * (s_ux[w & 1][tid + 1] - s_ux[w & 1][tid - 1]);
-        if (prm.eos) ring_m[j][8] = 0.5 * (s_hx[w & 1][tid + 1] - s_hx[w & 1][tid - 1]);
+        if constexpr (VDW) ring_m[j][NM - 1] = 0.5 * (s_hx[w & 1][tid + 1] - s_hx[w & 1][tid - 1]);
       }
       // ---- x derivative of phi_x on the gathered row -----------------------------------------
       if (row_real && own && prm.phi) {
@@ -381,7 +386,7 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
         }
         // y derivatives of T and u_y (transport control), central with zero-order wall ghosts
         double dTdy = 0.0, duydy = 0.0, dhdy = 0.0;
-        if (EXT && prm.full) {
+        if (X && prm.full) {
           int rm1 = c - 1, rp1 = c + 1;
           if (WALLS) {
             rm1 = rm1 < 0 ? 0 : rm1;
@@ -390,10 +395,10 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
           const int sm = ((rm1 % P) + P) % P, sp = ((rp1 % P) + P) % P;
           dTdy = 0.5 * (s_ty[sp][tid] - s_ty[sm][tid]);
           duydy = 0.5 * (s_uy[sp][tid] - s_uy[sm][tid]);
-          if (prm.eos) dhdy = 0.5 * (s_hy[sp][tid] - s_hy[sm][tid]);
+          if constexpr (VDW) dhdy = 0.5 * (s_hy[sp][tid] - s_hy[sm][tid]);
         }
         const int64_t off = (int64_t)cc * pitch + x;
-        collide_ddf<EXT>(ring_f[sc], ring_g[sc], ring_m[sc], phxx, phyy, dTdy, duydy, dhdy, prm,
+        collide_ddf<X, VDW>(ring_f[sc], ring_g[sc], ring_m[sc], phxx, phyy, dTdy, duydy, dhdy, prm,
                     [&](int i, double htf, double hfe, double htg, double hge) {
                       io.store(off, i, htf, hfe, htg, hge);
                     });
@@ -454,7 +459,8 @@ __global__ void k_moments_ddf(const S* __restrict__ A, int nx, int ny, int64_t p
     g[i] = (double)A[(9 + i) * plane + off] + prm.wg[i];
   }
   Moments m;
-  moments_closure<true>(f, g, prm, m, -prm.Fx, -prm.Fy, -prm.Q);
+  if (prm.eos) moments_closure<true, true>(f, g, prm, m, -prm.Fx, -prm.Fy, -prm.Q);
+  else moments_closure<true, false>(f, g, prm, m, -prm.Fx, -prm.Fy, -prm.Q);
   rho[n] = m.rho;
   u[n] = m.ux;
   u[nodes + n] = m.uy;
@@ -503,7 +509,7 @@ Grid make_grid_ddf(const Layout& L, int halo, bool reduced) {
   return G;
 }
 
-template <class IO, int HALO, bool WALLS, bool PULL, bool EXT>
+template <class IO, int HALO, bool WALLS, bool PULL, int EXT>
 static void ddf_launch_s(const IO& io, const Layout& L, const Grid& G, const DdfParams& prm,
                          double* partials, hipStream_t s) {
   dim3 grid(G.nbx, G.nby), block(kBlock);
@@ -520,12 +526,16 @@ template <class IO, int HALO, bool WALLS, bool PULL>
 static void ddf_launch(const IO& io, const Layout& L, const Grid& G, const DdfParams& prm,
                        double* partials, hipStream_t s) {
   if constexpr (!IO::kStaged) {
+    if (prm.eos) {
+      ddf_launch_s<IO, HALO, WALLS, PULL, 2>(io, L, G, prm, partials, s);
+      return;
+    }
     if (prm.ext()) {
-      ddf_launch_s<IO, HALO, WALLS, PULL, true>(io, L, G, prm, partials, s);
+      ddf_launch_s<IO, HALO, WALLS, PULL, 1>(io, L, G, prm, partials, s);
       return;
     }
   }
-  ddf_launch_s<IO, HALO, WALLS, PULL, false>(io, L, G, prm, partials, s);
+  ddf_launch_s<IO, HALO, WALLS, PULL, 0>(io, L, G, prm, partials, s);
 }
 
 template <class IO, int HALO>

@@ -50,11 +50,12 @@ struct Moments {
 };
 
 // rho = sum f, rho u = sum c f, rho E = sum g; T = (E - u^2/2)/c_v and theta = P/rho = R T.
+// VDW: van der Waals closure (Eq. lbm_temp); the ideal-gas instantiations carry none of it.
 // With sources (SRC) the half-step terms of Sec. II C enter: rho u = sum c f + sF/2 and
 // rho E = sum g + (u.sF + sQ)/2, (sF, sQ) = (F, Q) of the collision that follows. The
 // post-collision state (whose sums carry a whole step of the sources) gives the same moments
 // with (sF, sQ) = -(F, Q) of the collision that produced it.
-template <bool SRC = false>
+template <bool SRC = false, bool VDW = false>
 __device__ __forceinline__ void moments_closure(const double (&f)[9], const double (&g)[9],
                                                 const DdfParams& p, Moments& m, double sFx = 0.0,
                                                 double sFy = 0.0, double sQ = 0.0) {
@@ -72,7 +73,7 @@ __device__ __forceinline__ void moments_closure(const double (&f)[9], const doub
   m.uy = jy * inv;
   if (SRC) rE += 0.5 * ((m.ux * sFx + m.uy * sFy) + sQ);
   m.e = rE * inv - 0.5 * (m.ux * m.ux + m.uy * m.uy);  // specific internal energy
-  if (p.eos) {  // van der Waals: T = (e + a rho) / c_v (Eq. lbm_temp), theta = P / rho
+  if (VDW) {  // van der Waals: T = (e + a rho) / c_v (Eq. lbm_temp), theta = P / rho
     const double T = (m.e + p.va * rho) / p.cv;
     m.theta = p.R * T / (1.0 - p.vb * rho) - p.va * rho;
   } else {
@@ -81,9 +82,10 @@ __device__ __forceinline__ void moments_closure(const double (&f)[9], const doub
 }
 
 // Temperature of a node from its moments (ideal gas: theta / R; van der Waals: Eq. lbm_temp).
+template <bool VDW>
 __device__ __forceinline__ double node_temperature(const DdfParams& p, double rho, double e,
                                                    double theta) {
-  return p.eos ? (e + p.va * rho) / p.cv : theta * p.inv_R;
+  return VDW ? (e + p.va * rho) / p.cv : theta * p.inv_R;
 }
 
 // Pull of the nine populations of one distribution at node (x, row): f_i = A_i(x - c_i).
@@ -133,10 +135,10 @@ __device__ __forceinline__ double upwind_or_central(double pm2, double pm1, doub
 // theta* = theta + alpha theta div u + (gamma - 1) Q/rho with gamma - 1 = R/c_v (ideal gas),
 // c_v T* = e + Q/rho - F.F/(2 rho^2), and g* gains c_i.q^c/2 on the four velocities with
 // |c_i| = 1, q^c = P (c_p - k/mu) grad T (the ideal-gas form of P (grad h - (k/mu) grad T));
-// m[6], m[7], dTdy, duydy are used only when p.full; for the van der Waals fluid (p.eos)
+// m[6], m[7], dTdy, duydy are used only when p.full; for the van der Waals fluid (VDW)
 // gamma - 1 and alpha are per node and q^c = P (grad h - (k/mu) grad T) with h = e + P/rho
 // (m[8], dhdy).
-template <bool EXT = false, typename R, typename Sink>
+template <bool EXT = false, bool VDW = false, typename R, typename Sink>
 __device__ __forceinline__ void collide_ddf(const R (&hf)[9], const R (&hg)[9],
                                             const double* m, double phxx, double phyy,
                                             double dTdy, double duydy, double dhdy,
@@ -152,7 +154,7 @@ __device__ __forceinline__ void collide_ddf(const R (&hf)[9], const R (&hg)[9],
   if (EXT) {
     const double inv = 1.0 / rho;
     double thetas;
-    if (p.eos) {  // van der Waals: gamma - 1 = R / ((1 - b rho) c_v), alpha and q^c per node
+    if constexpr (VDW) {  // van der Waals: gamma - 1 = R / ((1 - b rho) c_v), alpha and q^c per node
       const double omb = 1.0 - p.vb * rho;
       const double T = (e + p.va * rho) / p.cv;
       const double cs2 = p.R * T / (omb * omb) - 2.0 * p.va * rho +
