@@ -227,6 +227,14 @@ def main():
             return binding.Lattice(rs, us, ts, model="ddf", tau=0.6, wall_y=True, phi=phi,
                                    storage=storage, **kw)
 
+        def vdw_lattice():
+            # van der Waals fluid above its critical point (T_cr 1.2, P_cr 0.25 in lattice
+            # units: a = 27 R^2 T_cr^2 / (64 P_cr), b = R T_cr / (8 P_cr)) at rho = 1, where
+            # theta = P / rho stays near 0.31
+            _, us, ts = inputs.thermal_shear_layer(4096, seed=0, T0=1.4, dT=0.03)
+            return binding.Lattice(np.ones_like(ts), us, ts, model="ddf", tau=0.6, wall_y=True,
+                                   phi=1, storage="fp32", vdw=(0.27, 0.2))
+
         red = "fp32 moments + %s f-f_eq (6 of 9 stored)"
         red_ddf = "fp32 moments + %s non-equilibrium (6 f + 8 g of 18 stored)"
         plan = [
@@ -266,6 +274,11 @@ def main():
                 max(100, vs // 4), 10, 144,
                 {"walls": "y, non-equilibrium extrapolation (u_W = -+0.05, T_W = 0.8 / 1.0)",
                  "phi": "central"})),
+            ("d2q9_ddf_fp32_4096_vdw", lambda n: variant(
+                n, lambda: vdw_lattice(), max(100, vs // 4), 10, 144,
+                {"walls": "y", "phi": "central",
+                 "eos": "van der Waals a = 0.27, b = 0.2 (T_cr 1.2, P_cr 0.25), rho 1, "
+                        "T 1.4 +- 0.03 shear layer"})),
             ("d3q27_ddf_fp32_256", lambda n: variant(
                 n, lambda: binding.Lattice(*inputs.thermal_taylor_green_3d(256, 0.05),
                                            lattice="D3Q27", model="ddf", tau=0.6, phi=1),

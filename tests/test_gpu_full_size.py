@@ -1,8 +1,8 @@
 """Full-size checks in the launch configurations that bench.py times, for the workloads with a
-body force, heat source, transport control, non-equilibrium extrapolation walls and the D3Q27
-double distribution: one GPU step from the GPU's own stored state against the oracle's step,
-element by element on whole lattices, row slabs or node neighbourhoods that the oracle can
-compute (a node's step reads its neighbours up to two spacings away: the pull, then the
+body force, heat source, transport control, a van der Waals fluid, non-equilibrium extrapolation
+walls and the D3Q27 double distribution: one GPU step from the GPU's own stored state against
+the oracle's step, element by element on whole lattices, row slabs or node neighbourhoods that
+the oracle can compute (a node's step reads its neighbours up to two spacings away: the pull, then the
 derivative stencils of the moments).
 
 Bar: float32 storage, one step from identical inputs: within 2e-6 of the largest population
@@ -95,6 +95,18 @@ def test_ddf_4096_extended(case):
     lat = _lattice(rho, u, T, model="ddf", tau=0.6, wall_y=True, phi=1, **kw)
     (f_post, g_post), (f_next, g_next) = _two_snapshots(lat, 10)
     _ddf_rows(f_post, g_post, f_next, g_next, gas, (0, 1, 2047, n - 2, n - 1), F, Q)
+
+
+def test_ddf_4096_vdw():
+    n = 4096
+    announce("DDF 4096^2 fp32 walls, van der Waals fluid (bench configuration): one step at "
+             "sampled rows")
+    _, u, T = inputs.thermal_shear_layer(n, seed=0, T0=1.4, dT=0.03)
+    rho = np.ones_like(T)
+    lat = _lattice(rho, u, T, model="ddf", tau=0.6, wall_y=True, phi=1, vdw=(0.27, 0.2))
+    (f_post, g_post), (f_next, g_next) = _two_snapshots(lat, 10)
+    gas = ddf.Gas(R, CV, 0.1 * P0, a=0.27, b=0.2)
+    _ddf_rows(f_post, g_post, f_next, g_next, gas, (0, 1, 2047, n - 2, n - 1))
 
 
 def test_ddf_4096_neq_walls():
