@@ -210,9 +210,11 @@ struct IoRed {
   }
 };
 
+// WALLS: 0 = periodic in y, 1 = bounce-back walls, 2 = non-equilibrium extrapolation walls
+// (boundary rows rebuilt by k_ddf_neq_rows into io.nb).
 // EXT: 0 = paper's collision without sources, 1 = extended path (sources and/or transport
 // control, ideal gas), 2 = extended path for the van der Waals fluid.
-template <class IO, int HALO, bool WALLS, bool PULL, bool DIAG, int EXT>
+template <class IO, int HALO, int WALLS, bool PULL, bool DIAG, int EXT>
 __global__ void __launch_bounds__(kBlock)
 k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
            double* __restrict__ partials) {
@@ -276,8 +278,8 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
     const int yp = rr == ny - 1 ? 0 : rr + 1;
     const int64_t r0 = (int64_t)rr * pitch, rm = (int64_t)ym * pitch, rp = (int64_t)yp * pitch;
     const bool top = WALLS && rr == ny - 1, bot = WALLS && rr == 0;
-    if constexpr (!IO::kStaged) {
-      if (WALLS && prm.neq && (top || bot)) {  // rebuilt boundary rows (k_ddf_neq_rows)
+    if constexpr (WALLS == 2) {
+      if (top || bot) {  // rebuilt boundary rows (k_ddf_neq_rows)
         io.gather_wall(top ? 1 : 0, x, pitch, hf, hg);
         return;
       }
@@ -509,7 +511,7 @@ Grid make_grid_ddf(const Layout& L, int halo, bool reduced) {
   return G;
 }
 
-template <class IO, int HALO, bool WALLS, bool PULL, int EXT>
+template <class IO, int HALO, int WALLS, bool PULL, int EXT>
 static void ddf_launch_s(const IO& io, const Layout& L, const Grid& G, const DdfParams& prm,
                          double* partials, hipStream_t s) {
   dim3 grid(G.nbx, G.nby), block(kBlock);
@@ -522,13 +524,15 @@ static void ddf_launch_s(const IO& io, const Layout& L, const Grid& G, const Ddf
 // The extended path (sources, transport control) exists for float32/float64 storage only (the
 // context rejects it with reduced storage, whose codec assumes a non-equilibrium part without
 // mass and momentum).
-template <class IO, int HALO, bool WALLS, bool PULL>
+template <class IO, int HALO, int WALLS, bool PULL>
 static void ddf_launch(const IO& io, const Layout& L, const Grid& G, const DdfParams& prm,
                        double* partials, hipStream_t s) {
   if constexpr (!IO::kStaged) {
-    if (prm.eos) {
-      ddf_launch_s<IO, HALO, WALLS, PULL, 2>(io, L, G, prm, partials, s);
-      return;
+    if constexpr (WALLS != 2) {  // the context admits the van der Waals fluid without NEQ walls
+      if (prm.eos) {
+        ddf_launch_s<IO, HALO, WALLS, PULL, 2>(io, L, G, prm, partials, s);
+        return;
+      }
     }
     if (prm.ext()) {
       ddf_launch_s<IO, HALO, WALLS, PULL, 1>(io, L, G, prm, partials, s);
@@ -542,11 +546,18 @@ template <class IO, int HALO>
 static void ddf_launch_w(bool walls, bool pull, const IO& io, const Layout& L, const Grid& G,
                          const DdfParams& prm, double* partials, hipStream_t s) {
   if (walls) {
-    if (pull) ddf_launch<IO, HALO, true, true>(io, L, G, prm, partials, s);
-    else ddf_launch<IO, HALO, true, false>(io, L, G, prm, partials, s);
+    if constexpr (!IO::kStaged) {  // NEQ walls: float32 / float64 storage only
+      if (prm.neq) {
+        if (pull) ddf_launch<IO, HALO, 2, true>(io, L, G, prm, partials, s);
+        else ddf_launch<IO, HALO, 2, false>(io, L, G, prm, partials, s);
+        return;
+      }
+    }
+    if (pull) ddf_launch<IO, HALO, 1, true>(io, L, G, prm, partials, s);
+    else ddf_launch<IO, HALO, 1, false>(io, L, G, prm, partials, s);
   } else {
-    if (pull) ddf_launch<IO, HALO, false, true>(io, L, G, prm, partials, s);
-    else ddf_launch<IO, HALO, false, false>(io, L, G, prm, partials, s);
+    if (pull) ddf_launch<IO, HALO, 0, true>(io, L, G, prm, partials, s);
+    else ddf_launch<IO, HALO, 0, false>(io, L, G, prm, partials, s);
   }
 }
 
@@ -622,7 +633,7 @@ hipError_t launch_ddf(int fmt, bool walls, bool pull, const void* A, void* B, co
                       double* partials, void* nb, hipStream_t s) {
   if (prm.ext() && fmt >= 2) return hipErrorInvalidValue;  // no extended path with reduced storage
   if (prm.neq) {
-    if (fmt >= 2 || !walls || !nb || L.ny < 3) return hipErrorInvalidValue;
+    if (fmt >= 2 || !walls || !nb || L.ny < 3 || prm.eos) return hipErrorInvalidValue;
     dim3 grid((L.nx + kBlock - 1) / kBlock, 2);
     if (fmt == 0) {
       if (pull) k_ddf_neq_rows<float, true><<<grid, kBlock, 0, s>>>(static_cast<const float*>(A), L.nx, L.ny, L.pitch, L.plane, prm, static_cast<float*>(nb));
