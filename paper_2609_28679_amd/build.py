@@ -1,7 +1,10 @@
 """Build the HIP library liblbm.so for gfx950 with hipcc (in-tree, next to this file)."""
 import os
+import shutil
 import subprocess
 import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -11,7 +14,7 @@ LIB = os.path.join(HERE, "liblbm.so")
 SOURCES = ["lbm_api.hip", "bgk.hip", "ddf.hip", "ddf3.hip", "reduced.hip", "mlp.hip"]
 
 FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
+    "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     # no packed-FP32 instructions (v_pk_*_f32) anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
@@ -25,17 +28,31 @@ def hipcc():
     return "hipcc"
 
 
-def build(verbose=False):
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [hipcc()] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC] + srcs + ["-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed (exit %d)" % res.returncode)
-    os.replace(tmp, LIB)
+        raise RuntimeError("hipcc failed (exit %d): %s" % (res.returncode, cmd[-3]))
+
+
+def build(verbose=False):
+    """Compile each source to an object in parallel (no device code crosses files), then link."""
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    tmpdir = tempfile.mkdtemp(prefix="lbm_build_")
+    try:
+        objs = [os.path.join(tmpdir, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+        cmds = [[hipcc()] + FLAGS + inc + ["-c", os.path.join(CSRC, s), "-o", o]
+                for s, o in zip(SOURCES, objs)]
+        workers = max(1, min(len(cmds), os.cpu_count() or 1, 8))
+        with ThreadPoolExecutor(workers) as ex:
+            list(ex.map(lambda c: _run(c, verbose), cmds))
+        tmp = LIB + ".tmp"
+        _run([hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950"] + objs + ["-o", tmp], verbose)
+        os.replace(tmp, LIB)
+    finally:
+        shutil.rmtree(tmpdir, ignore_errors=True)
     return LIB
 
 
