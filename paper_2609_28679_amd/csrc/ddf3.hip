@@ -161,12 +161,14 @@ __device__ __forceinline__ void collide3(const S (&hf)[27], const S (&hg)[27], c
 }
 
 // ---- kernels --------------------------------------------------------------------------------
-// Fields written by k_ddf3_flux (float64, each `plane` elements at the population offsets):
-//   0..2 phi_x, phi_y, phi_z;  with transport control 3: T, 4..6: u_x, u_y, u_z.
+// Fields written by k_ddf3_flux (in the storage type S, each `plane` elements at the population
+// offsets): 0..2 phi_x, phi_y, phi_z;  with transport control 3: T, 4..6: u_x, u_y, u_z.
+// With float32 storage the moments already carry the populations' float32 rounding, so float32
+// fields add an error of the same order and halve the field traffic of both sweeps.
 template <typename S, bool WALLS, bool PULL, bool EXT>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
 k_ddf3_flux(const S* __restrict__ A, int nx, int ny, int nz, int64_t pitch, int64_t plane,
-            DdfParams prm, int rows, double* __restrict__ fld) {
+            DdfParams prm, int rows, S* __restrict__ fld) {
   const int nbx = gridDim.x;
   const int tile = blockIdx.x + nbx * blockIdx.y;
   const int bx = tile % nbx, by = tile / nbx;
@@ -182,11 +184,11 @@ k_ddf3_flux(const S* __restrict__ A, int nx, int ny, int nz, int64_t pitch, int6
     const int64_t off = ((int64_t)z * ny + y) * pitch + x;
 #pragma unroll
     for (int a = 0; a < 3; ++a)
-      fld[a * plane + off] = m.rho * m.u[a] * (m.u[a] * m.u[a] + 3.0 * (m.theta - 1.0 / 3.0));
+      fld[a * plane + off] = (S)(m.rho * m.u[a] * (m.u[a] * m.u[a] + 3.0 * (m.theta - 1.0 / 3.0)));
     if (EXT && prm.full) {
-      fld[3 * plane + off] = m.theta * prm.inv_R;
+      fld[3 * plane + off] = (S)(m.theta * prm.inv_R);
 #pragma unroll
-      for (int a = 0; a < 3; ++a) fld[(4 + a) * plane + off] = m.u[a];
+      for (int a = 0; a < 3; ++a) fld[(4 + a) * plane + off] = (S)m.u[a];
     }
   }
 }
@@ -194,7 +196,7 @@ k_ddf3_flux(const S* __restrict__ A, int nx, int ny, int nz, int64_t pitch, int6
 template <typename S, int HALO, bool WALLS, bool PULL, bool DIAG, bool EXT>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
 k_ddf3_collide(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int nz,
-               int64_t pitch, int64_t plane, DdfParams prm, const double* __restrict__ fld,
+               int64_t pitch, int64_t plane, DdfParams prm, const S* __restrict__ fld,
                int rows, double* __restrict__ partials) {
   const int nbx = gridDim.x;
   const int tile = blockIdx.x + nbx * blockIdx.y;
@@ -230,13 +232,13 @@ k_ddf3_collide(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int n
         const double inv_rho = 1.0 / m.rho;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          const double* F = fld + a * plane;
+          const S* F = fld + a * plane;
           double d;
           if (HALO == 1)
-            d = 0.5 * (F[at(a, 1)] - F[at(a, -1)]);
+            d = 0.5 * ((double)F[at(a, 1)] - (double)F[at(a, -1)]);
           else
-            d = upwind_or_central(F[at(a, -2)], F[at(a, -1)], F[off], F[at(a, 1)], F[at(a, 2)],
-                                  m.u[a]);
+            d = upwind_or_central((double)F[at(a, -2)], (double)F[at(a, -1)], (double)F[off],
+                                  (double)F[at(a, 1)], (double)F[at(a, 2)], m.u[a]);
           ph[a] = -d * inv_rho;
         }
       }
@@ -244,8 +246,9 @@ k_ddf3_collide(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int n
       if (EXT && prm.full) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          gT[a] = 0.5 * (fld[3 * plane + at(a, 1)] - fld[3 * plane + at(a, -1)]);
-          divu += 0.5 * (fld[(4 + a) * plane + at(a, 1)] - fld[(4 + a) * plane + at(a, -1)]);
+          gT[a] = 0.5 * ((double)fld[3 * plane + at(a, 1)] - (double)fld[3 * plane + at(a, -1)]);
+          divu += 0.5 * ((double)fld[(4 + a) * plane + at(a, 1)] -
+                         (double)fld[(4 + a) * plane + at(a, -1)]);
         }
       }
       S* out = B + off;
@@ -350,8 +353,9 @@ static void flag(bool b, Fn&& fn) {
 
 template <typename S>
 static void ddf3_step(bool walls, bool pull, const S* A, S* B, const Layout& L, const Grid& G,
-                      const DdfParams& prm, double* fld, double* partials, hipStream_t s) {
+                      const DdfParams& prm, double* fld64, double* partials, hipStream_t s) {
   dim3 grid(G.nbx, G.nby), block(G.bx);
+  S* fld = reinterpret_cast<S*>(fld64);  // 7 planes of the storage type
   flag(walls, [&](auto W) {
     flag(pull, [&](auto Pl) {
       flag(prm.ext(), [&](auto E) {

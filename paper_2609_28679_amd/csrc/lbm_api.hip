@@ -103,7 +103,7 @@ void sync_sources(lbm_ctx* c) {
 
 struct Plan {
   int D, Q, kind, planes, codec;
-  size_t off_fld;  // D3Q27 double distribution: derivative fields (7 float64 planes)
+  size_t off_fld;  // D3Q27 double distribution: derivative fields (7 planes of the storage type)
   size_t off_nb;   // non-equilibrium extrapolation walls: 2 x 18 boundary rows
   bool ddf, aa;
   Layout L;
@@ -256,7 +256,7 @@ void make_plan(const lbm_params* p, Plan& P) {
   // weights 256 bytes further
   P.off_mlp = off; off = align_up(off + 256 + (size_t)kMlpParams * 4, 256);
   P.off_fld = off;
-  if (P.ddf && P.D == 3) off = align_up(off + (size_t)7 * P.L.plane * 8, 256);
+  if (P.ddf && P.D == 3) off = align_up(off + (size_t)7 * P.L.plane * P.elem, 256);
   P.off_nb = off;
   if (p->wall_y == 2) off = align_up(off + (size_t)36 * P.L.pitch * P.elem, 256);
   P.total = off;

@@ -132,8 +132,9 @@ hipError_t launch_moments_ddf(int kind, const void* A, const Layout& L, const Dd
 hipError_t launch_decode_ddf(int kind, int Q, int i, const void* A, const Layout& L,
                              const DdfParams& prm, float s_dec, double* out, hipStream_t s);
 // D3Q27 double distribution (float32 kind 0 / float64 kind 1 storage, 54 planes). One step is
-// two launches: fluxes (and, with transport control, T and u) into `fld` (7 float64 fields of
-// L.plane elements), then the collision; pull = false collides in place of streaming.
+// two launches: fluxes (and, with transport control, T and u) into `fld` (7 fields of L.plane
+// elements in the storage type, float32 or float64), then the collision; pull = false collides
+// in place of streaming.
 hipError_t launch_ddf3_rest_state(const DdfParams& prm, double* out, hipStream_t s);
 hipError_t launch_init_ddf3(int kind, const double* rho, const double* u, const double* T,
                             void* A, const Layout& L, const DdfParams& prm, hipStream_t s);
