@@ -343,6 +343,16 @@ hipError_t launch_moments_ddf3(int kind, const void* A, const Layout& L, const D
   return hipGetLastError();
 }
 
+// The isothermal grid (one row per workgroup at 256^3), with at least two rows per workgroup:
+// at 256^3 float32, 1 row -> 2256-2269 us per step, 2 -> 2222-2225, 4 -> 2223; 128-wide
+// workgroups 2266-2297, 64-wide 2437-2472.
+Grid make_grid_ddf3(const Layout& L) {
+  Grid G = make_grid(L);
+  if (G.rows < 2) G.rows = 2;
+  fit_rows(G, (int64_t)L.ny * L.nz);
+  return G;
+}
+
 template <typename Fn>
 static void flag(bool b, Fn&& fn) {
   if (b)

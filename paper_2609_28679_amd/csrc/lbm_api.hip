@@ -226,6 +226,8 @@ void make_plan(const lbm_params* p, Plan& P) {
   P.L = make_layout(p->nx, p->ny, p->nz, (int)P.elem);
   if (P.ddf && P.D == 2)
     P.G = make_grid_ddf(P.L, p->phi == 2 ? 2 : 1, P.codec >= 0);
+  else if (P.ddf)
+    P.G = make_grid_ddf3(P.L);
   else if (p->collision == LBM_COLLIDE_MLP)
     P.G = make_grid_mlp(P.L);
   else if (P.codec >= 0)

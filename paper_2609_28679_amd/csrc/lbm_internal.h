@@ -135,6 +135,7 @@ hipError_t launch_decode_ddf(int kind, int Q, int i, const void* A, const Layout
 // two launches: fluxes (and, with transport control, T and u) into `fld` (7 fields of L.plane
 // elements in the storage type, float32 or float64), then the collision; pull = false collides
 // in place of streaming.
+Grid make_grid_ddf3(const Layout& L);
 hipError_t launch_ddf3_rest_state(const DdfParams& prm, double* out, hipStream_t s);
 hipError_t launch_init_ddf3(int kind, const double* rho, const double* u, const double* T,
                             void* A, const Layout& L, const DdfParams& prm, hipStream_t s);
