@@ -133,3 +133,41 @@ def test_fp32_ragged_lattice(walls, phi):
     assert np.abs(gg - gt).max() <= 2e-6 * np.abs(gt).max()
     _, uo, to = ddf.temperature(f, g, gas)
     assert rel_l2(ug, uo) <= 1e-5
+
+
+@pytest.mark.parametrize("walls", [True, False])
+def test_fp64_tall_lattice_more_rows_than_grid_limit(walls):
+    # a 7 x 3 x 2 state tiled 6300 times along z: 132300 (y, z) rows exceed two rows per
+    # workgroup within the launch limit of 65535 workgroups, so each workgroup takes three. On a
+    # z-periodic lattice the tiled state evolves as the small lattice's solution, tiled.
+    reps = 6300
+    small = (7, 3, 2)
+    announce("D3Q27 DDF fp64 tall %s x %d along z, walls=%s, 3 steps" % (small, reps, walls))
+    rho, u, T = _fields(small, seed=44)
+    tile = lambda a: np.tile(a, (reps,) + (1,) * (a.ndim - 1))
+    rg, ug, tg, _, _, _ = _run(tile(rho), np.stack([tile(c) for c in u]), tile(T), 3, "fp64",
+                               wall_y=walls, phi=1)
+    gas = ddf.Gas(R, CV, 0.2 * P0)
+    f, g = ddf.run(*ddf.init_equilibrium(rho, u, T, gas), gas, 3, walls_y=walls)
+    ro, uo, to = ddf.temperature(f, g, gas)
+    assert np.abs(rg - tile(ro)).max() <= 1e-13
+    assert np.abs(ug - np.stack([tile(c) for c in uo])).max() <= 1e-13
+    assert np.abs(tg - tile(to)).max() <= 1e-13
+
+
+@pytest.mark.parametrize("shape,walls", [((1, 3, 1), True), ((1, 1, 1), False), ((2, 1, 3), False)])
+def test_fp64_one_node_wide(shape, walls):
+    # lattices one node wide along some axes: every neighbour along such an axis is the node
+    # itself (periodic) or a wall
+    announce("D3Q27 DDF fp64 %s walls=%s 4 steps" % (shape, walls))
+    rho, u, T = _fields(shape, seed=45)
+    rg, ug, tg, _, fg, gg = _run(rho, u, T, 4, "fp64", wall_y=walls, phi=1)
+    gas = ddf.Gas(R, CV, 0.2 * P0)
+    f, g = ddf.run(*ddf.init_equilibrium(rho, u, T, gas), gas, 4, walls_y=walls)
+    ro, uo, to = ddf.temperature(f, g, gas)
+    assert np.abs(rg - ro).max() <= 1e-13
+    assert np.abs(ug - uo).max() <= 1e-13
+    assert np.abs(tg - to).max() <= 1e-13
+    ft, gt = ddf.collide(f, g, gas, walls, True, "central")
+    assert np.abs(fg - ft).max() <= 1e-13
+    assert np.abs(gg - gt).max() <= 1e-13
