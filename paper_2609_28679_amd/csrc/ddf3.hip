@@ -370,8 +370,10 @@ static void ddf3_step(bool walls, bool pull, const S* A, S* B, const Layout& L, 
     flag(pull, [&](auto Pl) {
       flag(prm.ext(), [&](auto E) {
         constexpr bool w = decltype(W)::value, pl = decltype(Pl)::value, e = decltype(E)::value;
-        k_ddf3_flux<S, w, pl, e><<<grid, block, 0, s>>>(A, L.nx, L.ny, L.nz, L.pitch, L.plane,
-                                                        prm, G.rows, fld);
+        // the fields are read only for Phi and for transport control
+        if (prm.phi || (e && prm.full))
+          k_ddf3_flux<S, w, pl, e><<<grid, block, 0, s>>>(A, L.nx, L.ny, L.nz, L.pitch,
+                                                          L.plane, prm, G.rows, fld);
         flag(partials != nullptr, [&](auto Dg) {
           constexpr bool dg = decltype(Dg)::value;
           if (prm.phi == 2)
