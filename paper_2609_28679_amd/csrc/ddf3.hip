@@ -214,17 +214,25 @@ k_ddf3_collide(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int n
       const int64_t off = ((int64_t)z * ny + y) * pitch + x;
       // offset of the node k steps along axis a: periodic in x and z; in y periodic, or the
       // nearest fluid row beyond a wall (zero-order ghosts, Sec. III A)
+      // (|k| <= 2: two conditional wraps cover lattices down to one node along the axis)
+      auto wrap = [](int v, int n) {
+        if (v < 0) v += n;
+        if (v < 0) v += n;
+        if (v >= n) v -= n;
+        if (v >= n) v -= n;
+        return v;
+      };
       auto at = [&](int a, int k) -> int64_t {
         int xx = x, yy = y, zz = z;
-        if (a == 0) xx = ((x + k) % nx + nx) % nx;
+        if (a == 0) xx = wrap(x + k, nx);
         if (a == 1) {
           yy = y + k;
           if (WALLS)
             yy = yy < 0 ? 0 : (yy > ny - 1 ? ny - 1 : yy);
           else
-            yy = (yy % ny + ny) % ny;
+            yy = wrap(yy, ny);
         }
-        if (a == 2) zz = ((z + k) % nz + nz) % nz;
+        if (a == 2) zz = wrap(z + k, nz);
         return ((int64_t)zz * ny + yy) * pitch + xx;
       };
       double ph[3] = {0.0, 0.0, 0.0};
