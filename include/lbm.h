@@ -97,7 +97,7 @@ typedef struct {
                           FP32/FP64 storage. */
   int32_t eos;         /* DDF equation of state: 0 = ideal gas (Sec. III A), 1 = van der Waals
                           P = rho R T / (1 - b rho) - a rho^2 with e = c_v T - a rho (Sec. III C);
-                          van der Waals: D2Q9, FP32/FP64 storage, wall_y 0 or 1. Its alpha and
+                          van der Waals: D2Q9 or D3Q27, FP32/FP64 storage, wall_y 0 or 1. Its alpha and
                           q^c are per node (k/mu = (c_v + R) / prandtl). */
   double vdw_a, vdw_b; /* van der Waals a >= 0, b >= 0 (lattice units); 1 - b rho > 0 */
   double wall_u[2][3]; /* wall_y = 2: wall velocity [bottom (y = 0), top (y = ny-1)][x, y, z];

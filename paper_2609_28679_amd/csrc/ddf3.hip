@@ -62,8 +62,10 @@ __device__ __forceinline__ void gather27(const S* __restrict__ A, int64_t plane,
 }
 
 // rho = sum f, rho u = sum c f + sF/2, rho E = sum g + (u.sF + sQ)/2 (Sec. II C), then
-// T = (E - u^2/2)/c_v and theta = R T. (sF, sQ) as in moments_closure (ddf_common.h).
-template <bool EXT, typename S>
+// T = (E - u^2/2)/c_v and theta = R T; for the van der Waals fluid (EXT = 2)
+// T = (E - u^2/2 + a rho)/c_v (Eq. lbm_temp) and theta = P/rho. (sF, sQ) as in moments_closure
+// (ddf_common.h); EXT = 0 takes no sources.
+template <int EXT, typename S>
 __device__ __forceinline__ void moments3(const S (&hf)[27], const S (&hg)[27], const DdfParams& p,
                                          Moments3& m, double sFx, double sFy, double sFz,
                                          double sQ) {
@@ -89,7 +91,12 @@ __device__ __forceinline__ void moments3(const S (&hf)[27], const S (&hg)[27], c
   for (int a = 0; a < 3; ++a) m.u[a] = j[a] * inv;
   if (EXT) rE += 0.5 * ((m.u[0] * sFx + m.u[1] * sFy + m.u[2] * sFz) + sQ);
   m.e = rE * inv - 0.5 * (m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2]);
-  m.theta = p.r_cv * m.e;
+  if constexpr (EXT == 2) {
+    const double T = (m.e + p.va * rho) / p.cv;
+    m.theta = p.R * T / (1.0 - p.vb * rho) - p.va * rho;
+  } else {
+    m.theta = p.r_cv * m.e;
+  }
 }
 
 // f^eq and g^eq in product form (Sec. II C; the operator-generated g^eq in closed form,
@@ -104,11 +111,15 @@ __device__ __forceinline__ void equilibria3(double rho, double e, int i, const A
 }
 
 // Collision of one node (see collide_ddf in ddf_common.h for the D2Q9 form): ph[a] = Phi_aa,
-// gT[a] = dT/da and divu = div u (used only when p.full); sink(i, f~ - w, g~ - v).
-template <bool EXT, typename S, typename Sink>
+// gT[a] = dT/da and divu = div u (used only when p.full), gh[a] = dh/da of the enthalpy
+// h = e + P/rho (van der Waals only); sink(i, f~ - w, g~ - v). EXT: 0 without sources and
+// transport terms, 1 with them (ideal gas), 2 the van der Waals fluid (gamma - 1, alpha and
+// q^c = P (grad h - (k/mu) grad T) per node).
+template <int EXT, typename S, typename Sink>
 __device__ __forceinline__ void collide3(const S (&hf)[27], const S (&hg)[27], const Moments3& m,
                                          const double (&ph)[3], const double (&gT)[3],
-                                         double divu, const DdfParams& p, Sink&& sink) {
+                                         const double (&gh)[3], double divu, const DdfParams& p,
+                                         Sink&& sink) {
   const double rho = m.rho, theta = m.theta, e = m.e;
   const double P = rho * theta;
   Axis X[3];
@@ -119,11 +130,23 @@ __device__ __forceinline__ void collide3(const S (&hf)[27], const S (&hg)[27], c
   if (EXT) {
     const double inv = 1.0 / rho;
     const double Fa[3] = {p.Fx, p.Fy, p.Fz};
-    double thetas = theta + p.r_cv * p.Q * inv;
-    if (p.full) {
-      thetas += p.alpha * theta * divu;
+    double thetas;
+    if constexpr (EXT == 2) {
+      const double omb = 1.0 - p.vb * rho;
+      const double T = (e + p.va * rho) / p.cv;
+      const double cs2 = p.R * T / (omb * omb) - 2.0 * p.va * rho +
+                         T * p.R * p.R / (p.cv * omb * omb);
+      const double alpha = 5.0 / 3.0 - rho * cs2 / P - p.eta;  // (D+2)/D - rho c_s^2/P - eta/mu
+      thetas = theta + p.R / (omb * p.cv) * p.Q * inv + alpha * theta * divu;
 #pragma unroll
-      for (int a = 0; a < 3; ++a) q[a] = P * p.qc * gT[a];
+      for (int a = 0; a < 3; ++a) q[a] = P * (gh[a] - p.kmu * gT[a]);
+    } else {
+      thetas = theta + p.r_cv * p.Q * inv;
+      if (p.full) {
+        thetas += p.alpha * theta * divu;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) q[a] = P * p.qc * gT[a];
+      }
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) axis_eq(m.u[a] + Fa[a] * inv, thetas, XS[a]);
@@ -162,10 +185,11 @@ __device__ __forceinline__ void collide3(const S (&hf)[27], const S (&hg)[27], c
 
 // ---- kernels --------------------------------------------------------------------------------
 // Fields written by k_ddf3_flux (in the storage type S, each `plane` elements at the population
-// offsets): 0..2 phi_x, phi_y, phi_z;  with transport control 3: T, 4..6: u_x, u_y, u_z.
+// offsets): 0..2 phi_x, phi_y, phi_z;  with transport control 3: T, 4..6: u_x, u_y, u_z; for the
+// van der Waals fluid 7: h = e + P/rho.
 // With float32 storage the moments already carry the populations' float32 rounding, so float32
 // fields add an error of the same order and halve the field traffic of both sweeps.
-template <typename S, bool WALLS, bool PULL, bool EXT>
+template <typename S, bool WALLS, bool PULL, int EXT>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
 k_ddf3_flux(const S* __restrict__ A, int nx, int ny, int nz, int64_t pitch, int64_t plane,
             DdfParams prm, int rows, S* __restrict__ fld) {
@@ -186,14 +210,16 @@ k_ddf3_flux(const S* __restrict__ A, int nx, int ny, int nz, int64_t pitch, int6
     for (int a = 0; a < 3; ++a)
       fld[a * plane + off] = (S)(m.rho * m.u[a] * (m.u[a] * m.u[a] + 3.0 * (m.theta - 1.0 / 3.0)));
     if (EXT && prm.full) {
-      fld[3 * plane + off] = (S)(m.theta * prm.inv_R);
+      const double T = EXT == 2 ? (m.e + prm.va * m.rho) / prm.cv : m.theta * prm.inv_R;
+      fld[3 * plane + off] = (S)T;
 #pragma unroll
       for (int a = 0; a < 3; ++a) fld[(4 + a) * plane + off] = (S)m.u[a];
+      if (EXT == 2) fld[7 * plane + off] = (S)(m.e + m.theta);
     }
   }
 }
 
-template <typename S, int HALO, bool WALLS, bool PULL, bool DIAG, bool EXT>
+template <typename S, int HALO, bool WALLS, bool PULL, bool DIAG, int EXT>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
 k_ddf3_collide(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int nz,
                int64_t pitch, int64_t plane, DdfParams prm, const S* __restrict__ fld,
@@ -250,17 +276,19 @@ k_ddf3_collide(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int n
           ph[a] = -d * inv_rho;
         }
       }
-      double gT[3] = {0.0, 0.0, 0.0}, divu = 0.0;
+      double gT[3] = {0.0, 0.0, 0.0}, gh[3] = {0.0, 0.0, 0.0}, divu = 0.0;
       if (EXT && prm.full) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
           gT[a] = 0.5 * ((double)fld[3 * plane + at(a, 1)] - (double)fld[3 * plane + at(a, -1)]);
           divu += 0.5 * ((double)fld[(4 + a) * plane + at(a, 1)] -
                          (double)fld[(4 + a) * plane + at(a, -1)]);
+          if (EXT == 2)
+            gh[a] = 0.5 * ((double)fld[7 * plane + at(a, 1)] - (double)fld[7 * plane + at(a, -1)]);
         }
       }
       S* out = B + off;
-      collide3<EXT>(hf, hg, m, ph, gT, divu, prm, [&](int i, double tf, double tg) {
+      collide3<EXT>(hf, hg, m, ph, gT, gh, divu, prm, [&](int i, double tf, double tg) {
         store_nt(out + i * plane, (S)tf);
         store_nt(out + (27 + i) * plane, (S)tg);
       });
@@ -284,13 +312,17 @@ __global__ void k_init_ddf3(const double* __restrict__ rho, const double* __rest
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= nodes) return;
   const int64_t off = (n / nx) * pitch + (n % nx);
-  const double theta = prm.R * T[n];
+  double theta = prm.R * T[n], e = prm.cv * T[n];
+  if (prm.eos) {  // van der Waals: theta = P / rho, e = c_v T - a rho
+    theta = prm.R * T[n] / (1.0 - prm.vb * rho[n]) - prm.va * rho[n];
+    e -= prm.va * rho[n];
+  }
   const double uu[3] = {u[n], u[nodes + n], u[2 * nodes + n]};
   Axis X[3];
   for (int a = 0; a < 3; ++a) axis_eq(uu[a], theta, X[a]);
   for (int i = 0; i < 27; ++i) {
     double fe, ge;
-    equilibria3(rho[n], prm.cv * T[n], i, X, fe, ge);
+    equilibria3(rho[n], e, i, X, fe, ge);
     A[i * plane + off] = (S)(fe - prm.wf[i]);
     A[(27 + i) * plane + off] = (S)(ge - prm.wg[i]);
   }
@@ -312,10 +344,11 @@ __global__ void k_moments_ddf3(const S* __restrict__ A, int nx, int64_t nodes, i
     hg[i] = A[(27 + i) * plane + off];
   }
   Moments3 m;
-  moments3<true>(hf, hg, prm, m, -prm.Fx, -prm.Fy, -prm.Fz, -prm.Q);
+  if (prm.eos) moments3<2>(hf, hg, prm, m, -prm.Fx, -prm.Fy, -prm.Fz, -prm.Q);
+  else moments3<1>(hf, hg, prm, m, -prm.Fx, -prm.Fy, -prm.Fz, -prm.Q);
   rho[n] = m.rho;
   for (int a = 0; a < 3; ++a) u[a * nodes + n] = m.u[a];
-  T[n] = m.theta / prm.R;
+  T[n] = prm.eos ? (m.e + prm.va * m.rho) / prm.cv : m.theta / prm.R;
   edens[n] = m.rho * (m.e + 0.5 * (m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2]));
 }
 
@@ -369,15 +402,28 @@ static void flag(bool b, Fn&& fn) {
     fn(std::false_type{});
 }
 
+// The collision variant as a template argument: 0 plain, 1 sources / transport control (ideal
+// gas), 2 van der Waals fluid.
+template <typename Fn>
+static void ext_kind(const DdfParams& prm, Fn&& fn) {
+  if (prm.eos)
+    fn(std::integral_constant<int, 2>{});
+  else if (prm.ext())
+    fn(std::integral_constant<int, 1>{});
+  else
+    fn(std::integral_constant<int, 0>{});
+}
+
 template <typename S>
 static void ddf3_step(bool walls, bool pull, const S* A, S* B, const Layout& L, const Grid& G,
                       const DdfParams& prm, double* fld64, double* partials, hipStream_t s) {
   dim3 grid(G.nbx, G.nby), block(G.bx);
-  S* fld = reinterpret_cast<S*>(fld64);  // 7 planes of the storage type
+  S* fld = reinterpret_cast<S*>(fld64);  // 8 planes of the storage type
   flag(walls, [&](auto W) {
     flag(pull, [&](auto Pl) {
-      flag(prm.ext(), [&](auto E) {
-        constexpr bool w = decltype(W)::value, pl = decltype(Pl)::value, e = decltype(E)::value;
+      ext_kind(prm, [&](auto E) {
+        constexpr bool w = decltype(W)::value, pl = decltype(Pl)::value;
+        constexpr int e = decltype(E)::value;
         // the fields are read only for Phi and for transport control
         if (prm.phi || (e && prm.full))
           k_ddf3_flux<S, w, pl, e><<<grid, block, 0, s>>>(A, L.nx, L.ny, L.nz, L.pitch,

@@ -103,7 +103,7 @@ void sync_sources(lbm_ctx* c) {
 
 struct Plan {
   int D, Q, kind, planes, codec;
-  size_t off_fld;  // D3Q27 double distribution: derivative fields (7 planes of the storage type)
+  size_t off_fld;  // D3Q27 double distribution: derivative fields (8 planes of the storage type)
   size_t off_nb;   // non-equilibrium extrapolation walls: 2 x 18 boundary rows
   bool ddf, aa;
   Layout L;
@@ -177,9 +177,9 @@ int validate(const lbm_params* p, std::string& why) {
   }
   if (p->eos != 0 && p->eos != 1) { why = "eos must be 0 (ideal gas) or 1 (van der Waals)"; return LBM_EINVAL; }
   if (p->eos == 1) {
-    if (p->model != LBM_MODEL_DDF || p->lattice != LBM_D2Q9 ||
+    if (p->model != LBM_MODEL_DDF ||
         (p->storage != LBM_STORE_FP32 && p->storage != LBM_STORE_FP64) || p->wall_y == 2) {
-      why = "the van der Waals eos needs the D2Q9 double-distribution model, FP32 or FP64 storage and wall_y 0 or 1";
+      why = "the van der Waals eos needs the double-distribution model, FP32 or FP64 storage and wall_y 0 or 1";
       return LBM_EINVAL;
     }
     if (!(p->vdw_a >= 0.0) || !(p->vdw_b >= 0.0) || !std::isfinite(p->vdw_a) || !std::isfinite(p->vdw_b)) {
@@ -258,7 +258,7 @@ void make_plan(const lbm_params* p, Plan& P) {
   // weights 256 bytes further
   P.off_mlp = off; off = align_up(off + 256 + (size_t)kMlpParams * 4, 256);
   P.off_fld = off;
-  if (P.ddf && P.D == 3) off = align_up(off + (size_t)7 * P.L.plane * P.elem, 256);
+  if (P.ddf && P.D == 3) off = align_up(off + (size_t)8 * P.L.plane * P.elem, 256);
   P.off_nb = off;
   if (p->wall_y == 2) off = align_up(off + (size_t)36 * P.L.pitch * P.elem, 256);
   P.total = off;

@@ -66,7 +66,7 @@ struct DdfParams {
   // qc = c_p - k/mu in q^c = P qc grad T (Prandtl number); full = either non-zero
   double alpha = 0.0, qc = 0.0;
   bool full = false;
-  // van der Waals fluid (eos = 1; D2Q9): P = rho R T / (1 - vb rho) - va rho^2, e = c_v T - va rho.
+  // van der Waals fluid (eos = 1): P = rho R T / (1 - vb rho) - va rho^2, e = c_v T - va rho.
   // Its alpha is computed per node with the bulk viscosity ratio eta, and its heat flux
   // q^c = P (grad h - kmu grad T) uses kmu = k / mu = (c_v + R) / Pr; it always takes the
   // extended path (full).
@@ -132,9 +132,9 @@ hipError_t launch_moments_ddf(int kind, const void* A, const Layout& L, const Dd
 hipError_t launch_decode_ddf(int kind, int Q, int i, const void* A, const Layout& L,
                              const DdfParams& prm, float s_dec, double* out, hipStream_t s);
 // D3Q27 double distribution (float32 kind 0 / float64 kind 1 storage, 54 planes). One step is
-// two launches: fluxes (and, with transport control, T and u) into `fld` (7 fields of L.plane
-// elements in the storage type, float32 or float64), then the collision; pull = false collides
-// in place of streaming.
+// two launches: fluxes (and, with transport control, T and u; for the van der Waals fluid also
+// the enthalpy) into `fld` (8 fields of L.plane elements in the storage type, float32 or
+// float64), then the collision; pull = false collides in place of streaming.
 Grid make_grid_ddf3(const Layout& L);
 hipError_t launch_ddf3_rest_state(const DdfParams& prm, double* out, hipStream_t s);
 hipError_t launch_init_ddf3(int kind, const double* rho, const double* u, const double* T,

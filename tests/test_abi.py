@@ -234,7 +234,7 @@ def test_neq_walls_validate_wall_state(lib):
     assert lib.lbm_workspace_size(ctypes.byref(p), ctypes.byref(n)) == binding.LBM_EINVAL
 
 
-@pytest.mark.parametrize("kw", [dict(eos=2), dict(eos=1), dict(eos=1, model=1, lattice=1, nz=4),
+@pytest.mark.parametrize("kw", [dict(eos=2), dict(eos=1), dict(eos=1, model=1, wall_y=2),
                                 dict(eos=1, model=1, storage=1),
                                 dict(eos=1, model=1, vdw_a=-1.0),
                                 dict(eos=1, model=1, vdw_b=float("nan"))])
@@ -243,7 +243,10 @@ def test_van_der_waals_rejected_where_unsupported(lib, kw):
     assert rc == binding.LBM_EINVAL
 
 
-def test_van_der_waals_accepted_for_the_d2q9_thermal_model(lib):
+def test_van_der_waals_accepted_for_the_thermal_model(lib):
     for storage in (0, 3):
         rc, _ = _workspace(lib, eos=1, model=1, storage=storage, vdw_a=0.27, vdw_b=0.2)
+        assert rc == 0
+        rc, _ = _workspace(lib, eos=1, model=1, lattice=1, nz=4, storage=storage, vdw_a=0.27,
+                           vdw_b=0.2)
         assert rc == 0

@@ -1,6 +1,6 @@
-"""GPU parity of the D2Q9 double-distribution kernel for a van der Waals fluid (Sec. III C:
-P = rho R T / (1 - b rho) - a rho^2, T = (E - u^2/2 + a rho) / c_v; per-node gamma and alpha,
-q^c = P (grad h - (k/mu) grad T)) against the FP64 oracle.
+"""GPU parity of the D2Q9 and D3Q27 double-distribution kernels for a van der Waals fluid
+(Sec. III C: P = rho R T / (1 - b rho) - a rho^2, T = (E - u^2/2 + a rho) / c_v; per-node gamma
+and alpha, q^c = P (grad h - (k/mu) grad T)) against the FP64 oracle.
 
 Bars: float64 storage 1e-13 absolute on rho, u and T and on the stored populations; float32
 storage rel-L2 <= 1e-5 on velocity and temperature deviations; isochoric heating raises T and
@@ -113,3 +113,61 @@ def test_isochoric_heating():
         assert np.abs(P - P_first - t * dP).max() <= 2e-14
         lat.step(1)
     lat.close()
+
+
+# ---- D3Q27 (the paper's lattice): the same closure in the two-launch 3D kernels ----------------
+CASES3 = [dict(), dict(force=(1e-4, -2e-4, 1e-4), heat_source=1e-4),
+          dict(prandtl=0.71, eta_over_mu=1.0)]
+
+
+@pytest.mark.parametrize("case", [0, 1, 2])
+@pytest.mark.parametrize("phi", [1, 2])
+@pytest.mark.parametrize("walls", [True, False])
+def test_d3q27_fp64_matches_oracle(walls, phi, case):
+    kw = CASES3[case]
+    shape, steps, tau = (5, 7, 9), 5, 0.7
+    announce("D3Q27 DDF van der Waals fp64 %s walls=%s phi=%d %s" % (shape, walls, phi, kw))
+    rng = np.random.default_rng(70 + case)
+    rho = 1.0 + 0.01 * rng.standard_normal(shape)
+    T = 1.4 + 0.03 * rng.standard_normal(shape)
+    u = 0.02 * rng.standard_normal((3,) + shape)  # no exact zeros (upwind side choice)
+    lat = _lattice(rho, u, T, lattice="D3Q27", tau=tau, wall_y=walls, phi=phi, storage="fp64",
+                   **kw)
+    lat.step(steps)
+    rg, ug, tg, _ = lat.moments()
+    fg, gg = lat.populations()
+    lat.close()
+    gas = ddf.Gas(R, CV, (tau - 0.5) * P0, prandtl=kw.get("prandtl", 1.0),
+                  eta_over_mu=kw.get("eta_over_mu"), a=A, b=B)
+    F = np.asarray(kw["force"]) if "force" in kw else None
+    Q = kw.get("heat_source", 0.0)
+    f, g = ddf.run(*ddf.init_equilibrium(rho, u, T, gas), gas, steps, walls_y=walls,
+                   stencil=STENCIL[phi], F=F, Q=Q)
+    ro, uo, to = ddf.temperature(f, g, gas, F=F, Q=Q)
+    assert np.abs(rg - ro).max() <= 1e-13
+    assert np.abs(ug - uo).max() <= 1e-13
+    assert np.abs(tg - to).max() <= 1e-13
+    ft, gt = ddf.collide(f, g, gas, walls, True, STENCIL[phi], F=F, Q=Q)
+    assert np.abs(fg - ft).max() <= 1e-13
+    assert np.abs(gg - gt).max() <= 1e-13
+
+
+def test_d3q27_fp32_matches_oracle():
+    shape, steps = (8, 10, 24), 20
+    announce("D3Q27 DDF van der Waals fp32 %s walls %d steps" % (shape, steps))
+    Z, Y, X = np.meshgrid(*[np.arange(n) for n in shape], indexing="ij")
+    rho = 1.0 + 0.01 * np.cos(2 * np.pi * X / shape[2])
+    T = 1.4 + 0.03 * np.sin(2 * np.pi * (Y + 0.5) / shape[1]) * np.cos(2 * np.pi * Z / shape[0])
+    u = np.zeros((3,) + shape)
+    u[0] = 0.03 * np.sin(2 * np.pi * (Y + 0.5) / shape[1])
+    u[1] = 0.01 * np.sin(2 * np.pi * X / shape[2])
+    u[2] = 0.01 * np.cos(2 * np.pi * X / shape[2])
+    lat = _lattice(rho, u, T, lattice="D3Q27", tau=0.7, wall_y=True, phi=1, storage="fp32")
+    lat.step(steps)
+    _, ug, tg, _ = lat.moments()
+    lat.close()
+    gas = ddf.Gas(R, CV, 0.2 * P0, a=A, b=B)
+    f, g = ddf.run(*ddf.init_equilibrium(rho, u, T, gas), gas, steps, walls_y=True)
+    _, uo, to = ddf.temperature(f, g, gas)
+    assert rel_l2(ug, uo) <= 1e-5
+    assert rel_l2(tg - 1.4, to - 1.4) <= 1e-5

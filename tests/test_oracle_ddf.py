@@ -423,6 +423,44 @@ def test_d3q27_z_uniform_run_reproduces_d2q9():
             np.testing.assert_allclose(g3[sel].sum(axis=0)[1], g2[i2], rtol=0, atol=1e-14)
 
 
+def test_d3q27_z_uniform_van_der_waals_run_reproduces_d2q9():
+    # the same reduction for the van der Waals fluid (Sec. III C): with the default bulk
+    # viscosity eta/mu = 2/D - R/c_v, alpha = 1 - rho c_s^2/P + R/c_v per node does not depend on
+    # D, the heat flux P (grad h - (k/mu) grad T) has no z component, and the closure
+    # T = (e + a rho)/c_v is local; with a force, a heat source and Pr = 0.7
+    a_, b_ = 27.0 * R * R * 1.44 / (64.0 * 0.25), R * 1.2 / (8.0 * 0.25)
+    gas = ddf.Gas(R, CV, 0.2 * P0, prandtl=0.7, a=a_, b=b_)
+    rng = np.random.default_rng(8)
+    shape = (6, 7)
+    rho2 = 1.0 + 0.01 * rng.standard_normal(shape)
+    T2 = 1.4 + 0.03 * rng.standard_normal(shape)
+    u2 = 0.02 * rng.standard_normal((2,) + shape)
+    nz = 3
+    rho3 = np.repeat(rho2[None], nz, axis=0)
+    T3 = np.repeat(T2[None], nz, axis=0)
+    u3 = np.zeros((3, nz) + shape)
+    u3[:2] = u2[:, None]
+    F2, Q = np.array([1e-4, -2e-4]), 1e-4
+    f2, g2 = ddf.run(*ddf.init_equilibrium(rho2, u2, T2, gas), gas, 5, walls_y=True, F=F2, Q=Q)
+    f3, g3 = ddf.run(*ddf.init_equilibrium(rho3, u3, T3, gas), gas, 5, walls_y=True,
+                     F=np.array([F2[0], F2[1], 0.0]), Q=Q)
+    from oracle.lattice import velocities
+    c3 = velocities(3)
+    for i2, c in enumerate([tuple(c) for c in velocities(2)]):
+        sel = [i for i, cc in enumerate(c3) if (cc[0], cc[1]) == c]
+        np.testing.assert_allclose(f3[sel].sum(axis=0)[1], f2[i2], rtol=0, atol=1e-14)
+        np.testing.assert_allclose(g3[sel].sum(axis=0)[1], g2[i2], rtol=0, atol=1e-14)
+    # a wrong (D+2)/D in alpha breaks the reduction: the same run with alpha off by 1/3 in 3D
+    gas_bad = ddf.Gas(R, CV, 0.2 * P0, prandtl=0.7, eta_over_mu=2.0 / 3.0 - R / CV + 1.0 / 3.0,
+                      a=a_, b=b_)
+    f3b, _ = ddf.run(*ddf.init_equilibrium(rho3, u3, T3, gas_bad), gas_bad, 5, walls_y=True,
+                     F=np.array([F2[0], F2[1], 0.0]), Q=Q)
+    dev = max(np.abs(f3b[sel].sum(axis=0)[1] - f2[i2]).max()
+              for i2, c in enumerate([tuple(c) for c in velocities(2)])
+              for sel in [[i for i, cc in enumerate(c3) if (cc[0], cc[1]) == c]])
+    assert dev > 1e-9
+
+
 @pytest.mark.parametrize("walls", [True, False])
 def test_d3q27_conservation(walls):
     # mass and energy are conserved with or without the bounce-back walls; momentum only on
