@@ -235,6 +235,11 @@ def main():
             return binding.Lattice(np.ones_like(ts), us, ts, model="ddf", tau=0.6, wall_y=True,
                                    phi=1, storage="fp32", vdw=(0.27, 0.2))
 
+        def vdw_tgv3():
+            # the 3D Taylor-Green velocity at rho = 1, T = 1.4 (theta = P / rho ~ 0.31)
+            _, u3 = inputs.taylor_green_3d(256, 0.05)
+            return np.ones(u3.shape[1:]), u3, np.full(u3.shape[1:], 1.4)
+
         red = "fp32 moments + %s f-f_eq (6 of 9 stored)"
         red_ddf = "fp32 moments + %s non-equilibrium (6 f + 8 g of 18 stored)"
         plan = [
@@ -284,6 +289,12 @@ def main():
                                            lattice="D3Q27", model="ddf", tau=0.6, phi=1),
                 max(50, vs // 20), 5, 432,
                 {"phi": "central", "launches": "2 per step (fluxes, collision)"})),
+            ("d3q27_ddf_fp32_256_vdw", lambda n: variant(
+                n, lambda: binding.Lattice(*vdw_tgv3(), lattice="D3Q27", model="ddf", tau=0.6,
+                                           phi=1, vdw=(0.27, 0.2)),
+                max(50, vs // 20), 5, 432,
+                {"phi": "central", "launches": "2 per step (fluxes, collision)",
+                 "eos": "van der Waals a = 0.27, b = 0.2, rho 1, T 1.4"})),
             ("d2q9_ddf_fp32_4096_upwind", lambda n: variant(
                 n, lambda: ddf_lattice("fp32", phi=2), max(100, vs // 4), 10, 144,
                 {"walls": "y", "phi": "upwind"})),

@@ -219,8 +219,12 @@ k_ddf3_flux(const S* __restrict__ A, int nx, int ny, int nz, int64_t pitch, int6
   }
 }
 
+// Two waves per SIMD fit the plain collision (223 VGPRs); the extended ones need more than 256
+// registers and run one wave without spills (at two they spilled 228-252 bytes per lane and
+// took 3368 / 4153 / 4434 us per 256^3 step with sources / transport control / van der Waals,
+// against 2626 / 2909 / 3009 us at one wave).
 template <typename S, int HALO, bool WALLS, bool PULL, bool DIAG, int EXT>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(EXT == 0 ? 2 : 1)))
 k_ddf3_collide(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int nz,
                int64_t pitch, int64_t plane, DdfParams prm, const S* __restrict__ fld,
                int rows, double* __restrict__ partials) {

@@ -1,13 +1,9 @@
 """Full-size checks in the launch configurations that bench.py times, for the workloads with a
-body force, heat source, transport control, a van der Waals fluid, non-equilibrium extrapolation
-walls and the D3Q27 double distribution: one GPU step from the GPU's own stored state against
-the oracle's step, element by element on whole lattices, row slabs or node neighbourhoods that
-the oracle can compute (a node's step reads its neighbours up to two spacings away: the pull, then the
-derivative stencils of the moments).
-
-Bar: float32 storage, one step from identical inputs: within 2e-6 of the largest population
-of the compared set (a few float32 ulp of arithmetic done in float64).
-"""
+body force, heat source, transport control, a van der Waals fluid (D2Q9 and D3Q27),
+non-equilibrium extrapolation walls and the D3Q27 double distribution: one GPU step from the
+GPU's own stored state against the oracle's step, element by element on whole lattices, row
+slabs or node neighbourhoods that the oracle can compute (a node's step reads its neighbours up
+to two spacings away: the pull, then the derivative stencils of the moments)."""
 import numpy as np
 import pytest
 
@@ -133,20 +129,36 @@ def test_ddf_4096_neq_walls():
     _ddf_rows(f_post, g_post, f_next, g_next, gas, (2047,))
 
 
-def test_ddf3_256():
+def test_ddf3_256_vdw():
     n = 256
-    announce("D3Q27 DDF 256^3 fp32 periodic (bench configuration): one step at sampled nodes")
-    rho, u, T = inputs.thermal_taylor_green_3d(n, 0.05)
-    lat = _lattice(rho, u, T, lattice="D3Q27", model="ddf", tau=0.6, phi=1)
+    announce("D3Q27 DDF 256^3 fp32 periodic, van der Waals fluid (bench configuration): one "
+             "step at sampled nodes")
+    _, u = inputs.taylor_green_3d(n, 0.05)
+    rho, T = np.ones(u.shape[1:]), np.full(u.shape[1:], 1.4)
+    lat = _lattice(rho, u, T, lattice="D3Q27", model="ddf", tau=0.6, phi=1, vdw=(0.27, 0.2))
     (f_post, g_post), (f_next, g_next) = _two_snapshots(lat, 5)
-    gas = ddf.Gas(R, CV, 0.1 * P0)
-    rng = np.random.default_rng(3)
+    gas = ddf.Gas(R, CV, 0.1 * P0, a=0.27, b=0.2)
+    _ddf3_nodes(f_post, g_post, f_next, g_next, gas, n, seed=4)
+
+
+def _ddf3_nodes(f_post, g_post, f_next, g_next, gas, n, seed):
+    """Sampled nodes of a periodic D3Q27 double-distribution step, each from its 5^3
+    neighbourhood streamed and collided as a periodic box (its centre is exact)."""
+    rng = np.random.default_rng(seed)
     nodes = [(0, 0, 0), (255, 128, 1), (17, 255, 254)] + [tuple(v) for v in rng.integers(0, n, (3, 3))]
     for z, y, x in nodes:
-        # the 5^3 neighbourhood, streamed and collided as a periodic box: its centre is exact
         idx = np.ix_(*[[(c + d) % n for d in range(-2, 3)] for c in (z, y, x)])
         fb = np.stack([f_post[i][idx] for i in range(27)])
         gb = np.stack([g_post[i][idx] for i in range(27)])
         ft, gt = ddf.collide(bgk.stream(fb), bgk.stream(gb), gas, False, True, "central")
         assert _close(f_next[:, z, y, x], ft[:, 2, 2, 2]), (z, y, x)
         assert _close(g_next[:, z, y, x], gt[:, 2, 2, 2]), (z, y, x)
+
+
+def test_ddf3_256():
+    n = 256
+    announce("D3Q27 DDF 256^3 fp32 periodic (bench configuration): one step at sampled nodes")
+    rho, u, T = inputs.thermal_taylor_green_3d(n, 0.05)
+    lat = _lattice(rho, u, T, lattice="D3Q27", model="ddf", tau=0.6, phi=1)
+    (f_post, g_post), (f_next, g_next) = _two_snapshots(lat, 5)
+    _ddf3_nodes(f_post, g_post, f_next, g_next, ddf.Gas(R, CV, 0.1 * P0), n, seed=3)
