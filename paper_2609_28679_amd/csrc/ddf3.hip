@@ -61,6 +61,28 @@ __device__ __forceinline__ void gather27(const S* __restrict__ A, int64_t plane,
   }
 }
 
+// Pre-collision populations of node (x, y, z). WALLS: 0 periodic in y, 1 bounce-back walls,
+// 2 non-equilibrium extrapolation walls, whose boundary planes y = 0 and y = ny - 1 come
+// rebuilt from nb (k_ddf3_neq_rows: 2 sides x 54 populations, each nz x pitch elements).
+template <typename S, int WALLS, bool PULL>
+__device__ __forceinline__ void node_pops(const S* __restrict__ A, const S* __restrict__ nb,
+                                          int64_t plane, int nx, int ny, int nz, int64_t pitch,
+                                          int x, int y, int z, S (&hf)[27], S (&hg)[27]) {
+  if constexpr (WALLS == 2) {
+    if (y == 0 || y == ny - 1) {
+      const int64_t nbp = (int64_t)nz * pitch;
+      const int64_t o = (int64_t)(y == 0 ? 0 : 54) * nbp + (int64_t)z * pitch + x;
+#pragma unroll
+      for (int i = 0; i < 27; ++i) {
+        hf[i] = nb[o + i * nbp];
+        hg[i] = nb[o + (27 + i) * nbp];
+      }
+      return;
+    }
+  }
+  gather27<S, (WALLS != 0), PULL>(A, plane, nx, ny, nz, pitch, x, y, z, hf, hg);
+}
+
 // rho = sum f, rho u = sum c f + sF/2, rho E = sum g + (u.sF + sQ)/2 (Sec. II C), then
 // T = (E - u^2/2)/c_v and theta = R T; for the van der Waals fluid (EXT = 2)
 // T = (E - u^2/2 + a rho)/c_v (Eq. lbm_temp) and theta = P/rho. (sF, sQ) as in moments_closure
@@ -189,10 +211,10 @@ __device__ __forceinline__ void collide3(const S (&hf)[27], const S (&hg)[27], c
 // van der Waals fluid 7: h = e + P/rho.
 // With float32 storage the moments already carry the populations' float32 rounding, so float32
 // fields add an error of the same order and halve the field traffic of both sweeps.
-template <typename S, bool WALLS, bool PULL, int EXT>
+template <typename S, int WALLS, bool PULL, int EXT>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
-k_ddf3_flux(const S* __restrict__ A, int nx, int ny, int nz, int64_t pitch, int64_t plane,
-            DdfParams prm, int rows, S* __restrict__ fld) {
+k_ddf3_flux(const S* __restrict__ A, const S* __restrict__ nb, int nx, int ny, int nz,
+            int64_t pitch, int64_t plane, DdfParams prm, int rows, S* __restrict__ fld) {
   const int nbx = gridDim.x;
   const int tile = blockIdx.x + nbx * blockIdx.y;
   const int bx = tile % nbx, by = tile / nbx;
@@ -202,7 +224,7 @@ k_ddf3_flux(const S* __restrict__ A, int nx, int ny, int nz, int64_t pitch, int6
   for (int r = by * rows; r < r_end; ++r) {
     const int y = r % ny, z = r / ny;
     S hf[27], hg[27];
-    gather27<S, WALLS, PULL>(A, plane, nx, ny, nz, pitch, x, y, z, hf, hg);
+    node_pops<S, WALLS, PULL>(A, nb, plane, nx, ny, nz, pitch, x, y, z, hf, hg);
     Moments3 m;
     moments3<EXT>(hf, hg, prm, m, prm.Fx, prm.Fy, prm.Fz, prm.Q);
     const int64_t off = ((int64_t)z * ny + y) * pitch + x;
@@ -223,11 +245,11 @@ k_ddf3_flux(const S* __restrict__ A, int nx, int ny, int nz, int64_t pitch, int6
 // registers and run one wave without spills (at two they spilled 228-252 bytes per lane and
 // took 3368 / 4153 / 4434 us per 256^3 step with sources / transport control / van der Waals,
 // against 2626 / 2909 / 3009 us at one wave).
-template <typename S, int HALO, bool WALLS, bool PULL, bool DIAG, int EXT>
+template <typename S, int HALO, int WALLS, bool PULL, bool DIAG, int EXT>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(EXT == 0 ? 2 : 1)))
-k_ddf3_collide(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int nz,
-               int64_t pitch, int64_t plane, DdfParams prm, const S* __restrict__ fld,
-               int rows, double* __restrict__ partials) {
+k_ddf3_collide(const S* __restrict__ A, const S* __restrict__ nb, S* __restrict__ B, int nx,
+               int ny, int nz, int64_t pitch, int64_t plane, DdfParams prm,
+               const S* __restrict__ fld, int rows, double* __restrict__ partials) {
   const int nbx = gridDim.x;
   const int tile = blockIdx.x + nbx * blockIdx.y;
   const int bx = tile % nbx, by = tile / nbx;
@@ -238,7 +260,7 @@ k_ddf3_collide(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int n
     for (int r = by * rows; r < r_end; ++r) {
       const int y = r % ny, z = r / ny;
       S hf[27], hg[27];
-      gather27<S, WALLS, PULL>(A, plane, nx, ny, nz, pitch, x, y, z, hf, hg);
+      node_pops<S, WALLS, PULL>(A, nb, plane, nx, ny, nz, pitch, x, y, z, hf, hg);
       Moments3 m;
       moments3<EXT>(hf, hg, prm, m, prm.Fx, prm.Fy, prm.Fz, prm.Q);
       const int64_t off = ((int64_t)z * ny + y) * pitch + x;
@@ -418,43 +440,108 @@ static void ext_kind(const DdfParams& prm, Fn&& fn) {
     fn(std::integral_constant<int, 0>{});
 }
 
+// Non-equilibrium extrapolation walls (App. B; the D2Q9 form is k_ddf_neq_rows): the
+// pre-collision populations of the boundary planes B (y = 0 and ny - 1, on the walls) are
+// f^eq(rho_B, u_W, T_W) + f_N - f^eq(rho_N, u_N, T_N), N the neighbouring plane (1, ny - 2)
+// pulled like any fluid node, rho_B = rho_N T_N / T_W (pressure continued to the wall) or rho_N
+// (literal). One thread per (x, z, side); written to nb as node_pops reads it.
+template <typename S, bool PULL>
+__global__ void __launch_bounds__(kBlock)
+k_ddf3_neq_rows(const S* __restrict__ A, int nx, int ny, int nz, int64_t pitch, int64_t plane,
+                DdfParams prm, S* __restrict__ nb) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= 2 * (int64_t)nz * nx) return;
+  const int x = (int)(n % nx);
+  const int64_t t = n / nx;
+  const int z = (int)(t % nz), side = (int)(t / nz);
+  const int N = side ? ny - 2 : 1;
+  S hf[27], hg[27];
+  gather27<S, true, PULL>(A, plane, nx, ny, nz, pitch, x, N, z, hf, hg);
+  Moments3 m;
+  moments3<0>(hf, hg, prm, m, 0.0, 0.0, 0.0, 0.0);
+  const double TW = prm.Tw[side];
+  const double TN = m.theta * prm.inv_R;
+  const double rhoB = prm.neq_literal ? m.rho : m.rho * TN / TW;
+  const double uW[3] = {prm.uw[side][0], prm.uw[side][1], 0.0};
+  Axis X[3], XB[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    axis_eq(m.u[a], m.theta, X[a]);
+    axis_eq(uW[a], prm.R * TW, XB[a]);
+  }
+  const int64_t nbp = (int64_t)nz * pitch;
+  const int64_t o = (int64_t)side * 54 * nbp + (int64_t)z * pitch + x;
+  for (int i = 0; i < 27; ++i) {
+    double feN, geN, feB, geB;
+    equilibria3(m.rho, m.e, i, X, feN, geN);
+    equilibria3(rhoB, prm.cv * TW, i, XB, feB, geB);
+    const double f = (double)hf[i] + prm.wf[i], g = (double)hg[i] + prm.wg[i];
+    nb[o + i * nbp] = (S)(feB + (f - feN) - prm.wf[i]);
+    nb[o + (27 + i) * nbp] = (S)(geB + (g - geN) - prm.wg[i]);
+  }
+}
+
+// The wall type as a template argument: 0 periodic in y, 1 bounce-back, 2 NEQ extrapolation.
+template <typename Fn>
+static void wall_kind(bool walls, const DdfParams& prm, Fn&& fn) {
+  if (!walls)
+    fn(std::integral_constant<int, 0>{});
+  else if (prm.neq)
+    fn(std::integral_constant<int, 2>{});
+  else
+    fn(std::integral_constant<int, 1>{});
+}
+
 template <typename S>
 static void ddf3_step(bool walls, bool pull, const S* A, S* B, const Layout& L, const Grid& G,
-                      const DdfParams& prm, double* fld64, double* partials, hipStream_t s) {
+                      const DdfParams& prm, double* fld64, S* nb, double* partials,
+                      hipStream_t s) {
   dim3 grid(G.nbx, G.nby), block(G.bx);
   S* fld = reinterpret_cast<S*>(fld64);  // 8 planes of the storage type
-  flag(walls, [&](auto W) {
+  if (walls && prm.neq) {
+    const unsigned nblk = (unsigned)((2 * (int64_t)L.nz * L.nx + kBlock - 1) / kBlock);
+    if (pull)
+      k_ddf3_neq_rows<S, true><<<nblk, kBlock, 0, s>>>(A, L.nx, L.ny, L.nz, L.pitch, L.plane, prm, nb);
+    else
+      k_ddf3_neq_rows<S, false><<<nblk, kBlock, 0, s>>>(A, L.nx, L.ny, L.nz, L.pitch, L.plane, prm, nb);
+  }
+  wall_kind(walls, prm, [&](auto W) {
     flag(pull, [&](auto Pl) {
       ext_kind(prm, [&](auto E) {
-        constexpr bool w = decltype(W)::value, pl = decltype(Pl)::value;
-        constexpr int e = decltype(E)::value;
-        // the fields are read only for Phi and for transport control
-        if (prm.phi || (e && prm.full))
-          k_ddf3_flux<S, w, pl, e><<<grid, block, 0, s>>>(A, L.nx, L.ny, L.nz, L.pitch,
-                                                          L.plane, prm, G.rows, fld);
-        flag(partials != nullptr, [&](auto Dg) {
-          constexpr bool dg = decltype(Dg)::value;
-          if (prm.phi == 2)
-            k_ddf3_collide<S, 2, w, pl, dg, e><<<grid, block, 0, s>>>(
-                A, B, L.nx, L.ny, L.nz, L.pitch, L.plane, prm, fld, G.rows, partials);
-          else
-            k_ddf3_collide<S, 1, w, pl, dg, e><<<grid, block, 0, s>>>(
-                A, B, L.nx, L.ny, L.nz, L.pitch, L.plane, prm, fld, G.rows, partials);
-        });
+        constexpr int w = decltype(W)::value, e = decltype(E)::value;
+        constexpr bool pl = decltype(Pl)::value;
+        // the context admits the van der Waals fluid without NEQ walls
+        if constexpr (!(w == 2 && e == 2)) {
+          // the fields are read only for Phi and for transport control
+          if (prm.phi || (e && prm.full))
+            k_ddf3_flux<S, w, pl, e><<<grid, block, 0, s>>>(A, nb, L.nx, L.ny, L.nz, L.pitch,
+                                                            L.plane, prm, G.rows, fld);
+          flag(partials != nullptr, [&](auto Dg) {
+            constexpr bool dg = decltype(Dg)::value;
+            if (prm.phi == 2)
+              k_ddf3_collide<S, 2, w, pl, dg, e><<<grid, block, 0, s>>>(
+                  A, nb, B, L.nx, L.ny, L.nz, L.pitch, L.plane, prm, fld, G.rows, partials);
+            else
+              k_ddf3_collide<S, 1, w, pl, dg, e><<<grid, block, 0, s>>>(
+                  A, nb, B, L.nx, L.ny, L.nz, L.pitch, L.plane, prm, fld, G.rows, partials);
+          });
+        }
       });
     });
   });
 }
 
 hipError_t launch_ddf3(int kind, bool walls, bool pull, const void* A, void* B, const Layout& L,
-                       const Grid& G, const DdfParams& prm, double* fld, double* partials,
-                       hipStream_t s) {
+                       const Grid& G, const DdfParams& prm, double* fld, void* nb,
+                       double* partials, hipStream_t s) {
+  if (prm.neq && (!walls || !nb || L.ny < 3 || prm.eos || prm.src))
+    return hipErrorInvalidValue;
   if (kind == 0)
     ddf3_step<float>(walls, pull, static_cast<const float*>(A), static_cast<float*>(B), L, G,
-                     prm, fld, partials, s);
+                     prm, fld, static_cast<float*>(nb), partials, s);
   else
     ddf3_step<double>(walls, pull, static_cast<const double*>(A), static_cast<double*>(B), L, G,
-                      prm, fld, partials, s);
+                      prm, fld, static_cast<double*>(nb), partials, s);
   return hipGetLastError();
 }
 

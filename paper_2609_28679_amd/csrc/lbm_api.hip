@@ -104,7 +104,7 @@ void sync_sources(lbm_ctx* c) {
 struct Plan {
   int D, Q, kind, planes, codec;
   size_t off_fld;  // D3Q27 double distribution: derivative fields (8 planes of the storage type)
-  size_t off_nb;   // non-equilibrium extrapolation walls: 2 x 18 boundary rows
+  size_t off_nb;   // non-equilibrium extrapolation walls: boundary rows (2D) or planes (3D)
   bool ddf, aa;
   Layout L;
   Grid G;
@@ -154,9 +154,9 @@ int validate(const lbm_params* p, std::string& why) {
   if ((int64_t)p->nx * p->ny * p->nz > (int64_t)1 << 34) { why = "lattice too large"; return LBM_EINVAL; }
   if (p->wall_y < 0 || p->wall_y > 2) { why = "wall_y must be 0, 1 or 2"; return LBM_EINVAL; }
   if (p->wall_y == 2) {
-    if (p->model != LBM_MODEL_DDF || p->lattice != LBM_D2Q9 ||
+    if (p->model != LBM_MODEL_DDF ||
         (p->storage != LBM_STORE_FP32 && p->storage != LBM_STORE_FP64) || p->ny < 3) {
-      why = "non-equilibrium extrapolation walls (wall_y = 2) need the D2Q9 double-distribution model, FP32 or FP64 storage and ny >= 3";
+      why = "non-equilibrium extrapolation walls (wall_y = 2) need the double-distribution model, FP32 or FP64 storage and ny >= 3";
       return LBM_EINVAL;
     }
     for (int side = 0; side < 2; ++side) {
@@ -260,7 +260,9 @@ void make_plan(const lbm_params* p, Plan& P) {
   P.off_fld = off;
   if (P.ddf && P.D == 3) off = align_up(off + (size_t)8 * P.L.plane * P.elem, 256);
   P.off_nb = off;
-  if (p->wall_y == 2) off = align_up(off + (size_t)36 * P.L.pitch * P.elem, 256);
+  // D2Q9: 2 x 18 rows; D3Q27: 2 x 54 planes of nz x pitch
+  if (p->wall_y == 2)
+    off = align_up(off + (size_t)(P.D == 2 ? 36 : 108 * (size_t)P.L.nz) * P.L.pitch * P.elem, 256);
   P.total = off;
 }
 
@@ -461,7 +463,7 @@ int lbm_create(const lbm_params* p, const double* rho0, const double* u0, const 
       if (e == hipSuccess) e = launch_ddf(c->fmt, p->wall_y != 0, false, c->B, c->A, c->L, c->G, c->dp, c->s_enc, c->s_dec, nullptr, c->nb, c->stream);
     } else {
       if (e == hipSuccess) e = launch_init_ddf3(c->kind, c->readout, c->readout + nodes, d_T0, c->B, c->L, c->dp, c->stream);
-      if (e == hipSuccess) e = launch_ddf3(c->kind, p->wall_y != 0, false, c->B, c->A, c->L, c->G, c->dp, c->fld, nullptr, c->stream);
+      if (e == hipSuccess) e = launch_ddf3(c->kind, p->wall_y != 0, false, c->B, c->A, c->L, c->G, c->dp, c->fld, c->nb, nullptr, c->stream);
     }
   } else if (e == hipSuccess && c->codec >= 0) {
     e = launch_init_bgk_red(c->readout, c->readout + nodes, c->A, c->L, c->stream);
@@ -491,7 +493,7 @@ int lbm_step(lbm_ctx* c, int64_t n) {
       if (!c->mlp_set) return fail(c, LBM_ESTATE, "surrogate weights not installed (lbm_set_mlp)");
       e = launch_bgk_d2q9_mlp(c->A, c->B, c->L, c->G, c->omega, c->p.wall_y != 0, c->mlp_w, c->mlp_tol, c->mlp_cnt, part, c->stream);
     } else if (c->ddf && c->D == 3)
-      e = launch_ddf3(c->kind, c->p.wall_y != 0, true, c->A, c->B, c->L, c->G, c->dp, c->fld, part, c->stream);
+      e = launch_ddf3(c->kind, c->p.wall_y != 0, true, c->A, c->B, c->L, c->G, c->dp, c->fld, c->nb, part, c->stream);
     else if (c->ddf)
       e = launch_ddf(c->fmt, c->p.wall_y != 0, true, c->A, c->B, c->L, c->G, c->dp, c->s_enc, c->s_dec, part, c->nb, c->stream);
     else if (c->codec >= 0)

@@ -139,9 +139,11 @@ Grid make_grid_ddf3(const Layout& L);
 hipError_t launch_ddf3_rest_state(const DdfParams& prm, double* out, hipStream_t s);
 hipError_t launch_init_ddf3(int kind, const double* rho, const double* u, const double* T,
                             void* A, const Layout& L, const DdfParams& prm, hipStream_t s);
+// nb: boundary planes of the non-equilibrium extrapolation walls (2 x 54 planes of nz x pitch
+// storage elements; used when prm.neq, NULL otherwise).
 hipError_t launch_ddf3(int kind, bool walls, bool pull, const void* A, void* B, const Layout& L,
-                       const Grid& G, const DdfParams& prm, double* fld, double* partials,
-                       hipStream_t s);
+                       const Grid& G, const DdfParams& prm, double* fld, void* nb,
+                       double* partials, hipStream_t s);
 hipError_t launch_moments_ddf3(int kind, const void* A, const Layout& L, const DdfParams& prm,
                                double* rho, double* u, double* T, double* edens, hipStream_t s);
 // Reduced storage (D2Q9 isothermal): 3 float32 moment planes then 6 uint16 planes.

@@ -212,8 +212,9 @@ def _neq_params(lib, **kw):
     return p
 
 
-@pytest.mark.parametrize("kw", [dict(model=0), dict(storage=1), dict(lattice=1, nz=4),
-                                dict(ny=2), dict(wall_density=2), dict(heat_source=1e-5)])
+@pytest.mark.parametrize("kw", [dict(model=0), dict(storage=1), dict(lattice=1, nz=4, storage=2),
+                                dict(ny=2), dict(lattice=1, nz=4, ny=2), dict(wall_density=2),
+                                dict(heat_source=1e-5), dict(lattice=1, nz=4, heat_source=1e-5)])
 def test_neq_walls_rejected_where_unsupported(lib, kw):
     p = _neq_params(lib, **kw)
     n = ctypes.c_size_t(0)
@@ -224,6 +225,13 @@ def test_neq_walls_validate_wall_state(lib):
     n = ctypes.c_size_t(0)
     p = _neq_params(lib)
     assert lib.lbm_workspace_size(ctypes.byref(p), ctypes.byref(n)) == 0
+    # D3Q27: the boundary planes (2 x 54 of nz x pitch elements) add to the workspace
+    n3, n3w = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    p3 = _neq_params(lib, lattice=1, nz=4)
+    assert lib.lbm_workspace_size(ctypes.byref(p3), ctypes.byref(n3w)) == 0
+    p3.wall_y = 1
+    assert lib.lbm_workspace_size(ctypes.byref(p3), ctypes.byref(n3)) == 0
+    assert n3w.value - n3.value >= 108 * 4 * p3.nx * 4
     p.wall_T[1] = 0.0
     assert lib.lbm_workspace_size(ctypes.byref(p), ctypes.byref(n)) == binding.LBM_EINVAL
     p = _neq_params(lib)

@@ -84,3 +84,59 @@ def test_thermal_couette(storage, prandtl, tol):
     assert err <= tol
     assert np.abs(tg - tg[:, :1]).max() <= 1e-12  # uniform in x
     assert np.abs(ug[0][:, 0] - U * y).max() <= 1e-3 * U
+
+
+# ---- D3Q27: the boundary planes y = 0, ny - 1 rebuilt by k_ddf3_neq_rows --------------------
+@pytest.mark.parametrize("density", ["pressure", "literal"])
+@pytest.mark.parametrize("phi", [1, 0])
+def test_d3q27_fp64_matches_oracle(phi, density):
+    shape, steps, tau = (5, 7, 9), 5, 0.7
+    announce("D3Q27 DDF NEQ walls fp64 %s phi=%d density=%s %d steps" % (shape, phi, density,
+                                                                        steps))
+    rng = np.random.default_rng(60 + phi)
+    T = 0.9 + 0.03 * rng.standard_normal(shape)
+    rho = P0 / (R * T) * (1 + 0.01 * rng.standard_normal(shape))
+    u = 0.02 * rng.standard_normal((3,) + shape)
+    walls = dict(u=((0.0, 0.0), (0.05, 0.0)), T=(0.88, 0.93), density=density)
+    lat = _lattice(rho, u, T, walls, lattice="D3Q27", tau=tau, phi=phi, storage="fp64",
+                   prandtl=0.8)
+    lat.step(steps)
+    rg, ug, tg, _ = lat.moments()
+    fg, gg = lat.populations()
+    lat.close()
+    gas = ddf.Gas(R, CV, (tau - 0.5) * P0, prandtl=0.8)
+    w = ddf.NeqWalls((0.0, 0.0, 0.0), 0.88, (0.05, 0.0, 0.0), 0.93, density=density)
+    f, g = ddf.run(*ddf.init_equilibrium(rho, u, T, gas), gas, steps, phi_on=phi > 0,
+                   stencil=STENCIL[phi], neq=w)
+    ro, uo, to = ddf.temperature(f, g, gas)
+    assert np.abs(rg - ro).max() <= 1e-13
+    assert np.abs(ug - uo).max() <= 1e-13
+    assert np.abs(tg - to).max() <= 1e-13
+    ft, gt = ddf.collide(f, g, gas, True, phi > 0, STENCIL[phi])
+    assert np.abs(fg - ft).max() <= 1e-13
+    assert np.abs(gg - gt).max() <= 1e-13
+
+
+@pytest.mark.parametrize("storage,tol", [("fp64", 1e-5), ("fp32", 1e-4)])
+def test_d3q27_thermal_couette(storage, tol):
+    # the Couette set-up of test_thermal_couette on a D3Q27 lattice two planes deep (Pr = 1)
+    ny, nx, nz, tau, U, TC, dT = 33, 8, 2, 1.0, 0.1, 1.0, 0.02
+    announce("D3Q27 DDF NEQ thermal Couette ny=%d %s" % (ny, storage))
+    L = ny - 1
+    y = np.arange(ny) / L
+    T = (TC + dT * y)[None, :, None] * np.ones((nz, 1, nx))
+    u = np.zeros((3, nz, ny, nx))
+    u[0] = (U * y)[None, :, None]
+    walls = dict(u=((0.0, 0.0), (U, 0.0)), T=(TC, TC + dT))
+    lat = _lattice(P0 / (R * T), u, T, walls, lattice="D3Q27", tau=tau, phi=1, storage=storage)
+    nu = (tau - 0.5) * P0 / (P0 / R)
+    lat.step(int(16 * L * L / (np.pi ** 2 * nu)))
+    _, ug, tg, _ = lat.moments()
+    lat.close()
+    Ec = U * U / ((CV + R) * dT)
+    exact = TC + dT * (y + Ec / 2 * y * (1 - y))
+    prof = tg[0, :, 0]
+    err = np.sqrt(((prof - exact) ** 2).sum() / ((exact - TC) ** 2).sum())
+    assert err <= tol
+    assert np.abs(tg - tg[:1, :, :1]).max() <= 1e-12  # uniform in x and z
+    assert np.abs(ug[0][0, :, 0] - U * y).max() <= 1e-3 * U

@@ -461,6 +461,31 @@ def test_d3q27_z_uniform_van_der_waals_run_reproduces_d2q9():
     assert dev > 1e-9
 
 
+@pytest.mark.parametrize("density", ["pressure", "literal"])
+def test_d3q27_z_uniform_neq_walls_run_reproduces_d2q9(density):
+    # the non-equilibrium extrapolation walls (App. B) on the planes y = 0, ny - 1 of a z-uniform
+    # D3Q27 field reduce to the D2Q9 walls: the rebuild is linear in f_N, f^eq's z-marginal is
+    # the D2Q9 f^eq at u_z = 0, and rho_B, T_N are the same local moments; Pr = 0.8 (q^c on)
+    gas = ddf.Gas(R, CV, 0.2 * P0, prandtl=0.8)
+    rho2, u2, T2 = _fields3((7, 6), seed=9)
+    u2 = u2[:2]
+    nz = 3
+    rho3 = np.repeat(rho2[None], nz, axis=0)
+    T3 = np.repeat(T2[None], nz, axis=0)
+    u3 = np.zeros((3, nz) + rho2.shape)
+    u3[:2] = u2[:, None]
+    w2 = ddf.NeqWalls((0.0, 0.0), 0.88, (0.05, 0.0), 0.93, density=density)
+    w3 = ddf.NeqWalls((0.0, 0.0, 0.0), 0.88, (0.05, 0.0, 0.0), 0.93, density=density)
+    f2, g2 = ddf.run(*ddf.init_equilibrium(rho2, u2, T2, gas), gas, 5, neq=w2)
+    f3, g3 = ddf.run(*ddf.init_equilibrium(rho3, u3, T3, gas), gas, 5, neq=w3)
+    from oracle.lattice import velocities
+    c3 = velocities(3)
+    for i2, c in enumerate([tuple(c) for c in velocities(2)]):
+        sel = [i for i, cc in enumerate(c3) if (cc[0], cc[1]) == c]
+        np.testing.assert_allclose(f3[sel].sum(axis=0)[1], f2[i2], rtol=0, atol=1e-14)
+        np.testing.assert_allclose(g3[sel].sum(axis=0)[1], g2[i2], rtol=0, atol=1e-14)
+
+
 @pytest.mark.parametrize("walls", [True, False])
 def test_d3q27_conservation(walls):
     # mass and energy are conserved with or without the bounce-back walls; momentum only on
