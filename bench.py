@@ -295,6 +295,14 @@ def main():
                 max(50, vs // 20), 5, 432,
                 {"phi": "central", "launches": "2 per step (fluxes, collision)",
                  "eos": "van der Waals a = 0.27, b = 0.2, rho 1, T 1.4"})),
+            ("d3q27_ddf_fp32_256_neq_walls", lambda n: variant(
+                n, lambda: binding.Lattice(*inputs.thermal_taylor_green_3d(256, 0.05),
+                                           lattice="D3Q27", model="ddf", tau=0.6, phi=1,
+                                           neq_walls=dict(u=((-0.05, 0.0), (0.05, 0.0)),
+                                                          T=(0.8, 1.0))),
+                max(50, vs // 20), 5, 432,
+                {"phi": "central", "launches": "3 per step (boundary planes, fluxes, collision)",
+                 "walls": "y, non-equilibrium extrapolation (u_W = -+0.05, T_W = 0.8 / 1.0)"})),
             ("d2q9_ddf_fp32_4096_upwind", lambda n: variant(
                 n, lambda: ddf_lattice("fp32", phi=2), max(100, vs // 4), 10, 144,
                 {"walls": "y", "phi": "upwind"})),

@@ -72,9 +72,10 @@ typedef struct {
   int32_t collision; /* LBM_COLLIDE_*; MLP: D2Q9 BGK with FP32 storage only */
   int32_t nx, ny, nz; /* lattice size in nodes; nz = 1 for D2Q9; each >= 1 (nx, ny >= 3) */
   int32_t wall_y;     /* 0: periodic in y; 1: half-way bounce-back walls at y = -1/2 and ny-1/2;
-                         2 (DDF, D2Q9, FP32/FP64, ny >= 3, no sources): non-equilibrium
-                         extrapolation walls on the rows y = 0 and y = ny-1 with the velocities
-                         wall_u and temperatures wall_T (App. B, thermal Couette) */
+                         2 (DDF, D2Q9 or D3Q27, FP32/FP64, ny >= 3, ideal gas, no sources):
+                         non-equilibrium extrapolation walls on the rows (D2Q9) or planes
+                         (D3Q27) y = 0 and y = ny-1 with the velocities wall_u and temperatures
+                         wall_T (App. B, thermal Couette) */
   double tau;  /* BGK: tau_LB = 1/(2 beta) > 1/2, so nu = (tau - 1/2)/3.
                   DDF: the same value at the reference pressure P0 = 1/3 defines the dynamic
                   viscosity mu = (tau - 1/2) P0; per node tau_kin = mu / P (Sec. II A). */
@@ -97,11 +98,11 @@ typedef struct {
                           FP32/FP64 storage. */
   int32_t eos;         /* DDF equation of state: 0 = ideal gas (Sec. III A), 1 = van der Waals
                           P = rho R T / (1 - b rho) - a rho^2 with e = c_v T - a rho (Sec. III C);
-                          van der Waals: D2Q9 or D3Q27, FP32/FP64 storage, wall_y 0 or 1. Its alpha and
-                          q^c are per node (k/mu = (c_v + R) / prandtl). */
+                          van der Waals: D2Q9 or D3Q27, FP32/FP64 storage, wall_y 0 or 1.
+                          Its alpha and q^c are per node (k/mu = (c_v + R) / prandtl). */
   double vdw_a, vdw_b; /* van der Waals a >= 0, b >= 0 (lattice units); 1 - b rho > 0 */
   double wall_u[2][3]; /* wall_y = 2: wall velocity [bottom (y = 0), top (y = ny-1)][x, y, z];
-                          the normal component must be 0 */
+                          tangential along x: the y and z components must be 0 */
   double wall_T[2];    /* wall_y = 2: wall temperatures [bottom, top], > 0 */
   int32_t wall_density; /* wall_y = 2: boundary density rho_B; 0 (default) = rho_N T_N / T_W
                           (the neighbour's pressure continued to the wall), 1 = rho_N (the

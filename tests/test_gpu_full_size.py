@@ -155,6 +155,39 @@ def _ddf3_nodes(f_post, g_post, f_next, g_next, gas, n, seed):
         assert _close(g_next[:, z, y, x], gt[:, 2, 2, 2]), (z, y, x)
 
 
+def test_ddf3_256_neq_walls():
+    n = 256
+    announce("D3Q27 DDF 256^3 fp32 NEQ walls (bench configuration): one step at sampled nodes "
+             "next to and on the walls")
+    rho, u, T = inputs.thermal_taylor_green_3d(n, 0.05)
+    lat = _lattice(rho, u, T, lattice="D3Q27", model="ddf", tau=0.6, phi=1,
+                   neq_walls=dict(u=((-0.05, 0.0), (0.05, 0.0)), T=(0.8, 1.0)))
+    (f_post, g_post), (f_next, g_next) = _two_snapshots(lat, 5)
+    gas = ddf.Gas(R, CV, 0.1 * P0)
+    walls = ddf.NeqWalls((-0.05, 0.0, 0.0), 0.8, (0.05, 0.0, 0.0), 1.0)
+    # a 5 x 5 column of planes y = 0..4 and y = n-5..n-1 around (z, x), periodic in z and x: the
+    # boundary planes are rebuilt from planes 1 and n-2, and planes 0, 1, n-2, n-1 reach only
+    # planes inside their own block (the junction between the blocks is never read)
+    ys = np.r_[0:5, n - 5:n]
+    for z, x in ((0, 0), (131, 255), (7, 64)):
+        iz = [(z + d) % n for d in range(-2, 3)]
+        ix = [(x + d) % n for d in range(-2, 3)]
+        blocks = []
+        for lo in (0, n - 5):
+            idx = np.ix_(iz, list(range(lo, lo + 5)), ix)
+            fb = np.stack([f_post[i][idx] for i in range(27)])
+            gb = np.stack([g_post[i][idx] for i in range(27)])
+            blocks.append((bgk.stream(fb), bgk.stream(gb)))
+        fs = np.concatenate([b[0] for b in blocks], axis=2)
+        gs = np.concatenate([b[1] for b in blocks], axis=2)
+        fs, gs = ddf.apply_neq_walls(fs, gs, gas, walls)
+        ft, gt = ddf.collide(fs, gs, gas, True, True, "central")
+        for k in (0, 1, 8, 9):
+            y = ys[k]
+            assert _close(f_next[:, z, y, x], ft[:, 2, k, 2]), (z, y, x)
+            assert _close(g_next[:, z, y, x], gt[:, 2, k, 2]), (z, y, x)
+
+
 def test_ddf3_256():
     n = 256
     announce("D3Q27 DDF 256^3 fp32 periodic (bench configuration): one step at sampled nodes")
