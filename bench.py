@@ -289,6 +289,20 @@ def main():
                                            lattice="D3Q27", model="ddf", tau=0.6, phi=1),
                 max(50, vs // 20), 5, 432,
                 {"phi": "central", "launches": "2 per step (fluxes, collision)"})),
+            ("d3q27_ddf_fp32_256_sources", lambda n: variant(
+                n, lambda: binding.Lattice(*inputs.thermal_taylor_green_3d(256, 0.05),
+                                           lattice="D3Q27", model="ddf", tau=0.6, phi=1,
+                                           force=(1e-7, 0.0, 0.0), heat_source=1e-8),
+                max(50, vs // 20), 5, 432,
+                {"phi": "central", "launches": "2 per step (fluxes, collision)",
+                 "sources": "uniform force (1e-7, 0, 0) and heat source 1e-8"})),
+            ("d3q27_ddf_fp32_256_prandtl", lambda n: variant(
+                n, lambda: binding.Lattice(*inputs.thermal_taylor_green_3d(256, 0.05),
+                                           lattice="D3Q27", model="ddf", tau=0.6, phi=1,
+                                           prandtl=0.71, eta_over_mu=1.0),
+                max(50, vs // 20), 5, 432,
+                {"phi": "central", "launches": "2 per step (fluxes, collision)",
+                 "transport": "Pr 0.71 (heat flux q^c), eta/mu 1 (alpha theta div u)"})),
             ("d3q27_ddf_fp32_256_vdw", lambda n: variant(
                 n, lambda: binding.Lattice(*vdw_tgv3(), lattice="D3Q27", model="ddf", tau=0.6,
                                            phi=1, vdw=(0.27, 0.2)),

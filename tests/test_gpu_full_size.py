@@ -129,6 +129,23 @@ def test_ddf_4096_neq_walls():
     _ddf_rows(f_post, g_post, f_next, g_next, gas, (2047,))
 
 
+@pytest.mark.parametrize("case", ["sources", "transport"])
+def test_ddf3_256_extended(case):
+    n = 256
+    announce("D3Q27 DDF 256^3 fp32 periodic, %s (bench configuration): one step at sampled "
+             "nodes" % case)
+    rho, u, T = inputs.thermal_taylor_green_3d(n, 0.05)
+    if case == "sources":
+        kw, F, Q = dict(force=(1e-7, 0.0, 0.0), heat_source=1e-8), np.array([1e-7, 0.0, 0.0]), 1e-8
+        gas = ddf.Gas(R, CV, 0.1 * P0)
+    else:
+        kw, F, Q = dict(prandtl=0.71, eta_over_mu=1.0), None, 0.0
+        gas = ddf.Gas(R, CV, 0.1 * P0, prandtl=0.71, eta_over_mu=1.0)
+    lat = _lattice(rho, u, T, lattice="D3Q27", model="ddf", tau=0.6, phi=1, **kw)
+    (f_post, g_post), (f_next, g_next) = _two_snapshots(lat, 5)
+    _ddf3_nodes(f_post, g_post, f_next, g_next, gas, n, seed=5, F=F, Q=Q)
+
+
 def test_ddf3_256_vdw():
     n = 256
     announce("D3Q27 DDF 256^3 fp32 periodic, van der Waals fluid (bench configuration): one "
@@ -141,7 +158,7 @@ def test_ddf3_256_vdw():
     _ddf3_nodes(f_post, g_post, f_next, g_next, gas, n, seed=4)
 
 
-def _ddf3_nodes(f_post, g_post, f_next, g_next, gas, n, seed):
+def _ddf3_nodes(f_post, g_post, f_next, g_next, gas, n, seed, F=None, Q=0.0):
     """Sampled nodes of a periodic D3Q27 double-distribution step, each from its 5^3
     neighbourhood streamed and collided as a periodic box (its centre is exact)."""
     rng = np.random.default_rng(seed)
@@ -150,7 +167,8 @@ def _ddf3_nodes(f_post, g_post, f_next, g_next, gas, n, seed):
         idx = np.ix_(*[[(c + d) % n for d in range(-2, 3)] for c in (z, y, x)])
         fb = np.stack([f_post[i][idx] for i in range(27)])
         gb = np.stack([g_post[i][idx] for i in range(27)])
-        ft, gt = ddf.collide(bgk.stream(fb), bgk.stream(gb), gas, False, True, "central")
+        ft, gt = ddf.collide(bgk.stream(fb), bgk.stream(gb), gas, False, True, "central", F=F,
+                             Q=Q)
         assert _close(f_next[:, z, y, x], ft[:, 2, 2, 2]), (z, y, x)
         assert _close(g_next[:, z, y, x], gt[:, 2, 2, 2]), (z, y, x)
 
