@@ -1,11 +1,16 @@
-// Double-distribution (f, g) stream-collide step for D3Q27, ideal gas, float32 or float64
-// storage: Eq. (LBM_f) and Eq. (LBM_g) of Sec. II C in the order of Fig. 1, with the optional
-// body force, heat source and transport control of the D2Q9 kernel (ddf.hip).
+// Double-distribution (f, g) stream-collide step for D3Q27, float32 or float64 storage:
+// Eq. (LBM_f) and Eq. (LBM_g) of Sec. II C in the order of Fig. 1, for the ideal gas or the
+// van der Waals fluid (Sec. III C), with the optional body force, heat source and transport
+// control of the D2Q9 kernel (ddf.hip).
 //
-// Two launches per step:
+// Two launches per step (three with NEQ walls):
+//   k_ddf3_neq_rows rebuilds the pre-collision populations of the boundary planes y = 0 and
+//                   y = ny - 1 of the non-equilibrium extrapolation walls (App. B) into a side
+//                   buffer;
 //   k_ddf3_flux     pulls the 27 + 27 populations of every node, computes its moments and
 //                   writes the Galilean-correction fluxes phi_a = rho u_a (u_a^2 + 3 (theta - 1/3))
-//                   (and, with transport control, T and u) to a float64 field;
+//                   (and, with transport control, T and u; for the van der Waals fluid also the
+//                   enthalpy) to fields in the storage type;
 //   k_ddf3_collide  pulls the same populations again, recomputes the same moments, takes the
 //                   finite-difference derivatives of the neighbours' fields (central, or the
 //                   upwind-biased stencil for phi), collides and stores.
@@ -15,8 +20,8 @@
 // LDS; in 3D a node's derivative stencil spans three planes, which a one-row tile cannot hold.
 //
 // Storage: 54 planes, f_i - w_i (i < 27) then g_i - v_i, with w, v the equilibria at rest at
-// rho = 1, T = 1; i = (cx+1) + 3(cy+1) + 9(cz+1), opposite 26 - i. Walls: half-way bounce-back
-// at the y ends; x and z periodic. Arithmetic is float64.
+// rho = 1, T = 1; i = (cx+1) + 3(cy+1) + 9(cz+1), opposite 26 - i. Walls in y: half-way
+// bounce-back or NEQ extrapolation; x and z periodic. Arithmetic is float64.
 #include "ddf_common.h"
 
 #include <type_traits>
