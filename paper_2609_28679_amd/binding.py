@@ -121,8 +121,8 @@ class Lattice:
     rho0: (ny, nx) or (nz, ny, nx) float64; u0: (D,) + that shape; T0 for the DDF model;
     force: uniform body force (D components) or None; heat_source: uniform heat source Q,
     prandtl: Prandtl number, eta_over_mu: bulk viscosity ratio (< 0: Navier-Stokes value),
-    neq_walls: non-equilibrium extrapolation walls on the first and last rows,
-    dict(u=((ux, uy), (ux, uy)), T=(T_bottom, T_top), density="pressure"|"literal"),
+    neq_walls: non-equilibrium extrapolation walls on the first and last rows (D3Q27: planes)
+    in y, dict(u=((ux, uy), (ux, uy)), T=(T_bottom, T_top), density="pressure"|"literal"),
     vdw: (a, b) for a van der Waals fluid (double-distribution model).
     The context workspace is a torch uint8 tensor on the current device; launches go on
     torch's current stream.

@@ -74,8 +74,9 @@ struct DdfParams {
   double va = 0.0, vb = 0.0, eta = 0.0, kmu = 0.0;
   // the kernels take the extended path (shifted state with sources and/or transport terms)
   bool ext() const { return src || full; }
-  // non-equilibrium extrapolation walls (D2Q9, rows 0 and ny-1 on the walls): wall velocity
-  // uw[side][axis] and temperature Tw[side] (side 0: y = 0, 1: y = ny - 1); neq_literal selects
+  // non-equilibrium extrapolation walls (rows, in D3Q27 planes, y = 0 and ny-1 on the walls):
+  // wall velocity uw[side][axis] (x, y; z is 0) and temperature Tw[side] (side 0: y = 0,
+  // 1: y = ny - 1); neq_literal selects
   // rho_B = rho_N instead of rho_N T_N / T_W
   int neq = 0, neq_literal = 0;
   double uw[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
