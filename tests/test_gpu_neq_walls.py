@@ -140,3 +140,32 @@ def test_d3q27_thermal_couette(storage, tol):
     assert err <= tol
     assert np.abs(tg - tg[:1, :, :1]).max() <= 1e-12  # uniform in x and z
     assert np.abs(ug[0][0, :, 0] - U * y).max() <= 1e-3 * U
+
+
+def test_d3q27_diagnostics_history():
+    # the diagnostics instantiation of the D3Q27 kernels with NEQ walls: the float64 totals of
+    # every step (the walls exchange mass, momentum and energy) against the oracle's state
+    shape, steps, tau = (6, 7, 9), 4, 0.7
+    announce("D3Q27 DDF NEQ walls fp64 %s diagnostics every step" % (shape,))
+    rng = np.random.default_rng(65)
+    T = 0.9 + 0.03 * rng.standard_normal(shape)
+    rho = P0 / (R * T) * (1 + 0.01 * rng.standard_normal(shape))
+    u = 0.02 * rng.standard_normal((3,) + shape)
+    walls = dict(u=((0.0, 0.0), (0.05, 0.0)), T=(0.88, 0.93))
+    lat = _lattice(rho, u, T, walls, lattice="D3Q27", tau=tau, phi=1, storage="fp64",
+                   prandtl=0.8, diag_every=1)
+    lat.step(steps)
+    h = lat.diag_history()
+    lat.close()
+    assert h.shape[0] == steps
+    gas = ddf.Gas(R, CV, (tau - 0.5) * P0, prandtl=0.8)
+    w = ddf.NeqWalls((0.0, 0.0, 0.0), 0.88, (0.05, 0.0, 0.0), 0.93)
+    f, g = ddf.init_equilibrium(rho, u, T, gas)
+    for t in range(1, steps + 1):
+        f, g = ddf.run(f, g, gas, 1, neq=w)
+        ro, uo, to = ddf.temperature(f, g, gas)
+        want = [ro.sum()] + [(ro * uo[a]).sum() for a in range(3)] + \
+               [(ro * (CV * to + 0.5 * (uo ** 2).sum(axis=0))).sum()]
+        row = h[t - 1]
+        assert row[0] == t
+        assert np.abs(row[1:] - np.array(want)).max() <= 1e-12 * ro.sum(), t
