@@ -267,8 +267,9 @@ def collide(f, g, gas, walls_y, phi_on=True, stencil="central", F=None, Q=0.0):
 
 class NeqWalls:
     """Non-equilibrium extrapolation walls (App. B, thermal Couette): the first and last rows
-    (y = 0 and y = ny - 1) are boundary nodes B on the walls, with wall velocities u_lo, u_hi
-    (D components) and temperatures T_lo, T_hi; N is the neighbouring row (1 or ny - 2).
+    (D2Q9) or planes (D3Q27) y = 0 and y = ny - 1 are boundary nodes B on the walls, with wall
+    velocities u_lo, u_hi (D components) and temperatures T_lo, T_hi; N is the neighbouring row
+    or plane (1 or ny - 2).
     density="pressure" (the default reading) takes rho_B = rho_N T_N / T_W, the density that
     continues the pressure P_N = rho_N R T_N to the wall; density="literal" takes rho_B = rho_N,
     the paper's extrapolation written out (the two agree where T_N = T_W)."""
