@@ -102,7 +102,7 @@ typedef struct {
                           Its alpha and q^c are per node (k/mu = (c_v + R) / prandtl). */
   double vdw_a, vdw_b; /* van der Waals a >= 0, b >= 0 (lattice units); 1 - b rho > 0 */
   double wall_u[2][3]; /* wall_y = 2: wall velocity [bottom (y = 0), top (y = ny-1)][x, y, z];
-                          tangential along x: the y and z components must be 0 */
+                          tangential: y component 0; z component 0 in D2Q9 */
   double wall_T[2];    /* wall_y = 2: wall temperatures [bottom, top], > 0 */
   int32_t wall_density; /* wall_y = 2: boundary density rho_B; 0 (default) = rho_N T_N / T_W
                           (the neighbour's pressure continued to the wall), 1 = rho_N (the

@@ -122,7 +122,8 @@ class Lattice:
     force: uniform body force (D components) or None; heat_source: uniform heat source Q,
     prandtl: Prandtl number, eta_over_mu: bulk viscosity ratio (< 0: Navier-Stokes value),
     neq_walls: non-equilibrium extrapolation walls on the first and last rows (D3Q27: planes)
-    in y, dict(u=((ux, uy), (ux, uy)), T=(T_bottom, T_top), density="pressure"|"literal"),
+    in y, dict(u=((ux, uy[, uz]), (ux, uy[, uz])), T=(T_bottom, T_top),
+    density="pressure"|"literal"); the velocities are tangential (uy = 0; uz only in D3Q27),
     vdw: (a, b) for a van der Waals fluid (double-distribution model).
     The context workspace is a torch uint8 tensor on the current device; launches go on
     torch's current stream.

@@ -467,7 +467,7 @@ k_ddf3_neq_rows(const S* __restrict__ A, int nx, int ny, int nz, int64_t pitch, 
   const double TW = prm.Tw[side];
   const double TN = m.theta * prm.inv_R;
   const double rhoB = prm.neq_literal ? m.rho : m.rho * TN / TW;
-  const double uW[3] = {prm.uw[side][0], prm.uw[side][1], 0.0};
+  const double uW[3] = {prm.uw[side][0], prm.uw[side][1], prm.uw[side][2]};
   Axis X[3], XB[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {

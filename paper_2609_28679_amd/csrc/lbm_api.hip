@@ -159,11 +159,14 @@ int validate(const lbm_params* p, std::string& why) {
       why = "non-equilibrium extrapolation walls (wall_y = 2) need the double-distribution model, FP32 or FP64 storage and ny >= 3";
       return LBM_EINVAL;
     }
+    // tangential wall velocities: along x (D2Q9), along x and z (D3Q27)
+    const bool d3 = p->lattice == LBM_D3Q27;
     for (int side = 0; side < 2; ++side) {
-      const double T = p->wall_T[side], ux = p->wall_u[side][0];
-      if (!(T > 0.0) || !std::isfinite(T) || !std::isfinite(ux) || p->wall_u[side][1] != 0.0 ||
-          p->wall_u[side][2] != 0.0 || !admissible(p->R * T, ux) || !admissible(p->R * T, 0.0)) {
-        why = "wall_T must be positive and wall_u tangential (x only) and admissible";
+      const double T = p->wall_T[side], ux = p->wall_u[side][0], uz = p->wall_u[side][2];
+      if (!(T > 0.0) || !std::isfinite(T) || !std::isfinite(ux) || !std::isfinite(uz) ||
+          p->wall_u[side][1] != 0.0 || (!d3 && uz != 0.0) || !admissible(p->R * T, ux) ||
+          !admissible(p->R * T, uz) || !admissible(p->R * T, 0.0)) {
+        why = "wall_T must be positive and wall_u tangential (x; x and z in D3Q27) and admissible";
         return LBM_EINVAL;
       }
     }
@@ -369,8 +372,7 @@ int lbm_create(const lbm_params* p, const double* rho0, const double* u0, const 
     c->dp.neq = 1;
     c->dp.neq_literal = p->wall_density;
     for (int side = 0; side < 2; ++side) {
-      c->dp.uw[side][0] = p->wall_u[side][0];
-      c->dp.uw[side][1] = p->wall_u[side][1];
+      for (int a = 0; a < 3; ++a) c->dp.uw[side][a] = p->wall_u[side][a];
       c->dp.Tw[side] = p->wall_T[side];
     }
   }

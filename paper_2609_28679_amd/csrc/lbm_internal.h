@@ -75,11 +75,11 @@ struct DdfParams {
   // the kernels take the extended path (shifted state with sources and/or transport terms)
   bool ext() const { return src || full; }
   // non-equilibrium extrapolation walls (rows, in D3Q27 planes, y = 0 and ny-1 on the walls):
-  // wall velocity uw[side][axis] (x, y; z is 0) and temperature Tw[side] (side 0: y = 0,
-  // 1: y = ny - 1); neq_literal selects
-  // rho_B = rho_N instead of rho_N T_N / T_W
+  // wall velocity uw[side][axis] (x, y, z; y is 0, z is 0 in D2Q9) and temperature Tw[side]
+  // (side 0: y = 0, 1: y = ny - 1); neq_literal selects rho_B = rho_N instead of
+  // rho_N T_N / T_W
   int neq = 0, neq_literal = 0;
-  double uw[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+  double uw[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
   double Tw[2] = {1.0, 1.0};
   // storage shift: f^eq and g^eq at rest at the reference state rho = 1, T = 1 (computed by
   // launch_ddf_rest_state / launch_ddf3_rest_state on the device at context creation; the

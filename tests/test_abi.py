@@ -240,6 +240,14 @@ def test_neq_walls_validate_wall_state(lib):
     p = _neq_params(lib)
     p.wall_u[1][0] = 0.9  # inadmissible product-form factors at the wall
     assert lib.lbm_workspace_size(ctypes.byref(p), ctypes.byref(n)) == binding.LBM_EINVAL
+    p = _neq_params(lib)
+    p.wall_u[0][2] = 0.02  # a z velocity: D3Q27 only
+    assert lib.lbm_workspace_size(ctypes.byref(p), ctypes.byref(n)) == binding.LBM_EINVAL
+    p = _neq_params(lib, lattice=1, nz=4)
+    p.wall_u[0][2] = 0.02
+    assert lib.lbm_workspace_size(ctypes.byref(p), ctypes.byref(n)) == 0
+    p.wall_u[0][2] = 0.9
+    assert lib.lbm_workspace_size(ctypes.byref(p), ctypes.byref(n)) == binding.LBM_EINVAL
 
 
 @pytest.mark.parametrize("kw", [dict(eos=2), dict(eos=1), dict(eos=1, model=1, wall_y=2),

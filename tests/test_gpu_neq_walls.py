@@ -117,6 +117,33 @@ def test_d3q27_fp64_matches_oracle(phi, density):
     assert np.abs(gg - gt).max() <= 1e-13
 
 
+def test_d3q27_fp64_tangential_wall_velocities_in_x_and_z():
+    shape, steps, tau = (6, 7, 5), 5, 0.7
+    announce("D3Q27 DDF NEQ walls fp64 %s, wall velocities along x and z" % (shape,))
+    rng = np.random.default_rng(66)
+    T = 0.9 + 0.03 * rng.standard_normal(shape)
+    rho = P0 / (R * T) * (1 + 0.01 * rng.standard_normal(shape))
+    u = 0.02 * rng.standard_normal((3,) + shape)
+    uw = ((0.02, 0.0, -0.03), (0.05, 0.0, 0.01))
+    walls = dict(u=uw, T=(0.88, 0.93))
+    lat = _lattice(rho, u, T, walls, lattice="D3Q27", tau=tau, phi=1, storage="fp64",
+                   prandtl=0.8)
+    lat.step(steps)
+    rg, ug, tg, _ = lat.moments()
+    fg, gg = lat.populations()
+    lat.close()
+    gas = ddf.Gas(R, CV, (tau - 0.5) * P0, prandtl=0.8)
+    w = ddf.NeqWalls(uw[0], 0.88, uw[1], 0.93)
+    f, g = ddf.run(*ddf.init_equilibrium(rho, u, T, gas), gas, steps, neq=w)
+    ro, uo, to = ddf.temperature(f, g, gas)
+    assert np.abs(rg - ro).max() <= 1e-13
+    assert np.abs(ug - uo).max() <= 1e-13
+    assert np.abs(tg - to).max() <= 1e-13
+    ft, gt = ddf.collide(f, g, gas, True, True, "central")
+    assert np.abs(fg - ft).max() <= 1e-13
+    assert np.abs(gg - gt).max() <= 1e-13
+
+
 @pytest.mark.parametrize("storage,tol", [("fp64", 1e-5), ("fp32", 1e-4)])
 def test_d3q27_thermal_couette(storage, tol):
     # the Couette set-up of test_thermal_couette on a D3Q27 lattice two planes deep (Pr = 1)
