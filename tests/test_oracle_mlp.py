@@ -100,6 +100,46 @@ def test_adam_first_step_closed_form():
     np.testing.assert_allclose(q, p[0] - 1e-3 * g[0] / (np.abs(g[0]) + 1e-8), rtol=1e-15)
 
 
+def test_adam_constant_gradient_steps_closed_form():
+    # A constant gradient g gives m_t = (1 - b1^t) g and v_t = (1 - b2^t) g^2, so the
+    # bias-corrected moments are g and g^2 at every t and each step moves a parameter by
+    # exactly lr g / (|g| + eps). A wrong bias-correction power (or a missing correction)
+    # breaks this from t = 2 on.
+    lr, eps = 2e-3, 1e-8
+    g = np.array([0.5, -1e-3, 3e-7, -40.0])
+    p0 = np.array([1.0, -2.0, 3.0, 0.25])
+    opt = mlp.Adam(lr=lr, eps=eps)
+    p = [p0.copy()]
+    step = lr * g / (np.abs(g) + eps)
+    for t in range(1, 6):
+        before = p[0].copy()
+        p = opt.step(p, [g.copy()])
+        np.testing.assert_allclose(before - p[0], step, rtol=1e-12, atol=0)
+        np.testing.assert_allclose(p[0], p0 - t * step, rtol=1e-13)
+    # the two moment estimates themselves
+    np.testing.assert_allclose(opt.m[0], (1 - 0.9 ** 5) * g, rtol=1e-14)
+    np.testing.assert_allclose(opt.v[0], (1 - 0.999 ** 5) * g * g, rtol=1e-12)
+
+
+def test_adam_zero_gradient_after_one_step_decays_geometrically():
+    # g_1 = g, then g_t = 0: m_t = b1^(t-1) (1 - b1) g and v_t = b2^(t-1) (1 - b2) g^2, so for
+    # |g| >> eps the step at t is lr (b1 / sqrt(b2))^(t-1) sqrt(1 - b2^t) / (1 - b1^t)
+    # * (1 - b1) / sqrt(1 - b2) * sign(g): a ratio of 0.9 / sqrt(0.999) between late steps.
+    lr = 1e-3
+    g = np.array([2.0, -3.0])
+    opt = mlp.Adam(lr=lr, eps=0.0)
+    p = [np.zeros(2)]
+    steps = []
+    for t in range(1, 8):
+        before = p[0].copy()
+        p = opt.step(p, [g if t == 1 else np.zeros(2)])
+        steps.append(before - p[0])
+    for t, d in enumerate(steps, start=1):
+        exp = lr * (0.9 / np.sqrt(0.999)) ** (t - 1) * np.sqrt(1 - 0.999 ** t) / (1 - 0.9 ** t) \
+            * 0.1 / np.sqrt(0.001) * np.sign(g)
+        np.testing.assert_allclose(d, exp, rtol=1e-12)
+
+
 def test_surrogate_with_zero_tolerance_is_the_plain_collision():
     f, omega = _batch(128, 7)
     params = inputs.mlp_init(8)
