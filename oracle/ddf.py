@@ -37,7 +37,8 @@ shear layer the transverse velocity is near zero with a noisy sign, and that swi
 the thermal shear layer with walls blow up within a few hundred steps (first- and third-order
 sign-keyed variants behave the same), while the central stencil stays stable. Ghost rows at a
 wall use zero-order extrapolation of the nearest fluid row (the paper's default extrapolation
-for unspecified boundary data, Sec. III A, Rayleigh flow).
+for unspecified boundary data, Sec. III A, Rayleigh flow). On the boundary nodes of the
+non-equilibrium extrapolation walls the side is keyed on the wall velocity (upwind_key).
 """
 import numpy as np
 
@@ -183,9 +184,11 @@ def divergence(u, walls_y):
     return sum(central_derivative(u[a], u.ndim - 2 - a, walls_y and a == 1) for a in range(D))
 
 
-def galilean_correction(rho, u, theta, walls_y, stencil="central"):
-    """dt Phi_aa = -(1/rho) d_a (rho u_a^3 + 3 rho u_a (theta - varsigma^2)), per axis."""
+def galilean_correction(rho, u, theta, walls_y, stencil="central", key=None):
+    """dt Phi_aa = -(1/rho) d_a (rho u_a^3 + 3 rho u_a (theta - varsigma^2)), per axis.
+    key: the velocity whose sign picks the upwind side (default u; see upwind_key)."""
     D = u.shape[0]
+    key = u if key is None else key
     out = np.empty_like(u)
     for a in range(D):
         phi = rho * u[a] ** 3 + 3.0 * rho * u[a] * (theta - VARSIGMA2)
@@ -194,16 +197,35 @@ def galilean_correction(rho, u, theta, walls_y, stencil="central"):
         if stencil == "central":
             d = central_derivative(phi, axis, wall)
         elif stencil == "upwind":
-            d = upwind_derivative(phi, u[a], axis, wall)
+            d = upwind_derivative(phi, key[a], axis, wall)
         else:
             raise ValueError(stencil)
         out[a] = -d / rho
     return out
 
 
-def equilibria(rho, u, rhoE, gas, walls_y, phi_on=True, stencil="central", F=None, Q=0.0):
+def upwind_key(u, neq):
+    """Velocity that picks the upwind side of the Phi derivative. On the boundary nodes of the
+    non-equilibrium extrapolation walls (rows or planes y = 0 and ny - 1) it is the wall
+    velocity: there the fluid velocity equals it up to rounding, and the sign of a component
+    that vanishes (the normal one, or a zero tangential one) is rounding noise, so the y
+    derivative on those rows is central and the tangential ones follow the wall's motion.
+    Everywhere else, and without such walls, it is u itself."""
+    if neq is None:
+        return u
+    key = u.copy()
+    ny = u.shape[-2]
+    for side, row in enumerate((0, ny - 1)):
+        for a in range(u.shape[0]):
+            key[a][..., row, :] = neq.u[side][a]
+    return key
+
+
+def equilibria(rho, u, rhoE, gas, walls_y, phi_on=True, stencil="central", F=None, Q=0.0,
+               neq=None):
     """f^eq, f*, g^eq, g*, beta at every node (Fig. 1 order) from the moments (rho, u, rho E
-    already carry the half-step source terms)."""
+    already carry the half-step source terms); neq (NeqWalls) only keys the upwind side on
+    the boundary nodes (upwind_key)."""
     D = u.shape[0]
     T, P, theta = closure(rho, u, rhoE, gas)
     e = gas.internal_energy(rho, T)
@@ -215,7 +237,8 @@ def equilibria(rho, u, rhoE, gas, walls_y, phi_on=True, stencil="central", F=Non
         thetastar = thetastar + alpha * theta * divergence(u, walls_y)
     Tstar = T + Q / (rho * gas.cv) - (Fv * Fv).sum(axis=0) / (2.0 * rho * rho * gas.cv)
     fe = feq(rho, u, theta)
-    Phi = galilean_correction(rho, u, theta, walls_y, stencil) if phi_on else np.zeros_like(u)
+    Phi = (galilean_correction(rho, u, theta, walls_y, stencil, upwind_key(u, neq)) if phi_on
+           else np.zeros_like(u))
     fs = fstar(rho, ustar, thetastar, Phi)
     ge = geq(rho, u, theta, e)
     gs = geq(rho, ustar, thetastar, gas.internal_energy(rho, Tstar))
@@ -257,9 +280,9 @@ def init_equilibrium(rho, u, T, gas):
     return feq(rho, u, theta), geq(rho, u, theta, gas.internal_energy(rho, T))
 
 
-def collide(f, g, gas, walls_y, phi_on=True, stencil="central", F=None, Q=0.0):
+def collide(f, g, gas, walls_y, phi_on=True, stencil="central", F=None, Q=0.0, neq=None):
     rho, u, rhoE = moments(f, g, F, Q)
-    fe, fs, ge, gs, beta = equilibria(rho, u, rhoE, gas, walls_y, phi_on, stencil, F, Q)
+    fe, fs, ge, gs, beta = equilibria(rho, u, rhoE, gas, walls_y, phi_on, stencil, F, Q, neq)
     ft = f + 2.0 * beta * (fe - f) + (1.0 - beta) * (fs - fe)
     gt = g + 2.0 * beta * (ge - g) + (1.0 - beta) * (gs - ge)
     return ft, gt
@@ -270,9 +293,10 @@ class NeqWalls:
     (D2Q9) or planes (D3Q27) y = 0 and y = ny - 1 are boundary nodes B on the walls, with wall
     velocities u_lo, u_hi (D components) and temperatures T_lo, T_hi; N is the neighbouring row
     or plane (1 or ny - 2).
-    density="pressure" (the default reading) takes rho_B = rho_N T_N / T_W, the density that
-    continues the pressure P_N = rho_N R T_N to the wall; density="literal" takes rho_B = rho_N,
-    the paper's extrapolation written out (the two agree where T_N = T_W)."""
+    density="pressure" (the default reading) takes the rho_B that continues the neighbour's
+    pressure to the wall, P(rho_B, T_W) = P(rho_N, T_N): rho_N T_N / T_W for the ideal gas, the
+    root of the van der Waals isotherm (wall_density_vdw) otherwise; density="literal" takes
+    rho_B = rho_N, the paper's extrapolation written out (the two agree where T_N = T_W)."""
 
     def __init__(self, u_lo, T_lo, u_hi, T_hi, density="pressure"):
         self.u = (np.asarray(u_lo, dtype=np.float64), np.asarray(u_hi, dtype=np.float64))
@@ -282,27 +306,56 @@ class NeqWalls:
         self.density = density
 
 
+def critical_temperature(gas):
+    """T_cr = 8 a / (27 b R) of the van der Waals isotherms (Sec. III C): above it P(rho) is
+    strictly increasing on 0 < rho < 1/b."""
+    return 8.0 * gas.a / (27.0 * gas.b * gas.R)
+
+
+def wall_density_vdw(P_N, T_W, gas, iters=200):
+    """rho_B with P(rho_B, T_W) = P_N on a supercritical van der Waals isotherm (T_W > T_cr,
+    b > 0), by bisection on (0, 1/b) where P is strictly increasing; run until the bracket
+    stops shrinking (float64 resolution)."""
+    if not (gas.b > 0.0 and T_W > critical_temperature(gas)):
+        raise ValueError("the pressure-continued wall density needs b > 0 and T_W > T_cr")
+    lo = np.zeros_like(P_N)
+    hi = np.full_like(P_N, 1.0 / gas.b)
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        above = gas.pressure(mid, T_W) > P_N
+        hi = np.where(above, mid, hi)
+        lo = np.where(above, lo, mid)
+    return 0.5 * (lo + hi)
+
+
 def apply_neq_walls(f, g, gas, walls):
     """Boundary rows of the pre-collision populations:
     f_B = f^eq(rho_B, u_W, T_W) + (f_N - f^eq(rho_N, u_N, T_N)), and the same for g (App. B),
-    with rho_B from NeqWalls.density. No sources (the context rejects them with these walls)."""
-    if not gas.ideal:
-        raise ValueError("non-equilibrium extrapolation walls are written for the ideal gas")
+    with rho_B from NeqWalls.density; the wall equilibria take theta_W = P(rho_B, T_W)/rho_B
+    and e_W = e(rho_B, T_W) of the fluid's equation of state (R T_W and c_v T_W for the ideal
+    gas). No sources (the context rejects them with these walls)."""
     rho, u, rhoE = moments(f, g)
     T, _, theta = closure(rho, u, rhoE, gas)
     fe = feq(rho, u, theta)
-    ge = geq(rho, u, theta, gas.cv * T)
+    ge = geq(rho, u, theta, gas.internal_energy(rho, T))
     ny = f.shape[-2]
     f, g = f.copy(), g.copy()
     D = u.shape[0]
     for side, (B, N) in enumerate(((0, 1), (ny - 1, ny - 2))):
         TW = walls.T[side]
         rN, TN = rho[..., N, :], T[..., N, :]
-        rB = rN * TN / TW if walls.density == "pressure" else rN
+        if walls.density == "literal":
+            rB = rN
+        elif gas.ideal:
+            rB = rN * TN / TW
+        else:
+            rB = wall_density_vdw(gas.pressure(rN, TN), TW, gas)
         uW = walls.u[side].reshape((D,) + (1,) * rB.ndim) * np.ones((D,) + rB.shape)
         TWf = np.full(rB.shape, TW)
-        f[..., B, :] = feq(rB, uW, gas.R * TWf) + (f[..., N, :] - fe[..., N, :])
-        g[..., B, :] = geq(rB, uW, gas.R * TWf, gas.cv * TWf) + (g[..., N, :] - ge[..., N, :])
+        thetaW = gas.R * TWf if gas.ideal else gas.pressure(rB, TWf) / rB
+        eW = gas.internal_energy(rB, TWf)
+        f[..., B, :] = feq(rB, uW, thetaW) + (f[..., N, :] - fe[..., N, :])
+        g[..., B, :] = geq(rB, uW, thetaW, eW) + (g[..., N, :] - ge[..., N, :])
     return f, g
 
 
@@ -316,7 +369,7 @@ def run(f, g, gas, nsteps, walls_y=True, phi_on=True, stencil="central", F=None,
     if neq is not None:
         for _ in range(nsteps):
             f, g = apply_neq_walls(f, g, gas, neq)
-            ft, gt = collide(f, g, gas, True, phi_on, stencil, F, Q)
+            ft, gt = collide(f, g, gas, True, phi_on, stencil, F, Q, neq)
             f, g = bgk.stream(ft), bgk.stream(gt)
         return apply_neq_walls(f, g, gas, neq)
     for _ in range(nsteps):

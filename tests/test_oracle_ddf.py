@@ -662,3 +662,108 @@ def test_vdw_sound_speed():
     speed = np.pi / np.diff(zc).mean() / k
     assert speed == pytest.approx(np.sqrt(cs2), rel=5e-3)
     assert abs(speed / np.sqrt(GAMMA * R * T0) - 1) > 0.05
+
+
+# ---- van der Waals fluid with NEQ walls: the paper's thermal Couette state ------------------
+# App. B runs the thermal Couette flow on the van der Waals fluid at P0 = 3 P_cr with the cold
+# wall at T_C = 1.05 T_cr. Lattice units here put that state at theta = P/rho ~ 0.0625 (T_cr =
+# 0.3, P_cr = 0.0625, R = 1/3: rho ~ 3, 1 - b rho ~ 0.4) so the van der Waals sound speed stays
+# below the lattice speed; in the units of the other van der Waals tests (T_cr = 1.2, P_cr =
+# 0.25) the same reduced state has c_s^2 ~ 2 and the scheme is unstable there in any reading.
+
+def _vdw_couette(ny, density="pressure", U=0.03, efolds=3.0):
+    Tcr, Pcr = 0.3, 0.0625
+    gas = ddf.Gas(R, CV, 0.5 * P0, a=27 * R * R * Tcr * Tcr / (64 * Pcr), b=R * Tcr / (8 * Pcr))
+    TC, P, dT = 1.05 * Tcr, 3.0 * Pcr, 0.02 * 1.05 * Tcr
+    L = ny - 1
+    y = np.arange(ny) / L
+    k = gas.mu * gas.cp  # Pr = 1: k = mu c_p0 (k/mu = (c_v + R)/Pr)
+    # T'' = -mu U^2 / (k L^2) between the walls (Fourier heat flux, constant mu and k)
+    exact = TC + dT * y + gas.mu * U * U / (2 * k) * y * (1 - y)
+    # start from the analytic profile at uniform pressure: the discrete steady state is
+    # reached within a few viscous times
+    rho1 = np.array([ddf.wall_density_vdw(np.array([P]), Ti, gas)[0] for Ti in exact])
+    assert np.allclose(gas.pressure(rho1, exact), P, rtol=1e-13)
+    T = exact[:, None] * np.ones((1, 2))
+    rho = rho1[:, None] * np.ones((1, 2))
+    u = np.zeros((2, ny, 2))
+    u[0] = (U * y)[:, None]
+    f, g = ddf.init_equilibrium(rho, u, T, gas)
+    m0 = f.sum()
+    steps = int(efolds * L * L / (np.pi ** 2 * gas.mu / rho.mean()))
+    walls = ddf.NeqWalls((0.0, 0.0), TC, (U, 0.0), TC + dT, density=density)
+    f, g = ddf.run(f, g, gas, steps, neq=walls)
+    _, uu, Tn = ddf.temperature(f, g, gas)
+    err = np.sqrt(((Tn[:, 0] - exact) ** 2).sum() / ((exact - TC) ** 2).sum())
+    return err, np.abs(uu[0][:, 0] - U * y).max() / U, f.sum() / m0 - 1
+
+
+def test_vdw_wall_density_root_is_on_the_isotherm():
+    # P(rho_B, T_W) = P_N: the bisection root against a fixed point of the isotherm
+    gas = _vdw_gas()
+    rho = np.array([0.5, 1.0, 2.0, 3.5])
+    for TW in (1.25, 1.4, 2.0):  # above T_cr = 1.2
+        rb = ddf.wall_density_vdw(gas.pressure(rho, TW), TW, gas)
+        np.testing.assert_allclose(rb, rho, rtol=1e-14)
+    with pytest.raises(ValueError):
+        ddf.wall_density_vdw(np.array([0.3]), 1.1, gas)  # subcritical isotherm
+
+
+def test_vdw_thermal_couette_converges_to_the_analytic_profile():
+    # pressure-continued wall density: the steady profile approaches the analytic one as the
+    # channel is resolved (the zero-order ghosts of the heat-flux correction's grad h and
+    # grad T at the wall rows make the approach first order) and the walls keep the mass
+    e9, u9, m9 = _vdw_couette(9)
+    e17, _, m17 = _vdw_couette(17)
+    assert e9 < 1.3e-2 and e17 < 0.7 * e9
+    assert u9 < 1e-4
+    assert abs(m9) < 1e-5 and abs(m17) < 1e-5
+
+
+def test_vdw_literal_wall_density_leaks_mass():
+    err, _, dm = _vdw_couette(9, density="literal")
+    assert dm < -1e-3 and err > 2e-2
+
+
+def test_d3q27_z_uniform_vdw_neq_walls_run_reproduces_d2q9():
+    # the van der Waals wall state (root of the isotherm, theta_W, e_W) is local to each
+    # boundary node, so the z-uniform reduction of the NEQ walls holds for this fluid too
+    gas = _vdw_gas(prandtl=0.8)
+    rng = np.random.default_rng(12)
+    shape = (7, 6)
+    rho2 = 1.0 + 0.01 * rng.standard_normal(shape)
+    T2 = 1.4 + 0.03 * rng.standard_normal(shape)
+    u2 = 0.02 * rng.standard_normal((2,) + shape)
+    nz = 3
+    rho3 = np.repeat(rho2[None], nz, axis=0)
+    T3 = np.repeat(T2[None], nz, axis=0)
+    u3 = np.zeros((3, nz) + shape)
+    u3[:2] = u2[:, None]
+    for density in ("pressure", "literal"):
+        w2 = ddf.NeqWalls((0.0, 0.0), 1.38, (0.04, 0.0), 1.45, density=density)
+        w3 = ddf.NeqWalls((0.0, 0.0, 0.0), 1.38, (0.04, 0.0, 0.0), 1.45, density=density)
+        f2, g2 = ddf.run(*ddf.init_equilibrium(rho2, u2, T2, gas), gas, 5, neq=w2)
+        f3, g3 = ddf.run(*ddf.init_equilibrium(rho3, u3, T3, gas), gas, 5, neq=w3)
+        from oracle.lattice import velocities
+        c3 = velocities(3)
+        for i2, c in enumerate([tuple(c) for c in velocities(2)]):
+            sel = [i for i, cc in enumerate(c3) if (cc[0], cc[1]) == c]
+            np.testing.assert_allclose(f3[sel].sum(axis=0)[1], f2[i2], rtol=0, atol=1e-14)
+            np.testing.assert_allclose(g3[sel].sum(axis=0)[1], g2[i2], rtol=0, atol=1e-14)
+
+
+def test_upwind_key_on_neq_boundary_rows_is_the_wall_velocity():
+    # the keying velocity: the wall velocity on the boundary rows, u elsewhere; with a normal
+    # wall velocity of zero the y derivative there is central, whatever the rounding of u_y
+    rng = np.random.default_rng(13)
+    u = 0.02 * rng.standard_normal((2, 6, 5))
+    w = ddf.NeqWalls((0.0, 0.0), 1.0, (0.05, 0.0), 1.0)
+    key = ddf.upwind_key(u, w)
+    np.testing.assert_array_equal(key[:, 1:-1], u[:, 1:-1])
+    np.testing.assert_array_equal(key[0, 0], 0.0)
+    np.testing.assert_array_equal(key[0, -1], 0.05)
+    np.testing.assert_array_equal(key[1, [0, -1]], 0.0)
+    phi = rng.standard_normal((6, 5))
+    d = ddf.upwind_derivative(phi, key[1], 0, True)
+    np.testing.assert_array_equal(d[[0, -1]], ddf.central_derivative(phi, 0, True)[[0, -1]])
+    assert ddf.upwind_key(u, None) is u
