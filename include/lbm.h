@@ -72,10 +72,12 @@ typedef struct {
   int32_t collision; /* LBM_COLLIDE_*; MLP: D2Q9 BGK with FP32 storage only */
   int32_t nx, ny, nz; /* lattice size in nodes; nz = 1 for D2Q9; each >= 1 (nx, ny >= 3) */
   int32_t wall_y;     /* 0: periodic in y; 1: half-way bounce-back walls at y = -1/2 and ny-1/2;
-                         2 (DDF, D2Q9 or D3Q27, FP32/FP64, ny >= 3, ideal gas, no sources):
-                         non-equilibrium extrapolation walls on the rows (D2Q9) or planes
-                         (D3Q27) y = 0 and y = ny-1 with the velocities wall_u and temperatures
-                         wall_T (App. B, thermal Couette) */
+                         2 (DDF, D2Q9 or D3Q27, FP32/FP64, ny >= 3, no sources; ideal gas or
+                         van der Waals): non-equilibrium extrapolation walls on the rows (D2Q9)
+                         or planes (D3Q27) y = 0 and y = ny-1 with the velocities wall_u and
+                         temperatures wall_T (App. B, thermal Couette). With the upwind Phi
+                         derivative (phi = 2) the side on those rows follows the wall velocity
+                         (central in y there). */
   double tau;  /* BGK: tau_LB = 1/(2 beta) > 1/2, so nu = (tau - 1/2)/3.
                   DDF: the same value at the reference pressure P0 = 1/3 defines the dynamic
                   viscosity mu = (tau - 1/2) P0; per node tau_kin = mu / P (Sec. II A). */
@@ -98,15 +100,19 @@ typedef struct {
                           FP32/FP64 storage. */
   int32_t eos;         /* DDF equation of state: 0 = ideal gas (Sec. III A), 1 = van der Waals
                           P = rho R T / (1 - b rho) - a rho^2 with e = c_v T - a rho (Sec. III C);
-                          van der Waals: D2Q9 or D3Q27, FP32/FP64 storage, wall_y 0 or 1.
+                          van der Waals: D2Q9 or D3Q27, FP32/FP64 storage, any wall_y.
                           Its alpha and q^c are per node (k/mu = (c_v + R) / prandtl). */
   double vdw_a, vdw_b; /* van der Waals a >= 0, b >= 0 (lattice units); 1 - b rho > 0 */
   double wall_u[2][3]; /* wall_y = 2: wall velocity [bottom (y = 0), top (y = ny-1)][x, y, z];
                           tangential: y component 0; z component 0 in D2Q9 */
   double wall_T[2];    /* wall_y = 2: wall temperatures [bottom, top], > 0 */
-  int32_t wall_density; /* wall_y = 2: boundary density rho_B; 0 (default) = rho_N T_N / T_W
-                          (the neighbour's pressure continued to the wall), 1 = rho_N (the
-                          extrapolation as written in App. B; it leaks mass where T_N != T_W) */
+  int32_t wall_density; /* wall_y = 2: boundary density rho_B; 0 (default) = the density with
+                          P(rho_B, T_W) = P(rho_N, T_N), the neighbour's pressure continued to the
+                          wall (ideal gas: rho_N T_N / T_W; van der Waals: the root on the wall
+                          isotherm, which must be supercritical: T_W > 8 a / (27 b R), b > 0),
+                          1 = rho_N (the extrapolation as written in App. B; it leaks mass where
+                          T_N != T_W). The wall equilibrium takes theta_W = P(rho_B, T_W)/rho_B
+                          and e_W = e(rho_B, T_W). */
   int32_t phi;         /* DDF: 1 = Galilean correction Phi on (the paper), 0 = off */
   int32_t fp16_scale_log2; /* LBM_STORE_FP16: S in [0, 24]; stored value = (f - f^eq) * 2^S */
   int32_t diag_every;  /* > 0: every diag_every steps record float64 totals (mass, momentum,
@@ -211,9 +217,11 @@ void lbm_mlp_destroy(lbm_mlp* m);
 int lbm_mlp_get(lbm_mlp* m, float* weights);
 /* Forward pass for n samples: dev_x [n][12] -> dev_y [n][9] (projected outputs). */
 int lbm_mlp_forward(lbm_mlp* m, const float* dev_x, int64_t n, float* dev_y);
-/* Mean-squared-error loss and its gradient for one batch of n samples (dev_x [n][12],
-   dev_t [n][9]); dev_grad receives 5577 float32 values in the blob layout, *loss the loss
-   (pass NULL to skip the loss read, which avoids a synchronisation). */
+/* Mean-squared-error loss and its gradient for one batch of 1 <= n <= 2^20 samples
+   (dev_x [n][12], dev_t [n][9]); dev_grad receives 5577 float32 values in the blob layout,
+   *loss the loss (pass NULL to skip the loss read, which avoids a synchronisation). The
+   per-64-sample partial gradients live in a trainer buffer (22 KiB per 64 samples) that is
+   allocated, or grown, on the first call that needs it. */
 int lbm_mlp_grad(lbm_mlp* m, const float* dev_x, const float* dev_t, int64_t n,
                  float* dev_grad, float* loss);
 /* Train: for each of `steps` batches of `batch` consecutive samples (wrapping around n),

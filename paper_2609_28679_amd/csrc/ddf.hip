@@ -43,6 +43,7 @@
 #include "reduced_common.h"
 
 #include <cstdlib>
+#include <type_traits>
 
 namespace lbm {
 
@@ -354,8 +355,10 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
         if (HALO == 1) {
           d = 0.5 * (px[tid + 1] - px[tid - 1]);
         } else {
-          d = upwind_or_central(px[tid - 2], px[tid - 1], px[tid], px[tid + 1], px[tid + 2],
-                                ring_m[j][1]);
+          // the upwind side follows u_x, on the boundary rows of NEQ walls the wall's u_x
+          double key = ring_m[j][1];
+          if (WALLS == 2 && (r == 0 || r == ny - 1)) key = prm.uw[r == 0 ? 0 : 1][0];
+          d = upwind_or_central(px[tid - 2], px[tid - 1], px[tid], px[tid + 1], px[tid + 2], key);
         }
         ring_m[j][5] = -d;  // -d(phi_x)/dx; divided by rho at the collision
       }
@@ -374,10 +377,15 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
             q[o + 2] = s_phiy[((row % P) + P) % P][tid];
           }
           double d;
-          if (HALO == 1)
+          if (HALO == 1) {
             d = 0.5 * (q[3] - q[1]);
-          else
-            d = upwind_or_central(q[0], q[1], q[2], q[3], q[4], ring_m[sc][2]);
+          } else {
+            // on the boundary rows of NEQ walls the side follows the wall's normal velocity,
+            // zero: the y derivative there is central
+            double key = ring_m[sc][2];
+            if (WALLS == 2 && (c == 0 || c == ny - 1)) key = prm.uw[c == 0 ? 0 : 1][1];
+            d = upwind_or_central(q[0], q[1], q[2], q[3], q[4], key);
+          }
           phyy = -d;
         }
         double phxx = 0.0;
@@ -528,11 +536,9 @@ template <class IO, int HALO, int WALLS, bool PULL>
 static void ddf_launch(const IO& io, const Layout& L, const Grid& G, const DdfParams& prm,
                        double* partials, hipStream_t s) {
   if constexpr (!IO::kStaged) {
-    if constexpr (WALLS != 2) {  // the context admits the van der Waals fluid without NEQ walls
-      if (prm.eos) {
-        ddf_launch_s<IO, HALO, WALLS, PULL, 2>(io, L, G, prm, partials, s);
-        return;
-      }
+    if (prm.eos) {
+      ddf_launch_s<IO, HALO, WALLS, PULL, 2>(io, L, G, prm, partials, s);
+      return;
     }
     if (prm.ext()) {
       ddf_launch_s<IO, HALO, WALLS, PULL, 1>(io, L, G, prm, partials, s);
@@ -585,10 +591,10 @@ static IoRed<Codec> make_red(const void* A, void* B, const Layout& L, float se, 
 // Non-equilibrium extrapolation walls (App. B): the pre-collision populations of the boundary
 // rows B (y = 0, ny - 1, on the walls) are f^eq(rho_B, u_W, T_W) + f_N - f^eq(rho_N, u_N, T_N)
 // with N the neighbouring row (1, ny - 2), pulled like any fluid row (PULL = false: its own
-// slots), and rho_B = rho_N T_N / T_W (pressure continued to the wall) or rho_N (literal).
-// One thread per column, gridDim.y = 2 walls; the rows go to nb[(side*18 + k)*pitch + x],
-// k < 9 f - w, k >= 9 g - v.
-template <typename S, bool PULL>
+// slots), and rho_B the pressure-continued or the literal density (neq_wall_state); VDW: the
+// van der Waals closure at N and at the wall. One thread per column, gridDim.y = 2 walls; the
+// rows go to nb[(side*18 + k)*pitch + x], k < 9 f - w, k >= 9 g - v.
+template <typename S, bool PULL, bool VDW>
 __global__ void __launch_bounds__(kBlock)
 k_ddf_neq_rows(const S* __restrict__ A, int nx, int ny, int64_t pitch, int64_t plane,
                DdfParams prm, S* __restrict__ nb) {
@@ -615,13 +621,13 @@ k_ddf_neq_rows(const S* __restrict__ A, int nx, int ny, int64_t pitch, int64_t p
     g[i] = (double)hg[i] + prm.wg[i];
   }
   Moments m;
-  moments_closure(f, g, prm, m);
+  moments_closure<false, VDW>(f, g, prm, m);
   double feN[9], geN[9], feB[9], geB[9];
   equilibria(m.rho, m.ux, m.uy, m.theta, m.e, feN, geN);
-  const double TW = prm.Tw[side];
-  const double TN = m.theta * prm.inv_R;
-  const double rhoB = prm.neq_literal ? m.rho : m.rho * TN / TW;
-  equilibria(rhoB, prm.uw[side][0], prm.uw[side][1], prm.R * TW, prm.cv * TW, feB, geB);
+  const double TN = node_temperature<VDW>(prm, m.rho, m.e, m.theta);
+  double rhoB, thetaW, eW;
+  neq_wall_state<VDW>(prm, side, m.rho, TN, m.rho * m.theta, rhoB, thetaW, eW);
+  equilibria(rhoB, prm.uw[side][0], prm.uw[side][1], thetaW, eW, feB, geB);
   for (int i = 0; i < 9; ++i) {
     nb[(side * 18 + i) * pitch + x] = (S)(feB[i] + (f[i] - feN[i]) - prm.wf[i]);
     nb[(side * 18 + 9 + i) * pitch + x] = (S)(geB[i] + (g[i] - geN[i]) - prm.wg[i]);
@@ -633,15 +639,24 @@ hipError_t launch_ddf(int fmt, bool walls, bool pull, const void* A, void* B, co
                       double* partials, void* nb, hipStream_t s) {
   if (prm.ext() && fmt >= 2) return hipErrorInvalidValue;  // no extended path with reduced storage
   if (prm.neq) {
-    if (fmt >= 2 || !walls || !nb || L.ny < 3 || prm.eos) return hipErrorInvalidValue;
+    if (fmt >= 2 || !walls || !nb || L.ny < 3 || prm.src) return hipErrorInvalidValue;
     dim3 grid((L.nx + kBlock - 1) / kBlock, 2);
-    if (fmt == 0) {
-      if (pull) k_ddf_neq_rows<float, true><<<grid, kBlock, 0, s>>>(static_cast<const float*>(A), L.nx, L.ny, L.pitch, L.plane, prm, static_cast<float*>(nb));
-      else k_ddf_neq_rows<float, false><<<grid, kBlock, 0, s>>>(static_cast<const float*>(A), L.nx, L.ny, L.pitch, L.plane, prm, static_cast<float*>(nb));
-    } else {
-      if (pull) k_ddf_neq_rows<double, true><<<grid, kBlock, 0, s>>>(static_cast<const double*>(A), L.nx, L.ny, L.pitch, L.plane, prm, static_cast<double*>(nb));
-      else k_ddf_neq_rows<double, false><<<grid, kBlock, 0, s>>>(static_cast<const double*>(A), L.nx, L.ny, L.pitch, L.plane, prm, static_cast<double*>(nb));
-    }
+    auto rows = [&](auto tag, auto pl, auto vdw) {
+      using S = decltype(tag);
+      k_ddf_neq_rows<S, decltype(pl)::value, decltype(vdw)::value><<<grid, kBlock, 0, s>>>(
+          static_cast<const S*>(A), L.nx, L.ny, L.pitch, L.plane, prm, static_cast<S*>(nb));
+    };
+    auto by_flags = [&](auto tag) {
+      if (pull) {
+        if (prm.eos) rows(tag, std::true_type{}, std::true_type{});
+        else rows(tag, std::true_type{}, std::false_type{});
+      } else {
+        if (prm.eos) rows(tag, std::false_type{}, std::true_type{});
+        else rows(tag, std::false_type{}, std::false_type{});
+      }
+    };
+    if (fmt == 0) by_flags(float{});
+    else by_flags(double{});
   }
   if (fmt == 0) {
     IoFull<float> io{static_cast<const float*>(A), static_cast<float*>(B), L.plane,

@@ -299,11 +299,16 @@ k_ddf3_collide(const S* __restrict__ A, const S* __restrict__ nb, S* __restrict_
         for (int a = 0; a < 3; ++a) {
           const S* F = fld + a * plane;
           double d;
-          if (HALO == 1)
+          if (HALO == 1) {
             d = 0.5 * ((double)F[at(a, 1)] - (double)F[at(a, -1)]);
-          else
+          } else {
+            // the upwind side follows u_a; on the boundary planes of NEQ walls the wall's
+            // velocity (normal component zero: central in y there)
+            double key = m.u[a];
+            if (WALLS == 2 && (y == 0 || y == ny - 1)) key = prm.uw[y == 0 ? 0 : 1][a];
             d = upwind_or_central((double)F[at(a, -2)], (double)F[at(a, -1)], (double)F[off],
-                                  (double)F[at(a, 1)], (double)F[at(a, 2)], m.u[a]);
+                                  (double)F[at(a, 1)], (double)F[at(a, 2)], key);
+          }
           ph[a] = -d * inv_rho;
         }
       }
@@ -448,9 +453,10 @@ static void ext_kind(const DdfParams& prm, Fn&& fn) {
 // Non-equilibrium extrapolation walls (App. B; the D2Q9 form is k_ddf_neq_rows): the
 // pre-collision populations of the boundary planes B (y = 0 and ny - 1, on the walls) are
 // f^eq(rho_B, u_W, T_W) + f_N - f^eq(rho_N, u_N, T_N), N the neighbouring plane (1, ny - 2)
-// pulled like any fluid node, rho_B = rho_N T_N / T_W (pressure continued to the wall) or rho_N
-// (literal). One thread per (x, z, side); written to nb as node_pops reads it.
-template <typename S, bool PULL>
+// pulled like any fluid node, rho_B the pressure-continued or the literal density
+// (neq_wall_state); EXT = 2: the van der Waals closure at N and at the wall. One thread per
+// (x, z, side); written to nb as node_pops reads it.
+template <typename S, bool PULL, int EXT>
 __global__ void __launch_bounds__(kBlock)
 k_ddf3_neq_rows(const S* __restrict__ A, int nx, int ny, int nz, int64_t pitch, int64_t plane,
                 DdfParams prm, S* __restrict__ nb) {
@@ -463,23 +469,24 @@ k_ddf3_neq_rows(const S* __restrict__ A, int nx, int ny, int nz, int64_t pitch, 
   S hf[27], hg[27];
   gather27<S, true, PULL>(A, plane, nx, ny, nz, pitch, x, N, z, hf, hg);
   Moments3 m;
-  moments3<0>(hf, hg, prm, m, 0.0, 0.0, 0.0, 0.0);
-  const double TW = prm.Tw[side];
-  const double TN = m.theta * prm.inv_R;
-  const double rhoB = prm.neq_literal ? m.rho : m.rho * TN / TW;
+  moments3<EXT == 2 ? 2 : 0>(hf, hg, prm, m, 0.0, 0.0, 0.0, 0.0);
+  constexpr bool VDW = EXT == 2;
+  const double TN = node_temperature<VDW>(prm, m.rho, m.e, m.theta);
+  double rhoB, thetaW, eW;
+  neq_wall_state<VDW>(prm, side, m.rho, TN, m.rho * m.theta, rhoB, thetaW, eW);
   const double uW[3] = {prm.uw[side][0], prm.uw[side][1], prm.uw[side][2]};
   Axis X[3], XB[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     axis_eq(m.u[a], m.theta, X[a]);
-    axis_eq(uW[a], prm.R * TW, XB[a]);
+    axis_eq(uW[a], thetaW, XB[a]);
   }
   const int64_t nbp = (int64_t)nz * pitch;
   const int64_t o = (int64_t)side * 54 * nbp + (int64_t)z * pitch + x;
   for (int i = 0; i < 27; ++i) {
     double feN, geN, feB, geB;
     equilibria3(m.rho, m.e, i, X, feN, geN);
-    equilibria3(rhoB, prm.cv * TW, i, XB, feB, geB);
+    equilibria3(rhoB, eW, i, XB, feB, geB);
     const double f = (double)hf[i] + prm.wf[i], g = (double)hg[i] + prm.wg[i];
     nb[o + i * nbp] = (S)(feB + (f - feN) - prm.wf[i]);
     nb[o + (27 + i) * nbp] = (S)(geB + (g - geN) - prm.wg[i]);
@@ -505,18 +512,19 @@ static void ddf3_step(bool walls, bool pull, const S* A, S* B, const Layout& L, 
   S* fld = reinterpret_cast<S*>(fld64);  // 8 planes of the storage type
   if (walls && prm.neq) {
     const unsigned nblk = (unsigned)((2 * (int64_t)L.nz * L.nx + kBlock - 1) / kBlock);
-    if (pull)
-      k_ddf3_neq_rows<S, true><<<nblk, kBlock, 0, s>>>(A, L.nx, L.ny, L.nz, L.pitch, L.plane, prm, nb);
-    else
-      k_ddf3_neq_rows<S, false><<<nblk, kBlock, 0, s>>>(A, L.nx, L.ny, L.nz, L.pitch, L.plane, prm, nb);
+    flag(pull, [&](auto Pl) {
+      flag(prm.eos != 0, [&](auto V) {
+        k_ddf3_neq_rows<S, decltype(Pl)::value, decltype(V)::value ? 2 : 0>
+            <<<nblk, kBlock, 0, s>>>(A, L.nx, L.ny, L.nz, L.pitch, L.plane, prm, nb);
+      });
+    });
   }
   wall_kind(walls, prm, [&](auto W) {
     flag(pull, [&](auto Pl) {
       ext_kind(prm, [&](auto E) {
         constexpr int w = decltype(W)::value, e = decltype(E)::value;
         constexpr bool pl = decltype(Pl)::value;
-        // the context admits the van der Waals fluid without NEQ walls
-        if constexpr (!(w == 2 && e == 2)) {
+        {
           // the fields are read only for Phi and for transport control
           if (prm.phi || (e && prm.full))
             k_ddf3_flux<S, w, pl, e><<<grid, block, 0, s>>>(A, nb, L.nx, L.ny, L.nz, L.pitch,
@@ -539,7 +547,7 @@ static void ddf3_step(bool walls, bool pull, const S* A, S* B, const Layout& L, 
 hipError_t launch_ddf3(int kind, bool walls, bool pull, const void* A, void* B, const Layout& L,
                        const Grid& G, const DdfParams& prm, double* fld, void* nb,
                        double* partials, hipStream_t s) {
-  if (prm.neq && (!walls || !nb || L.ny < 3 || prm.eos || prm.src))
+  if (prm.neq && (!walls || !nb || L.ny < 3 || prm.src))
     return hipErrorInvalidValue;
   if (kind == 0)
     ddf3_step<float>(walls, pull, static_cast<const float*>(A), static_cast<float*>(B), L, G,

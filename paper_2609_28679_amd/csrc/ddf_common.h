@@ -88,6 +88,47 @@ __device__ __forceinline__ double node_temperature(const DdfParams& p, double rh
   return VDW ? (e + p.va * rho) / p.cv : theta * p.inv_R;
 }
 
+// State of a boundary node of the non-equilibrium extrapolation walls (App. B) next to the
+// fluid node N (density rhoN, temperature TN, pressure PN): the density rho_B and the wall
+// equilibrium's theta_W = P(rho_B, T_W)/rho_B and e_W = e(rho_B, T_W) at the wall temperature
+// of `side`. rho_B = rho_N with p.neq_literal, otherwise the density that continues P_N to the
+// wall: rho_N T_N / T_W for the ideal gas; for the van der Waals fluid (VDW) the root of
+// P(rho, T_W) = P_N on a supercritical isotherm (T_W > T_cr, checked at context creation),
+// where P is strictly increasing on 0 < rho < 1/b: Newton steps from rho_N kept inside a
+// bisection bracket, until the iterate repeats or 100 steps.
+template <bool VDW>
+__device__ __forceinline__ void neq_wall_state(const DdfParams& p, int side, double rhoN,
+                                               double TN, double PN, double& rhoB,
+                                               double& thetaW, double& eW) {
+  const double TW = p.Tw[side];
+  if constexpr (VDW) {
+    rhoB = rhoN;
+    if (!p.neq_literal) {
+      const double RT = p.R * TW;
+      double lo = 0.0, hi = 1.0 / p.vb, r = rhoN;
+      if (!(r > lo && r < hi)) r = 0.5 * hi;
+      for (int it = 0; it < 100; ++it) {
+        const double omb = 1.0 - p.vb * r;
+        const double P = r * RT / omb - p.va * r * r;
+        if (P > PN) hi = r;
+        else lo = r;
+        double rn = r - (P - PN) / (RT / (omb * omb) - 2.0 * p.va * r);
+        if (!(rn > lo && rn < hi)) rn = 0.5 * (lo + hi);
+        if (rn == r) break;
+        r = rn;
+      }
+      rhoB = r;
+    }
+    thetaW = p.R * TW / (1.0 - p.vb * rhoB) - p.va * rhoB;
+    eW = p.cv * TW - p.va * rhoB;
+  } else {
+    (void)PN;
+    rhoB = p.neq_literal ? rhoN : rhoN * TN / TW;
+    thetaW = p.R * TW;
+    eW = p.cv * TW;
+  }
+}
+
 // Pull of the nine populations of one distribution at node (x, row): f_i = A_i(x - c_i).
 // top/bot: the row touches the upper/lower half-way bounce-back wall.
 template <typename S>

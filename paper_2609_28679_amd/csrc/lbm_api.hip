@@ -159,18 +159,31 @@ int validate(const lbm_params* p, std::string& why) {
       why = "non-equilibrium extrapolation walls (wall_y = 2) need the double-distribution model, FP32 or FP64 storage and ny >= 3";
       return LBM_EINVAL;
     }
-    // tangential wall velocities: along x (D2Q9), along x and z (D3Q27)
+    // tangential wall velocities: along x (D2Q9), along x and z (D3Q27); for the ideal gas the
+    // wall equilibrium's factors at theta_W = R T_W must be positive (for the van der Waals
+    // fluid theta_W depends on the boundary density, known only during the run)
     const bool d3 = p->lattice == LBM_D3Q27;
     for (int side = 0; side < 2; ++side) {
       const double T = p->wall_T[side], ux = p->wall_u[side][0], uz = p->wall_u[side][2];
+      const bool ok_state = p->eos == 1 || (admissible(p->R * T, ux) &&
+                                            admissible(p->R * T, uz) && admissible(p->R * T, 0.0));
       if (!(T > 0.0) || !std::isfinite(T) || !std::isfinite(ux) || !std::isfinite(uz) ||
-          p->wall_u[side][1] != 0.0 || (!d3 && uz != 0.0) || !admissible(p->R * T, ux) ||
-          !admissible(p->R * T, uz) || !admissible(p->R * T, 0.0)) {
+          p->wall_u[side][1] != 0.0 || (!d3 && uz != 0.0) || !ok_state) {
         why = "wall_T must be positive and wall_u tangential (x; x and z in D3Q27) and admissible";
         return LBM_EINVAL;
       }
     }
     if (p->wall_density != 0 && p->wall_density != 1) { why = "wall_density must be 0 or 1"; return LBM_EINVAL; }
+    // van der Waals fluid with the pressure-continued wall density: the isotherms of the wall
+    // temperatures must be supercritical (T_W > T_cr = 8 a / (27 b R), b > 0) so that
+    // P(rho, T_W) = P_N has exactly one root with 1 - b rho > 0
+    if (p->eos == 1 && p->wall_density == 0) {
+      const double Tcr = p->vdw_b > 0.0 ? 8.0 * p->vdw_a / (27.0 * p->vdw_b * p->R) : INFINITY;
+      if (!(p->wall_T[0] > Tcr) || !(p->wall_T[1] > Tcr)) {
+        why = "NEQ walls with the van der Waals fluid and wall_density 0 need vdw_b > 0 and wall temperatures above T_cr = 8 a / (27 b R)";
+        return LBM_EINVAL;
+      }
+    }
   }
   if (!(p->tau > 0.5) || !std::isfinite(p->tau)) { why = "tau must be a finite value > 1/2"; return LBM_EINVAL; }
   if (p->diag_every < 0) { why = "diag_every must be >= 0"; return LBM_EINVAL; }
@@ -181,8 +194,8 @@ int validate(const lbm_params* p, std::string& why) {
   if (p->eos != 0 && p->eos != 1) { why = "eos must be 0 (ideal gas) or 1 (van der Waals)"; return LBM_EINVAL; }
   if (p->eos == 1) {
     if (p->model != LBM_MODEL_DDF ||
-        (p->storage != LBM_STORE_FP32 && p->storage != LBM_STORE_FP64) || p->wall_y == 2) {
-      why = "the van der Waals eos needs the double-distribution model, FP32 or FP64 storage and wall_y 0 or 1";
+        (p->storage != LBM_STORE_FP32 && p->storage != LBM_STORE_FP64)) {
+      why = "the van der Waals eos needs the double-distribution model and FP32 or FP64 storage";
       return LBM_EINVAL;
     }
     if (!(p->vdw_a >= 0.0) || !(p->vdw_b >= 0.0) || !std::isfinite(p->vdw_a) || !std::isfinite(p->vdw_b)) {
@@ -269,6 +282,18 @@ void make_plan(const lbm_params* p, Plan& P) {
   P.total = off;
 }
 
+// Every region of the workspace starts on a 256-byte boundary (the caller's workspace is
+// 256-byte aligned), so the 64-bit atomic counters of the surrogate at off_mlp and the float64
+// arrays are naturally aligned: a misaligned 64-bit atomic faults the GPU. Checked for every
+// plan before any device work.
+bool plan_aligned(const Plan& P) {
+  const size_t offs[] = {P.off_A, P.off_B, P.off_part, P.off_hist, P.off_read,
+                         P.off_mlp, P.off_mlp + 256, P.off_fld, P.off_nb, P.total};
+  for (size_t o : offs)
+    if (o % 256 != 0) return false;
+  return true;
+}
+
 // Layout of the stored state for the read-out kernels: -1 two buffers, else the parity of t.
 int view_of(const lbm_ctx* c) { return c->aa ? (int)(c->t & 1) : -1; }
 
@@ -310,6 +335,7 @@ int lbm_workspace_size(const lbm_params* p, size_t* bytes) {
   if (!bytes) return fail(nullptr, LBM_EINVAL, "bytes is NULL");
   Plan P;
   make_plan(p, P);
+  if (!plan_aligned(P)) return fail(nullptr, LBM_EINVAL, "internal: misaligned workspace plan");
   *bytes = P.total;
   return LBM_OK;
 }
@@ -324,6 +350,7 @@ int lbm_create(const lbm_params* p, const double* rho0, const double* u0, const 
   if (!rho0 || !u0) return fail(nullptr, LBM_EINVAL, "rho0 and u0 are required");
   Plan P;
   make_plan(p, P);
+  if (!plan_aligned(P)) return fail(nullptr, LBM_EINVAL, "internal: misaligned workspace plan");
   if (P.ddf && !T0) return fail(nullptr, LBM_EINVAL, "the double-distribution model needs T0");
   const int64_t nodes = P.L.nodes();
   // host-side admissibility of the initial state
@@ -753,8 +780,11 @@ int lbm_mlp_forward(lbm_mlp* m, const float* x, int64_t n, float* y) {
 }
 
 int lbm_mlp_grad(lbm_mlp* m, const float* x, const float* t, int64_t n, float* g, float* loss) {
+  // n is capped at the training batch limit (checked first, before any state): the partials
+  // hold one row of 5578 floats per 64 samples (22 KiB), about 360 MB at 2^20 samples
+  if (n <= 0 || n > (1 << 20)) return mlp_fail(LBM_EINVAL, "n outside [1, 2^20]");
   if (!m) return mlp_fail(LBM_ESTATE, "NULL trainer");
-  if (n <= 0 || n > (1 << 24) || !x || !t || !g) return mlp_fail(LBM_EINVAL, "invalid buffers or n outside [1, 2^24]");
+  if (!x || !t || !g) return mlp_fail(LBM_EINVAL, "invalid buffers");
   int rc = mlp_ensure_partials(m, (int)n);
   if (rc) return rc;
   hipError_t e = launch_mlp_grad(x, t, n, 0, (int)n, m->w, m->partials, m->stream);

@@ -213,7 +213,7 @@ Grid make_grid_red(const Layout& L) {
 #ifdef LBM_TUNING_ENV
   if (const char* v = getenv("LBM_RED_ROWS")) G.rows = atoi(v);
 #endif
-  G.nby = (L.ny + G.rows - 1) / G.rows;
+  fit_rows(G, L.ny);  // tall lattices take more rows per workgroup (grid y <= kMaxGridY)
   return G;
 }
 

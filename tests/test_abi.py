@@ -250,7 +250,7 @@ def test_neq_walls_validate_wall_state(lib):
     assert lib.lbm_workspace_size(ctypes.byref(p), ctypes.byref(n)) == binding.LBM_EINVAL
 
 
-@pytest.mark.parametrize("kw", [dict(eos=2), dict(eos=1), dict(eos=1, model=1, wall_y=2),
+@pytest.mark.parametrize("kw", [dict(eos=2), dict(eos=1),
                                 dict(eos=1, model=1, storage=1),
                                 dict(eos=1, model=1, vdw_a=-1.0),
                                 dict(eos=1, model=1, vdw_b=float("nan"))])
@@ -266,3 +266,49 @@ def test_van_der_waals_accepted_for_the_thermal_model(lib):
         rc, _ = _workspace(lib, eos=1, model=1, lattice=1, nz=4, storage=storage, vdw_a=0.27,
                            vdw_b=0.2)
         assert rc == 0
+
+
+def test_van_der_waals_neq_walls_need_supercritical_wall_isotherms(lib):
+    # the pressure-continued wall density solves P(rho_B, T_W) = P_N on the wall isotherm,
+    # which has one root only above T_cr = 8 a / (27 b R) = 1.2 here
+    n = ctypes.c_size_t(0)
+    for lattice, nz in ((0, 1), (1, 4)):
+        p = _neq_params(lib, eos=1, vdw_a=0.27, vdw_b=0.2, lattice=lattice, nz=nz)
+        p.wall_T[0], p.wall_T[1] = 1.4, 1.45
+        assert lib.lbm_workspace_size(ctypes.byref(p), ctypes.byref(n)) == 0
+        p.wall_T[0] = 1.1  # subcritical wall
+        assert lib.lbm_workspace_size(ctypes.byref(p), ctypes.byref(n)) == binding.LBM_EINVAL
+        p.wall_density = 1  # the literal density needs no root
+        assert lib.lbm_workspace_size(ctypes.byref(p), ctypes.byref(n)) == 0
+        p.wall_density, p.vdw_b, p.wall_T[0] = 0, 0.0, 1.4  # b = 0: no supercritical isotherm
+        assert lib.lbm_workspace_size(ctypes.byref(p), ctypes.byref(n)) == binding.LBM_EINVAL
+
+
+@pytest.mark.parametrize("lattice,model,storage,collision,wall_y,nz", [
+    (0, 0, 0, 0, 0, 1), (0, 0, 3, 0, 1, 1), (0, 0, 1, 0, 0, 1), (0, 0, 2, 0, 1, 1),
+    (0, 0, 0, 1, 0, 1), (0, 0, 0, 1, 1, 1), (0, 1, 0, 0, 1, 1), (0, 1, 3, 0, 2, 1),
+    (0, 1, 1, 0, 1, 1), (1, 0, 0, 0, 0, 5), (1, 0, 3, 0, 1, 3), (1, 1, 0, 0, 2, 3),
+    (1, 1, 3, 0, 0, 7)])
+def test_workspace_regions_are_256_byte_aligned(lib, lattice, model, storage, collision, wall_y,
+                                                nz):
+    # every region of the workspace (populations, diagnostics partials, history, read-out,
+    # the surrogate's 64-bit atomic counters and weights, derivative fields, wall rows) starts
+    # on a 256-byte boundary: lbm_workspace_size refuses a plan where one does not, so a
+    # successful size over ragged shapes and every configuration is the check
+    for nx, ny in ((3, 3), (37, 5), (100, 17), (257, 3), (1000, 33)):
+        p = _neq_params(lib, lattice=lattice, model=model, storage=storage, collision=collision,
+                        wall_y=wall_y, nx=nx, ny=ny, nz=nz)
+        for streaming in (0, 1, 2) if model == 0 and collision == 0 and storage in (0, 3) else (0,):
+            p.streaming = streaming
+            n = ctypes.c_size_t(0)
+            assert lib.lbm_workspace_size(ctypes.byref(p), ctypes.byref(n)) == 0, (nx, ny)
+            assert n.value % 256 == 0
+
+
+def test_mlp_gradient_batch_limit_checked_before_state(lib):
+    # at most 2^20 samples per gradient call (the partials take 22 KiB per 64 samples)
+    f = ctypes.c_float(0.0)
+    assert lib.lbm_mlp_grad(None, None, None, (1 << 20) + 1, None, ctypes.byref(f)) == binding.LBM_EINVAL
+    assert lib.lbm_mlp_grad(None, None, None, 0, None, ctypes.byref(f)) == binding.LBM_EINVAL
+    assert lib.lbm_mlp_grad(None, None, None, 1 << 20, None, ctypes.byref(f)) == binding.LBM_ESTATE
+

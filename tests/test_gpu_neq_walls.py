@@ -14,7 +14,7 @@ from oracle import ddf
 pytestmark = pytest.mark.gpu
 
 R, CV, P0 = 1.0 / 3.0, 5.0 / 6.0, 1.0 / 3.0
-STENCIL = {0: "central", 1: "central"}
+STENCIL = {0: "central", 1: "central", 2: "upwind"}
 
 
 @pytest.fixture(autouse=True)
@@ -27,12 +27,12 @@ def _lattice(rho, u, T, walls, **kw):
     return Lattice(rho, u, T, model="ddf", R=R, cv=CV, neq_walls=walls, **kw)
 
 
-# The upwind reading of the Phi derivative (phi = 2) picks its side by the sign of u_y, which on
-# the boundary rows is zero up to rounding (no normal wall velocity), so two float64
-# implementations may legitimately pick different sides there; parity is checked with the
-# central stencil and without Phi.
+# The upwind reading of the Phi derivative (phi = 2) picks its side by the sign of u_a; on the
+# boundary rows both the oracle and the kernels key it on the wall velocity (its normal
+# component is zero: central in y there), so every side choice is defined; the random fields
+# hold no exact zeros elsewhere.
 @pytest.mark.parametrize("density", ["pressure", "literal"])
-@pytest.mark.parametrize("phi", [1, 0])
+@pytest.mark.parametrize("phi", [1, 0, 2])
 def test_fp64_matches_oracle(phi, density):
     ny, nx, steps, tau = 37, 50, 7, 0.7
     announce("DDF NEQ walls fp64 %dx%d phi=%d density=%s %d steps" % (nx, ny, phi, density, steps))
@@ -54,7 +54,7 @@ def test_fp64_matches_oracle(phi, density):
     assert np.abs(rg - ro).max() <= 1e-13
     assert np.abs(ug - uo).max() <= 1e-13
     assert np.abs(tg - to).max() <= 1e-13
-    ft, gt = ddf.collide(f, g, gas, True, phi > 0, STENCIL[phi])
+    ft, gt = ddf.collide(f, g, gas, True, phi > 0, STENCIL[phi], neq=w)
     assert np.abs(fg - ft).max() <= 1e-13
     assert np.abs(gg - gt).max() <= 1e-13
 
@@ -88,7 +88,7 @@ def test_thermal_couette(storage, prandtl, tol):
 
 # ---- D3Q27: the boundary planes y = 0, ny - 1 rebuilt by k_ddf3_neq_rows --------------------
 @pytest.mark.parametrize("density", ["pressure", "literal"])
-@pytest.mark.parametrize("phi", [1, 0])
+@pytest.mark.parametrize("phi", [1, 0, 2])
 def test_d3q27_fp64_matches_oracle(phi, density):
     shape, steps, tau = (5, 7, 9), 5, 0.7
     announce("D3Q27 DDF NEQ walls fp64 %s phi=%d density=%s %d steps" % (shape, phi, density,
@@ -112,7 +112,7 @@ def test_d3q27_fp64_matches_oracle(phi, density):
     assert np.abs(rg - ro).max() <= 1e-13
     assert np.abs(ug - uo).max() <= 1e-13
     assert np.abs(tg - to).max() <= 1e-13
-    ft, gt = ddf.collide(f, g, gas, True, phi > 0, STENCIL[phi])
+    ft, gt = ddf.collide(f, g, gas, True, phi > 0, STENCIL[phi], neq=w)
     assert np.abs(fg - ft).max() <= 1e-13
     assert np.abs(gg - gt).max() <= 1e-13
 
@@ -196,3 +196,48 @@ def test_d3q27_diagnostics_history():
         row = h[t - 1]
         assert row[0] == t
         assert np.abs(row[1:] - np.array(want)).max() <= 1e-12 * ro.sum(), t
+
+
+# ---- van der Waals fluid (Sec. III C) with NEQ walls ----------------------------------------
+# Lattice units with R = 1/3: critical state T_cr = 1.2, P_cr = 0.25 (a = 0.27, b = 0.2); the
+# fields sit at T ~ 1.4, rho ~ 1 (theta = P/rho ~ 0.31), wall isotherms supercritical.
+VDW = (27.0 * R * R * 1.44 / (64.0 * 0.25), R * 1.2 / (8.0 * 0.25))
+
+
+def _vdw_fields(shape, seed):
+    rng = np.random.default_rng(seed)
+    T = 1.4 + 0.03 * rng.standard_normal(shape)
+    rho = 1.0 + 0.01 * rng.standard_normal(shape)
+    u = 0.02 * rng.standard_normal((len(shape),) + shape)
+    return rho, u, T
+
+
+@pytest.mark.parametrize("lattice", ["D2Q9", "D3Q27"])
+@pytest.mark.parametrize("density", ["pressure", "literal"])
+@pytest.mark.parametrize("phi", [1, 2])
+def test_vdw_fp64_matches_oracle(lattice, density, phi):
+    shape = (37, 50) if lattice == "D2Q9" else (5, 7, 9)
+    steps, tau = 6, 0.7
+    announce("vdW NEQ walls fp64 %s %s phi=%d density=%s %d steps" % (lattice, shape, phi,
+                                                                   density, steps))
+    rho, u, T = _vdw_fields(shape, 70 + phi)
+    D = len(shape)
+    uw = ((0.0,) * D, (0.04,) + (0.0,) * (D - 1))
+    walls = dict(u=uw, T=(1.38, 1.45), density=density)
+    lat = _lattice(rho, u, T, walls, lattice=lattice, tau=tau, phi=phi, storage="fp64",
+                   prandtl=0.8, vdw=VDW)
+    lat.step(steps)
+    rg, ug, tg, _ = lat.moments()
+    fg, gg = lat.populations()
+    lat.close()
+    gas = ddf.Gas(R, CV, (tau - 0.5) * P0, prandtl=0.8, a=VDW[0], b=VDW[1])
+    w = ddf.NeqWalls(uw[0], 1.38, uw[1], 1.45, density=density)
+    f, g = ddf.run(*ddf.init_equilibrium(rho, u, T, gas), gas, steps, phi_on=True,
+                   stencil=STENCIL[phi], neq=w)
+    ro, uo, to = ddf.temperature(f, g, gas)
+    assert np.abs(rg - ro).max() <= 1e-13
+    assert np.abs(ug - uo).max() <= 1e-13
+    assert np.abs(tg - to).max() <= 1e-13
+    ft, gt = ddf.collide(f, g, gas, True, True, STENCIL[phi], neq=w)
+    assert np.abs(fg - ft).max() <= 1e-13
+    assert np.abs(gg - gt).max() <= 1e-13

@@ -201,3 +201,47 @@ def test_long_horizon_10000_steps():
         _, ug, _, _ = lat.moments()
         lat.close()
         assert rel_l2(ug, uo) <= bar, storage
+
+
+@pytest.mark.parametrize("scale", [0, 8, 12, 20])
+def test_fp16_scale_exponents(scale):
+    # the float16 code stores (f - f^eq) 2^S: other exponents than the default S = 16 trade
+    # underflow of small non-equilibrium values (S small) against overflow headroom (S large);
+    # the 256^2 turbulence at tau 0.6 stays within the reduced-storage bar for all of them
+    announce("reduced fp16 S=%d turbulence 256^2 tau 0.6 300 steps" % scale)
+    rho, u = inputs.random_phase_turbulence_2d(256, seed=0)
+    _, ug, _ = _run(rho, u, 0.6, 300, "fp16", fp16_scale_log2=scale)
+    _, uo = _oracle(rho, u, 0.6, 300)
+    err = rel_l2(ug, uo)
+    print("fp16 S=%d: velocity rel-L2 %.3e" % (scale, err), flush=True)
+    assert err <= 1e-3
+
+
+def test_fp16_scale_exponent_in_the_double_distribution_kernel():
+    announce("reduced fp16 S=12 DDF 128x64 walls 300 steps")
+    from oracle import ddf
+    rho, u, T = inputs.thermal_shear_layer(128, seed=0, ny=64)
+    lat = _lattice(rho, u, T, model="ddf", tau=0.6, wall_y=True, phi=1, storage="fp16",
+                   fp16_scale_log2=12)
+    lat.step(300)
+    _, ug, tg, _ = lat.moments()
+    lat.close()
+    gas = ddf.Gas(1.0 / 3.0, 5.0 / 6.0, 0.1 / 3.0)
+    f, g = ddf.run(*ddf.init_equilibrium(rho, u, T, gas), gas, 300, walls_y=True)
+    _, uo, to = ddf.temperature(f, g, gas)
+    assert rel_l2(ug, uo) <= 1e-3
+    assert rel_l2(tg - to.mean(), to - to.mean()) <= 1e-3
+
+
+@pytest.mark.parametrize("storage", CODECS)
+def test_tall_lattice_beyond_the_grid_row_limit(storage):
+    # 3 x 1.1e6 nodes: with 16 rows per workgroup the row tiles would exceed the 65535 limit of
+    # the grid's second dimension; the plan takes more rows per workgroup instead
+    ny, nx, steps = 1_100_000, 3, 2
+    announce("reduced %s tall lattice %dx%d %d steps" % (storage, nx, ny, steps))
+    rng = np.random.default_rng(44)
+    rho = 1.0 + 0.01 * rng.standard_normal((ny, nx))
+    u = 0.03 * rng.standard_normal((2, ny, nx))
+    _, ug, _ = _run(rho, u, 0.7, steps, storage)
+    _, uo = _oracle(rho, u, 0.7, steps)
+    assert rel_l2(ug, uo) <= 1e-3
