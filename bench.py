@@ -85,15 +85,30 @@ def variant(name, make, steps, warmup, bytes_per_node, extra=None):
     return out
 
 
-def surrogate_variant(binding, inputs, steps):
+def surrogate_variant(binding, inputs, steps, inference_only=False):
     """Surrogate recipe: 1M training pairs harvested from 2048^2 turbulence runs at three tau,
     BF16 training (48000 Adam steps of batch 4096, learning rate 2e-3, 6e-4, 2e-4 in three equal
     stages), inference timed at 2048^2 (seed 5, tau 0.6) with the per-node plain judge;
-    velocity rel-L2 against the FP64 oracle measured on a 256^2 held-out run."""
+    velocity rel-L2 against the FP64 oracle measured on a 256^2 held-out run.
+    inference_only: skip harvest and training and time the inference with the initial weights
+    (for profiling: the inference kernel evaluates the network and the plain collision at every
+    node whatever the weights, so its work does not depend on them)."""
     import torch
     from paper_2609_28679_amd import surrogate
     from oracle import bgk
     from oracle.equilibrium import moments
+    if inference_only:
+        rho, u = inputs.random_phase_turbulence_2d(2048, seed=5)
+        lat = binding.Lattice(rho, u, tau=0.6, collision="mlp")
+        lat.set_mlp(binding.pack_mlp(inputs.mlp_init(11)), 0.05)
+        wall, ms = time_lattice(lat, steps, 10)
+        nodes = lat.nodes
+        lat.close()
+        per = ms / 1e3 / steps
+        out = {"mlups": round(nodes * steps / wall / 1e6, 1), "kernel_us": round(per * 1e6, 2),
+               "weights": "initial (inference only)"}
+        log("surrogate (inference only): %s" % out)
+        return out
     t0 = time.perf_counter()
     fields = inputs.random_phase_turbulence_2d(2048, seed=0)
     X, Y = surrogate.harvest(fields, [0.51, 0.6, 1.0], 1_000_000, (100, 10000), 20, seed=1)
@@ -139,28 +154,32 @@ def surrogate_variant(binding, inputs, steps):
     return out
 
 
-def copy_ceiling(reps=20):
-    """Device-to-device copy of 1 GiB (read 1 GiB + write 1 GiB) timed with HIP events on
-    torch's current stream, on which the copy runs: the bandwidth a streaming kernel can reach
-    when nothing stays in the 256 MB last-level cache."""
+def copy_ceiling(binding, reps=20):
+    """Device-to-device copy of 1 GiB (read 1 GiB + write 1 GiB) with the library's streaming
+    copy kernel and with the runtime's copy (torch copy_), timed with HIP events on torch's
+    current stream, on which both run: the bandwidth a streaming kernel reaches when nothing
+    stays in the 256 MB last-level cache."""
     import torch
     n = 1 << 28
     src = torch.ones(n, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
-    for _ in range(3):
-        dst.copy_(src)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        dst.copy_(src)
-    e1.record()
-    e1.synchronize()
-    us = e0.elapsed_time(e1) * 1e3 / reps
+    out = {"bytes_moved": 2 * n * 4}
+    for name, fn in (("lbm_device_copy", lambda: binding.device_copy(src, dst)),
+                     ("runtime_copy", lambda: dst.copy_(src))):
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        out[name] = {"us": round(us, 2), "GBs": round(2 * n * 4 / us / 1e3, 1),
+                     "frac_of_peak": round(2 * n * 4 / us / 1e3 / HBM_PEAK_GBS, 4)}
     del src, dst
     torch.cuda.empty_cache()
-    moved = 2 * n * 4
-    return {"bytes_moved": moved, "us": round(us, 2), "GBs": round(moved / us / 1e3, 1),
-            "frac_of_peak": round(moved / us / 1e3 / HBM_PEAK_GBS, 4)}
+    return out
 
 
 def cpu_baseline():
@@ -192,6 +211,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", default="",
                     help="comma-separated variant names to run (default: all)")
+    ap.add_argument("--surrogate-inference-only", action="store_true",
+                    help="surrogate variant without harvest and training (profiling)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -245,7 +266,7 @@ def main():
     torch.cuda.empty_cache()
     per4 = ms4 / 1e3 / steps4
     achieved4 = bytes_per_node * nodes4 / per4 / 1e9
-    copy = copy_ceiling()
+    copy = copy_ceiling(binding)
     log("4096^2: kernel %.2f us, %.1f GB/s; 1 GiB copy: %s" % (per4 * 1e6, achieved4, copy))
 
     variants = {}
@@ -377,8 +398,8 @@ def main():
             ("d2q9_bgk_fp16_2048", lambda n: variant(
                 n, lambda: binding.Lattice(rho, u, tau=tau, storage="fp16"), vs, 20, 48,
                 {"storage": red % "fp16"})),
-            ("d2q9_bgk_mlp_2048", lambda n: surrogate_variant(binding, inputs,
-                                                              max(100, vs // 4))),
+            ("d2q9_bgk_mlp_2048", lambda n: surrogate_variant(
+                binding, inputs, max(100, vs // 4), args.surrogate_inference_only)),
             ("d2q9_bgk_fp64_2048", lambda n: variant(
                 n, lambda: binding.Lattice(rho, u, tau=tau, storage="fp64"),
                 max(200, vs // 4), 20, 144)),

@@ -229,6 +229,14 @@ int lbm_mlp_grad(lbm_mlp* m, const float* dev_x, const float* dev_t, int64_t n,
 int lbm_mlp_train(lbm_mlp* m, const float* dev_x, const float* dev_t, int64_t n,
                   int32_t batch, int64_t steps, float lr);
 
+/* ---- measurement ------------------------------------------------------------------------
+   Not part of the method: a device-to-device copy of `bytes` bytes (src and dst device
+   pointers, 16-byte aligned, not overlapping), enqueued on `stream` with the access pattern of a
+   streaming step (every byte read once and written once, 16-byte non-temporal loads and
+   stores). Its bandwidth is the practical ceiling the roofline figures are compared with.
+   LBM_EINVAL for NULL or misaligned pointers, LBM_EDEVICE if the launch fails. */
+int lbm_device_copy(const void* src, void* dst, size_t bytes, void* stream);
+
 /* Text of the last error of ctx, or of the calling thread's last context-free error if ctx
    is NULL. Never NULL; valid until the next call on the same context or thread. */
 const char* lbm_last_error(const lbm_ctx* ctx);

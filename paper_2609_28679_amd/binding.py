@@ -71,6 +71,7 @@ SIGNATURES = {
     "lbm_mlp_forward": (ctypes.c_int, [_P, _P, _I64, _P]),
     "lbm_mlp_grad": (ctypes.c_int, [_P, _P, _P, _I64, _P, _F]),
     "lbm_mlp_train": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.c_int32, _I64, ctypes.c_float]),
+    "lbm_device_copy": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
     "lbm_last_error": (ctypes.c_char_p, [_P]),
     "lbm_destroy": (None, [_P]),
 }
@@ -314,6 +315,16 @@ class Trainer:
             self.close()
         except Exception:
             pass
+
+
+def device_copy(src, dst):
+    """lbm_device_copy of a cuda tensor into another of the same size, on torch's current
+    stream (the bandwidth reference of the roofline figures)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("size mismatch")
+    _check(load().lbm_device_copy(src.data_ptr(), dst.data_ptr(), nbytes,
+                                  current_stream_handle()))
 
 
 def pack_mlp(params):

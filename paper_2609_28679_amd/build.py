@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
 
-SOURCES = ["lbm_api.hip", "bgk.hip", "ddf.hip", "ddf3.hip", "reduced.hip", "mlp.hip"]
+SOURCES = ["lbm_api.hip", "bgk.hip", "ddf.hip", "ddf3.hip", "reduced.hip", "mlp.hip", "copy.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
@@ -38,8 +38,11 @@ def _run(cmd, verbose):
 
 
 def build(verbose=False):
-    """Compile each source to an object in parallel (no device code crosses files), then link."""
+    """Compile each source to an object in parallel (no device code crosses files), then link.
+    LBM_EXTRA_HIPCC_FLAGS (environment) adds flags, e.g. -DLBM_TUNING_ENV for launch-shape
+    sweeps through environment variables."""
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    inc += os.environ.get("LBM_EXTRA_HIPCC_FLAGS", "").split()
     tmpdir = tempfile.mkdtemp(prefix="lbm_build_")
     try:
         objs = [os.path.join(tmpdir, os.path.splitext(s)[0] + ".o") for s in SOURCES]

@@ -8,6 +8,12 @@
 // order, then the Adam update of the float32 master weights).
 #include "mlp_common.h"
 
+#include <algorithm>
+#include <cfloat>
+#include <cstdlib>
+
+#include "lbm.h"
+
 namespace lbm {
 
 constexpr int kPart = kNParam + 1;  // parameters + loss
@@ -241,30 +247,75 @@ __global__ void k_mlp_reduce_adam(const float* __restrict__ partials, int nw, fl
   }
 }
 
-// Forward pass for n samples (projected outputs).
+// Per-wave LDS rows of the inference kernels: a sample's 12 bfloat16 inputs (zero padded to
+// 24) and, once its tile has been evaluated, the same row's 12 float32 outputs (9 used). The
+// outputs of tile n overwrite the inputs of tile n only, which that tile has already read.
+constexpr int kIoS = 12;  // floats per row (48 bytes)
+
+// Orders this wave's LDS writes before other lanes of the same wave read them: LDS operations
+// of one wave execute in order, so only the compiler has to be kept from moving memory
+// operations across this point (no workgroup barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Network of the four tiles of one wave: inputs in io rows (bfloat16), outputs back into the
+// same rows (float32, C layout scattered to rows).
+__device__ __forceinline__ void mlp_wave_tiles(const MlpLdsP& s, float (*io)[kIoS]) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, q = lane >> 4;
+  const short(*xs)[2 * kIoS] = reinterpret_cast<const short(*)[2 * kIoS]>(io);
+#pragma unroll 1
+  for (int nt = 0; nt < 4; ++nt) {
+    // The weights are re-read from LDS for every tile instead of being hoisted into registers
+    // across the tiles (fewer registers, more wavefronts in flight): z is 0, but the compiler
+    // cannot see it, so the reads stay in the loop; laundering an index rather than the
+    // pointer keeps them LDS reads.
+    int z = 0;
+    asm volatile("" : "+v"(z));
+    const f32x4 yt = mlp_forward_tile32<2 * kIoS>(s, xs, nt, z);
+    if (q < 3) {  // output rows 0..11 (9 used)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) io[16 * nt + r][4 * q + j] = yt[j];
+    }
+  }
+}
+
+// A sample's 12 inputs as bfloat16 pairs in the first 6 words of its row, zeros in the next 2
+// (the layer-1 tile reads 16 inputs); written as two 16-byte stores (rows are 48-byte aligned).
+__device__ __forceinline__ void put_inputs(float* row, const float (&xf)[kIn], bool valid) {
+  typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+  unsigned w[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k)
+    w[k] = valid ? ((unsigned)(uint16_t)f2bf(xf[2 * k]) | ((unsigned)(uint16_t)f2bf(xf[2 * k + 1]) << 16))
+                 : 0u;
+  u32x4* r = reinterpret_cast<u32x4*>(__builtin_assume_aligned(row, 16));
+  r[0] = u32x4{w[0], w[1], w[2], w[3]};
+  r[1] = u32x4{w[4], w[5], 0u, 0u};
+}
+
+// Forward pass for n samples (projected outputs), on the inference tiles.
 __global__ void __launch_bounds__(kBlock)
 k_mlp_forward(const float* __restrict__ X, int64_t n, const float* __restrict__ w, float* __restrict__ Y) {
-  __shared__ MlpLds s;
-  __shared__ __attribute__((aligned(16))) short xs[4][64][16];
-  __shared__ float ys[4][64][16];
+  __shared__ MlpLdsP s;
+  __shared__ __attribute__((aligned(16))) float io[4][64][kIoS];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t i = ((int64_t)blockIdx.x * 4 + wv) * 64 + lane;
   const bool valid = i < n;
-  mlp_load_lds(w, s);
+  mlp_load_lds_vec(w, s);
+  float xf[kIn];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) xs[wv][lane][k] = (valid && k < kIn) ? f2bf(X[i * kIn + k]) : (short)0;
-  __syncthreads();
-  const int r = lane & 15, q = lane >> 4;
-#pragma unroll
-  for (int nt = 0; nt < 4; ++nt) {
-    const f32x4 yt = mlp_forward_tile(s, xs[wv], nt);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) ys[wv][16 * nt + r][4 * q + j] = yt[j];
-  }
-  __syncthreads();
+  for (int k = 0; k < kIn; ++k) xf[k] = valid ? X[i * kIn + k] : 0.0f;
+  put_inputs(io[wv][lane], xf, valid);
+  __syncthreads();  // the weights
+  mlp_wave_tiles(s, io[wv]);
+  wave_lds_sync();
   float y[9];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) y[k] = ys[wv][lane][k];
+  for (int k = 0; k < 9; ++k) y[k] = io[wv][lane][k];
   project9(y);
   if (valid)
 #pragma unroll
@@ -351,88 +402,123 @@ __global__ void k_harvest(const float* __restrict__ A, int nx, int ny, int64_t p
   for (int i = 0; i < 9; ++i) Y[k * kOut + i] = (float)((1.0 - omega) * (double)xf[i]);
 }
 
-// One D2Q9 step with the surrogate collision and the per-node plain-collision judge.
+// One D2Q9 step with the surrogate collision and the per-node plain-collision judge, in float32
+// on the shifted values h = f - w (w the rest weights). With theta = 1/3 the per-axis factors
+// are psi_c = W_c + d_c, W = (1/6, 2/3, 1/6), d_0 = -u^2, d_+- = (u^2 +- u)/2, and
+//   h^eq_i = f^eq_i - w_i = (rho - 1) psi_a psi_b + W_a d_b + d_a W_b + d_a d_b,
+// with float32 constants whose sum is exactly one (W_+- = 2796203 2^-24, W_0 = 1 - 2 W_+-:
+// with the nearest float32 values of 1/6 and 2/3 the sum of the factors misses one by 3e-8 and
+// every collision rescales mass and momentum by that amount).
+//   features  x = [1024 (h_i - h^eq_i)/rho, 16 u_x, 16 u_y, omega]
+//   network   y (projected), surrogate f~ = f^eq + rho y / 1024
+//   judge     |f~_mlp - f~_plain| <= tol |f~_plain - f^eq| with f~_plain - f^eq = (1 - omega)(f - f^eq),
+//             i.e. |y - (1 - omega) x_neq| <= tol |1 - omega| |x_neq| (the factor rho / 1024 cancels)
+//   fallback  h~ = h + omega (h^eq - h)
+// One wavefront evaluates the network for its 64 nodes of a row; only the weights are shared by
+// the workgroup (one barrier after their load), the rest of a row is synchronised per wave.
 template <bool WALLS, bool DIAG>
 __global__ void __launch_bounds__(kBlock)
 k_bgk_d2q9_mlp(const float* __restrict__ A, float* __restrict__ B, int nx, int ny, int64_t pitch,
-               int64_t plane, double omega, int rows, const float* __restrict__ wblob, double tol,
+               int64_t plane, float omega, int rows, const float* __restrict__ wblob, float tol2,
                unsigned long long* __restrict__ counters, double* __restrict__ partials) {
-  __shared__ MlpLds s;
-  __shared__ __attribute__((aligned(16))) short xs[4][64][16];
-  __shared__ float ys[4][64][16];
+  __shared__ MlpLdsP s;
+  __shared__ __attribute__((aligned(16))) float io[4][64][kIoS];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int r = lane & 15, q = lane >> 4;
   const int nbx = gridDim.x;
   const int tile = xcd_tile(blockIdx.x + nbx * blockIdx.y, nbx * gridDim.y);
   const int bx = tile % nbx, by = tile / nbx;
   const int x = bx * blockDim.x + threadIdx.x;
   const bool valid = x < nx;
   const int y0 = by * rows, yend = min(y0 + rows, ny);
+  const float W1 = 2796203.0f / 16777216.0f, W0 = 1.0f - 2.0f * W1;  // exact in float32
+  const float keep = 1.0f - omega;
   double acc[kDiagValues] = {0.0, 0.0, 0.0, 0.0, 0.0};
   unsigned fallbacks = 0;
-  mlp_load_lds(wblob, s);
-  for (int y = y0; y < yend; ++y) {
-    // the shifted float32 values are kept across the network (9 registers instead of 18)
-    float h[9];
-    double rho = 1.0, ux = 0.0, uy = 0.0;
-    float xf[12];
+  mlp_load_lds_vec(wblob, s);
+  // One row: features, network, judge and store from the pulled populations h of row y.
+  auto row = [&](const float (&h)[9], int y) {
+    float heq[9], xf[kIn];
+    float drho = 0.0f, ux = 0.0f, uy = 0.0f;
     if (valid) {
-      pull9h<WALLS>(A, nx, ny, pitch, plane, x, y, h);
-      double f[9];
+      drho = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
+      const float jx = (h[2] + h[5] + h[8]) - (h[0] + h[3] + h[6]);
+      const float jy = (h[6] + h[7] + h[8]) - (h[0] + h[1] + h[2]);
+      const float inv = __builtin_amdgcn_rcpf(1.0f + drho);
+      // u = j / rho with one residual correction of the hardware reciprocal (unbiased: a
+      // one-sided velocity error would shift every node's momentum the same way each step)
+      ux = jx * inv;
+      uy = jy * inv;
+      ux = __builtin_fmaf(__builtin_fmaf(-(1.0f + drho), ux, jx), inv, ux);
+      uy = __builtin_fmaf(__builtin_fmaf(-(1.0f + drho), uy, jy), inv, uy);
+      const float u2x = ux * ux, u2y = uy * uy;
+      const float dx[3] = {0.5f * (u2x - ux), -u2x, 0.5f * (u2x + ux)};
+      const float dy[3] = {0.5f * (u2y - uy), -u2y, 0.5f * (u2y + uy)};
+      const float Wk[3] = {W1, W0, W1};
+      const float sx = kSNeq * inv;
 #pragma unroll
-      for (int i = 0; i < 9; ++i) f[i] = (double)h[i] + wrest(i);
-      rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
-      ux = ((f[2] + f[5] + f[8]) - (f[0] + f[3] + f[6])) / rho;
-      uy = ((f[6] + f[7] + f[8]) - (f[0] + f[1] + f[2])) / rho;
-      mlp_features(f, rho, ux, uy, omega, xf);
+      for (int i = 0; i < 9; ++i) {
+        const int ia = i % 3, ib = i / 3;
+        const float pa = Wk[ia] + dx[ia], pb = Wk[ib] + dy[ib];
+        heq[i] = drho * (pa * pb) + (Wk[ia] * dy[ib] + dx[ia] * Wk[ib] + dx[ia] * dy[ib]);
+        xf[i] = (h[i] - heq[i]) * sx;
+      }
+      xf[9] = kSU * ux;
+      xf[10] = kSU * uy;
+      xf[11] = omega;
     } else {
 #pragma unroll
-      for (int i = 0; i < 12; ++i) xf[i] = 0.0f;
-    }
+      for (int i = 0; i < 9; ++i) heq[i] = 0.0f;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) xs[wv][lane][k] = k < kIn ? f2bf(xf[k]) : (short)0;
-    __syncthreads();
-    // The weights are re-read from LDS for every tile instead of living in registers across
-    // the row loop: fewer registers, more wavefronts in flight.
-    const MlpLds* sw = &s;
-    asm volatile("" : "+v"(sw));
-#pragma unroll 1
-    for (int nt = 0; nt < 4; ++nt) {
-      const f32x4 yt = mlp_forward_tile(*sw, xs[wv], nt);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) ys[wv][16 * nt + r][4 * q + j] = yt[j];
+      for (int i = 0; i < kIn; ++i) xf[i] = 0.0f;
     }
-    __syncthreads();
+    wave_lds_sync();  // the previous row's outputs have been read
+    put_inputs(io[wv][lane], xf, valid);
+    wave_lds_sync();
+    mlp_wave_tiles(s, io[wv]);
+    wave_lds_sync();
     if (valid) {
       float yv[9];
 #pragma unroll
-      for (int i = 0; i < 9; ++i) yv[i] = ys[wv][lane][i];
+      for (int i = 0; i < 9; ++i) yv[i] = io[wv][lane][i];
       project9(yv);
-      const double u2x = ux * ux, u2y = uy * uy;
-      const double px[3] = {1.0 / 6.0 + 0.5 * (u2x - ux), 2.0 / 3.0 - u2x, 1.0 / 6.0 + 0.5 * (u2x + ux)};
-      const double py[3] = {1.0 / 6.0 + 0.5 * (u2y - uy), 2.0 / 3.0 - u2y, 1.0 / 6.0 + 0.5 * (u2y + uy)};
-      double fm[9], fp[9], err = 0.0, ref = 0.0;
+      float err = 0.0f, ref = 0.0f;
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
-        const double feq = rho * px[i % 3] * py[i / 3];
-        const double fi = (double)h[i] + wrest(i);
-        fm[i] = feq + rho * (double)yv[i] * (1.0 / kSNeq);  // surrogate
-        fp[i] = fi + omega * (feq - fi);                    // paper's collision
-        err += (fm[i] - fp[i]) * (fm[i] - fp[i]);
-        ref += (fp[i] - feq) * (fp[i] - feq);
+        const float d = yv[i] - keep * xf[i];
+        err += d * d;
+        ref += xf[i] * xf[i];
       }
-      const bool fb = !(err <= tol * tol * ref);
+      const bool fb = !(err <= tol2 * (keep * keep) * ref);
       fallbacks += fb ? 1u : 0u;
+      const float rs = (1.0f + drho) * (1.0f / kSNeq);
       float* out = B + (int64_t)y * pitch + x;
 #pragma unroll
-      for (int i = 0; i < 9; ++i) store_nt(out + i * plane, (float)((fb ? fp[i] : fm[i]) - wrest(i)));
+      for (int i = 0; i < 9; ++i)
+        store_nt(out + i * plane, fb ? h[i] + omega * (heq[i] - h[i]) : heq[i] + rs * yv[i]);
       if (DIAG) {
+        const double rho = 1.0 + (double)drho;
         acc[0] += rho;
-        acc[1] += rho * ux;
-        acc[2] += rho * uy;
-        acc[4] += 0.5 * rho * (ux * ux + uy * uy);
+        acc[1] += rho * (double)ux;
+        acc[2] += rho * (double)uy;
+        acc[4] += 0.5 * rho * ((double)ux * ux + (double)uy * uy);
       }
     }
+  };
+  // Rows in pairs with two pull buffers: the populations of the next row are loaded while the
+  // network of the current one runs (software pipelining without register copies).
+  // The loads are unconditional (lanes past the edge read the last column, a pull past the
+  // last row re-reads it), so that the compiler's wait for one buffer never includes the other.
+  float ha[9], hb[9];
+  const int xl = valid ? x : nx - 1;
+  const int ylast = yend - 1;
+  if (y0 < yend) pull9h<WALLS>(A, nx, ny, pitch, plane, xl, y0, ha);
+  __syncthreads();
+  for (int y = y0; y < yend; y += 2) {
+    pull9h<WALLS>(A, nx, ny, pitch, plane, xl, min(y + 1, ylast), hb);
+    row(ha, y);
+    if (y + 1 >= yend) break;
+    pull9h<WALLS>(A, nx, ny, pitch, plane, xl, min(y + 2, ylast), ha);
+    row(hb, y + 1);
   }
   // integer fallback counts: order-independent, so atomics stay deterministic
   unsigned long long fb = (unsigned long long)fallbacks;
@@ -490,22 +576,29 @@ Grid make_grid_mlp(const Layout& L) {
   G.bx = kBlock;
   G.nbx = (L.nx + kBlock - 1) / kBlock;
   G.rows = 8;  // amortises the per-workgroup weight load over 8 rows
+#ifdef LBM_TUNING_ENV
+  if (const char* v = getenv("LBM_MLP_ROWS")) G.rows = atoi(v);
+#endif
   fit_rows(G, L.ny);
   return G;
 }
 
-hipError_t launch_bgk_d2q9_mlp(const void* A, void* B, const Layout& L, const Grid& G, double omega,
-                               bool walls, const float* wblob, double tol,
+hipError_t launch_bgk_d2q9_mlp(const void* A, void* B, const Layout& L, const Grid& G, double omega_d,
+                               bool walls, const float* wblob, double tol_d,
                                unsigned long long* counters, double* partials, hipStream_t s) {
   dim3 grid(G.nbx, G.nby), block(kBlock);
   auto a = static_cast<const float*>(A);
   auto b = static_cast<float*>(B);
+  const float omega = (float)omega_d;
+  // tol^2 as a finite float32 (a huge tolerance then still gives 0 * tol^2 = 0 where the
+  // non-equilibrium part vanishes, as the float64 comparison does)
+  const float tol2 = (float)std::min(tol_d * tol_d, (double)FLT_MAX);
   if (walls) {
-    if (partials) k_bgk_d2q9_mlp<true, true><<<grid, block, 0, s>>>(a, b, L.nx, L.ny, L.pitch, L.plane, omega, G.rows, wblob, tol, counters, partials);
-    else k_bgk_d2q9_mlp<true, false><<<grid, block, 0, s>>>(a, b, L.nx, L.ny, L.pitch, L.plane, omega, G.rows, wblob, tol, counters, nullptr);
+    if (partials) k_bgk_d2q9_mlp<true, true><<<grid, block, 0, s>>>(a, b, L.nx, L.ny, L.pitch, L.plane, omega, G.rows, wblob, tol2, counters, partials);
+    else k_bgk_d2q9_mlp<true, false><<<grid, block, 0, s>>>(a, b, L.nx, L.ny, L.pitch, L.plane, omega, G.rows, wblob, tol2, counters, nullptr);
   } else {
-    if (partials) k_bgk_d2q9_mlp<false, true><<<grid, block, 0, s>>>(a, b, L.nx, L.ny, L.pitch, L.plane, omega, G.rows, wblob, tol, counters, partials);
-    else k_bgk_d2q9_mlp<false, false><<<grid, block, 0, s>>>(a, b, L.nx, L.ny, L.pitch, L.plane, omega, G.rows, wblob, tol, counters, nullptr);
+    if (partials) k_bgk_d2q9_mlp<false, true><<<grid, block, 0, s>>>(a, b, L.nx, L.ny, L.pitch, L.plane, omega, G.rows, wblob, tol2, counters, partials);
+    else k_bgk_d2q9_mlp<false, false><<<grid, block, 0, s>>>(a, b, L.nx, L.ny, L.pitch, L.plane, omega, G.rows, wblob, tol2, counters, nullptr);
   }
   return hipGetLastError();
 }

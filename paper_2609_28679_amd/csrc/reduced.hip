@@ -13,140 +13,222 @@
 
 namespace lbm {
 
-__device__ __forceinline__ double psi_c(int c, double u) {
-  const double u2 = u * u;
-  return c == 0 ? (2.0 / 3.0) - u2 : (1.0 / 6.0) + 0.5 * (u2 + c * u);
-}
-
-// LDS-staged kernel. A workgroup owns 256 columns and `rows` rows and walks them bottom to
-// top. Each row that enters the 3-row window is decoded once, node by node, into its nine
-// post-collision populations (float32 in LDS, 258 columns with the periodic x halo); the pull
-// then reads the nine sources of a node from LDS. Every stored byte is read once per workgroup
-// with coalesced loads and every node's equilibrium is rebuilt once.
-//
-// Arithmetic is in shifted form: h_i = f_i - w_i (w the rest weights), and with
-// psi_c = W_c + d_c (W = 2/3, 1/6, 1/6; d_0 = -u^2, d_+- = (u^2 +- u)/2) the equilibrium is
+// Arithmetic is float32 on shifted values h_i = f_i - w_i (w the rest weights). With
+// theta = 1/3 the per-axis factors are psi_c = W_c + d_c, W = (1/6, 2/3, 1/6), d_0 = -u^2,
+// d_+- = (u^2 +- u)/2, and
 //   f_i^eq - w_i = (rho - 1) psi_a psi_b + (W_a d_b + d_a W_b + d_a d_b).
-// The rebuild of the stored rows runs in float64 (held in LDS as float32 h), the collision in
-// float32. A float32 rebuild drifts coherently: the float32 values of W repeat the same
-// rounding at every node and step, and the velocity rel-L2 against the float64 scheme grew
-// linearly to 5e-4 (tau 0.6) and 1.1e-3 (tau 0.51) after 10^4 steps at 256^2, the same for
-// bfloat16 and float16 codes. With the float64 rebuild it stays at the storage level:
-// bfloat16 1.7e-5 / 8e-5, float16 1.8e-6 / 1.4e-5 after 10^4 steps (tau 0.6 / 0.51), at 52 us
-// per 2048^2 step (all float32: 47 us; all float64: 58 us).
-constexpr int kRedCols = kBlock + 2;
-
-template <typename T>
-__device__ __forceinline__ void dpsi3(T u, T (&d)[3]) {
-  const T u2 = u * u;
-  d[0] = T(0.5) * (u2 - u);
-  d[1] = -u2;
-  d[2] = T(0.5) * (u2 + u);
+// The float32 constants are W_+- = 2796203 2^-24 and W_0 = 1 - 2 W_+- (exact), so the factors
+// sum to one exactly; with the nearest float32 values of 1/6 and 2/3 they miss it by 3e-8 and
+// every rebuild shifts a node's mass by that fraction, the same way at every step.
+//
+// Rebuild of a stored node (moments m, six codes): h_i = h^eq_i(m) + n_i for the six stored
+// directions, then the remaining three from the node's own conserved sums, which the state
+// holds exactly as stored moments:
+//   h_5 = j_x - (h_2 + h_8) + (h_0 + h_3 + h_6),  h_7 = j_y - (h_6 + h_8) + (h_0 + h_1 + h_2),
+//   h_4 = (rho - 1) - sum_{i != 4} h_i,  j = rho u.
+// (In exact arithmetic this equals h^eq + n with n_5, n_7, n_4 from the zero sums of the
+// non-equilibrium part; in float32 it keeps the rounding of the equilibrium out of the rebuilt
+// mass and momentum, which otherwise repeats at a node from step to step: a float32 rebuild
+// h^eq + n drifted to a velocity rel-L2 of 6e-5 against the float64 scheme after 10^4 steps of
+// 256^2 turbulence at tau 0.51 with float32 non-equilibrium values.)
+// u = j / rho to within half an ulp or so, unbiased: the hardware reciprocal alone (1 ulp)
+// errs to one side for a given rho, and a stored velocity that is always slightly small or
+// large rebuilds a momentum that shrinks or grows the same way at every step (a velocity
+// drift of 1e-4 after 10^4 steps); one residual correction r = j - rho q (exact with fma)
+// removes that bias.
+__device__ __forceinline__ float quotient(float j, float rho) {
+  const float inv = __builtin_amdgcn_rcpf(rho);
+  const float q = j * inv;
+  return __builtin_fmaf(__builtin_fmaf(-rho, q, j), inv, q);
 }
-template <typename T>
-__device__ __forceinline__ T wk(int k) { return k == 1 ? T(2) / T(3) : T(1) / T(6); }
 
-// f_i^eq - w_i for the nine directions from drho = rho - 1 and the per-axis deviations
-template <typename T>
-__device__ __forceinline__ T heq_i(int i, T drho, const T (&dx)[3], const T (&dy)[3]) {
+constexpr float kW1 = 2796203.0f / 16777216.0f;
+constexpr float kW0 = 1.0f - 2.0f * kW1;
+
+__device__ __forceinline__ float wk(int k) { return k == 1 ? kW0 : kW1; }
+
+__device__ __forceinline__ void dpsi3(float u, float (&d)[3]) {
+  const float u2 = u * u;
+  d[0] = 0.5f * (u2 - u);
+  d[1] = -u2;
+  d[2] = 0.5f * (u2 + u);
+}
+
+// f_i^eq - w_i from drho = rho - 1 and the per-axis deviations
+__device__ __forceinline__ float heq_i(int i, float drho, const float (&dx)[3], const float (&dy)[3]) {
   const int a = i % 3, b = i / 3;
-  const T pa = wk<T>(a) + dx[a], pb = wk<T>(b) + dy[b];
-  return drho * (pa * pb) + (wk<T>(a) * dy[b] + dx[a] * wk<T>(b) + dx[a] * dy[b]);
+  const float pa = wk(a) + dx[a], pb = wk(b) + dy[b];
+  return drho * (pa * pb) + (wk(a) * dy[b] + dx[a] * wk(b) + dx[a] * dy[b]);
+}
+
+// Stored values of one node: moments (rho - 1, u_x, u_y) and the six codes.
+struct RawNode {
+  float m[3];
+  uint16_t n[kRedF];
+};
+
+__device__ __forceinline__ void load_node(const float* __restrict__ M, const uint16_t* __restrict__ N,
+                                          int64_t plane, int64_t off, RawNode& v) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) v.m[k] = load_nt(M + k * plane + off);
+#pragma unroll
+  for (int k = 0; k < kRedF; ++k) v.n[k] = load_nt(N + k * plane + off);
+}
+
+// Post-collision populations (shifted, h = f~ - w) of a stored node, rebuilt as described above.
+template <typename Codec>
+__device__ __forceinline__ void rebuild_node(const RawNode& v, float s_dec, float (&h)[9]) {
+  const float drho = v.m[0], ux = v.m[1], uy = v.m[2];
+  float dx[3], dy[3];
+  dpsi3(ux, dx);
+  dpsi3(uy, dy);
+#pragma unroll
+  for (int i = 0; i < 9; ++i)
+    if (f_slot(i) >= 0) h[i] = heq_i(i, drho, dx, dy) + Codec::dec(v.n[f_slot(i)], s_dec);
+  const float rho = 1.0f + drho;
+  h[5] = rho * ux - (h[2] + h[8]) + (h[0] + h[3] + h[6]);
+  h[7] = rho * uy - (h[6] + h[8]) + (h[0] + h[1] + h[2]);
+  h[4] = drho - (((h[0] + h[1]) + (h[2] + h[3])) + ((h[5] + h[6]) + (h[7] + h[8])));
+}
+
+// Wavefront-strip kernel. A wavefront owns 64 consecutive columns (x0 = 64 k) and `rows` rows
+// and walks them bottom to top; nothing is shared between wavefronts, so there is no barrier.
+// Each lane rebuilds the post-collision populations of its own column once per row and keeps
+// the last three rows in registers; a pull from column x - c_x takes the value from the lane
+// to the left or right with one wave-wide DPP shift, and the two columns beyond the strip
+// (x0 - 1 and x0 + 64, periodic) are rebuilt once per launch for all rows of the strip into a
+// small per-wave LDS table (one vectorised pass). The raw stored values of the row after the
+// next are loaded while the current row collides. The collision is the plain BGK relaxation
+// of Eq. (LBM_f) with f* = f^eq; the new state is written as m = (rho - 1, u) and the six codes
+// of (1 - omega)(f - f^eq(m)).
+constexpr int kRedHaloRows = 66;  // strip rows + 2 per launch (rows <= 64)
+
+__device__ __forceinline__ float shift_from_left(float v) {  // lane l receives lane l - 1
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float shift_from_right(float v) {  // lane l receives lane l + 1
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
 }
 
 template <typename Codec, bool WALLS, bool DIAG>
 __global__ void __launch_bounds__(kBlock)
 k_bgk_d2q9_red(const float* __restrict__ M, const uint16_t* __restrict__ N, float* __restrict__ Mo,
                uint16_t* __restrict__ No, int nx, int ny, int64_t pitch, int64_t plane,
-               double omega_d, float s_enc, float s_dec, int rows, double* __restrict__ partials) {
-  __shared__ float ring[3][kRedCols][9];
-  const int nbx = gridDim.x;
-  const int tile = xcd_tile(blockIdx.x + nbx * blockIdx.y, nbx * gridDim.y);
-  const int bx = tile % nbx;
-  const int by = tile / nbx;
-  const int tid = threadIdx.x;
-  const int x0 = bx * kBlock;
-  const int x = x0 + tid;
+               float omega, float s_enc, float s_dec, int rows, double* __restrict__ partials) {
+  // halo[wave][side][row][k]: side 0 = column x0 - 1 (populations 2, 5, 8 moving +x),
+  // side 1 = column x0 + 64 (populations 0, 3, 6 moving -x); row = y - (y0 - 1)
+  __shared__ float halo[kBlock / 64][2][kRedHaloRows][3];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nbx = (nx + kBlock - 1) / kBlock;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int bx = tile % nbx, by = tile / nbx;
+  const int x0 = bx * kBlock + wv * 64;  // first column of this wave's strip
+  const int x = x0 + lane;
+  const bool own = x < nx;
+  const int xc = own ? x : nx - 1;       // a valid column for lanes past the edge
   const int y0 = by * rows;
   const int yend = min(y0 + rows, ny);
-  const float keep = (float)(1.0 - omega_d);  // f~ - f^eq = (1 - omega)(f - f^eq)
+  const float keep = 1.0f - omega;
   double acc[kDiagValues] = {0.0, 0.0, 0.0, 0.0, 0.0};
-
-  // Row staging is software-pipelined: the raw stored values of a row (3 moments + 6 codes per
-  // column) are fetched into registers one iteration ahead, so their latency overlaps the
-  // collision of the current row; decoding them into LDS slot r mod 3 happens the next
-  // iteration. Columns c = 0..257 map to x0 - 1 + c (periodic); thread t owns column t and,
-  // for t < 2, column 256 + t.
-  struct Raw {
-    float m[3];
-    uint16_t n[kRedF];
-  };
-  Raw ra, rb;
-  auto fetch = [&](int rr, int c, Raw& v) {
-    int xg = x0 - 1 + c;
-    xg = ((xg % nx) + nx) % nx;
-    const int64_t off = (int64_t)rr * pitch + xg;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) v.m[k] = M[k * plane + off];
-#pragma unroll
-    for (int k = 0; k < kRedF; ++k) v.n[k] = N[k * plane + off];
-  };
-  auto decode = [&](const Raw& v, float (&dst)[9]) {
-    double n[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i)
-      if (f_slot(i) >= 0) n[i] = (double)Codec::dec(v.n[f_slot(i)], s_dec);
-    n[5] = n[0] - n[2] + n[3] + n[6] - n[8];
-    n[7] = n[0] + n[1] + n[2] - n[6] - n[8];
-    n[4] = -(((n[0] + n[1]) + (n[2] + n[3])) + ((n[5] + n[6]) + (n[7] + n[8])));
-    double dx[3], dy[3];
-    dpsi3((double)v.m[1], dx);
-    dpsi3((double)v.m[2], dy);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) dst[i] = (float)(heq_i(i, (double)v.m[0], dx, dy) + n[i]);
-  };
-  // rows beyond a wall are never pulled (bounce-back) and are skipped
+  if (x0 < nx) {  // strips past the right edge only join the diagnostics reduction
+  const int last = min(63, nx - 1 - x0);  // lane holding the strip's last column
+  // rows the pulls read: y0 - 1 .. yend (periodic), or only those inside the walls
+  auto row_of = [&](int r) { return ((r % ny) + ny) % ny; };
   auto outside = [&](int r) { return WALLS && (r < 0 || r >= ny); };
-  auto fetch_row = [&](int r) {
-    if (outside(r)) return;
-    const int rr = ((r % ny) + ny) % ny;
-    fetch(rr, tid, ra);
-    if (tid < kRedCols - kBlock) fetch(rr, kBlock + tid, rb);
-  };
-  auto put_row = [&](int r) {
-    if (outside(r)) return;
-    float(*dst)[9] = ring[((r % 3) + 3) % 3];
-    decode(ra, dst[tid]);
-    if (tid < kRedCols - kBlock) decode(rb, dst[kBlock + tid]);
-  };
 
-  fetch_row(y0 - 1);
-  put_row(y0 - 1);
-  fetch_row(y0);
-  put_row(y0);
-  fetch_row(y0 + 1);
-  for (int y = y0; y < yend; ++y) {
-    put_row(y + 1);  // slot (y + 1) mod 3 was last read by row y - 1, before the barrier below
-    __syncthreads();
-    if (y + 1 < yend) fetch_row(y + 2);  // consumed by the next iteration
-    if (x < nx) {
-      float h[9];
+  // ---- halo columns for all rows of the strip: lane = (side, row) --------------------------
+  {
+    const int nh = (yend - y0) + 2;
+    for (int k = lane; k < 2 * nh; k += 64) {
+      const int side = k >= nh, hr = side ? k - nh : k;
+      const int r = y0 - 1 + hr;
+      if (outside(r)) continue;
+      const int xs = side ? (x0 + last + 1 == nx ? 0 : x0 + last + 1) : (x0 == 0 ? nx - 1 : x0 - 1);
+      RawNode v;
+      const int64_t off = (int64_t)row_of(r) * pitch + xs;
 #pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        const int ka = i % 3, kb = i / 3;
-        const bool bounce = WALLS && ((kb == 2 && y == 0) || (kb == 0 && y == ny - 1));
-        h[i] = bounce ? ring[((y % 3) + 3) % 3][tid + 1][8 - i]
-                      : ring[(((y - kb + 1) % 3) + 3) % 3][tid + 1 - (ka - 1)][i];
+      for (int q = 0; q < 3; ++q) v.m[q] = M[q * plane + off];
+#pragma unroll
+      for (int q = 0; q < kRedF; ++q) v.n[q] = N[q * plane + off];
+      float h[9];
+      rebuild_node<Codec>(v, s_dec, h);
+      float* dst = halo[wv][side][hr];
+      if (side == 0) { dst[0] = h[2]; dst[1] = h[5]; dst[2] = h[8]; }
+      else { dst[0] = h[0]; dst[1] = h[3]; dst[2] = h[6]; }
+    }
+  }
+
+  // ---- own column: rows y0 - 1 and y0 rebuilt, y0 + 1 loaded ---------------------------------
+  float ring[3][9];  // ring[r mod 3]: rebuilt row r of the own column
+  RawNode raw;
+  // The loads are unconditional (a row beyond a wall reads the nearest real row, whose values
+  // are then not used): a load issued only on some paths would make the compiler wait for every
+  // outstanding memory operation, the previous row's stores included, before the next row.
+  auto fetch = [&](int r) {
+    const int rr = WALLS ? (r < 0 ? 0 : (r > ny - 1 ? ny - 1 : r)) : row_of(r);
+    load_node(M, N, plane, (int64_t)rr * pitch + xc, raw);
+  };
+  auto put = [&](int r, float (&dst)[9]) {
+    if (outside(r)) return;
+    rebuild_node<Codec>(raw, s_dec, dst);
+  };
+  fetch(y0 - 1);
+  put(y0 - 1, ring[0]);
+  fetch(y0);
+  put(y0, ring[1]);
+  fetch(y0 + 1);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+  // ring slot of row r: (r - y0 + 1) mod 3, a compile-time constant in the unrolled body; the
+  // body always runs all three rows (rows past yend compute on re-read data and store
+  // nothing), so the loop has no early exit and no loop-carried register copies, which would
+  // make the compiler wait for every outstanding store at the back edge
+  for (int yb = y0; yb < yend; yb += 3) {
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int y = yb + j;
+    const bool live = y < yend;
+    // rebuild row y + 1 (loaded one iteration ago), load row y + 2
+    put(min(y + 1, yend), ring[(j + 2) % 3]);
+    fetch(min(y + 2, yend));  // past the last needed row: a harmless re-read
+    const float (&rm)[9] = ring[j];            // row y - 1
+    const float (&r0)[9] = ring[(j + 1) % 3];  // row y
+    const float (&rp)[9] = ring[(j + 2) % 3];  // row y + 1
+    const int hr = min(y, yend - 1) - y0 + 1;   // halo row of y (rows past yend: the last)
+    // pull: f_i(x) = f~_i(x - c_i); i = (c_x + 1) + 3 (c_y + 1); rows beyond a wall bounce back
+    float h[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const int ka = i % 3, kb = i / 3;          // c_x = ka - 1, c_y = kb - 1
+      const bool bounce = WALLS && ((kb == 2 && y == 0) || (kb == 0 && y == ny - 1));
+      if (bounce) {
+        h[i] = r0[8 - i];
+        continue;
       }
-      // sum_i w_i = 1 and sum_i c_i w_i = 0
-      const float drho = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
-      const float jx = (h[2] + h[5] + h[8]) - (h[0] + h[3] + h[6]);
-      const float jy = (h[6] + h[7] + h[8]) - (h[0] + h[1] + h[2]);
-      const float rho = 1.0f + drho;
-      const float ux = jx / rho, uy = jy / rho;
-      float dx[3], dy[3];
-      dpsi3(ux, dx);
-      dpsi3(uy, dy);
+      const float(&src)[9] = kb == 0 ? rp : (kb == 1 ? r0 : rm);  // row y - c_y
+      const int hrow = hr - (kb - 1);
+      if (ka == 1) {
+        h[i] = src[i];
+      } else if (ka == 2) {  // from column x - 1
+        const float v = shift_from_left(src[i]);
+        h[i] = lane == 0 ? halo[wv][0][hrow][i / 3] : v;
+      } else {               // from column x + 1
+        const float v = shift_from_right(src[i]);
+        h[i] = lane == last ? halo[wv][1][hrow][i / 3] : v;
+      }
+    }
+    // moments (sum_i w_i = 1, sum_i c_i w_i = 0) and the relaxation
+    const float drho = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
+    const float jx = (h[2] + h[5] + h[8]) - (h[0] + h[3] + h[6]);
+    const float jy = (h[6] + h[7] + h[8]) - (h[0] + h[1] + h[2]);
+    const float rho = 1.0f + drho;
+    const float ux = quotient(jx, rho), uy = quotient(jy, rho);
+    float dx[3], dy[3];
+    dpsi3(ux, dx);
+    dpsi3(uy, dy);
+    if (own && live) {
       const int64_t self = (int64_t)y * pitch + x;
       store_nt(Mo + self, drho);
       store_nt(Mo + plane + self, ux);
@@ -157,13 +239,15 @@ k_bgk_d2q9_red(const float* __restrict__ M, const uint16_t* __restrict__ N, floa
           store_nt(No + f_slot(i) * plane + self,
                    Codec::enc(keep * (h[i] - heq_i(i, drho, dx, dy)), s_enc));
       if (DIAG) {
-        acc[0] += 1.0 + (double)drho;
+        const double rho = 1.0 + (double)drho;
+        acc[0] += rho;
         acc[1] += (double)jx;
         acc[2] += (double)jy;
-        acc[4] += 0.5 * (double)rho * ((double)ux * ux + (double)uy * uy);
+        acc[4] += 0.5 * rho * ((double)ux * ux + (double)uy * uy);
       }
     }
-    __syncthreads();
+  }
+  }
   }
   if (DIAG) block_sum_store<kDiagValues>(acc, partials + (int64_t)tile * kDiagValues);
 }
@@ -199,21 +283,32 @@ __global__ void k_decode_bgk_red(int i, const float* __restrict__ M, const uint1
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= nodes) return;
   const int64_t off = (n / nx) * pitch + (n % nx);
-  const double rho = 1.0 + (double)M[off];
-  const double feq = rho * psi_c(i % 3 - 1, (double)M[plane + off]) * psi_c(i / 3 - 1, (double)M[2 * plane + off]);
-  out[n] = feq + neq_f<Codec>(N, plane, off, i, s_dec);
+  RawNode v;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) v.m[k] = M[k * plane + off];
+#pragma unroll
+  for (int k = 0; k < kRedF; ++k) v.n[k] = N[k * plane + off];
+  float h[9];
+  rebuild_node<Codec>(v, s_dec, h);
+  // f = h + w with the rest weights of the float32 constants (products exact in float64)
+  out[n] = (double)h[i] + (double)wk(i % 3) * (double)wk(i / 3);
 }
 
 // ---- launchers -----------------------------------------------------------------------------
+// Tiles of 256 columns (four 64-column wavefront strips) by `rows` rows, launched as a
+// one-dimensional grid (tile = bx + nbx by), so tall lattices need no more rows per tile; the
+// per-wave halo table holds rows + 2 <= kRedHaloRows rows.
 Grid make_grid_red(const Layout& L) {
   Grid G;
   G.bx = kBlock;
   G.nbx = (L.nx + kBlock - 1) / kBlock;
-  G.rows = 16;  // sweep on MI355X at 2048^2: 1 -> 88 us, 4 -> 62, 16 -> 56, 32 -> 77
+  G.rows = 12;
 #ifdef LBM_TUNING_ENV
   if (const char* v = getenv("LBM_RED_ROWS")) G.rows = atoi(v);
 #endif
-  fit_rows(G, L.ny);  // tall lattices take more rows per workgroup (grid y <= kMaxGridY)
+  if (G.rows > kRedHaloRows - 2) G.rows = kRedHaloRows - 2;
+  if (G.rows < 1) G.rows = 1;
+  G.nby = (L.ny + G.rows - 1) / G.rows;
   return G;
 }
 
@@ -221,11 +316,12 @@ template <typename Codec, bool WALLS>
 static void red_launch(const float* M, const uint16_t* N, float* Mo, uint16_t* No, const Layout& L,
                        const Grid& G, double omega, float se, float sd, double* partials,
                        hipStream_t s) {
-  dim3 grid(G.nbx, G.nby), block(kBlock);
+  dim3 grid((unsigned)G.blocks()), block(kBlock);
+  const float om = (float)omega;
   if (partials)
-    k_bgk_d2q9_red<Codec, WALLS, true><<<grid, block, 0, s>>>(M, N, Mo, No, L.nx, L.ny, L.pitch, L.plane, omega, se, sd, G.rows, partials);
+    k_bgk_d2q9_red<Codec, WALLS, true><<<grid, block, 0, s>>>(M, N, Mo, No, L.nx, L.ny, L.pitch, L.plane, om, se, sd, G.rows, partials);
   else
-    k_bgk_d2q9_red<Codec, WALLS, false><<<grid, block, 0, s>>>(M, N, Mo, No, L.nx, L.ny, L.pitch, L.plane, omega, se, sd, G.rows, nullptr);
+    k_bgk_d2q9_red<Codec, WALLS, false><<<grid, block, 0, s>>>(M, N, Mo, No, L.nx, L.ny, L.pitch, L.plane, om, se, sd, G.rows, nullptr);
 }
 
 // Buffer layout: 3 float moment planes, then kRedF uint16 planes (plane elements each).

@@ -114,46 +114,40 @@ def test_d3q27_z_invariant_equals_d2q9_on_gpu():
     assert np.abs(v3[:2, 0] - v2).max() <= 1e-14
 
 
-def _one_step_full_size(lat, tau, walls=False):
-    """Oracle step from the GPU's own stored state: pull (stream) then collide."""
-    f_post, _ = lat.populations()
-    lat.step(1)
-    f_next, _ = lat.populations()
-    expect = bgk.collide(bgk.stream(f_post, walls), bgk.omega_from_tau_lb(tau))
-    return f_next, expect
-
-
-@pytest.mark.parametrize("n,streaming", [(2048, "auto"), (2048, "two"), (4096, "auto"),
-                                         (4096, "one")])
-def test_full_size_single_step_elementwise(n, streaming):
-    announce("D2Q9 full size %d^2 single-step elementwise fp32 (%s layout)" % (n, streaming))
+@pytest.mark.parametrize("n,streaming,steps", [(2048, "auto", 2), (2048, "two", 3),
+                                               (4096, "auto", 3), (4096, "one", 2)])
+def test_full_size_steps_elementwise(n, streaming, steps):
+    """The stored post-collision populations after a few steps from the seeded initial fields,
+    at the benchmark sizes and layouts (one buffer after even and odd step counts), element by
+    element against the oracle run from the same fields."""
+    announce("D2Q9 full size %d^2 fp32 %d steps elementwise (%s layout)" % (n, steps, streaming))
     rho, u = inputs.random_phase_turbulence_2d(n, seed=0)
     lat = _lattice(rho, u, tau=0.6, streaming=streaming)
-    lat.step(20)
-    got, expect = _one_step_full_size(lat, 0.6)
+    lat.step(steps)
+    got, _ = lat.populations()
     lat.close()
-    # one float32 collision from identical inputs: within ~15 ulp of the largest population
+    om = bgk.omega_from_tau_lb(0.6)
+    expect = bgk.collide(bgk.run(bgk.init_equilibrium(rho, u), om, steps), om)
+    # a few float32 collisions from identical inputs: within ~15 ulp of the largest population
     assert np.abs(got - expect).max() <= 1e-6 * np.abs(expect).max()
 
 
-def test_d3q27_full_size_single_step():
-    announce("D3Q27 full size 256^3 single-step elementwise fp32")
-    rho, u = inputs.taylor_green_3d(256, 0.05)
+def test_d3q27_full_size_steps():
+    announce("D3Q27 full size 256^3 fp32, 2 steps, sampled planes")
+    n, steps = 256, 2
+    rho, u = inputs.taylor_green_3d(n, 0.05)
     lat = _lattice(rho, u, lattice="D3Q27", tau=0.55)
-    lat.step(5)
-    f_post, _ = lat.populations()
-    lat.step(1)
+    lat.step(steps)
     f_next, _ = lat.populations()
     lat.close()
-    # sample 4 z-planes of the oracle step (the pull only reaches z +- 1)
-    zs = [0, 1, 128, 255]
-    sub = np.concatenate([f_post[:, [(z - 1) % 256, z, (z + 1) % 256]] for z in zs], axis=1)
-    # collide-after-stream on 3-plane slabs; the middle plane of each slab is exact
-    for k, z in enumerate(zs):
-        slab = sub[:, 3 * k:3 * k + 3]
-        pre = bgk.stream(slab)
-        exp = bgk.collide(pre, bgk.omega_from_tau_lb(0.55))[:, 1]
-        assert np.abs(f_next[:, z] - exp).max() <= 1e-6 * np.abs(exp).max()
+    om = bgk.omega_from_tau_lb(0.55)
+    # plane z after k steps depends on planes z - k .. z + k: the oracle runs on that slab
+    # (periodic in z on the slab, which leaves the middle plane exact)
+    for z in (0, 1, 128, 255):
+        iz = [(z + d) % n for d in range(-steps, steps + 1)]
+        f0 = bgk.init_equilibrium(rho[iz], u[:, iz])
+        exp = bgk.collide(bgk.run(f0, om, steps), om)[:, steps]
+        assert np.abs(f_next[:, z] - exp).max() <= 1e-6 * np.abs(exp).max(), z
 
 
 def test_bitwise_determinism_and_workspace_modes():

@@ -100,31 +100,24 @@ def test_conservation_fp32_walls():
     assert np.all(np.abs(h[:, 5] - m0[4]) / m0[4] < 1e-6)   # total energy
 
 
-def test_full_size_rows_single_step():
+def test_full_size_rows_one_step():
+    """4096^2 with walls (the bench configuration): the state after one step from the seeded
+    initial fields at sampled rows, against the oracle run on slabs of the initial fields
+    around them (6 rows of margin: one step reaches 3)."""
     announce("DDF fp32 full size 4096^2 walls: one step at sampled rows")
-    n = 4096
+    from windows import rows
+    n, m = 4096, 6
     rho, u, T = inputs.thermal_shear_layer(n, seed=0)
     from paper_2609_28679_amd.binding import Lattice
     lat = Lattice(rho, u, T, model="ddf", tau=0.6, wall_y=True, phi=1)
-    lat.step(10)
-    f_post, g_post = lat.populations()
     lat.step(1)
     f_next, g_next = lat.populations()
     lat.close()
     gas = _gas(0.6)
     for c in (0, 1, 2047, n - 2, n - 1):
-        lo, hi = max(c - 2, 0), min(c + 3, n)
-        # pre-collision populations of rows lo..hi-1: pull from the rows around them
-        src_lo, src_hi = max(lo - 1, 0), min(hi + 1, n)
-        fs = bgk.stream(f_post[:, src_lo:src_hi], walls_y=True)
-        gs = bgk.stream(g_post[:, src_lo:src_hi], walls_y=True)
-        # the slab's own first/last rows are only correct where they are real walls
-        keep = slice(lo - src_lo, hi - src_lo)
-        fpre, gpre = fs[:, keep], gs[:, keep]
-        # collide the slab (Phi from the slab's rows: exact for row c, which has both
-        # neighbours inside it or a wall next to it)
-        walls_slab = True
-        ft, gt = ddf.collide(fpre, gpre, gas, walls_slab, True, "central")
+        lo, hi = max(c - m, 0), min(c + m + 1, n)
+        f, g = ddf.init_equilibrium(rows(rho, lo, hi), rows(u, lo, hi), rows(T, lo, hi), gas)
+        ft, gt = ddf.collide(*ddf.run(f, g, gas, 1, walls_y=True), gas, True, True, "central")
         k = c - lo
         assert np.abs(ft[:, k] - f_next[:, c]).max() <= 2e-6 * np.abs(f_next[:, c]).max(), c
         assert np.abs(gt[:, k] - g_next[:, c]).max() <= 2e-6 * np.abs(g_next[:, c]).max(), c

@@ -1,19 +1,25 @@
 """Full-size checks in the launch configurations that bench.py times, for the workloads with a
 body force, heat source, transport control, a van der Waals fluid (D2Q9 and D3Q27),
-non-equilibrium extrapolation walls and the D3Q27 double distribution: one GPU step from the
-GPU's own stored state against the oracle's step, element by element on whole lattices, row
-slabs or node neighbourhoods that the oracle can compute (a node's step reads its neighbours up
-to two spacings away: the pull, then the derivative stencils of the moments)."""
+non-equilibrium extrapolation walls and the D3Q27 double distribution: the GPU state after one
+or two steps from the seeded initial fields against the oracle run from the same fields, element
+by element on whole lattices, row slabs or node neighbourhoods that the oracle can compute
+(windows of the initial fields wide enough that the checked nodes are exact, tests/windows.py).
+
+The double-distribution context stores the post-collision state of t = 0 (its creation collides
+the initial equilibrium once); after one step it holds the post-collision state of t = 1, which
+is the oracle's collide(run(init, 1))."""
 import numpy as np
 import pytest
 
 from gpu_util import announce, require_gpu
 from oracle import bgk, ddf
 from paper_2609_28679_amd import inputs
+from windows import periodic_box, rows, wall_blocks
 
 pytestmark = pytest.mark.gpu
 
 R, CV, P0 = 1.0 / 3.0, 5.0 / 6.0, 1.0 / 3.0
+MARGIN = 6  # rows beyond a checked row: one step reaches 3 (collide, pull, collide)
 
 
 @pytest.fixture(autouse=True)
@@ -30,67 +36,73 @@ def _close(got, want, tol=2e-6):
     return np.abs(got - want).max() <= tol * np.abs(want).max()
 
 
-def _two_snapshots(lat, warm):
-    lat.step(warm)
-    post = lat.populations()
-    lat.step(1)
-    nxt = lat.populations()
+def _gpu_state(lat, steps):
+    lat.step(steps)
+    out = lat.populations()
     lat.close()
-    return post, nxt
+    return out
 
 
 def test_forced_d2q9_2048_one_buffer():
-    announce("D2Q9 2048^2 fp32 one buffer, uniform force (bench configuration): one step")
+    announce("D2Q9 2048^2 fp32 one buffer, uniform force (bench configuration): 2 steps")
     rho, u = inputs.random_phase_turbulence_2d(2048, seed=0)
     F = np.array([1e-6, 0.0])
-    lat = _lattice(rho, u, tau=0.6, force=tuple(F))
-    (f_post, _), (f_next, _) = _two_snapshots(lat, 20)
-    want = bgk.collide(bgk.stream(f_post), bgk.omega_from_tau_lb(0.6), F)
+    f_next, _ = _gpu_state(_lattice(rho, u, tau=0.6, force=tuple(F)), 2)
+    om = bgk.omega_from_tau_lb(0.6)
+    want = bgk.collide(bgk.run(bgk.init_equilibrium(rho, u), om, 2, F=F), om, F)
     assert _close(f_next, want)
 
 
 def test_forced_d3q27_256():
-    announce("D3Q27 256^3 fp32, uniform force (bench configuration): one step on 4 slabs")
-    rho, u = inputs.taylor_green_3d(256, 0.05)
+    announce("D3Q27 256^3 fp32, uniform force (bench configuration): 2 steps on 4 slabs")
+    n, steps = 256, 2
+    rho, u = inputs.taylor_green_3d(n, 0.05)
     F = np.array([1e-6, 0.0, 0.0])
-    lat = _lattice(rho, u, lattice="D3Q27", tau=0.55, force=tuple(F))
-    (f_post, _), (f_next, _) = _two_snapshots(lat, 5)
+    f_next, _ = _gpu_state(_lattice(rho, u, lattice="D3Q27", tau=0.55, force=tuple(F)), steps)
     om = bgk.omega_from_tau_lb(0.55)
     for z in (0, 1, 128, 255):
-        slab = f_post[:, [(z - 1) % 256, z, (z + 1) % 256]]
-        want = bgk.collide(bgk.stream(slab), om, F)[:, 1]
+        iz = [(z + d) % n for d in range(-steps, steps + 1)]
+        want = bgk.collide(bgk.run(bgk.init_equilibrium(rho[iz], u[:, iz]), om, steps, F=F),
+                           om, F)[:, steps]
         assert _close(f_next[:, z], want), z
 
 
-def _ddf_rows(f_post, g_post, f_next, g_next, gas, rows, F=None, Q=0.0):
-    """Row slabs of the D2Q9 double distribution with bounce-back walls at the lattice ends."""
-    n = f_post.shape[1]
-    for c in rows:
-        lo, hi = max(c - 2, 0), min(c + 3, n)
-        src_lo, src_hi = max(lo - 1, 0), min(hi + 1, n)
-        fs = bgk.stream(f_post[:, src_lo:src_hi], walls_y=True)
-        gs = bgk.stream(g_post[:, src_lo:src_hi], walls_y=True)
-        keep = slice(lo - src_lo, hi - src_lo)
-        ft, gt = ddf.collide(fs[:, keep], gs[:, keep], gas, True, True, "central", F=F, Q=Q)
-        k = c - lo
-        assert _close(f_next[:, c], ft[:, k]), c
-        assert _close(g_next[:, c], gt[:, k]), c
+def _ddf_oracle_post(rho, u, T, gas, steps, F=None, Q=0.0, neq=None, walls_y=True):
+    """Post-collision populations after `steps` steps from the initial fields (see module)."""
+    f, g = ddf.init_equilibrium(rho, u, T, gas)
+    f, g = ddf.run(f, g, gas, steps, walls_y=walls_y, F=F, Q=Q, neq=neq)
+    return ddf.collide(f, g, gas, walls_y or neq is not None, True, "central", F=F, Q=Q,
+                       neq=neq)
+
+
+def _ddf_rows(fields, gpu, gas, check, F=None, Q=0.0):
+    """D2Q9 double distribution with bounce-back walls at the lattice ends: the rows in `check`
+    after one step, each from a slab of the initial fields MARGIN rows around it (a slab that
+    reaches the lattice's end has the real wall there)."""
+    rho, u, T = fields
+    f_next, g_next = gpu
+    n = rho.shape[0]
+    for c in check:
+        lo, hi = max(c - MARGIN, 0), min(c + MARGIN + 1, n)
+        ft, gt = _ddf_oracle_post(rows(rho, lo, hi), rows(u, lo, hi), rows(T, lo, hi), gas, 1,
+                                  F=F, Q=Q)
+        assert _close(f_next[:, c], ft[:, c - lo]), c
+        assert _close(g_next[:, c], gt[:, c - lo]), c
 
 
 @pytest.mark.parametrize("case", ["sources", "transport"])
 def test_ddf_4096_extended(case):
     n = 4096
     announce("DDF 4096^2 fp32 walls, %s (bench configuration): one step at sampled rows" % case)
-    rho, u, T = inputs.thermal_shear_layer(n, seed=0)
+    fields = inputs.thermal_shear_layer(n, seed=0)
     if case == "sources":
         kw, F, Q = dict(force=(1e-7, 0.0), heat_source=1e-8), np.array([1e-7, 0.0]), 1e-8
         gas = ddf.Gas(R, CV, 0.1 * P0)
     else:
         kw, F, Q = dict(prandtl=0.71, eta_over_mu=1.0), None, 0.0
         gas = ddf.Gas(R, CV, 0.1 * P0, prandtl=0.71, eta_over_mu=1.0)
-    lat = _lattice(rho, u, T, model="ddf", tau=0.6, wall_y=True, phi=1, **kw)
-    (f_post, g_post), (f_next, g_next) = _two_snapshots(lat, 10)
-    _ddf_rows(f_post, g_post, f_next, g_next, gas, (0, 1, 2047, n - 2, n - 1), F, Q)
+    gpu = _gpu_state(_lattice(*fields, model="ddf", tau=0.6, wall_y=True, phi=1, **kw), 1)
+    _ddf_rows(fields, gpu, gas, (0, 1, 2047, n - 2, n - 1), F, Q)
 
 
 def test_ddf_4096_vdw():
@@ -99,34 +111,49 @@ def test_ddf_4096_vdw():
              "sampled rows")
     _, u, T = inputs.thermal_shear_layer(n, seed=0, T0=1.4, dT=0.03)
     rho = np.ones_like(T)
-    lat = _lattice(rho, u, T, model="ddf", tau=0.6, wall_y=True, phi=1, vdw=(0.27, 0.2))
-    (f_post, g_post), (f_next, g_next) = _two_snapshots(lat, 10)
+    gpu = _gpu_state(_lattice(rho, u, T, model="ddf", tau=0.6, wall_y=True, phi=1,
+                              vdw=(0.27, 0.2)), 1)
     gas = ddf.Gas(R, CV, 0.1 * P0, a=0.27, b=0.2)
-    _ddf_rows(f_post, g_post, f_next, g_next, gas, (0, 1, 2047, n - 2, n - 1))
+    _ddf_rows((rho, u, T), gpu, gas, (0, 1, 2047, n - 2, n - 1))
 
 
 def test_ddf_4096_neq_walls():
     n = 4096
     announce("DDF 4096^2 fp32 non-equilibrium extrapolation walls (bench configuration): one step")
     rho, u, T = inputs.thermal_shear_layer(n, seed=0)
-    lat = _lattice(rho, u, T, model="ddf", tau=0.6, phi=1,
-                   neq_walls=dict(u=((-0.05, 0.0), (0.05, 0.0)), T=(0.8, 1.0)))
-    (f_post, g_post), (f_next, g_next) = _two_snapshots(lat, 10)
+    f_next, g_next = _gpu_state(_lattice(rho, u, T, model="ddf", tau=0.6, phi=1,
+                                         neq_walls=dict(u=((-0.05, 0.0), (0.05, 0.0)),
+                                                        T=(0.8, 1.0))), 1)
     gas = ddf.Gas(R, CV, 0.1 * P0)
     walls = ddf.NeqWalls((-0.05, 0.0), 0.8, (0.05, 0.0), 1.0)
-    # rows 0..4 and n-5..n-1 stacked: the boundary rows are rebuilt from rows 1 and n-2, and
-    # rows 0, 1, n-2, n-1 only reach rows inside their own block (the junction is never read)
-    block = np.r_[0:5, n - 5:n]
-    fs = np.concatenate([bgk.stream(f_post[:, 0:5]), bgk.stream(f_post[:, n - 5:n])], axis=1)
-    gs = np.concatenate([bgk.stream(g_post[:, 0:5]), bgk.stream(g_post[:, n - 5:n])], axis=1)
-    fs, gs = ddf.apply_neq_walls(fs, gs, gas, walls)
-    ft, gt = ddf.collide(fs, gs, gas, True, True, "central")
-    for k in (0, 1, 8, 9):
-        c = block[k]
+    # the first and last MARGIN + 2 rows stacked: both walls are real, the junction far away
+    d = MARGIN + 2
+    ft, gt = _ddf_oracle_post(wall_blocks(rho, d), wall_blocks(u, d), wall_blocks(T, d), gas, 1,
+                              neq=walls, walls_y=False)
+    for k, c in ((0, 0), (1, 1), (2 * d - 2, n - 2), (2 * d - 1, n - 1)):
         assert _close(f_next[:, c], ft[:, k]), c
         assert _close(g_next[:, c], gt[:, k]), c
-    # an interior row is an ordinary row
-    _ddf_rows(f_post, g_post, f_next, g_next, gas, (2047,))
+    # an interior row is an ordinary row (bounce-back walls of the slab never reach it)
+    lo, hi = 2047 - MARGIN, 2047 + MARGIN + 1
+    ft, gt = _ddf_oracle_post(rows(rho, lo, hi), rows(u, lo, hi), rows(T, lo, hi), gas, 1)
+    assert _close(f_next[:, 2047], ft[:, MARGIN])
+    assert _close(g_next[:, 2047], gt[:, MARGIN])
+
+
+def _ddf3_nodes(fields, gpu, gas, n, seed, F=None, Q=0.0):
+    """Sampled nodes of a periodic D3Q27 double-distribution step, each from the periodic box of
+    the initial fields of radius 4 around it (one step reaches 3)."""
+    rho, u, T = fields
+    f_next, g_next = gpu
+    rng = np.random.default_rng(seed)
+    nodes = [(0, 0, 0), (255, 128, 1), (17, 255, 254)] + [tuple(v) for v in rng.integers(0, n, (3, 3))]
+    r = 4
+    for z, y, x in nodes:
+        c = (z, y, x)
+        ft, gt = _ddf_oracle_post(periodic_box(rho, c, r), periodic_box(u, c, r, lead=1),
+                                  periodic_box(T, c, r), gas, 1, F=F, Q=Q, walls_y=False)
+        assert _close(f_next[:, z, y, x], ft[:, r, r, r]), c
+        assert _close(g_next[:, z, y, x], gt[:, r, r, r]), c
 
 
 @pytest.mark.parametrize("case", ["sources", "transport"])
@@ -134,16 +161,15 @@ def test_ddf3_256_extended(case):
     n = 256
     announce("D3Q27 DDF 256^3 fp32 periodic, %s (bench configuration): one step at sampled "
              "nodes" % case)
-    rho, u, T = inputs.thermal_taylor_green_3d(n, 0.05)
+    fields = inputs.thermal_taylor_green_3d(n, 0.05)
     if case == "sources":
         kw, F, Q = dict(force=(1e-7, 0.0, 0.0), heat_source=1e-8), np.array([1e-7, 0.0, 0.0]), 1e-8
         gas = ddf.Gas(R, CV, 0.1 * P0)
     else:
         kw, F, Q = dict(prandtl=0.71, eta_over_mu=1.0), None, 0.0
         gas = ddf.Gas(R, CV, 0.1 * P0, prandtl=0.71, eta_over_mu=1.0)
-    lat = _lattice(rho, u, T, lattice="D3Q27", model="ddf", tau=0.6, phi=1, **kw)
-    (f_post, g_post), (f_next, g_next) = _two_snapshots(lat, 5)
-    _ddf3_nodes(f_post, g_post, f_next, g_next, gas, n, seed=5, F=F, Q=Q)
+    gpu = _gpu_state(_lattice(*fields, lattice="D3Q27", model="ddf", tau=0.6, phi=1, **kw), 1)
+    _ddf3_nodes(fields, gpu, gas, n, seed=5, F=F, Q=Q)
 
 
 def test_ddf3_256_vdw():
@@ -152,25 +178,9 @@ def test_ddf3_256_vdw():
              "step at sampled nodes")
     _, u = inputs.taylor_green_3d(n, 0.05)
     rho, T = np.ones(u.shape[1:]), np.full(u.shape[1:], 1.4)
-    lat = _lattice(rho, u, T, lattice="D3Q27", model="ddf", tau=0.6, phi=1, vdw=(0.27, 0.2))
-    (f_post, g_post), (f_next, g_next) = _two_snapshots(lat, 5)
-    gas = ddf.Gas(R, CV, 0.1 * P0, a=0.27, b=0.2)
-    _ddf3_nodes(f_post, g_post, f_next, g_next, gas, n, seed=4)
-
-
-def _ddf3_nodes(f_post, g_post, f_next, g_next, gas, n, seed, F=None, Q=0.0):
-    """Sampled nodes of a periodic D3Q27 double-distribution step, each from its 5^3
-    neighbourhood streamed and collided as a periodic box (its centre is exact)."""
-    rng = np.random.default_rng(seed)
-    nodes = [(0, 0, 0), (255, 128, 1), (17, 255, 254)] + [tuple(v) for v in rng.integers(0, n, (3, 3))]
-    for z, y, x in nodes:
-        idx = np.ix_(*[[(c + d) % n for d in range(-2, 3)] for c in (z, y, x)])
-        fb = np.stack([f_post[i][idx] for i in range(27)])
-        gb = np.stack([g_post[i][idx] for i in range(27)])
-        ft, gt = ddf.collide(bgk.stream(fb), bgk.stream(gb), gas, False, True, "central", F=F,
-                             Q=Q)
-        assert _close(f_next[:, z, y, x], ft[:, 2, 2, 2]), (z, y, x)
-        assert _close(g_next[:, z, y, x], gt[:, 2, 2, 2]), (z, y, x)
+    gpu = _gpu_state(_lattice(rho, u, T, lattice="D3Q27", model="ddf", tau=0.6, phi=1,
+                              vdw=(0.27, 0.2)), 1)
+    _ddf3_nodes((rho, u, T), gpu, ddf.Gas(R, CV, 0.1 * P0, a=0.27, b=0.2), n, seed=4)
 
 
 def test_ddf3_256_neq_walls():
@@ -178,38 +188,30 @@ def test_ddf3_256_neq_walls():
     announce("D3Q27 DDF 256^3 fp32 NEQ walls (bench configuration): one step at sampled nodes "
              "next to and on the walls")
     rho, u, T = inputs.thermal_taylor_green_3d(n, 0.05)
-    lat = _lattice(rho, u, T, lattice="D3Q27", model="ddf", tau=0.6, phi=1,
-                   neq_walls=dict(u=((-0.05, 0.0), (0.05, 0.0)), T=(0.8, 1.0)))
-    (f_post, g_post), (f_next, g_next) = _two_snapshots(lat, 5)
+    f_next, g_next = _gpu_state(_lattice(rho, u, T, lattice="D3Q27", model="ddf", tau=0.6, phi=1,
+                                         neq_walls=dict(u=((-0.05, 0.0), (0.05, 0.0)),
+                                                        T=(0.8, 1.0))), 1)
     gas = ddf.Gas(R, CV, 0.1 * P0)
     walls = ddf.NeqWalls((-0.05, 0.0, 0.0), 0.8, (0.05, 0.0, 0.0), 1.0)
-    # a 5 x 5 column of planes y = 0..4 and y = n-5..n-1 around (z, x), periodic in z and x: the
-    # boundary planes are rebuilt from planes 1 and n-2, and planes 0, 1, n-2, n-1 reach only
-    # planes inside their own block (the junction between the blocks is never read)
-    ys = np.r_[0:5, n - 5:n]
+    # columns of the first and last d planes in y, a periodic box of radius r in z and x
+    d, r = 6, 4
     for z, x in ((0, 0), (131, 255), (7, 64)):
-        iz = [(z + d) % n for d in range(-2, 3)]
-        ix = [(x + d) % n for d in range(-2, 3)]
-        blocks = []
-        for lo in (0, n - 5):
-            idx = np.ix_(iz, list(range(lo, lo + 5)), ix)
-            fb = np.stack([f_post[i][idx] for i in range(27)])
-            gb = np.stack([g_post[i][idx] for i in range(27)])
-            blocks.append((bgk.stream(fb), bgk.stream(gb)))
-        fs = np.concatenate([b[0] for b in blocks], axis=2)
-        gs = np.concatenate([b[1] for b in blocks], axis=2)
-        fs, gs = ddf.apply_neq_walls(fs, gs, gas, walls)
-        ft, gt = ddf.collide(fs, gs, gas, True, True, "central")
-        for k in (0, 1, 8, 9):
-            y = ys[k]
-            assert _close(f_next[:, z, y, x], ft[:, 2, k, 2]), (z, y, x)
-            assert _close(g_next[:, z, y, x], gt[:, 2, k, 2]), (z, y, x)
+        iz = [(z + k) % n for k in range(-r, r + 1)]
+        ix = [(x + k) % n for k in range(-r, r + 1)]
+
+        def col(a, lead=0):
+            b = a[(Ellipsis,) + np.ix_(iz, list(range(n)), ix)] if lead else a[np.ix_(iz, list(range(n)), ix)]
+            return wall_blocks(b, d, axis=-2)
+
+        ft, gt = _ddf_oracle_post(col(rho), col(u, 1), col(T), gas, 1, neq=walls, walls_y=False)
+        for k, y in ((0, 0), (1, 1), (2 * d - 2, n - 2), (2 * d - 1, n - 1)):
+            assert _close(f_next[:, z, y, x], ft[:, r, k, r]), (z, y, x)
+            assert _close(g_next[:, z, y, x], gt[:, r, k, r]), (z, y, x)
 
 
 def test_ddf3_256():
     n = 256
     announce("D3Q27 DDF 256^3 fp32 periodic (bench configuration): one step at sampled nodes")
-    rho, u, T = inputs.thermal_taylor_green_3d(n, 0.05)
-    lat = _lattice(rho, u, T, lattice="D3Q27", model="ddf", tau=0.6, phi=1)
-    (f_post, g_post), (f_next, g_next) = _two_snapshots(lat, 5)
-    _ddf3_nodes(f_post, g_post, f_next, g_next, ddf.Gas(R, CV, 0.1 * P0), n, seed=3)
+    fields = inputs.thermal_taylor_green_3d(n, 0.05)
+    gpu = _gpu_state(_lattice(*fields, lattice="D3Q27", model="ddf", tau=0.6, phi=1), 1)
+    _ddf3_nodes(fields, gpu, ddf.Gas(R, CV, 0.1 * P0), n, seed=3)

@@ -54,8 +54,11 @@ def test_forward_matches_oracle_with_bf16_roundings():
     got = y.cpu().numpy().astype(np.float64)
     exp, _ = mlp.forward(b.unpack_mlp(blob), x.astype(np.float64), bf16=True)
     tr.close()
+    # the same bfloat16 operands on both sides; what differs is float32 accumulation and the
+    # hardware exp2/reciprocal in GELU (a few float32 ulp), which flips the bfloat16 rounding of
+    # an activation now and then (one bfloat16 ulp, 2^-8 relative): measured 1.4e-5
     print("forward rel-L2 vs oracle: %.3e" % rel_l2(got, exp), flush=True)
-    assert rel_l2(got, exp) <= 2e-3
+    assert rel_l2(got, exp) <= 1e-4
     np.testing.assert_allclose(got @ mlp.constraint_matrix().T, 0.0, atol=1e-5)
 
 
@@ -78,24 +81,29 @@ def test_gradients_match_oracle_with_bf16_roundings():
     errs = {name: rel_l2(got[k], exp[k])
             for k, name in enumerate(["W1", "b1", "W2", "b2", "W3", "b3"])}
     print("gradient rel-L2 vs oracle:", {k: "%.3e" % v for k, v in errs.items()}, flush=True)
+    # same roundings on both sides; float32 accumulation over 2000 samples: measured <= 2e-6
     for name, e in errs.items():
-        assert e <= 5e-3, name
+        assert e <= 1e-4, name
 
 
-def test_harvest_features_and_targets():
-    announce("harvest 256^2 vs oracle features")
+@pytest.mark.parametrize("steps", [30, 31])
+def test_harvest_features_and_targets(steps):
+    announce("harvest 256^2 after %d steps vs oracle features" % steps)
     import torch
     b = _binding()
     rho, u = inputs.random_phase_turbulence_2d(256, seed=2)
     lat = b.Lattice(rho, u, tau=0.6)
-    lat.step(30)
-    f_post, _ = lat.populations()
+    lat.step(steps)
     idx = np.sort(np.random.default_rng(0).choice(256 * 256, 500, replace=False)).astype(np.int64)
     X = torch.empty((500, 12), dtype=torch.float32, device="cuda")
     Y = torch.empty((500, 9), dtype=torch.float32, device="cuda")
     lat.harvest(torch.from_numpy(idx).cuda(), X, Y)
     lat.close()
-    pre = bgk.stream(f_post).reshape(9, -1)[:, idx].T
+    # the populations the next step collides: the oracle's pre-collision state of t + 1, run
+    # from the same initial fields (both one-buffer parities, even and odd step counts)
+    om = 1 / 0.6
+    pre = bgk.stream(bgk.collide(bgk.run(bgk.init_equilibrium(rho, u), om, steps), om))
+    pre = pre.reshape(9, -1)[:, idx].T
     omega = np.full(500, 1 / 0.6)
     xo, _, _ = mlp.features(pre, omega)
     to = mlp.targets(pre, omega)
@@ -153,37 +161,44 @@ def test_training_and_surrogate_gain_and_parity():
     assert res["trained"][1] <= 1e-2
 
 
-def test_full_size_surrogate_step_sampled():
-    announce("surrogate 2048^2 one step (no fallback) vs oracle network at sampled nodes")
+def test_full_size_surrogate_steps_sampled():
+    """The 2048^2 surrogate step (the bench configuration) twice from the seeded initial fields
+    with a judge that never rejects, against the oracle network and streaming from the same
+    fields, at 20000 sampled nodes."""
+    announce("surrogate 2048^2 two steps (no fallback) vs oracle network at 4000 sampled nodes")
     b = _binding()
     from oracle.equilibrium import feq
     from oracle.lattice import VARSIGMA2
-    n, tau = 2048, 0.6
+    n, tau, steps = 2048, 0.6, 2
     rho, u = inputs.random_phase_turbulence_2d(n, seed=5)
     blob = b.pack_mlp(inputs.mlp_init(11))
     lat = b.Lattice(rho, u, tau=tau, collision="mlp")
     lat.set_mlp(blob, 1e30)  # the judge never rejects: every node takes the network output
-    lat.step(3)
-    f_post, _ = lat.populations()
-    lat.step(1)
+    lat.step(steps)
     f_next, _ = lat.populations()
     fb, up = lat.mlp_stats()
     lat.close()
-    assert fb == 0 and up == 4 * n * n
-    idx = np.random.default_rng(4).choice(n * n, 20000, replace=False)
-    pre = bgk.stream(f_post).reshape(9, -1)[:, idx].T
-    got = f_next.reshape(9, -1)[:, idx].T
-    omega = np.full(idx.size, 1 / tau)
-    exp, fallback = mlp.surrogate_collide(b.unpack_mlp(blob), pre, omega, 1e30, bf16=True)
-    assert not fallback.any()
-    r, v = pre.sum(axis=1), np.stack([pre[:, [2, 5, 8]].sum(1) - pre[:, [0, 3, 6]].sum(1),
-                                      pre[:, [6, 7, 8]].sum(1) - pre[:, [0, 1, 2]].sum(1)])
+    assert fb == 0 and up == steps * n * n
+    # each sampled node after two steps depends on the initial fields within two spacings: the
+    # oracle runs on the periodic 5 x 5 boxes around the samples (their centres are exact)
+    idx = np.random.default_rng(4).choice(n * n, 4000, replace=False)
+    ys, xs = idx // n, idx % n
+    d = np.arange(-2, 3)
+    by = (ys[:, None, None] + d[None, :, None]) % n
+    bx = (xs[:, None, None] + d[None, None, :]) % n
+    fo = _surrogate_oracle_run(rho[by, bx], u[:, by, bx], tau, steps, b.unpack_mlp(blob), False)
+    got = f_next[:, ys, xs].T
+    exp = fo[:, :, 2, 2].T
+    r = exp.sum(axis=1)
+    v = np.stack([exp[:, [2, 5, 8]].sum(1) - exp[:, [0, 3, 6]].sum(1),
+                  exp[:, [6, 7, 8]].sum(1) - exp[:, [0, 1, 2]].sum(1)])
     fe = feq(r, v / r, VARSIGMA2).T
-    # network outputs agree to the bfloat16 activation roundings (forward test: 2e-3); mass
-    # and momentum of the output are those of the input on both sides
-    assert rel_l2(got - fe, exp - fe) <= 5e-3
-    np.testing.assert_allclose(got.sum(axis=1), r, rtol=0, atol=2e-6)
-
+    err = rel_l2(got - fe, exp - fe)
+    print("surrogate 2048^2 two steps: rel-L2 of f - f^eq = %.3e" % err, flush=True)
+    # network outputs agree to the bfloat16 activation roundings (forward test); the total
+    # mass is the initial one
+    assert err <= 1e-3
+    assert abs(f_next.sum() / rho.sum() - 1.0) <= 1e-6
 
 def test_adam_training_steps_match_oracle():
     """Five lbm_mlp_train steps on five consecutive batches (the gradients differ from step
@@ -214,23 +229,26 @@ def test_adam_training_steps_match_oracle():
     print("Adam: max |dW_gpu - dW_oracle| / lr = %.3e, rel-L2 of dW = %.3e, "
           "99th percentile / lr = %.3e" % (diff.max() / lr, rel_l2(d_gpu, d_or),
                                           np.percentile(diff, 99) / lr), flush=True)
-    assert rel_l2(d_gpu, d_or) <= 1e-3
-    assert np.percentile(diff, 99) <= 1e-2 * lr
-    assert diff.max() <= 0.2 * lr
+    # measured: rel-L2 7.7e-6, 99th percentile 7e-5 lr, max 5e-4 lr (a weight whose gradient
+    # is near zero changes its Adam direction most under the float32 summation differences)
+    assert rel_l2(d_gpu, d_or) <= 1e-4
+    assert np.percentile(diff, 99) <= 1e-3 * lr
+    assert diff.max() <= 1e-2 * lr
 
 
 def _surrogate_oracle_run(rho, u, tau, steps, params, walls):
     """Oracle of the surrogate context: the stored state starts at the equilibrium (the
     paper's collision leaves it unchanged), then every step streams and applies the
-    surrogate collision (no fallback). Returns the post-collision populations."""
+    surrogate collision (no fallback). Returns the post-collision populations. Leading axes
+    before (y, x) are a batch of independent periodic lattices."""
     f = bgk.init_equilibrium(rho, u)
-    Q, ny, nx = f.shape
-    omega = np.full(ny * nx, 1.0 / tau)
+    shape = f.shape
+    omega = np.full(int(np.prod(shape[1:])), 1.0 / tau)
     for _ in range(steps):
-        pre = bgk.stream(f, walls_y=walls).reshape(Q, -1).T
+        pre = bgk.stream(f, walls_y=walls).reshape(shape[0], -1).T
         out, fb = mlp.surrogate_collide(params, pre, omega, 1e30, bf16=True)
         assert not fb.any()
-        f = out.T.reshape(Q, ny, nx)
+        f = out.T.reshape(shape)
     return f
 
 
@@ -263,10 +281,11 @@ def test_surrogate_steps_match_oracle(walls):
     err = rel_l2(fg - fe, fo - fe)
     print("surrogate steps walls=%s: rel-L2 of f - f^eq = %.3e, max |df| = %.3e"
           % (walls, err, np.abs(fg - fo).max()), flush=True)
-    # the non-equilibrium part agrees to the bfloat16 activation roundings (forward test);
-    # mass and momentum are those of the pulled populations on both sides
-    assert err <= 5e-3
-    np.testing.assert_allclose(fg.sum(axis=0), r, rtol=0, atol=2e-6)
+    # the non-equilibrium part agrees to the bfloat16 activation roundings (forward test;
+    # measured 1.2e-4 with the float32 features); the collision keeps the mass, so the total
+    # is the initial one on both lattices (bounce-back walls included)
+    assert err <= 1e-3
+    assert abs(fg.sum() / rho.sum() - 1.0) <= 1e-6
 
 
 def test_zero_tolerance_with_walls_is_the_plain_collision():
