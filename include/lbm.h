@@ -229,6 +229,21 @@ int lbm_mlp_grad(lbm_mlp* m, const float* dev_x, const float* dev_t, int64_t n,
 int lbm_mlp_train(lbm_mlp* m, const float* dev_x, const float* dev_t, int64_t n,
                   int32_t batch, int64_t steps, float lr);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+   or training loops, harnesses that forbid hipMalloc): the loss and gradient of lbm_mlp_grad
+   without a trainer and without any allocation. dev_weights: the float32 parameter blob
+   (5577 values, device); dev_x [n][12], dev_t [n][9] as in lbm_mlp_grad, with
+   1 <= n <= LBM_MLP_STATIC_MAX_SAMPLES; dev_grad receives 5577 float32 values; dev_loss one
+   float32 (device) or NULL. Enqueued on `stream` (hipStream_t, NULL = null stream); no
+   synchronisation. The per-64-sample partial gradients go to a fixed array of the library
+   (about 5.5 MiB per GPU, held until the process ends) instead of a trainer buffer: calls that
+   overlap on one GPU race on it, so serialise them (one stream, or events). Returns LBM_EINVAL
+   for n outside the range or NULL buffers, LBM_EDEVICE if a launch fails; the text of neither
+   is kept (no context). Results equal lbm_mlp_grad's for the same weights. */
+#define LBM_MLP_STATIC_MAX_SAMPLES 16384
+int lbm_mlp_grad_static(const float* dev_weights, const float* dev_x, const float* dev_t,
+                        int64_t n, float* dev_grad, float* dev_loss, void* stream);
+
 /* ---- measurement ------------------------------------------------------------------------
    Not part of the method: a device-to-device copy of `bytes` bytes (src and dst device
    pointers, 16-byte aligned, not overlapping), enqueued on `stream` with the access pattern of a

@@ -19,6 +19,7 @@ STORAGES = {"fp32": 0, "bf16": 1, "fp16": 2, "fp64": 3}
 COLLISIONS = {"plain": 0, "mlp": 1}
 STREAMINGS = {"auto": 0, "two": 1, "one": 2}
 MLP_NPARAM = 5577
+MLP_STATIC_MAX_SAMPLES = 16384  # LBM_MLP_STATIC_MAX_SAMPLES
 
 
 class LbmError(RuntimeError):
@@ -71,6 +72,7 @@ SIGNATURES = {
     "lbm_mlp_forward": (ctypes.c_int, [_P, _P, _I64, _P]),
     "lbm_mlp_grad": (ctypes.c_int, [_P, _P, _P, _I64, _P, _F]),
     "lbm_mlp_train": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.c_int32, _I64, ctypes.c_float]),
+    "lbm_mlp_grad_static": (ctypes.c_int, [_P, _P, _P, _I64, _P, _P, _P]),
     "lbm_device_copy": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
     "lbm_last_error": (ctypes.c_char_p, [_P]),
     "lbm_destroy": (None, [_P]),
@@ -315,6 +317,16 @@ class Trainer:
             self.close()
         except Exception:
             pass
+
+
+def mlp_grad_static(w_dev, x_dev, t_dev, grad_dev, loss_dev=None):
+    """lbm_mlp_grad_static: loss and gradient without a trainer or any allocation (float32
+    cuda tensors: weights (5577,), x (n, 12), t (n, 9), grad (5577,), loss (1,) or None), on
+    torch's current stream."""
+    _check(load().lbm_mlp_grad_static(w_dev.data_ptr(), x_dev.data_ptr(), t_dev.data_ptr(),
+                                      x_dev.shape[0], grad_dev.data_ptr(),
+                                      loss_dev.data_ptr() if loss_dev is not None else None,
+                                      current_stream_handle()))
 
 
 def device_copy(src, dst):

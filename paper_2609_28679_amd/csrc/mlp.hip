@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cfloat>
 #include <cstdlib>
+#include <mutex>
 
 #include "lbm.h"
 
@@ -603,4 +604,58 @@ hipError_t launch_bgk_d2q9_mlp(const void* A, void* B, const Layout& L, const Gr
   return hipGetLastError();
 }
 
+// ---- gradient without allocation ---------------------------------------------------------------
+// For callers that cannot call hipMalloc (graph capture, serving loops): the per-wavefront
+// partial gradients of k_mlp_grad go to a fixed device array instead of a trainer buffer. Each
+// GPU the library runs on holds its own copy of the array until the process ends; its device
+// address is looked up once per device (with that device current) and kept. k_mlp_grad writes
+// every entry of the rows it uses, so nothing has to be cleared between calls; calls that
+// overlap on one GPU race on the array.
+namespace {
+constexpr int kStaticMaxSamples = LBM_MLP_STATIC_MAX_SAMPLES;
+constexpr int kStaticRows = ((kStaticMaxSamples + 63) / 64 + 3) / 4 * 4;
+static __device__ __align__(256) float scratch[(size_t)kStaticRows * kPart];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first call per device).
+hipError_t scratch_on_current_device(float** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<float*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
+
 }  // namespace lbm
+
+extern "C" int lbm_mlp_grad_static(const float* dev_weights, const float* dev_x,
+                                   const float* dev_t, int64_t n, float* dev_grad,
+                                   float* dev_loss, void* stream) {
+  using namespace lbm;
+  if (n <= 0 || n > kStaticMaxSamples) return LBM_EINVAL;
+  if (!dev_weights || !dev_x || !dev_t || !dev_grad) return LBM_EINVAL;
+  static_assert((size_t)kStaticRows * kPart * sizeof(float) <= ((size_t)8 << 20),
+                "the fixed partials array stays below 8 MiB");
+  float* part = nullptr;
+  if (scratch_on_current_device(&part) != hipSuccess) return LBM_EDEVICE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int B = (int)n;
+  hipError_t e = launch_mlp_grad(dev_x, dev_t, n, 0, B, dev_weights, part, s);
+  // adam = false: the kernel reads the partials and writes grad (and loss); w, m, v untouched
+  if (e == hipSuccess)
+    e = launch_mlp_reduce_adam(part, mlp_partial_count(B), dev_grad, dev_loss,
+                               const_cast<float*>(dev_weights), nullptr, nullptr, false, 0.0f, 1, s);
+  return e == hipSuccess ? LBM_OK : LBM_EDEVICE;
+}
