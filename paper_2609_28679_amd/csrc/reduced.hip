@@ -54,11 +54,37 @@ __device__ __forceinline__ void dpsi3(float u, float (&d)[3]) {
   d[2] = 0.5f * (u2 + u);
 }
 
-// f_i^eq - w_i from drho = rho - 1 and the per-axis deviations
-__device__ __forceinline__ float heq_i(int i, float drho, const float (&dx)[3], const float (&dy)[3]) {
-  const int a = i % 3, b = i / 3;
-  const float pa = wk(a) + dx[a], pb = wk(b) + dy[b];
-  return drho * (pa * pb) + (wk(a) * dy[b] + dx[a] * wk(b) + dx[a] * dy[b]);
+// f_i^eq - w_i of the six stored directions from drho = rho - 1 and the per-axis deviations,
+// factored as psi_b (drho psi_a + d_a) + W_a d_b (psi = W + d, the same sum regrouped): six
+// per-axis values, then one fma per direction.
+__device__ __forceinline__ void heq_stored(float drho, const float (&dx)[3], const float (&dy)[3],
+                                           float (&e)[9]) {
+  float A[3], P[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    A[k] = __builtin_fmaf(drho, wk(k) + dx[k], dx[k]);
+    P[k] = wk(k) + dy[k];
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i)
+    if (f_slot(i) >= 0) e[i] = __builtin_fmaf(P[i / 3], A[i % 3], wk(i % 3) * dy[i / 3]);
+}
+
+// Post-collision populations (shifted, h = f~ - w) of a stored node from its moments and its
+// six decoded non-equilibrium values, rebuilt as described above.
+__device__ __forceinline__ void rebuild(float drho, float ux, float uy, const float (&n)[kRedF],
+                                        float (&h)[9]) {
+  float dx[3], dy[3], e[9];
+  dpsi3(ux, dx);
+  dpsi3(uy, dy);
+  heq_stored(drho, dx, dy, e);
+#pragma unroll
+  for (int i = 0; i < 9; ++i)
+    if (f_slot(i) >= 0) h[i] = e[i] + n[f_slot(i)];
+  const float rho = 1.0f + drho;
+  h[5] = rho * ux - (h[2] + h[8]) + (h[0] + h[3] + h[6]);
+  h[7] = rho * uy - (h[6] + h[8]) + (h[0] + h[1] + h[2]);
+  h[4] = drho - (((h[0] + h[1]) + (h[2] + h[3])) + ((h[5] + h[6]) + (h[7] + h[8])));
 }
 
 // Stored values of one node: moments (rho - 1, u_x, u_y) and the six codes.
@@ -67,41 +93,31 @@ struct RawNode {
   uint16_t n[kRedF];
 };
 
-__device__ __forceinline__ void load_node(const float* __restrict__ M, const uint16_t* __restrict__ N,
-                                          int64_t plane, int64_t off, RawNode& v) {
-#pragma unroll
-  for (int k = 0; k < 3; ++k) v.m[k] = load_nt(M + k * plane + off);
-#pragma unroll
-  for (int k = 0; k < kRedF; ++k) v.n[k] = load_nt(N + k * plane + off);
-}
-
-// Post-collision populations (shifted, h = f~ - w) of a stored node, rebuilt as described above.
 template <typename Codec>
 __device__ __forceinline__ void rebuild_node(const RawNode& v, float s_dec, float (&h)[9]) {
-  const float drho = v.m[0], ux = v.m[1], uy = v.m[2];
-  float dx[3], dy[3];
-  dpsi3(ux, dx);
-  dpsi3(uy, dy);
+  float n[kRedF];
 #pragma unroll
-  for (int i = 0; i < 9; ++i)
-    if (f_slot(i) >= 0) h[i] = heq_i(i, drho, dx, dy) + Codec::dec(v.n[f_slot(i)], s_dec);
-  const float rho = 1.0f + drho;
-  h[5] = rho * ux - (h[2] + h[8]) + (h[0] + h[3] + h[6]);
-  h[7] = rho * uy - (h[6] + h[8]) + (h[0] + h[1] + h[2]);
-  h[4] = drho - (((h[0] + h[1]) + (h[2] + h[3])) + ((h[5] + h[6]) + (h[7] + h[8])));
+  for (int k = 0; k < kRedF; ++k) n[k] = Codec::dec(v.n[k], s_dec);
+  rebuild(v.m[0], v.m[1], v.m[2], n, h);
 }
 
-// Wavefront-strip kernel. A wavefront owns 64 consecutive columns (x0 = 64 k) and `rows` rows
-// and walks them bottom to top; nothing is shared between wavefronts, so there is no barrier.
-// Each lane rebuilds the post-collision populations of its own column once per row and keeps
-// the last three rows in registers; a pull from column x - c_x takes the value from the lane
-// to the left or right with one wave-wide DPP shift, and the two columns beyond the strip
-// (x0 - 1 and x0 + 64, periodic) are rebuilt once per launch for all rows of the strip into a
-// small per-wave LDS table (one vectorised pass). The raw stored values of the row after the
-// next are loaded while the current row collides. The collision is the plain BGK relaxation
-// of Eq. (LBM_f) with f* = f^eq; the new state is written as m = (rho - 1, u) and the six codes
-// of (1 - omega)(f - f^eq(m)).
-constexpr int kRedHaloRows = 66;  // strip rows + 2 per launch (rows <= 64)
+// Wavefront-strip kernel. A wavefront owns 128 consecutive columns (x0 = 128 k), two per lane
+// (columns x0 + 2 l and x0 + 2 l + 1, so every load and store moves a pair: 8 bytes of a moment
+// plane, 4 bytes of a code plane), and `rows` rows, which it walks bottom to top; nothing is
+// shared between wavefronts, so there is no barrier. Each lane rebuilds the post-collision
+// populations of its two columns once per row and keeps the last three rows in registers. A
+// pull from column x - c_x takes the value from the lane's other column or, across a pair
+// boundary, from the neighbouring lane with one wave-wide DPP shift. The two columns beyond the
+// strip (x0 - 1 and the one after the strip's last column, periodic) are rebuilt once per
+// launch for all rows of the strip, one node per lane (lanes 0-31 the left column, 32-63 the
+// right one, row y0 - 1 + lane mod 32), and read with readlane. The stored values of the row
+// after the next are loaded while the current row collides. The collision is the plain BGK
+// relaxation of Eq. (LBM_f) with f* = f^eq; the new state is written as m = (rho - 1, u) and
+// the six codes of (1 - omega)(f - f^eq(m)).
+constexpr int kRedMaxRows = 30;              // rows + 2 halo rows per half wavefront
+constexpr int kRedBlockCols = 2 * kBlock;    // columns of one workgroup
+
+typedef float f2v __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ float shift_from_left(float v) {  // lane l receives lane l - 1
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
@@ -109,77 +125,159 @@ __device__ __forceinline__ float shift_from_left(float v) {  // lane l receives 
 __device__ __forceinline__ float shift_from_right(float v) {  // lane l receives lane l + 1
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
 }
+// Global-memory (address space 1) accesses, the form the scalar-base addressing below needs.
+#define LBM_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ T gload_nt(const LBM_GLOBAL T* p) {
+#if defined(LBM_CACHED_LOADS)
+  return *p;
+#else
+  return __builtin_nontemporal_load(p);
+#endif
+}
+template <typename T>
+__device__ __forceinline__ void gstore_nt(LBM_GLOBAL T* p, T v) {
+#if defined(LBM_PLAIN_STORES)
+  *p = v;
+#else
+  __builtin_nontemporal_store(v, p);
+#endif
+}
+// A wave-uniform pointer held in scalar registers, so that an access p[i] with a 32-bit lane
+// index i takes the scalar-base form (one vector offset register, no 64-bit address per lane).
+template <typename T>
+__device__ __forceinline__ LBM_GLOBAL T* sbase(T* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return reinterpret_cast<LBM_GLOBAL T*>(((uint64_t)hi << 32) | lo);
+}
+// base + a 32-bit byte offset (a zero-extended 32-bit offset is what the scalar-base form takes)
+template <typename T>
+__device__ __forceinline__ LBM_GLOBAL T* at_byte(LBM_GLOBAL T* base, uint32_t off) {
+  typedef LBM_GLOBAL char* cp;
+  typedef LBM_GLOBAL T* tp;
+  return (tp)((cp)(base) + off);
+}
+__device__ __forceinline__ float read_lane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+// Pre-collision moments and the scaled non-equilibrium part (1 - omega)(f - f^eq) of the six
+// stored directions of one column.
+struct Collided {
+  float drho, ux, uy, jx, jy;
+  float q[kRedF];
+};
+
+__device__ __forceinline__ Collided collide_column(const float (&h)[9], float keep) {
+  Collided c;
+  c.drho = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
+  c.jx = (h[2] + h[5] + h[8]) - (h[0] + h[3] + h[6]);
+  c.jy = (h[6] + h[7] + h[8]) - (h[0] + h[1] + h[2]);
+  const float rho = 1.0f + c.drho;
+  c.ux = quotient(c.jx, rho);
+  c.uy = quotient(c.jy, rho);
+  float dx[3], dy[3], e[9];
+  dpsi3(c.ux, dx);
+  dpsi3(c.uy, dy);
+  heq_stored(c.drho, dx, dy, e);
+#pragma unroll
+  for (int i = 0; i < 9; ++i)
+    if (f_slot(i) >= 0) c.q[f_slot(i)] = keep * (h[i] - e[i]);
+  return c;
+}
 
 template <typename Codec, bool WALLS, bool DIAG>
 __global__ void __launch_bounds__(kBlock)
 k_bgk_d2q9_red(const float* __restrict__ M, const uint16_t* __restrict__ N, float* __restrict__ Mo,
                uint16_t* __restrict__ No, int nx, int ny, int64_t pitch, int64_t plane,
                float omega, float s_enc, float s_dec, int rows, double* __restrict__ partials) {
-  // halo[wave][side][row][k]: side 0 = column x0 - 1 (populations 2, 5, 8 moving +x),
-  // side 1 = column x0 + 64 (populations 0, 3, 6 moving -x); row = y - (y0 - 1)
-  __shared__ float halo[kBlock / 64][2][kRedHaloRows][3];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int nbx = (nx + kBlock - 1) / kBlock;
+  const int nbx = (nx + kRedBlockCols - 1) / kRedBlockCols;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int bx = tile % nbx, by = tile / nbx;
-  const int x0 = bx * kBlock + wv * 64;  // first column of this wave's strip
-  const int x = x0 + lane;
-  const bool own = x < nx;
-  const int xc = own ? x : nx - 1;       // a valid column for lanes past the edge
+  const int x0 = bx * kRedBlockCols + wv * 128;  // first column of this wave's strip
   const int y0 = by * rows;
   const int yend = min(y0 + rows, ny);
   const float keep = 1.0f - omega;
+  const int64_t hp = plane >> 1;                 // plane stride in pairs (planes are even)
   double acc[kDiagValues] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (x0 < nx) {  // strips past the right edge only join the diagnostics reduction
-  const int last = min(63, nx - 1 - x0);  // lane holding the strip's last column
-  // rows the pulls read: y0 - 1 .. yend (periodic), or only those inside the walls
-  auto row_of = [&](int r) { return ((r % ny) + ny) % ny; };
-  auto outside = [&](int r) { return WALLS && (r < 0 || r >= ny); };
+  const int ncol = min(128, nx - x0);
+  const int ll = (ncol - 1) >> 1;                // lane holding the strip's last column
+  const bool last_even = ((ncol - 1) & 1) == 0;  // ... in its first slot
+  // column pair of this lane; pairs past the row's end load the last pair (the odd column of
+  // an odd-width row lies in the row padding) and store nothing
+  const int pmax = (nx + 1) / 2 - 1;
+  const int p = x0 / 2 + lane;
+  const uint32_t pc = (uint32_t)min(p, pmax);
+  const bool own0 = p <= pmax, own1 = 2 * p + 1 < nx;
+  const uint32_t pc8 = pc * 8u, pc4 = pc * 4u;  // byte offsets in a row (rows are < 4 GiB)
+  // a row beyond a wall reads the nearest real row (its values are then not used)
+  auto src_row = [&](int r) {
+    return WALLS ? min(max(r, 0), ny - 1) : (r < 0 ? r + ny : (r >= ny ? r - ny : r));
+  };
 
-  // ---- halo columns for all rows of the strip: lane = (side, row) --------------------------
+  // ---- halo columns, one node per lane ------------------------------------------------------
+  // left lanes keep populations 2, 5, 8 (moving +x), right lanes 0, 3, 6 (moving -x)
+  float hv[3];
   {
-    const int nh = (yend - y0) + 2;
-    for (int k = lane; k < 2 * nh; k += 64) {
-      const int side = k >= nh, hr = side ? k - nh : k;
-      const int r = y0 - 1 + hr;
-      if (outside(r)) continue;
-      const int xs = side ? (x0 + last + 1 == nx ? 0 : x0 + last + 1) : (x0 == 0 ? nx - 1 : x0 - 1);
-      RawNode v;
-      const int64_t off = (int64_t)row_of(r) * pitch + xs;
+    const int side = lane >> 5;
+    const int hr = min(lane & 31, yend - y0 + 1);
+    const int xs = side ? (x0 + ncol == nx ? 0 : x0 + ncol) : (x0 == 0 ? nx - 1 : x0 - 1);
+    const int64_t off = (int64_t)src_row(y0 - 1 + hr) * pitch + xs;
+    RawNode v;
 #pragma unroll
-      for (int q = 0; q < 3; ++q) v.m[q] = M[q * plane + off];
+    for (int k = 0; k < 3; ++k) v.m[k] = M[k * plane + off];
 #pragma unroll
-      for (int q = 0; q < kRedF; ++q) v.n[q] = N[q * plane + off];
-      float h[9];
-      rebuild_node<Codec>(v, s_dec, h);
-      float* dst = halo[wv][side][hr];
-      if (side == 0) { dst[0] = h[2]; dst[1] = h[5]; dst[2] = h[8]; }
-      else { dst[0] = h[0]; dst[1] = h[3]; dst[2] = h[6]; }
-    }
+    for (int k = 0; k < kRedF; ++k) v.n[k] = N[k * plane + off];
+    float h[9];
+    rebuild_node<Codec>(v, s_dec, h);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) hv[k] = side ? h[3 * k] : h[3 * k + 2];
   }
 
-  // ---- own column: rows y0 - 1 and y0 rebuilt, y0 + 1 loaded ---------------------------------
-  float ring[3][9];  // ring[r mod 3]: rebuilt row r of the own column
-  RawNode raw;
-  // The loads are unconditional (a row beyond a wall reads the nearest real row, whose values
-  // are then not used): a load issued only on some paths would make the compiler wait for every
-  // outstanding memory operation, the previous row's stores included, before the next row.
+  // ---- own columns: rows y0 - 1 and y0 rebuilt, y0 + 1 loaded --------------------------------
+  float R0[3][9], R1[3][9];  // [r mod 3]: rebuilt row r of the even / odd column
+  f2v rm[3];
+  uint32_t rn[kRedF];
+  // The loads are unconditional: a load issued only on some paths would make the compiler wait
+  // for every outstanding memory operation, the previous row's stores included.
+  // The 32-bit lane offsets are re-declared where they are used (an empty asm), so that the
+  // compiler does not hoist their 64-bit extension out of the loop, which loses the scalar-base
+  // form of the accesses.
   auto fetch = [&](int r) {
-    const int rr = WALLS ? (r < 0 ? 0 : (r > ny - 1 ? ny - 1 : r)) : row_of(r);
-    load_node(M, N, plane, (int64_t)rr * pitch + xc, raw);
+    uint32_t o8 = pc8, o4 = pc4;
+    asm volatile("" : "+v"(o8), "+v"(o4));
+    const int64_t base = (int64_t)src_row(r) * pitch;
+    const f2v* mrow = reinterpret_cast<const f2v*>(M + base);
+    const uint32_t* nrow = reinterpret_cast<const uint32_t*>(N + base);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) rm[k] = gload_nt(at_byte(sbase(mrow + k * hp), o8));
+#pragma unroll
+    for (int k = 0; k < kRedF; ++k) rn[k] = gload_nt(at_byte(sbase(nrow + k * hp), o4));
   };
-  auto put = [&](int r, float (&dst)[9]) {
-    if (outside(r)) return;
-    rebuild_node<Codec>(raw, s_dec, dst);
+  auto put = [&](float (&d0)[9], float (&d1)[9]) {
+    float n0[kRedF], n1[kRedF];
+#pragma unroll
+    for (int k = 0; k < kRedF; ++k) {
+      n0[k] = Codec::dec_lo(rn[k], s_dec);
+      n1[k] = Codec::dec_hi(rn[k], s_dec);
+    }
+    rebuild(rm[0].x, rm[1].x, rm[2].x, n0, d0);
+    rebuild(rm[0].y, rm[1].y, rm[2].y, n1, d1);
   };
   fetch(y0 - 1);
-  put(y0 - 1, ring[0]);
+  put(R0[0], R1[0]);
   fetch(y0);
-  put(y0, ring[1]);
+  put(R0[1], R1[1]);
   fetch(y0 + 1);
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // a per-lane copy of yend: the store conditions below are then lane masks, whose skip paths
+  // the compiler's wait counting handles without draining every outstanding load and store at
+  // the top of the loop (a uniform branch around the stores made it wait for everything)
+  int yend_v = yend;
+  asm volatile("" : "+v"(yend_v));
 
   // ring slot of row r: (r - y0 + 1) mod 3, a compile-time constant in the unrolled body; the
   // body always runs all three rows (rows past yend compute on re-read data and store
@@ -189,61 +287,73 @@ k_bgk_d2q9_red(const float* __restrict__ M, const uint16_t* __restrict__ N, floa
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
     const int y = yb + j;
-    const bool live = y < yend;
-    // rebuild row y + 1 (loaded one iteration ago), load row y + 2
-    put(min(y + 1, yend), ring[(j + 2) % 3]);
+    const bool live = y < yend_v;
+    // rebuild row y + 1 (loaded one row ago), load row y + 2
+    put(R0[(j + 2) % 3], R1[(j + 2) % 3]);
     fetch(min(y + 2, yend));  // past the last needed row: a harmless re-read
-    const float (&rm)[9] = ring[j];            // row y - 1
-    const float (&r0)[9] = ring[(j + 1) % 3];  // row y
-    const float (&rp)[9] = ring[(j + 2) % 3];  // row y + 1
-    const int hr = min(y, yend - 1) - y0 + 1;   // halo row of y (rows past yend: the last)
+    const int hr = min(y, yend - 1) - y0 + 1;  // halo row of y (rows past yend: the last)
     // pull: f_i(x) = f~_i(x - c_i); i = (c_x + 1) + 3 (c_y + 1); rows beyond a wall bounce back
-    float h[9];
+    float a[9], b[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      const int ka = i % 3, kb = i / 3;          // c_x = ka - 1, c_y = kb - 1
+      const int ka = i % 3, kb = i / 3;  // c_x = ka - 1, c_y = kb - 1
+      const int cur = (j + 1) % 3;
       const bool bounce = WALLS && ((kb == 2 && y == 0) || (kb == 0 && y == ny - 1));
       if (bounce) {
-        h[i] = r0[8 - i];
+        a[i] = R0[cur][8 - i];
+        b[i] = R1[cur][8 - i];
         continue;
       }
-      const float(&src)[9] = kb == 0 ? rp : (kb == 1 ? r0 : rm);  // row y - c_y
+      const int sr = kb == 0 ? (j + 2) % 3 : (kb == 1 ? cur : j);  // ring slot of row y - c_y
       const int hrow = hr - (kb - 1);
       if (ka == 1) {
-        h[i] = src[i];
+        a[i] = R0[sr][i];
+        b[i] = R1[sr][i];
       } else if (ka == 2) {  // from column x - 1
-        const float v = shift_from_left(src[i]);
-        h[i] = lane == 0 ? halo[wv][0][hrow][i / 3] : v;
+        b[i] = R0[sr][i];
+        const float v = shift_from_left(R1[sr][i]);
+        const float edge = read_lane(hv[kb], hrow);
+        a[i] = lane == 0 ? edge : v;
       } else {               // from column x + 1
-        const float v = shift_from_right(src[i]);
-        h[i] = lane == last ? halo[wv][1][hrow][i / 3] : v;
+        const float edge = read_lane(hv[kb], 32 + hrow);
+        a[i] = (lane == ll && last_even) ? edge : R1[sr][i];
+        const float v = shift_from_right(R0[sr][i]);
+        b[i] = lane == ll ? edge : v;
       }
     }
-    // moments (sum_i w_i = 1, sum_i c_i w_i = 0) and the relaxation
-    const float drho = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
-    const float jx = (h[2] + h[5] + h[8]) - (h[0] + h[3] + h[6]);
-    const float jy = (h[6] + h[7] + h[8]) - (h[0] + h[1] + h[2]);
-    const float rho = 1.0f + drho;
-    const float ux = quotient(jx, rho), uy = quotient(jy, rho);
-    float dx[3], dy[3];
-    dpsi3(ux, dx);
-    dpsi3(uy, dy);
-    if (own && live) {
-      const int64_t self = (int64_t)y * pitch + x;
-      store_nt(Mo + self, drho);
-      store_nt(Mo + plane + self, ux);
-      store_nt(Mo + 2 * plane + self, uy);
+    const Collided c0 = collide_column(a, keep);
+    const Collided c1 = collide_column(b, keep);
+    {
+      // a pair store also for the last column of an odd-width row: its second column is the
+      // row's padding (pitch > nx), which nothing reads
+      const int64_t self = (int64_t)y * pitch;
+      if (own0 && live) {
+        uint32_t o8 = pc8, o4 = pc4;
+        asm volatile("" : "+v"(o8), "+v"(o4));
+        f2v* mrow = reinterpret_cast<f2v*>(Mo + self);
+        uint32_t* nrow = reinterpret_cast<uint32_t*>(No + self);
+        gstore_nt(at_byte(sbase(mrow), o8), f2v{c0.drho, c1.drho});
+        gstore_nt(at_byte(sbase(mrow + hp), o8), f2v{c0.ux, c1.ux});
+        gstore_nt(at_byte(sbase(mrow + 2 * hp), o8), f2v{c0.uy, c1.uy});
 #pragma unroll
-      for (int i = 0; i < 9; ++i)
-        if (f_slot(i) >= 0)
-          store_nt(No + f_slot(i) * plane + self,
-                   Codec::enc(keep * (h[i] - heq_i(i, drho, dx, dy)), s_enc));
+        for (int k = 0; k < kRedF; ++k)
+          gstore_nt(at_byte(sbase(nrow + k * hp), o4), Codec::enc2(c0.q[k], c1.q[k], s_enc));
+      }
       if (DIAG) {
-        const double rho = 1.0 + (double)drho;
-        acc[0] += rho;
-        acc[1] += (double)jx;
-        acc[2] += (double)jy;
-        acc[4] += 0.5 * rho * ((double)ux * ux + (double)uy * uy);
+        if (own0 && live) {
+          const double rho = 1.0 + (double)c0.drho;
+          acc[0] += rho;
+          acc[1] += (double)c0.jx;
+          acc[2] += (double)c0.jy;
+          acc[4] += 0.5 * rho * ((double)c0.ux * c0.ux + (double)c0.uy * c0.uy);
+        }
+        if (own1 && live) {
+          const double rho = 1.0 + (double)c1.drho;
+          acc[0] += rho;
+          acc[1] += (double)c1.jx;
+          acc[2] += (double)c1.jy;
+          acc[4] += 0.5 * rho * ((double)c1.ux * c1.ux + (double)c1.uy * c1.uy);
+        }
       }
     }
   }
@@ -295,18 +405,18 @@ __global__ void k_decode_bgk_red(int i, const float* __restrict__ M, const uint1
 }
 
 // ---- launchers -----------------------------------------------------------------------------
-// Tiles of 256 columns (four 64-column wavefront strips) by `rows` rows, launched as a
+// Tiles of 512 columns (four 128-column wavefront strips) by `rows` rows, launched as a
 // one-dimensional grid (tile = bx + nbx by), so tall lattices need no more rows per tile; the
-// per-wave halo table holds rows + 2 <= kRedHaloRows rows.
+// halo rows of a strip (rows + 2) fit one half wavefront.
 Grid make_grid_red(const Layout& L) {
   Grid G;
   G.bx = kBlock;
-  G.nbx = (L.nx + kBlock - 1) / kBlock;
+  G.nbx = (L.nx + kRedBlockCols - 1) / kRedBlockCols;
   G.rows = 12;
 #ifdef LBM_TUNING_ENV
   if (const char* v = getenv("LBM_RED_ROWS")) G.rows = atoi(v);
 #endif
-  if (G.rows > kRedHaloRows - 2) G.rows = kRedHaloRows - 2;
+  if (G.rows > kRedMaxRows) G.rows = kRedMaxRows;
   if (G.rows < 1) G.rows = 1;
   G.nby = (L.ny + G.rows - 1) / G.rows;
   return G;
@@ -332,6 +442,9 @@ static inline const uint16_t* neq_of(const void* buf, const Layout& L, int nm) {
 hipError_t launch_bgk_d2q9_red(int codec, const void* A, void* B, const Layout& L, const Grid& G,
                                double omega, bool walls, float s_enc, float s_dec,
                                double* partials, hipStream_t s) {
+  // the step moves column pairs: 8-byte moment pairs and 4-byte code pairs
+  if ((L.pitch | L.plane) & 1) return hipErrorInvalidValue;
+  if (G.rows < 1 || G.rows > kRedMaxRows) return hipErrorInvalidValue;
   const float* M = static_cast<const float*>(A);
   const uint16_t* N = neq_of(A, L, 3);
   float* Mo = static_cast<float*>(B);

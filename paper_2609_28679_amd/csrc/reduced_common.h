@@ -29,6 +29,18 @@ struct CodecBF16 {
   __device__ static __forceinline__ float dec(uint16_t h, float) {
     return __uint_as_float((uint32_t)h << 16);
   }
+  // Two codes in one 32-bit word (first value in the low half, the lower address): one
+  // hardware conversion, round to nearest even as enc.
+  __device__ static __forceinline__ uint32_t enc2(float a, float b, float) {
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    const f32x2 v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+  }
+  __device__ static __forceinline__ float dec_lo(uint32_t w, float) { return __uint_as_float(w << 16); }
+  __device__ static __forceinline__ float dec_hi(uint32_t w, float) {
+    return __uint_as_float(w & 0xFFFF0000u);
+  }
 };
 
 struct CodecFP16 {
@@ -39,6 +51,15 @@ struct CodecFP16 {
   }
   __device__ static __forceinline__ float dec(uint16_t h, float inv_scale) {
     return (float)__builtin_bit_cast(_Float16, h) * inv_scale;
+  }
+  __device__ static __forceinline__ uint32_t enc2(float a, float b, float scale) {
+    return (uint32_t)enc(a, scale) | ((uint32_t)enc(b, scale) << 16);
+  }
+  __device__ static __forceinline__ float dec_lo(uint32_t w, float inv_scale) {
+    return dec((uint16_t)(w & 0xFFFFu), inv_scale);
+  }
+  __device__ static __forceinline__ float dec_hi(uint32_t w, float inv_scale) {
+    return dec((uint16_t)(w >> 16), inv_scale);
   }
 };
 
