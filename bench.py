@@ -154,13 +154,14 @@ def surrogate_variant(binding, inputs, steps, inference_only=False):
     return out
 
 
-def copy_ceiling(binding, reps=20):
-    """Device-to-device copy of 1 GiB (read 1 GiB + write 1 GiB) with the library's streaming
-    copy kernel and with the runtime's copy (torch copy_), timed with HIP events on torch's
-    current stream, on which both run: the bandwidth a streaming kernel reaches when nothing
-    stays in the 256 MB last-level cache."""
+def copy_ceiling(binding, nbytes=1 << 30, reps=20):
+    """Device-to-device copy of nbytes (read nbytes + write nbytes) with the library's
+    streaming copy kernel and with the runtime's copy (torch copy_), timed with HIP events on
+    torch's current stream, on which both run. At 1 GiB nothing stays in the 256 MB
+    last-level cache (the HBM ceiling of a streaming kernel); at the size of one 2048^2
+    reduced-storage state (two buffers of 100.7 MB) both buffers fit it."""
     import torch
-    n = 1 << 28
+    n = nbytes // 4
     src = torch.ones(n, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     out = {"bytes_moved": 2 * n * 4}
@@ -268,6 +269,8 @@ def main():
     achieved4 = bytes_per_node * nodes4 / per4 / 1e9
     copy = copy_ceiling(binding)
     log("4096^2: kernel %.2f us, %.1f GB/s; 1 GiB copy: %s" % (per4 * 1e6, achieved4, copy))
+    copy_llc = copy_ceiling(binding, 2048 * 2048 * 24, reps=200)
+    log("copy of one 2048^2 reduced-storage state (100.7 MB): %s" % copy_llc)
 
     variants = {}
     if not args.no_variants:
@@ -452,7 +455,8 @@ def main():
                                       "kernel_us": round(per4 * 1e6, 2),
                                       "achieved": round(achieved4, 1),
                                       "frac": round(achieved4 / HBM_PEAK_GBS, 4)},
-                     "copy_ceiling": copy},
+                     "copy_ceiling": copy,
+                     "copy_ceiling_cache_resident": copy_llc},
         "variants": variants,
     }
     if not args.no_cpu:

@@ -20,6 +20,12 @@ FLAGS = [
     "-Wall", "-Wno-unused-result",
 ]
 
+# Per-source additions. mlp.hip: matrix-core results in ordinary vector registers (no copy out
+# of the accumulation registers after every tile; the surrogate step reads each result once).
+SOURCE_FLAGS = {
+    "mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=true"],
+}
+
 
 def hipcc():
     for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc"):
@@ -46,7 +52,8 @@ def build(verbose=False):
     tmpdir = tempfile.mkdtemp(prefix="lbm_build_")
     try:
         objs = [os.path.join(tmpdir, os.path.splitext(s)[0] + ".o") for s in SOURCES]
-        cmds = [[hipcc()] + FLAGS + inc + ["-c", os.path.join(CSRC, s), "-o", o]
+        cmds = [[hipcc()] + FLAGS + SOURCE_FLAGS.get(s, []) + inc
+                + ["-c", os.path.join(CSRC, s), "-o", o]
                 for s, o in zip(SOURCES, objs)]
         workers = max(1, min(len(cmds), os.cpu_count() or 1, 8))
         with ThreadPoolExecutor(workers) as ex:

@@ -77,4 +77,50 @@ __device__ __forceinline__ void store_nt(T* p, T v) {
 #endif
 }
 
+
+// ---- scalar-base addressing ------------------------------------------------------------------
+// A row of a plane is wave-uniform in the streaming kernels; with its address in scalar
+// registers and a 32-bit lane offset, a load or store needs one vector register for the
+// address instead of a 64-bit address computed per lane.
+// Global-memory (address space 1) accesses, the form the scalar-base addressing takes.
+#define LBM_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ T gload_nt(const LBM_GLOBAL T* p) {
+#if defined(LBM_CACHED_LOADS)
+  return *p;
+#else
+  return __builtin_nontemporal_load(p);
+#endif
+}
+template <typename T>
+__device__ __forceinline__ void gstore_nt(LBM_GLOBAL T* p, T v) {
+#if defined(LBM_PLAIN_STORES)
+  *p = v;
+#else
+  __builtin_nontemporal_store(v, p);
+#endif
+}
+// A wave-uniform pointer held in scalar registers, so that an access p[i] with a 32-bit lane
+// index i takes the scalar-base form (one vector offset register, no 64-bit address per lane).
+template <typename T>
+__device__ __forceinline__ LBM_GLOBAL T* sbase(T* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return reinterpret_cast<LBM_GLOBAL T*>(((uint64_t)hi << 32) | lo);
+}
+// A 32-bit lane offset re-declared at its use (an empty asm), so that the compiler does not
+// hoist its 64-bit extension out of a loop, which loses the scalar-base form of the access.
+__device__ __forceinline__ uint32_t fresh(uint32_t o) {
+  asm volatile("" : "+v"(o));
+  return o;
+}
+// base + a 32-bit byte offset (a zero-extended 32-bit offset is what the scalar-base form takes)
+template <typename T>
+__device__ __forceinline__ LBM_GLOBAL T* at_byte(LBM_GLOBAL T* base, uint32_t off) {
+  typedef LBM_GLOBAL char* cp;
+  typedef LBM_GLOBAL T* tp;
+  return (tp)((cp)(base) + off);
+}
+
 }  // namespace lbm

@@ -263,7 +263,7 @@ void make_plan(const lbm_params* p, Plan& P) {
   // reduced storage: float32 moment planes + uint16 non-equilibrium planes
   // (isothermal: 3 + 6, double distribution: 4 + 6 + 8)
   const size_t pop = P.codec >= 0 ? (P.ddf ? (size_t)P.L.plane * (4 * 4 + 14 * 2)
-                                           : (size_t)P.L.plane * (3 * 4 + 6 * 2))
+                                           : red_state_bytes(P.L))
                                    : (size_t)P.planes * P.L.plane * P.elem;
   P.off_A = off; off = align_up(off + pop, 256);
   P.off_B = off; if (!P.aa) off = align_up(off + pop, 256);

@@ -150,6 +150,8 @@ hipError_t launch_moments_ddf3(int kind, const void* A, const Layout& L, const D
 // Reduced storage (D2Q9 isothermal): 3 float32 moment planes then 6 uint16 planes.
 // codec 0 = bfloat16, 1 = float16 with scale s_enc = 2^S, s_dec = 2^-S.
 Grid make_grid_red(const Layout& L);
+// bytes of one isothermal reduced-storage state buffer (planes and strip edge records)
+size_t red_state_bytes(const Layout& L);
 hipError_t launch_bgk_d2q9_red(int codec, const void* A, void* B, const Layout& L, const Grid& G,
                                double omega, bool walls, float s_enc, float s_dec,
                                double* partials, hipStream_t s);

@@ -332,14 +332,17 @@ __device__ __forceinline__ double wrest(int i) {
 template <bool WALLS>
 __device__ __forceinline__ void pull9h(const float* __restrict__ A, int nx, int ny, int64_t pitch,
                                        int64_t plane, int x, int y, float (&h)[9]) {
-  const int xs[3] = {x == nx - 1 ? 0 : x + 1, x, x == 0 ? nx - 1 : x - 1};
+  // byte offsets of the source columns (the rows are wave-uniform: scalar bases)
+  const uint32_t xs[3] = {fresh(4u * (x == nx - 1 ? 0 : x + 1)), fresh(4u * x),
+                          fresh(4u * (x == 0 ? nx - 1 : x - 1))};
   const int ys[3] = {y == ny - 1 ? 0 : y + 1, y, y == 0 ? ny - 1 : y - 1};
-  const int64_t self = (int64_t)y * pitch + x;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     const int ka = i % 3, kb = i / 3;
     const bool bounce = WALLS && ((kb == 2 && y == 0) || (kb == 0 && y == ny - 1));
-    h[i] = bounce ? load_nt(A + (8 - i) * plane + self) : load_nt(A + i * plane + (int64_t)ys[kb] * pitch + xs[ka]);
+    const float* row = bounce ? A + (8 - i) * plane + (int64_t)y * pitch
+                              : A + i * plane + (int64_t)ys[kb] * pitch;
+    h[i] = gload_nt(at_byte(sbase(row), bounce ? xs[1] : xs[ka]));
   }
 }
 
@@ -492,10 +495,11 @@ k_bgk_d2q9_mlp(const float* __restrict__ A, float* __restrict__ B, int nx, int n
       const bool fb = !(err <= tol2 * (keep * keep) * ref);
       fallbacks += fb ? 1u : 0u;
       const float rs = (1.0f + drho) * (1.0f / kSNeq);
-      float* out = B + (int64_t)y * pitch + x;
+      const uint32_t xo = fresh(4u * x);
 #pragma unroll
       for (int i = 0; i < 9; ++i)
-        store_nt(out + i * plane, fb ? h[i] + omega * (heq[i] - h[i]) : heq[i] + rs * yv[i]);
+        gstore_nt(at_byte(sbase(B + i * plane + (int64_t)y * pitch), xo),
+                  fb ? h[i] + omega * (heq[i] - h[i]) : heq[i] + rs * yv[i]);
       if (DIAG) {
         const double rho = 1.0 + (double)drho;
         acc[0] += rho;
@@ -572,11 +576,33 @@ hipError_t launch_harvest(const void* A, const Layout& L, bool walls, int view, 
   return hipGetLastError();
 }
 
+// Workgroups of the surrogate step that the current device holds at once (compute units times
+// the workgroups one compute unit holds with this kernel's registers and LDS), or 0 if the
+// device cannot be queried.
+static int mlp_resident_workgroups() {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_bgk_d2q9_mlp<false, false>, kBlock, 0) !=
+      hipSuccess)
+    return 0;
+  return cus * per;
+}
+
+// Rows per workgroup: as few as keep every workgroup resident at once (one round over the
+// chip, so no tail of late workgroups), which also spreads the per-workgroup weight load over
+// as many rows as possible. 2048^2 on MI355X: 13 rows, 1264 workgroups for 256 x 5 resident.
 Grid make_grid_mlp(const Layout& L) {
   Grid G;
   G.bx = kBlock;
   G.nbx = (L.nx + kBlock - 1) / kBlock;
-  G.rows = 8;  // amortises the per-workgroup weight load over 8 rows
+  G.rows = 8;
+  const int64_t resident = mlp_resident_workgroups();
+  if (resident > 0) {
+    const int64_t units = (int64_t)L.ny * G.nbx;
+    G.rows = (int)std::max<int64_t>(1, (units + resident - 1) / resident);
+  }
 #ifdef LBM_TUNING_ENV
   if (const char* v = getenv("LBM_MLP_ROWS")) G.rows = atoi(v);
 #endif

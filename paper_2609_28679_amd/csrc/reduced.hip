@@ -109,13 +109,31 @@ __device__ __forceinline__ void rebuild_node(const RawNode& v, float s_dec, floa
 // pull from column x - c_x takes the value from the lane's other column or, across a pair
 // boundary, from the neighbouring lane with one wave-wide DPP shift. The two columns beyond the
 // strip (x0 - 1 and the one after the strip's last column, periodic) are rebuilt once per
-// launch for all rows of the strip, one node per lane (lanes 0-31 the left column, 32-63 the
-// right one, row y0 - 1 + lane mod 32), and read with readlane. The stored values of the row
-// after the next are loaded while the current row collides. The collision is the plain BGK
+// launch for all rows of the strip from the edge records below, one node per lane (lanes 0-31
+// the left column, 32-63 the right one, row y0 - 1 + lane mod 32), and read with readlane. The
+// stored values of a row are loaded three rows ahead of its turn. The collision is the plain BGK
 // relaxation of Eq. (LBM_f) with f* = f^eq; the new state is written as m = (rho - 1, u) and
 // the six codes of (1 - omega)(f - f^eq(m)).
 constexpr int kRedMaxRows = 30;              // rows + 2 halo rows per half wavefront
 constexpr int kRedBlockCols = 2 * kBlock;    // columns of one workgroup
+constexpr int kRedStrip = 128;               // columns of one wavefront strip
+
+// Edge records: the stored values (moments and codes, the same bits as in the planes) of the
+// first and last column of every 128-column strip, contiguous in y, written by the step that
+// produces them. A strip's neighbour columns are the last column of the strip to its left and
+// the first column of the strip to its right (periodic), so the halo table of a wavefront reads
+// a few cache lines instead of one line per value: read from the planes, the halo of a strip of
+// 12 rows pulled 64 lines per load instruction through the L1 for 256 useful bytes, which
+// delayed the start of every wavefront (49 vs 43 us at 2048^2).
+struct __attribute__((aligned(16))) EdgeRec {
+  float m[4];        // rho - 1, u_x, u_y, unused
+  uint16_t n[8];     // the six codes, two unused
+};
+static_assert(sizeof(EdgeRec) == 32, "edge records are two 16-byte words");
+// record of strip s, side e (0 first column, 1 last column), row y
+__host__ __device__ inline int64_t edge_index(int s, int e, int y, int ny) {
+  return ((int64_t)s * 2 + e) * ny + y;
+}
 
 typedef float f2v __attribute__((ext_vector_type(2)));
 
@@ -124,40 +142,6 @@ __device__ __forceinline__ float shift_from_left(float v) {  // lane l receives 
 }
 __device__ __forceinline__ float shift_from_right(float v) {  // lane l receives lane l + 1
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
-}
-// Global-memory (address space 1) accesses, the form the scalar-base addressing below needs.
-#define LBM_GLOBAL __attribute__((address_space(1)))
-template <typename T>
-__device__ __forceinline__ T gload_nt(const LBM_GLOBAL T* p) {
-#if defined(LBM_CACHED_LOADS)
-  return *p;
-#else
-  return __builtin_nontemporal_load(p);
-#endif
-}
-template <typename T>
-__device__ __forceinline__ void gstore_nt(LBM_GLOBAL T* p, T v) {
-#if defined(LBM_PLAIN_STORES)
-  *p = v;
-#else
-  __builtin_nontemporal_store(v, p);
-#endif
-}
-// A wave-uniform pointer held in scalar registers, so that an access p[i] with a 32-bit lane
-// index i takes the scalar-base form (one vector offset register, no 64-bit address per lane).
-template <typename T>
-__device__ __forceinline__ LBM_GLOBAL T* sbase(T* p) {
-  const uint64_t v = reinterpret_cast<uint64_t>(p);
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-  return reinterpret_cast<LBM_GLOBAL T*>(((uint64_t)hi << 32) | lo);
-}
-// base + a 32-bit byte offset (a zero-extended 32-bit offset is what the scalar-base form takes)
-template <typename T>
-__device__ __forceinline__ LBM_GLOBAL T* at_byte(LBM_GLOBAL T* base, uint32_t off) {
-  typedef LBM_GLOBAL char* cp;
-  typedef LBM_GLOBAL T* tp;
-  return (tp)((cp)(base) + off);
 }
 __device__ __forceinline__ float read_lane(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
@@ -190,8 +174,9 @@ __device__ __forceinline__ Collided collide_column(const float (&h)[9], float ke
 
 template <typename Codec, bool WALLS, bool DIAG>
 __global__ void __launch_bounds__(kBlock)
-k_bgk_d2q9_red(const float* __restrict__ M, const uint16_t* __restrict__ N, float* __restrict__ Mo,
-               uint16_t* __restrict__ No, int nx, int ny, int64_t pitch, int64_t plane,
+k_bgk_d2q9_red(const float* __restrict__ M, const uint16_t* __restrict__ N,
+               const EdgeRec* __restrict__ E, float* __restrict__ Mo, uint16_t* __restrict__ No,
+               EdgeRec* __restrict__ Eo, int nx, int ny, int64_t pitch, int64_t plane,
                float omega, float s_enc, float s_dec, int rows, double* __restrict__ partials) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int nbx = (nx + kRedBlockCols - 1) / kRedBlockCols;
@@ -219,68 +204,78 @@ k_bgk_d2q9_red(const float* __restrict__ M, const uint16_t* __restrict__ N, floa
     return WALLS ? min(max(r, 0), ny - 1) : (r < 0 ? r + ny : (r >= ny ? r - ny : r));
   };
 
-  // ---- halo columns, one node per lane ------------------------------------------------------
-  // left lanes keep populations 2, 5, 8 (moving +x), right lanes 0, 3, 6 (moving -x)
+  // ---- halo columns, one node per lane, from the edge records --------------------------------
+  // lanes 0-31: the column left of the strip (last column of strip s - 1), keeping populations
+  // 2, 5, 8 (moving +x); lanes 32-63: the column right of it (first column of strip s + 1),
+  // keeping 0, 3, 6 (moving -x); row y0 - 1 + lane mod 32
   float hv[3];
   {
+    const int ns = (nx + kRedStrip - 1) / kRedStrip, s = x0 / kRedStrip;
     const int side = lane >> 5;
     const int hr = min(lane & 31, yend - y0 + 1);
-    const int xs = side ? (x0 + ncol == nx ? 0 : x0 + ncol) : (x0 == 0 ? nx - 1 : x0 - 1);
-    const int64_t off = (int64_t)src_row(y0 - 1 + hr) * pitch + xs;
+    const int64_t rec = side ? edge_index(s + 1 == ns ? 0 : s + 1, 0, src_row(y0 - 1 + hr), ny)
+                             : edge_index(s == 0 ? ns - 1 : s - 1, 1, src_row(y0 - 1 + hr), ny);
+    typedef float f4v __attribute__((ext_vector_type(4)));
+    typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+    const f4v em = *reinterpret_cast<const f4v*>(&E[rec].m[0]);
+    const u4v en = *reinterpret_cast<const u4v*>(&E[rec].n[0]);
     RawNode v;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) v.m[k] = M[k * plane + off];
-#pragma unroll
-    for (int k = 0; k < kRedF; ++k) v.n[k] = N[k * plane + off];
+    v.m[0] = em.x; v.m[1] = em.y; v.m[2] = em.z;
+    v.n[0] = (uint16_t)(en.x & 0xFFFFu); v.n[1] = (uint16_t)(en.x >> 16);
+    v.n[2] = (uint16_t)(en.y & 0xFFFFu); v.n[3] = (uint16_t)(en.y >> 16);
+    v.n[4] = (uint16_t)(en.z & 0xFFFFu); v.n[5] = (uint16_t)(en.z >> 16);
     float h[9];
     rebuild_node<Codec>(v, s_dec, h);
 #pragma unroll
     for (int k = 0; k < 3; ++k) hv[k] = side ? h[3 * k] : h[3 * k + 2];
   }
 
-  // ---- own columns: rows y0 - 1 and y0 rebuilt, y0 + 1 loaded --------------------------------
-  float R0[3][9], R1[3][9];  // [r mod 3]: rebuilt row r of the even / odd column
-  f2v rm[3];
-  uint32_t rn[kRedF];
+  // ---- own columns: rows y0 - 1 and y0 rebuilt, y0 + 1 and y0 + 2 loading -------------------
+  // Slot of row r in both rings: (r - y0 + 1) mod 3, a compile-time constant in the unrolled
+  // loop body. The stored values of a row are loaded three rows before its turn (two rows in
+  // flight per wavefront while one collides), rebuilt one row before.
+  float R0[3][9], R1[3][9];  // rebuilt rows of the even / odd column
+  f2v rm[3][3];              // raw moments of the rows in flight
+  uint32_t rn[3][kRedF];     // raw code pairs of the rows in flight
   // The loads are unconditional: a load issued only on some paths would make the compiler wait
   // for every outstanding memory operation, the previous row's stores included.
   // The 32-bit lane offsets are re-declared where they are used (an empty asm), so that the
   // compiler does not hoist their 64-bit extension out of the loop, which loses the scalar-base
   // form of the accesses.
-  auto fetch = [&](int r) {
+  auto fetch = [&](int r, f2v (&m)[3], uint32_t (&n)[kRedF]) {
     uint32_t o8 = pc8, o4 = pc4;
     asm volatile("" : "+v"(o8), "+v"(o4));
     const int64_t base = (int64_t)src_row(r) * pitch;
     const f2v* mrow = reinterpret_cast<const f2v*>(M + base);
     const uint32_t* nrow = reinterpret_cast<const uint32_t*>(N + base);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) rm[k] = gload_nt(at_byte(sbase(mrow + k * hp), o8));
+    for (int k = 0; k < 3; ++k) m[k] = gload_nt(at_byte(sbase(mrow + k * hp), o8));
 #pragma unroll
-    for (int k = 0; k < kRedF; ++k) rn[k] = gload_nt(at_byte(sbase(nrow + k * hp), o4));
+    for (int k = 0; k < kRedF; ++k) n[k] = gload_nt(at_byte(sbase(nrow + k * hp), o4));
   };
-  auto put = [&](float (&d0)[9], float (&d1)[9]) {
+  auto put = [&](const f2v (&m)[3], const uint32_t (&n)[kRedF], float (&d0)[9], float (&d1)[9]) {
     float n0[kRedF], n1[kRedF];
 #pragma unroll
     for (int k = 0; k < kRedF; ++k) {
-      n0[k] = Codec::dec_lo(rn[k], s_dec);
-      n1[k] = Codec::dec_hi(rn[k], s_dec);
+      n0[k] = Codec::dec_lo(n[k], s_dec);
+      n1[k] = Codec::dec_hi(n[k], s_dec);
     }
-    rebuild(rm[0].x, rm[1].x, rm[2].x, n0, d0);
-    rebuild(rm[0].y, rm[1].y, rm[2].y, n1, d1);
+    rebuild(m[0].x, m[1].x, m[2].x, n0, d0);
+    rebuild(m[0].y, m[1].y, m[2].y, n1, d1);
   };
-  fetch(y0 - 1);
-  put(R0[0], R1[0]);
-  fetch(y0);
-  put(R0[1], R1[1]);
-  fetch(y0 + 1);
+  fetch(y0 - 1, rm[0], rn[0]);
+  put(rm[0], rn[0], R0[0], R1[0]);
+  fetch(y0, rm[1], rn[1]);
+  put(rm[1], rn[1], R0[1], R1[1]);
+  fetch(y0 + 1, rm[2], rn[2]);
+  fetch(min(y0 + 2, yend), rm[0], rn[0]);
   // a per-lane copy of yend: the store conditions below are then lane masks, whose skip paths
   // the compiler's wait counting handles without draining every outstanding load and store at
   // the top of the loop (a uniform branch around the stores made it wait for everything)
   int yend_v = yend;
   asm volatile("" : "+v"(yend_v));
 
-  // ring slot of row r: (r - y0 + 1) mod 3, a compile-time constant in the unrolled body; the
-  // body always runs all three rows (rows past yend compute on re-read data and store
+  // the body always runs all three rows (rows past yend compute on re-read data and store
   // nothing), so the loop has no early exit and no loop-carried register copies, which would
   // make the compiler wait for every outstanding store at the back edge
   for (int yb = y0; yb < yend; yb += 3) {
@@ -288,9 +283,9 @@ k_bgk_d2q9_red(const float* __restrict__ M, const uint16_t* __restrict__ N, floa
   for (int j = 0; j < 3; ++j) {
     const int y = yb + j;
     const bool live = y < yend_v;
-    // rebuild row y + 1 (loaded one row ago), load row y + 2
-    put(R0[(j + 2) % 3], R1[(j + 2) % 3]);
-    fetch(min(y + 2, yend));  // past the last needed row: a harmless re-read
+    // rebuild row y + 1, load row y + 3 (into the slot row y held)
+    put(rm[(j + 2) % 3], rn[(j + 2) % 3], R0[(j + 2) % 3], R1[(j + 2) % 3]);
+    fetch(min(y + 3, yend), rm[(j + 1) % 3], rn[(j + 1) % 3]);  // past yend: a harmless re-read
     const int hr = min(y, yend - 1) - y0 + 1;  // halo row of y (rows past yend: the last)
     // pull: f_i(x) = f~_i(x - c_i); i = (c_x + 1) + 3 (c_y + 1); rows beyond a wall bounce back
     float a[9], b[9];
@@ -335,9 +330,36 @@ k_bgk_d2q9_red(const float* __restrict__ M, const uint16_t* __restrict__ N, floa
         gstore_nt(at_byte(sbase(mrow), o8), f2v{c0.drho, c1.drho});
         gstore_nt(at_byte(sbase(mrow + hp), o8), f2v{c0.ux, c1.ux});
         gstore_nt(at_byte(sbase(mrow + 2 * hp), o8), f2v{c0.uy, c1.uy});
+        uint32_t w[kRedF];
 #pragma unroll
-        for (int k = 0; k < kRedF; ++k)
-          gstore_nt(at_byte(sbase(nrow + k * hp), o4), Codec::enc2(c0.q[k], c1.q[k], s_enc));
+        for (int k = 0; k < kRedF; ++k) w[k] = Codec::enc2(c0.q[k], c1.q[k], s_enc);
+#pragma unroll
+        for (int k = 0; k < kRedF; ++k) gstore_nt(at_byte(sbase(nrow + k * hp), o4), w[k]);
+        // edge records of the strip's first column (lane 0, even slot) and last column
+        typedef float f4v __attribute__((ext_vector_type(4)));
+        typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+        const int s = x0 / kRedStrip;
+        if (lane == 0) {
+          EdgeRec* r = Eo + edge_index(s, 0, y, ny);
+          *reinterpret_cast<f4v*>(&r->m[0]) = f4v{c0.drho, c0.ux, c0.uy, 0.0f};
+          *reinterpret_cast<u4v*>(&r->n[0]) = u4v{(w[0] & 0xFFFFu) | (w[1] << 16),
+                                                  (w[2] & 0xFFFFu) | (w[3] << 16),
+                                                  (w[4] & 0xFFFFu) | (w[5] << 16), 0u};
+        }
+        if (lane == ll) {
+          EdgeRec* r = Eo + edge_index(s, 1, y, ny);
+          if (last_even) {
+            *reinterpret_cast<f4v*>(&r->m[0]) = f4v{c0.drho, c0.ux, c0.uy, 0.0f};
+            *reinterpret_cast<u4v*>(&r->n[0]) = u4v{(w[0] & 0xFFFFu) | (w[1] << 16),
+                                                    (w[2] & 0xFFFFu) | (w[3] << 16),
+                                                    (w[4] & 0xFFFFu) | (w[5] << 16), 0u};
+          } else {
+            *reinterpret_cast<f4v*>(&r->m[0]) = f4v{c1.drho, c1.ux, c1.uy, 0.0f};
+            *reinterpret_cast<u4v*>(&r->n[0]) = u4v{(w[0] >> 16) | (w[1] & 0xFFFF0000u),
+                                                    (w[2] >> 16) | (w[3] & 0xFFFF0000u),
+                                                    (w[4] >> 16) | (w[5] & 0xFFFF0000u), 0u};
+          }
+        }
       }
       if (DIAG) {
         if (own0 && live) {
@@ -364,15 +386,29 @@ k_bgk_d2q9_red(const float* __restrict__ M, const uint16_t* __restrict__ N, floa
 
 // Initial state f = f^eq(rho0, u0): moments stored, non-equilibrium part zero.
 __global__ void k_init_bgk_red(const double* __restrict__ rho, const double* __restrict__ u,
-                               float* __restrict__ M, uint16_t* __restrict__ N, int nx,
-                               int64_t nodes, int64_t pitch, int64_t plane) {
+                               float* __restrict__ M, uint16_t* __restrict__ N,
+                               EdgeRec* __restrict__ E, int nx, int ny, int64_t nodes,
+                               int64_t pitch, int64_t plane) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= nodes) return;
-  const int64_t off = (n / nx) * pitch + (n % nx);
-  M[off] = (float)(rho[n] - 1.0);
-  M[plane + off] = (float)u[n];
-  M[2 * plane + off] = (float)u[nodes + n];
+  const int x = (int)(n % nx), y = (int)(n / nx);
+  const int64_t off = (int64_t)y * pitch + x;
+  const float m[3] = {(float)(rho[n] - 1.0), (float)u[n], (float)u[nodes + n]};
+  M[off] = m[0];
+  M[plane + off] = m[1];
+  M[2 * plane + off] = m[2];
   for (int k = 0; k < kRedF; ++k) N[k * plane + off] = 0;  // +0 in both codecs
+  // the same values in the edge records of the strip's first and last column
+  const int s = x / kRedStrip;
+  for (int e = 0; e < 2; ++e) {
+    if (e == 0 ? x % kRedStrip != 0 : (x % kRedStrip != kRedStrip - 1 && x != nx - 1)) continue;
+    EdgeRec& r = E[edge_index(s, e, y, ny)];
+    r.m[0] = m[0];
+    r.m[1] = m[1];
+    r.m[2] = m[2];
+    r.m[3] = 0.0f;
+    for (int k = 0; k < 8; ++k) r.n[k] = 0;
+  }
 }
 
 __global__ void k_moments_bgk_red(const float* __restrict__ M, int nx, int64_t nodes,
@@ -407,12 +443,14 @@ __global__ void k_decode_bgk_red(int i, const float* __restrict__ M, const uint1
 // ---- launchers -----------------------------------------------------------------------------
 // Tiles of 512 columns (four 128-column wavefront strips) by `rows` rows, launched as a
 // one-dimensional grid (tile = bx + nbx by), so tall lattices need no more rows per tile; the
-// halo rows of a strip (rows + 2) fit one half wavefront.
+// halo rows of a strip (rows + 2) fit one half wavefront. 18 rows measured best on MI355X
+// (bf16, 2048^2 / 4096^2: 44.6 / 178 us at 18 rows; 45.4 / 185 at 12; 48.7 / 196 at 6;
+// 54.4 / 185 at 30).
 Grid make_grid_red(const Layout& L) {
   Grid G;
   G.bx = kBlock;
   G.nbx = (L.nx + kRedBlockCols - 1) / kRedBlockCols;
-  G.rows = 12;
+  G.rows = 18;
 #ifdef LBM_TUNING_ENV
   if (const char* v = getenv("LBM_RED_ROWS")) G.rows = atoi(v);
 #endif
@@ -423,20 +461,32 @@ Grid make_grid_red(const Layout& L) {
 }
 
 template <typename Codec, bool WALLS>
-static void red_launch(const float* M, const uint16_t* N, float* Mo, uint16_t* No, const Layout& L,
-                       const Grid& G, double omega, float se, float sd, double* partials,
-                       hipStream_t s) {
+static void red_launch(const float* M, const uint16_t* N, const EdgeRec* E, float* Mo,
+                       uint16_t* No, EdgeRec* Eo, const Layout& L, const Grid& G, double omega,
+                       float se, float sd, double* partials, hipStream_t s) {
   dim3 grid((unsigned)G.blocks()), block(kBlock);
   const float om = (float)omega;
   if (partials)
-    k_bgk_d2q9_red<Codec, WALLS, true><<<grid, block, 0, s>>>(M, N, Mo, No, L.nx, L.ny, L.pitch, L.plane, om, se, sd, G.rows, partials);
+    k_bgk_d2q9_red<Codec, WALLS, true><<<grid, block, 0, s>>>(M, N, E, Mo, No, Eo, L.nx, L.ny, L.pitch, L.plane, om, se, sd, G.rows, partials);
   else
-    k_bgk_d2q9_red<Codec, WALLS, false><<<grid, block, 0, s>>>(M, N, Mo, No, L.nx, L.ny, L.pitch, L.plane, om, se, sd, G.rows, nullptr);
+    k_bgk_d2q9_red<Codec, WALLS, false><<<grid, block, 0, s>>>(M, N, E, Mo, No, Eo, L.nx, L.ny, L.pitch, L.plane, om, se, sd, G.rows, nullptr);
 }
 
-// Buffer layout: 3 float moment planes, then kRedF uint16 planes (plane elements each).
+// Buffer layout: 3 float moment planes, then kRedF uint16 planes (plane elements each), then
+// (256-byte aligned) the edge records of every strip, side and row.
 static inline const uint16_t* neq_of(const void* buf, const Layout& L, int nm) {
   return reinterpret_cast<const uint16_t*>(static_cast<const float*>(buf) + nm * L.plane);
+}
+static inline size_t red_edge_offset(const Layout& L) {
+  return ((size_t)L.plane * (3 * 4 + kRedF * 2) + 255) / 256 * 256;
+}
+static inline EdgeRec* edges_of(const void* buf, const Layout& L) {
+  return reinterpret_cast<EdgeRec*>(const_cast<char*>(static_cast<const char*>(buf)) +
+                                    red_edge_offset(L));
+}
+size_t red_state_bytes(const Layout& L) {
+  const size_t strips = ((size_t)L.nx + kRedStrip - 1) / kRedStrip;
+  return red_edge_offset(L) + strips * 2 * (size_t)L.ny * sizeof(EdgeRec);
 }
 
 hipError_t launch_bgk_d2q9_red(int codec, const void* A, void* B, const Layout& L, const Grid& G,
@@ -449,12 +499,14 @@ hipError_t launch_bgk_d2q9_red(int codec, const void* A, void* B, const Layout& 
   const uint16_t* N = neq_of(A, L, 3);
   float* Mo = static_cast<float*>(B);
   uint16_t* No = const_cast<uint16_t*>(neq_of(B, L, 3));
+  const EdgeRec* E = edges_of(A, L);
+  EdgeRec* Eo = edges_of(B, L);
   if (codec == 0) {
-    if (walls) red_launch<CodecBF16, true>(M, N, Mo, No, L, G, omega, s_enc, s_dec, partials, s);
-    else red_launch<CodecBF16, false>(M, N, Mo, No, L, G, omega, s_enc, s_dec, partials, s);
+    if (walls) red_launch<CodecBF16, true>(M, N, E, Mo, No, Eo, L, G, omega, s_enc, s_dec, partials, s);
+    else red_launch<CodecBF16, false>(M, N, E, Mo, No, Eo, L, G, omega, s_enc, s_dec, partials, s);
   } else {
-    if (walls) red_launch<CodecFP16, true>(M, N, Mo, No, L, G, omega, s_enc, s_dec, partials, s);
-    else red_launch<CodecFP16, false>(M, N, Mo, No, L, G, omega, s_enc, s_dec, partials, s);
+    if (walls) red_launch<CodecFP16, true>(M, N, E, Mo, No, Eo, L, G, omega, s_enc, s_dec, partials, s);
+    else red_launch<CodecFP16, false>(M, N, E, Mo, No, Eo, L, G, omega, s_enc, s_dec, partials, s);
   }
   return hipGetLastError();
 }
@@ -464,8 +516,9 @@ static inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kB
 hipError_t launch_init_bgk_red(const double* rho, const double* u, void* A, const Layout& L,
                                hipStream_t s) {
   k_init_bgk_red<<<nblk(L.nodes()), kBlock, 0, s>>>(rho, u, static_cast<float*>(A),
-                                                    const_cast<uint16_t*>(neq_of(A, L, 3)), L.nx,
-                                                    L.nodes(), L.pitch, L.plane);
+                                                    const_cast<uint16_t*>(neq_of(A, L, 3)),
+                                                    edges_of(A, L), L.nx, L.ny, L.nodes(),
+                                                    L.pitch, L.plane);
   return hipGetLastError();
 }
 
