@@ -271,12 +271,14 @@ __device__ __forceinline__ void mlp_wave_tiles(const MlpLdsP& s, float (*io)[kIo
 #pragma unroll 1
   for (int nt = 0; nt < 4; ++nt) {
     // The weights are re-read from LDS for every tile instead of being hoisted into registers
-    // across the tiles (fewer registers, more wavefronts in flight): z is 0, but the compiler
-    // cannot see it, so the reads stay in the loop; laundering an index rather than the
-    // pointer keeps them LDS reads.
+    // across the tiles (fewer registers, more wavefronts in flight): the byte offset z is 0,
+    // but the compiler cannot see it, so the reads stay in the loop. Offsetting the LDS object
+    // (rather than laundering the pointer itself) keeps them LDS reads, and every read is the
+    // offset base plus an immediate.
     int z = 0;
     asm volatile("" : "+v"(z));
-    const f32x4 yt = mlp_forward_tile32<2 * kIoS>(s, xs, nt, z);
+    const MlpLdsP& sz = *reinterpret_cast<const MlpLdsP*>(reinterpret_cast<const char*>(&s) + z);
+    const f32x4 yt = mlp_forward_tile32<2 * kIoS>(sz, xs, nt);
     if (q < 3) {  // output rows 0..11 (9 used)
 #pragma unroll
       for (int j = 0; j < 4; ++j) io[16 * nt + r][4 * q + j] = yt[j];
@@ -459,11 +461,17 @@ k_bgk_d2q9_mlp(const float* __restrict__ A, float* __restrict__ B, int nx, int n
       const float dy[3] = {0.5f * (u2y - uy), -u2y, 0.5f * (u2y + uy)};
       const float Wk[3] = {W1, W0, W1};
       const float sx = kSNeq * inv;
+      // the same sum regrouped: h^eq_i = psi_b (drho psi_a + d_a) + W_a d_b (psi = W + d)
+      float A[3], P[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        A[k] = __builtin_fmaf(drho, Wk[k] + dx[k], dx[k]);
+        P[k] = Wk[k] + dy[k];
+      }
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         const int ia = i % 3, ib = i / 3;
-        const float pa = Wk[ia] + dx[ia], pb = Wk[ib] + dy[ib];
-        heq[i] = drho * (pa * pb) + (Wk[ia] * dy[ib] + dx[ia] * Wk[ib] + dx[ia] * dy[ib]);
+        heq[i] = __builtin_fmaf(P[ib], A[ia], Wk[ia] * dy[ib]);
         xf[i] = (h[i] - heq[i]) * sx;
       }
       xf[9] = kSU * ux;

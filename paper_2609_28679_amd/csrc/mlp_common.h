@@ -157,14 +157,10 @@ __device__ __forceinline__ bf16x4 ld4(const short* p) {
   return *reinterpret_cast<const bf16x4*>(__builtin_assume_aligned(p, 8));
 }
 
+// b: 16-byte aligned; one 16-byte read (its 16-bit immediate offset reaches every bias array,
+// where two-word reads would need an address add each)
 __device__ __forceinline__ f32x4 bias4(const float* b, int lane) {
-  const int r = 4 * (lane >> 4);
-  f32x4 c;
-  c[0] = b[r];
-  c[1] = b[r + 1];
-  c[2] = b[r + 2];
-  c[3] = b[r + 3];
-  return c;
+  return *reinterpret_cast<const f32x4*>(b + 4 * (lane >> 4));
 }
 
 // Forward pass of one wavefront: 64 samples, sample s = 16 n + (l % 16) in tile column n.
@@ -259,26 +255,24 @@ __device__ __forceinline__ f32x4 mlp_forward_tile(const MlpLds& s, const short (
 // still go from one layer to the next in registers. 4 + 8 + 2 = 14 matrix instructions per 16
 // samples. xs: [64][xstride] bfloat16 inputs (row = sample). Returns the output tile (C
 // layout, rows 0..8 valid).
-// z: a row offset that is 0 at run time but opaque to the compiler (see mlp_wave_tiles); it
-// keeps the weight reads inside the tile loop without hiding that they are LDS reads.
 template <int XS>
 __device__ __forceinline__ f32x4 mlp_forward_tile32(const MlpLdsP& s, const short (*xs)[XS],
-                                                    int n, int z) {
+                                                    int n) {
   const int lane = threadIdx.x & 63;
   const int r = lane & 15, q = lane >> 4;
-  const int rz = r + z;
+  const int rz = r;
   const bf16x4 xb = ld4(&xs[16 * n + r][4 * q]);
   bf16x4 h1[4], h2[4];
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    f32x4 acc = bias4(s.b1 + 16 * m + z, lane);
+    f32x4 acc = bias4(s.b1 + 16 * m, lane);
     acc = mfma16(ld4(&s.w1[16 * m + rz][4 * q]), xb, acc);
 #pragma unroll
     for (int j = 0; j < 4; ++j) h1[m][j] = f2bf(gelu(acc[j]));
   }
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    f32x4 acc = bias4(s.b2 + 16 * m + z, lane);
+    f32x4 acc = bias4(s.b2 + 16 * m, lane);
 #pragma unroll
     for (int p = 0; p < 2; ++p)
       acc = mfma32(cat8(ld4(&s.w2[16 * m + rz][32 * p + 4 * q]),
@@ -287,7 +281,7 @@ __device__ __forceinline__ f32x4 mlp_forward_tile32(const MlpLdsP& s, const shor
 #pragma unroll
     for (int j = 0; j < 4; ++j) h2[m][j] = f2bf(gelu(acc[j]));
   }
-  f32x4 acc = bias4(s.b3 + z, lane);
+  f32x4 acc = bias4(s.b3, lane);
 #pragma unroll
   for (int p = 0; p < 2; ++p)
     acc = mfma32(cat8(ld4(&s.w3[rz][32 * p + 4 * q]), ld4(&s.w3[rz][32 * p + 16 + 4 * q])),
