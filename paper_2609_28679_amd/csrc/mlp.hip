@@ -442,10 +442,12 @@ k_bgk_d2q9_mlp(const float* __restrict__ A, float* __restrict__ B, int nx, int n
   unsigned fallbacks = 0;
   mlp_load_lds_vec(wblob, s);
   // One row: features, network, judge and store from the pulled populations h of row y.
+  // Lanes past the right edge work on the last column's values (pulled from a valid column,
+  // so finite) and store nothing: no separate zero-filled path.
   auto row = [&](const float (&h)[9], int y) {
     float heq[9], xf[kIn];
-    float drho = 0.0f, ux = 0.0f, uy = 0.0f;
-    if (valid) {
+    float drho, ux, uy;
+    {
       drho = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
       const float jx = (h[2] + h[5] + h[8]) - (h[0] + h[3] + h[6]);
       const float jy = (h[6] + h[7] + h[8]) - (h[0] + h[1] + h[2]);
@@ -477,14 +479,9 @@ k_bgk_d2q9_mlp(const float* __restrict__ A, float* __restrict__ B, int nx, int n
       xf[9] = kSU * ux;
       xf[10] = kSU * uy;
       xf[11] = omega;
-    } else {
-#pragma unroll
-      for (int i = 0; i < 9; ++i) heq[i] = 0.0f;
-#pragma unroll
-      for (int i = 0; i < kIn; ++i) xf[i] = 0.0f;
     }
     wave_lds_sync();  // the previous row's outputs have been read
-    put_inputs(io[wv][lane], xf, valid);
+    put_inputs(io[wv][lane], xf, true);
     wave_lds_sync();
     mlp_wave_tiles(s, io[wv]);
     wave_lds_sync();
