@@ -23,6 +23,12 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2609_28679_amd", "csrc", f)
                   for f in ("bgk.hip", "device_common.h")]
 
 
+# The density reading of the non-equilibrium extrapolation walls that the bench runs (the
+# library's default): the wall node continues the neighbour's pressure.
+NEQ_DENSITY = "pressure-continued rho_B = rho_N T_N / T_W (default; wall_density 1 selects " \
+              "the literal rho_B = rho_N)"
+
+
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
@@ -344,7 +350,15 @@ def main():
                                                               T=(0.8, 1.0))),
                 max(100, vs // 4), 10, 144,
                 {"walls": "y, non-equilibrium extrapolation (u_W = -+0.05, T_W = 0.8 / 1.0)",
-                 "phi": "central"})),
+                 "wall_density": NEQ_DENSITY, "phi": "central"})),
+            ("d2q9_ddf_fp32_4096_neq_walls_upwind", lambda n: variant(
+                n, lambda: ddf_lattice("fp32", phi=2,
+                                       neq_walls=dict(u=((-0.05, 0.0), (0.05, 0.0)),
+                                                      T=(0.8, 1.0))),
+                max(100, vs // 4), 10, 144,
+                {"walls": "y, non-equilibrium extrapolation (u_W = -+0.05, T_W = 0.8 / 1.0)",
+                 "wall_density": NEQ_DENSITY,
+                 "phi": "upwind (sides keyed on the wall velocity on the boundary rows)"})),
             ("d2q9_ddf_fp32_4096_vdw", lambda n: variant(
                 n, lambda: vdw_lattice(), max(100, vs // 4), 10, 144,
                 {"walls": "y", "phi": "central",
@@ -382,7 +396,13 @@ def main():
                                                           T=(0.8, 1.0))),
                 max(50, vs // 20), 5, 432,
                 {"phi": "central", "launches": "3 per step (boundary planes, fluxes, collision)",
-                 "walls": "y, non-equilibrium extrapolation (u_W = -+0.05, T_W = 0.8 / 1.0)"})),
+                 "walls": "y, non-equilibrium extrapolation (u_W = -+0.05, T_W = 0.8 / 1.0)",
+                 "wall_density": NEQ_DENSITY})),
+            ("d3q27_ddf_fp32_256_upwind", lambda n: variant(
+                n, lambda: binding.Lattice(*inputs.thermal_taylor_green_3d(256, 0.05),
+                                           lattice="D3Q27", model="ddf", tau=0.6, phi=2),
+                max(50, vs // 20), 5, 432,
+                {"phi": "upwind", "launches": "2 per step (fluxes, collision)"})),
             ("d2q9_ddf_fp32_4096_upwind", lambda n: variant(
                 n, lambda: ddf_lattice("fp32", phi=2), max(100, vs // 4), 10, 144,
                 {"walls": "y", "phi": "upwind"})),
