@@ -331,20 +331,33 @@ __device__ __forceinline__ double wrest(int i) {
 }
 
 // Pre-collision shifted values h_i = f_i - w_i at node (x, y) pulled from the state A.
-template <bool WALLS>
+// ROW_UNIFORM: every lane of the wavefront pulls for the same row y (the surrogate step), so
+// the source rows are addressed from scalar bases with 32-bit lane offsets; otherwise (the
+// harvest, one sampled node per lane) each lane forms its own addresses.
+template <bool WALLS, bool ROW_UNIFORM>
 __device__ __forceinline__ void pull9h(const float* __restrict__ A, int nx, int ny, int64_t pitch,
                                        int64_t plane, int x, int y, float (&h)[9]) {
-  // byte offsets of the source columns (the rows are wave-uniform: scalar bases)
-  const uint32_t xs[3] = {fresh(4u * (x == nx - 1 ? 0 : x + 1)), fresh(4u * x),
-                          fresh(4u * (x == 0 ? nx - 1 : x - 1))};
+  const int xc[3] = {x == nx - 1 ? 0 : x + 1, x, x == 0 ? nx - 1 : x - 1};
   const int ys[3] = {y == ny - 1 ? 0 : y + 1, y, y == 0 ? ny - 1 : y - 1};
+  if constexpr (ROW_UNIFORM) {
+    // byte offsets of the source columns
+    const uint32_t xs[3] = {fresh(4u * xc[0]), fresh(4u * xc[1]), fresh(4u * xc[2])};
 #pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    const int ka = i % 3, kb = i / 3;
-    const bool bounce = WALLS && ((kb == 2 && y == 0) || (kb == 0 && y == ny - 1));
-    const float* row = bounce ? A + (8 - i) * plane + (int64_t)y * pitch
-                              : A + i * plane + (int64_t)ys[kb] * pitch;
-    h[i] = gload_nt(at_byte(sbase(row), bounce ? xs[1] : xs[ka]));
+    for (int i = 0; i < 9; ++i) {
+      const int ka = i % 3, kb = i / 3;
+      const bool bounce = WALLS && ((kb == 2 && y == 0) || (kb == 0 && y == ny - 1));
+      const float* row = bounce ? A + (8 - i) * plane + (int64_t)y * pitch
+                                : A + i * plane + (int64_t)ys[kb] * pitch;
+      h[i] = gload_nt(at_byte(sbase(row), bounce ? xs[1] : xs[ka]));
+    }
+  } else {
+    const int64_t self = (int64_t)y * pitch + x;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const int ka = i % 3, kb = i / 3;
+      const bool bounce = WALLS && ((kb == 2 && y == 0) || (kb == 0 && y == ny - 1));
+      h[i] = bounce ? A[(8 - i) * plane + self] : A[i * plane + (int64_t)ys[kb] * pitch + xc[ka]];
+    }
   }
 }
 
@@ -353,7 +366,7 @@ template <bool WALLS>
 __device__ __forceinline__ void pull9(const float* __restrict__ A, int nx, int ny, int64_t pitch,
                                       int64_t plane, int x, int y, double (&f)[9]) {
   float h[9];
-  pull9h<WALLS>(A, nx, ny, pitch, plane, x, y, h);
+  pull9h<WALLS, false>(A, nx, ny, pitch, plane, x, y, h);
 #pragma unroll
   for (int i = 0; i < 9; ++i) f[i] = (double)h[i] + wrest(i);
 }
@@ -521,13 +534,13 @@ k_bgk_d2q9_mlp(const float* __restrict__ A, float* __restrict__ B, int nx, int n
   float ha[9], hb[9];
   const int xl = valid ? x : nx - 1;
   const int ylast = yend - 1;
-  if (y0 < yend) pull9h<WALLS>(A, nx, ny, pitch, plane, xl, y0, ha);
+  if (y0 < yend) pull9h<WALLS, true>(A, nx, ny, pitch, plane, xl, y0, ha);
   __syncthreads();
   for (int y = y0; y < yend; y += 2) {
-    pull9h<WALLS>(A, nx, ny, pitch, plane, xl, min(y + 1, ylast), hb);
+    pull9h<WALLS, true>(A, nx, ny, pitch, plane, xl, min(y + 1, ylast), hb);
     row(ha, y);
     if (y + 1 >= yend) break;
-    pull9h<WALLS>(A, nx, ny, pitch, plane, xl, min(y + 2, ylast), ha);
+    pull9h<WALLS, true>(A, nx, ny, pitch, plane, xl, min(y + 2, ylast), ha);
     row(hb, y + 1);
   }
   // integer fallback counts: order-independent, so atomics stay deterministic

@@ -86,13 +86,16 @@ def test_gradients_match_oracle_with_bf16_roundings():
         assert e <= 1e-4, name
 
 
+@pytest.mark.parametrize("streaming", ["auto", "two"])
 @pytest.mark.parametrize("steps", [30, 31])
-def test_harvest_features_and_targets(steps):
-    announce("harvest 256^2 after %d steps vs oracle features" % steps)
+def test_harvest_features_and_targets(steps, streaming):
+    """Harvested features and targets against the oracle's, from the one-buffer layout (both
+    parities) and from the two-buffer layout, whose harvest pulls one sampled node per lane."""
+    announce("harvest 256^2 after %d steps (%s layout) vs oracle features" % (steps, streaming))
     import torch
     b = _binding()
     rho, u = inputs.random_phase_turbulence_2d(256, seed=2)
-    lat = b.Lattice(rho, u, tau=0.6)
+    lat = b.Lattice(rho, u, tau=0.6, streaming=streaming)
     lat.step(steps)
     idx = np.sort(np.random.default_rng(0).choice(256 * 256, 500, replace=False)).astype(np.int64)
     X = torch.empty((500, 12), dtype=torch.float32, device="cuda")
