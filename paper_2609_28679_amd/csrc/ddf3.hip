@@ -34,8 +34,11 @@ struct Moments3 {
 
 // Pull of the 27 + 27 populations of node (x, y, z): h_i = A_i(x - c_i), or the node's own
 // opposite population where x - c_i lies beyond a y wall; PULL = false reads the node's own
-// slots (the collide-only pass at creation).
-template <typename S, bool WALLS, bool PULL>
+// slots (the collide-only pass at creation). ROW_UNIFORM: (y, z) is the same for every lane of
+// the wavefront (the sweeps, one x row per workgroup row), so the source rows are addressed
+// from scalar bases with 32-bit column offsets; otherwise (the NEQ boundary rebuild, one (x, z)
+// node per lane) every lane forms its own addresses.
+template <typename S, bool WALLS, bool PULL, bool ROW_UNIFORM>
 __device__ __forceinline__ void gather27(const S* __restrict__ A, int64_t plane, int nx, int ny,
                                          int nz, int64_t pitch, int x, int y, int z,
                                          S (&hf)[27], S (&hg)[27]) {
@@ -48,20 +51,44 @@ __device__ __forceinline__ void gather27(const S* __restrict__ A, int64_t plane,
     }
     return;
   }
-  const int xs[3] = {x == nx - 1 ? 0 : x + 1, x, x == 0 ? nx - 1 : x - 1};  // x - c_x
+  const int xc[3] = {x == nx - 1 ? 0 : x + 1, x, x == 0 ? nx - 1 : x - 1};  // x - c_x
   const int ys[3] = {y == ny - 1 ? 0 : y + 1, y, y == 0 ? ny - 1 : y - 1};
   const int zs[3] = {z == nz - 1 ? 0 : z + 1, z, z == 0 ? nz - 1 : z - 1};
+  if constexpr (!ROW_UNIFORM) {
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+      const int a = i % 3, b = (i / 3) % 3, c = i / 9;
+      const bool bounce = WALLS && ((b == 2 && y == 0) || (b == 0 && y == ny - 1));
+      if (bounce) {
+        hf[i] = A[(26 - i) * plane + self];
+        hg[i] = A[(53 - i) * plane + self];
+      } else {
+        const int64_t src = ((int64_t)zs[c] * ny + ys[b]) * pitch + xc[a];
+        hf[i] = A[i * plane + src];
+        hg[i] = A[(27 + i) * plane + src];
+      }
+    }
+    return;
+  }
+  const uint32_t xs[3] = {fresh((uint32_t)sizeof(S) * xc[0]), fresh((uint32_t)sizeof(S) * xc[1]),
+                          fresh((uint32_t)sizeof(S) * xc[2])};
+  const int64_t row = ((int64_t)z * ny + y) * pitch;
+  // plane strides re-declared here (an empty asm): otherwise the compiler keeps the 54 plane
+  // offsets of the loop-invariant products in scalar registers across the row loop and spills
+  // them to vector lanes
+  int64_t pl = plane;
+  asm volatile("" : "+s"(pl));
 #pragma unroll
   for (int i = 0; i < 27; ++i) {
     const int a = i % 3, b = (i / 3) % 3, c = i / 9;
     const bool bounce = WALLS && ((b == 2 && y == 0) || (b == 0 && y == ny - 1));
     if (bounce) {
-      hf[i] = A[(26 - i) * plane + self];
-      hg[i] = A[(53 - i) * plane + self];
+      hf[i] = *at_byte(sbase(A + (26 - i) * pl + row), xs[1]);
+      hg[i] = *at_byte(sbase(A + (53 - i) * pl + row), xs[1]);
     } else {
-      const int64_t src = ((int64_t)zs[c] * ny + ys[b]) * pitch + xs[a];
-      hf[i] = A[i * plane + src];
-      hg[i] = A[(27 + i) * plane + src];
+      const int64_t src = ((int64_t)zs[c] * ny + ys[b]) * pitch;
+      hf[i] = *at_byte(sbase(A + i * pl + src), xs[a]);
+      hg[i] = *at_byte(sbase(A + (27 + i) * pl + src), xs[a]);
     }
   }
 }
@@ -69,7 +96,7 @@ __device__ __forceinline__ void gather27(const S* __restrict__ A, int64_t plane,
 // Pre-collision populations of node (x, y, z). WALLS: 0 periodic in y, 1 bounce-back walls,
 // 2 non-equilibrium extrapolation walls, whose boundary planes y = 0 and y = ny - 1 come
 // rebuilt from nb (k_ddf3_neq_rows: 2 sides x 54 populations, each nz x pitch elements).
-template <typename S, int WALLS, bool PULL>
+template <typename S, int WALLS, bool PULL, bool ROW_UNIFORM>
 __device__ __forceinline__ void node_pops(const S* __restrict__ A, const S* __restrict__ nb,
                                           int64_t plane, int nx, int ny, int nz, int64_t pitch,
                                           int x, int y, int z, S (&hf)[27], S (&hg)[27]) {
@@ -85,27 +112,29 @@ __device__ __forceinline__ void node_pops(const S* __restrict__ A, const S* __re
       return;
     }
   }
-  gather27<S, (WALLS != 0), PULL>(A, plane, nx, ny, nz, pitch, x, y, z, hf, hg);
+  gather27<S, (WALLS != 0), PULL, ROW_UNIFORM>(A, plane, nx, ny, nz, pitch, x, y, z, hf, hg);
 }
 
 // rho = sum f, rho u = sum c f + sF/2, rho E = sum g + (u.sF + sQ)/2 (Sec. II C), then
 // T = (E - u^2/2)/c_v and theta = R T; for the van der Waals fluid (EXT = 2)
 // T = (E - u^2/2 + a rho)/c_v (Eq. lbm_temp) and theta = P/rho. (sF, sQ) as in moments_closure
 // (ddf_common.h); EXT = 0 takes no sources.
+// wf, wg: the rest-state shift (p.wf, p.wg; the sweep kernels pass a copy in LDS, see
+// RestShift below)
 template <int EXT, typename S>
 __device__ __forceinline__ void moments3(const S (&hf)[27], const S (&hg)[27], const DdfParams& p,
                                          Moments3& m, double sFx, double sFy, double sFz,
-                                         double sQ) {
+                                         double sQ, const double* wf, const double* wg) {
   double rho = 0.0, j[3] = {0.0, 0.0, 0.0}, rE = 0.0;
 #pragma unroll
   for (int i = 0; i < 27; ++i) {
-    const double f = (double)hf[i] + p.wf[i];
+    const double f = (double)hf[i] + wf[i];
     rho += f;
     const int c[3] = {i % 3 - 1, (i / 3) % 3 - 1, i / 9 - 1};
 #pragma unroll
     for (int a = 0; a < 3; ++a)
       if (c[a]) j[a] += c[a] > 0 ? f : -f;
-    rE += (double)hg[i] + p.wg[i];
+    rE += (double)hg[i] + wg[i];
   }
   if (EXT) {
     j[0] += 0.5 * sFx;
@@ -146,7 +175,7 @@ template <int EXT, typename S, typename Sink>
 __device__ __forceinline__ void collide3(const S (&hf)[27], const S (&hg)[27], const Moments3& m,
                                          const double (&ph)[3], const double (&gT)[3],
                                          const double (&gh)[3], double divu, const DdfParams& p,
-                                         Sink&& sink) {
+                                         const double* wf, const double* wg, Sink&& sink) {
   const double rho = m.rho, theta = m.theta, e = m.e;
   const double P = rho * theta;
   Axis X[3];
@@ -194,7 +223,7 @@ __device__ __forceinline__ void collide3(const S (&hf)[27], const S (&hg)[27], c
     const int a = i % 3, b = (i / 3) % 3, c = i / 9;
     double fe, ge;
     equilibria3(rho, e, i, X, fe, ge);
-    const double hfe = fe - p.wf[i], hge = ge - p.wg[i];
+    const double hfe = fe - wf[i], hge = ge - wg[i];
     const double f = (double)hf[i], g = (double)hg[i];
     const double fs = rho * (s[0][a] * s[1][b] * s[2][c]);
     double gstar_minus_ge = 0.0;
@@ -211,6 +240,33 @@ __device__ __forceinline__ void collide3(const S (&hf)[27], const S (&hg)[27], c
 }
 
 // ---- kernels --------------------------------------------------------------------------------
+// The rest-state shift of the 54 populations in LDS, read per use: as kernel parameters the 54
+// doubles took 108 scalar registers for the whole kernel and spilled some 330 of them to vector
+// lanes (about 700 extra vector instructions per node in the collision sweep). The offset z is
+// 0 but re-declared per row, so the reads stay at their uses instead of being hoisted into
+// registers. Taken, with scalar-base row addressing, by the sweeps without sources, transport
+// terms or NEQ walls (kLean below): 256^3 central 2226 -> 2152 us, upwind 2678 -> 2466 us; the
+// extended sweeps (one wave per SIMD, ~310 registers) measured 2-3% slower with it and the NEQ
+// sweeps 1.5% slower, so they keep the parameter arrays and per-lane addresses.
+struct RestShift {
+  double w[54];
+  __device__ __forceinline__ void fill(const DdfParams& p) {
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int i = 0; i < 27; ++i) {
+        w[i] = p.wf[i];
+        w[27 + i] = p.wg[i];
+      }
+    }
+    __syncthreads();
+  }
+  __device__ __forceinline__ const double* at_row() const {
+    int z = 0;
+    asm volatile("" : "+v"(z));
+    return w + z;
+  }
+};
+
 // Fields written by k_ddf3_flux (in the storage type S, each `plane` elements at the population
 // offsets): 0..2 phi_x, phi_y, phi_z;  with transport control 3: T, 4..6: u_x, u_y, u_z; for the
 // van der Waals fluid 7: h = e + P/rho.
@@ -220,6 +276,9 @@ template <typename S, int WALLS, bool PULL, int EXT>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
 k_ddf3_flux(const S* __restrict__ A, const S* __restrict__ nb, int nx, int ny, int nz,
             int64_t pitch, int64_t plane, DdfParams prm, int rows, S* __restrict__ fld) {
+  constexpr bool kLean = EXT == 0 && WALLS != 2;
+  __shared__ RestShift rs;
+  if (kLean) rs.fill(prm);
   const int nbx = gridDim.x;
   const int tile = blockIdx.x + nbx * blockIdx.y;
   const int bx = tile % nbx, by = tile / nbx;
@@ -229,9 +288,10 @@ k_ddf3_flux(const S* __restrict__ A, const S* __restrict__ nb, int nx, int ny, i
   for (int r = by * rows; r < r_end; ++r) {
     const int y = r % ny, z = r / ny;
     S hf[27], hg[27];
-    node_pops<S, WALLS, PULL>(A, nb, plane, nx, ny, nz, pitch, x, y, z, hf, hg);
+    node_pops<S, WALLS, PULL, kLean>(A, nb, plane, nx, ny, nz, pitch, x, y, z, hf, hg);
     Moments3 m;
-    moments3<EXT>(hf, hg, prm, m, prm.Fx, prm.Fy, prm.Fz, prm.Q);
+    const double* w = kLean ? rs.at_row() : prm.wf;
+    moments3<EXT>(hf, hg, prm, m, prm.Fx, prm.Fy, prm.Fz, prm.Q, w, kLean ? w + 27 : prm.wg);
     const int64_t off = ((int64_t)z * ny + y) * pitch + x;
 #pragma unroll
     for (int a = 0; a < 3; ++a)
@@ -255,6 +315,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(EXT
 k_ddf3_collide(const S* __restrict__ A, const S* __restrict__ nb, S* __restrict__ B, int nx,
                int ny, int nz, int64_t pitch, int64_t plane, DdfParams prm,
                const S* __restrict__ fld, int rows, double* __restrict__ partials) {
+  constexpr bool kLean = EXT == 0 && WALLS != 2;  // see RestShift
+  __shared__ RestShift rs;
+  if (kLean) rs.fill(prm);
   const int nbx = gridDim.x;
   const int tile = blockIdx.x + nbx * blockIdx.y;
   const int bx = tile % nbx, by = tile / nbx;
@@ -265,9 +328,10 @@ k_ddf3_collide(const S* __restrict__ A, const S* __restrict__ nb, S* __restrict_
     for (int r = by * rows; r < r_end; ++r) {
       const int y = r % ny, z = r / ny;
       S hf[27], hg[27];
-      node_pops<S, WALLS, PULL>(A, nb, plane, nx, ny, nz, pitch, x, y, z, hf, hg);
+      node_pops<S, WALLS, PULL, kLean>(A, nb, plane, nx, ny, nz, pitch, x, y, z, hf, hg);
       Moments3 m;
-      moments3<EXT>(hf, hg, prm, m, prm.Fx, prm.Fy, prm.Fz, prm.Q);
+      const double* w = kLean ? rs.at_row() : prm.wf;
+      moments3<EXT>(hf, hg, prm, m, prm.Fx, prm.Fy, prm.Fz, prm.Q, w, kLean ? w + 27 : prm.wg);
       const int64_t off = ((int64_t)z * ny + y) * pitch + x;
       // offset of the node k steps along axis a: periodic in x and z; in y periodic, or the
       // nearest fluid row beyond a wall (zero-order ghosts, Sec. III A)
@@ -323,11 +387,25 @@ k_ddf3_collide(const S* __restrict__ A, const S* __restrict__ nb, S* __restrict_
             gh[a] = 0.5 * ((double)fld[7 * plane + at(a, 1)] - (double)fld[7 * plane + at(a, -1)]);
         }
       }
-      S* out = B + off;
-      collide3<EXT>(hf, hg, m, ph, gT, gh, divu, prm, [&](int i, double tf, double tg) {
-        store_nt(out + i * plane, (S)tf);
-        store_nt(out + (27 + i) * plane, (S)tg);
-      });
+      const double* w2 = kLean ? rs.at_row() : prm.wf;
+      if constexpr (kLean) {
+        S* out = B + ((int64_t)z * ny + y) * pitch;  // row base (wave-uniform)
+        const uint32_t xo = fresh((uint32_t)sizeof(S) * x);
+        int64_t pl = plane;
+        asm volatile("" : "+s"(pl));
+        collide3<EXT>(hf, hg, m, ph, gT, gh, divu, prm, w2, w2 + 27,
+                      [&](int i, double tf, double tg) {
+          gstore_nt(at_byte(sbase(out + i * pl), xo), (S)tf);
+          gstore_nt(at_byte(sbase(out + (27 + i) * pl), xo), (S)tg);
+        });
+      } else {
+        S* out = B + off;
+        collide3<EXT>(hf, hg, m, ph, gT, gh, divu, prm, w2, prm.wg,
+                      [&](int i, double tf, double tg) {
+          store_nt(out + i * plane, (S)tf);
+          store_nt(out + (27 + i) * plane, (S)tg);
+        });
+      }
       if (DIAG) {
         acc[0] += m.rho;
 #pragma unroll
@@ -380,8 +458,8 @@ __global__ void k_moments_ddf3(const S* __restrict__ A, int nx, int64_t nodes, i
     hg[i] = A[(27 + i) * plane + off];
   }
   Moments3 m;
-  if (prm.eos) moments3<2>(hf, hg, prm, m, -prm.Fx, -prm.Fy, -prm.Fz, -prm.Q);
-  else moments3<1>(hf, hg, prm, m, -prm.Fx, -prm.Fy, -prm.Fz, -prm.Q);
+  if (prm.eos) moments3<2>(hf, hg, prm, m, -prm.Fx, -prm.Fy, -prm.Fz, -prm.Q, prm.wf, prm.wg);
+  else moments3<1>(hf, hg, prm, m, -prm.Fx, -prm.Fy, -prm.Fz, -prm.Q, prm.wf, prm.wg);
   rho[n] = m.rho;
   for (int a = 0; a < 3; ++a) u[a * nodes + n] = m.u[a];
   T[n] = prm.eos ? (m.e + prm.va * m.rho) / prm.cv : m.theta / prm.R;
@@ -467,9 +545,9 @@ k_ddf3_neq_rows(const S* __restrict__ A, int nx, int ny, int nz, int64_t pitch, 
   const int z = (int)(t % nz), side = (int)(t / nz);
   const int N = side ? ny - 2 : 1;
   S hf[27], hg[27];
-  gather27<S, true, PULL>(A, plane, nx, ny, nz, pitch, x, N, z, hf, hg);
+  gather27<S, true, PULL, false>(A, plane, nx, ny, nz, pitch, x, N, z, hf, hg);
   Moments3 m;
-  moments3<EXT == 2 ? 2 : 0>(hf, hg, prm, m, 0.0, 0.0, 0.0, 0.0);
+  moments3<EXT == 2 ? 2 : 0>(hf, hg, prm, m, 0.0, 0.0, 0.0, 0.0, prm.wf, prm.wg);
   constexpr bool VDW = EXT == 2;
   const double TN = node_temperature<VDW>(prm, m.rho, m.e, m.theta);
   double rhoB, thetaW, eW;
