@@ -55,17 +55,19 @@ __device__ __forceinline__ void gather27(const S* __restrict__ A, int64_t plane,
   const int ys[3] = {y == ny - 1 ? 0 : y + 1, y, y == 0 ? ny - 1 : y - 1};
   const int zs[3] = {z == nz - 1 ? 0 : z + 1, z, z == 0 ? nz - 1 : z - 1};
   if constexpr (!ROW_UNIFORM) {
+    int64_t pl = plane;  // re-declared: see the row-uniform path below
+    asm volatile("" : "+s"(pl));
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
       const int a = i % 3, b = (i / 3) % 3, c = i / 9;
       const bool bounce = WALLS && ((b == 2 && y == 0) || (b == 0 && y == ny - 1));
       if (bounce) {
-        hf[i] = A[(26 - i) * plane + self];
-        hg[i] = A[(53 - i) * plane + self];
+        hf[i] = A[(26 - i) * pl + self];
+        hg[i] = A[(53 - i) * pl + self];
       } else {
         const int64_t src = ((int64_t)zs[c] * ny + ys[b]) * pitch + xc[a];
-        hf[i] = A[i * plane + src];
-        hg[i] = A[(27 + i) * plane + src];
+        hf[i] = A[i * pl + src];
+        hg[i] = A[(27 + i) * pl + src];
       }
     }
     return;
@@ -418,6 +420,186 @@ k_ddf3_collide(const S* __restrict__ A, const S* __restrict__ nb, S* __restrict_
   if (DIAG) block_sum_store<kDiagValues>(acc, partials + (int64_t)tile * kDiagValues);
 }
 
+// ---- one-launch step --------------------------------------------------------------------------
+// For the collision without sources, transport terms or NEQ walls and with the central
+// derivative of Phi, the flux and collision sweeps are fused into one launch that marches along
+// z. A workgroup owns a tile of kF3Cols columns by kF3Rows rows (one row per wavefront) and a
+// range of planes. Per plane z every wavefront
+//   1. computes the fluxes of one halo piece of plane z + 1: the rows below and above the tile
+//      (wavefronts 1 and 2) or phi_x of the columns left and right of two of its rows
+//      (wavefronts 0 and 3, one node per lane);
+//   2. pulls its own row of plane z + 1, computes the moments and fluxes;
+//   3. swaps populations with LDS: reads those of plane z (pulled one plane earlier) and writes
+//      those of plane z + 1 in their place;
+//   4. collides its row of plane z and stores it;
+// and one barrier per plane orders the flux buffers. Every wavefront does the same work, so the
+// collision arithmetic is spread over all four SIMDs of a compute unit. phi_x and phi_y go to
+// two LDS buffers (planes z, z + 1), phi_z to a ring of three registers per column. float64
+// populations do not fit in LDS for two workgroups per compute unit and are pulled again at
+// step 3, from the caches. Fluxes are rounded to the storage type as the two-sweep field stores
+// them, so both paths give identical results. Traffic: the populations are read from memory
+// once and written once per node (432 B in float32), against about 1.5x that for two sweeps.
+constexpr int kF3Cols = 64;                // columns per tile (one wavefront row)
+constexpr int kF3Rows = 4;                 // rows per tile = wavefronts per workgroup
+constexpr int kF3Slots = 512;              // resident workgroups: 256 compute units x 2
+static_assert(kF3Rows * 64 == kBlock, "one row per wavefront");
+
+template <typename S, bool WALLS, bool PULL, bool DIAG>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
+k_ddf3_fused(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int nz, int64_t pitch,
+             int64_t plane, DdfParams prm, int nbx, int nby, int nzc,
+             double* __restrict__ partials) {
+  constexpr bool kLds = sizeof(S) == 4;  // populations kept in LDS between pull and collision
+  constexpr int NR = kLds ? kF3Rows : 1, NQ = kLds ? 54 : 1;
+  __shared__ RestShift rs;
+  __shared__ double s_px[2][kF3Rows][kF3Cols + 2];   // phi_x of the tile rows, slot column + 1
+  __shared__ double s_py[2][kF3Rows + 2][kF3Cols];   // phi_y of rows y0 - 1 .. y0 + kF3Rows
+  __shared__ S s_pop[NR][NQ][kF3Cols];               // each wavefront's row of one plane
+  rs.fill(prm);
+  const int T = nbx * nby;
+  const int b = xcd_tile(blockIdx.x, gridDim.x);
+  const int tile = b % T, chunk = b / T;
+  const int bx = tile % nbx, by = tile / nbx;
+  const int zb = (int)((int64_t)chunk * nz / nzc);
+  const int ze = (int)((int64_t)(chunk + 1) * nz / nzc);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int x0 = bx * kF3Cols, y0 = by * kF3Rows;
+  const int ncols = min(kF3Cols, nx - x0);
+  const bool col_ok = lane < ncols;
+  const int x = col_ok ? x0 + lane : x0 + ncols - 1;  // idle lanes repeat the last column
+  // own row; past the last row of the lattice (not collided) its periodic image, or the last
+  // row inside the walls, whose phi_y the row below takes as its neighbour's
+  const bool row_ok = y0 + wv < ny;
+  const int y = row_ok ? y0 + wv : (WALLS ? ny - 1 : (y0 + wv) % ny);
+  // halo piece. Wavefronts 1, 2: row y0 - 1 or y0 + kF3Rows (periodic, or the nearest row
+  // inside the walls: zero-order ghosts, Sec. III A). Wavefronts 0, 3: rows y0 + hr0 and
+  // y0 + hr0 + 1, lane 2k + s: row hr0 + k, s = 0 the column left of the tile, 1 the column
+  // right of it (periodic); lanes past 3 repeat lane 0 and store nothing.
+  const bool hrow = wv == 1 || wv == 2;
+  int yr = wv == 1 ? y0 - 1 : y0 + kF3Rows;
+  if (WALLS)
+    yr = yr < 0 ? 0 : (yr > ny - 1 ? ny - 1 : yr);
+  else
+    yr = ((yr % ny) + ny) % ny;
+  const int pyslot = wv == 1 ? 0 : kF3Rows + 1;
+  const int hr0 = wv == 0 ? 0 : 2;
+  const int hk = lane < 4 ? lane >> 1 : 0, hs = lane < 4 ? lane & 1 : 0;
+  const bool hx_ok = lane < 4 && y0 + hr0 + hk < ny;
+  const int yx = hx_ok ? y0 + hr0 + hk : y0;
+  const int xx = hs ? (x0 + ncols == nx ? 0 : x0 + ncols) : (x0 == 0 ? nx - 1 : x0 - 1);
+  const int pxslot = hs ? ncols + 1 : 0;
+  auto wrapz = [&](int z) { return z < 0 ? z + nz : (z >= nz ? z - nz : z); };
+  auto phi_of = [](const Moments3& m, int a) {
+    return (double)(S)(m.rho * m.u[a] * (m.u[a] * m.u[a] + 3.0 * (m.theta - 1.0 / 3.0)));
+  };
+  auto moments = [&](const S (&hf)[27], const S (&hg)[27], Moments3& m) {
+    const double* w = rs.at_row();
+    moments3<0>(hf, hg, prm, m, 0.0, 0.0, 0.0, 0.0, w, w + 27);
+  };
+  // step 1 for plane z into flux buffer k
+  auto halo = [&](int z, int k) {
+    S hf[27], hg[27];
+    Moments3 m;
+    if (hrow) {
+      gather27<S, WALLS, PULL, true>(A, plane, nx, ny, nz, pitch, x, yr, wrapz(z), hf, hg);
+      moments(hf, hg, m);
+      if (col_ok) s_py[k][pyslot][lane] = phi_of(m, 1);
+    } else {
+      gather27<S, WALLS, PULL, false>(A, plane, nx, ny, nz, pitch, xx, yx, wrapz(z), hf, hg);
+      moments(hf, hg, m);
+      if (hx_ok) s_px[k][hr0 + hk][pxslot] = phi_of(m, 0);
+    }
+  };
+  // step 2 for plane z into flux buffer k: own row pulled into hf, hg; returns phi_z
+  auto own = [&](int z, int k, S (&hf)[27], S (&hg)[27], Moments3& m) {
+    gather27<S, WALLS, PULL, true>(A, plane, nx, ny, nz, pitch, x, y, wrapz(z), hf, hg);
+    moments(hf, hg, m);
+    if (col_ok) {
+      s_px[k][wv][lane + 1] = phi_of(m, 0);
+      s_py[k][wv + 1][lane] = phi_of(m, 1);
+    }
+    return phi_of(m, 2);
+  };
+  auto put = [&](const S (&hf)[27], const S (&hg)[27]) {
+    if constexpr (kLds) {
+#pragma unroll
+      for (int i = 0; i < 27; ++i) {
+        s_pop[wv][i][lane] = hf[i];
+        s_pop[wv][27 + i][lane] = hg[i];
+      }
+    }
+  };
+  double acc[kDiagValues] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (ze > zb) {
+    Moments3 m0;
+    double pz_prv, pz_cur;
+    {
+      S hf[27], hg[27];
+      Moments3 m;
+      pz_prv = own(zb - 1, 1, hf, hg, m);  // phi_z below the range (buffer 1 rewritten below)
+      halo(zb, 0);
+      pz_cur = own(zb, 0, hf, hg, m0);
+      put(hf, hg);
+    }
+    __syncthreads();
+    int kc = 0;  // flux buffer of plane z
+    for (int z = zb; z < ze; ++z) {
+      const int kn = kc ^ 1;
+      halo(z + 1, kn);
+      S hf[27], hg[27];
+      double pz_nxt;
+      Moments3 m1;
+      {
+        S nf[27], ng[27];
+        pz_nxt = own(z + 1, kn, nf, ng, m1);
+        if constexpr (kLds) {
+#pragma unroll
+          for (int i = 0; i < 27; ++i) {
+            hf[i] = s_pop[wv][i][lane];
+            hg[i] = s_pop[wv][27 + i][lane];
+          }
+          put(nf, ng);
+        } else {
+          gather27<S, WALLS, PULL, true>(A, plane, nx, ny, nz, pitch, x, y, z, hf, hg);
+        }
+      }
+      if (row_ok) {
+        const double inv_rho = 1.0 / m0.rho;
+        double ph[3];
+        ph[0] = -(0.5 * (s_px[kc][wv][lane + 2] - s_px[kc][wv][lane])) * inv_rho;
+        ph[1] = -(0.5 * (s_py[kc][wv + 2][lane] - s_py[kc][wv][lane])) * inv_rho;
+        ph[2] = -(0.5 * (pz_nxt - pz_prv)) * inv_rho;
+        const double zero3[3] = {0.0, 0.0, 0.0};
+        const double* w2 = rs.at_row();
+        S* out = B + ((int64_t)z * ny + y) * pitch;  // row base (wave-uniform)
+        const uint32_t xo = fresh((uint32_t)sizeof(S) * x);
+        int64_t pl = plane;
+        asm volatile("" : "+s"(pl));
+        collide3<0>(hf, hg, m0, ph, zero3, zero3, 0.0, prm, w2, w2 + 27,
+                    [&](int i, double tf, double tg) {
+          if (col_ok) {
+            gstore_nt(at_byte(sbase(out + i * pl), xo), (S)tf);
+            gstore_nt(at_byte(sbase(out + (27 + i) * pl), xo), (S)tg);
+          }
+        });
+        if (DIAG && col_ok) {
+          acc[0] += m0.rho;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) acc[1 + a] += m0.rho * m0.u[a];
+          const double u2 = m0.u[0] * m0.u[0] + m0.u[1] * m0.u[1] + m0.u[2] * m0.u[2];
+          acc[4] += m0.rho * (m0.e + 0.5 * u2);
+        }
+      }
+      m0 = m1;
+      pz_prv = pz_cur;
+      pz_cur = pz_nxt;
+      kc = kn;
+      __syncthreads();
+    }
+  }
+  if (DIAG) block_sum_store<kDiagValues>(acc, partials + (int64_t)blockIdx.x * kDiagValues);
+}
+
 // f <- f^eq, g <- g^eq of the initial fields (Fig. 1), shifted by the rest state.
 template <typename S>
 __global__ void k_init_ddf3(const double* __restrict__ rho, const double* __restrict__ u,
@@ -582,10 +764,57 @@ static void wall_kind(bool walls, const DdfParams& prm, Fn&& fn) {
     fn(std::integral_constant<int, 1>{});
 }
 
+// Shape of the one-launch step: tiles of kF3Cols x kF3Rows nodes, each with its planes split
+// into nzc balanced ranges. nzc minimises the launch's rounds of kF3Slots resident workgroups
+// times the planes per range (plus the two flux planes a range starts with).
+struct Fused3 {
+  int nbx, nby, nzc;
+  int64_t blocks() const { return (int64_t)nbx * nby * nzc; }
+};
+
+static Fused3 fused3_shape(const Layout& L) {
+  Fused3 F;
+  F.nbx = (L.nx + kF3Cols - 1) / kF3Cols;
+  F.nby = (L.ny + kF3Rows - 1) / kF3Rows;
+  F.nzc = 1;
+  const int64_t T = (int64_t)F.nbx * F.nby;
+  int64_t best = -1;
+  for (int c = 1; c <= std::min(L.nz, 64); ++c) {
+    if (T * c > (int64_t)1 << 30) break;
+    const int64_t cost = ((T * c + kF3Slots - 1) / kF3Slots) * ((L.nz + c - 1) / c + 2);
+    if (best < 0 || cost < best) {
+      best = cost;
+      F.nzc = c;
+    }
+  }
+  return F;
+}
+
+int64_t ddf3_fused_blocks(const Layout& L) { return fused3_shape(L).blocks(); }
+
+static bool fused3_ok(bool walls, const DdfParams& prm) {
+  return prm.phi == 1 && !prm.ext() && prm.eos == 0 && !(walls && prm.neq);
+}
+
 template <typename S>
 static void ddf3_step(bool walls, bool pull, const S* A, S* B, const Layout& L, const Grid& G,
                       const DdfParams& prm, double* fld64, S* nb, double* partials,
-                      hipStream_t s) {
+                      int* records, hipStream_t s) {
+  if (fused3_ok(walls, prm)) {
+    const Fused3 F = fused3_shape(L);
+    *records = (int)F.blocks();
+    flag(walls, [&](auto W) {
+      flag(pull, [&](auto Pl) {
+        flag(partials != nullptr, [&](auto Dg) {
+          k_ddf3_fused<S, decltype(W)::value, decltype(Pl)::value, decltype(Dg)::value>
+              <<<(unsigned)F.blocks(), kBlock, 0, s>>>(A, B, L.nx, L.ny, L.nz, L.pitch, L.plane,
+                                                       prm, F.nbx, F.nby, F.nzc, partials);
+        });
+      });
+    });
+    return;
+  }
+  *records = G.blocks();
   dim3 grid(G.nbx, G.nby), block(G.bx);
   S* fld = reinterpret_cast<S*>(fld64);  // 8 planes of the storage type
   if (walls && prm.neq) {
@@ -624,15 +853,17 @@ static void ddf3_step(bool walls, bool pull, const S* A, S* B, const Layout& L, 
 
 hipError_t launch_ddf3(int kind, bool walls, bool pull, const void* A, void* B, const Layout& L,
                        const Grid& G, const DdfParams& prm, double* fld, void* nb,
-                       double* partials, hipStream_t s) {
+                       double* partials, int* records, hipStream_t s) {
   if (prm.neq && (!walls || !nb || L.ny < 3 || prm.src))
     return hipErrorInvalidValue;
+  int rec = 0;
   if (kind == 0)
     ddf3_step<float>(walls, pull, static_cast<const float*>(A), static_cast<float*>(B), L, G,
-                     prm, fld, static_cast<float*>(nb), partials, s);
+                     prm, fld, static_cast<float*>(nb), partials, &rec, s);
   else
     ddf3_step<double>(walls, pull, static_cast<const double*>(A), static_cast<double*>(B), L, G,
-                      prm, fld, static_cast<double*>(nb), partials, s);
+                      prm, fld, static_cast<double*>(nb), partials, &rec, s);
+  if (records) *records = rec;
   return hipGetLastError();
 }
 

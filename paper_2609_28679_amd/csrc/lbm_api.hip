@@ -251,6 +251,8 @@ void make_plan(const lbm_params* p, Plan& P) {
   else
     P.G = make_grid(P.L);
   P.partial_slots = std::max(P.G.blocks(), 1024);
+  if (P.ddf && P.D == 3)  // the one-launch step writes one record per workgroup
+    P.partial_slots = (int)std::max<int64_t>(P.partial_slots, ddf3_fused_blocks(P.L));
   // One in-place buffer where supported and either requested or small enough to profit from
   // the 256 MB last-level cache. Measured float32 D2Q9 step times (one vs two buffers): 44 vs
   // 51 us at 151 MB per buffer, 122 vs 131 us at 340 MB, equal at 399 MB, 235 vs 209 us at
@@ -492,7 +494,7 @@ int lbm_create(const lbm_params* p, const double* rho0, const double* u0, const 
       if (e == hipSuccess) e = launch_ddf(c->fmt, p->wall_y != 0, false, c->B, c->A, c->L, c->G, c->dp, c->s_enc, c->s_dec, nullptr, c->nb, c->stream);
     } else {
       if (e == hipSuccess) e = launch_init_ddf3(c->kind, c->readout, c->readout + nodes, d_T0, c->B, c->L, c->dp, c->stream);
-      if (e == hipSuccess) e = launch_ddf3(c->kind, p->wall_y != 0, false, c->B, c->A, c->L, c->G, c->dp, c->fld, c->nb, nullptr, c->stream);
+      if (e == hipSuccess) e = launch_ddf3(c->kind, p->wall_y != 0, false, c->B, c->A, c->L, c->G, c->dp, c->fld, c->nb, nullptr, nullptr, c->stream);
     }
   } else if (e == hipSuccess && c->codec >= 0) {
     e = launch_init_bgk_red(c->readout, c->readout + nodes, c->A, c->L, c->stream);
@@ -517,12 +519,13 @@ int lbm_step(lbm_ctx* c, int64_t n) {
     const int64_t tn = c->t + 1;
     const bool diag = de > 0 && tn % de == 0;
     double* part = diag ? c->partials : nullptr;
+    int records = c->G.blocks();  // diagnostics records the step writes
     hipError_t e;
     if (c->p.collision == LBM_COLLIDE_MLP) {
       if (!c->mlp_set) return fail(c, LBM_ESTATE, "surrogate weights not installed (lbm_set_mlp)");
       e = launch_bgk_d2q9_mlp(c->A, c->B, c->L, c->G, c->omega, c->p.wall_y != 0, c->mlp_w, c->mlp_tol, c->mlp_cnt, part, c->stream);
     } else if (c->ddf && c->D == 3)
-      e = launch_ddf3(c->kind, c->p.wall_y != 0, true, c->A, c->B, c->L, c->G, c->dp, c->fld, c->nb, part, c->stream);
+      e = launch_ddf3(c->kind, c->p.wall_y != 0, true, c->A, c->B, c->L, c->G, c->dp, c->fld, c->nb, part, &records, c->stream);
     else if (c->ddf)
       e = launch_ddf(c->fmt, c->p.wall_y != 0, true, c->A, c->B, c->L, c->G, c->dp, c->s_enc, c->s_dec, part, c->nb, c->stream);
     else if (c->codec >= 0)
@@ -538,7 +541,7 @@ int lbm_step(lbm_ctx* c, int64_t n) {
     if (e != hipSuccess) return hip_fail(c, e, "step kernel launch");
     if (diag) {
       double* slot = c->history + (c->hist_written % kHistoryCap) * 6;
-      e = launch_diag_finalize(c->partials, c->G.blocks(), (double)tn, slot, c->stream);
+      e = launch_diag_finalize(c->partials, records, (double)tn, slot, c->stream);
       if (e != hipSuccess) return hip_fail(c, e, "diagnostics launch");
       ++c->hist_written;
     }

@@ -135,16 +135,21 @@ hipError_t launch_decode_ddf(int kind, int Q, int i, const void* A, const Layout
 // D3Q27 double distribution (float32 kind 0 / float64 kind 1 storage, 54 planes). One step is
 // two launches: fluxes (and, with transport control, T and u; for the van der Waals fluid also
 // the enthalpy) into `fld` (8 fields of L.plane elements in the storage type, float32 or
-// float64), then the collision; pull = false collides in place of streaming.
+// float64), then the collision; pull = false collides in place of streaming. The collision
+// without sources, transport terms or NEQ walls, with the central derivative of Phi, is one
+// launch that marches along z instead (ddf3_fused_blocks workgroups).
 Grid make_grid_ddf3(const Layout& L);
 hipError_t launch_ddf3_rest_state(const DdfParams& prm, double* out, hipStream_t s);
 hipError_t launch_init_ddf3(int kind, const double* rho, const double* u, const double* T,
                             void* A, const Layout& L, const DdfParams& prm, hipStream_t s);
 // nb: boundary planes of the non-equilibrium extrapolation walls (2 x 54 planes of nz x pitch
 // storage elements; used when prm.neq, NULL otherwise).
+// records: set to the number of per-workgroup diagnostics records the step writes to
+// partials (may be NULL).
 hipError_t launch_ddf3(int kind, bool walls, bool pull, const void* A, void* B, const Layout& L,
                        const Grid& G, const DdfParams& prm, double* fld, void* nb,
-                       double* partials, hipStream_t s);
+                       double* partials, int* records, hipStream_t s);
+int64_t ddf3_fused_blocks(const Layout& L);
 hipError_t launch_moments_ddf3(int kind, const void* A, const Layout& L, const DdfParams& prm,
                                double* rho, double* u, double* T, double* edens, hipStream_t s);
 // Reduced storage (D2Q9 isothermal): 3 float32 moment planes then 6 uint16 planes.
