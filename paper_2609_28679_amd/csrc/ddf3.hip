@@ -120,24 +120,26 @@ __device__ __forceinline__ void node_pops(const S* __restrict__ A, const S* __re
 // rho = sum f, rho u = sum c f + sF/2, rho E = sum g + (u.sF + sQ)/2 (Sec. II C), then
 // T = (E - u^2/2)/c_v and theta = R T; for the van der Waals fluid (EXT = 2)
 // T = (E - u^2/2 + a rho)/c_v (Eq. lbm_temp) and theta = P/rho. (sF, sQ) as in moments_closure
-// (ddf_common.h); EXT = 0 takes no sources.
-// wf, wg: the rest-state shift (p.wf, p.wg; the sweep kernels pass a copy in LDS, see
-// RestShift below)
+// (ddf_common.h); EXT = 0 takes no sources. The sums run over the stored deviations
+// h = f - w, g - v and add the rest totals sum w, sum v once (p.wsum_f, p.wsum_g); sum c w
+// vanishes, w being even in every velocity component.
 template <int EXT, typename S>
 __device__ __forceinline__ void moments3(const S (&hf)[27], const S (&hg)[27], const DdfParams& p,
                                          Moments3& m, double sFx, double sFy, double sFz,
-                                         double sQ, const double* wf, const double* wg) {
+                                         double sQ) {
   double rho = 0.0, j[3] = {0.0, 0.0, 0.0}, rE = 0.0;
 #pragma unroll
   for (int i = 0; i < 27; ++i) {
-    const double f = (double)hf[i] + wf[i];
+    const double f = (double)hf[i];
     rho += f;
     const int c[3] = {i % 3 - 1, (i / 3) % 3 - 1, i / 9 - 1};
 #pragma unroll
     for (int a = 0; a < 3; ++a)
       if (c[a]) j[a] += c[a] > 0 ? f : -f;
-    rE += (double)hg[i] + wg[i];
+    rE += (double)hg[i];
   }
+  rho += p.wsum_f;
+  rE += p.wsum_g;
   if (EXT) {
     j[0] += 0.5 * sFx;
     j[1] += 0.5 * sFy;
@@ -246,8 +248,9 @@ __device__ __forceinline__ void collide3(const S (&hf)[27], const S (&hg)[27], c
 // doubles took 108 scalar registers for the whole kernel and spilled some 330 of them to vector
 // lanes (about 700 extra vector instructions per node in the collision sweep). The offset z is
 // 0 but re-declared per row, so the reads stay at their uses instead of being hoisted into
-// registers. Taken, with scalar-base row addressing, by the sweeps without sources, transport
-// terms or NEQ walls (kLean below): 256^3 central 2226 -> 2152 us, upwind 2678 -> 2466 us; the
+// registers (the moments need only the shift's totals, held in DdfParams). Taken, with
+// scalar-base row addressing, by the collisions without sources, transport terms or NEQ walls
+// (kLean below, and the one-launch step): 256^3 central 2226 -> 2152 us, upwind 2678 -> 2466 us; the
 // extended sweeps (one wave per SIMD, ~310 registers) measured 2-3% slower with it and the NEQ
 // sweeps 1.5% slower, so they keep the parameter arrays and per-lane addresses.
 struct RestShift {
@@ -278,9 +281,7 @@ template <typename S, int WALLS, bool PULL, int EXT>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
 k_ddf3_flux(const S* __restrict__ A, const S* __restrict__ nb, int nx, int ny, int nz,
             int64_t pitch, int64_t plane, DdfParams prm, int rows, S* __restrict__ fld) {
-  constexpr bool kLean = EXT == 0 && WALLS != 2;
-  __shared__ RestShift rs;
-  if (kLean) rs.fill(prm);
+  constexpr bool kLean = EXT == 0 && WALLS != 2;  // scalar-base row addressing
   const int nbx = gridDim.x;
   const int tile = blockIdx.x + nbx * blockIdx.y;
   const int bx = tile % nbx, by = tile / nbx;
@@ -292,8 +293,7 @@ k_ddf3_flux(const S* __restrict__ A, const S* __restrict__ nb, int nx, int ny, i
     S hf[27], hg[27];
     node_pops<S, WALLS, PULL, kLean>(A, nb, plane, nx, ny, nz, pitch, x, y, z, hf, hg);
     Moments3 m;
-    const double* w = kLean ? rs.at_row() : prm.wf;
-    moments3<EXT>(hf, hg, prm, m, prm.Fx, prm.Fy, prm.Fz, prm.Q, w, kLean ? w + 27 : prm.wg);
+    moments3<EXT>(hf, hg, prm, m, prm.Fx, prm.Fy, prm.Fz, prm.Q);
     const int64_t off = ((int64_t)z * ny + y) * pitch + x;
 #pragma unroll
     for (int a = 0; a < 3; ++a)
@@ -332,8 +332,7 @@ k_ddf3_collide(const S* __restrict__ A, const S* __restrict__ nb, S* __restrict_
       S hf[27], hg[27];
       node_pops<S, WALLS, PULL, kLean>(A, nb, plane, nx, ny, nz, pitch, x, y, z, hf, hg);
       Moments3 m;
-      const double* w = kLean ? rs.at_row() : prm.wf;
-      moments3<EXT>(hf, hg, prm, m, prm.Fx, prm.Fy, prm.Fz, prm.Q, w, kLean ? w + 27 : prm.wg);
+      moments3<EXT>(hf, hg, prm, m, prm.Fx, prm.Fy, prm.Fz, prm.Q);
       const int64_t off = ((int64_t)z * ny + y) * pitch + x;
       // offset of the node k steps along axis a: periodic in x and z; in y periodic, or the
       // nearest fluid row beyond a wall (zero-order ghosts, Sec. III A)
@@ -462,7 +461,9 @@ k_ddf3_fused(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int nz,
   const int bx = tile % nbx, by = tile / nbx;
   const int zb = (int)((int64_t)chunk * nz / nzc);
   const int ze = (int)((int64_t)(chunk + 1) * nz / nzc);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // wavefront index as a scalar: the rows and their addresses are then computed once per
+  // wavefront instead of per lane
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int x0 = bx * kF3Cols, y0 = by * kF3Rows;
   const int ncols = min(kF3Cols, nx - x0);
   const bool col_ok = lane < ncols;
@@ -492,9 +493,12 @@ k_ddf3_fused(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int nz,
   auto phi_of = [](const Moments3& m, int a) {
     return (double)(S)(m.rho * m.u[a] * (m.u[a] * m.u[a] + 3.0 * (m.theta - 1.0 / 3.0)));
   };
+  // all 54 loads of a pull are issued before the sums start: without the scheduling barrier
+  // the compiler moves each load next to its single use and waits for it there, one load in
+  // flight at a time
   auto moments = [&](const S (&hf)[27], const S (&hg)[27], Moments3& m) {
-    const double* w = rs.at_row();
-    moments3<0>(hf, hg, prm, m, 0.0, 0.0, 0.0, 0.0, w, w + 27);
+    __builtin_amdgcn_sched_barrier(0);
+    moments3<0>(hf, hg, prm, m, 0.0, 0.0, 0.0, 0.0);
   };
   // step 1 for plane z into flux buffer k
   auto halo = [&](int z, int k) {
@@ -640,8 +644,8 @@ __global__ void k_moments_ddf3(const S* __restrict__ A, int nx, int64_t nodes, i
     hg[i] = A[(27 + i) * plane + off];
   }
   Moments3 m;
-  if (prm.eos) moments3<2>(hf, hg, prm, m, -prm.Fx, -prm.Fy, -prm.Fz, -prm.Q, prm.wf, prm.wg);
-  else moments3<1>(hf, hg, prm, m, -prm.Fx, -prm.Fy, -prm.Fz, -prm.Q, prm.wf, prm.wg);
+  if (prm.eos) moments3<2>(hf, hg, prm, m, -prm.Fx, -prm.Fy, -prm.Fz, -prm.Q);
+  else moments3<1>(hf, hg, prm, m, -prm.Fx, -prm.Fy, -prm.Fz, -prm.Q);
   rho[n] = m.rho;
   for (int a = 0; a < 3; ++a) u[a * nodes + n] = m.u[a];
   T[n] = prm.eos ? (m.e + prm.va * m.rho) / prm.cv : m.theta / prm.R;
@@ -729,7 +733,7 @@ k_ddf3_neq_rows(const S* __restrict__ A, int nx, int ny, int nz, int64_t pitch, 
   S hf[27], hg[27];
   gather27<S, true, PULL, false>(A, plane, nx, ny, nz, pitch, x, N, z, hf, hg);
   Moments3 m;
-  moments3<EXT == 2 ? 2 : 0>(hf, hg, prm, m, 0.0, 0.0, 0.0, 0.0, prm.wf, prm.wg);
+  moments3<EXT == 2 ? 2 : 0>(hf, hg, prm, m, 0.0, 0.0, 0.0, 0.0);
   constexpr bool VDW = EXT == 2;
   const double TN = node_temperature<VDW>(prm, m.rho, m.e, m.theta);
   double rhoB, thetaW, eW;

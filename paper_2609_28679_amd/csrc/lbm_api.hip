@@ -485,9 +485,12 @@ int lbm_create(const lbm_params* p, const double* rho0, const double* u0, const 
     double rest[54];
     if (e == hipSuccess) e = hipMemcpyAsync(rest, c->partials, sizeof(rest), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    c->dp.wsum_f = c->dp.wsum_g = 0.0;
     for (int i = 0; i < P.Q; ++i) {
       c->dp.wf[i] = rest[i];
       c->dp.wg[i] = rest[P.Q + i];
+      c->dp.wsum_f += rest[i];
+      c->dp.wsum_g += rest[P.Q + i];
     }
     if (P.D == 2) {
       if (e == hipSuccess) e = launch_init_ddf(c->fmt, c->readout, c->readout + nodes, d_T0, c->B, c->L, c->dp, c->stream);

@@ -86,6 +86,9 @@ struct DdfParams {
   // first 9 entries for D2Q9, 27 for D3Q27)
   double wf[27];
   double wg[27];
+  // their totals sum_i wf_i and sum_i wg_i (D3Q27: the moments sum the stored deviations and
+  // add these once)
+  double wsum_f = 0.0, wsum_g = 0.0;
 };
 
 // ---- launchers (return the first HIP error) -----------------------------------------------
