@@ -312,14 +312,8 @@ k_ddf_d2q9(IO io, int nx, int ny, int64_t pitch, DdfParams prm, int rows,
         // ---- gather (pull) ----------------------------------------------------------------
         gather_row(r, ring_f[j], ring_g[j]);
         // ---- moments and closure ------------------------------------------------------------
-        double f[9], g[9];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-          f[i] = (double)ring_f[j][i] + prm.wf[i];
-          g[i] = (double)ring_g[j][i] + prm.wg[i];
-        }
         Moments m;
-        moments_closure<X, VDW>(f, g, prm, m, prm.Fx, prm.Fy, prm.Q);
+        moments_closure_dev<X, VDW>(ring_f[j], ring_g[j], prm, m, prm.Fx, prm.Fy, prm.Q);
         ring_m[j][0] = m.rho;
         ring_m[j][1] = m.ux;
         ring_m[j][2] = m.uy;

@@ -81,6 +81,44 @@ __device__ __forceinline__ void moments_closure(const double (&f)[9], const doub
   }
 }
 
+// The same closure from the stored deviations h = f - w, g - v of the shifted storage: the
+// sums run over the deviations and add the rest totals sum w, sum v once (p.wsum_f, p.wsum_g);
+// the momentum sums need no shift, w being even in each velocity component.
+template <bool SRC = false, bool VDW = false, typename R>
+__device__ __forceinline__ void moments_closure_dev(const R (&hf)[9], const R (&hg)[9],
+                                                    const DdfParams& p, Moments& m,
+                                                    double sFx = 0.0, double sFy = 0.0,
+                                                    double sQ = 0.0) {
+  double f[9], g[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    f[i] = (double)hf[i];
+    g[i] = (double)hg[i];
+  }
+  const double rho =
+      (((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8]) + p.wsum_f;
+  double jx = (f[2] + f[5] + f[8]) - (f[0] + f[3] + f[6]);
+  double jy = (f[6] + f[7] + f[8]) - (f[0] + f[1] + f[2]);
+  double rE =
+      (((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8]) + p.wsum_g;
+  if (SRC) {
+    jx += 0.5 * sFx;
+    jy += 0.5 * sFy;
+  }
+  const double inv = 1.0 / rho;
+  m.rho = rho;
+  m.ux = jx * inv;
+  m.uy = jy * inv;
+  if (SRC) rE += 0.5 * ((m.ux * sFx + m.uy * sFy) + sQ);
+  m.e = rE * inv - 0.5 * (m.ux * m.ux + m.uy * m.uy);
+  if (VDW) {
+    const double T = (m.e + p.va * rho) / p.cv;
+    m.theta = p.R * T / (1.0 - p.vb * rho) - p.va * rho;
+  } else {
+    m.theta = p.r_cv * m.e;
+  }
+}
+
 // Temperature of a node from its moments (ideal gas: theta / R; van der Waals: Eq. lbm_temp).
 template <bool VDW>
 __device__ __forceinline__ double node_temperature(const DdfParams& p, double rho, double e,
