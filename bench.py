@@ -368,7 +368,7 @@ def main():
                 n, lambda: binding.Lattice(*inputs.thermal_taylor_green_3d(256, 0.05),
                                            lattice="D3Q27", model="ddf", tau=0.6, phi=1),
                 max(50, vs // 20), 5, 432,
-                {"phi": "central", "launches": "2 per step (fluxes, collision)"})),
+                {"phi": "central", "launches": "1 per step (fluxes and collision, marching in z)"})),
             ("d3q27_ddf_fp32_256_sources", lambda n: variant(
                 n, lambda: binding.Lattice(*inputs.thermal_taylor_green_3d(256, 0.05),
                                            lattice="D3Q27", model="ddf", tau=0.6, phi=1,
