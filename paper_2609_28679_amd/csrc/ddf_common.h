@@ -196,12 +196,15 @@ __device__ __forceinline__ void gather9(const S* __restrict__ A, int64_t plane, 
   }
 }
 
-// Second-order one-sided difference on the upwind side of u (central when u = 0).
+// Second-order one-sided difference on the upwind side of u (central when u = 0). All three
+// stencils are formed and one is selected: written as branches, the compiler moved each field
+// load into the branch that uses it and waited for it there.
 __device__ __forceinline__ double upwind_or_central(double pm2, double pm1, double p0, double pp1,
                                                     double pp2, double u) {
-  if (u > 0.0) return 0.5 * (3.0 * p0 - 4.0 * pm1 + pm2);
-  if (u < 0.0) return -0.5 * (3.0 * p0 - 4.0 * pp1 + pp2);
-  return 0.5 * (pp1 - pm1);
+  const double up = 0.5 * (3.0 * p0 - 4.0 * pm1 + pm2);
+  const double un = -0.5 * (3.0 * p0 - 4.0 * pp1 + pp2);
+  const double c = 0.5 * (pp1 - pm1);
+  return u > 0.0 ? up : (u < 0.0 ? un : c);
 }
 
 // Collision of one node from its pre-collision populations held shifted by the rest state
