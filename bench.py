@@ -395,7 +395,7 @@ def main():
                                            neq_walls=dict(u=((-0.05, 0.0), (0.05, 0.0)),
                                                           T=(0.8, 1.0))),
                 max(50, vs // 20), 5, 432,
-                {"phi": "central", "launches": "3 per step (boundary planes, fluxes, collision)",
+                {"phi": "central", "launches": "2 per step (boundary planes; fluxes and collision, marching in z)",
                  "walls": "y, non-equilibrium extrapolation (u_W = -+0.05, T_W = 0.8 / 1.0)",
                  "wall_density": NEQ_DENSITY})),
             ("d3q27_ddf_fp32_256_upwind", lambda n: variant(

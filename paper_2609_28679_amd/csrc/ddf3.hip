@@ -250,7 +250,7 @@ __device__ __forceinline__ void collide3(const S (&hf)[27], const S (&hg)[27], c
 // 0 but re-declared per row, so the reads stay at their uses instead of being hoisted into
 // registers (the moments need only the shift's totals, held in DdfParams). Taken, with
 // scalar-base row addressing, by the collisions without sources, transport terms or NEQ walls
-// (kLean below, and the one-launch step): 256^3 central 2226 -> 2152 us, upwind 2678 -> 2466 us; the
+// (kLean below) and by the one-launch step: 256^3 central 2226 -> 2152 us, upwind 2678 -> 2466 us; the
 // extended sweeps (one wave per SIMD, ~310 registers) measured 2-3% slower with it and the NEQ
 // sweeps 1.5% slower, so they keep the parameter arrays and per-lane addresses.
 struct RestShift {
@@ -441,9 +441,8 @@ k_ddf3_collide(const S* __restrict__ A, const S* __restrict__ nb, S* __restrict_
 }
 
 // ---- one-launch step --------------------------------------------------------------------------
-// For the collision without sources, transport terms or NEQ walls and with the central
-// derivative of Phi, the flux and collision sweeps are fused into one launch that marches along
-// z. A workgroup owns a tile of kF3Cols columns by kF3Rows rows (one row per wavefront) and a
+// For the collision without sources or transport terms and with the central derivative of Phi,
+// the flux and collision sweeps are fused into one launch that marches along z. A workgroup owns a tile of kF3Cols columns by kF3Rows rows (one row per wavefront) and a
 // range of planes. Per plane z every wavefront
 //   1. computes the fluxes of one halo piece of plane z + 1: the rows below and above the tile
 //      (wavefronts 1 and 2) or phi_x of the columns left and right of two of its rows
@@ -464,11 +463,13 @@ constexpr int kF3Rows = 4;                 // rows per tile = wavefronts per wor
 constexpr int kF3Slots = 512;              // resident workgroups: 256 compute units x 2
 static_assert(kF3Rows * 64 == kBlock, "one row per wavefront");
 
-template <typename S, bool WALLS, bool PULL, bool DIAG>
+// WALLS: 0 periodic in y, 1 bounce-back walls, 2 non-equilibrium extrapolation walls (boundary
+// planes read from nb, rebuilt by k_ddf3_neq_rows, as in the two sweeps).
+template <typename S, int WALLS, bool PULL, bool DIAG>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
-k_ddf3_fused(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int nz, int64_t pitch,
-             int64_t plane, DdfParams prm, int nbx, int nby, int nzc,
-             double* __restrict__ partials) {
+k_ddf3_fused(const S* __restrict__ A, const S* __restrict__ nb, S* __restrict__ B, int nx,
+             int ny, int nz, int64_t pitch, int64_t plane, DdfParams prm, int nbx, int nby,
+             int nzc, double* __restrict__ partials) {
   constexpr bool kLds = sizeof(S) == 4;  // populations kept in LDS between pull and collision
   constexpr int NR = kLds ? kF3Rows : 1, NQ = kLds ? 54 : 1;
   __shared__ RestShift rs;
@@ -526,18 +527,18 @@ k_ddf3_fused(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int nz,
     S hf[27], hg[27];
     Moments3 m;
     if (hrow) {
-      gather27<S, WALLS, PULL, true>(A, plane, nx, ny, nz, pitch, x, yr, wrapz(z), hf, hg);
+      node_pops<S, WALLS, PULL, true>(A, nb, plane, nx, ny, nz, pitch, x, yr, wrapz(z), hf, hg);
       moments(hf, hg, m);
       if (col_ok) s_py[k][pyslot][lane] = phi_of(m, 1);
     } else {
-      gather27<S, WALLS, PULL, false>(A, plane, nx, ny, nz, pitch, xx, yx, wrapz(z), hf, hg);
+      node_pops<S, WALLS, PULL, false>(A, nb, plane, nx, ny, nz, pitch, xx, yx, wrapz(z), hf, hg);
       moments(hf, hg, m);
       if (hx_ok) s_px[k][hr0 + hk][pxslot] = phi_of(m, 0);
     }
   };
   // step 2 for plane z into flux buffer k: own row pulled into hf, hg; returns phi_z
   auto own = [&](int z, int k, S (&hf)[27], S (&hg)[27], Moments3& m) {
-    gather27<S, WALLS, PULL, true>(A, plane, nx, ny, nz, pitch, x, y, wrapz(z), hf, hg);
+    node_pops<S, WALLS, PULL, true>(A, nb, plane, nx, ny, nz, pitch, x, y, wrapz(z), hf, hg);
     moments(hf, hg, m);
     if (col_ok) {
       s_px[k][wv][lane + 1] = phi_of(m, 0);
@@ -585,7 +586,7 @@ k_ddf3_fused(const S* __restrict__ A, S* __restrict__ B, int nx, int ny, int nz,
           }
           put(nf, ng);
         } else {
-          gather27<S, WALLS, PULL, true>(A, plane, nx, ny, nz, pitch, x, y, z, hf, hg);
+          node_pops<S, WALLS, PULL, true>(A, nb, plane, nx, ny, nz, pitch, x, y, z, hf, hg);
         }
       }
       if (row_ok) {
@@ -817,31 +818,14 @@ static Fused3 fused3_shape(const Layout& L) {
 
 int64_t ddf3_fused_blocks(const Layout& L) { return fused3_shape(L).blocks(); }
 
-static bool fused3_ok(bool walls, const DdfParams& prm) {
-  return prm.phi == 1 && !prm.ext() && prm.eos == 0 && !(walls && prm.neq);
+static bool fused3_ok(const DdfParams& prm) {
+  return prm.phi == 1 && !prm.ext() && prm.eos == 0;
 }
 
 template <typename S>
 static void ddf3_step(bool walls, bool pull, const S* A, S* B, const Layout& L, const Grid& G,
                       const DdfParams& prm, double* fld64, S* nb, double* partials,
                       int* records, hipStream_t s) {
-  if (fused3_ok(walls, prm)) {
-    const Fused3 F = fused3_shape(L);
-    *records = (int)F.blocks();
-    flag(walls, [&](auto W) {
-      flag(pull, [&](auto Pl) {
-        flag(partials != nullptr, [&](auto Dg) {
-          k_ddf3_fused<S, decltype(W)::value, decltype(Pl)::value, decltype(Dg)::value>
-              <<<(unsigned)F.blocks(), kBlock, 0, s>>>(A, B, L.nx, L.ny, L.nz, L.pitch, L.plane,
-                                                       prm, F.nbx, F.nby, F.nzc, partials);
-        });
-      });
-    });
-    return;
-  }
-  *records = G.blocks();
-  dim3 grid(G.nbx, G.nby), block(G.bx);
-  S* fld = reinterpret_cast<S*>(fld64);  // 8 planes of the storage type
   if (walls && prm.neq) {
     const unsigned nblk = (unsigned)((2 * (int64_t)L.nz * L.nx + kBlock - 1) / kBlock);
     flag(pull, [&](auto Pl) {
@@ -851,6 +835,24 @@ static void ddf3_step(bool walls, bool pull, const S* A, S* B, const Layout& L, 
       });
     });
   }
+  if (fused3_ok(prm)) {
+    const Fused3 F = fused3_shape(L);
+    *records = (int)F.blocks();
+    wall_kind(walls, prm, [&](auto W) {
+      flag(pull, [&](auto Pl) {
+        flag(partials != nullptr, [&](auto Dg) {
+          k_ddf3_fused<S, decltype(W)::value, decltype(Pl)::value, decltype(Dg)::value>
+              <<<(unsigned)F.blocks(), kBlock, 0, s>>>(A, nb, B, L.nx, L.ny, L.nz, L.pitch,
+                                                       L.plane, prm, F.nbx, F.nby, F.nzc,
+                                                       partials);
+        });
+      });
+    });
+    return;
+  }
+  *records = G.blocks();
+  dim3 grid(G.nbx, G.nby), block(G.bx);
+  S* fld = reinterpret_cast<S*>(fld64);  // 8 planes of the storage type
   wall_kind(walls, prm, [&](auto W) {
     flag(pull, [&](auto Pl) {
       ext_kind(prm, [&](auto E) {
