@@ -374,7 +374,7 @@ def main():
                                            lattice="D3Q27", model="ddf", tau=0.6, phi=1,
                                            force=(1e-7, 0.0, 0.0), heat_source=1e-8),
                 max(50, vs // 20), 5, 432,
-                {"phi": "central", "launches": "2 per step (fluxes, collision)",
+                {"phi": "central", "launches": "1 per step (fluxes and collision, marching in z)",
                  "sources": "uniform force (1e-7, 0, 0) and heat source 1e-8"})),
             ("d3q27_ddf_fp32_256_prandtl", lambda n: variant(
                 n, lambda: binding.Lattice(*inputs.thermal_taylor_green_3d(256, 0.05),

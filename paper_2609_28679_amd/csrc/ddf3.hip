@@ -175,7 +175,8 @@ __device__ __forceinline__ void equilibria3(double rho, double e, int i, const A
 // h = e + P/rho (van der Waals only); sink(i, f~ - w, g~ - v). EXT: 0 without sources and
 // transport terms, 1 with them (ideal gas), 2 the van der Waals fluid (gamma - 1, alpha and
 // q^c = P (grad h - (k/mu) grad T) per node).
-template <int EXT, typename S, typename Sink>
+// FULL = false drops the transport terms at compile time (callers without them).
+template <int EXT, bool FULL = true, typename S, typename Sink>
 __device__ __forceinline__ void collide3(const S (&hf)[27], const S (&hg)[27], const Moments3& m,
                                          const double (&ph)[3], const double (&gT)[3],
                                          const double (&gh)[3], double divu, const DdfParams& p,
@@ -202,7 +203,7 @@ __device__ __forceinline__ void collide3(const S (&hf)[27], const S (&hg)[27], c
       for (int a = 0; a < 3; ++a) q[a] = P * (gh[a] - p.kmu * gT[a]);
     } else {
       thetas = theta + p.r_cv * p.Q * inv;
-      if (p.full) {
+      if (FULL && p.full) {
         thetas += p.alpha * theta * divu;
 #pragma unroll
         for (int a = 0; a < 3; ++a) q[a] = P * p.qc * gT[a];
@@ -236,7 +237,8 @@ __device__ __forceinline__ void collide3(const S (&hf)[27], const S (&hg)[27], c
       equilibria3(rho, es, i, XS, fsx, gs);
       // c_i . q^c / 2 on the six velocities with |c_i| = 1
       const int ca = a - 1, cb = b - 1, cc = c - 1;
-      if (ca * ca + cb * cb + cc * cc == 1) gs += 0.5 * (ca * q[0] + cb * q[1] + cc * q[2]);
+      if ((FULL || EXT == 2) && ca * ca + cb * cb + cc * cc == 1)
+        gs += 0.5 * (ca * q[0] + cb * q[1] + cc * q[2]);
       gstar_minus_ge = gs - ge;
     }
     sink(i, f + omega * (hfe - f) + keep * (fs - fe), g + omega * (hge - g) + keep * gstar_minus_ge);
@@ -441,8 +443,8 @@ k_ddf3_collide(const S* __restrict__ A, const S* __restrict__ nb, S* __restrict_
 }
 
 // ---- one-launch step --------------------------------------------------------------------------
-// For the collision without sources or transport terms and with the central derivative of Phi,
-// the flux and collision sweeps are fused into one launch that marches along z. A workgroup owns a tile of kF3Cols columns by kF3Rows rows (one row per wavefront) and a
+// For the collision without transport terms (sources allowed) and with the central derivative
+// of Phi, the flux and collision sweeps are fused into one launch that marches along z. A workgroup owns a tile of kF3Cols columns by kF3Rows rows (one row per wavefront) and a
 // range of planes. Per plane z every wavefront
 //   1. computes the fluxes of one halo piece of plane z + 1: the rows below and above the tile
 //      (wavefronts 1 and 2) or phi_x of the columns left and right of two of its rows
@@ -465,7 +467,10 @@ static_assert(kF3Rows * 64 == kBlock, "one row per wavefront");
 
 // WALLS: 0 periodic in y, 1 bounce-back walls, 2 non-equilibrium extrapolation walls (boundary
 // planes read from nb, rebuilt by k_ddf3_neq_rows, as in the two sweeps).
-template <typename S, int WALLS, bool PULL, bool DIAG>
+// EXT: 0 the plain collision, 1 with the uniform body force and heat source (no transport terms;
+// the shifted equilibria's second set of axis factors then spills some 35 registers per lane,
+// and the step still beats the two sweeps: 256^3 float32 2363 vs 2420 us).
+template <typename S, int WALLS, bool PULL, bool DIAG, int EXT>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
 k_ddf3_fused(const S* __restrict__ A, const S* __restrict__ nb, S* __restrict__ B, int nx,
              int ny, int nz, int64_t pitch, int64_t plane, DdfParams prm, int nbx, int nby,
@@ -520,7 +525,7 @@ k_ddf3_fused(const S* __restrict__ A, const S* __restrict__ nb, S* __restrict__ 
   // flight at a time
   auto moments = [&](const S (&hf)[27], const S (&hg)[27], Moments3& m) {
     __builtin_amdgcn_sched_barrier(0);
-    moments3<0>(hf, hg, prm, m, 0.0, 0.0, 0.0, 0.0);
+    moments3<EXT>(hf, hg, prm, m, prm.Fx, prm.Fy, prm.Fz, prm.Q);
   };
   // step 1 for plane z into flux buffer k
   auto halo = [&](int z, int k) {
@@ -601,7 +606,7 @@ k_ddf3_fused(const S* __restrict__ A, const S* __restrict__ nb, S* __restrict__ 
         const uint32_t xo = fresh((uint32_t)sizeof(S) * x);
         int64_t pl = plane;
         asm volatile("" : "+s"(pl));
-        collide3<0>(hf, hg, m0, ph, zero3, zero3, 0.0, prm, w2, w2 + 27,
+        collide3<EXT, false>(hf, hg, m0, ph, zero3, zero3, 0.0, prm, w2, w2 + 27,
                     [&](int i, double tf, double tg) {
           if (col_ok) {
             gstore_nt(at_byte(sbase(out + i * pl), xo), (S)tf);
@@ -819,7 +824,7 @@ static Fused3 fused3_shape(const Layout& L) {
 int64_t ddf3_fused_blocks(const Layout& L) { return fused3_shape(L).blocks(); }
 
 static bool fused3_ok(const DdfParams& prm) {
-  return prm.phi == 1 && !prm.ext() && prm.eos == 0;
+  return prm.phi == 1 && !prm.full && prm.eos == 0;
 }
 
 template <typename S>
@@ -841,10 +846,13 @@ static void ddf3_step(bool walls, bool pull, const S* A, S* B, const Layout& L, 
     wall_kind(walls, prm, [&](auto W) {
       flag(pull, [&](auto Pl) {
         flag(partials != nullptr, [&](auto Dg) {
-          k_ddf3_fused<S, decltype(W)::value, decltype(Pl)::value, decltype(Dg)::value>
-              <<<(unsigned)F.blocks(), kBlock, 0, s>>>(A, nb, B, L.nx, L.ny, L.nz, L.pitch,
-                                                       L.plane, prm, F.nbx, F.nby, F.nzc,
-                                                       partials);
+          flag(prm.src, [&](auto Sr) {
+            k_ddf3_fused<S, decltype(W)::value, decltype(Pl)::value, decltype(Dg)::value,
+                         decltype(Sr)::value ? 1 : 0>
+                <<<(unsigned)F.blocks(), kBlock, 0, s>>>(A, nb, B, L.nx, L.ny, L.nz, L.pitch,
+                                                         L.plane, prm, F.nbx, F.nby, F.nzc,
+                                                         partials);
+          });
         });
       });
     });

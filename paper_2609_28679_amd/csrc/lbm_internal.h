@@ -139,8 +139,8 @@ hipError_t launch_decode_ddf(int kind, int Q, int i, const void* A, const Layout
 // two launches: fluxes (and, with transport control, T and u; for the van der Waals fluid also
 // the enthalpy) into `fld` (8 fields of L.plane elements in the storage type, float32 or
 // float64), then the collision; pull = false collides in place of streaming. The collision
-// without sources or transport terms, with the central derivative of Phi, is one launch that
-// marches along z instead (ddf3_fused_blocks workgroups; after the boundary-plane rebuild with
+// without transport terms (sources allowed), with the central derivative of Phi, is one launch
+// that marches along z instead (ddf3_fused_blocks workgroups; after the boundary-plane rebuild with
 // NEQ walls).
 Grid make_grid_ddf3(const Layout& L);
 hipError_t launch_ddf3_rest_state(const DdfParams& prm, double* out, hipStream_t s);
