@@ -43,11 +43,14 @@ def _run(rho, u, T, steps, storage, tau=0.7, **kw):
     return r, v, t, tot, f, g
 
 
+# 0: plain; 1: sources and transport terms (the two launches); 2: sources only (with central
+# Phi the one-launch step, which drops the transport terms at compile time)
 EXTRA = [dict(), dict(force=(1e-4, -2e-4, 1e-4), heat_source=1e-4, prandtl=0.71,
-                      eta_over_mu=1.5)]
+                      eta_over_mu=1.5),
+         dict(force=(1e-4, -2e-4, 1e-4), heat_source=1e-4)]
 
 
-@pytest.mark.parametrize("extra", [0, 1])
+@pytest.mark.parametrize("extra", [0, 1, 2])
 @pytest.mark.parametrize("phi", [1, 2, 0])
 @pytest.mark.parametrize("walls", [True, False])
 def test_fp64_matches_oracle(walls, phi, extra):
