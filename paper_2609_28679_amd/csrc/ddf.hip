@@ -628,10 +628,23 @@ k_ddf_neq_rows(const S* __restrict__ A, int nx, int ny, int64_t pitch, int64_t p
   }
 }
 
+// Rows per workgroup of the extended collisions (sources, transport control, van der Waals):
+// their longer per-row arithmetic favours taller windows than the plain step's. Measured at
+// 4096^2 with walls, central Phi, float32 (4 / 6 / 8 / 10 rows): sources 618 / 589 / 582 /
+// 583 us, Pr 0.71 646 / 613 / 601 / 599, van der Waals 719 / 673 / 649 / 644; the plain and NEQ
+// steps keep their 4 (552 / 568 at 6 and 561 / 580).
+constexpr int kDdfExtRows = 8;
+
 hipError_t launch_ddf(int fmt, bool walls, bool pull, const void* A, void* B, const Layout& L,
-                      const Grid& G, const DdfParams& prm, float s_enc, float s_dec,
-                      double* partials, void* nb, hipStream_t s) {
+                      const Grid& G0, const DdfParams& prm, float s_enc, float s_dec,
+                      double* partials, void* nb, int* records, hipStream_t s) {
   if (prm.ext() && fmt >= 2) return hipErrorInvalidValue;  // no extended path with reduced storage
+  Grid G = G0;
+  if (fmt < 2 && (prm.ext() || prm.eos) && G.rows < kDdfExtRows) {
+    G.rows = kDdfExtRows;
+    fit_rows(G, L.ny);
+  }
+  if (records) *records = G.blocks();
   if (prm.neq) {
     if (fmt >= 2 || !walls || !nb || L.ny < 3 || prm.src) return hipErrorInvalidValue;
     dim3 grid((L.nx + kBlock - 1) / kBlock, 2);

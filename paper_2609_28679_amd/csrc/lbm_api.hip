@@ -494,7 +494,7 @@ int lbm_create(const lbm_params* p, const double* rho0, const double* u0, const 
     }
     if (P.D == 2) {
       if (e == hipSuccess) e = launch_init_ddf(c->fmt, c->readout, c->readout + nodes, d_T0, c->B, c->L, c->dp, c->stream);
-      if (e == hipSuccess) e = launch_ddf(c->fmt, p->wall_y != 0, false, c->B, c->A, c->L, c->G, c->dp, c->s_enc, c->s_dec, nullptr, c->nb, c->stream);
+      if (e == hipSuccess) e = launch_ddf(c->fmt, p->wall_y != 0, false, c->B, c->A, c->L, c->G, c->dp, c->s_enc, c->s_dec, nullptr, c->nb, nullptr, c->stream);
     } else {
       if (e == hipSuccess) e = launch_init_ddf3(c->kind, c->readout, c->readout + nodes, d_T0, c->B, c->L, c->dp, c->stream);
       if (e == hipSuccess) e = launch_ddf3(c->kind, p->wall_y != 0, false, c->B, c->A, c->L, c->G, c->dp, c->fld, c->nb, nullptr, nullptr, c->stream);
@@ -530,7 +530,7 @@ int lbm_step(lbm_ctx* c, int64_t n) {
     } else if (c->ddf && c->D == 3)
       e = launch_ddf3(c->kind, c->p.wall_y != 0, true, c->A, c->B, c->L, c->G, c->dp, c->fld, c->nb, part, &records, c->stream);
     else if (c->ddf)
-      e = launch_ddf(c->fmt, c->p.wall_y != 0, true, c->A, c->B, c->L, c->G, c->dp, c->s_enc, c->s_dec, part, c->nb, c->stream);
+      e = launch_ddf(c->fmt, c->p.wall_y != 0, true, c->A, c->B, c->L, c->G, c->dp, c->s_enc, c->s_dec, part, c->nb, &records, c->stream);
     else if (c->codec >= 0)
       e = launch_bgk_d2q9_red(c->codec, c->A, c->B, c->L, c->G, c->omega, c->p.wall_y != 0, c->s_enc, c->s_dec, part, c->stream);
     else if (c->aa && c->D == 2)

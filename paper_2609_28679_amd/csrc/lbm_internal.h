@@ -126,9 +126,11 @@ Grid make_grid_ddf(const Layout& L, int halo, bool reduced);
 hipError_t launch_ddf_rest_state(const DdfParams& prm, double* out, hipStream_t s);
 // nb: boundary-row buffer of the non-equilibrium extrapolation walls (2 x 18 rows of `pitch`
 // storage elements; used when prm.neq, NULL otherwise).
+// records: set to the number of per-workgroup diagnostics records the step writes to partials
+// (at most G.blocks(); may be NULL).
 hipError_t launch_ddf(int fmt, bool walls, bool pull, const void* A, void* B, const Layout& L,
                       const Grid& G, const DdfParams& prm, float s_enc, float s_dec,
-                      double* partials, void* nb, hipStream_t s);
+                      double* partials, void* nb, int* records, hipStream_t s);
 hipError_t launch_init_ddf(int kind, const double* rho, const double* u, const double* T,
                            void* A, const Layout& L, const DdfParams& prm, hipStream_t s);
 hipError_t launch_moments_ddf(int kind, const void* A, const Layout& L, const DdfParams& prm,
