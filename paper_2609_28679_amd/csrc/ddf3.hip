@@ -24,6 +24,7 @@
 // bounce-back or NEQ extrapolation; x and z periodic. Arithmetic is float64.
 #include "ddf_common.h"
 
+#include <cstdlib>
 #include <type_traits>
 
 namespace lbm {
@@ -443,9 +444,10 @@ k_ddf3_collide(const S* __restrict__ A, const S* __restrict__ nb, S* __restrict_
 }
 
 // ---- one-launch step --------------------------------------------------------------------------
-// For the collision without transport terms (sources allowed) and with the central derivative
-// of Phi, the flux and collision sweeps are fused into one launch that marches along z. A workgroup owns a tile of kF3Cols columns by kF3Rows rows (one row per wavefront) and a
-// range of planes. Per plane z every wavefront
+// For the collision without transport terms (sources and NEQ walls allowed) and with the
+// central derivative of Phi, the flux and collision sweeps are fused into one launch that
+// marches along z. A workgroup owns a tile of kF3Cols columns by kF3Rows rows (one row per
+// wavefront) and a range of planes. Per plane z every wavefront
 //   1. computes the fluxes of one halo piece of plane z + 1: the rows below and above the tile
 //      (wavefronts 1 and 2) or phi_x of the columns left and right of two of its rows
 //      (wavefronts 0 and 3, one node per lane);
@@ -717,6 +719,9 @@ hipError_t launch_moments_ddf3(int kind, const void* A, const Layout& L, const D
 Grid make_grid_ddf3(const Layout& L) {
   Grid G = make_grid(L);
   if (G.rows < 2) G.rows = 2;
+#ifdef LBM_TUNING_ENV
+  if (const char* v = getenv("LBM_DDF3_ROWS")) G.rows = atoi(v);
+#endif
   fit_rows(G, (int64_t)L.ny * L.nz);
   return G;
 }
@@ -821,14 +826,26 @@ static Fused3 fused3_shape(const Layout& L) {
   return F;
 }
 
-int64_t ddf3_fused_blocks(const Layout& L) { return fused3_shape(L).blocks(); }
+// The upwind collision sweep takes one row per workgroup (256^3 float32 with upwind Phi: 1 row
+// 2080 us, 2 rows 2151, 4 rows 2170; the transport-control and van der Waals sweeps are even
+// between 2 and 4 rows and keep the plan's).
+static Grid upwind3_grid(const Layout& L, const Grid& G) {
+  Grid U = G;
+  U.rows = 1;
+  fit_rows(U, (int64_t)L.ny * L.nz);
+  return U;
+}
+
+int64_t ddf3_max_records(const Layout& L, const Grid& G) {
+  return std::max<int64_t>(fused3_shape(L).blocks(), upwind3_grid(L, G).blocks());
+}
 
 static bool fused3_ok(const DdfParams& prm) {
   return prm.phi == 1 && !prm.full && prm.eos == 0;
 }
 
 template <typename S>
-static void ddf3_step(bool walls, bool pull, const S* A, S* B, const Layout& L, const Grid& G,
+static void ddf3_step(bool walls, bool pull, const S* A, S* B, const Layout& L, const Grid& G0,
                       const DdfParams& prm, double* fld64, S* nb, double* partials,
                       int* records, hipStream_t s) {
   if (walls && prm.neq) {
@@ -858,8 +875,9 @@ static void ddf3_step(bool walls, bool pull, const S* A, S* B, const Layout& L, 
     });
     return;
   }
-  *records = G.blocks();
-  dim3 grid(G.nbx, G.nby), block(G.bx);
+  const Grid Gs = prm.phi == 2 ? upwind3_grid(L, G0) : G0;
+  *records = Gs.blocks();
+  dim3 grid(Gs.nbx, Gs.nby), block(Gs.bx);
   S* fld = reinterpret_cast<S*>(fld64);  // 8 planes of the storage type
   wall_kind(walls, prm, [&](auto W) {
     flag(pull, [&](auto Pl) {
@@ -870,15 +888,15 @@ static void ddf3_step(bool walls, bool pull, const S* A, S* B, const Layout& L, 
           // the fields are read only for Phi and for transport control
           if (prm.phi || (e && prm.full))
             k_ddf3_flux<S, w, pl, e><<<grid, block, 0, s>>>(A, nb, L.nx, L.ny, L.nz, L.pitch,
-                                                            L.plane, prm, G.rows, fld);
+                                                            L.plane, prm, Gs.rows, fld);
           flag(partials != nullptr, [&](auto Dg) {
             constexpr bool dg = decltype(Dg)::value;
             if (prm.phi == 2)
               k_ddf3_collide<S, 2, w, pl, dg, e><<<grid, block, 0, s>>>(
-                  A, nb, B, L.nx, L.ny, L.nz, L.pitch, L.plane, prm, fld, G.rows, partials);
+                  A, nb, B, L.nx, L.ny, L.nz, L.pitch, L.plane, prm, fld, Gs.rows, partials);
             else
               k_ddf3_collide<S, 1, w, pl, dg, e><<<grid, block, 0, s>>>(
-                  A, nb, B, L.nx, L.ny, L.nz, L.pitch, L.plane, prm, fld, G.rows, partials);
+                  A, nb, B, L.nx, L.ny, L.nz, L.pitch, L.plane, prm, fld, Gs.rows, partials);
           });
         }
       });

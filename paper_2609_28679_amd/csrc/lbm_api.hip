@@ -251,8 +251,8 @@ void make_plan(const lbm_params* p, Plan& P) {
   else
     P.G = make_grid(P.L);
   P.partial_slots = std::max(P.G.blocks(), 1024);
-  if (P.ddf && P.D == 3)  // the one-launch step writes one record per workgroup
-    P.partial_slots = (int)std::max<int64_t>(P.partial_slots, ddf3_fused_blocks(P.L));
+  if (P.ddf && P.D == 3)  // the one-launch step and the upwind sweeps have their own grids
+    P.partial_slots = (int)std::max<int64_t>(P.partial_slots, ddf3_max_records(P.L, P.G));
   // One in-place buffer where supported and either requested or small enough to profit from
   // the 256 MB last-level cache. Measured float32 D2Q9 step times (one vs two buffers): 44 vs
   // 51 us at 151 MB per buffer, 122 vs 131 us at 340 MB, equal at 399 MB, 235 vs 209 us at

@@ -142,8 +142,7 @@ hipError_t launch_decode_ddf(int kind, int Q, int i, const void* A, const Layout
 // the enthalpy) into `fld` (8 fields of L.plane elements in the storage type, float32 or
 // float64), then the collision; pull = false collides in place of streaming. The collision
 // without transport terms (sources allowed), with the central derivative of Phi, is one launch
-// that marches along z instead (ddf3_fused_blocks workgroups; after the boundary-plane rebuild with
-// NEQ walls).
+// that marches along z instead (after the boundary-plane rebuild with NEQ walls).
 Grid make_grid_ddf3(const Layout& L);
 hipError_t launch_ddf3_rest_state(const DdfParams& prm, double* out, hipStream_t s);
 hipError_t launch_init_ddf3(int kind, const double* rho, const double* u, const double* T,
@@ -155,7 +154,8 @@ hipError_t launch_init_ddf3(int kind, const double* rho, const double* u, const 
 hipError_t launch_ddf3(int kind, bool walls, bool pull, const void* A, void* B, const Layout& L,
                        const Grid& G, const DdfParams& prm, double* fld, void* nb,
                        double* partials, int* records, hipStream_t s);
-int64_t ddf3_fused_blocks(const Layout& L);
+// Most diagnostics records any D3Q27 double-distribution step writes (grid G of the plan).
+int64_t ddf3_max_records(const Layout& L, const Grid& G);
 hipError_t launch_moments_ddf3(int kind, const void* A, const Layout& L, const DdfParams& prm,
                                double* rho, double* u, double* T, double* edens, hipStream_t s);
 // Reduced storage (D2Q9 isothermal): 3 float32 moment planes then 6 uint16 planes.

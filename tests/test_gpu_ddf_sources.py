@@ -156,14 +156,16 @@ def test_sources_changed_between_steps():
     lat.close()
 
 
+@pytest.mark.parametrize("phi", [1, 2])
 @pytest.mark.parametrize("lattice", ["D2Q9", "D3Q27"])
-def test_diagnostics_across_source_switches(lattice):
+def test_diagnostics_across_source_switches(lattice, phi):
     # a force and heat source change momentum and energy but conserve mass exactly; switching
     # them on and off between steps moves the step between launch shapes (D2Q9: taller rows on
-    # the extended path; D3Q27: the one-launch step with and without sources), which write
+    # the extended path; D3Q27: the one-launch step with and without sources, or with upwind
+    # Phi the two sweeps on one row per workgroup, twice the plan's records), which write
     # different numbers of diagnostics records. The history's mass is the oracle's at every
     # recorded step only if each step's records alone are summed.
-    announce("DDF fp64 %s diagnostics with sources switched on and off" % lattice)
+    announce("DDF fp64 %s phi=%d diagnostics with sources switched on and off" % (lattice, phi))
     if lattice == "D2Q9":
         rho, u, T = _random_fields(37, 70, seed=8)
         shape = (37, 70)
@@ -175,7 +177,7 @@ def test_diagnostics_across_source_switches(lattice):
         u = 0.02 * rng.standard_normal((3,) + shape)
     zero = (0.0,) * (2 if lattice == "D2Q9" else 3)
     on = (1e-4, -2e-4) if lattice == "D2Q9" else (1e-4, -2e-4, 5e-5)
-    lat = _lattice(rho, u, T, lattice=lattice, tau=0.7, wall_y=False, phi=1, storage="fp64",
+    lat = _lattice(rho, u, T, lattice=lattice, tau=0.7, wall_y=False, phi=phi, storage="fp64",
                    diag_every=2)
     m0 = lat.moments()[3][0]
     for F, Q in [(zero, 0.0), (on, 2e-4), (zero, 0.0), (on, -1e-4)]:
