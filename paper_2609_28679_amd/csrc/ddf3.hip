@@ -175,7 +175,8 @@ __device__ __forceinline__ void equilibria3(double rho, double e, int i, const A
 // gT[a] = dT/da and divu = div u (used only when p.full), gh[a] = dh/da of the enthalpy
 // h = e + P/rho (van der Waals only); sink(i, f~ - w, g~ - v). EXT: 0 without sources and
 // transport terms, 1 with them (ideal gas), 2 the van der Waals fluid (gamma - 1, alpha and
-// q^c = P (grad h - (k/mu) grad T) per node).
+// q^c = P (grad h - (k/mu) grad T) per node). sink(k, value): post-collision population k,
+// shifted (k < 27: f~_k - w_k, else g~_{k-27} - v_{k-27}).
 // FULL = false drops the transport terms at compile time (callers without them).
 template <int EXT, bool FULL = true, typename S, typename Sink>
 __device__ __forceinline__ void collide3(const S (&hf)[27], const S (&hg)[27], const Moments3& m,
@@ -224,14 +225,25 @@ __device__ __forceinline__ void collide3(const S (&hf)[27], const S (&hg)[27], c
   }
   const double omega = 2.0 * P / (2.0 * p.mu + P);  // 2 beta, beta = 1/(2 tau + 1), tau = mu/P
   const double keep = 1.0 - 0.5 * omega;            // 1 - beta
+  // all f first, then all g (the same arithmetic per value): fewer values are live at once
+  // than with f_i and g_i together
 #pragma unroll
   for (int i = 0; i < 27; ++i) {
     const int a = i % 3, b = (i / 3) % 3, c = i / 9;
     double fe, ge;
     equilibria3(rho, e, i, X, fe, ge);
-    const double hfe = fe - wf[i], hge = ge - wg[i];
-    const double f = (double)hf[i], g = (double)hg[i];
+    const double hfe = fe - wf[i];
+    const double f = (double)hf[i];
     const double fs = rho * (s[0][a] * s[1][b] * s[2][c]);
+    sink(i, f + omega * (hfe - f) + keep * (fs - fe));
+  }
+#pragma unroll
+  for (int i = 0; i < 27; ++i) {
+    const int a = i % 3, b = (i / 3) % 3, c = i / 9;
+    double fe, ge;
+    equilibria3(rho, e, i, X, fe, ge);
+    const double hge = ge - wg[i];
+    const double g = (double)hg[i];
     double gstar_minus_ge = 0.0;
     if (EXT) {
       double gs, fsx;
@@ -242,7 +254,7 @@ __device__ __forceinline__ void collide3(const S (&hf)[27], const S (&hg)[27], c
         gs += 0.5 * (ca * q[0] + cb * q[1] + cc * q[2]);
       gstar_minus_ge = gs - ge;
     }
-    sink(i, f + omega * (hfe - f) + keep * (fs - fe), g + omega * (hge - g) + keep * gstar_minus_ge);
+    sink(27 + i, g + omega * (hge - g) + keep * gstar_minus_ge);
   }
 }
 
@@ -419,17 +431,11 @@ k_ddf3_collide(const S* __restrict__ A, const S* __restrict__ nb, S* __restrict_
         int64_t pl = plane;
         asm volatile("" : "+s"(pl));
         collide3<EXT>(hf, hg, m, ph, gT, gh, divu, prm, w2, kLean ? w2 + 27 : prm.wg,
-                      [&](int i, double tf, double tg) {
-          gstore_nt(at_byte(sbase(out + i * pl), xo), (S)tf);
-          gstore_nt(at_byte(sbase(out + (27 + i) * pl), xo), (S)tg);
-        });
+                      [&](int k, double t) { gstore_nt(at_byte(sbase(out + k * pl), xo), (S)t); });
       } else {
         S* out = B + off;
         collide3<EXT>(hf, hg, m, ph, gT, gh, divu, prm, w2, prm.wg,
-                      [&](int i, double tf, double tg) {
-          store_nt(out + i * plane, (S)tf);
-          store_nt(out + (27 + i) * plane, (S)tg);
-        });
+                      [&](int k, double t) { store_nt(out + k * plane, (S)t); });
       }
       if (DIAG) {
         acc[0] += m.rho;
@@ -470,8 +476,8 @@ static_assert(kF3Rows * 64 == kBlock, "one row per wavefront");
 // WALLS: 0 periodic in y, 1 bounce-back walls, 2 non-equilibrium extrapolation walls (boundary
 // planes read from nb, rebuilt by k_ddf3_neq_rows, as in the two sweeps).
 // EXT: 0 the plain collision, 1 with the uniform body force and heat source (no transport terms;
-// the shifted equilibria's second set of axis factors then spills some 35 registers per lane,
-// and the step still beats the two sweeps: 256^3 float32 2363 vs 2420 us).
+// the shifted equilibria's second set of axis factors then spills some 20 registers per lane,
+// and the step still beats the two sweeps: 256^3 float32 about 2000 vs 2420 us).
 template <typename S, int WALLS, bool PULL, bool DIAG, int EXT>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
 k_ddf3_fused(const S* __restrict__ A, const S* __restrict__ nb, S* __restrict__ B, int nx,
@@ -609,11 +615,8 @@ k_ddf3_fused(const S* __restrict__ A, const S* __restrict__ nb, S* __restrict__ 
         int64_t pl = plane;
         asm volatile("" : "+s"(pl));
         collide3<EXT, false>(hf, hg, m0, ph, zero3, zero3, 0.0, prm, w2, w2 + 27,
-                    [&](int i, double tf, double tg) {
-          if (col_ok) {
-            gstore_nt(at_byte(sbase(out + i * pl), xo), (S)tf);
-            gstore_nt(at_byte(sbase(out + (27 + i) * pl), xo), (S)tg);
-          }
+                             [&](int k, double t) {
+          if (col_ok) gstore_nt(at_byte(sbase(out + k * pl), xo), (S)t);
         });
         if (DIAG && col_ok) {
           acc[0] += m0.rho;
