@@ -381,13 +381,13 @@ def main():
                                            lattice="D3Q27", model="ddf", tau=0.6, phi=1,
                                            prandtl=0.71, eta_over_mu=1.0),
                 max(50, vs // 20), 5, 432,
-                {"phi": "central", "launches": "2 per step (fluxes, collision)",
+                {"phi": "central", "launches": "1 per step (fluxes and collision, marching in z)",
                  "transport": "Pr 0.71 (heat flux q^c), eta/mu 1 (alpha theta div u)"})),
             ("d3q27_ddf_fp32_256_vdw", lambda n: variant(
                 n, lambda: binding.Lattice(*vdw_tgv3(), lattice="D3Q27", model="ddf", tau=0.6,
                                            phi=1, vdw=(0.27, 0.2)),
                 max(50, vs // 20), 5, 432,
-                {"phi": "central", "launches": "2 per step (fluxes, collision)",
+                {"phi": "central", "launches": "1 per step (fluxes and collision, marching in z)",
                  "eos": "van der Waals a = 0.27, b = 0.2, rho 1, T 1.4"})),
             ("d3q27_ddf_fp32_256_neq_walls", lambda n: variant(
                 n, lambda: binding.Lattice(*inputs.thermal_taylor_green_3d(256, 0.05),

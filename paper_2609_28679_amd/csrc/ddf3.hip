@@ -3,7 +3,9 @@
 // van der Waals fluid (Sec. III C), with the optional body force, heat source and transport
 // control of the D2Q9 kernel (ddf.hip).
 //
-// Two launches per step (three with NEQ walls):
+// With the central derivative of Phi one launch per step, k_ddf3_fused (below), marches along z
+// and computes the fluxes and the collision together (after k_ddf3_neq_rows with NEQ walls).
+// With the upwind derivative, or without Phi, two launches per step (three with NEQ walls):
 //   k_ddf3_neq_rows rebuilds the pre-collision populations of the boundary planes y = 0 and
 //                   y = ny - 1 of the non-equilibrium extrapolation walls (App. B) into a side
 //                   buffer;
@@ -15,9 +17,9 @@
 //                   finite-difference derivatives of the neighbours' fields (central, or the
 //                   upwind-biased stencil for phi), collides and stores.
 // The second pull re-reads what the first one read: 432 B of populations per node in float32
-// are read twice, so the pair moves about 1.5x the algorithmic traffic of one fused sweep.
-// The D2Q9 kernel avoids the re-read by exchanging the moments of a workgroup's row through
-// LDS; in 3D a node's derivative stencil spans three planes, which a one-row tile cannot hold.
+// are read twice, so the pair moves about 1.5x the algorithmic traffic of one fused sweep; the
+// one-launch step avoids that with a plane ring (the upwind stencil would need two planes of
+// ring and of halo each way).
 //
 // Storage: 54 planes, f_i - w_i (i < 27) then g_i - v_i, with w, v the equilibria at rest at
 // rho = 1, T = 1; i = (cx+1) + 3(cy+1) + 9(cz+1), opposite 26 - i. Walls in y: half-way
@@ -450,9 +452,9 @@ k_ddf3_collide(const S* __restrict__ A, const S* __restrict__ nb, S* __restrict_
 }
 
 // ---- one-launch step --------------------------------------------------------------------------
-// For the collision without transport terms (sources and NEQ walls allowed) and with the
-// central derivative of Phi, the flux and collision sweeps are fused into one launch that
-// marches along z. A workgroup owns a tile of kF3Cols columns by kF3Rows rows (one row per
+// With the central derivative of Phi (any collision: sources, transport control, the van der
+// Waals fluid, NEQ walls), the flux and collision sweeps are fused into one launch that marches
+// along z. A workgroup owns a tile of kF3Cols columns by kF3Rows rows (one row per
 // wavefront) and a range of planes. Per plane z every wavefront
 //   1. computes the fluxes of one halo piece of plane z + 1: the rows below and above the tile
 //      (wavefronts 1 and 2) or phi_x of the columns left and right of two of its rows
@@ -465,8 +467,8 @@ k_ddf3_collide(const S* __restrict__ A, const S* __restrict__ nb, S* __restrict_
 // collision arithmetic is spread over all four SIMDs of a compute unit. phi_x and phi_y go to
 // two LDS buffers (planes z, z + 1), phi_z to a ring of three registers per column. float64
 // populations do not fit in LDS for two workgroups per compute unit and are pulled again at
-// step 3, from the caches. Fluxes are rounded to the storage type as the two-sweep field stores
-// them, so both paths give identical results. Traffic: the populations are read from memory
+// step 3, from the caches. Fluxes and fields are rounded to the storage type as the two-sweep
+// fields store them, so both paths give identical results. Traffic: the populations are read from memory
 // once and written once per node (432 B in float32), against about 1.5x that for two sweeps.
 constexpr int kF3Cols = 64;                // columns per tile (one wavefront row)
 constexpr int kF3Rows = 4;                 // rows per tile = wavefronts per workgroup
@@ -475,20 +477,31 @@ static_assert(kF3Rows * 64 == kBlock, "one row per wavefront");
 
 // WALLS: 0 periodic in y, 1 bounce-back walls, 2 non-equilibrium extrapolation walls (boundary
 // planes read from nb, rebuilt by k_ddf3_neq_rows, as in the two sweeps).
-// EXT: 0 the plain collision, 1 with the uniform body force and heat source (no transport terms;
-// the shifted equilibria's second set of axis factors then spills some 20 registers per lane,
-// and the step still beats the two sweeps: 256^3 float32 about 2000 vs 2420 us).
-template <typename S, int WALLS, bool PULL, bool DIAG, int EXT>
+// EXT: 0 the plain collision, 1 the ideal gas with the uniform body force and heat source and,
+// with TR, transport control (Prandtl number, bulk viscosity), 2 the van der Waals fluid (TR).
+// TR: the transport terms, whose fields T, u_a (and for the van der Waals fluid the enthalpy h)
+// are exchanged like the fluxes: x neighbours through LDS with the halo columns, y neighbours
+// through LDS with the halo rows, z neighbours in a register ring. The shifted equilibria's
+// second set of axis factors spills some 20 registers per lane (with TR about 30), and the step
+// still beats the two sweeps (256^3 float32: sources about 2000 vs 2420 us, Pr 0.71 2110 vs
+// 2645 us, van der Waals 2090 vs 2742 us).
+// Fluxes and fields are kept in the storage type, as the two-sweep fields are.
+template <typename S, int WALLS, bool PULL, bool DIAG, int EXT, bool TR>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
 k_ddf3_fused(const S* __restrict__ A, const S* __restrict__ nb, S* __restrict__ B, int nx,
              int ny, int nz, int64_t pitch, int64_t plane, DdfParams prm, int nbx, int nby,
              int nzc, double* __restrict__ partials) {
   constexpr bool kLds = sizeof(S) == 4;  // populations kept in LDS between pull and collision
   constexpr int NR = kLds ? kF3Rows : 1, NQ = kLds ? 54 : 1;
+  // fields: 0 T, 1 u along the exchange axis, 2 h (van der Waals)
+  constexpr int NF = TR ? (EXT == 2 ? 3 : 2) : 1;
+  constexpr int FR = TR ? kF3Rows : 1, FC = TR ? kF3Cols : 1;
   __shared__ RestShift rs;
-  __shared__ double s_px[2][kF3Rows][kF3Cols + 2];   // phi_x of the tile rows, slot column + 1
-  __shared__ double s_py[2][kF3Rows + 2][kF3Cols];   // phi_y of rows y0 - 1 .. y0 + kF3Rows
-  __shared__ S s_pop[NR][NQ][kF3Cols];               // each wavefront's row of one plane
+  __shared__ S s_px[2][kF3Rows][kF3Cols + 2];   // phi_x of the tile rows, slot column + 1
+  __shared__ S s_py[2][kF3Rows + 2][kF3Cols];   // phi_y of rows y0 - 1 .. y0 + kF3Rows
+  __shared__ S s_pop[NR][NQ][kF3Cols];          // each wavefront's row of one plane
+  __shared__ S s_fx[2][NF][FR][FC + 2];         // T, u_x (, h) like phi_x
+  __shared__ S s_fy[2][NF][FR + 2][FC];         // T, u_y (, h) like phi_y
   rs.fill(prm);
   const int T = nbx * nby;
   const int b = xcd_tile(blockIdx.x, gridDim.x);
@@ -526,7 +539,14 @@ k_ddf3_fused(const S* __restrict__ A, const S* __restrict__ nb, S* __restrict__ 
   const int pxslot = hs ? ncols + 1 : 0;
   auto wrapz = [&](int z) { return z < 0 ? z + nz : (z >= nz ? z - nz : z); };
   auto phi_of = [](const Moments3& m, int a) {
-    return (double)(S)(m.rho * m.u[a] * (m.u[a] * m.u[a] + 3.0 * (m.theta - 1.0 / 3.0)));
+    return (S)(m.rho * m.u[a] * (m.u[a] * m.u[a] + 3.0 * (m.theta - 1.0 / 3.0)));
+  };
+  // field f of the node along axis a (0 T, 1 u_a, 2 h), in the storage type as the two-sweep
+  // fields store it
+  auto field = [&](const Moments3& m, int f, int a) -> S {
+    if (f == 0) return (S)(EXT == 2 ? (m.e + prm.va * m.rho) / prm.cv : m.theta * prm.inv_R);
+    if (f == 1) return (S)m.u[a];
+    return (S)(m.e + m.theta);
   };
   // all 54 loads of a pull are issued before the sums start: without the scheduling barrier
   // the compiler moves each load next to its single use and waits for it there, one load in
@@ -542,22 +562,46 @@ k_ddf3_fused(const S* __restrict__ A, const S* __restrict__ nb, S* __restrict__ 
     if (hrow) {
       node_pops<S, WALLS, PULL, true>(A, nb, plane, nx, ny, nz, pitch, x, yr, wrapz(z), hf, hg);
       moments(hf, hg, m);
-      if (col_ok) s_py[k][pyslot][lane] = phi_of(m, 1);
+      if (col_ok) {
+        s_py[k][pyslot][lane] = phi_of(m, 1);
+        if constexpr (TR) {
+#pragma unroll
+          for (int f = 0; f < NF; ++f) s_fy[k][f][pyslot][lane] = field(m, f, 1);
+        }
+      }
     } else {
       node_pops<S, WALLS, PULL, false>(A, nb, plane, nx, ny, nz, pitch, xx, yx, wrapz(z), hf, hg);
       moments(hf, hg, m);
-      if (hx_ok) s_px[k][hr0 + hk][pxslot] = phi_of(m, 0);
+      if (hx_ok) {
+        s_px[k][hr0 + hk][pxslot] = phi_of(m, 0);
+        if constexpr (TR) {
+#pragma unroll
+          for (int f = 0; f < NF; ++f) s_fx[k][f][hr0 + hk][pxslot] = field(m, f, 0);
+        }
+      }
     }
   };
-  // step 2 for plane z into flux buffer k: own row pulled into hf, hg; returns phi_z
-  auto own = [&](int z, int k, S (&hf)[27], S (&hg)[27], Moments3& m) {
+  // step 2 for plane z into flux buffer k: own row pulled into hf, hg; phi_z and the fields
+  // along z into zv
+  auto own = [&](int z, int k, S (&hf)[27], S (&hg)[27], Moments3& m, S (&zv)[NF + 1]) {
     node_pops<S, WALLS, PULL, true>(A, nb, plane, nx, ny, nz, pitch, x, y, wrapz(z), hf, hg);
     moments(hf, hg, m);
     if (col_ok) {
       s_px[k][wv][lane + 1] = phi_of(m, 0);
       s_py[k][wv + 1][lane] = phi_of(m, 1);
+      if constexpr (TR) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+          s_fx[k][f][wv][lane + 1] = field(m, f, 0);
+          s_fy[k][f][wv + 1][lane] = field(m, f, 1);
+        }
+      }
     }
-    return phi_of(m, 2);
+    zv[0] = phi_of(m, 2);
+    if constexpr (TR) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) zv[1 + f] = field(m, f, 2);
+    }
   };
   auto put = [&](const S (&hf)[27], const S (&hg)[27]) {
     if constexpr (kLds) {
@@ -571,13 +615,13 @@ k_ddf3_fused(const S* __restrict__ A, const S* __restrict__ nb, S* __restrict__ 
   double acc[kDiagValues] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (ze > zb) {
     Moments3 m0;
-    double pz_prv, pz_cur;
+    S zv_prv[NF + 1], zv_cur[NF + 1];  // phi_z and the fields of planes z - 1, z
     {
       S hf[27], hg[27];
       Moments3 m;
-      pz_prv = own(zb - 1, 1, hf, hg, m);  // phi_z below the range (buffer 1 rewritten below)
+      own(zb - 1, 1, hf, hg, m, zv_prv);  // below the range (buffer 1 rewritten below)
       halo(zb, 0);
-      pz_cur = own(zb, 0, hf, hg, m0);
+      own(zb, 0, hf, hg, m0, zv_cur);
       put(hf, hg);
     }
     __syncthreads();
@@ -586,11 +630,11 @@ k_ddf3_fused(const S* __restrict__ A, const S* __restrict__ nb, S* __restrict__ 
       const int kn = kc ^ 1;
       halo(z + 1, kn);
       S hf[27], hg[27];
-      double pz_nxt;
+      S zv_nxt[NF + 1];
       Moments3 m1;
       {
         S nf[27], ng[27];
-        pz_nxt = own(z + 1, kn, nf, ng, m1);
+        own(z + 1, kn, nf, ng, m1, zv_nxt);
         if constexpr (kLds) {
 #pragma unroll
           for (int i = 0; i < 27; ++i) {
@@ -605,17 +649,39 @@ k_ddf3_fused(const S* __restrict__ A, const S* __restrict__ nb, S* __restrict__ 
       if (row_ok) {
         const double inv_rho = 1.0 / m0.rho;
         double ph[3];
-        ph[0] = -(0.5 * (s_px[kc][wv][lane + 2] - s_px[kc][wv][lane])) * inv_rho;
-        ph[1] = -(0.5 * (s_py[kc][wv + 2][lane] - s_py[kc][wv][lane])) * inv_rho;
-        ph[2] = -(0.5 * (pz_nxt - pz_prv)) * inv_rho;
-        const double zero3[3] = {0.0, 0.0, 0.0};
+        ph[0] = -(0.5 * ((double)s_px[kc][wv][lane + 2] - (double)s_px[kc][wv][lane])) * inv_rho;
+        ph[1] = -(0.5 * ((double)s_py[kc][wv + 2][lane] - (double)s_py[kc][wv][lane])) * inv_rho;
+        ph[2] = -(0.5 * ((double)zv_nxt[0] - (double)zv_prv[0])) * inv_rho;
+        // derivatives of the fields, in the two sweeps' order: gT and gh per axis, div u summed
+        // over x, y, z
+        double gT[3] = {0.0, 0.0, 0.0}, gh[3] = {0.0, 0.0, 0.0}, divu = 0.0;
+        if constexpr (TR) {
+          auto dx = [&](int f) {
+            return 0.5 * ((double)s_fx[kc][f][wv][lane + 2] - (double)s_fx[kc][f][wv][lane]);
+          };
+          auto dy = [&](int f) {
+            return 0.5 * ((double)s_fy[kc][f][wv + 2][lane] - (double)s_fy[kc][f][wv][lane]);
+          };
+          auto dz = [&](int f) { return 0.5 * ((double)zv_nxt[1 + f] - (double)zv_prv[1 + f]); };
+          gT[0] = dx(0);
+          divu += dx(1);
+          gT[1] = dy(0);
+          divu += dy(1);
+          gT[2] = dz(0);
+          divu += dz(1);
+          if constexpr (EXT == 2) {
+            gh[0] = dx(2);
+            gh[1] = dy(2);
+            gh[2] = dz(2);
+          }
+        }
         const double* w2 = rs.at_row();
         S* out = B + ((int64_t)z * ny + y) * pitch;  // row base (wave-uniform)
         const uint32_t xo = fresh((uint32_t)sizeof(S) * x);
         int64_t pl = plane;
         asm volatile("" : "+s"(pl));
-        collide3<EXT, false>(hf, hg, m0, ph, zero3, zero3, 0.0, prm, w2, w2 + 27,
-                             [&](int k, double t) {
+        collide3<EXT, TR>(hf, hg, m0, ph, gT, gh, divu, prm, w2, w2 + 27,
+                          [&](int k, double t) {
           if (col_ok) gstore_nt(at_byte(sbase(out + k * pl), xo), (S)t);
         });
         if (DIAG && col_ok) {
@@ -627,8 +693,11 @@ k_ddf3_fused(const S* __restrict__ A, const S* __restrict__ nb, S* __restrict__ 
         }
       }
       m0 = m1;
-      pz_prv = pz_cur;
-      pz_cur = pz_nxt;
+#pragma unroll
+      for (int f = 0; f <= NF; ++f) {
+        zv_prv[f] = zv_cur[f];
+        zv_cur[f] = zv_nxt[f];
+      }
       kc = kn;
       __syncthreads();
     }
@@ -843,9 +912,7 @@ int64_t ddf3_max_records(const Layout& L, const Grid& G) {
   return std::max<int64_t>(fused3_shape(L).blocks(), upwind3_grid(L, G).blocks());
 }
 
-static bool fused3_ok(const DdfParams& prm) {
-  return prm.phi == 1 && !prm.full && prm.eos == 0;
-}
+static bool fused3_ok(const DdfParams& prm) { return prm.phi == 1; }
 
 template <typename S>
 static void ddf3_step(bool walls, bool pull, const S* A, S* B, const Layout& L, const Grid& G0,
@@ -866,13 +933,21 @@ static void ddf3_step(bool walls, bool pull, const S* A, S* B, const Layout& L, 
     wall_kind(walls, prm, [&](auto W) {
       flag(pull, [&](auto Pl) {
         flag(partials != nullptr, [&](auto Dg) {
-          flag(prm.src, [&](auto Sr) {
-            k_ddf3_fused<S, decltype(W)::value, decltype(Pl)::value, decltype(Dg)::value,
-                         decltype(Sr)::value ? 1 : 0>
-                <<<(unsigned)F.blocks(), kBlock, 0, s>>>(A, nb, B, L.nx, L.ny, L.nz, L.pitch,
-                                                         L.plane, prm, F.nbx, F.nby, F.nzc,
-                                                         partials);
-          });
+          constexpr int w = decltype(W)::value;
+          constexpr bool pl = decltype(Pl)::value, dg = decltype(Dg)::value;
+          const unsigned nb_blocks = (unsigned)F.blocks();
+          auto go = [&](auto kern) {
+            kern<<<nb_blocks, kBlock, 0, s>>>(A, nb, B, L.nx, L.ny, L.nz, L.pitch, L.plane, prm,
+                                              F.nbx, F.nby, F.nzc, partials);
+          };
+          if (prm.eos)
+            go(k_ddf3_fused<S, w, pl, dg, 2, true>);
+          else if (prm.full)
+            go(k_ddf3_fused<S, w, pl, dg, 1, true>);
+          else if (prm.src)
+            go(k_ddf3_fused<S, w, pl, dg, 1, false>);
+          else
+            go(k_ddf3_fused<S, w, pl, dg, 0, false>);
         });
       });
     });

@@ -140,9 +140,9 @@ hipError_t launch_decode_ddf(int kind, int Q, int i, const void* A, const Layout
 // D3Q27 double distribution (float32 kind 0 / float64 kind 1 storage, 54 planes). One step is
 // two launches: fluxes (and, with transport control, T and u; for the van der Waals fluid also
 // the enthalpy) into `fld` (8 fields of L.plane elements in the storage type, float32 or
-// float64), then the collision; pull = false collides in place of streaming. The collision
-// without transport terms (sources allowed), with the central derivative of Phi, is one launch
-// that marches along z instead (after the boundary-plane rebuild with NEQ walls).
+// float64), then the collision; pull = false collides in place of streaming. With the central
+// derivative of Phi, one launch that marches along z takes both instead (after the
+// boundary-plane rebuild with NEQ walls).
 Grid make_grid_ddf3(const Layout& L);
 hipError_t launch_ddf3_rest_state(const DdfParams& prm, double* out, hipStream_t s);
 hipError_t launch_init_ddf3(int kind, const double* rho, const double* u, const double* T,
