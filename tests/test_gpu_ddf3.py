@@ -139,6 +139,26 @@ def test_fp32_ragged_lattice(walls, phi):
 
 
 @pytest.mark.parametrize("walls", [True, False])
+def test_fp32_ragged_lattice_transport_control(walls):
+    # the same ragged lattice with Pr 0.71 and bulk viscosity (T and u exchanged between tiles
+    # like the fluxes in the one-launch step), 4 steps against the oracle
+    shape = (20, 33, 37)
+    announce("D3Q27 DDF fp32 %s walls=%s Pr 0.71 eta/mu 1.5 4 steps" % (shape, walls))
+    rho, u, T = _fields(shape, seed=47)
+    tau = 0.7
+    _, ug, tg, _, fg, gg = _run(rho, u, T, 4, "fp32", tau=tau, wall_y=walls, phi=1,
+                                prandtl=0.71, eta_over_mu=1.5)
+    gas = ddf.Gas(R, CV, (tau - 0.5) * P0, prandtl=0.71, eta_over_mu=1.5)
+    f, g = ddf.run(*ddf.init_equilibrium(rho, u, T, gas), gas, 4, walls_y=walls)
+    ft, gt = ddf.collide(f, g, gas, walls, True, "central")
+    assert np.abs(fg - ft).max() <= 2e-6 * np.abs(ft).max()
+    assert np.abs(gg - gt).max() <= 2e-6 * np.abs(gt).max()
+    _, uo, to = ddf.temperature(f, g, gas)
+    assert rel_l2(ug, uo) <= 1e-5
+    assert rel_l2(tg - tg.mean(), to - to.mean()) <= 1e-4
+
+
+@pytest.mark.parametrize("walls", [True, False])
 def test_fp64_tall_lattice_more_rows_than_grid_limit(walls):
     # a 7 x 3 x 2 state tiled 6300 times along z: 132300 (y, z) rows exceed two rows per
     # workgroup within the launch limit of 65535 workgroups, so each workgroup takes three. On a
