@@ -455,25 +455,54 @@ k_ddf3_collide(const S* __restrict__ A, const S* __restrict__ nb, S* __restrict_
 // With the central derivative of Phi (any collision: sources, transport control, the van der
 // Waals fluid, NEQ walls), the flux and collision sweeps are fused into one launch that marches
 // along z. A workgroup owns a tile of kF3Cols columns by kF3Rows rows (one row per
-// wavefront) and a range of planes. Per plane z every wavefront
-//   1. computes the fluxes of one halo piece of plane z + 1: the rows below and above the tile
-//      (wavefronts 1 and 2) or phi_x of the columns left and right of two of its rows
-//      (wavefronts 0 and 3, one node per lane);
-//   2. pulls its own row of plane z + 1, computes the moments and fluxes;
+// wavefront) and a range of planes. Per plane z
+//   1. four wavefronts compute the fluxes of one halo piece each of plane z + 1: the rows below
+//      and above the tile (wavefronts 1 and 2) or phi_x of the columns left and right of half of
+//      its rows (wavefronts 0 and 3, one node per lane);
+//   2. every wavefront pulls its own row of plane z + 1, computes the moments and fluxes;
 //   3. swaps populations with LDS: reads those of plane z (pulled one plane earlier) and writes
 //      those of plane z + 1 in their place;
 //   4. collides its row of plane z and stores it;
-// and one barrier per plane orders the flux buffers. Every wavefront does the same work, so the
-// collision arithmetic is spread over all four SIMDs of a compute unit. phi_x and phi_y go to
+// and one barrier per plane orders the flux buffers. Wavefronts w and w + 4 share a SIMD, so each
+// SIMD carries one halo piece and two rows per plane and the collision arithmetic is spread
+// evenly over the four SIMDs of a compute unit. Eight rows per tile amortise the two halo rows
+// over eight (256^3 float32, eight against four rows: plain 1692 vs 1810 us, sources 1789 vs
+// 2002, Pr 0.71 1863 vs 2103, van der Waals 1922 vs 2090, NEQ walls 1752 vs 1900); the float32
+// populations of the eight rows take 108 KB of LDS, so one workgroup of eight wavefronts runs
+// per compute unit (two per SIMD, as before with two workgroups of four). phi_x and phi_y go to
 // two LDS buffers (planes z, z + 1), phi_z to a ring of three registers per column. float64
-// populations do not fit in LDS for two workgroups per compute unit and are pulled again at
-// step 3, from the caches. Fluxes and fields are rounded to the storage type as the two-sweep
-// fields store them, so both paths give identical results. Traffic: the populations are read from memory
-// once and written once per node (432 B in float32), against about 1.5x that for two sweeps.
+// populations are not held in LDS and are pulled again at step 3, from the caches. Fluxes and
+// fields are rounded to the storage type as the two-sweep fields store them, so both paths give
+// identical results. Traffic: the populations are read from memory once and written once per
+// node (432 B in float32), against about 1.5x that for two sweeps.
 constexpr int kF3Cols = 64;                // columns per tile (one wavefront row)
-constexpr int kF3Rows = 4;                 // rows per tile = wavefronts per workgroup
-constexpr int kF3Slots = 512;              // resident workgroups: 256 compute units x 2
-static_assert(kF3Rows * 64 == kBlock, "one row per wavefront");
+constexpr int kF3Rows = 8;                 // rows per tile = wavefronts per workgroup
+constexpr int kF3Threads = kF3Rows * 64;   // one row per wavefront
+constexpr int kF3Slots = 256;              // resident workgroups: 256 compute units x 1
+
+// Workgroup sum of N doubles per thread over the kF3Rows wavefronts of a one-launch workgroup,
+// in block_sum_store's order (wavefront sums, then the wavefronts in order); thread 0 writes
+// out[0..N).
+template <int N>
+__device__ __forceinline__ void fused3_sum_store(double (&v)[N], double* out) {
+  __shared__ double red[kF3Rows][N];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) red[wid][k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      double t = 0.0;
+      for (int w = 0; w < kF3Rows; ++w) t += red[w][k];
+      out[k] = t;
+    }
+  }
+}
 
 // WALLS: 0 periodic in y, 1 bounce-back walls, 2 non-equilibrium extrapolation walls (boundary
 // planes read from nb, rebuilt by k_ddf3_neq_rows, as in the two sweeps).
@@ -487,7 +516,7 @@ static_assert(kF3Rows * 64 == kBlock, "one row per wavefront");
 // 2645 us, van der Waals 2090 vs 2742 us).
 // Fluxes and fields are kept in the storage type, as the two-sweep fields are.
 template <typename S, int WALLS, bool PULL, bool DIAG, int EXT, bool TR>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(kF3Threads) __attribute__((amdgpu_waves_per_eu(2)))
 k_ddf3_fused(const S* __restrict__ A, const S* __restrict__ nb, S* __restrict__ B, int nx,
              int ny, int nz, int64_t pitch, int64_t plane, DdfParams prm, int nbx, int nby,
              int nzc, double* __restrict__ partials) {
@@ -524,9 +553,10 @@ k_ddf3_fused(const S* __restrict__ A, const S* __restrict__ nb, S* __restrict__ 
   const bool row_ok = y0 + wv < ny;
   const int y = row_ok ? y0 + wv : (WALLS ? ny - 1 : (y0 + wv) % ny);
   // halo piece. Wavefronts 1, 2: row y0 - 1 or y0 + kF3Rows (periodic, or the nearest row
-  // inside the walls: zero-order ghosts, Sec. III A). Wavefronts 0, 3: rows y0 + hr0 and
-  // y0 + hr0 + 1, lane 2k + s: row hr0 + k, s = 0 the column left of the tile, 1 the column
-  // right of it (periodic); lanes past 3 repeat lane 0 and store nothing.
+  // inside the walls: zero-order ghosts, Sec. III A). Wavefronts 0, 3: rows y0 + hr0 ..
+  // y0 + hr0 + kF3Rows / 2 - 1, lane 2k + s: row hr0 + k, s = 0 the column left of the tile, 1
+  // the column right of it (periodic); lanes past kF3Rows - 1 repeat lane 0 and store nothing.
+  // The other wavefronts have no halo piece.
   const bool hrow = wv == 1 || wv == 2;
   int yr = wv == 1 ? y0 - 1 : y0 + kF3Rows;
   if (WALLS)
@@ -534,9 +564,10 @@ k_ddf3_fused(const S* __restrict__ A, const S* __restrict__ nb, S* __restrict__ 
   else
     yr = ((yr % ny) + ny) % ny;
   const int pyslot = wv == 1 ? 0 : kF3Rows + 1;
-  const int hr0 = wv == 0 ? 0 : 2;
-  const int hk = lane < 4 ? lane >> 1 : 0, hs = lane < 4 ? lane & 1 : 0;
-  const bool hx_ok = lane < 4 && y0 + hr0 + hk < ny;
+  const bool xrow = wv == 0 || wv == 3;
+  const int hr0 = wv == 0 ? 0 : kF3Rows / 2;
+  const int hk = lane < kF3Rows ? lane >> 1 : 0, hs = lane < kF3Rows ? lane & 1 : 0;
+  const bool hx_ok = xrow && lane < kF3Rows && y0 + hr0 + hk < ny;
   const int yx = hx_ok ? y0 + hr0 + hk : y0;
   const int xx = hs ? (x0 + ncols == nx ? 0 : x0 + ncols) : (x0 == 0 ? nx - 1 : x0 - 1);
   const int pxslot = hs ? ncols + 1 : 0;
@@ -572,7 +603,7 @@ k_ddf3_fused(const S* __restrict__ A, const S* __restrict__ nb, S* __restrict__ 
           for (int f = 0; f < NF; ++f) s_fy[k][f][pyslot][lane] = field(m, f, 1);
         }
       }
-    } else {
+    } else if (xrow) {
       node_pops<S, WALLS, PULL, false>(A, nb, plane, nx, ny, nz, pitch, xx, yx, wrapz(z), hf, hg);
       moments(hf, hg, m);
       if (hx_ok) {
@@ -705,7 +736,7 @@ k_ddf3_fused(const S* __restrict__ A, const S* __restrict__ nb, S* __restrict__ 
       __syncthreads();
     }
   }
-  if (DIAG) block_sum_store<kDiagValues>(acc, partials + (int64_t)blockIdx.x * kDiagValues);
+  if (DIAG) fused3_sum_store<kDiagValues>(acc, partials + (int64_t)blockIdx.x * kDiagValues);
 }
 
 // f <- f^eq, g <- g^eq of the initial fields (Fig. 1), shifted by the rest state.
@@ -940,7 +971,7 @@ static void ddf3_step(bool walls, bool pull, const S* A, S* B, const Layout& L, 
           constexpr bool pl = decltype(Pl)::value, dg = decltype(Dg)::value;
           const unsigned nb_blocks = (unsigned)F.blocks();
           auto go = [&](auto kern) {
-            kern<<<nb_blocks, kBlock, 0, s>>>(A, nb, B, L.nx, L.ny, L.nz, L.pitch, L.plane, prm,
+            kern<<<nb_blocks, kF3Threads, 0, s>>>(A, nb, B, L.nx, L.ny, L.nz, L.pitch, L.plane, prm,
                                               F.nbx, F.nby, F.nzc, partials);
           };
           if (prm.eos)
